@@ -1,0 +1,160 @@
+"""Seeded point/load generators for the lattice Poisson workloads.
+
+The paper's experiments (Section 9) use synthetic geometries: loads drawn uniformly at
+random in an n-by-n box of Z^2, dense boxes and points on a circle.  The generators below
+produce those shapes plus the clustered and multi-instance mixes used for measurement.
+
+Every generator returns ``(xy, f)`` with ``xy`` an int32 array of shape [N, 2] (column 0
+is the first lattice coordinate m1, column 1 is m2) and ``f`` a float64 array of N loads
+whose exact sum is zero (the well-posedness condition of Section 1).
+
+Zero sum is made exact, not approximate: loads are mean-subtracted, rounded to integer
+multiples of 2^-32, and the last one is set to minus the sum of the others.  All values are
+then exactly representable, so sum(f) == 0 holds in exact arithmetic.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+_QUANT = 2.0 ** 32
+
+
+def zero_sum_loads(raw: np.ndarray) -> np.ndarray:
+    """Mean-subtract ``raw`` and quantise so that the loads sum to exactly zero."""
+    raw = np.asarray(raw, dtype=np.float64)
+    if raw.size == 0:
+        return raw.copy()
+    centred = raw - raw.mean()
+    k = np.rint(centred * _QUANT).astype(np.int64)
+    k[-1] = -int(k[:-1].sum())
+    return k.astype(np.float64) / _QUANT
+
+
+def uniform_box(rng: np.random.Generator, n: int, side: int, origin=(0, 0)) -> np.ndarray:
+    """``n`` distinct lattice cells drawn uniformly (without replacement) from a side x side box."""
+    side = int(side)
+    if n > side * side:
+        raise ValueError("more points than cells")
+    cells = rng.choice(side * side, size=n, replace=False)
+    xy = np.empty((n, 2), dtype=np.int64)
+    xy[:, 0] = cells % side + origin[0]
+    xy[:, 1] = cells // side + origin[1]
+    return xy.astype(np.int32)
+
+
+def gaussian_clusters(rng: np.random.Generator, n: int, centres: np.ndarray, sigma: float,
+                      extent: int) -> np.ndarray:
+    """``n`` distinct lattice points, split evenly over Gaussian clusters.
+
+    Each point is round(centre + sigma * g) with g standard normal in 2-D, clipped to
+    [0, extent).  Duplicate cells are redrawn until ``n`` distinct points exist.
+    """
+    centres = np.asarray(centres, dtype=np.float64)
+    k = len(centres)
+    per = np.full(k, n // k, dtype=np.int64)
+    per[: n - per.sum()] += 1
+    extent = int(extent)
+    keys = np.empty(0, dtype=np.int64)       # accepted cells, in acceptance order
+    need = per.copy()
+    while need.sum() > 0:
+        draws = []
+        for c in range(k):
+            if need[c] == 0:
+                continue
+            g = rng.standard_normal((int(need[c]), 2))
+            p = np.rint(centres[c] + sigma * g).astype(np.int64)
+            np.clip(p, 0, extent - 1, out=p)
+            draws.append((c, p[:, 0] * extent + p[:, 1]))
+        cand = np.concatenate([keys] + [d for _, d in draws])
+        owner = np.concatenate([np.full(len(keys), -1)] + [np.full(len(d), c) for c, d in draws])
+        _, first = np.unique(cand, return_index=True)
+        keep = np.zeros(len(cand), dtype=bool)
+        keep[first] = True
+        keep[: len(keys)] = True                 # earlier acceptances always stay
+        new_mask = keep[len(keys):]
+        new_owner = owner[len(keys):]
+        keys = cand[keep]
+        for c in range(k):
+            need[c] -= int(np.count_nonzero(new_mask & (new_owner == c)))
+    xy = np.empty((n, 2), dtype=np.int64)
+    xy[:, 0] = keys // extent
+    xy[:, 1] = keys % extent
+    return xy.astype(np.int32)
+
+
+# ----------------------------------------------------------------------------------------
+# Named workloads.  Sizes follow the measurement configurations of the build: a small
+# uniform case the oracle sums in seconds, a 1e6-source uniform case, a clustered case in
+# a 2^20 region, a batch of 512 uneven instances and a stream of serving requests.
+# ----------------------------------------------------------------------------------------
+
+def config_small_uniform(seed: int = 1, n: int = 1000, side: int = 256):
+    """1,000 distinct sources uniform in a 256 x 256 box, N(0,1) loads, zero sum."""
+    rng = np.random.default_rng(seed)
+    xy = uniform_box(rng, n, side)
+    f = zero_sum_loads(rng.standard_normal(n))
+    return xy, f
+
+
+def config_large_uniform(seed: int = 2, n: int = 1_000_000, side: int = 4096):
+    """1,000,000 distinct sources uniform in a 4096 x 4096 box, N(0,1) loads, zero sum."""
+    rng = np.random.default_rng(seed)
+    xy = uniform_box(rng, n, side)
+    f = zero_sum_loads(rng.standard_normal(n))
+    return xy, f
+
+
+def config_clusters(seed: int = 3, n: int = 2_000_000, n_clusters: int = 64,
+                    sigma: float = 2000.0, extent: int = 1 << 20, margin: float = 6000.0):
+    """Sources in Gaussian clusters (sigma = 2,000) inside a 2^20 x 2^20 region, U(-1,1) loads."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(margin, extent - margin, size=(n_clusters, 2))
+    xy = gaussian_clusters(rng, n, centres, sigma, extent)
+    f = zero_sum_loads(rng.uniform(-1.0, 1.0, size=n))
+    return xy, f
+
+
+def batched_sizes(seed: int = 4, n_inst: int = 512, lo: float = 1e3, hi: float = 1e5):
+    rng = np.random.default_rng(seed)
+    return np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), size=n_inst))).astype(np.int64)
+
+
+def config_batched(seed: int = 4, n_inst: int = 512, lo: float = 1e3, hi: float = 1e5):
+    """Independent uniform instances with log-uniform sizes, each in a box of side ceil(4 sqrt N)."""
+    sizes = batched_sizes(seed, n_inst, lo, hi)
+    out = []
+    for i, n in enumerate(sizes):
+        rng = np.random.default_rng([seed, i])
+        side = int(math.ceil(4.0 * math.sqrt(int(n))))
+        xy = uniform_box(rng, int(n), side)
+        f = zero_sum_loads(rng.standard_normal(int(n)))
+        out.append((xy, f))
+    return out
+
+
+def config_serving_request(seed: int, index: int, lo: float = 1e2, hi: float = 1e6):
+    """One serving request: log-uniform size, uniform or 8-cluster layout chosen by the seed."""
+    rng = np.random.default_rng([seed, index])
+    n = int(np.rint(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+    n = max(n, 2)
+    if rng.uniform() < 0.5:
+        side = int(math.ceil(4.0 * math.sqrt(n)))
+        xy = uniform_box(rng, n, side)
+        layout = "uniform"
+    else:
+        sigma = math.sqrt(n)
+        box = int(math.ceil(16.0 * math.sqrt(n)))
+        centres = rng.uniform(3 * sigma, box - 3 * sigma, size=(8, 2))
+        xy = gaussian_clusters(rng, n, centres, sigma, box)
+        layout = "clusters"
+    f = zero_sum_loads(rng.standard_normal(n))
+    return xy, f, layout
+
+
+def sample_targets(seed: int, n: int, k: int) -> np.ndarray:
+    """Indices of ``min(k, n)`` targets sampled without replacement, sorted."""
+    rng = np.random.default_rng(seed)
+    k = min(int(k), int(n))
+    return np.sort(rng.choice(n, size=k, replace=False)).astype(np.int64)

@@ -1,0 +1,210 @@
+/*
+ * lfmm.h -- C ABI of the lattice fast multipole library for MI355X (gfx950).
+ *
+ * The library evaluates the lattice convolution (eq. 1.7 of Gillman & Martinsson, "A fast
+ * solver for Poisson problems on infinite regular lattices")
+ *
+ *     u(m) = sum over sources n of phi(m - n) f(n),      m, n in Z^2,
+ *
+ * where phi is the fundamental solution of the 5-point discrete Laplacian (eq. 1.2, eq. 1.8),
+ * at the source points themselves ("we seek the potential at the source points", Section
+ * 8.1).  The fast method is the lattice FMM of Sections 4-8: a quadtree on the sources
+ * (Section 6), outgoing/incoming skeleton expansions built by interpolative decomposition
+ * (Sections 4.3, 5, 7), the five translation operators (Section 7) and the upward,
+ * interaction and downward passes (Section 8.2), with the near field summed against a
+ * tabulated phi (Sections 2, 3).
+ *
+ * Conventions (all calls):
+ *  - Every call returns an lfmm_status; nothing throws across the ABI.  On an error the
+ *    calling thread's lfmm_last_error() holds a human-readable detail string.
+ *  - Pointers named *_dev are device pointers (hipMalloc'd or torch CUDA tensors on ROCm);
+ *    pointers named *_host are host pointers.  The caller owns every buffer it passes; the
+ *    library owns the internals of lfmm_ctx, lfmm_plan and lfmm_opset and frees them on
+ *    destroy.
+ *  - Coordinates are int32 pairs (m1, m2), row i = point i, so xy has 2*n entries.  Loads
+ *    f and potentials u are float64.  The extent of the coordinates along either axis must
+ *    be below 2^31 (else LFMM_E_RANGE).  Duplicate points are allowed (loads superpose) and
+ *    a target on a source gets no self term, since phi(0) = 0.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued on it in
+ *    order; calls that must read sizes back (plan creation) synchronise the stream.
+ *  - The well-posedness condition of Section 1 is a zero total load.  The library returns
+ *    the finite sum for any loads; a non-zero sum is not an error.
+ *  - One host thread per context at a time.  Plans of one context are independent.
+ *    Destroy every plan before its context: plans draw their device memory from the
+ *    context's pool.
+ */
+#ifndef LFMM_H
+#define LFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lfmm_status {
+    LFMM_OK = 0,
+    LFMM_E_INVAL = -1,        /* null pointer, bad size, bad option value              */
+    LFMM_E_RANGE = -2,        /* coordinate extent >= 2^31, or a size the plan cannot hold */
+    LFMM_E_NOMEM = -3,        /* device or host allocation failed                        */
+    LFMM_E_HIP = -4,          /* a HIP runtime call failed; the plan is unusable          */
+    LFMM_E_UNSUPPORTED = -5,  /* valid request this build does not implement              */
+    LFMM_E_NODEVICE = -6      /* no GPU visible, or the device id does not exist          */
+} lfmm_status;
+
+typedef enum lfmm_precision {
+    LFMM_FP64 = 0,            /* every step in FP64                                        */
+    LFMM_MIXED = 1            /* M2L as FP32 matrix-core products with hi/lo splitting,
+                                 accumulated in FP64; everything else FP64                 */
+} lfmm_precision;
+
+typedef struct lfmm_options {
+    double eps;               /* ID tolerance relative to the first pivot (Section 4:
+                                 requested precision); default 1e-12                       */
+    int32_t max_leaf;         /* N_leaf of Section 6: most points a leaf may hold before the
+                                 tree is refined; 0 = default (64)                         */
+    int32_t precision;        /* lfmm_precision of the interaction (M2L) pass              */
+    int32_t proxy_per_edge;   /* proxy points per edge of the proxy ring once the full ring
+                                 is larger (Remark 5.1); default 64                        */
+    int32_t max_rank;         /* cap on the skeleton size P, 16..64, multiple of 16;
+                                 default 48                                                */
+    int32_t flags;            /* reserved, 0                                               */
+} lfmm_options;
+
+typedef struct lfmm_ctx lfmm_ctx;     /* device, phi table, per-leaf-side operator cache  */
+typedef struct lfmm_plan lfmm_plan;   /* one point set: sorted points, tree, lists and
+                                         expansion storage, resident until destroyed       */
+typedef struct lfmm_opset lfmm_opset; /* host copy of the operators for one leaf side     */
+
+typedef struct lfmm_plan_info {
+    int64_t n_points;
+    int32_t root_bits;        /* root box side is 2^root_bits                              */
+    int32_t leaf_level;       /* L: leaves are the boxes of level L (Section 6)            */
+    int64_t leaf_side;        /* lattice side of a leaf box, 2^(root_bits - L)             */
+    int32_t rank;             /* padded skeleton size P used by the kernels                */
+    int32_t leaf_kind;        /* 0: dense-model outgoing operator (Remark 8.2)             */
+    int64_t n_boxes;          /* non-empty boxes over all levels                           */
+    int64_t n_leaves;         /* non-empty leaves                                          */
+    int64_t near_pairs;       /* (target, source) pairs summed directly (Section 2)        */
+    int64_t m2l_pairs;        /* (box, interaction-list box) pairs (Section 8.2, step 3)   */
+} lfmm_plan_info;
+
+/* Fills *opt with the defaults listed above. */
+lfmm_status lfmm_options_init(lfmm_options* opt);
+
+/* Creates a context on HIP device `device` (Section 8.1 precompute that does not depend on
+ * the points: the phi table of Section 3 is built on the host and uploaded; operators are
+ * built per leaf side on first use and cached).  opt may be NULL for the defaults.
+ * LFMM_E_NODEVICE if the device does not exist. */
+lfmm_status lfmm_ctx_create(int32_t device, const lfmm_options* opt, lfmm_ctx** out);
+lfmm_status lfmm_ctx_destroy(lfmm_ctx* ctx);
+
+/* Builds the tree of Section 6 (Morton keys, sort, levels, parent/child, neighbor and
+ * interaction lists of Definition 6.1) for the n points xy_dev[2n] (device, int32), and the
+ * operators for its leaf side if the context lacks them.  The points are copied; xy_dev may
+ * be freed afterwards.  n >= 1. */
+lfmm_status lfmm_plan_create(lfmm_ctx* ctx, int64_t n, const int32_t* xy_dev, void* stream,
+                             lfmm_plan** out);
+
+/* Evaluates u_dev[i] = sum_j phi(x_i - x_j) f_dev[j] over the plan's points (eq. 1.7) by the
+ * passes of Section 8.2: P2M (T_ofs), M2M (T_ofo), M2L (T_ifo), L2L (T_ifi = T_ofo^T),
+ * L2P (T_tfi = T_ofs^T) and the direct near field.  f_dev and u_dev are device float64
+ * arrays of n entries in the caller's point order.  Enqueued on `stream`; no sync. */
+lfmm_status lfmm_execute(lfmm_plan* plan, const double* f_dev, double* u_dev, void* stream);
+
+/* Evaluates several plans of one context in shared launches (one launch per pass covers
+ * every plan).  f_dev[k], u_dev[k] belong to plans[k].  Results equal those of
+ * lfmm_execute on each plan alone. */
+lfmm_status lfmm_execute_batch(lfmm_ctx* ctx, int32_t n_plans, lfmm_plan* const* plans,
+                               const double* const* f_dev, double* const* u_dev, void* stream);
+
+lfmm_status lfmm_plan_get_info(lfmm_plan* plan, lfmm_plan_info* out);
+
+/* Phases of lfmm_execute, in launch order, for lfmm_plan_phase_times. */
+typedef enum lfmm_phase {
+    LFMM_PHASE_GATHER = 0,    /* loads into Morton order                                   */
+    LFMM_PHASE_P2M = 1,       /* T_ofs, Section 8.2 step 1                                 */
+    LFMM_PHASE_M2M = 2,       /* T_ofo, step 2                                             */
+    LFMM_PHASE_M2L = 3,       /* T_ifo, step 3                                             */
+    LFMM_PHASE_L2L = 4,       /* T_ifi, step 4                                             */
+    LFMM_PHASE_LEAF = 5,      /* T_tfi + near field + caller order, step 5                 */
+    LFMM_NUM_PHASES = 6
+} lfmm_phase;
+
+/* Turns per-phase timing of later lfmm_execute calls on or off (HIP events recorded on
+ * the execute stream around each phase; off by default). */
+lfmm_status lfmm_plan_set_timing(lfmm_plan* plan, int32_t enable);
+
+/* Milliseconds spent in each phase by the most recent timed lfmm_execute of this plan,
+ * ms_host[LFMM_NUM_PHASES]; waits for that execute to finish. */
+lfmm_status lfmm_plan_phase_times(lfmm_plan* plan, double* ms_host);
+
+/* Plan internals that lfmm_plan_export copies to the host, for inspection and tests. */
+typedef enum lfmm_export_item {
+    LFMM_EXPORT_POINTS = 0,     /* int32 [n][2]: points in Morton order, shifted so the root
+                                   box is [0, 2^root_bits)^2                                  */
+    LFMM_EXPORT_PERM = 1,       /* int32 [n]: caller index of each Morton-ordered point      */
+    LFMM_EXPORT_LEVEL_OFFSETS = 2, /* int32 [L+2]: boxes of level l are [off[l], off[l+1]) */
+    LFMM_EXPORT_BOX_KEY = 3,    /* uint64 [n_boxes]: Morton key of the box at its level      */
+    LFMM_EXPORT_BOX_BEGIN = 4,  /* int32 [n_boxes]: first Morton-ordered point of the box    */
+    LFMM_EXPORT_BOX_END = 5,    /* int32 [n_boxes]: one past its last point                  */
+    LFMM_EXPORT_BOX_PARENT = 6, /* int32 [n_boxes]: parent box, -1 for the root              */
+    LFMM_EXPORT_BOX_CHILD = 7,  /* int32 [n_boxes][4]: child c = x bit + 2 y bit, or -1      */
+    LFMM_EXPORT_INTERACTION = 8,/* int32 [boxes of levels >= 2][27]: interaction list slots  */
+    LFMM_EXPORT_NEIGHBOR = 9,   /* int32 [n_leaves][9]: 3x3 neighbourhood of each leaf       */
+    LFMM_EXPORT_QHAT = 10,      /* float64 [n_boxes][rank]: outgoing expansions (last execute) */
+    LFMM_EXPORT_UHAT = 11,      /* float64 [n_boxes][rank]: incoming expansions (last execute) */
+    LFMM_EXPORT_LOADS = 12      /* float64 [n]: loads of the last execute in Morton order   */
+} lfmm_export_item;
+
+/* Copies plan item `item` into host_out.  With host_out NULL, stores the byte size in *bytes;
+ * otherwise *bytes must hold at least that size.  Waits for the device. */
+lfmm_status lfmm_plan_export(lfmm_plan* plan, int32_t item, void* host_out, size_t* bytes);
+
+/* Device bytes a plan for n points would hold (tree, lists, expansions, scratch), a bound
+ * used for admission by memory footprint. */
+lfmm_status lfmm_plan_footprint_bytes(const lfmm_ctx* ctx, int64_t n, size_t* out);
+
+lfmm_status lfmm_plan_destroy(lfmm_plan* plan);
+
+/* One-shot: plan, execute, destroy.  Synchronises the stream before returning. */
+lfmm_status lfmm_solve(lfmm_ctx* ctx, int64_t n, const int32_t* xy_dev, const double* f_dev,
+                       double* u_dev, void* stream);
+
+/* Direct O(n_t n_s) sum on the GPU, u_dev[t] = sum_s phi(txy_t - sxy_s) f_dev[s] (eq. 1.7),
+ * with phi from the table (|m|_inf <= 128) or the expansion eq. (3.1).  For small inputs and
+ * for checking. */
+lfmm_status lfmm_direct(lfmm_ctx* ctx, int64_t n_t, const int32_t* txy_dev, int64_t n_s,
+                        const int32_t* sxy_dev, const double* f_dev, double* u_dev, void* stream);
+
+const char* lfmm_status_string(lfmm_status s);
+const char* lfmm_last_error(void);
+
+/* ---- host-only calls (no GPU needed): the library's own phi and operators ------------ */
+
+/* phi at n integer offsets mxy_host[2n] (table for |m|_inf <= 128 from the reduced 1-D
+ * integral of the remark closing Section 3, eq. (3.1) beyond), into out_host[n]. */
+lfmm_status lfmm_host_phi(int64_t n, const int32_t* mxy_host, double* out_host);
+
+/* Builds the operators of Sections 5 and 7 for leaves of side leaf_side and n_levels
+ * heights above the leaf (opt may be NULL). */
+lfmm_status lfmm_host_opset_create(int64_t leaf_side, int32_t n_levels, const lfmm_options* opt,
+                                   lfmm_opset** out);
+/* Side and skeleton size of height h (h = 0 is the leaf). */
+lfmm_status lfmm_host_opset_level(const lfmm_opset* ops, int32_t h, int64_t* side, int32_t* rank);
+/* Skeleton points of height h relative to the box corner, out_host[2*rank]. */
+lfmm_status lfmm_host_opset_skeleton(const lfmm_opset* ops, int32_t h, int64_t* out_host);
+/* T_ofo for child c (0..3, c = x bit + 2 y bit) of height h >= 1, row-major
+ * rank(h) x rank(h-1). */
+lfmm_status lfmm_host_opset_ofo(const lfmm_opset* ops, int32_t h, int32_t c, double* out_host);
+/* Dense-model T_ofs of the leaf (Remark 8.2), row-major rank(0) x side^2, column
+ * x + side*y for the cell (x, y).  LFMM_E_UNSUPPORTED if the leaf is not dense. */
+lfmm_status lfmm_host_opset_leaf(const lfmm_opset* ops, double* out_host);
+lfmm_status lfmm_host_opset_destroy(lfmm_opset* ops);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LFMM_H */

@@ -1,0 +1,309 @@
+"""ctypes declarations for include/lfmm.h and small Python wrappers with the same names."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liblfmm.so")
+_HEADER = os.path.join(os.path.dirname(_HERE), "include", "lfmm.h")
+
+PRECISIONS = {"fp64": 0, "mixed": 1}
+
+_i32, _i64, _dbl, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+
+class LfmmError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__("lfmm status %d: %s" % (status, detail))
+        self.status = status
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("eps", _dbl), ("max_leaf", _i32), ("precision", _i32), ("proxy_per_edge", _i32),
+                ("max_rank", _i32), ("flags", _i32)]
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("n_points", _i64), ("root_bits", _i32), ("leaf_level", _i32), ("leaf_side", _i64),
+                ("rank", _i32), ("leaf_kind", _i32), ("n_boxes", _i64), ("n_leaves", _i64),
+                ("near_pairs", _i64), ("m2l_pairs", _i64)]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError("liblfmm.so is not built; run `python paper_1105_3505_amd/build.py`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    sig = {
+        "lfmm_options_init": [_vp],
+        "lfmm_ctx_create": [_i32, _vp, _vp],
+        "lfmm_ctx_destroy": [_vp],
+        "lfmm_plan_create": [_vp, _i64, _vp, _vp, _vp],
+        "lfmm_execute": [_vp, _vp, _vp, _vp],
+        "lfmm_execute_batch": [_vp, _i32, _vp, _vp, _vp, _vp],
+        "lfmm_plan_get_info": [_vp, _vp],
+        "lfmm_plan_set_timing": [_vp, _i32],
+        "lfmm_plan_export": [_vp, _i32, _vp, _vp],
+        "lfmm_plan_phase_times": [_vp, _vp],
+        "lfmm_plan_footprint_bytes": [_vp, _i64, _vp],
+        "lfmm_plan_destroy": [_vp],
+        "lfmm_solve": [_vp, _i64, _vp, _vp, _vp, _vp],
+        "lfmm_direct": [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp],
+        "lfmm_host_phi": [_i64, _vp, _vp],
+        "lfmm_host_opset_create": [_i64, _i32, _vp, _vp],
+        "lfmm_host_opset_level": [_vp, _i32, _vp, _vp],
+        "lfmm_host_opset_skeleton": [_vp, _i32, _vp],
+        "lfmm_host_opset_ofo": [_vp, _i32, _i32, _vp],
+        "lfmm_host_opset_leaf": [_vp, _vp],
+        "lfmm_host_opset_destroy": [_vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.lfmm_status_string.argtypes = [ctypes.c_int]
+    lib.lfmm_status_string.restype = ctypes.c_char_p
+    lib.lfmm_last_error.argtypes = []
+    lib.lfmm_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        detail = (_lib.lfmm_last_error() or b"").decode(errors="replace")
+        name = (_lib.lfmm_status_string(status) or b"").decode()
+        raise LfmmError(status, "%s: %s" % (name, detail))
+
+
+def exported_symbols() -> list[str]:
+    """Every function name declared in include/lfmm.h."""
+    with open(_HEADER) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"\b(lfmm_[a-z_0-9]+)\s*\(", text)))
+
+
+def _options(eps=None, max_leaf=None, precision=None, proxy_per_edge=None, max_rank=None) -> _Options:
+    o = _Options()
+    _check(_lib.lfmm_options_init(ctypes.byref(o)))
+    if eps is not None:
+        o.eps = float(eps)
+    if max_leaf is not None:
+        o.max_leaf = int(max_leaf)
+    if precision is not None:
+        o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    if proxy_per_edge is not None:
+        o.proxy_per_edge = int(proxy_per_edge)
+    if max_rank is not None:
+        o.max_rank = int(max_rank)
+    return o
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _dev_tensor(t, dtype, shape_tail, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must live on the GPU" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s" % (name, dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape_tail is not None and tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError("%s must have shape [n, %s]" % (name, ",".join(map(str, shape_tail))))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """lfmm_ctx: a device, the phi table and the operator cache."""
+
+    def __init__(self, device: int = 0, **opts):
+        self._opts = _options(**opts)
+        h = ctypes.c_void_p()
+        _check(_lib.lfmm_ctx_create(int(device), ctypes.byref(self._opts), ctypes.byref(h)))
+        self._h = h
+        self.device = int(device)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.lfmm_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def plan(self, xy, stream=None) -> "Plan":
+        import torch
+        ptr = _dev_tensor(xy, torch.int32, (2,), "xy")
+        h = ctypes.c_void_p()
+        _check(_lib.lfmm_plan_create(self._h, int(xy.shape[0]), ptr, _stream_handle(stream), ctypes.byref(h)))
+        return Plan(self, h, int(xy.shape[0]))
+
+    def solve(self, xy, f, u=None, stream=None):
+        import torch
+        n = int(xy.shape[0])
+        if u is None:
+            u = torch.empty(n, dtype=torch.float64, device=f.device)
+        _check(_lib.lfmm_solve(self._h, n, _dev_tensor(xy, torch.int32, (2,), "xy"),
+                               _dev_tensor(f, torch.float64, (), "f"), _dev_tensor(u, torch.float64, (), "u"),
+                               _stream_handle(stream)))
+        return u
+
+    def direct(self, txy, sxy, f, u=None, stream=None):
+        import torch
+        nt, ns = int(txy.shape[0]), int(sxy.shape[0])
+        if u is None:
+            u = torch.empty(nt, dtype=torch.float64, device=f.device)
+        _check(_lib.lfmm_direct(self._h, nt, _dev_tensor(txy, torch.int32, (2,), "txy"), ns,
+                                _dev_tensor(sxy, torch.int32, (2,), "sxy"), _dev_tensor(f, torch.float64, (), "f"),
+                                _dev_tensor(u, torch.float64, (), "u"), _stream_handle(stream)))
+        return u
+
+    def execute_batch(self, plans, fs, us, stream=None):
+        import torch
+        k = len(plans)
+        hp = (ctypes.c_void_p * k)(*[p._h for p in plans])
+        fp = (ctypes.c_void_p * k)(*[_dev_tensor(f, torch.float64, (), "f").value for f in fs])
+        up = (ctypes.c_void_p * k)(*[_dev_tensor(u, torch.float64, (), "u").value for u in us])
+        _check(_lib.lfmm_execute_batch(self._h, k, hp, fp, up, _stream_handle(stream)))
+        return us
+
+    def footprint_bytes(self, n: int) -> int:
+        out = ctypes.c_size_t()
+        _check(_lib.lfmm_plan_footprint_bytes(self._h, int(n), ctypes.byref(out)))
+        return int(out.value)
+
+
+class Plan:
+    """lfmm_plan: the tree of one point set, resident on the device."""
+
+    def __init__(self, ctx: Context, handle, n: int):
+        self.ctx = ctx
+        self._h = handle
+        self.n = n
+
+    def execute(self, f, u=None, stream=None):
+        import torch
+        if int(f.shape[0]) != self.n:
+            raise ValueError("f must have one load per point")
+        if u is None:
+            u = torch.empty(self.n, dtype=torch.float64, device=f.device)
+        _check(_lib.lfmm_execute(self._h, _dev_tensor(f, torch.float64, (), "f"),
+                                 _dev_tensor(u, torch.float64, (), "u"), _stream_handle(stream)))
+        return u
+
+    PHASES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf")
+    EXPORTS = {"points": (0, np.int32, 2), "perm": (1, np.int32, 0), "level_offsets": (2, np.int32, 0),
+               "box_key": (3, np.uint64, 0), "box_begin": (4, np.int32, 0), "box_end": (5, np.int32, 0),
+               "box_parent": (6, np.int32, 0), "box_child": (7, np.int32, 4), "interaction": (8, np.int32, 27),
+               "neighbor": (9, np.int32, 9), "qhat": (10, np.float64, 48), "uhat": (11, np.float64, 48),
+               "loads": (12, np.float64, 0)}
+
+    def export(self, name: str) -> np.ndarray:
+        """Copy of a plan internal (lfmm_plan_export) as a numpy array."""
+        item, dtype, width = self.EXPORTS[name]
+        size = ctypes.c_size_t()
+        _check(_lib.lfmm_plan_export(self._h, item, None, ctypes.byref(size)))
+        out = np.empty(size.value // np.dtype(dtype).itemsize, dtype=dtype)
+        if size.value:
+            _check(_lib.lfmm_plan_export(self._h, item, out.ctypes.data_as(_vp), ctypes.byref(size)))
+        return out.reshape(-1, width) if width else out
+
+    def set_timing(self, enable: bool = True) -> None:
+        _check(_lib.lfmm_plan_set_timing(self._h, 1 if enable else 0))
+
+    def phase_times(self) -> dict:
+        """Milliseconds per phase of the last timed execute (HIP events on its stream)."""
+        out = (ctypes.c_double * len(self.PHASES))()
+        _check(_lib.lfmm_plan_phase_times(self._h, out))
+        return dict(zip(self.PHASES, list(out)))
+
+    def info(self) -> dict:
+        i = _PlanInfo()
+        _check(_lib.lfmm_plan_get_info(self._h, ctypes.byref(i)))
+        return {name: getattr(i, name) for name, _ in _PlanInfo._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.lfmm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def host_phi(mxy) -> np.ndarray:
+    """The library's phi at integer offsets (host computation, no GPU)."""
+    m = np.ascontiguousarray(np.asarray(mxy, dtype=np.int32).reshape(-1, 2))
+    out = np.empty(len(m), dtype=np.float64)
+    _check(_lib.lfmm_host_phi(len(m), m.ctypes.data_as(_vp), out.ctypes.data_as(_vp)))
+    return out
+
+
+class HostOperators:
+    """Host copy of the operators for one leaf side (lfmm_opset)."""
+
+    def __init__(self, leaf_side: int, n_levels: int, **opts):
+        o = _options(**opts)
+        h = ctypes.c_void_p()
+        _check(_lib.lfmm_host_opset_create(int(leaf_side), int(n_levels), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.n_levels = int(n_levels)
+        self.leaf_side = int(leaf_side)
+
+    def level(self, h: int):
+        side, rank = ctypes.c_int64(), ctypes.c_int32()
+        _check(_lib.lfmm_host_opset_level(self._h, int(h), ctypes.byref(side), ctypes.byref(rank)))
+        return int(side.value), int(rank.value)
+
+    def skeleton(self, h: int) -> np.ndarray:
+        _, r = self.level(h)
+        out = np.empty(2 * r, dtype=np.int64)
+        _check(_lib.lfmm_host_opset_skeleton(self._h, int(h), out.ctypes.data_as(_vp)))
+        return out.reshape(r, 2)
+
+    def ofo(self, h: int, c: int) -> np.ndarray:
+        _, r = self.level(h)
+        _, rc = self.level(h - 1)
+        out = np.empty((r, rc), dtype=np.float64)
+        _check(_lib.lfmm_host_opset_ofo(self._h, int(h), int(c), out.ctypes.data_as(_vp)))
+        return out
+
+    def leaf(self) -> np.ndarray:
+        _, r = self.level(0)
+        out = np.empty((r, self.leaf_side ** 2), dtype=np.float64)
+        _check(_lib.lfmm_host_opset_leaf(self._h, out.ctypes.data_as(_vp)))
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.lfmm_host_opset_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,24 @@
+// Internal helpers shared by the host-side translation units of the C ABI.
+#pragma once
+
+#include <string>
+
+#include "host_math.h"
+#include "lfmm.h"
+
+namespace lfmm {
+
+// Largest skeleton size the kernels store per box (expansion vectors hold kMaxRank slots
+// at most; the per-plan padded rank is a multiple of 16 up to this).
+constexpr int kMaxRank = 64;
+
+// Largest leaf side with a dense-model outgoing operator (Remark 8.2).  Its table holds
+// rank x side^2 doubles (48 x 16384 x 8 B = 6.3 MB at side 128).
+constexpr int64_t kDenseLeafMax = 128;
+
+extern thread_local std::string g_last_error;
+lfmm_status fail(lfmm_status s, const std::string& msg);
+lfmm_status validate_options(const lfmm_options* o);
+OperatorParams operator_params(const lfmm_options& o);
+
+}  // namespace lfmm

@@ -69,8 +69,12 @@ typedef struct lfmm_options {
                                  is larger (Remark 5.1); default 64                        */
     int32_t max_rank;         /* cap on the skeleton size P, 16..64, multiple of 16;
                                  default 48                                                */
-    int32_t flags;            /* reserved, 0                                               */
+    int32_t flags;            /* LFMM_FLAG_* bits, default 0                               */
 } lfmm_options;
+
+/* options.flags: run the first-generation kernels (one wave per M2L tile, lanes = targets
+ * in the near field) instead of the default ones; same results to rounding, for comparison. */
+#define LFMM_FLAG_SIMPLE_KERNELS 1
 
 typedef struct lfmm_ctx lfmm_ctx;     /* device, phi table, per-leaf-side operator cache  */
 typedef struct lfmm_plan lfmm_plan;   /* one point set: sorted points, tree, lists and

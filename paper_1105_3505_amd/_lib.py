@@ -4,6 +4,7 @@ from __future__ import annotations
 import ctypes
 import os
 import re
+import weakref
 
 import numpy as np
 
@@ -92,7 +93,11 @@ def exported_symbols() -> list[str]:
     return sorted(set(re.findall(r"\b(lfmm_[a-z_0-9]+)\s*\(", text)))
 
 
-def _options(eps=None, max_leaf=None, precision=None, proxy_per_edge=None, max_rank=None) -> _Options:
+FLAG_SIMPLE_KERNELS = 1
+
+
+def _options(eps=None, max_leaf=None, precision=None, proxy_per_edge=None, max_rank=None,
+             flags=None) -> _Options:
     o = _Options()
     _check(_lib.lfmm_options_init(ctypes.byref(o)))
     if eps is not None:
@@ -105,6 +110,8 @@ def _options(eps=None, max_leaf=None, precision=None, proxy_per_edge=None, max_r
         o.proxy_per_edge = int(proxy_per_edge)
     if max_rank is not None:
         o.max_rank = int(max_rank)
+    if flags is not None:
+        o.flags = int(flags)
     return o
 
 
@@ -139,9 +146,13 @@ class Context:
         _check(_lib.lfmm_ctx_create(int(device), ctypes.byref(self._opts), ctypes.byref(h)))
         self._h = h
         self.device = int(device)
+        self._plans = weakref.WeakSet()
 
     def close(self) -> None:
+        """Destroys the context; its live plans are destroyed first (they use its memory)."""
         if getattr(self, "_h", None):
+            for p in list(self._plans):
+                p.close()
             _lib.lfmm_ctx_destroy(self._h)
             self._h = None
 
@@ -156,7 +167,9 @@ class Context:
         ptr = _dev_tensor(xy, torch.int32, (2,), "xy")
         h = ctypes.c_void_p()
         _check(_lib.lfmm_plan_create(self._h, int(xy.shape[0]), ptr, _stream_handle(stream), ctypes.byref(h)))
-        return Plan(self, h, int(xy.shape[0]))
+        plan = Plan(self, h, int(xy.shape[0]))
+        self._plans.add(plan)
+        return plan
 
     def solve(self, xy, f, u=None, stream=None):
         import torch

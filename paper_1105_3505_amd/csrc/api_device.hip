@@ -178,6 +178,7 @@ struct lfmm_plan {
     uint64_t* box_key = nullptr;
     M2LTile* tiles = nullptr;
     double *Q = nullptr, *U = nullptr, *fs = nullptr;
+    uint32_t* pkey = nullptr;    // window keys of the points (leaves of side <= 16)
     bool failed = false;
     bool timing = false;
     bool timed_once = false;
@@ -245,14 +246,34 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st) {
     co->mem.reserve(ofo_cm.size() * sizeof(double));
     co->mem.reserve(ofo_rm.size() * sizeof(double));
     co->mem.reserve(ifo.size() * sizeof(double));
-    // FP32 hi/lo split of T_ifo for the mixed-precision M2L
-    std::vector<float> ifo_hi(ifo.size()), ifo_lo(ifo.size());
-    for (size_t i = 0; i < ifo.size(); ++i) {
-        ifo_hi[i] = float(ifo[i]);
-        ifo_lo[i] = float(ifo[i] - double(ifo_hi[i]));
+    // mixed precision: T^d = c_d 1 1^T + R^d (c_d = mean entry over the true rank), R^d split
+    // into FP32 hi + lo; padded rows and columns stay zero
+    std::vector<float> ifo_hi(ifo.size(), 0.f), ifo_lo(ifo.size(), 0.f);
+    std::vector<double> mono(size_t(nlev) * kNumIfoSlots, 0.0);
+    std::vector<int32_t> ranks(static_cast<size_t>(nlev), 0);
+    for (int h = 0; h < nlev; ++h) {
+        const int r = H.level[size_t(h)].rank;
+        ranks[size_t(h)] = r;
+        for (int slot = 0; slot < kNumIfoSlots; ++slot) {
+            const size_t base = (size_t(h) * kNumIfoSlots + slot) * P * P;
+            double mean = 0.0;
+            for (int p = 0; p < r; ++p)
+                for (int q = 0; q < r; ++q) mean += ifo[base + size_t(p) * P + q];
+            mean /= double(r) * double(r);
+            mono[size_t(h) * kNumIfoSlots + slot] = mean;
+            for (int p = 0; p < r; ++p)
+                for (int q = 0; q < r; ++q) {
+                    const double rem = ifo[base + size_t(p) * P + q] - mean;
+                    const float hi = float(rem);
+                    ifo_hi[base + size_t(p) * P + q] = hi;
+                    ifo_lo[base + size_t(p) * P + q] = float(rem - double(hi));
+                }
+        }
     }
     co->mem.reserve(ifo.size() * sizeof(float));
     co->mem.reserve(ifo.size() * sizeof(float));
+    co->mem.reserve(mono.size() * sizeof(double));
+    co->mem.reserve(ranks.size() * sizeof(int32_t));
     co->mem.allocate();
     co->dev.leaf_side = side;
     co->dev.nlev = nlev;
@@ -262,12 +283,16 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st) {
     co->dev.ifo = co->mem.take<double>(ifo.size());
     co->dev.ifo_hi = co->mem.take<float>(ifo.size());
     co->dev.ifo_lo = co->mem.take<float>(ifo.size());
+    co->dev.mono = co->mem.take<double>(mono.size());
+    co->dev.rank = co->mem.take<int32_t>(ranks.size());
     LFMM_HIP(hipMemcpyAsync(co->dev.leafT, leafT.data(), leafT.size() * 8, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipMemcpyAsync(co->dev.ofo_cm, ofo_cm.data(), ofo_cm.size() * 8, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipMemcpyAsync(co->dev.ofo_rm, ofo_rm.data(), ofo_rm.size() * 8, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipMemcpyAsync(co->dev.ifo, ifo.data(), ifo.size() * 8, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipMemcpyAsync(co->dev.ifo_hi, ifo_hi.data(), ifo.size() * 4, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipMemcpyAsync(co->dev.ifo_lo, ifo_lo.data(), ifo.size() * 4, hipMemcpyHostToDevice, st));
+    LFMM_HIP(hipMemcpyAsync(co->dev.mono, mono.data(), mono.size() * 8, hipMemcpyHostToDevice, st));
+    LFMM_HIP(hipMemcpyAsync(co->dev.rank, ranks.data(), ranks.size() * 4, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipStreamSynchronize(st));
     CachedOps* raw = co.get();
     ctx->ops[side] = raw;             // a shallower set stays alive for the plans using it
@@ -373,6 +398,7 @@ void build_plan(lfmm_plan* pl, const int32_t* xy, hipStream_t st) {
     m.reserve(size_t(max_tiles + 1) * sizeof(M2LTile));
     m.reserve(size_t(nb) * P * 8);              // Q
     m.reserve(size_t(nb) * P * 8);              // U
+    m.reserve(size_t(n) * 4);                   // point keys
     m.allocate();
     pl->pts = m.take<int32_t>(size_t(n) * 2);
     pl->perm = m.take<int32_t>(n);
@@ -390,8 +416,10 @@ void build_plan(lfmm_plan* pl, const int32_t* xy, hipStream_t st) {
     pl->tiles = m.take<M2LTile>(size_t(max_tiles + 1));
     pl->Q = m.take<double>(size_t(nb) * P);
     pl->U = m.take<double>(size_t(nb) * P);
+    pl->pkey = m.take<uint32_t>(n);
 
     launch_gather_points(xy, vals, n, bb[0], bb[1], pl->pts, pl->perm, st);
+    if (pl->side <= 16) launch_point_keys(pl->pts, n, pl->side, pl->pkey, st);
 
     // ---- leaves ------------------------------------------------------------------------------
     // level-scan temporaries reuse the sort buffers: leaf arrays need <= n entries each
@@ -435,6 +463,7 @@ void build_plan(lfmm_plan* pl, const int32_t* xy, hipStream_t st) {
 void run_plan(lfmm_plan* pl, const double* f, double* u, hipStream_t st) {
     const DevOps& op = pl->ops->dev;
     const int L = pl->L;
+    const bool simple = (pl->ctx->opt.flags & LFMM_FLAG_SIMPLE_KERNELS) != 0;
     auto mark = [&](int k) {
         if (pl->timing) LFMM_HIP(hipEventRecord(pl->ev[k], st));
     };
@@ -456,10 +485,10 @@ void run_plan(lfmm_plan* pl, const double* f, double* u, hipStream_t st) {
     if (far) {
         if (pl->ctx->opt.precision == LFMM_MIXED)
             launch_m2l_mixed(pl->tiles, pl->ntiles, pl->max_tiles, pl->cls_box, pl->ilist, pl->ilist_off, pl->Q,
-                             pl->U, op.ifo_hi, op.ifo_lo, st);
+                             pl->U, op.ifo_hi, op.ifo_lo, op.mono, op.rank, st);
         else
             launch_m2l(pl->tiles, pl->ntiles, pl->max_tiles, pl->cls_box, pl->ilist, pl->ilist_off, pl->Q, pl->U,
-                       op.ifo, st);
+                       op.ifo, simple, st);
     }
     mark(4);
     if (far) {
@@ -469,13 +498,17 @@ void run_plan(lfmm_plan* pl, const double* f, double* u, hipStream_t st) {
     }
     mark(5);
     launch_leaf_eval(pl->nleaves, pl->leaf_off, pl->box_pt0, pl->box_pt1, pl->box_key, pl->nlist, L, pl->side,
-                     pl->pts, pl->fs, pl->perm, pl->U, op.leafT, far, pl->ctx->phi_oct, u, st);
+                     pl->pts, pl->side <= 16 ? pl->pkey : nullptr, pl->fs, pl->perm, pl->U, op.leafT, far,
+                     pl->ctx->phi_oct, u, simple, st);
     mark(6);
     if (pl->timing) pl->timed_once = true;
 }
 
 template <class F>
 lfmm_status guarded(F&& f) {
+    // the per-thread "last error" may hold an error from another library's HIP call (the
+    // caller's framework shares this thread): clear it so that only our launches are checked
+    (void)hipGetLastError();
     try {
         return f();
     } catch (const HipFailure& e) {

@@ -33,8 +33,11 @@ struct DevOps {
     double* ofo_cm = nullptr;      // [nlev][4][q child][r parent]  (M2M reads columns)
     double* ofo_rm = nullptr;      // [nlev][4][r parent][q child]  (L2L reads rows)
     double* ifo = nullptr;         // [nlev][49][p][q] row-major T_ifo per offset slot
-    float* ifo_hi = nullptr;       // mixed precision: FP32 hi/lo split of ifo
+    // mixed precision: T_ifo^d = c_d 1 1^T + R^d with c_d the mean entry; R^d in FP32 hi + lo
+    float* ifo_hi = nullptr;
     float* ifo_lo = nullptr;
+    double* mono = nullptr;        // [nlev][49] c_d
+    int32_t* rank = nullptr;       // [nlev] skeleton size of each height
 };
 
 // ---- launchers (all enqueue on `st`) ----------------------------------------------------
@@ -85,15 +88,17 @@ void launch_l2l(int32_t box_begin, int32_t box_end, int height_parent, const int
                 const uint64_t* box_key, const double* ofo_rm, double* U, hipStream_t st);
 void launch_m2l(const M2LTile* tiles, const int32_t* ntiles, int32_t max_tiles,
                 const int32_t* cls_box, const int32_t* ilist, int32_t ilist_off, const double* Q,
-                double* U, const double* ifo, hipStream_t st);
+                double* U, const double* ifo, bool simple, hipStream_t st);
+// window keys 8 (y (4 side - 1) + x) mod 2^32 of the Morton-ordered points
+void launch_point_keys(const int32_t* pts, int64_t n, int64_t side, uint32_t* key, hipStream_t st);
 void launch_m2l_mixed(const M2LTile* tiles, const int32_t* ntiles, int32_t max_tiles, const int32_t* cls_box,
                       const int32_t* ilist, int32_t ilist_off, const double* Q, double* U, const float* ifo_hi,
-                      const float* ifo_lo, hipStream_t st);
+                      const float* ifo_lo, const double* mono, const int32_t* rank, hipStream_t st);
 void launch_leaf_eval(int64_t nleaves, int32_t leaf_off, const int32_t* box_pt0,
                       const int32_t* box_pt1, const uint64_t* box_key, const int32_t* nlist,
-                      int L, int64_t side, const int32_t* pts, const double* fs,
+                      int L, int64_t side, const int32_t* pts, const uint32_t* pkey, const double* fs,
                       const int32_t* perm, const double* U, const double* leafT, bool far,
-                      const double* phi_oct, double* u, hipStream_t st);
+                      const double* phi_oct, double* u, bool simple, hipStream_t st);
 void launch_direct(int64_t nt, const int32_t* txy, int64_t ns, const int32_t* sxy,
                    const double* f, const double* phi_oct, double* u, hipStream_t st);
 

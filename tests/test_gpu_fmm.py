@@ -179,3 +179,46 @@ def test_large_uniform_sampled(torch_mod, ctx):
     print("n=1e6 leaf level %d side %d near pairs %d m2l pairs %d rel err %.3e"
           % (info["leaf_level"], info["leaf_side"], info["near_pairs"], info["m2l_pairs"], err))
     assert err <= FMM_TOL
+
+
+def test_first_generation_kernels_agree(torch_mod):
+    # LFMM_FLAG_SIMPLE_KERNELS selects the one-wave-per-tile M2L and lanes-as-targets near
+    # field; both forms must meet the same bar
+    import paper_1105_3505_amd as lf
+    ctx = lf.Context(0, flags=1)
+    for seed, n, side in [(41, 1000, 256), (42, 20000, 560)]:
+        rng = np.random.default_rng(seed)
+        xy = wl.uniform_box(rng, n, side)
+        f = wl.zero_sum_loads(rng.standard_normal(n))
+        u, _ = _fmm(torch_mod, ctx, xy, f)
+        assert _rel(u, od.direct_sum(xy, xy, f)) <= FMM_TOL
+    ctx.close()
+
+
+@pytest.mark.parametrize("max_leaf", [8, 16, 32, 128, 256])
+def test_leaf_sizes(torch_mod, max_leaf):
+    # leaf sides from 2 to 64: window table, quadrant table and global-table near fields
+    import paper_1105_3505_amd as lf
+    ctx = lf.Context(0, max_leaf=max_leaf)
+    rng = np.random.default_rng(50 + max_leaf)
+    xy = wl.uniform_box(rng, 12000, 440)
+    f = wl.zero_sum_loads(rng.standard_normal(12000))
+    u, plan = _fmm(torch_mod, ctx, xy, f)
+    assert _rel(u, od.direct_sum(xy, xy, f)) <= FMM_TOL
+    plan.close()
+    ctx.close()
+
+
+def test_mixed_precision_m2l(torch_mod):
+    # FP32 hi/lo matrix-core M2L; everything else FP64; target 1e-7
+    import paper_1105_3505_amd as lf
+    ctx = lf.Context(0, precision="mixed")
+    for seed, n, side in [(61, 1000, 256), (62, 30000, 700)]:
+        rng = np.random.default_rng(seed)
+        xy = wl.uniform_box(rng, n, side)
+        f = wl.zero_sum_loads(rng.standard_normal(n))
+        u, _ = _fmm(torch_mod, ctx, xy, f)
+        err = _rel(u, od.direct_sum(xy, xy, f))
+        print("mixed n=%d rel err %.3e" % (n, err))
+        assert err <= 1e-7
+    ctx.close()

@@ -50,7 +50,8 @@ typedef enum lfmm_status {
     LFMM_E_NOMEM = -3,        /* device or host allocation failed                        */
     LFMM_E_HIP = -4,          /* a HIP runtime call failed; the plan is unusable          */
     LFMM_E_UNSUPPORTED = -5,  /* valid request this build does not implement              */
-    LFMM_E_NODEVICE = -6      /* no GPU visible, or the device id does not exist          */
+    LFMM_E_NODEVICE = -6,     /* no GPU visible, or the device id does not exist          */
+    LFMM_E_BUSY = -7          /* a wait timed out before the request was done             */
 } lfmm_status;
 
 typedef enum lfmm_precision {
@@ -69,27 +70,25 @@ typedef struct lfmm_options {
                                  is larger (Remark 5.1); default 64                        */
     int32_t max_rank;         /* cap on the skeleton size P, 16..64, multiple of 16;
                                  default 48                                                */
-    int32_t flags;            /* LFMM_FLAG_* bits, default 0                               */
+    int32_t flags;            /* reserved, must be 0                                       */
 } lfmm_options;
 
-/* options.flags: run the first-generation kernels (one wave per M2L tile, lanes = targets
- * in the near field) instead of the default ones; same results to rounding, for comparison. */
-#define LFMM_FLAG_SIMPLE_KERNELS 1
-
 typedef struct lfmm_ctx lfmm_ctx;     /* device, phi table, per-leaf-side operator cache  */
-typedef struct lfmm_plan lfmm_plan;   /* one point set: sorted points, tree, lists and
-                                         expansion storage, resident until destroyed       */
+typedef struct lfmm_plan lfmm_plan;   /* one or more point sets (instances): sorted points,
+                                         trees, lists and expansion storage, resident until
+                                         destroyed                                          */
 typedef struct lfmm_opset lfmm_opset; /* host copy of the operators for one leaf side     */
 
 typedef struct lfmm_plan_info {
-    int64_t n_points;
-    int32_t root_bits;        /* root box side is 2^root_bits                              */
-    int32_t leaf_level;       /* L: leaves are the boxes of level L (Section 6)            */
-    int64_t leaf_side;        /* lattice side of a leaf box, 2^(root_bits - L)             */
+    int64_t n_points;         /* over all instances                                        */
+    int32_t n_instances;
+    int32_t root_bits;        /* instance 0: root box side is 2^root_bits                  */
+    int32_t leaf_level;       /* instance 0: L, leaves are the boxes of level L (Section 6) */
+    int64_t leaf_side;        /* instance 0: lattice side of a leaf, 2^(root_bits - L)     */
     int32_t rank;             /* padded skeleton size P used by the kernels                */
     int32_t leaf_kind;        /* 0: dense-model outgoing operator (Remark 8.2)             */
-    int64_t n_boxes;          /* non-empty boxes over all levels                           */
-    int64_t n_leaves;         /* non-empty leaves                                          */
+    int64_t n_boxes;          /* non-empty boxes over all levels and instances             */
+    int64_t n_leaves;         /* non-empty leaves over all instances                       */
     int64_t near_pairs;       /* (target, source) pairs summed directly (Section 2)        */
     int64_t m2l_pairs;        /* (box, interaction-list box) pairs (Section 8.2, step 3)   */
 } lfmm_plan_info;
@@ -107,9 +106,21 @@ lfmm_status lfmm_ctx_destroy(lfmm_ctx* ctx);
 /* Builds the tree of Section 6 (Morton keys, sort, levels, parent/child, neighbor and
  * interaction lists of Definition 6.1) for the n points xy_dev[2n] (device, int32), and the
  * operators for its leaf side if the context lacks them.  The points are copied; xy_dev may
- * be freed afterwards.  n >= 1. */
+ * be freed afterwards.  1 <= n <= 2^30.  The leaf level is the smallest at which no leaf
+ * holds more than max_leaf points, raised where needed so that a leaf is at most 128 cells
+ * wide (the dense-model outgoing operator of Remark 8.2 is tabulated up to that side). */
 lfmm_status lfmm_plan_create(lfmm_ctx* ctx, int64_t n, const int32_t* xy_dev, void* stream,
                              lfmm_plan** out);
+
+/* Builds one plan over n_inst independent point sets (instances): instance k has
+ * n_host[k] >= 1 points at xy_dev[k][2 n_host[k]] (device, int32; n_host and the pointer
+ * array xy_dev are host memory).  Each instance gets its own root box and tree, exactly as
+ * lfmm_plan_create would build it alone, so its potentials equal the ones of a plan of its
+ * own bit for bit; all instances share every construction and evaluation launch.  At most
+ * 2^30 points in total; LFMM_E_RANGE if the instance count and coordinate extents do not
+ * fit the 64-bit sort key (2 * root bits + bits of n_inst - 1 <= 64). */
+lfmm_status lfmm_plan_create_batch(lfmm_ctx* ctx, int32_t n_inst, const int64_t* n_host,
+                                   const int32_t* const* xy_dev, void* stream, lfmm_plan** out);
 
 /* Evaluates u_dev[i] = sum_j phi(x_i - x_j) f_dev[j] over the plan's points (eq. 1.7) by the
  * passes of Section 8.2: P2M (T_ofs), M2M (T_ofo), M2L (T_ifo), L2L (T_ifi = T_ofo^T),
@@ -117,9 +128,14 @@ lfmm_status lfmm_plan_create(lfmm_ctx* ctx, int64_t n, const int32_t* xy_dev, vo
  * arrays of n entries in the caller's point order.  Enqueued on `stream`; no sync. */
 lfmm_status lfmm_execute(lfmm_plan* plan, const double* f_dev, double* u_dev, void* stream);
 
-/* Evaluates several plans of one context in shared launches (one launch per pass covers
- * every plan).  f_dev[k], u_dev[k] belong to plans[k].  Results equal those of
- * lfmm_execute on each plan alone. */
+/* lfmm_execute for a plan of several instances: f_dev[k] and u_dev[k] (device arrays of
+ * n_host[k] float64, in instance k's caller order) belong to instance k; the pointer arrays
+ * are host memory read during the call.  One launch per pass covers every instance. */
+lfmm_status lfmm_execute_instances(lfmm_plan* plan, const double* const* f_dev,
+                                   double* const* u_dev, void* stream);
+
+/* Runs lfmm_execute on each single-instance plan of one context, in order, on one stream
+ * (separate launches per plan; build one plan with lfmm_plan_create_batch to share them). */
 lfmm_status lfmm_execute_batch(lfmm_ctx* ctx, int32_t n_plans, lfmm_plan* const* plans,
                                const double* const* f_dev, double* const* u_dev, void* stream);
 
@@ -144,22 +160,33 @@ lfmm_status lfmm_plan_set_timing(lfmm_plan* plan, int32_t enable);
  * ms_host[LFMM_NUM_PHASES]; waits for that execute to finish. */
 lfmm_status lfmm_plan_phase_times(lfmm_plan* plan, double* ms_host);
 
-/* Plan internals that lfmm_plan_export copies to the host, for inspection and tests. */
+/* Plan internals that lfmm_plan_export copies to the host, for inspection and tests.
+ * Points of all instances are concatenated in instance order, Morton-ordered inside each
+ * instance.  Boxes are numbered by height above their instance's leaf level (all leaves
+ * first), then by instance, then by Morton key. */
 typedef enum lfmm_export_item {
-    LFMM_EXPORT_POINTS = 0,     /* int32 [n][2]: points in Morton order, shifted so the root
-                                   box is [0, 2^root_bits)^2                                  */
-    LFMM_EXPORT_PERM = 1,       /* int32 [n]: caller index of each Morton-ordered point      */
-    LFMM_EXPORT_LEVEL_OFFSETS = 2, /* int32 [L+2]: boxes of level l are [off[l], off[l+1]) */
+    LFMM_EXPORT_POINTS = 0,     /* int32 [n][2]: points in Morton order, shifted so that the
+                                   instance's root box is [0, 2^root_bits)^2                 */
+    LFMM_EXPORT_PERM = 1,       /* int32 [n]: index of each Morton-ordered point in its
+                                   instance's caller order                                   */
+    LFMM_EXPORT_LEVEL_BASE = 2, /* int32 [L+1], instance 0: boxes of level l are
+                                   [base[l], base[l] + count[l])                             */
     LFMM_EXPORT_BOX_KEY = 3,    /* uint64 [n_boxes]: Morton key of the box at its level      */
     LFMM_EXPORT_BOX_BEGIN = 4,  /* int32 [n_boxes]: first Morton-ordered point of the box    */
     LFMM_EXPORT_BOX_END = 5,    /* int32 [n_boxes]: one past its last point                  */
-    LFMM_EXPORT_BOX_PARENT = 6, /* int32 [n_boxes]: parent box, -1 for the root              */
+    LFMM_EXPORT_BOX_PARENT = 6, /* int32 [n_boxes]: parent box, -1 for a root                */
     LFMM_EXPORT_BOX_CHILD = 7,  /* int32 [n_boxes][4]: child c = x bit + 2 y bit, or -1      */
-    LFMM_EXPORT_INTERACTION = 8,/* int32 [boxes of levels >= 2][27]: interaction list slots  */
-    LFMM_EXPORT_NEIGHBOR = 9,   /* int32 [n_leaves][9]: 3x3 neighbourhood of each leaf       */
-    LFMM_EXPORT_QHAT = 10,      /* float64 [n_boxes][rank]: outgoing expansions (last execute) */
-    LFMM_EXPORT_UHAT = 11,      /* float64 [n_boxes][rank]: incoming expansions (last execute) */
-    LFMM_EXPORT_LOADS = 12      /* float64 [n]: loads of the last execute in Morton order   */
+    LFMM_EXPORT_INTERACTION = 8,/* int32 [n_boxes][27]: interaction list slots, in the order
+                                   dy = -3..3 outer, dx = -3..3 inner over the 7x7 block of
+                                   the parent's neighbours minus the 3x3 block around the
+                                   box; -1 = empty slot or level < 2                         */
+    LFMM_EXPORT_NEIGHBOR = 9,   /* int32 [n_boxes][9]: 3x3 neighbourhood, dy outer, dx inner */
+    LFMM_EXPORT_QHAT = 10,      /* float64 [n_boxes][48]: outgoing expansions (last execute) */
+    LFMM_EXPORT_UHAT = 11,      /* float64 [n_boxes][48]: incoming expansions (last execute) */
+    LFMM_EXPORT_LOADS = 12,     /* float64 [n]: loads of the last execute in Morton order   */
+    LFMM_EXPORT_LEVEL_COUNT = 13, /* int32 [L+1], instance 0: boxes of level l              */
+    LFMM_EXPORT_BOX_LEVEL = 14, /* int8 [n_boxes]: level of the box in its instance's tree   */
+    LFMM_EXPORT_BOX_INSTANCE = 15 /* int32 [n_boxes]: instance of the box                    */
 } lfmm_export_item;
 
 /* Copies plan item `item` into host_out.  With host_out NULL, stores the byte size in *bytes;
@@ -184,6 +211,54 @@ lfmm_status lfmm_direct(lfmm_ctx* ctx, int64_t n_t, const int32_t* txy_dev, int6
 
 const char* lfmm_status_string(lfmm_status s);
 const char* lfmm_last_error(void);
+
+/* ---- serving: continuous batching of solve requests on one context ------------------- */
+
+/* A server owns a worker thread that drives its context (the caller must not use that
+ * context while the server lives).  Requests are admitted in arrival order, as many per
+ * scheduling iteration as the limits below allow; each iteration builds one forest plan over
+ * its admitted requests (lfmm_plan_create_batch) and evaluates it, on one of max_inflight
+ * streams, so that the tree construction of a new iteration overlaps on the device with
+ * the evaluation of earlier ones.  A request's potentials equal, bit for bit, those of
+ * lfmm_solve on the same input alone, whatever it was batched with.  Plans stay resident
+ * until their evaluation has completed, then their memory returns to the context's pool. */
+typedef struct lfmm_server lfmm_server;
+
+typedef struct lfmm_server_options {
+    size_t hbm_budget_bytes;  /* bound on lfmm_plan_footprint_bytes summed over the requests
+                                 on the device; 0 = half of the device's free memory      */
+    int32_t max_batch;        /* most requests admitted in one iteration; 0 = 256          */
+    int32_t max_inflight;     /* iterations on the device at once (one stream each); 0 = 3 */
+    int64_t max_batch_points; /* most points admitted in one iteration; 0 = 2^24           */
+} lfmm_server_options;
+
+typedef struct lfmm_request_stats {
+    int32_t status;           /* lfmm_status of the request                                */
+    int32_t batch_size;       /* requests in the iteration that served it                  */
+    int64_t batch_id;         /* scheduling iteration, counted from 0                      */
+    double t_submit;          /* seconds since server creation: submit call                */
+    double t_admit;           /* admitted into an iteration                                */
+    double t_done;            /* its evaluation was seen complete on the device            */
+} lfmm_request_stats;
+
+/* Starts a server on ctx (opt may be NULL for the defaults). */
+lfmm_status lfmm_server_create(lfmm_ctx* ctx, const lfmm_server_options* opt, lfmm_server** out);
+
+/* Queues a solve of n points: xy_dev[2n] int32, f_dev[n] and u_dev[n] float64, all device
+ * memory that the caller keeps valid and untouched until lfmm_server_wait reports the
+ * request done.  Thread-safe.  *ticket identifies the request.  LFMM_E_NOMEM if the request
+ * alone exceeds the memory budget. */
+lfmm_status lfmm_server_submit(lfmm_server* srv, int64_t n, const int32_t* xy_dev,
+                               const double* f_dev, double* u_dev, uint64_t* ticket);
+
+/* Waits up to timeout_s seconds (< 0: without limit) for request `ticket`; fills *out when
+ * it is done and forgets the ticket.  LFMM_E_BUSY if it is not done in time.  Returns the
+ * request's own status otherwise.  Thread-safe. */
+lfmm_status lfmm_server_wait(lfmm_server* srv, uint64_t ticket, double timeout_s,
+                             lfmm_request_stats* out);
+
+/* Finishes every queued request, stops the worker and frees the server. */
+lfmm_status lfmm_server_destroy(lfmm_server* srv);
 
 /* ---- host-only calls (no GPU needed): the library's own phi and operators ------------ */
 

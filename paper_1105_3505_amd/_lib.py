@@ -29,7 +29,8 @@ class _Options(ctypes.Structure):
 
 
 class _PlanInfo(ctypes.Structure):
-    _fields_ = [("n_points", _i64), ("root_bits", _i32), ("leaf_level", _i32), ("leaf_side", _i64),
+    _fields_ = [("n_points", _i64), ("n_instances", _i32), ("root_bits", _i32), ("leaf_level", _i32),
+                ("leaf_side", _i64),
                 ("rank", _i32), ("leaf_kind", _i32), ("n_boxes", _i64), ("n_leaves", _i64),
                 ("near_pairs", _i64), ("m2l_pairs", _i64)]
 
@@ -47,7 +48,9 @@ def _load():
         "lfmm_ctx_create": [_i32, _vp, _vp],
         "lfmm_ctx_destroy": [_vp],
         "lfmm_plan_create": [_vp, _i64, _vp, _vp, _vp],
+        "lfmm_plan_create_batch": [_vp, _i32, _vp, _vp, _vp, _vp],
         "lfmm_execute": [_vp, _vp, _vp, _vp],
+        "lfmm_execute_instances": [_vp, _vp, _vp, _vp],
         "lfmm_execute_batch": [_vp, _i32, _vp, _vp, _vp, _vp],
         "lfmm_plan_get_info": [_vp, _vp],
         "lfmm_plan_set_timing": [_vp, _i32],
@@ -91,9 +94,6 @@ def exported_symbols() -> list[str]:
     with open(_HEADER) as fh:
         text = fh.read()
     return sorted(set(re.findall(r"\b(lfmm_[a-z_0-9]+)\s*\(", text)))
-
-
-FLAG_SIMPLE_KERNELS = 1
 
 
 def _options(eps=None, max_leaf=None, precision=None, proxy_per_edge=None, max_rank=None,
@@ -167,7 +167,21 @@ class Context:
         ptr = _dev_tensor(xy, torch.int32, (2,), "xy")
         h = ctypes.c_void_p()
         _check(_lib.lfmm_plan_create(self._h, int(xy.shape[0]), ptr, _stream_handle(stream), ctypes.byref(h)))
-        plan = Plan(self, h, int(xy.shape[0]))
+        plan = Plan(self, h, [int(xy.shape[0])])
+        self._plans.add(plan)
+        return plan
+
+    def plan_batch(self, xys, stream=None) -> "Plan":
+        """One plan over several point sets (lfmm_plan_create_batch): every pass is one
+        launch over all of them; each instance's result equals that of a plan of its own."""
+        import torch
+        k = len(xys)
+        ptrs = (ctypes.c_void_p * k)(*[_dev_tensor(xy, torch.int32, (2,), "xy").value for xy in xys])
+        sizes = np.ascontiguousarray([int(xy.shape[0]) for xy in xys], dtype=np.int64)
+        h = ctypes.c_void_p()
+        _check(_lib.lfmm_plan_create_batch(self._h, k, sizes.ctypes.data_as(_vp), ptrs, _stream_handle(stream),
+                                           ctypes.byref(h)))
+        plan = Plan(self, h, [int(v) for v in sizes])
         self._plans.add(plan)
         return plan
 
@@ -207,12 +221,13 @@ class Context:
 
 
 class Plan:
-    """lfmm_plan: the tree of one point set, resident on the device."""
+    """lfmm_plan: the trees of one or more point sets (instances), resident on the device."""
 
-    def __init__(self, ctx: Context, handle, n: int):
+    def __init__(self, ctx: Context, handle, sizes):
         self.ctx = ctx
         self._h = handle
-        self.n = n
+        self.sizes = list(sizes)
+        self.n = sum(self.sizes)
 
     def execute(self, f, u=None, stream=None):
         import torch
@@ -224,12 +239,29 @@ class Plan:
                                  _dev_tensor(u, torch.float64, (), "u"), _stream_handle(stream)))
         return u
 
+    def execute_instances(self, fs, us=None, stream=None):
+        """lfmm_execute_instances: fs[k] (and us[k]) belong to instance k."""
+        import torch
+        k = len(self.sizes)
+        if len(fs) != k:
+            raise ValueError("one load vector per instance")
+        for f, n in zip(fs, self.sizes):
+            if int(f.shape[0]) != n:
+                raise ValueError("f must have one load per point of its instance")
+        if us is None:
+            us = [torch.empty(n, dtype=torch.float64, device=f.device) for f, n in zip(fs, self.sizes)]
+        fp = (ctypes.c_void_p * k)(*[_dev_tensor(f, torch.float64, (), "f").value for f in fs])
+        up = (ctypes.c_void_p * k)(*[_dev_tensor(u, torch.float64, (), "u").value for u in us])
+        _check(_lib.lfmm_execute_instances(self._h, fp, up, _stream_handle(stream)))
+        return us
+
     PHASES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf")
-    EXPORTS = {"points": (0, np.int32, 2), "perm": (1, np.int32, 0), "level_offsets": (2, np.int32, 0),
+    EXPORTS = {"points": (0, np.int32, 2), "perm": (1, np.int32, 0), "level_base": (2, np.int32, 0),
                "box_key": (3, np.uint64, 0), "box_begin": (4, np.int32, 0), "box_end": (5, np.int32, 0),
                "box_parent": (6, np.int32, 0), "box_child": (7, np.int32, 4), "interaction": (8, np.int32, 27),
                "neighbor": (9, np.int32, 9), "qhat": (10, np.float64, 48), "uhat": (11, np.float64, 48),
-               "loads": (12, np.float64, 0)}
+               "loads": (12, np.float64, 0), "level_count": (13, np.int32, 0), "box_level": (14, np.int8, 0),
+               "box_instance": (15, np.int32, 0)}
 
     def export(self, name: str) -> np.ndarray:
         """Copy of a plan internal (lfmm_plan_export) as a numpy array."""

@@ -21,4 +21,10 @@ lfmm_status fail(lfmm_status s, const std::string& msg);
 lfmm_status validate_options(const lfmm_options* o);
 OperatorParams operator_params(const lfmm_options& o);
 
+// Frees a plan whose device work is known to be complete (its last execute's completion
+// was observed), without the device-wide synchronisation of lfmm_plan_destroy.
+void plan_destroy_completed(lfmm_plan* plan);
+// Device of a context.
+int ctx_device(const lfmm_ctx* ctx);
+
 }  // namespace lfmm

@@ -1,5 +1,5 @@
 // Device part of the C ABI: contexts (phi table and cached operators on the GPU), plans
-// (the quadtree of one point set, built on the GPU) and evaluation (Section 8.2 passes).
+// (the quadtrees of one or more point sets, built on the GPU) and evaluation (Section 8.2).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,10 +16,6 @@
 #include "host_math.h"
 #include "kernels.h"
 #include "lfmm.h"
-
-namespace lfmm {
-hipError_t upload_dslots();
-}
 
 using namespace lfmm;
 
@@ -151,10 +147,44 @@ struct CachedOps {
 };
 
 }  // namespace
+// Pinned host blocks for the per-execute pointer tables of batched plans, cached by size
+// class: allocating or freeing pinned memory may synchronise the device.
+class PinnedPool {
+  public:
+    void* acquire(size_t bytes, size_t* got) {
+        size_t cls = 4096;
+        while (cls < bytes) cls <<= 1;
+        *got = cls;
+        {
+            std::lock_guard<std::mutex> lock(mu_);
+            auto it = free_.find(cls);
+            if (it != free_.end()) {
+                void* p = it->second;
+                free_.erase(it);
+                return p;
+            }
+        }
+        void* p = nullptr;
+        LFMM_HIP(hipHostMalloc(&p, cls));
+        return p;
+    }
+    void release(void* p, size_t cls) {
+        std::lock_guard<std::mutex> lock(mu_);
+        free_.emplace(cls, p);
+    }
+    ~PinnedPool() {
+        for (auto& kv : free_) (void)hipHostFree(kv.second);
+    }
+
+  private:
+    std::multimap<size_t, void*> free_;
+    std::mutex mu_;
+};
 
 struct lfmm_ctx {
     int device = 0;
     lfmm_options opt{};
+    PinnedPool pinned;
     DevicePool pool;             // plan storage and temporaries (declared first: freed last)
     Arena table_mem;
     double* phi_oct = nullptr;   // octant table, radius 128
@@ -163,22 +193,42 @@ struct lfmm_ctx {
     std::mutex mu;
 };
 
+struct TileRange {
+    int32_t t0 = 0, n = 0;
+};
+
 struct lfmm_plan {
     lfmm_ctx* ctx = nullptr;
-    CachedOps* ops = nullptr;
-    int64_t n = 0;
-    int D = 0, L = 0;
-    int64_t side = 1;
-    std::vector<int32_t> off;    // level offsets, L + 2 entries
-    int32_t nboxes = 0, nleaves = 0, leaf_off = 0, ilist_off = 0, max_tiles = 0;
-    Arena mem;
-    int32_t *pts = nullptr, *perm = nullptr, *box_pt0 = nullptr, *box_pt1 = nullptr, *box_parent = nullptr,
-            *box_child = nullptr, *ilist = nullptr, *nlist = nullptr, *cls_cnt = nullptr, *cls_box = nullptr,
-            *ntiles = nullptr;
+    int32_t K = 0;                          // instances
+    int64_t n = 0;                          // points of all instances
+    std::vector<int32_t> pt_off;            // K + 1
+    std::vector<InstInfo> inst;             // host copy of the instance table
+    std::vector<CachedOps*> ops;            // operator sets used, by index
+    int Dmax = 0, Lmax = 0, Hmax = 0;
+    int32_t nbox = 0, nleaf = 0;
+    std::vector<int32_t> hbase;             // first box of each height, Hmax + 2 entries
+    std::vector<TileRange> leaf_of_ops;     // leaves of each operator set
+    TileRange m2l;                          // M2L tiles (class-sorted, some empty)
+    std::vector<TileRange> m2m, l2l;        // tiles per height
+    int64_t m2l_pairs = 0;
+    Arena mem_small, mem_pts, mem_box;
+    InstInfo* d_inst = nullptr;
+    OpsPtrs* d_ops = nullptr;
+    uint8_t* d_far = nullptr;
+    ExecPtrs* d_exec = nullptr;
+    int32_t* d_m2l_ntiles = nullptr;
+    int32_t *pts = nullptr, *perm = nullptr, *pinst = nullptr;
+    uint32_t* pkey = nullptr;
+    double* fs = nullptr;
     uint64_t* box_key = nullptr;
-    M2LTile* tiles = nullptr;
-    double *Q = nullptr, *U = nullptr, *fs = nullptr;
-    uint32_t* pkey = nullptr;    // window keys of the points (leaves of side <= 16)
+    int32_t *box_pt0 = nullptr, *box_pt1 = nullptr, *box_parent = nullptr, *box_child = nullptr,
+            *box_inst = nullptr, *nb9 = nullptr, *il27 = nullptr, *cls_box = nullptr;
+    int8_t* box_lev = nullptr;
+    BoxTile* tiles = nullptr;
+    double *Q = nullptr, *U = nullptr;
+    ExecPtrs* h_exec = nullptr;             // pinned staging of the per-execute pointers
+    size_t h_exec_cls = 0;
+    hipEvent_t exec_copied = nullptr;       // the last staging copy has been read
     bool failed = false;
     bool timing = false;
     bool timed_once = false;
@@ -186,6 +236,8 @@ struct lfmm_plan {
     ~lfmm_plan() {
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
+        if (exec_copied) (void)hipEventDestroy(exec_copied);
+        if (h_exec) ctx->pinned.release(h_exec, h_exec_cls);
     }
 };
 
@@ -300,28 +352,78 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st) {
     return raw;
 }
 
-void build_plan(lfmm_plan* pl, const int32_t* xy, hipStream_t st) {
-    lfmm_ctx* ctx = pl->ctx;
-    const int64_t n = pl->n;
-    const int nleaf_max = ctx->opt.max_leaf;
+OpsPtrs ops_ptrs(const CachedOps* co) {
+    OpsPtrs p{};
+    p.leafT = co->dev.leafT;
+    p.ofo_rm = co->dev.ofo_rm;
+    p.ofo_cm = co->dev.ofo_cm;
+    p.ifo = co->dev.ifo;
+    p.ifo_hi = co->dev.ifo_hi;
+    p.ifo_lo = co->dev.ifo_lo;
+    p.mono = co->dev.mono;
+    p.rank = co->dev.rank;
+    p.side = co->dev.leaf_side;
+    p.nlev = co->dev.nlev;
+    return p;
+}
 
-    // ---- temporaries sized by n ----------------------------------------------------------
+template <class T>
+void upload(T* dst, const std::vector<T>& src, hipStream_t st) {
+    if (!src.empty()) LFMM_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+// Builds the forest of K point sets: Section 6 tree of every instance, lists of Definition 6.1,
+// operator sets for every leaf side used, and the tiles of the matrix passes.
+void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t* const* xy_ptrs, hipStream_t st) {
+    lfmm_ctx* ctx = pl->ctx;
+    const int nleaf_max = ctx->opt.max_leaf;
+    pl->K = K;
+    pl->pt_off.assign(size_t(K) + 1, 0);
+    for (int32_t k = 0; k < K; ++k) pl->pt_off[size_t(k) + 1] = pl->pt_off[size_t(k)] + int32_t(sizes[k]);
+    const int64_t n = pl->pt_off[size_t(K)];
+    pl->n = n;
+
+    // chunks of <= kChunk points, each inside one instance
+    std::vector<Chunk> chunks;
+    std::vector<int32_t> chunk_first(static_cast<size_t>(K) + 1, 0);
+    for (int32_t k = 0; k < K; ++k) {
+        chunk_first[size_t(k)] = int32_t(chunks.size());
+        for (int32_t b = pl->pt_off[size_t(k)]; b < pl->pt_off[size_t(k) + 1]; b += kChunk)
+            chunks.push_back(Chunk{k, b, std::min(b + kChunk, pl->pt_off[size_t(k) + 1]), 0});
+    }
+    chunk_first[size_t(K)] = int32_t(chunks.size());
+    const int32_t nch = int32_t(chunks.size());
+
+    // ---- temporaries sized by n (one reserve per take) ------------------------------------
     Arena tmp(&ctx->pool);
-    // one reserve per take below (each piece is 256-byte aligned)
-    tmp.reserve(4 * 4);                             // bbox
-    tmp.reserve(64 * 4);                            // level histogram + max
-    tmp.reserve(size_t(n) * 8);                     // keys
-    tmp.reserve(size_t(n) * 8);                     // keys_tmp
-    tmp.reserve(size_t(n) * 4);                     // vals
-    tmp.reserve(size_t(n) * 4);                     // vals_tmp
-    tmp.reserve(size_t(n));                         // cl
-    tmp.reserve(size_t(n) * 4);                     // flags
-    tmp.reserve(size_t(n) * 4);                     // scan
+    tmp.reserve(size_t(K) * sizeof(void*));     // xy table
+    tmp.reserve(size_t(K + 1) * 4);             // pt_off
+    tmp.reserve(size_t(nch) * sizeof(Chunk));
+    tmp.reserve(size_t(K + 1) * 4);             // chunk_first
+    tmp.reserve(size_t(nch) * 16);              // bbox partials
+    tmp.reserve(size_t(K) * 16);                // bbox
+    tmp.reserve(size_t(K) * (kMaxLevels + 2) * 4);   // level histograms
+    tmp.reserve(size_t(K) * 4);                 // lookahead maxima
+    tmp.reserve(K > 1 ? size_t(n) * 8 : 0);     // concatenated points
+    tmp.reserve(size_t(n) * 8);                 // keys
+    tmp.reserve(size_t(n) * 8);                 // keys_tmp
+    tmp.reserve(size_t(n) * 4);                 // vals
+    tmp.reserve(size_t(n) * 4);                 // vals_tmp
+    tmp.reserve(size_t(n));                     // cl
+    tmp.reserve(size_t(n) * 4);                 // flags
+    tmp.reserve(size_t(n) * 4);                 // scan
     tmp.reserve(radix_scratch_bytes(n));
     tmp.reserve(scan_scratch_bytes(n, 1));
     tmp.allocate();
-    int32_t* bbox = tmp.take<int32_t>(4);
-    int32_t* stats = tmp.take<int32_t>(64);
+    const int32_t** d_xytab = tmp.take<const int32_t*>(K);
+    int32_t* d_ptoff = tmp.take<int32_t>(K + 1);
+    Chunk* d_chunks = tmp.take<Chunk>(nch);
+    int32_t* d_chfirst = tmp.take<int32_t>(K + 1);
+    int32_t* d_part = tmp.take<int32_t>(size_t(nch) * 4);
+    int32_t* d_bbox = tmp.take<int32_t>(size_t(K) * 4);
+    int32_t* d_hist = tmp.take<int32_t>(size_t(K) * (kMaxLevels + 2));
+    int32_t* d_maxc = tmp.take<int32_t>(K);
+    int32_t* d_xyc = (K > 1) ? tmp.take<int32_t>(size_t(n) * 2) : nullptr;
     uint64_t* keys = tmp.take<uint64_t>(n);
     uint64_t* keys_tmp = tmp.take<uint64_t>(n);
     uint32_t* vals = tmp.take<uint32_t>(n);
@@ -332,177 +434,394 @@ void build_plan(lfmm_plan* pl, const int32_t* xy, hipStream_t st) {
     void* rscr = tmp.take<char>(radix_scratch_bytes(n));
     void* sscr = tmp.take<char>(scan_scratch_bytes(n, 1));
 
-    // ---- root box --------------------------------------------------------------------------
-    int32_t init[4] = {INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN};
-    LFMM_HIP(hipMemcpyAsync(bbox, init, sizeof(init), hipMemcpyHostToDevice, st));
-    launch_bbox(xy, n, bbox, st);
-    int32_t bb[4];
-    LFMM_HIP(hipMemcpyAsync(bb, bbox, sizeof(bb), hipMemcpyDeviceToHost, st));
+    std::vector<const int32_t*> xytab(xy_ptrs, xy_ptrs + K);
+    upload(d_xytab, xytab, st);
+    upload(d_ptoff, pl->pt_off, st);
+    upload(d_chunks, chunks, st);
+    upload(d_chfirst, chunk_first, st);
+    const int32_t* xy = xy_ptrs[0];
+    if (K > 1) {
+        launch_concat(K, d_xytab, d_ptoff, n, d_xyc, st);
+        xy = d_xyc;
+    }
+
+    // ---- root boxes ----------------------------------------------------------------------
+    launch_bbox_chunks(xy, d_chunks, nch, d_part, st);
+    launch_bbox_final(d_part, d_chfirst, K, d_bbox, st);
+    std::vector<int32_t> bb(static_cast<size_t>(K) * 4);
+    LFMM_HIP(hipMemcpyAsync(bb.data(), d_bbox, bb.size() * 4, hipMemcpyDeviceToHost, st));
     LFMM_HIP(hipStreamSynchronize(st));
-    const int64_t extent = std::max(int64_t(bb[2]) - bb[0], int64_t(bb[3]) - bb[1]) + 1;
-    if (extent > (int64_t(1) << 31)) throw std::out_of_range("coordinate extent of 2^31 or more");
-    const int D = bits_for_extent(extent);
-    pl->D = D;
+    pl->inst.assign(size_t(K), InstInfo{});
+    int Dmax = 0;
+    for (int32_t k = 0; k < K; ++k) {
+        InstInfo& I = pl->inst[size_t(k)];
+        const int32_t* b = &bb[size_t(k) * 4];
+        const int64_t extent = std::max(int64_t(b[2]) - b[0], int64_t(b[3]) - b[1]) + 1;
+        if (extent > (int64_t(1) << 31)) throw std::out_of_range("coordinate extent of 2^31 or more");
+        I.pt0 = pl->pt_off[size_t(k)];
+        I.pt1 = pl->pt_off[size_t(k) + 1];
+        I.ox = b[0];
+        I.oy = b[1];
+        I.D = bits_for_extent(extent);
+        Dmax = std::max(Dmax, I.D);
+    }
+    int ibits = 0;
+    while ((int64_t(1) << ibits) < K) ++ibits;
+    if (2 * Dmax + ibits > 64) throw std::out_of_range("too many instances for the coordinate extent");
+    pl->Dmax = Dmax;
+
+    // plan storage sized by K and n
+    Arena& ms = pl->mem_small;
+    ms.set_pool(&ctx->pool);
+    ms.reserve(size_t(K) * sizeof(InstInfo));
+    ms.reserve(size_t(64) * sizeof(OpsPtrs));
+    ms.reserve(size_t(K));                      // far flags
+    ms.reserve(size_t(K) * sizeof(ExecPtrs));
+    ms.reserve(16);                             // M2L tile count
+    ms.allocate();
+    pl->d_inst = ms.take<InstInfo>(K);
+    pl->d_ops = ms.take<OpsPtrs>(64);
+    pl->d_far = ms.take<uint8_t>(K);
+    pl->d_exec = ms.take<ExecPtrs>(K);
+    pl->d_m2l_ntiles = ms.take<int32_t>(4);
+    Arena& mp = pl->mem_pts;
+    mp.set_pool(&ctx->pool);
+    mp.reserve(size_t(n) * 8);                  // pts
+    mp.reserve(size_t(n) * 4);                  // perm
+    mp.reserve(size_t(n) * 4);                  // pinst
+    mp.reserve(size_t(n) * 4);                  // pkey
+    mp.reserve(size_t(n) * 8);                  // fs
+    mp.allocate();
+    pl->pts = mp.take<int32_t>(size_t(n) * 2);
+    pl->perm = mp.take<int32_t>(n);
+    pl->pinst = mp.take<int32_t>(n);
+    pl->pkey = mp.take<uint32_t>(n);
+    pl->fs = mp.take<double>(n);
+    upload(pl->d_inst, pl->inst, st);
 
     // ---- Morton order ----------------------------------------------------------------------
-    launch_morton(xy, n, bb[0], bb[1], keys, vals, st);
-    radix_sort_pairs(keys, vals, keys_tmp, vals_tmp, n, 2 * D, rscr, st);
+    launch_keys(xy, d_ptoff, K, pl->d_inst, Dmax, n, keys, vals, st);
+    const int which = radix_sort_pairs(keys, vals, keys_tmp, vals_tmp, n, 2 * Dmax + ibits, rscr, st);
+    uint64_t* skeys = which ? keys_tmp : keys;
+    uint32_t* svals = which ? vals_tmp : vals;
+    launch_gather_sorted(skeys, svals, xy, pl->d_inst, d_ptoff, Dmax, K, n, pl->pts, pl->perm, pl->pinst, st);
 
-    // ---- leaf level and box counts ----------------------------------------------------------
-    LFMM_HIP(hipMemsetAsync(stats, 0, 64 * 4, st));
-    launch_level_stats(keys, n, D, nleaf_max, cl, stats, stats + 40, st);
-    int32_t hs[64];
-    LFMM_HIP(hipMemcpyAsync(hs, stats, sizeof(hs), hipMemcpyDeviceToHost, st));
+    // ---- leaf levels and box counts ---------------------------------------------------------
+    LFMM_HIP(hipMemsetAsync(d_hist, 0, size_t(K) * (kMaxLevels + 2) * 4, st));
+    LFMM_HIP(hipMemsetAsync(d_maxc, 0, size_t(K) * 4, st));
+    launch_level_stats(skeys, d_chunks, nch, pl->d_inst, Dmax, nleaf_max, cl, d_hist, d_maxc, st);
+    std::vector<int32_t> hist(static_cast<size_t>(K) * (kMaxLevels + 2)), maxc(static_cast<size_t>(K));
+    LFMM_HIP(hipMemcpyAsync(hist.data(), d_hist, hist.size() * 4, hipMemcpyDeviceToHost, st));
+    LFMM_HIP(hipMemcpyAsync(maxc.data(), d_maxc, maxc.size() * 4, hipMemcpyDeviceToHost, st));
     LFMM_HIP(hipStreamSynchronize(st));
-    int L = (n > nleaf_max) ? std::min(D, hs[40] + 1) : 0;
-    // leaves no wider than the dense-model limit (Remark 8.2)
-    int min_L = 0;
-    while ((int64_t(1) << (D - min_L)) > kDenseLeafMax) ++min_L;
-    L = std::max(L, min_L);
-    pl->L = L;
-    pl->side = int64_t(1) << (D - L);
-    pl->off.assign(size_t(L) + 2, 0);
-    for (int lev = 0; lev <= L; ++lev) {
-        int32_t b = 0;
-        for (int c = -1; c < lev; ++c) b += hs[c + 1];
-        pl->off[size_t(lev) + 1] = pl->off[size_t(lev)] + b;
-    }
-    pl->nboxes = pl->off[size_t(L) + 1];
-    pl->nleaves = pl->off[size_t(L) + 1] - pl->off[size_t(L)];
-    pl->leaf_off = pl->off[size_t(L)];
-    pl->ilist_off = (L >= 2) ? pl->off[2] : pl->nboxes;
-    const int32_t n_m2l = pl->nboxes - pl->ilist_off;
-    int32_t max_tiles = 0;
-    for (int lev = 2; lev <= L; ++lev) max_tiles += (pl->off[size_t(lev) + 1] - pl->off[size_t(lev)] + 15) / 16 + 4;
-    pl->max_tiles = max_tiles;
 
-    // ---- plan storage ------------------------------------------------------------------------
+    std::map<int64_t, int> side_index;
+    std::vector<int> nlev_of_side;
+    std::vector<int64_t> side_of;
+    int Lmax = 0;
+    std::vector<std::vector<int32_t>> cnt(static_cast<size_t>(K));
+    for (int32_t k = 0; k < K; ++k) {
+        InstInfo& I = pl->inst[size_t(k)];
+        const int64_t nk = I.pt1 - I.pt0;
+        int L = (nk > nleaf_max) ? std::min(I.D, maxc[size_t(k)] + 1) : 0;
+        int min_L = 0;   // leaves no wider than the dense-model limit (Remark 8.2)
+        while ((int64_t(1) << (I.D - min_L)) > kDenseLeafMax) ++min_L;
+        L = std::max(L, min_L);
+        I.L = L;
+        Lmax = std::max(Lmax, L);
+        const int64_t side = int64_t(1) << (I.D - L);
+        auto it = side_index.find(side);
+        if (it == side_index.end()) {
+            it = side_index.emplace(side, int(side_of.size())).first;
+            side_of.push_back(side);
+            nlev_of_side.push_back(1);
+        }
+        I.ops = it->second;
+        nlev_of_side[size_t(I.ops)] = std::max(nlev_of_side[size_t(I.ops)], std::max(L - 1, 1));
+        cnt[size_t(k)].assign(size_t(L) + 1, 0);
+        for (int lev = 0; lev <= L; ++lev) {
+            int32_t b = 0;
+            for (int c = -1; c < lev; ++c) b += hist[size_t(k) * (kMaxLevels + 2) + size_t(c + 1)];
+            cnt[size_t(k)][size_t(lev)] = b;
+            I.lev_count[lev] = b;
+        }
+    }
+    pl->Lmax = Lmax;
+    pl->Hmax = Lmax;
+    if (side_of.size() > 64) throw std::out_of_range("more than 64 distinct leaf sides in one plan");
+    pl->ops.resize(side_of.size());
+    for (size_t o = 0; o < side_of.size(); ++o) pl->ops[o] = get_ops(ctx, side_of[o], nlev_of_side[o], st);
+
+    // instance order inside every height block: by operator set, then deepest first, so that
+    // the boxes of one operator set with level >= 2 (or >= 3) form one contiguous range
+    std::vector<int32_t> order(static_cast<size_t>(K));
+    for (int32_t k = 0; k < K; ++k) order[size_t(k)] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const InstInfo &A = pl->inst[size_t(a)], &B = pl->inst[size_t(b)];
+        if (A.ops != B.ops) return A.ops < B.ops;
+        return A.L > B.L;
+    });
+    const int H = pl->Hmax;
+    pl->hbase.assign(size_t(H) + 2, 0);
+    int32_t cur = 0;
+    for (int h = 0; h <= H; ++h) {
+        pl->hbase[size_t(h)] = cur;
+        for (int32_t k : order) {
+            InstInfo& I = pl->inst[size_t(k)];
+            if (I.L < h) continue;
+            const int lev = I.L - h;
+            I.lev_base[lev] = cur;
+            cur += cnt[size_t(k)][size_t(lev)];
+        }
+    }
+    pl->hbase[size_t(H) + 1] = cur;
+    pl->nbox = cur;
+    pl->nleaf = pl->hbase[1];
+    {
+        int32_t r = 0;
+        for (int32_t k = 0; k < K; ++k) {
+            pl->inst[size_t(k)].leaf_rank0 = r;
+            r += cnt[size_t(k)][size_t(pl->inst[size_t(k)].L)];
+        }
+    }
+    // range of boxes of height h, operator set o and level >= minlev
+    auto range_of = [&](int h, int o, int minlev, int32_t& g0, int32_t& g1) {
+        g0 = g1 = -1;
+        for (int32_t k : order) {
+            const InstInfo& I = pl->inst[size_t(k)];
+            if (I.ops != o || I.L < h || I.L - h < minlev) continue;
+            const int lev = I.L - h;
+            if (g0 < 0) g0 = I.lev_base[lev];
+            g1 = I.lev_base[lev] + cnt[size_t(k)][size_t(lev)];
+        }
+    };
+    pl->leaf_of_ops.assign(side_of.size(), TileRange{});
+    for (size_t o = 0; o < side_of.size(); ++o) {
+        int32_t g0, g1;
+        range_of(0, int(o), 0, g0, g1);
+        if (g0 >= 0) pl->leaf_of_ops[o] = TileRange{g0, g1 - g0};
+    }
+    // groups for the class-sorted passes and the M2M tiles
+    std::vector<BoxGroup> m2l_groups, l2l_groups;
+    std::vector<BoxTile> m2m_tiles;
+    pl->m2m.assign(size_t(H) + 1, TileRange{});
+    pl->l2l.assign(size_t(H) + 1, TileRange{});
+    int32_t cls_slots = 0, tile_slots = 0;
+    for (int h = 0; h <= H; ++h)
+        for (size_t o = 0; o < side_of.size(); ++o) {
+            int32_t g0, g1;
+            range_of(h, int(o), 2, g0, g1);
+            if (g0 < 0 || g1 <= g0) continue;
+            const int32_t cap = (g1 - g0 + 15) / 16 + 3;
+            m2l_groups.push_back(BoxGroup{int32_t(o), h, g0, g1, cls_slots, tile_slots, cap, 0});
+            cls_slots += 4 * (g1 - g0);
+            tile_slots += cap;
+        }
+    pl->m2l = TileRange{0, tile_slots};
+    for (int h = 0; h <= H; ++h) {
+        pl->l2l[size_t(h)].t0 = tile_slots;
+        for (size_t o = 0; o < side_of.size(); ++o) {
+            int32_t g0, g1;
+            range_of(h, int(o), 3, g0, g1);
+            if (g0 < 0 || g1 <= g0) continue;
+            const int32_t cap = (g1 - g0 + 15) / 16 + 3;
+            l2l_groups.push_back(BoxGroup{int32_t(o), h, g0, g1, cls_slots, tile_slots, cap, 0});
+            cls_slots += 4 * (g1 - g0);
+            tile_slots += cap;
+        }
+        pl->l2l[size_t(h)].n = tile_slots - pl->l2l[size_t(h)].t0;
+    }
+    const int32_t m2m_base = tile_slots;
+    for (int h = 1; h <= H; ++h) {
+        pl->m2m[size_t(h)].t0 = tile_slots;
+        for (size_t o = 0; o < side_of.size(); ++o) {
+            int32_t g0, g1;
+            range_of(h, int(o), 2, g0, g1);
+            for (int32_t s = g0; g0 >= 0 && s < g1; s += 16) {
+                m2m_tiles.push_back(BoxTile{int32_t(o), h, 0, s, std::min(16, g1 - s), 0, 0, 0});
+                ++tile_slots;
+            }
+        }
+        pl->m2m[size_t(h)].n = tile_slots - pl->m2m[size_t(h)].t0;
+    }
+
+    // ---- plan storage sized by the boxes --------------------------------------------------------
+    const int64_t nb = pl->nbox, nl = pl->nleaf;
     const int P = kRankPad;
-    const int64_t nb = pl->nboxes, nl = pl->nleaves;
-    Arena& m = pl->mem;
-    m.set_pool(&ctx->pool);
-    // one reserve per take below (each piece is 256-byte aligned)
-    m.reserve(size_t(n) * 8);                   // pts
-    m.reserve(size_t(n) * 4);                   // perm
-    m.reserve(size_t(n) * 8);                   // fs
-    m.reserve(size_t(nb) * 8);                  // box_key
-    m.reserve(size_t(nb) * 4);                  // pt0
-    m.reserve(size_t(nb) * 4);                  // pt1
-    m.reserve(size_t(nb) * 4);                  // parent
-    m.reserve(size_t(nb) * 16);                 // child
-    m.reserve(size_t(std::max(n_m2l, 1)) * 4 * kNumInteractions);
-    m.reserve(size_t(nl) * 4 * 9);
-    m.reserve(4 * 4 * 34);                      // class counters
-    m.reserve(size_t(std::max(n_m2l, 1)) * 4 * 4);   // class-sorted boxes (4 regions per level)
-    m.reserve(4 * 4);                           // tile count
-    m.reserve(size_t(max_tiles + 1) * sizeof(M2LTile));
-    m.reserve(size_t(nb) * P * 8);              // Q
-    m.reserve(size_t(nb) * P * 8);              // U
-    m.reserve(size_t(n) * 4);                   // point keys
-    m.allocate();
-    pl->pts = m.take<int32_t>(size_t(n) * 2);
-    pl->perm = m.take<int32_t>(n);
-    pl->fs = m.take<double>(n);
-    pl->box_key = m.take<uint64_t>(nb);
-    pl->box_pt0 = m.take<int32_t>(nb);
-    pl->box_pt1 = m.take<int32_t>(nb);
-    pl->box_parent = m.take<int32_t>(nb);
-    pl->box_child = m.take<int32_t>(size_t(nb) * 4);
-    pl->ilist = m.take<int32_t>(size_t(std::max(n_m2l, 1)) * kNumInteractions);
-    pl->nlist = m.take<int32_t>(size_t(nl) * 9);
-    pl->cls_cnt = m.take<int32_t>(4 * 34);
-    pl->cls_box = m.take<int32_t>(size_t(std::max(n_m2l, 1)) * 4);
-    pl->ntiles = m.take<int32_t>(4);
-    pl->tiles = m.take<M2LTile>(size_t(max_tiles + 1));
-    pl->Q = m.take<double>(size_t(nb) * P);
-    pl->U = m.take<double>(size_t(nb) * P);
-    pl->pkey = m.take<uint32_t>(n);
+    Arena& mb = pl->mem_box;
+    mb.set_pool(&ctx->pool);
+    mb.reserve(size_t(nb) * 8);                          // key
+    for (int q = 0; q < 5; ++q) mb.reserve(size_t(nb) * 4);   // pt0, pt1, parent, inst, (pad)
+    mb.reserve(size_t(nb));                              // level
+    mb.reserve(size_t(nb) * 16);                         // child
+    mb.reserve(size_t(nb) * 36);                         // neighbour lists
+    mb.reserve(size_t(nb) * 4 * kNumInteractions);       // interaction lists
+    mb.reserve(size_t(std::max(cls_slots, 1)) * 4);
+    mb.reserve(size_t(std::max(tile_slots, 1)) * sizeof(BoxTile));
+    mb.reserve(size_t(std::max<size_t>(m2l_groups.size() + l2l_groups.size(), 1)) * sizeof(BoxGroup));
+    mb.reserve(size_t(nb) * P * 8);                      // Q
+    mb.reserve(size_t(nb) * P * 8);                      // U
+    mb.allocate();
+    pl->box_key = mb.take<uint64_t>(nb);
+    pl->box_pt0 = mb.take<int32_t>(nb);
+    pl->box_pt1 = mb.take<int32_t>(nb);
+    pl->box_parent = mb.take<int32_t>(nb);
+    pl->box_inst = mb.take<int32_t>(nb);
+    (void)mb.take<int32_t>(nb);
+    pl->box_lev = mb.take<int8_t>(nb);
+    pl->box_child = mb.take<int32_t>(size_t(nb) * 4);
+    pl->nb9 = mb.take<int32_t>(size_t(nb) * 9);
+    pl->il27 = mb.take<int32_t>(size_t(nb) * kNumInteractions);
+    pl->cls_box = mb.take<int32_t>(std::max(cls_slots, 1));
+    pl->tiles = mb.take<BoxTile>(std::max(tile_slots, 1));
+    BoxGroup* d_groups = mb.take<BoxGroup>(std::max<size_t>(m2l_groups.size() + l2l_groups.size(), 1));
+    pl->Q = mb.take<double>(size_t(nb) * P);
+    pl->U = mb.take<double>(size_t(nb) * P);
 
-    launch_gather_points(xy, vals, n, bb[0], bb[1], pl->pts, pl->perm, st);
-    if (pl->side <= 16) launch_point_keys(pl->pts, n, pl->side, pl->pkey, st);
+    // ---- tables ---------------------------------------------------------------------------------
+    upload(pl->d_inst, pl->inst, st);
+    std::vector<OpsPtrs> optab;
+    for (CachedOps* co : pl->ops) optab.push_back(ops_ptrs(co));
+    upload(pl->d_ops, optab, st);
+    std::vector<uint8_t> far(static_cast<size_t>(K));
+    for (int32_t k = 0; k < K; ++k) far[size_t(k)] = pl->inst[size_t(k)].L >= 2 ? 1 : 0;
+    upload(pl->d_far, far, st);
+    std::vector<BoxGroup> groups = m2l_groups;
+    groups.insert(groups.end(), l2l_groups.begin(), l2l_groups.end());
+    upload(d_groups, groups, st);
+    if (!m2m_tiles.empty())
+        LFMM_HIP(hipMemcpyAsync(pl->tiles + m2m_base, m2m_tiles.data(), m2m_tiles.size() * sizeof(BoxTile),
+                                hipMemcpyHostToDevice, st));
+    std::vector<int32_t> m2l_n{pl->m2l.n};
+    upload(pl->d_m2l_ntiles, m2l_n, st);
 
-    // ---- leaves ------------------------------------------------------------------------------
-    // level-scan temporaries reuse the sort buffers: leaf arrays need <= n entries each
-    int32_t* leaf_pt0 = reinterpret_cast<int32_t*>(keys_tmp);
+    // ---- leaves ---------------------------------------------------------------------------------
     Arena tmp2(&ctx->pool);
-    tmp2.reserve(size_t(nl) * 8);                              // leaf keys
-    tmp2.reserve(size_t(nl));                                  // leaf cl
-    tmp2.reserve(size_t(std::max(L, 1)) * nl * 4);             // level flags
-    tmp2.reserve(size_t(std::max(L, 1)) * nl * 4);             // level scans
-    tmp2.reserve(scan_scratch_bytes(nl, std::max(L, 1)));
+    const int rows = std::max(Lmax, 1);
+    tmp2.reserve(size_t(nl) * 4);                        // leaf first point
+    tmp2.reserve(size_t(nl) * 8);                        // leaf keys
+    tmp2.reserve(size_t(nl));                            // leaf cl
+    tmp2.reserve(size_t(nl) * 4);                        // leaf instance
+    tmp2.reserve(size_t(rows) * nl * 4);                 // level flags
+    tmp2.reserve(size_t(rows) * nl * 4);                 // level scans
+    tmp2.reserve(scan_scratch_bytes(nl, rows));
+    tmp2.reserve(size_t(nb) * 4 * 4);                    // class flags
+    tmp2.reserve(size_t(nb) * 4 * 4);                    // class scans
+    tmp2.reserve(64);                                    // class totals
+    tmp2.reserve(scan_scratch_bytes(nb, 4));
     tmp2.allocate();
-    uint64_t* lkey = tmp2.take<uint64_t>(nl);
-    int8_t* lcl = tmp2.take<int8_t>(nl);
-    int32_t* lflags = tmp2.take<int32_t>(size_t(std::max(L, 1)) * nl);
-    int32_t* lscan = tmp2.take<int32_t>(size_t(std::max(L, 1)) * nl);
-    void* lscr = tmp2.take<char>(scan_scratch_bytes(nl, std::max(L, 1)));
+    int32_t* leaf_pt0 = tmp2.take<int32_t>(nl);
+    uint64_t* leaf_key = tmp2.take<uint64_t>(nl);
+    int8_t* leaf_cl = tmp2.take<int8_t>(nl);
+    int32_t* leaf_inst = tmp2.take<int32_t>(nl);
+    int32_t* lflags = tmp2.take<int32_t>(size_t(rows) * nl);
+    int32_t* lscan = tmp2.take<int32_t>(size_t(rows) * nl);
+    void* lscr = tmp2.take<char>(scan_scratch_bytes(nl, rows));
+    int32_t* cflags = tmp2.take<int32_t>(size_t(nb) * 4);
+    int32_t* cscan = tmp2.take<int32_t>(size_t(nb) * 4);
+    int32_t* ctotal = tmp2.take<int32_t>(16);
+    void* cscr = tmp2.take<char>(scan_scratch_bytes(nb, 4));
 
-    launch_leaf_flags(cl, n, L, flags, st);
+    launch_leaf_flags(cl, pl->pinst, pl->d_inst, n, flags, st);
     scan_rows(flags, scan, n, 1, nullptr, sscr, st);
-    launch_leaf_scatter(flags, scan, keys, cl, n, D, L, leaf_pt0, lkey, lcl, st);
-    if (L > 0) {
-        launch_level_flags(lcl, nl, L, lflags, st);
-        scan_rows(lflags, lscan, nl, L, nullptr, lscr, st);
+    launch_leaf_scatter(flags, scan, skeys, cl, pl->pinst, pl->d_inst, Dmax, n, leaf_pt0, leaf_key, leaf_cl,
+                        leaf_inst, st);
+    if (Lmax > 0) {
+        launch_level_flags(leaf_cl, leaf_inst, pl->d_inst, nl, Lmax, lflags, st);
+        scan_rows(lflags, lscan, nl, Lmax, nullptr, lscr, st);
     }
-    launch_build_boxes(lscan, lcl, leaf_pt0, lkey, nl, L, pl->off.data(), n, pl->box_key, pl->box_pt0,
-                       pl->box_pt1, pl->box_parent, pl->box_child, st);
-    LFMM_HIP(hipMemsetAsync(pl->cls_cnt, 0, 4 * 4 * 34, st));
-    launch_lists(pl->box_key, pl->off.data(), L, pl->ilist, pl->nlist, pl->cls_cnt, pl->cls_box, st);
-    if (L >= 2) {
-        launch_m2l_tiles(pl->cls_cnt, pl->off.data(), L, pl->tiles, pl->ntiles, st);
-    } else {
-        LFMM_HIP(hipMemsetAsync(pl->ntiles, 0, 4, st));
-    }
+    launch_build_boxes(lscan, leaf_cl, leaf_pt0, leaf_key, leaf_inst, pl->d_inst, nl, Lmax, pl->box_key, pl->box_pt0,
+                       pl->box_parent, pl->box_child, pl->box_inst, pl->box_lev, st);
+    launch_link_boxes(pl->box_key, pl->box_parent, pl->box_inst, pl->box_lev, pl->d_inst, nb, pl->box_pt0,
+                      pl->box_child, pl->box_pt1, st);
+    for (int h = H; h >= 0; --h)
+        launch_lists_height(pl->hbase[size_t(h)], pl->hbase[size_t(h) + 1], pl->box_key, pl->box_parent,
+                            pl->box_child, pl->box_lev, pl->nb9, pl->il27, st);
+    launch_class_flags(pl->box_key, nb, cflags, st);
+    scan_rows(cflags, cscan, nb, 4, ctotal, cscr, st);
+    launch_class_lists(d_groups, int32_t(groups.size()), cscan, ctotal, pl->box_key, nb, pl->cls_box, pl->tiles,
+                       nullptr, st);
+    if (std::any_of(side_of.begin(), side_of.end(), [](int64_t s) { return s <= 16; }))
+        launch_point_keys(pl->pts, pl->pinst, pl->d_inst, pl->d_ops, n, pl->pkey, st);
     LFMM_HIP(hipGetLastError());
-    pl->ops = get_ops(ctx, pl->side, std::max(L - 1, 1), st);
+    // staging for the per-execute pointer table of batched plans
+    if (K > 1) {
+        pl->h_exec = static_cast<ExecPtrs*>(ctx->pinned.acquire(size_t(K) * sizeof(ExecPtrs), &pl->h_exec_cls));
+        LFMM_HIP(hipEventCreateWithFlags(&pl->exec_copied, hipEventDisableTiming));
+    }
     LFMM_HIP(hipStreamSynchronize(st));
     tmp.release();
     tmp2.release();
 }
 
-void run_plan(lfmm_plan* pl, const double* f, double* u, hipStream_t st) {
-    const DevOps& op = pl->ops->dev;
-    const int L = pl->L;
-    const bool simple = (pl->ctx->opt.flags & LFMM_FLAG_SIMPLE_KERNELS) != 0;
+void run_forest(lfmm_plan* pl, const double* const* f, double* const* u, hipStream_t st) {
+    const ExecPtrs* tab = nullptr;
+    const double* f1 = nullptr;
+    double* u1 = nullptr;
+    if (pl->K == 1) {
+        f1 = f[0];
+        u1 = u[0];
+    } else {
+        // the previous execute's copy must have read the staging buffer before it is rewritten
+        LFMM_HIP(hipEventSynchronize(pl->exec_copied));
+        for (int32_t k = 0; k < pl->K; ++k) pl->h_exec[k] = ExecPtrs{f[k], u[k]};
+        LFMM_HIP(hipMemcpyAsync(pl->d_exec, pl->h_exec, size_t(pl->K) * sizeof(ExecPtrs), hipMemcpyHostToDevice, st));
+        LFMM_HIP(hipEventRecord(pl->exec_copied, st));
+        tab = pl->d_exec;
+    }
+    const bool mixed = pl->ctx->opt.precision == LFMM_MIXED;
     auto mark = [&](int k) {
         if (pl->timing) LFMM_HIP(hipEventRecord(pl->ev[k], st));
     };
     mark(0);
-    launch_gather_f(f, pl->perm, pl->n, pl->fs, st);
+    launch_gather_f(tab, f1, pl->perm, pl->pinst, pl->n, pl->fs, st);
     mark(1);
-    const bool far = L >= 2;
-    if (far) {
-        launch_p2m_dense(pl->nleaves, pl->leaf_off, pl->box_pt0, pl->box_pt1, pl->box_key, L, pl->side, pl->pts,
-                         pl->fs, op.leafT, pl->Q, st);
+    for (size_t o = 0; o < pl->ops.size(); ++o) {
+        const TileRange& r = pl->leaf_of_ops[o];
+        launch_p2m(r.t0, r.t0 + r.n, pl->box_pt0, pl->box_pt1, pl->box_key, pl->ops[o]->dev.leaf_side, pl->pts,
+                   pl->fs, pl->ops[o]->dev.leafT, pl->Q, st);
     }
     mark(2);
-    if (far) {
-        for (int lev = L - 1; lev >= 2; --lev)
-            launch_m2m(pl->off[size_t(lev)], pl->off[size_t(lev) + 1], L - lev, pl->box_child, op.ofo_cm, pl->Q,
-                       pl->Q, st);
+    for (int h = 1; h <= pl->Hmax; ++h) {
+        const TileRange& r = pl->m2m[size_t(h)];
+        if (r.n > 0)
+            launch_boxmat(kModeM2M, pl->tiles, r.t0, nullptr, r.n, r.n, nullptr, pl->box_child, pl->d_ops, pl->Q,
+                          pl->Q, st);
     }
     mark(3);
-    if (far) {
-        if (pl->ctx->opt.precision == LFMM_MIXED)
-            launch_m2l_mixed(pl->tiles, pl->ntiles, pl->max_tiles, pl->cls_box, pl->ilist, pl->ilist_off, pl->Q,
-                             pl->U, op.ifo_hi, op.ifo_lo, op.mono, op.rank, st);
+    if (pl->m2l.n > 0) {
+        if (mixed)
+            launch_m2l_mixed(pl->tiles + pl->m2l.t0, pl->d_m2l_ntiles, pl->m2l.n, pl->cls_box, pl->il27, pl->d_ops,
+                             pl->Q, pl->U, st);
         else
-            launch_m2l(pl->tiles, pl->ntiles, pl->max_tiles, pl->cls_box, pl->ilist, pl->ilist_off, pl->Q, pl->U,
-                       op.ifo, simple, st);
+            launch_boxmat(kModeM2L, pl->tiles, pl->m2l.t0, nullptr, pl->m2l.n, pl->m2l.n, pl->cls_box, pl->il27,
+                          pl->d_ops, pl->Q, pl->U, st);
     }
     mark(4);
-    if (far) {
-        for (int lev = 2; lev <= L - 1; ++lev)
-            launch_l2l(pl->off[size_t(lev) + 1], pl->off[size_t(lev) + 2], L - lev, pl->box_parent, pl->box_key,
-                       op.ofo_rm, pl->U, st);
+    for (int h = pl->Hmax; h >= 0; --h) {
+        const TileRange& r = pl->l2l[size_t(h)];
+        if (r.n > 0)
+            launch_boxmat(kModeL2L, pl->tiles, r.t0, nullptr, r.n, r.n, pl->cls_box, pl->box_parent, pl->d_ops, pl->U,
+                          pl->U, st);
     }
     mark(5);
-    launch_leaf_eval(pl->nleaves, pl->leaf_off, pl->box_pt0, pl->box_pt1, pl->box_key, pl->nlist, L, pl->side,
-                     pl->pts, pl->side <= 16 ? pl->pkey : nullptr, pl->fs, pl->perm, pl->U, op.leafT, far,
-                     pl->ctx->phi_oct, u, simple, st);
+    for (size_t o = 0; o < pl->ops.size(); ++o) {
+        const TileRange& r = pl->leaf_of_ops[o];
+        launch_leaf(r.t0, r.t0 + r.n, pl->box_pt0, pl->box_pt1, pl->box_key, pl->box_inst, pl->nb9,
+                    pl->ops[o]->dev.leaf_side, pl->pts, pl->pkey, pl->fs, pl->perm, pl->pinst, pl->d_inst, tab, u1,
+                    pl->U, pl->ops[o]->dev.leafT, pl->d_far, pl->ctx->phi_oct, st);
+    }
     mark(6);
     if (pl->timing) pl->timed_once = true;
 }
+
+}  // namespace
+
+void lfmm::plan_destroy_completed(lfmm_plan* pl) { delete pl; }
+
+int lfmm::ctx_device(const lfmm_ctx* ctx) { return ctx->device; }
+
+namespace {
 
 template <class F>
 lfmm_status guarded(F&& f) {
@@ -522,6 +841,40 @@ lfmm_status guarded(F&& f) {
     } catch (const std::exception& e) {
         return fail(LFMM_E_INVAL, e.what());
     }
+}
+
+lfmm_status create_forest(lfmm_ctx* ctx, int32_t K, const int64_t* sizes, const int32_t* const* xy, void* stream,
+                          lfmm_plan** out) {
+    if (!ctx || !out || !sizes || !xy || K < 1) return fail(LFMM_E_INVAL, "null argument or no instance");
+    *out = nullptr;
+    int64_t total = 0;
+    for (int32_t k = 0; k < K; ++k) {
+        if (sizes[k] < 1 || !xy[k]) return fail(LFMM_E_INVAL, "every instance needs n >= 1 and coordinates");
+        total += sizes[k];
+    }
+    if (total > (int64_t(1) << 30)) return fail(LFMM_E_INVAL, "more than 2^30 points in one plan");
+    return guarded([&]() -> lfmm_status {
+        LFMM_HIP(hipSetDevice(ctx->device));
+        auto pl = std::make_unique<lfmm_plan>();
+        pl->ctx = ctx;
+        build_forest(pl.get(), K, sizes, xy, as_stream(stream));
+        *out = pl.release();
+        return LFMM_OK;
+    });
+}
+
+lfmm_status execute_forest(lfmm_plan* pl, const double* const* f, double* const* u, void* stream) {
+    if (pl->failed) return fail(LFMM_E_HIP, "plan is in a failed state");
+    return guarded([&]() -> lfmm_status {
+        LFMM_HIP(hipSetDevice(pl->ctx->device));
+        run_forest(pl, f, u, as_stream(stream));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            pl->failed = true;
+            throw HipFailure(std::string("kernel launch: ") + hipGetErrorString(e));
+        }
+        return LFMM_OK;
+    });
 }
 
 }  // namespace
@@ -569,32 +922,30 @@ lfmm_status lfmm_ctx_destroy(lfmm_ctx* ctx) {
 
 lfmm_status lfmm_plan_create(lfmm_ctx* ctx, int64_t n, const int32_t* xy, void* stream, lfmm_plan** out) {
     if (!ctx || !out || !xy) return fail(LFMM_E_INVAL, "null argument");
-    *out = nullptr;
     if (n < 1 || n > (int64_t(1) << 30)) return fail(LFMM_E_INVAL, "n must lie in [1, 2^30]");
-    return guarded([&]() -> lfmm_status {
-        LFMM_HIP(hipSetDevice(ctx->device));
-        auto pl = std::make_unique<lfmm_plan>();
-        pl->ctx = ctx;
-        pl->n = n;
-        build_plan(pl.get(), xy, as_stream(stream));
-        *out = pl.release();
-        return LFMM_OK;
-    });
+    const int64_t sizes[1] = {n};
+    const int32_t* ptrs[1] = {xy};
+    return create_forest(ctx, 1, sizes, ptrs, stream, out);
+}
+
+lfmm_status lfmm_plan_create_batch(lfmm_ctx* ctx, int32_t n_inst, const int64_t* n_host,
+                                   const int32_t* const* xy_dev, void* stream, lfmm_plan** out) {
+    return create_forest(ctx, n_inst, n_host, xy_dev, stream, out);
 }
 
 lfmm_status lfmm_execute(lfmm_plan* pl, const double* f, double* u, void* stream) {
     if (!pl || !f || !u) return fail(LFMM_E_INVAL, "null argument");
-    if (pl->failed) return fail(LFMM_E_HIP, "plan is in a failed state");
-    return guarded([&]() -> lfmm_status {
-        LFMM_HIP(hipSetDevice(pl->ctx->device));
-        run_plan(pl, f, u, as_stream(stream));
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) {
-            pl->failed = true;
-            throw HipFailure(std::string("kernel launch: ") + hipGetErrorString(e));
-        }
-        return LFMM_OK;
-    });
+    if (pl->K != 1) return fail(LFMM_E_INVAL, "plan holds several instances: use lfmm_execute_instances");
+    const double* fa[1] = {f};
+    double* ua[1] = {u};
+    return execute_forest(pl, fa, ua, stream);
+}
+
+lfmm_status lfmm_execute_instances(lfmm_plan* pl, const double* const* f, double* const* u, void* stream) {
+    if (!pl || !f || !u) return fail(LFMM_E_INVAL, "null argument");
+    for (int32_t k = 0; k < pl->K; ++k)
+        if (!f[k] || !u[k]) return fail(LFMM_E_INVAL, "null load or potential pointer");
+    return execute_forest(pl, f, u, stream);
 }
 
 lfmm_status lfmm_execute_batch(lfmm_ctx* ctx, int32_t n_plans, lfmm_plan* const* plans, const double* const* f,
@@ -613,36 +964,38 @@ lfmm_status lfmm_plan_get_info(lfmm_plan* pl, lfmm_plan_info* out) {
     return guarded([&]() -> lfmm_status {
         LFMM_HIP(hipSetDevice(pl->ctx->device));
         std::memset(out, 0, sizeof(*out));
+        const InstInfo& I0 = pl->inst[0];
         out->n_points = pl->n;
-        out->root_bits = pl->D;
-        out->leaf_level = pl->L;
-        out->leaf_side = pl->side;
+        out->n_instances = pl->K;
+        out->root_bits = I0.D;
+        out->leaf_level = I0.L;
+        out->leaf_side = int64_t(1) << (I0.D - I0.L);
         out->rank = kRankPad;
         out->leaf_kind = 0;
-        out->n_boxes = pl->nboxes;
-        out->n_leaves = pl->nleaves;
+        out->n_boxes = pl->nbox;
+        out->n_leaves = pl->nleaf;
         // pair counts from the lists (host side, for reporting)
-        std::vector<int32_t> pt0(size_t(pl->nboxes)), pt1(size_t(pl->nboxes)), nl(size_t(pl->nleaves) * 9);
-        LFMM_HIP(hipMemcpy(pt0.data(), pl->box_pt0, pt0.size() * 4, hipMemcpyDeviceToHost));
-        LFMM_HIP(hipMemcpy(pt1.data(), pl->box_pt1, pt1.size() * 4, hipMemcpyDeviceToHost));
-        LFMM_HIP(hipMemcpy(nl.data(), pl->nlist, nl.size() * 4, hipMemcpyDeviceToHost));
-        int64_t near = 0;
-        for (int32_t b = 0; b < pl->nleaves; ++b) {
-            int32_t g = pl->leaf_off + b;
-            int64_t nt = pt1[size_t(g)] - pt0[size_t(g)], ns = 0;
+        const size_t nb = size_t(pl->nbox);
+        std::vector<int32_t> pt0(nb), pt1(nb), nb9(nb * 9), il(nb * kNumInteractions);
+        std::vector<int8_t> lev(nb);
+        LFMM_HIP(hipMemcpy(pt0.data(), pl->box_pt0, nb * 4, hipMemcpyDeviceToHost));
+        LFMM_HIP(hipMemcpy(pt1.data(), pl->box_pt1, nb * 4, hipMemcpyDeviceToHost));
+        LFMM_HIP(hipMemcpy(nb9.data(), pl->nb9, nb * 36, hipMemcpyDeviceToHost));
+        LFMM_HIP(hipMemcpy(il.data(), pl->il27, nb * 4 * kNumInteractions, hipMemcpyDeviceToHost));
+        LFMM_HIP(hipMemcpy(lev.data(), pl->box_lev, nb, hipMemcpyDeviceToHost));
+        int64_t near = 0, m2l = 0;
+        for (int32_t g = 0; g < pl->nleaf; ++g) {
+            int64_t ns = 0;
             for (int q = 0; q < 9; ++q) {
-                int32_t s = nl[size_t(b) * 9 + q];
+                const int32_t s = nb9[size_t(g) * 9 + q];
                 if (s >= 0) ns += pt1[size_t(s)] - pt0[size_t(s)];
             }
-            near += nt * ns;
+            near += int64_t(pt1[size_t(g)] - pt0[size_t(g)]) * ns;
         }
+        for (size_t g = 0; g < nb; ++g)
+            if (lev[g] >= 2)
+                for (int k = 0; k < kNumInteractions; ++k) m2l += (il[g * kNumInteractions + k] >= 0);
         out->near_pairs = near;
-        int64_t m2l = 0;
-        if (pl->L >= 2) {
-            std::vector<int32_t> il(size_t(pl->nboxes - pl->ilist_off) * kNumInteractions);
-            LFMM_HIP(hipMemcpy(il.data(), pl->ilist, il.size() * 4, hipMemcpyDeviceToHost));
-            for (int32_t v : il) m2l += (v >= 0);
-        }
         out->m2l_pairs = m2l;
         return LFMM_OK;
     });
@@ -652,24 +1005,34 @@ lfmm_status lfmm_plan_export(lfmm_plan* pl, int32_t item, void* out, size_t* byt
     if (!pl || !bytes) return fail(LFMM_E_INVAL, "null argument");
     const void* src = nullptr;
     size_t size = 0;
-    const size_t nb = size_t(pl->nboxes), n = size_t(pl->n), P = kRankPad;
+    const size_t nb = size_t(pl->nbox), n = size_t(pl->n), P = kRankPad;
+    std::vector<int32_t> levels;
+    bool host = false;
     switch (item) {
         case LFMM_EXPORT_POINTS: src = pl->pts; size = n * 8; break;
         case LFMM_EXPORT_PERM: src = pl->perm; size = n * 4; break;
-        case LFMM_EXPORT_LEVEL_OFFSETS: src = pl->off.data(); size = pl->off.size() * 4; break;
+        case LFMM_EXPORT_LEVEL_BASE:
+        case LFMM_EXPORT_LEVEL_COUNT: {
+            const InstInfo& I0 = pl->inst[0];
+            for (int lev = 0; lev <= I0.L; ++lev)
+                levels.push_back(item == LFMM_EXPORT_LEVEL_BASE ? I0.lev_base[lev] : I0.lev_count[lev]);
+            src = levels.data();
+            size = levels.size() * 4;
+            host = true;
+            break;
+        }
         case LFMM_EXPORT_BOX_KEY: src = pl->box_key; size = nb * 8; break;
         case LFMM_EXPORT_BOX_BEGIN: src = pl->box_pt0; size = nb * 4; break;
         case LFMM_EXPORT_BOX_END: src = pl->box_pt1; size = nb * 4; break;
         case LFMM_EXPORT_BOX_PARENT: src = pl->box_parent; size = nb * 4; break;
         case LFMM_EXPORT_BOX_CHILD: src = pl->box_child; size = nb * 16; break;
-        case LFMM_EXPORT_INTERACTION:
-            src = pl->ilist;
-            size = size_t(pl->nboxes - pl->ilist_off) * kNumInteractions * 4;
-            break;
-        case LFMM_EXPORT_NEIGHBOR: src = pl->nlist; size = size_t(pl->nleaves) * 9 * 4; break;
+        case LFMM_EXPORT_INTERACTION: src = pl->il27; size = nb * kNumInteractions * 4; break;
+        case LFMM_EXPORT_NEIGHBOR: src = pl->nb9; size = nb * 9 * 4; break;
         case LFMM_EXPORT_QHAT: src = pl->Q; size = nb * P * 8; break;
         case LFMM_EXPORT_UHAT: src = pl->U; size = nb * P * 8; break;
         case LFMM_EXPORT_LOADS: src = pl->fs; size = n * 8; break;
+        case LFMM_EXPORT_BOX_LEVEL: src = pl->box_lev; size = nb; break;
+        case LFMM_EXPORT_BOX_INSTANCE: src = pl->box_inst; size = nb * 4; break;
         default: return fail(LFMM_E_INVAL, "unknown export item");
     }
     if (!out) {
@@ -681,7 +1044,7 @@ lfmm_status lfmm_plan_export(lfmm_plan* pl, int32_t item, void* out, size_t* byt
     return guarded([&]() -> lfmm_status {
         LFMM_HIP(hipSetDevice(pl->ctx->device));
         LFMM_HIP(hipDeviceSynchronize());
-        if (item == LFMM_EXPORT_LEVEL_OFFSETS) std::memcpy(out, src, size);
+        if (host) std::memcpy(out, src, size);
         else if (size) LFMM_HIP(hipMemcpy(out, src, size, hipMemcpyDeviceToHost));
         return LFMM_OK;
     });
@@ -715,12 +1078,13 @@ lfmm_status lfmm_plan_phase_times(lfmm_plan* pl, double* ms) {
 
 lfmm_status lfmm_plan_footprint_bytes(const lfmm_ctx* ctx, int64_t n, size_t* out) {
     if (!ctx || !out || n < 0) return fail(LFMM_E_INVAL, "bad argument");
-    // boxes <= 4/3 * n / (leaf occupancy >= 1) bounded by 2 n; per box: Q, U, keys and lists
+    // boxes <= 4/3 of the leaves, leaves <= points; per box: Q, U, keys, links and lists;
+    // per point: coordinates, indices, keys and loads; plus the construction temporaries
     const size_t nb = size_t(2 * n + 64);
-    size_t per_box = size_t(kRankPad) * 16 + 8 + 4 * 7 + 4 * kNumInteractions + 4 * 4 + 4 * 9;
-    size_t per_point = 8 + 4 + 8;
-    size_t tmp = size_t(n) * (16 + 8 + 1 + 8) + radix_scratch_bytes(n) + scan_scratch_bytes(n, 1);
-    *out = nb * per_box + size_t(n) * per_point + tmp + (1u << 20);
+    const size_t per_box = size_t(kRankPad) * 16 + 8 + 4 * 6 + 1 + 16 + 36 + 4 * kNumInteractions + 4 * 8;
+    const size_t per_point = 8 + 4 * 3 + 8;
+    const size_t tmp = size_t(n) * (8 + 16 + 8 + 1 + 8) + radix_scratch_bytes(n) + scan_scratch_bytes(n, 1);
+    *out = nb * per_box + size_t(n) * per_point + tmp + (size_t(1) << 20);
     return LFMM_OK;
 }
 

@@ -27,7 +27,7 @@ lfmm_status validate_options(const lfmm_options* o) {
         return fail(LFMM_E_INVAL, "proxy_per_edge must lie in [8, 4096]");
     if (o->max_rank < 16 || o->max_rank > kMaxRank || o->max_rank % 16 != 0)
         return fail(LFMM_E_INVAL, "max_rank must be 16, 32, 48 or 64");
-    if (o->flags & ~LFMM_FLAG_SIMPLE_KERNELS) return fail(LFMM_E_INVAL, "unknown flag bits");
+    if (o->flags != 0) return fail(LFMM_E_INVAL, "options.flags is reserved and must be 0");
     return LFMM_OK;
 }
 
@@ -70,6 +70,7 @@ const char* lfmm_status_string(lfmm_status s) {
         case LFMM_E_HIP: return "HIP runtime error";
         case LFMM_E_UNSUPPORTED: return "unsupported";
         case LFMM_E_NODEVICE: return "no such device";
+        case LFMM_E_BUSY: return "not done yet";
     }
     return "unknown status";
 }

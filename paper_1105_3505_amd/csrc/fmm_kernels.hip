@@ -1,14 +1,13 @@
-// Evaluation passes of the lattice FMM on gfx950 (Section 8.2).
+// Evaluation passes of the lattice FMM on gfx950 (Section 8.2), for a forest of instances.
 //
 // Expansions are stored box-major: box g owns kRankPad consecutive FP64 coefficients in Q
-// (outgoing, q-hat) and U (incoming, u-hat).  Boxes of every level are numbered
-// consecutively level by level, each level in Morton order; leaves are the last level.
+// (outgoing, q-hat) and U (incoming, u-hat).
 //
-//   P2M   q^tau   = T_ofs^tau q(J^tau)             one wave per leaf, lanes = skeleton index
-//   M2M   q^tau   = sum_c T_ofo^(c) q^child_c      one wave per parent
-//   M2L   u^tau   = sum_{sigma in L_int} T_ifo^d q^sigma   FP64 MFMA, 16 boxes per wave
-//   L2L   u^child += T_ofo^(c)T u^tau              one wave per child
-//   L2P + near field + un-permutation              one wave per leaf, lanes = targets
+//   P2M   q^tau   = T_ofs^tau q(J^tau)                 one wave per leaf, lanes = skeleton index
+//   M2M   q^tau   = sum_c T_ofo^(c) q^child_c          FP64 MFMA box-matrix kernel
+//   M2L   u^tau   = sum_{sigma in L_int} T_ifo^d q^sigma   FP64 MFMA box-matrix kernel
+//   L2L   u^child += T_ofo^(c)T u^tau                  FP64 MFMA box-matrix kernel
+//   L2P + near field + un-permutation                  one wave per leaf, lanes = targets x slices
 #include "kernels.h"
 
 #include <hip/hip_runtime.h>
@@ -26,6 +25,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kEulerGamma = 0.57721566490153286061;
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
 
 // Interaction-list slot k of a box in child position c lies at offset slot c_dslot[c][k]
 // of the 7 x 7 offset grid; the order matches the list builder (dy outer, dx inner).
@@ -44,140 +44,65 @@ __device__ inline uint32_t compact_bits(uint64_t x) {
 
 // eq. (3.1), truncated after the |m|^-8 term, true Euler constant; (a, b) != 0
 __device__ inline double phi_expansion_dev(double a, double b) {
-    double r2 = a * a + b * b;
-    double ir2 = 1.0 / r2;
-    double c = a * a * ir2, s = b * b * ir2;
-    double lead = -(0.5 * log(r2) + (kEulerGamma + 0.5 * 2.0794415416798357)) * (1.0 / (2.0 * kPi));
-    double t4 = (c * c - 6.0 * c * s + s * s) * ir2 * (1.0 / (24.0 * kPi));
-    double c2 = c * c, s2 = s * s;
-    double t8 = (43.0 * c2 * c2 - 772.0 * c2 * c * s + 1570.0 * c2 * s2 - 772.0 * c * s2 * s + 43.0 * s2 * s2)
-                * ir2 * ir2 * (1.0 / (480.0 * kPi));
+    const double r2 = a * a + b * b;
+    const double ir2 = 1.0 / r2;
+    const double c = a * a * ir2, s = b * b * ir2;
+    const double lead = -(0.5 * log(r2) + (kEulerGamma + 0.5 * 2.0794415416798357)) * (1.0 / (2.0 * kPi));
+    const double t4 = (c * c - 6.0 * c * s + s * s) * ir2 * (1.0 / (24.0 * kPi));
+    const double c2 = c * c, s2 = s * s;
+    const double t8 = (43.0 * c2 * c2 - 772.0 * c2 * c * s + 1570.0 * c2 * s2 - 772.0 * c * s2 * s + 43.0 * s2 * s2)
+                      * ir2 * ir2 * (1.0 / (480.0 * kPi));
     return lead + t4 + t8;
 }
 
 // phi at offset (a, b), a, b >= 0: octant table inside radius 128, expansion outside
 __device__ inline double phi_oct(int a, int b, const double* oct) {
-    int hi = max(a, b), lo = min(a, b);
+    const int hi = max(a, b), lo = min(a, b);
     if (hi <= kOctRadius) return oct[hi * (hi + 1) / 2 + lo];
     return phi_expansion_dev(double(hi), double(lo));
 }
 
-__global__ void k_gather_f(const double* f, const int32_t* perm, int64_t n, double* fs) {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) fs[i] = f[perm[i]];
+inline unsigned grid_for(int64_t n, int per_block = kBlock) {
+    const int64_t g = (n + per_block - 1) / per_block;
+    return unsigned(g < 1 ? 1 : g);
 }
 
+__global__ void k_gather_f(const ExecPtrs* tab, const double* f_single, const int32_t* perm_local,
+                           const int32_t* pinst, int64_t n, double* fs) {
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const double* f = tab ? tab[pinst[s]].f : f_single;
+    fs[s] = f[perm_local[s]];
+}
+
+// P2M with the dense-model operator (Remark 8.2): q-hat[p] = sum_j T[loc(j)][p] f_j; one
+// wave per leaf, four independent accumulators so that four rows are in flight.
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_p2m_dense(int64_t nleaves, int32_t leaf_off, const int32_t* box_pt0,
-                                                       const int32_t* box_pt1, const uint64_t* box_key, int64_t side,
-                                                       const int2* pts, const double* fs, const double* leafT,
-                                                       double* Q) {
+__global__ __launch_bounds__(kBlock) void k_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0,
+                                                 const int32_t* box_pt1, const uint64_t* box_key, int64_t side,
+                                                 const int2* pts, const double* fs, const double* leafT, double* Q) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int64_t leaf = int64_t(blockIdx.x) * kWaves + wave;
-    if (leaf >= nleaves) return;
-    const int32_t g = leaf_off + int32_t(leaf);
+    const int32_t g = leaf0 + int32_t(blockIdx.x) * kWaves + wave;
+    if (g >= leaf1) return;
     const int32_t p0 = box_pt0[g], p1 = box_pt1[g];
     const uint64_t key = box_key[g];
     const int32_t cx = int32_t(compact_bits(key) * side), cy = int32_t(compact_bits(key >> 1) * side);
-    double acc = 0.0;
     const int l = lane < P ? lane : 0;
-    for (int32_t j = p0; j < p1; ++j) {
-        int2 p = pts[j];
-        int64_t loc = int64_t(p.x - cx) + side * int64_t(p.y - cy);
-        acc += leafT[loc * P + l] * fs[j];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int32_t j = p0;
+    for (; j + 3 < p1; j += 4) {
+        const int2 q0 = pts[j], q1 = pts[j + 1], q2 = pts[j + 2], q3 = pts[j + 3];
+        const double f0 = fs[j], f1 = fs[j + 1], f2 = fs[j + 2], f3 = fs[j + 3];
+        a0 += leafT[(int64_t(q0.x - cx) + side * int64_t(q0.y - cy)) * P + l] * f0;
+        a1 += leafT[(int64_t(q1.x - cx) + side * int64_t(q1.y - cy)) * P + l] * f1;
+        a2 += leafT[(int64_t(q2.x - cx) + side * int64_t(q2.y - cy)) * P + l] * f2;
+        a3 += leafT[(int64_t(q3.x - cx) + side * int64_t(q3.y - cy)) * P + l] * f3;
     }
-    if (lane < P) Q[size_t(g) * P + lane] = acc;
-}
-
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_m2m(int32_t begin, int32_t end, int height, const int32_t* box_child,
-                                                 const double* ofo_cm, double* Q) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int32_t g = begin + int32_t(blockIdx.x) * kWaves + wave;
-    if (g >= end) return;
-    const int l = lane < P ? lane : 0;
-    double acc = 0.0;
-    for (int c = 0; c < 4; ++c) {
-        const int32_t ch = box_child[size_t(g) * 4 + c];
-        if (ch < 0) continue;
-        const double* T = ofo_cm + (size_t(height) * 4 + c) * P * P;   // [q][r]
-        const double* qc = Q + size_t(ch) * P;
-        #pragma unroll 8
-        for (int q = 0; q < P; ++q) acc += T[q * P + l] * qc[q];
+    for (; j < p1; ++j) {
+        const int2 q = pts[j];
+        a0 += leafT[(int64_t(q.x - cx) + side * int64_t(q.y - cy)) * P + l] * fs[j];
     }
-    if (lane < P) Q[size_t(g) * P + lane] = acc;
-}
-
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_l2l(int32_t begin, int32_t end, int height_parent,
-                                                 const int32_t* box_parent, const uint64_t* box_key,
-                                                 const double* ofo_rm, double* U) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int32_t g = begin + int32_t(blockIdx.x) * kWaves + wave;
-    if (g >= end) return;
-    const int l = lane < P ? lane : 0;
-    const int32_t par = box_parent[g];
-    const int c = int(box_key[g] & 3ull);
-    const double* T = ofo_rm + (size_t(height_parent) * 4 + c) * P * P;   // [r][q]
-    const double* up = U + size_t(par) * P;
-    double acc = U[size_t(g) * P + l];
-    #pragma unroll 8
-    for (int r = 0; r < P; ++r) acc += T[r * P + l] * up[r];
-    if (lane < P) U[size_t(g) * P + lane] = acc;
-}
-
-// M2L on the FP64 matrix cores.  A wave owns a tile of up to 16 target boxes sharing a
-// level and a child position, so all 16 share the 27 operators T_ifo^d.  For each list
-// slot k: C[p][box] += sum_q T^d[p][q] Q[src_k(box)][q], as 16x16x4 MFMA steps.  In step kk
-// lane group g (= lane / 16) contributes column q = g * P/4 + kk, so each lane's operands
-// for one slot are P/4 consecutive doubles of a row of T^d and of the source's Q.
-// The FP64 16x16x4 instruction returns element i of lane (g, n) as row g + 4 i, column n
-// of the 16 x 16 block (the FP32 16x16x4 one returns row 4 g + i).
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_m2l(const M2LTile* tiles, const int32_t* ntiles_p,
-                                                 const int32_t* cls_box, const int32_t* ilist, int32_t ilist_off,
-                                                 const double* Q, double* U, const double* ifo) {
-    constexpr int MT = P / 16, KQ = P / 4;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int n = lane & 15, g = lane >> 4;
-    const int32_t ntiles = *ntiles_p;
-    for (int32_t t = int32_t(blockIdx.x) * kWaves + wave; t < ntiles; t += int32_t(gridDim.x) * kWaves) {
-        const M2LTile tl = tiles[t];
-        const int32_t box = (n < tl.count) ? cls_box[tl.start + n] : -1;
-        const int32_t* il = ilist + size_t(box >= 0 ? box - ilist_off : 0) * kNumInteractions;
-        double4_t acc[MT];
-        #pragma unroll
-        for (int m = 0; m < MT; ++m) acc[m] = double4_t{0.0, 0.0, 0.0, 0.0};
-        for (int k = 0; k < kNumInteractions; ++k) {
-            const int d = c_dslot.s[tl.cls][k];
-            const int32_t src = (box >= 0) ? il[k] : -1;
-            double b[KQ];
-            if (src >= 0) {
-                const double* qs = Q + size_t(src) * P + g * KQ;
-                #pragma unroll
-                for (int kk = 0; kk < KQ; ++kk) b[kk] = qs[kk];
-            } else {
-                #pragma unroll
-                for (int kk = 0; kk < KQ; ++kk) b[kk] = 0.0;
-            }
-            const double* T = ifo + (size_t(tl.height) * kNumIfoSlots + d) * P * P;
-            #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                const double* a = T + size_t(16 * m + n) * P + g * KQ;
-                #pragma unroll
-                for (int kk = 0; kk < KQ; ++kk)
-                    acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b[kk], acc[m], 0, 0, 0);
-            }
-        }
-        if (box >= 0) {
-            double* ub = U + size_t(box) * P;
-            #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                #pragma unroll
-                for (int i = 0; i < 4; ++i) ub[16 * m + g + 4 * i] = acc[m][i];
-            }
-        }
-    }
+    if (lane < P) Q[size_t(g) * P + lane] = (a0 + a1) + (a2 + a3);
 }
 
 // XCD-aware tile order: blocks are dispatched round-robin over the 8 XCDs (block b runs on
@@ -190,48 +115,72 @@ __device__ inline int32_t xcd_tile(int32_t b, int32_t G, int32_t step, int32_t n
     return (t < min(ntiles, (x + 1) * chunk)) ? t : -1;
 }
 
-// M2L with the 27 list slots of a 16-box tile split over the four waves of a block (slots
-// k = wave, wave + 4, ...), partial products reduced through LDS in a fixed order, so the
-// result is deterministic and a level with few boxes still gives every SIMD several waves.
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_m2l_split(const M2LTile* tiles, const int32_t* ntiles_p,
-                                                       const int32_t* cls_box, const int32_t* ilist,
-                                                       int32_t ilist_off, const double* Q, double* U,
-                                                       const double* ifo) {
+// Box-matrix products on the FP64 matrix cores: for a tile of up to 16 target boxes that
+// share their operators, out[box] (+)= sum_k A_k in[src_k(box)] with 48 x 48 operators A_k:
+//   M2L: k = 27 interaction slots, A_k = T_ifo^d(c, k) at the tile's height, out = U;
+//   M2M: k = 4 children,            A_k = T_ofo^(k) at the tile's height,      out = Q;
+//   L2L: k = the parent,            A   = T_ofo^(c)T at the parent's height,  out += U.
+// The 16x16x4 FP64 instruction is issued per 16-row block of A: in step kk lane group g
+// (= lane / 16) contributes column q = g * 12 + kk, so each lane's operands are 12
+// consecutive doubles of a row of A and of the source expansion.  The instruction returns
+// element i of lane (g, n) as row g + 4 i, column n.  Slots are split over the block's four
+// waves (rows, for the single-slot L2L) and partial results are summed through LDS in a
+// fixed order, so results are deterministic.
+template <int P, int MODE>
+__global__ __launch_bounds__(kBlock) void k_boxmat(const BoxTile* tiles, int32_t tile0, const int32_t* ntiles_dev,
+                                                    int32_t ntiles_host, const int32_t* box_list, const int32_t* src_tab,
+                                                    const OpsPtrs* ops, const double* in, double* out) {
     constexpr int MT = P / 16, KQ = P / 4;
+    constexpr int NSRC = (MODE == kModeM2L) ? kNumInteractions : (MODE == kModeM2M ? 4 : 1);
     __shared__ double red[kWaves - 1][P][16];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int n = lane & 15, g = lane >> 4;
-    const int32_t ntiles = *ntiles_p;
+    const int32_t ntiles = ntiles_dev ? *ntiles_dev : ntiles_host;
     const int32_t G = int32_t(gridDim.x);
     for (int32_t step = 0;; ++step) {
         const int32_t t = xcd_tile(int32_t(blockIdx.x), G, step, ntiles);
         if (t < 0) break;                                   // uniform over the block
-        const M2LTile tl = tiles[t];
-        const int32_t box = (n < tl.count) ? cls_box[tl.start + n] : -1;
-        const int32_t* il = ilist + size_t(box >= 0 ? box - ilist_off : 0) * kNumInteractions;
+        const BoxTile tl = tiles[tile0 + t];
+        if (tl.count == 0) continue;
+        const int32_t box = (n < tl.count) ? (box_list ? box_list[tl.start + n] : tl.start + n) : -1;
+        const OpsPtrs& op = ops[tl.ops];
         double4_t acc[MT];
         #pragma unroll
         for (int m = 0; m < MT; ++m) acc[m] = double4_t{0.0, 0.0, 0.0, 0.0};
-        for (int k = wave; k < kNumInteractions; k += kWaves) {
-            const int d = c_dslot.s[tl.cls][k];
-            const int32_t src = (box >= 0) ? il[k] : -1;
-            double b[KQ];
-            if (src >= 0) {
-                const double* qs = Q + size_t(src) * P + g * KQ;
+        const int k_first = (NSRC >= kWaves) ? wave : 0;
+        const int k_step = (NSRC >= kWaves) ? kWaves : 1;
+        const bool active = (NSRC >= kWaves) || wave < MT;   // single-slot L2L: wave = row block
+        if (active) {
+            for (int k = k_first; k < NSRC; k += k_step) {
+                int32_t src = -1;
+                const double* A;
+                if (MODE == kModeM2L) {
+                    src = (box >= 0) ? src_tab[size_t(box) * kNumInteractions + k] : -1;
+                    A = op.ifo + (size_t(tl.height) * kNumIfoSlots + c_dslot.s[tl.cls][k]) * P * P;
+                } else if (MODE == kModeM2M) {
+                    src = (box >= 0) ? src_tab[size_t(box) * 4 + k] : -1;
+                    A = op.ofo_rm + (size_t(tl.height) * 4 + k) * P * P;
+                } else {
+                    src = (box >= 0) ? src_tab[box] : -1;
+                    A = op.ofo_cm + (size_t(tl.height + 1) * 4 + tl.cls) * P * P;
+                }
+                double b[KQ];
+                if (src >= 0) {
+                    const double* qs = in + size_t(src) * P + g * KQ;
+                    #pragma unroll
+                    for (int kk = 0; kk < KQ; ++kk) b[kk] = qs[kk];
+                } else {
+                    #pragma unroll
+                    for (int kk = 0; kk < KQ; ++kk) b[kk] = 0.0;
+                }
                 #pragma unroll
-                for (int kk = 0; kk < KQ; ++kk) b[kk] = qs[kk];
-            } else {
-                #pragma unroll
-                for (int kk = 0; kk < KQ; ++kk) b[kk] = 0.0;
-            }
-            const double* T = ifo + (size_t(tl.height) * kNumIfoSlots + d) * P * P;
-            #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                const double* a = T + size_t(16 * m + n) * P + g * KQ;
-                #pragma unroll
-                for (int kk = 0; kk < KQ; ++kk)
-                    acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b[kk], acc[m], 0, 0, 0);
+                for (int m = 0; m < MT; ++m) {
+                    if (MODE == kModeL2L && m != wave) continue;
+                    const double* a = A + size_t(16 * m + n) * P + g * KQ;
+                    #pragma unroll
+                    for (int kk = 0; kk < KQ; ++kk)
+                        acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b[kk], acc[m], 0, 0, 0);
+                }
             }
         }
         if (wave > 0) {
@@ -243,16 +192,16 @@ __global__ __launch_bounds__(kBlock) void k_m2l_split(const M2LTile* tiles, cons
         }
         __syncthreads();
         if (wave == 0 && box >= 0) {
-            double* ub = U + size_t(box) * P;
+            double* ob = out + size_t(box) * P;
             #pragma unroll
             for (int m = 0; m < MT; ++m) {
                 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int r = 16 * m + g + 4 * i;   // FP64 output layout
+                    const int r = 16 * m + g + 4 * i;
                     double v = acc[m][i];
                     #pragma unroll
                     for (int w = 0; w < kWaves - 1; ++w) v += red[w][r][n];
-                    ub[r] = v;
+                    ob[r] = (MODE == kModeL2L) ? ob[r] + v : v;
                 }
             }
         }
@@ -267,31 +216,33 @@ __global__ __launch_bounds__(kBlock) void k_m2l_split(const M2LTile* tiles, cons
 // each 16x16x4 step forms R_hi q_hi in one FP32 accumulator and R_hi q_lo + R_lo q_hi in
 // another (the cross terms are ~2^-24 of the first and would be rounded away if added to
 // it), and both are flushed into FP64 accumulators after every step, so FP32 rounding acts on
-// four-term partial sums only.  u-hat is stored in FP64.
-typedef float float4_t __attribute__((ext_vector_type(4)));
-
+// four-term partial sums only.  The FP32 instruction returns element i of lane (g, n) as row
+// 4 g + i.  Slots are split over the waves of a block as in the FP64 kernel.
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_m2l_mixed(const M2LTile* tiles, const int32_t* ntiles_p,
-                                                       const int32_t* cls_box, const int32_t* ilist,
-                                                       int32_t ilist_off, const double* Q, double* U,
-                                                       const float* ifo_hi, const float* ifo_lo,
-                                                       const double* mono, const int32_t* rank) {
+__global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_p,
+                                                       const int32_t* box_list, const int32_t* il27,
+                                                       const OpsPtrs* ops, const double* Q, double* U) {
     constexpr int MT = P / 16, KQ = P / 4;
+    __shared__ double red[kWaves - 1][P][16];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int n = lane & 15, g = lane >> 4;
     const int32_t ntiles = *ntiles_p;
+    const int32_t G = int32_t(gridDim.x);
     const float4_t zero = {0.f, 0.f, 0.f, 0.f};
-    for (int32_t t = int32_t(blockIdx.x) * kWaves + wave; t < ntiles; t += int32_t(gridDim.x) * kWaves) {
-        const M2LTile tl = tiles[t];
-        const int32_t box = (n < tl.count) ? cls_box[tl.start + n] : -1;
-        const int32_t* il = ilist + size_t(box >= 0 ? box - ilist_off : 0) * kNumInteractions;
-        const int rk = rank[tl.height];
+    for (int32_t step = 0;; ++step) {
+        const int32_t t = xcd_tile(int32_t(blockIdx.x), G, step, ntiles);
+        if (t < 0) break;
+        const BoxTile tl = tiles[t];
+        if (tl.count == 0) continue;
+        const int32_t box = (n < tl.count) ? box_list[tl.start + n] : -1;
+        const OpsPtrs& op = ops[tl.ops];
+        const int rk = op.rank[tl.height];
         double4_t acc[MT];
         #pragma unroll
         for (int m = 0; m < MT; ++m) acc[m] = double4_t{0.0, 0.0, 0.0, 0.0};
-        for (int k = 0; k < kNumInteractions; ++k) {
+        for (int k = wave; k < kNumInteractions; k += kWaves) {
             const int d = c_dslot.s[tl.cls][k];
-            const int32_t src = (box >= 0) ? il[k] : -1;
+            const int32_t src = (box >= 0) ? il27[size_t(box) * kNumInteractions + k] : -1;
             float bh[KQ], bl[KQ];
             double qsum = 0.0;
             #pragma unroll
@@ -304,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const M2LTile* tiles, cons
             // charge sum of source column n: the four lane groups hold a quarter each
             qsum += __shfl_xor(qsum, 16, 64);
             qsum += __shfl_xor(qsum, 32, 64);
-            const double cq = mono[size_t(tl.height) * kNumIfoSlots + d] * qsum;
+            const double cq = op.mono[size_t(tl.height) * kNumIfoSlots + d] * qsum;
             #pragma unroll
             for (int m = 0; m < MT; ++m) {
                 #pragma unroll
@@ -314,11 +265,11 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const M2LTile* tiles, cons
             const size_t base = (size_t(tl.height) * kNumIfoSlots + d) * P * P;
             #pragma unroll
             for (int m = 0; m < MT; ++m) {
-                const float* ah = ifo_hi + base + size_t(16 * m + n) * P + g * KQ;
-                const float* al = ifo_lo + base + size_t(16 * m + n) * P + g * KQ;
+                const float* ah = op.ifo_hi + base + size_t(16 * m + n) * P + g * KQ;
+                const float* al = op.ifo_lo + base + size_t(16 * m + n) * P + g * KQ;
                 #pragma unroll
                 for (int kk = 0; kk < KQ; ++kk) {
-                    float4_t main = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[kk], bh[kk], zero, 0, 0, 0);
+                    const float4_t main = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[kk], bh[kk], zero, 0, 0, 0);
                     float4_t cross = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[kk], bl[kk], zero, 0, 0, 0);
                     cross = __builtin_amdgcn_mfma_f32_16x16x4f32(al[kk], bh[kk], cross, 0, 0, 0);
                     #pragma unroll
@@ -326,90 +277,50 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const M2LTile* tiles, cons
                 }
             }
         }
-        if (box >= 0) {
+        if (wave > 0) {
+            #pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                #pragma unroll
+                for (int i = 0; i < 4; ++i) red[wave - 1][16 * m + 4 * g + i][n] = acc[m][i];
+            }
+        }
+        __syncthreads();
+        if (wave == 0 && box >= 0) {
             double* ub = U + size_t(box) * P;
             #pragma unroll
             for (int m = 0; m < MT; ++m) {
                 #pragma unroll
-                for (int i = 0; i < 4; ++i) ub[16 * m + 4 * g + i] = acc[m][i];
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 16 * m + 4 * g + i;   // FP32 output layout
+                    double v = acc[m][i];
+                    #pragma unroll
+                    for (int w = 0; w < kWaves - 1; ++w) v += red[w][r][n];
+                    ub[r] = v;
+                }
             }
-        }
-    }
-}
-
-// Leaf pass: for every point of a leaf (lanes = targets), the far field T_tfi u-hat with
-// T_tfi = T_ofs^T (Section 7, symmetric kernel and targets = sources), plus the direct sum
-// over the points of the leaf and its neighbors (Section 8.2 step 5), written back in the
-// caller's point order.  QUAD: every near offset lies in a W x W quadrant table in LDS;
-// otherwise the octant table of radius 128 sits in LDS and larger offsets use eq. (3.1).
-template <int P, bool QUAD>
-__global__ __launch_bounds__(kBlock) void k_leaf_eval(int64_t nleaves, int32_t leaf_off, const int32_t* box_pt0,
-                                                       const int32_t* box_pt1, const uint64_t* box_key,
-                                                       const int32_t* nlist, int64_t side, int W, const int2* pts,
-                                                       const double* fs, const int32_t* perm, const double* U,
-                                                       const double* leafT, int far, const double* phi_oct_tab,
-                                                       double* u) {
-    extern __shared__ double tab[];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    if (QUAD) {
-        for (int i = tid; i < W * W; i += kBlock) {
-            int dy = i / W, dx = i - dy * W;
-            int hi = max(dx, dy), lo = min(dx, dy);
-            tab[i] = phi_oct_tab[hi * (hi + 1) / 2 + lo];
         }
         __syncthreads();
     }
-    for (int64_t leaf = int64_t(blockIdx.x) * kWaves + wave; leaf < nleaves; leaf += int64_t(gridDim.x) * kWaves) {
-        const int32_t g = leaf_off + int32_t(leaf);
-        const int32_t p0 = box_pt0[g], p1 = box_pt1[g];
-        const uint64_t key = box_key[g];
-        const int32_t cx = int32_t(compact_bits(key) * side), cy = int32_t(compact_bits(key >> 1) * side);
-        const int32_t* nl = nlist + size_t(leaf) * 9;
-        for (int32_t i0 = p0; i0 < p1; i0 += 64) {
-            const int32_t i = i0 + lane;
-            const bool valid = i < p1;
-            const int2 pi = pts[valid ? i : p0];
-            double acc = 0.0;
-            for (int q = 0; q < 9; ++q) {
-                const int32_t nb = nl[q];
-                if (nb < 0) continue;
-                const int32_t s0 = box_pt0[nb], s1 = box_pt1[nb];
-                for (int32_t j = s0; j < s1; ++j) {
-                    const int2 pj = pts[j];
-                    const int dx = abs(pi.x - pj.x), dy = abs(pi.y - pj.y);
-                    double ph;
-                    if (QUAD) {
-                        ph = tab[dy * W + dx];
-                    } else {
-                        ph = phi_oct(dx, dy, phi_oct_tab);
-                    }
-                    acc += ph * fs[j];
-                }
-            }
-            if (far) {
-                const int64_t loc = int64_t(pi.x - cx) + side * int64_t(pi.y - cy);
-                const double* tl = leafT + loc * P;
-                const double* uh = U + size_t(g) * P;
-                #pragma unroll 8
-                for (int p = 0; p < P; ++p) acc += tl[p] * uh[p];
-            }
-            if (valid) u[perm[i]] = acc;
-        }
-    }
 }
 
-// Near field + L2P, second form, for leaves of side <= 32.  A wave takes one leaf at a time:
-// the points of the 9 leaves around it are staged once into the wave's part of LDS, and the
-// wave's 64 lanes are split into S slices of T lanes (T = targets per pass, a power of two),
-// slice s summing sources s, s + S, ...; slices are reduced with xor shuffles.  For leaves of
-// side s <= 16 phi sits in a window table over all offsets in [-(2s-1), 2s-1]^2 and each
-// point carries the key K = 8 (y W + x) mod 2^32 (W = 4s - 1), so the byte offset of phi(x_i
-// - x_j) in the table is K_i - K_j plus a constant: one integer subtraction per pair.  For
-// side 32 a quadrant table over |dx|, |dy| < 64 is used.
-constexpr int kStage = 384;   // staged sources per wave and pass
+// Leaf pass: far field T_tfi u-hat with T_tfi = T_ofs^T (Section 7, symmetric kernel and
+// targets = sources) plus the direct sum over the points of the leaf and its neighbours
+// (Section 8.2 step 5), written back in the caller's point order.  A wave takes one leaf at
+// a time; the points of the 9 leaves around it are staged once into the wave's part of LDS,
+// and the 64 lanes are split into S slices of T lanes (T = targets per pass, a power of two),
+// slice s summing sources s, s + S, ...; slices are reduced with xor shuffles.
+//   WINDOW (side <= 16): phi sits in a window table over all offsets in [-(2s-1), 2s-1]^2 and
+//     each point carries the key K = 8 (y W + x) mod 2^32 (W = 4s - 1), so the byte offset of
+//     phi(x_i - x_j) is K_i - K_j plus a constant: one subtraction per pair.
+//   QUAD (side 32): a table over |dx|, |dy| < 64.
+//   GLOBAL (side >= 64): the octant table of radius 128 in global memory, eq. (3.1) beyond.
+constexpr int kLeafBlock = 512;
+constexpr int kLeafWaves = kLeafBlock / 64;
+constexpr int kStage = 192;   // staged sources per wave and pass
+enum LeafMode { kWindow = 0, kQuad = 1, kGlobal = 2 };
 
 struct SrcRec {
-    uint32_t a, b;   // window mode: a = key; quadrant mode: a = x, b = y
+    uint32_t a, b;   // window mode: a = key; otherwise a = x, b = y
     double f;
 };
 
@@ -419,37 +330,40 @@ __device__ inline void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int P, bool WINDOW>
-__global__ __launch_bounds__(kBlock) void k_leaf_near(int64_t nleaves, int32_t leaf_off, const int32_t* box_pt0,
-                                                       const int32_t* box_pt1, const uint64_t* box_key,
-                                                       const int32_t* nlist, int64_t side, int W, const int2* pts,
-                                                       const uint32_t* pkey, const double* fs, const int32_t* perm,
-                                                       const double* U, const double* leafT, int far,
-                                                       const double* phi_oct_tab, double* u) {
+template <int P, int MODE>
+__global__ __launch_bounds__(kLeafBlock) void k_leaf(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0,
+                                                      const int32_t* box_pt1, const uint64_t* box_key,
+                                                      const int32_t* box_inst, const int32_t* nb9, int64_t side, int W,
+                                                      const int2* pts, const uint32_t* pkey, const double* fs,
+                                                      const int32_t* perm_local, const ExecPtrs* tab_ptrs,
+                                                      double* u_single, const double* U, const double* leafT,
+                                                      const uint8_t* far_inst, const double* phi_oct_tab) {
     extern __shared__ double smem[];
     double* tab = smem;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    SrcRec* stage = reinterpret_cast<SrcRec*>(smem + ((W * W + 1) & ~1)) + wave * kStage;   // 16-B aligned
-    const int c = WINDOW ? int(2 * side - 1) : 0;
-    for (int i = tid; i < W * W; i += kBlock) {
-        int dy = i / W - c, dx = i - (i / W) * W - c;
-        dx = dx < 0 ? -dx : dx;
-        dy = dy < 0 ? -dy : dy;
-        int hi = max(dx, dy), lo = min(dx, dy);
-        tab[i] = phi_oct_tab[hi * (hi + 1) / 2 + lo];
+    const int tabn = (MODE == kGlobal) ? 0 : ((W * W + 1) & ~1);   // keeps the staging 16-B aligned
+    SrcRec* stage = reinterpret_cast<SrcRec*>(smem + tabn) + wave * kStage;
+    const int c = (MODE == kWindow) ? int(2 * side - 1) : 0;
+    if (MODE != kGlobal) {
+        for (int i = tid; i < W * W; i += kLeafBlock) {
+            int dy = i / W - c, dx = i - (i / W) * W - c;
+            dx = dx < 0 ? -dx : dx;
+            dy = dy < 0 ? -dy : dy;
+            const int hi = max(dx, dy), lo = min(dx, dy);
+            tab[i] = phi_oct_tab[hi * (hi + 1) / 2 + lo];
+        }
+        __syncthreads();
     }
-    __syncthreads();
     const char* tb = reinterpret_cast<const char*>(tab) + size_t(8) * size_t(c * W + c);
-    for (int64_t leaf = int64_t(blockIdx.x) * kWaves + wave; leaf < nleaves; leaf += int64_t(gridDim.x) * kWaves) {
-        const int32_t g = leaf_off + int32_t(leaf);
+    for (int32_t g = leaf0 + int32_t(blockIdx.x) * kLeafWaves + wave; g < leaf1;
+         g += int32_t(gridDim.x) * kLeafWaves) {
         const int32_t p0 = box_pt0[g], p1 = box_pt1[g];
         const int32_t nt = p1 - p0;
         int T = 1;
         while (T < nt && T < 64) T <<= 1;
         const int S = 64 / T, t = lane & (T - 1), sl = lane / T;
-        // the 9 neighbour ranges (uniform)
         int32_t b0[9], cnt[9], total = 0;
-        const int32_t* nl = nlist + size_t(leaf) * 9;
+        const int32_t* nl = nb9 + size_t(g) * 9;
         #pragma unroll
         for (int q = 0; q < 9; ++q) {
             const int32_t nb = nl[q];
@@ -457,6 +371,9 @@ __global__ __launch_bounds__(kBlock) void k_leaf_near(int64_t nleaves, int32_t l
             cnt[q] = nb >= 0 ? box_pt1[nb] - b0[q] : 0;
             total += cnt[q];
         }
+        const int32_t k_inst = box_inst[g];
+        const bool far = far_inst[k_inst] != 0;
+        double* u = tab_ptrs ? tab_ptrs[k_inst].u : u_single;
         const uint64_t key = box_key[g];
         const int32_t cx = int32_t(compact_bits(key) * side), cy = int32_t(compact_bits(key >> 1) * side);
         for (int32_t i0 = p0; i0 < p1; i0 += T) {
@@ -464,8 +381,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf_near(int64_t nleaves, int32_t l
             const bool valid = i < p1;
             const int32_t ii = valid ? i : p0;
             const int2 pi = pts[ii];
-            const uint32_t ki = WINDOW ? pkey[ii] : 0u;
-            double acc = 0.0;
+            const uint32_t ki = (MODE == kWindow) ? pkey[ii] : 0u;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
             for (int32_t c0 = 0; c0 < total; c0 += kStage) {
                 const int32_t cn = min(kStage, total - c0);
                 for (int32_t pos = lane; pos < cn; pos += 64) {
@@ -478,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_near(int64_t nleaves, int32_t l
                         }
                     }
                     SrcRec rec;
-                    if (WINDOW) {
+                    if (MODE == kWindow) {
                         rec.a = pkey[j];
                         rec.b = 0u;
                     } else {
@@ -490,16 +407,23 @@ __global__ __launch_bounds__(kBlock) void k_leaf_near(int64_t nleaves, int32_t l
                     stage[pos] = rec;
                 }
                 wave_sync_lds();
-                for (int32_t jj = sl; jj < cn; jj += S) {
-                    const SrcRec rec = stage[jj];
-                    double ph;
-                    if (WINDOW) {
-                        ph = *reinterpret_cast<const double*>(tb + int32_t(ki - rec.a));
-                    } else {
-                        const int dx = abs(pi.x - int32_t(rec.a)), dy = abs(pi.y - int32_t(rec.b));
-                        ph = tab[dy * W + dx];
-                    }
-                    acc += ph * rec.f;
+                auto phi_of = [&](const SrcRec& rec) -> double {
+                    if (MODE == kWindow) return *reinterpret_cast<const double*>(tb + int32_t(ki - rec.a));
+                    const int dx = abs(pi.x - int32_t(rec.a)), dy = abs(pi.y - int32_t(rec.b));
+                    if (MODE == kQuad) return tab[dy * W + dx];
+                    return phi_oct(dx, dy, phi_oct_tab);
+                };
+                int32_t jj = sl;
+                for (; jj + 3 * S < cn; jj += 4 * S) {
+                    const SrcRec r0 = stage[jj], r1 = stage[jj + S], r2 = stage[jj + 2 * S], r3 = stage[jj + 3 * S];
+                    a0 += phi_of(r0) * r0.f;
+                    a1 += phi_of(r1) * r1.f;
+                    a2 += phi_of(r2) * r2.f;
+                    a3 += phi_of(r3) * r3.f;
+                }
+                for (; jj < cn; jj += S) {
+                    const SrcRec r0 = stage[jj];
+                    a0 += phi_of(r0) * r0.f;
                 }
                 wave_sync_lds();
             }
@@ -507,19 +431,19 @@ __global__ __launch_bounds__(kBlock) void k_leaf_near(int64_t nleaves, int32_t l
                 const int64_t loc = int64_t(pi.x - cx) + side * int64_t(pi.y - cy);
                 const double* tl = leafT + loc * P;
                 const double* uh = U + size_t(g) * P;
-                for (int p = sl; p < P; p += S) acc += tl[p] * uh[p];
+                int p = sl;
+                for (; p + 3 * S < P; p += 4 * S) {
+                    a0 += tl[p] * uh[p];
+                    a1 += tl[p + S] * uh[p + S];
+                    a2 += tl[p + 2 * S] * uh[p + 2 * S];
+                    a3 += tl[p + 3 * S] * uh[p + 3 * S];
+                }
+                for (; p < P; p += S) a0 += tl[p] * uh[p];
             }
+            double acc = (a0 + a1) + (a2 + a3);
             for (int o = T; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
-            if (sl == 0 && valid) u[perm[i]] = acc;
+            if (sl == 0 && valid) u[perm_local[i]] = acc;
         }
-    }
-}
-
-__global__ void k_point_keys(const int2* pts, int64_t n, uint32_t W, uint32_t* key) {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) {
-        const int2 p = pts[i];
-        key[i] = 8u * (uint32_t(p.y) * W + uint32_t(p.x));   // modulo 2^32 on purpose
     }
 }
 
@@ -555,17 +479,13 @@ __global__ __launch_bounds__(kBlock) void k_direct(int64_t nt, const int2* txy, 
     if (valid) u[t] = acc;
 }
 
-inline unsigned grid_for(int64_t n, int per_block = kBlock) {
-    int64_t g = (n + per_block - 1) / per_block;
-    return unsigned(g < 1 ? 1 : g);
-}
-
 }  // namespace
 
 hipError_t upload_dslots() {
     DSlots ds{};
     for (int c = 0; c < 4; ++c) {
-        int cx = c & 1, cy = c >> 1, k = 0;
+        const int cx = c & 1, cy = c >> 1;
+        int k = 0;
         for (int dy = -2 - cy; dy <= 3 - cy; ++dy)
             for (int dx = -2 - cx; dx <= 3 - cx; ++dx) {
                 if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
@@ -584,101 +504,74 @@ hipError_t upload_dslots() {
     return hipSuccess;
 }
 
-void launch_gather_f(const double* f, const int32_t* perm, int64_t n, double* fs, hipStream_t st) {
-    hipLaunchKernelGGL(k_gather_f, dim3(grid_for(n)), dim3(kBlock), 0, st, f, perm, n, fs);
+void launch_gather_f(const ExecPtrs* tab, const double* f_single, const int32_t* perm_local, const int32_t* pinst,
+                     int64_t n, double* fs, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_f, dim3(grid_for(n)), dim3(kBlock), 0, st, tab, f_single, perm_local, pinst, n, fs);
 }
 
-void launch_p2m_dense(int64_t nleaves, int32_t leaf_off, const int32_t* box_pt0, const int32_t* box_pt1,
-                      const uint64_t* box_key, int L, int64_t side, const int32_t* pts, const double* fs,
-                      const double* leafT, double* Q, hipStream_t st) {
-    (void)L;
-    if (nleaves <= 0) return;
-    hipLaunchKernelGGL(k_p2m_dense<kRankPad>, dim3(grid_for(nleaves, kWaves)), dim3(kBlock), 0, st, nleaves,
-                       leaf_off, box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), fs, leafT, Q);
+void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1, const uint64_t* box_key,
+                int64_t side, const int32_t* pts, const double* fs, const double* leafT, double* Q, hipStream_t st) {
+    if (leaf1 <= leaf0) return;
+    hipLaunchKernelGGL(k_p2m<kRankPad>, dim3(grid_for(leaf1 - leaf0, kWaves)), dim3(kBlock), 0, st, leaf0, leaf1,
+                       box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), fs, leafT, Q);
 }
 
-void launch_m2m(int32_t box_begin, int32_t box_end, int height, const int32_t* box_child, const double* ofo_cm,
-                const double* Q_in, double* Q_out, hipStream_t st) {
-    (void)Q_in;
-    if (box_end <= box_begin) return;
-    hipLaunchKernelGGL(k_m2m<kRankPad>, dim3(grid_for(box_end - box_begin, kWaves)), dim3(kBlock), 0, st, box_begin,
-                       box_end, height, box_child, ofo_cm, Q_out);
-}
-
-void launch_l2l(int32_t box_begin, int32_t box_end, int height_parent, const int32_t* box_parent,
-                const uint64_t* box_key, const double* ofo_rm, double* U, hipStream_t st) {
-    if (box_end <= box_begin) return;
-    hipLaunchKernelGGL(k_l2l<kRankPad>, dim3(grid_for(box_end - box_begin, kWaves)), dim3(kBlock), 0, st, box_begin,
-                       box_end, height_parent, box_parent, box_key, ofo_rm, U);
-}
-
-void launch_m2l(const M2LTile* tiles, const int32_t* ntiles, int32_t max_tiles, const int32_t* cls_box,
-                const int32_t* ilist, int32_t ilist_off, const double* Q, double* U, const double* ifo,
-                bool simple, hipStream_t st) {
+void launch_boxmat(int mode, const BoxTile* tiles, int32_t tile0, const int32_t* ntiles_dev, int32_t ntiles_host,
+                   int32_t max_tiles, const int32_t* box_list, const int32_t* src, const OpsPtrs* ops,
+                   const double* in, double* out, hipStream_t st) {
     if (max_tiles <= 0) return;
-    if (simple) {
-        unsigned g = grid_for(max_tiles, kWaves);
-        if (g > 2048) g = 2048;
-        hipLaunchKernelGGL(k_m2l<kRankPad>, dim3(g), dim3(kBlock), 0, st, tiles, ntiles, cls_box, ilist, ilist_off,
-                           Q, U, ifo);
-        return;
-    }
     // one tile per block and step; a multiple of 8 blocks keeps the XCD chunks balanced
     int64_t g = std::min<int64_t>(max_tiles, 8192);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
-    hipLaunchKernelGGL(k_m2l_split<kRankPad>, dim3(unsigned(g)), dim3(kBlock), 0, st, tiles, ntiles, cls_box, ilist,
-                       ilist_off, Q, U, ifo);
+    const dim3 grid(static_cast<unsigned>(g)), block(kBlock);
+    if (mode == kModeM2L)
+        hipLaunchKernelGGL((k_boxmat<kRankPad, kModeM2L>), grid, block, 0, st, tiles, tile0, ntiles_dev, ntiles_host,
+                           box_list, src, ops, in, out);
+    else if (mode == kModeM2M)
+        hipLaunchKernelGGL((k_boxmat<kRankPad, kModeM2M>), grid, block, 0, st, tiles, tile0, ntiles_dev, ntiles_host,
+                           box_list, src, ops, in, out);
+    else
+        hipLaunchKernelGGL((k_boxmat<kRankPad, kModeL2L>), grid, block, 0, st, tiles, tile0, ntiles_dev, ntiles_host,
+                           box_list, src, ops, in, out);
 }
 
-void launch_point_keys(const int32_t* pts, int64_t n, int64_t side, uint32_t* key, hipStream_t st) {
-    hipLaunchKernelGGL(k_point_keys, dim3(grid_for(n)), dim3(kBlock), 0, st, reinterpret_cast<const int2*>(pts), n,
-                       uint32_t(4 * side - 1), key);
-}
-
-void launch_m2l_mixed(const M2LTile* tiles, const int32_t* ntiles, int32_t max_tiles, const int32_t* cls_box,
-                      const int32_t* ilist, int32_t ilist_off, const double* Q, double* U, const float* ifo_hi,
-                      const float* ifo_lo, const double* mono, const int32_t* rank, hipStream_t st) {
+void launch_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t max_tiles, const int32_t* box_list,
+                      const int32_t* il27, const OpsPtrs* ops, const double* Q, double* U, hipStream_t st) {
     if (max_tiles <= 0) return;
-    unsigned g = grid_for(max_tiles, kWaves);
-    if (g > 2048) g = 2048;
-    hipLaunchKernelGGL(k_m2l_mixed<kRankPad>, dim3(g), dim3(kBlock), 0, st, tiles, ntiles, cls_box, ilist, ilist_off,
-                       Q, U, ifo_hi, ifo_lo, mono, rank);
+    int64_t g = std::min<int64_t>(max_tiles, 8192);
+    g = std::max<int64_t>(8, (g + 7) / 8 * 8);
+    hipLaunchKernelGGL(k_m2l_mixed<kRankPad>, dim3(unsigned(g)), dim3(kBlock), 0, st, tiles, ntiles_dev, box_list,
+                       il27, ops, Q, U);
 }
 
-void launch_leaf_eval(int64_t nleaves, int32_t leaf_off, const int32_t* box_pt0, const int32_t* box_pt1,
-                      const uint64_t* box_key, const int32_t* nlist, int L, int64_t side, const int32_t* pts,
-                      const uint32_t* pkey, const double* fs, const int32_t* perm, const double* U,
-                      const double* leafT, bool far, const double* phi_oct, double* u, bool simple, hipStream_t st) {
-    (void)L;
-    if (nleaves <= 0) return;
-    unsigned g = grid_for(nleaves, kWaves);
-    if (g > 4096) g = 4096;
-    if (!simple && side <= 16 && pkey) {
-        const int Ww = int(4 * side - 1);
-        size_t lds = size_t((Ww * Ww + 1) & ~1) * sizeof(double) + size_t(kWaves) * kStage * sizeof(SrcRec);
-        hipLaunchKernelGGL((k_leaf_near<kRankPad, true>), dim3(g), dim3(kBlock), lds, st, nleaves, leaf_off, box_pt0,
-                           box_pt1, box_key, nlist, side, Ww, reinterpret_cast<const int2*>(pts), pkey, fs, perm, U,
-                           leafT, far ? 1 : 0, phi_oct, u);
-        return;
-    }
-    if (!simple && side <= 32) {
-        const int Wq = int(2 * side);
-        size_t lds = size_t((Wq * Wq + 1) & ~1) * sizeof(double) + size_t(kWaves) * kStage * sizeof(SrcRec);
-        hipLaunchKernelGGL((k_leaf_near<kRankPad, false>), dim3(g), dim3(kBlock), lds, st, nleaves, leaf_off,
-                           box_pt0, box_pt1, box_key, nlist, side, Wq, reinterpret_cast<const int2*>(pts), pkey, fs,
-                           perm, U, leafT, far ? 1 : 0, phi_oct, u);
-        return;
-    }
-    const int W = int(2 * side);
-    if (2 * side <= 64) {
-        size_t lds = size_t(W) * W * sizeof(double);
-        hipLaunchKernelGGL((k_leaf_eval<kRankPad, true>), dim3(g), dim3(kBlock), lds, st, nleaves, leaf_off, box_pt0,
-                           box_pt1, box_key, nlist, side, W, reinterpret_cast<const int2*>(pts), fs, perm, U, leafT,
-                           far ? 1 : 0, phi_oct, u);
+void launch_leaf(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1, const uint64_t* box_key,
+                 const int32_t* box_inst, const int32_t* nb9, int64_t side, const int32_t* pts, const uint32_t* pkey,
+                 const double* fs, const int32_t* perm_local, const int32_t* pinst, const InstInfo* inst,
+                 const ExecPtrs* tab, double* u_single, const double* U, const double* leafT,
+                 const uint8_t* far_inst, const double* phi_oct, hipStream_t st) {
+    (void)inst;
+    (void)pinst;
+    if (leaf1 <= leaf0) return;
+    unsigned g = grid_for(leaf1 - leaf0, kLeafWaves);
+    if (g > 2048) g = 2048;
+    const size_t stage = size_t(kLeafWaves) * kStage * sizeof(SrcRec);
+    const int2* p2 = reinterpret_cast<const int2*>(pts);
+    if (side <= 16) {
+        const int W = int(4 * side - 1);
+        const size_t lds = size_t((W * W + 1) & ~1) * sizeof(double) + stage;
+        hipLaunchKernelGGL((k_leaf<kRankPad, kWindow>), dim3(g), dim3(kLeafBlock), lds, st, leaf0, leaf1, box_pt0,
+                           box_pt1, box_key, box_inst, nb9, side, W, p2, pkey, fs, perm_local, tab, u_single, U, leafT,
+                           far_inst, phi_oct);
+    } else if (side <= 32) {
+        const int W = int(2 * side);
+        const size_t lds = size_t((W * W + 1) & ~1) * sizeof(double) + stage;
+        hipLaunchKernelGGL((k_leaf<kRankPad, kQuad>), dim3(g), dim3(kLeafBlock), lds, st, leaf0, leaf1, box_pt0,
+                           box_pt1, box_key, box_inst, nb9, side, W, p2, pkey, fs, perm_local, tab, u_single, U, leafT,
+                           far_inst, phi_oct);
     } else {
-        hipLaunchKernelGGL((k_leaf_eval<kRankPad, false>), dim3(g), dim3(kBlock), 0, st, nleaves, leaf_off,
-                           box_pt0, box_pt1, box_key, nlist, side, W, reinterpret_cast<const int2*>(pts), fs, perm, U,
-                           leafT, far ? 1 : 0, phi_oct, u);
+        hipLaunchKernelGGL((k_leaf<kRankPad, kGlobal>), dim3(g), dim3(kLeafBlock), stage, st, leaf0, leaf1, box_pt0,
+                           box_pt1, box_key, box_inst, nb9, side, 0, p2, pkey, fs, perm_local, tab, u_single, U, leafT,
+                           far_inst, phi_oct);
     }
 }
 

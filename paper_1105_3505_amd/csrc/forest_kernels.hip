@@ -1,0 +1,653 @@
+// Quadtree construction on the GPU for a forest of instances (Section 6, Definition 6.1).
+//
+// Points of every instance are shifted to the origin of their root box [0, 2^D)^2 and given
+// keys (instance << 2 Dmax) | Morton(x, y) (first coordinate in the even bits), so one sort
+// orders all instances at once and every box of every level is a contiguous run of points.
+// The leaf level L of an instance is the smallest level whose boxes hold at most N_leaf of
+// its points (Section 6).  The common-prefix length of consecutive keys tells, per point, at
+// which levels a new box starts; one pass over the sorted keys yields L and the box count of
+// every level; scans over the leaves then place every box.  Neighbour and interaction lists
+// are built top-down: the boxes around a box are children of the boxes around its parent.
+#include "kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <utility>
+
+namespace lfmm {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ inline uint64_t spread_bits(uint32_t v) {
+    uint64_t x = v;
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+}
+
+__device__ inline uint32_t compact_bits(uint64_t x) {
+    x &= 0x5555555555555555ull;
+    x = (x | (x >> 1)) & 0x3333333333333333ull;
+    x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x >> 4)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x >> 8)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x >> 16)) & 0x00000000FFFFFFFFull;
+    return uint32_t(x);
+}
+
+__device__ inline uint64_t morton_mask(int Dmax) {
+    return (Dmax >= 32) ? ~0ull : ((1ull << (2 * Dmax)) - 1ull);
+}
+
+// levels (of a root of side 2^Dmax) at which the boxes of Morton parts a and b coincide
+__device__ inline int common_levels(uint64_t a, uint64_t b, int Dmax) {
+    const uint64_t x = (a ^ b) & morton_mask(Dmax);
+    if (x == 0) return Dmax;
+    return (__clzll(x) - (64 - 2 * Dmax)) >> 1;
+}
+
+// instance owning position i: the largest k with off[k] <= i (off has K + 1 entries)
+__device__ inline int32_t find_inst(const int32_t* off, int32_t K, int64_t i) {
+    int32_t lo = 0, hi = K - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+inline unsigned grid_for(int64_t n, int per_block = kBlock) {
+    int64_t g = (n + per_block - 1) / per_block;
+    return unsigned(g < 1 ? 1 : g);
+}
+
+__global__ void k_concat(int32_t K, const int2* const* xy_tab, const int32_t* pt_off, int64_t n, int2* xyc) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t k = find_inst(pt_off, K, i);
+    xyc[i] = xy_tab[k][i - pt_off[k]];
+}
+
+__device__ inline void block_minmax4(int v[4], int32_t* out) {
+    // v = {min x, min y, max x, max y}: wave shuffles, then the four waves through LDS
+    #pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        v[0] = min(v[0], __shfl_xor(v[0], o, 64));
+        v[1] = min(v[1], __shfl_xor(v[1], o, 64));
+        v[2] = max(v[2], __shfl_xor(v[2], o, 64));
+        v[3] = max(v[3], __shfl_xor(v[3], o, 64));
+    }
+    __shared__ int s[kBlock / 64][4];
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 4; ++q) s[wave][q] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int r[4] = {s[0][0], s[0][1], s[0][2], s[0][3]};
+        for (int w = 1; w < kBlock / 64; ++w) {
+            r[0] = min(r[0], s[w][0]); r[1] = min(r[1], s[w][1]);
+            r[2] = max(r[2], s[w][2]); r[3] = max(r[3], s[w][3]);
+        }
+        for (int q = 0; q < 4; ++q) out[q] = r[q];
+    }
+}
+
+__global__ void k_bbox_chunks(const int2* xy, const Chunk* chunks, int32_t* part) {
+    const Chunk c = chunks[blockIdx.x];
+    int v[4] = {INT_MAX, INT_MAX, INT_MIN, INT_MIN};
+    for (int32_t i = c.begin + int32_t(threadIdx.x); i < c.end; i += kBlock) {
+        const int2 p = xy[i];
+        v[0] = min(v[0], p.x); v[1] = min(v[1], p.y);
+        v[2] = max(v[2], p.x); v[3] = max(v[3], p.y);
+    }
+    block_minmax4(v, part + size_t(blockIdx.x) * 4);
+}
+
+__global__ void k_bbox_final(const int32_t* part, const int32_t* chunk_first, int32_t K, int32_t* bbox) {
+    const int32_t k = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    int r[4] = {INT_MAX, INT_MAX, INT_MIN, INT_MIN};
+    for (int32_t c = chunk_first[k]; c < chunk_first[k + 1]; ++c) {
+        r[0] = min(r[0], part[4 * c]); r[1] = min(r[1], part[4 * c + 1]);
+        r[2] = max(r[2], part[4 * c + 2]); r[3] = max(r[3], part[4 * c + 3]);
+    }
+    for (int q = 0; q < 4; ++q) bbox[4 * k + q] = r[q];
+}
+
+__global__ void k_keys(const int2* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst, int Dmax, int64_t n,
+                       uint64_t* keys, uint32_t* vals) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t k = (K > 1) ? find_inst(pt_off, K, i) : 0;
+    const int2 p = xy[i];
+    const uint32_t x = uint32_t(int64_t(p.x) - inst[k].ox), y = uint32_t(int64_t(p.y) - inst[k].oy);
+    const uint64_t m = spread_bits(x) | (spread_bits(y) << 1);
+    keys[i] = (K > 1) ? ((uint64_t(k) << (2 * Dmax)) | m) : m;
+    vals[i] = uint32_t(i);
+}
+
+__global__ void k_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int2* xy, const InstInfo* inst,
+                                const int32_t* pt_off, int Dmax, int K, int64_t n, int2* pts, int32_t* perm_local,
+                                int32_t* pinst) {
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const uint32_t p = vals[s];
+    const int32_t k = (K > 1) ? int32_t(keys[s] >> (2 * Dmax)) : 0;
+    const int2 q = xy[p];
+    pts[s] = make_int2(int32_t(int64_t(q.x) - inst[k].ox), int32_t(int64_t(q.y) - inst[k].oy));
+    perm_local[s] = int32_t(p) - pt_off[k];
+    pinst[s] = k;
+}
+
+// One block per chunk of one instance: per point the number of levels its box shares with
+// the previous point's (-1 at the instance's first point), a histogram of those counts
+// (equal values of a wave are counted with ballots, one LDS add per distinct value), and the
+// levels shared with the point N_leaf positions ahead (a box of that level would hold more
+// than N_leaf points), reduced to one atomic per block.
+__global__ void k_level_stats(const uint64_t* keys, const Chunk* chunks, const InstInfo* inst, int Dmax, int nleaf,
+                              int8_t* cl, int32_t* hist, int32_t* maxc) {
+    __shared__ int32_t h[kMaxLevels + 2];
+    __shared__ int32_t wmax[kBlock / 64];
+    const Chunk c = chunks[blockIdx.x];
+    const InstInfo& I = inst[c.inst];
+    const int shift = Dmax - I.D;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x < kMaxLevels + 2) h[threadIdx.x] = 0;
+    __syncthreads();
+    int mc = -1;
+    for (int32_t base = c.begin; base < c.end; base += kBlock) {
+        const int32_t s = base + int32_t(threadIdx.x);
+        const bool valid = s < c.end;
+        int v = -1;
+        if (valid) {
+            const uint64_t key = keys[s];
+            v = (s == I.pt0) ? -1 : common_levels(key, keys[s - 1], Dmax) - shift;
+            cl[s] = int8_t(v);
+            if (s + nleaf < I.pt1) mc = max(mc, common_levels(key, keys[s + nleaf], Dmax) - shift);
+        }
+        uint64_t active = __ballot(valid);
+        while (active) {
+            const int leader = __ffsll((unsigned long long)active) - 1;
+            const int vv = __shfl(v, leader, 64);
+            const uint64_t m = __ballot(valid && v == vv);
+            if (lane == leader) atomicAdd(&h[vv + 1], int32_t(__popcll(m)));
+            active &= ~m;
+        }
+    }
+    #pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mc = max(mc, __shfl_xor(mc, o, 64));
+    if (lane == 0) wmax[wave] = mc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int bm = wmax[0];
+        for (int w = 1; w < kBlock / 64; ++w) bm = max(bm, wmax[w]);
+        if (bm >= 0) atomicMax(&maxc[c.inst], bm);
+    }
+    if (threadIdx.x < kMaxLevels + 2 && h[threadIdx.x] != 0)
+        atomicAdd(&hist[size_t(c.inst) * (kMaxLevels + 2) + threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void k_leaf_flags(const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int64_t n, int32_t* flags) {
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s < n) flags[s] = (cl[s] < inst[pinst[s]].L) ? 1 : 0;
+}
+
+__global__ void k_leaf_scatter(const int32_t* flags, const int32_t* scan, const uint64_t* keys, const int8_t* cl,
+                               const int32_t* pinst, const InstInfo* inst, int Dmax, int64_t n, int32_t* leaf_pt0,
+                               uint64_t* leaf_key, int8_t* leaf_cl, int32_t* leaf_inst) {
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= n || !flags[s]) return;
+    const int32_t r = scan[s], k = pinst[s];
+    leaf_pt0[r] = int32_t(s);
+    leaf_key[r] = (keys[s] & morton_mask(Dmax)) >> (2 * (inst[k].D - inst[k].L));
+    leaf_cl[r] = cl[s];
+    leaf_inst[r] = k;
+}
+
+__global__ void k_level_flags(const int8_t* leaf_cl, const int32_t* leaf_inst, const InstInfo* inst, int64_t nleaf,
+                              int32_t* flags) {
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int lev = blockIdx.y;
+    if (b < nleaf) flags[size_t(lev) * nleaf + b] = (lev < inst[leaf_inst[b]].L && leaf_cl[b] < lev) ? 1 : 0;
+}
+
+// One thread per (leaf, level): the leaf that starts a box of that level writes the box and
+// its parent link.
+__global__ void k_build_boxes(const int32_t* lscan, const int8_t* leaf_cl, const int32_t* leaf_pt0,
+                              const uint64_t* leaf_key, const int32_t* leaf_inst, const InstInfo* inst, int64_t nleaf,
+                              uint64_t* box_key, int32_t* box_pt0, int32_t* box_parent, int32_t* box_child,
+                              int32_t* box_inst, int8_t* box_lev) {
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int lev = blockIdx.y;
+    if (b >= nleaf) return;
+    const int32_t k = leaf_inst[b];
+    const InstInfo& I = inst[k];
+    if (lev > I.L) return;
+    const int c = leaf_cl[b];
+    if (lev != I.L && c >= lev) return;
+    const int32_t local = (lev == I.L) ? int32_t(b) - I.leaf_rank0
+                                        : lscan[size_t(lev) * nleaf + b] - lscan[size_t(lev) * nleaf + I.leaf_rank0];
+    const int32_t g = I.lev_base[lev] + local;
+    box_key[g] = leaf_key[b] >> (2 * (I.L - lev));
+    box_pt0[g] = leaf_pt0[b];
+    box_inst[g] = k;
+    box_lev[g] = int8_t(lev);
+    for (int q = 0; q < 4; ++q) box_child[size_t(g) * 4 + q] = -1;
+    if (lev == 0) {
+        box_parent[g] = -1;
+        return;
+    }
+    int32_t pl = 0;
+    if (lev - 1 > 0) {
+        const size_t row = size_t(lev - 1) * nleaf;
+        pl = lscan[row + b] + ((c < lev - 1) ? 1 : 0) - 1 - lscan[row + I.leaf_rank0];
+    }
+    box_parent[g] = I.lev_base[lev - 1] + pl;
+}
+
+__global__ void k_link_boxes(const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_inst,
+                             const int8_t* box_lev, const InstInfo* inst, int64_t nbox, const int32_t* box_pt0,
+                             int32_t* box_child, int32_t* box_pt1) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= nbox) return;
+    const int32_t p = box_parent[g];
+    if (p >= 0) box_child[size_t(p) * 4 + int(box_key[g] & 3ull)] = int32_t(g);
+    const InstInfo& I = inst[box_inst[g]];
+    const int lev = box_lev[g];
+    const int32_t local = int32_t(g) - I.lev_base[lev];
+    box_pt1[g] = (local + 1 < I.lev_count[lev]) ? box_pt0[g + 1] : I.pt1;
+}
+
+// box at lattice-level cell (x, y) of the level of a box whose parent's 3 x 3 neighbourhood
+// (centre = parent at (px, py)) is pn; -1 when absent
+__device__ inline int32_t child_at(int32_t x, int32_t y, int32_t px, int32_t py, const int32_t* pn,
+                                   const int32_t* box_child) {
+    if (x < 0 || y < 0) return -1;
+    const int32_t ox = (x >> 1) - px, oy = (y >> 1) - py;
+    const int32_t q = pn[(oy + 1) * 3 + (ox + 1)];
+    if (q < 0) return -1;
+    return box_child[size_t(q) * 4 + (x & 1) + 2 * (y & 1)];
+}
+
+__global__ void k_lists_height(int32_t g0, int32_t g1, const uint64_t* box_key, const int32_t* box_parent,
+                               const int32_t* box_child, const int8_t* box_lev, int32_t* nb9, int32_t* il27) {
+    const int32_t g = g0 + int32_t(blockIdx.x * blockDim.x + threadIdx.x);
+    if (g >= g1) return;
+    const int lev = box_lev[g];
+    int32_t* nl = nb9 + size_t(g) * 9;
+    if (lev < 2) {   // no interaction list above level 2
+        int32_t* il = il27 + size_t(g) * kNumInteractions;
+        for (int k = 0; k < kNumInteractions; ++k) il[k] = -1;
+    }
+    if (lev == 0) {
+        for (int q = 0; q < 9; ++q) nl[q] = (q == 4) ? g : -1;
+        return;
+    }
+    const uint64_t key = box_key[g];
+    const int32_t bx = int32_t(compact_bits(key)), by = int32_t(compact_bits(key >> 1));
+    const int32_t px = bx >> 1, py = by >> 1;
+    int32_t pn[9];
+    const int32_t* pp = nb9 + size_t(box_parent[g]) * 9;
+    #pragma unroll
+    for (int q = 0; q < 9; ++q) pn[q] = pp[q];
+    #pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+        #pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) nl[(dy + 1) * 3 + dx + 1] = child_at(bx + dx, by + dy, px, py, pn, box_child);
+    if (lev < 2) return;
+    const int cx = bx & 1, cy = by & 1;
+    int32_t* il = il27 + size_t(g) * kNumInteractions;
+    int k = 0;
+    for (int dy = -2 - cy; dy <= 3 - cy; ++dy)
+        for (int dx = -2 - cx; dx <= 3 - cx; ++dx) {
+            if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
+            il[k++] = child_at(bx + dx, by + dy, px, py, pn, box_child);
+        }
+}
+
+__global__ void k_class_flags(const uint64_t* box_key, int64_t nbox, int32_t* flags) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= nbox) return;
+    const int c = int(box_key[g] & 3ull);
+    for (int q = 0; q < 4; ++q) flags[size_t(q) * nbox + g] = (q == c) ? 1 : 0;
+}
+
+__device__ inline int32_t scan_at(const int32_t* cscan, const int32_t* ctotal, int64_t nbox, int c, int64_t g) {
+    return (g < nbox) ? cscan[size_t(c) * nbox + g] : ctotal[c];
+}
+
+// box -> position in the class list of every group containing it
+__global__ void k_class_boxes(const BoxGroup* groups, int32_t ngroups, const int32_t* cscan, const int32_t* ctotal,
+                              const uint64_t* box_key, int64_t nbox, int32_t* cls_box) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= nbox) return;
+    const int c = int(box_key[g] & 3ull);
+    for (int32_t q = 0; q < ngroups; ++q) {   // groups are few (heights x leaf sides x 2)
+        const BoxGroup G = groups[q];
+        if (g < G.g0 || g >= G.g1) continue;
+        const int32_t pos = cscan[size_t(c) * nbox + g] - scan_at(cscan, ctotal, nbox, c, G.g0);
+        cls_box[G.cls_base + c * (G.g1 - G.g0) + pos] = int32_t(g);
+    }
+}
+
+// one thread per (group, class): the tiles of that class, then empty tiles up to the cap
+__global__ void k_class_tiles(const BoxGroup* groups, int32_t ngroups, const int32_t* cscan, const int32_t* ctotal,
+                              int64_t nbox, BoxTile* tiles) {
+    const int32_t q = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= ngroups) return;
+    const BoxGroup G = groups[q];
+    int32_t t = G.tile_base;
+    for (int c = 0; c < 4; ++c) {
+        const int32_t cnt = scan_at(cscan, ctotal, nbox, c, G.g1) - scan_at(cscan, ctotal, nbox, c, G.g0);
+        for (int32_t s = 0; s < cnt; s += 16) {
+            BoxTile tl;
+            tl.ops = G.ops;
+            tl.height = G.height;
+            tl.cls = c;
+            tl.start = G.cls_base + c * (G.g1 - G.g0) + s;
+            tl.count = min(16, cnt - s);
+            tl.pad0 = tl.pad1 = tl.pad2 = 0;
+            tiles[t++] = tl;
+        }
+    }
+    for (; t < G.tile_base + G.tile_cap; ++t) {
+        BoxTile tl{};
+        tl.count = 0;
+        tiles[t] = tl;
+    }
+}
+
+__global__ void k_point_keys(const int2* pts, const int32_t* pinst, const InstInfo* inst, const OpsPtrs* ops,
+                             int64_t n, uint32_t* key) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t side = ops[inst[pinst[i]].ops].side;
+    const int2 p = pts[i];
+    const uint32_t W = uint32_t(4 * side - 1);
+    key[i] = 8u * (uint32_t(p.y) * W + uint32_t(p.x));   // modulo 2^32 on purpose
+}
+
+// ---- radix sort: 8-bit digits, tiles of 4096 keys per block ----------------------------
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kBlock * kRsItems;
+
+__global__ void k_rs_hist(const uint64_t* keys, int64_t n, int shift, uint32_t* hist, int nblk) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = int64_t(blockIdx.x) * kRsTile;
+    for (int i = threadIdx.x; i < kRsTile; i += kBlock) {
+        const int64_t idx = base + i;
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[size_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: within a round of 256 keys, lanes of a wave find equal digits by eight
+// ballots; waves are ordered through LDS counts; rounds and blocks are ordered by offsets.
+__global__ void k_rs_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t n,
+                             int shift, const int32_t* offs, int nblk) {
+    __shared__ uint32_t running[256];
+    __shared__ uint32_t wcnt[kBlock / 64][256];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    running[tid] = uint32_t(offs[size_t(tid) * nblk + blockIdx.x]);
+    const int64_t base = int64_t(blockIdx.x) * kRsTile;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < kRsItems; ++r) {
+        for (int w = 0; w < kBlock / 64; ++w) wcnt[w][tid] = 0;
+        __syncthreads();
+        const int64_t idx = base + int64_t(r) * kBlock + tid;
+        const bool valid = idx < n;
+        const uint64_t key = valid ? kin[idx] : 0ull;
+        const uint32_t d = uint32_t((key >> shift) & 255u);
+        uint64_t mask = __ballot(valid);
+        #pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bb = __ballot(valid && ((d >> b) & 1u));
+            mask &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        const uint32_t rank = uint32_t(__popcll(mask & lt_mask));
+        if (valid && rank == 0) wcnt[wave][d] = uint32_t(__popcll(mask));
+        __syncthreads();
+        if (valid) {
+            uint32_t pre = 0;
+            for (int w = 0; w < wave; ++w) pre += wcnt[w][d];
+            const uint32_t pos = running[d] + pre + rank;
+            kout[pos] = key;
+            vout[pos] = vin[idx];
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int w = 0; w < kBlock / 64; ++w) add += wcnt[w][tid];
+        running[tid] += add;
+        __syncthreads();
+    }
+}
+
+// ---- exclusive scan over rows of int32 -------------------------------------------------
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ inline int32_t block_exclusive_scan(int32_t v, int32_t* total) {
+    __shared__ int32_t wsum[kBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t x = v;
+    #pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    int32_t pre = 0, tot = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+        if (w < wave) pre += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + x - v;
+}
+
+__global__ void k_scan_tiles(const int32_t* in, int32_t* out, int64_t n, int32_t* bsum, int nblk) {
+    const int row = blockIdx.y;
+    const int32_t* rin = in + size_t(row) * n;
+    int32_t* rout = out + size_t(row) * n;
+    const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+    int32_t v[kScanItems];
+    int32_t s = 0;
+    #pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? rin[base + k] : 0;
+        s += v[k];
+    }
+    int32_t tot;
+    int32_t pre = block_exclusive_scan(s, &tot);
+    #pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) rout[base + k] = pre;
+        pre += v[k];
+    }
+    if (threadIdx.x == 0) bsum[size_t(row) * nblk + blockIdx.x] = tot;
+}
+
+__global__ void k_scan_add(int32_t* out, int64_t n, const int32_t* bscan, int nblk) {
+    const int row = blockIdx.y;
+    const int32_t add = bscan[size_t(row) * nblk + blockIdx.x];
+    const int64_t base = int64_t(blockIdx.x) * kScanTile;
+    for (int k = threadIdx.x; k < kScanTile; k += kBlock)
+        if (base + k < n) out[size_t(row) * n + base + k] += add;
+}
+
+__global__ void k_scan_totals(const int32_t* in, const int32_t* out, int64_t n, int rows, int32_t* totals) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < rows) totals[r] = (n > 0) ? out[size_t(r) * n + n - 1] + in[size_t(r) * n + n - 1] : 0;
+}
+
+}  // namespace
+
+size_t scan_scratch_bytes(int64_t n, int rows) {
+    size_t total = 0;
+    int64_t m = n;
+    while (m > 0) {
+        const int64_t nb = (m + kScanTile - 1) / kScanTile;
+        total += size_t(nb) * rows * 2 * sizeof(int32_t);
+        if (nb <= 1) break;
+        m = nb;
+    }
+    return total + 256;
+}
+
+void scan_rows(const int32_t* in, int32_t* out, int64_t n, int rows, int32_t* totals, void* scratch, hipStream_t st) {
+    if (n <= 0 || rows <= 0) return;
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    int32_t* bsum = static_cast<int32_t*>(scratch);
+    int32_t* bscan = bsum + size_t(nb) * rows;
+    hipLaunchKernelGGL(k_scan_tiles, dim3(unsigned(nb), unsigned(rows)), dim3(kBlock), 0, st, in, out, n, bsum,
+                       int(nb));
+    if (nb > 1) {
+        scan_rows(bsum, bscan, nb, rows, nullptr, bscan + size_t(nb) * rows, st);
+        hipLaunchKernelGGL(k_scan_add, dim3(unsigned(nb), unsigned(rows)), dim3(kBlock), 0, st, out, n, bscan,
+                           int(nb));
+    }
+    if (totals)
+        hipLaunchKernelGGL(k_scan_totals, dim3(grid_for(rows)), dim3(kBlock), 0, st, in, out, n, rows, totals);
+}
+
+size_t radix_scratch_bytes(int64_t n) {
+    const int64_t nblk = (n + kRsTile - 1) / kRsTile;
+    const size_t hist = size_t(256) * size_t(nblk) * sizeof(int32_t);
+    return 2 * hist + scan_scratch_bytes(256 * nblk, 1) + 256;
+}
+
+int radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp, int64_t n, int nbits,
+                     void* scratch, hipStream_t st) {
+    if (n <= 1 || nbits <= 0) return 0;
+    const int nblk = int((n + kRsTile - 1) / kRsTile);
+    int32_t* hist = static_cast<int32_t*>(scratch);
+    int32_t* offs = hist + size_t(256) * nblk;
+    void* sscr = offs + size_t(256) * nblk;
+    uint64_t *ka = keys, *kb = keys_tmp;
+    uint32_t *va = vals, *vb = vals_tmp;
+    const int passes = (nbits + 7) / 8;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kBlock), 0, st, ka, n, shift,
+                           reinterpret_cast<uint32_t*>(hist), nblk);
+        scan_rows(hist, offs, int64_t(256) * nblk, 1, nullptr, sscr, st);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(kBlock), 0, st, ka, va, kb, vb, n, shift, offs, nblk);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    return (ka == keys) ? 0 : 1;
+}
+
+void launch_concat(int32_t K, const int32_t* const* xy_tab, const int32_t* pt_off, int64_t n, int32_t* xyc,
+                   hipStream_t st) {
+    hipLaunchKernelGGL(k_concat, dim3(grid_for(n)), dim3(kBlock), 0, st, K,
+                       reinterpret_cast<const int2* const*>(xy_tab), pt_off, n, reinterpret_cast<int2*>(xyc));
+}
+
+void launch_bbox_chunks(const int32_t* xy, const Chunk* chunks, int32_t nchunks, int32_t* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_bbox_chunks, dim3(unsigned(nchunks)), dim3(kBlock), 0, st, reinterpret_cast<const int2*>(xy),
+                       chunks, part);
+}
+
+void launch_bbox_final(const int32_t* part, const int32_t* chunk_first, int32_t K, int32_t* bbox, hipStream_t st) {
+    hipLaunchKernelGGL(k_bbox_final, dim3(grid_for(K)), dim3(kBlock), 0, st, part, chunk_first, K, bbox);
+}
+
+void launch_keys(const int32_t* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst, int Dmax, int64_t n,
+                 uint64_t* keys, uint32_t* vals, hipStream_t st) {
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(kBlock), 0, st, reinterpret_cast<const int2*>(xy), pt_off, K,
+                       inst, Dmax, n, keys, vals);
+}
+
+void launch_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int32_t* xy, const InstInfo* inst,
+                          const int32_t* pt_off, int Dmax, int K, int64_t n, int32_t* pts, int32_t* perm_local,
+                          int32_t* pinst, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_sorted, dim3(grid_for(n)), dim3(kBlock), 0, st, keys, vals,
+                       reinterpret_cast<const int2*>(xy), inst, pt_off, Dmax, K, n, reinterpret_cast<int2*>(pts),
+                       perm_local, pinst);
+}
+
+void launch_level_stats(const uint64_t* keys, const Chunk* chunks, int32_t nchunks, const InstInfo* inst, int Dmax,
+                        int nleaf, int8_t* cl, int32_t* hist, int32_t* maxc, hipStream_t st) {
+    hipLaunchKernelGGL(k_level_stats, dim3(unsigned(nchunks)), dim3(kBlock), 0, st, keys, chunks, inst, Dmax, nleaf,
+                       cl, hist, maxc);
+}
+
+void launch_leaf_flags(const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int64_t n, int32_t* flags,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_leaf_flags, dim3(grid_for(n)), dim3(kBlock), 0, st, cl, pinst, inst, n, flags);
+}
+
+void launch_leaf_scatter(const int32_t* flags, const int32_t* scan, const uint64_t* keys, const int8_t* cl,
+                         const int32_t* pinst, const InstInfo* inst, int Dmax, int64_t n, int32_t* leaf_pt0,
+                         uint64_t* leaf_key, int8_t* leaf_cl, int32_t* leaf_inst, hipStream_t st) {
+    hipLaunchKernelGGL(k_leaf_scatter, dim3(grid_for(n)), dim3(kBlock), 0, st, flags, scan, keys, cl, pinst, inst, Dmax,
+                       n, leaf_pt0, leaf_key, leaf_cl, leaf_inst);
+}
+
+void launch_level_flags(const int8_t* leaf_cl, const int32_t* leaf_inst, const InstInfo* inst, int64_t nleaf, int Lmax,
+                        int32_t* flags, hipStream_t st) {
+    if (Lmax <= 0 || nleaf <= 0) return;
+    hipLaunchKernelGGL(k_level_flags, dim3(grid_for(nleaf), unsigned(Lmax)), dim3(kBlock), 0, st, leaf_cl, leaf_inst,
+                       inst, nleaf, flags);
+}
+
+void launch_build_boxes(const int32_t* lscan, const int8_t* leaf_cl, const int32_t* leaf_pt0, const uint64_t* leaf_key,
+                        const int32_t* leaf_inst, const InstInfo* inst, int64_t nleaf, int Lmax, uint64_t* box_key,
+                        int32_t* box_pt0, int32_t* box_parent, int32_t* box_child, int32_t* box_inst,
+                        int8_t* box_lev, hipStream_t st) {
+    hipLaunchKernelGGL(k_build_boxes, dim3(grid_for(nleaf), unsigned(Lmax + 1)), dim3(kBlock), 0, st, lscan, leaf_cl,
+                       leaf_pt0, leaf_key, leaf_inst, inst, nleaf, box_key, box_pt0, box_parent, box_child, box_inst,
+                       box_lev);
+}
+
+void launch_link_boxes(const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_inst,
+                       const int8_t* box_lev, const InstInfo* inst, int64_t nbox, const int32_t* box_pt0,
+                       int32_t* box_child, int32_t* box_pt1, hipStream_t st) {
+    hipLaunchKernelGGL(k_link_boxes, dim3(grid_for(nbox)), dim3(kBlock), 0, st, box_key, box_parent, box_inst, box_lev,
+                       inst, nbox, box_pt0, box_child, box_pt1);
+}
+
+void launch_lists_height(int32_t g0, int32_t g1, const uint64_t* box_key, const int32_t* box_parent,
+                         const int32_t* box_child, const int8_t* box_lev, int32_t* nb9, int32_t* il27,
+                         hipStream_t st) {
+    if (g1 <= g0) return;
+    hipLaunchKernelGGL(k_lists_height, dim3(grid_for(g1 - g0)), dim3(kBlock), 0, st, g0, g1, box_key, box_parent,
+                       box_child, box_lev, nb9, il27);
+}
+
+void launch_class_flags(const uint64_t* box_key, int64_t nbox, int32_t* flags, hipStream_t st) {
+    hipLaunchKernelGGL(k_class_flags, dim3(grid_for(nbox)), dim3(kBlock), 0, st, box_key, nbox, flags);
+}
+
+void launch_class_lists(const BoxGroup* groups, int32_t ngroups, const int32_t* cscan, const int32_t* ctotal,
+                        const uint64_t* box_key, int64_t nbox, int32_t* cls_box, BoxTile* tiles, int32_t* tile_count,
+                        hipStream_t st) {
+    (void)tile_count;
+    if (ngroups <= 0) return;
+    hipLaunchKernelGGL(k_class_boxes, dim3(grid_for(nbox)), dim3(kBlock), 0, st, groups, ngroups, cscan, ctotal,
+                       box_key, nbox, cls_box);
+    hipLaunchKernelGGL(k_class_tiles, dim3(grid_for(ngroups, 64)), dim3(64), 0, st, groups, ngroups, cscan, ctotal,
+                       nbox, tiles);
+}
+
+void launch_point_keys(const int32_t* pts, const int32_t* pinst, const InstInfo* inst, const OpsPtrs* ops, int64_t n,
+                       uint32_t* key, hipStream_t st) {
+    hipLaunchKernelGGL(k_point_keys, dim3(grid_for(n)), dim3(kBlock), 0, st, reinterpret_cast<const int2*>(pts), pinst,
+                       inst, ops, n, key);
+}
+
+}  // namespace lfmm

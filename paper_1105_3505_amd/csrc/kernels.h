@@ -1,4 +1,11 @@
 // Device-side data layouts and kernel launchers of the lattice FMM (gfx950).
+//
+// A plan is a forest: K independent point sets (instances) whose trees live in shared
+// arrays, so that every pass is one launch over all instances.  Points are concatenated in
+// instance order and Morton-sorted inside each instance.  Boxes are numbered by height
+// above their instance's leaf level first (all leaves of all instances form the first
+// block, height 0), then by instance, then by Morton key; so the boxes one launch of M2M or
+// L2L needs (one height, all instances) are one contiguous range.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,7 +16,7 @@ namespace lfmm {
 
 // Skeleton size the kernels are compiled for: every expansion vector holds kRankPad FP64
 // coefficients (the ID rank is capped there; unused slots stay zero).  Three 16-row tiles
-// of the 16x16x4 FP64 matrix instruction.
+// of the 16x16x4 matrix instruction.
 constexpr int kRankPad = 48;
 
 // Interaction offsets: the 27 boxes of a box's interaction list (Definition 6.1) lie at
@@ -17,12 +24,29 @@ constexpr int kRankPad = 48;
 // its parent (c = x bit + 2 y bit).  Offsets index a 7 x 7 grid, d = (dy + 3) * 7 + dx + 3.
 constexpr int kNumIfoSlots = 49;
 constexpr int kNumInteractions = 27;
+constexpr int kMaxLevels = 32;
 
-struct M2LTile {        // up to 16 boxes of one level and one child position
-    int32_t height;     // height above the leaf level (selects the operators)
-    int32_t cls;        // child position c of every box in the tile
-    int32_t start;      // first entry in the class-sorted box array
-    int32_t count;      // 1..16
+struct InstInfo {                   // one instance of a forest
+    int32_t pt0, pt1;               // its Morton-ordered points
+    int32_t ox, oy;                 // lower-left corner of its root box
+    int32_t D, L;                   // root box side 2^D, leaf level L
+    int32_t ops;                    // operator set (leaf side)
+    int32_t leaf_rank0;             // leaves of the instances before it (point order)
+    int32_t lev_base[kMaxLevels];   // first box of level l
+    int32_t lev_count[kMaxLevels];  // boxes of level l
+};
+
+// Tile of up to 16 target boxes that share their operators (same operator set, height and,
+// for M2L and L2L, child position).  Boxes are box_list[start .. start + count) or, when
+// box_list is null, the consecutive boxes start .. start + count - 1.
+struct BoxTile {
+    int32_t ops, height, cls, start, count, pad0, pad1, pad2;
+};
+
+// Group of target boxes for the tiled passes: contiguous box range [g0, g1) of one height
+// and one operator set; class lists for it start at cls_base (4 regions of g1 - g0 slots).
+struct BoxGroup {
+    int32_t ops, height, g0, g1, cls_base, tile_base, tile_cap, pad;
 };
 
 // Per leaf side: operators in device memory (uploaded once, shared by every plan).
@@ -30,8 +54,8 @@ struct DevOps {
     int64_t leaf_side = 0;
     int nlev = 0;                  // heights 0 .. nlev-1
     double* leafT = nullptr;       // [side^2][kRankPad]: T_ofs column of each cell, cell-major
-    double* ofo_cm = nullptr;      // [nlev][4][q child][r parent]  (M2M reads columns)
-    double* ofo_rm = nullptr;      // [nlev][4][r parent][q child]  (L2L reads rows)
+    double* ofo_rm = nullptr;      // [nlev][4][r parent][q child]: T_ofo (M2M operand)
+    double* ofo_cm = nullptr;      // [nlev][4][q child][r parent]: T_ofo^T (L2L operand)
     double* ifo = nullptr;         // [nlev][49][p][q] row-major T_ifo per offset slot
     // mixed precision: T_ifo^d = c_d 1 1^T + R^d with c_d the mean entry; R^d in FP32 hi + lo
     float* ifo_hi = nullptr;
@@ -40,66 +64,106 @@ struct DevOps {
     int32_t* rank = nullptr;       // [nlev] skeleton size of each height
 };
 
-// ---- launchers (all enqueue on `st`) ----------------------------------------------------
-void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
-void launch_bbox(const int32_t* xy, int64_t n, int32_t* out4, hipStream_t st);
-void launch_morton(const int32_t* xy, int64_t n, int32_t ox, int32_t oy, uint64_t* keys,
-                   uint32_t* vals, hipStream_t st);
-// LSD radix sort of (keys, vals) on bits [0, nbits); tmp buffers of the same sizes.  The
-// sorted result ends in (keys, vals).  scratch: radix_scratch_bytes(n) bytes.
+// Device copy of the operator pointers of every operator set a plan uses.
+struct OpsPtrs {
+    const double* leafT;
+    const double* ofo_rm;
+    const double* ofo_cm;
+    const double* ifo;
+    const float* ifo_hi;
+    const float* ifo_lo;
+    const double* mono;
+    const int32_t* rank;
+    int64_t side;
+    int32_t nlev, pad;
+};
+
+// Per-execute load/potential pointers of each instance.
+struct ExecPtrs {
+    const double* f;
+    double* u;
+};
+
+enum BoxMatMode { kModeM2L = 0, kModeM2M = 1, kModeL2L = 2 };
+
+// ---- construction (forest_kernels.hip) ---------------------------------------------------
 size_t radix_scratch_bytes(int64_t n);
-void radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp,
-                      int64_t n, int nbits, void* scratch, hipStream_t st);
+// LSD radix sort of (keys, vals) on bits [0, nbits); returns which pair of buffers holds the
+// result: 0 = (keys, vals), 1 = (keys_tmp, vals_tmp).
+int radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp,
+                     int64_t n, int nbits, void* scratch, hipStream_t st);
 // exclusive scan of `rows` rows of n int32 each (row stride n); totals[rows] if non-null.
 size_t scan_scratch_bytes(int64_t n, int rows);
 void scan_rows(const int32_t* in, int32_t* out, int64_t n, int rows, int32_t* totals,
                void* scratch, hipStream_t st);
-void launch_gather_points(const int32_t* xy, const uint32_t* perm, int64_t n, int32_t ox,
-                          int32_t oy, int32_t* pts, int32_t* perm_out, hipStream_t st);
-void launch_level_stats(const uint64_t* keys, int64_t n, int D, int nleaf, int8_t* cl,
-                        int32_t* hist /*[D+2]*/, int32_t* maxc, hipStream_t st);
-void launch_leaf_flags(const int8_t* cl, int64_t n, int L, int32_t* flags, hipStream_t st);
-void launch_leaf_scatter(const int32_t* flags, const int32_t* scan, const uint64_t* keys,
-                         const int8_t* cl, int64_t n, int D, int L, int32_t* leaf_pt0,
-                         uint64_t* leaf_key, int8_t* leaf_cl, hipStream_t st);
-void launch_level_flags(const int8_t* leaf_cl, int64_t nleaf, int L, int32_t* flags,
-                        hipStream_t st);
-void launch_build_boxes(const int32_t* lvl_scan, const int8_t* leaf_cl, const int32_t* leaf_pt0,
-                        const uint64_t* leaf_key, int64_t nleaf, int L, const int32_t* level_off,
-                        int64_t npts, uint64_t* box_key, int32_t* box_pt0, int32_t* box_pt1,
-                        int32_t* box_parent, int32_t* box_child, hipStream_t st);
-void launch_box_ends(const int32_t* level_off_host, int L, int64_t npts, const int32_t* box_pt0,
-                     int32_t* box_pt1, hipStream_t st);
-void launch_lists(const uint64_t* box_key, const int32_t* level_off_host, int L,
-                  int32_t* ilist, int32_t* nlist, int32_t* cls_cnt, int32_t* cls_box,
-                  hipStream_t st);
-void launch_m2l_tiles(const int32_t* cls_cnt, const int32_t* level_off_host, int L,
-                      M2LTile* tiles, int32_t* ntiles, hipStream_t st);
 
-// ---- evaluation passes --------------------------------------------------------------------
-void launch_gather_f(const double* f, const int32_t* perm, int64_t n, double* fs, hipStream_t st);
-void launch_p2m_dense(int64_t nleaves, int32_t leaf_off, const int32_t* box_pt0,
-                      const int32_t* box_pt1, const uint64_t* box_key, int L, int64_t side,
-                      const int32_t* pts, const double* fs, const double* leafT, double* Q,
-                      hipStream_t st);
-void launch_m2m(int32_t box_begin, int32_t box_end, int height, const int32_t* box_child,
-                const double* ofo_cm, const double* Q_in, double* Q_out, hipStream_t st);
-void launch_l2l(int32_t box_begin, int32_t box_end, int height_parent, const int32_t* box_parent,
-                const uint64_t* box_key, const double* ofo_rm, double* U, hipStream_t st);
-void launch_m2l(const M2LTile* tiles, const int32_t* ntiles, int32_t max_tiles,
-                const int32_t* cls_box, const int32_t* ilist, int32_t ilist_off, const double* Q,
-                double* U, const double* ifo, bool simple, hipStream_t st);
-// window keys 8 (y (4 side - 1) + x) mod 2^32 of the Morton-ordered points
-void launch_point_keys(const int32_t* pts, int64_t n, int64_t side, uint32_t* key, hipStream_t st);
-void launch_m2l_mixed(const M2LTile* tiles, const int32_t* ntiles, int32_t max_tiles, const int32_t* cls_box,
-                      const int32_t* ilist, int32_t ilist_off, const double* Q, double* U, const float* ifo_hi,
-                      const float* ifo_lo, const double* mono, const int32_t* rank, hipStream_t st);
-void launch_leaf_eval(int64_t nleaves, int32_t leaf_off, const int32_t* box_pt0,
-                      const int32_t* box_pt1, const uint64_t* box_key, const int32_t* nlist,
-                      int L, int64_t side, const int32_t* pts, const uint32_t* pkey, const double* fs,
-                      const int32_t* perm, const double* U, const double* leafT, bool far,
-                      const double* phi_oct, double* u, bool simple, hipStream_t st);
+struct Chunk { int32_t inst, begin, end, pad; };   // <= kChunk points of one instance
+constexpr int32_t kChunk = 8192;
+
+void launch_concat(int32_t K, const int32_t* const* xy_tab, const int32_t* pt_off, int64_t n,
+                   int32_t* xyc, hipStream_t st);
+void launch_bbox_chunks(const int32_t* xy, const Chunk* chunks, int32_t nchunks, int32_t* part,
+                        hipStream_t st);
+void launch_bbox_final(const int32_t* part, const int32_t* chunk_first, int32_t K, int32_t* bbox,
+                       hipStream_t st);
+void launch_keys(const int32_t* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst,
+                 int Dmax, int64_t n, uint64_t* keys, uint32_t* vals, hipStream_t st);
+void launch_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int32_t* xy,
+                          const InstInfo* inst, const int32_t* pt_off, int Dmax, int K, int64_t n,
+                          int32_t* pts, int32_t* perm_local, int32_t* pinst, hipStream_t st);
+void launch_level_stats(const uint64_t* keys, const Chunk* chunks, int32_t nchunks,
+                        const InstInfo* inst, int Dmax, int nleaf, int8_t* cl, int32_t* hist,
+                        int32_t* maxc, hipStream_t st);
+void launch_leaf_flags(const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int64_t n,
+                       int32_t* flags, hipStream_t st);
+void launch_leaf_scatter(const int32_t* flags, const int32_t* scan, const uint64_t* keys,
+                         const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int Dmax,
+                         int64_t n, int32_t* leaf_pt0, uint64_t* leaf_key, int8_t* leaf_cl,
+                         int32_t* leaf_inst, hipStream_t st);
+void launch_level_flags(const int8_t* leaf_cl, const int32_t* leaf_inst, const InstInfo* inst,
+                        int64_t nleaf, int Lmax, int32_t* flags, hipStream_t st);
+void launch_build_boxes(const int32_t* lscan, const int8_t* leaf_cl, const int32_t* leaf_pt0,
+                        const uint64_t* leaf_key, const int32_t* leaf_inst, const InstInfo* inst,
+                        int64_t nleaf, int Lmax, uint64_t* box_key, int32_t* box_pt0,
+                        int32_t* box_parent, int32_t* box_child, int32_t* box_inst,
+                        int8_t* box_lev, hipStream_t st);
+void launch_link_boxes(const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_inst,
+                       const int8_t* box_lev, const InstInfo* inst, int64_t nbox,
+                       const int32_t* box_pt0, int32_t* box_child, int32_t* box_pt1,
+                       hipStream_t st);
+// neighbour (9 slots, every box) and interaction (27 slots, boxes of level >= 2) lists of the
+// boxes [g0, g1) of one height, from their parents' neighbour lists
+void launch_lists_height(int32_t g0, int32_t g1, const uint64_t* box_key, const int32_t* box_parent,
+                         const int32_t* box_child, const int8_t* box_lev, int32_t* nb9,
+                         int32_t* il27, hipStream_t st);
+void launch_class_flags(const uint64_t* box_key, int64_t nbox, int32_t* flags, hipStream_t st);
+void launch_class_lists(const BoxGroup* groups, int32_t ngroups, const int32_t* cscan,
+                        const int32_t* ctotal, const uint64_t* box_key, int64_t nbox,
+                        int32_t* cls_box, BoxTile* tiles, int32_t* tile_count, hipStream_t st);
+void launch_point_keys(const int32_t* pts, const int32_t* pinst, const InstInfo* inst,
+                       const OpsPtrs* ops, int64_t n, uint32_t* key, hipStream_t st);
+
+// ---- evaluation passes (fmm_kernels.hip) ---------------------------------------------------
+void launch_gather_f(const ExecPtrs* tab, const double* f_single, const int32_t* perm_local,
+                     const int32_t* pinst, int64_t n, double* fs, hipStream_t st);
+void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1,
+                const uint64_t* box_key, int64_t side, const int32_t* pts, const double* fs,
+                const double* leafT, double* Q, hipStream_t st);
+void launch_boxmat(int mode, const BoxTile* tiles, int32_t tile0, const int32_t* ntiles_dev,
+                   int32_t ntiles_host, int32_t max_tiles, const int32_t* box_list,
+                   const int32_t* src, const OpsPtrs* ops, const double* in, double* out,
+                   hipStream_t st);
+void launch_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t max_tiles,
+                      const int32_t* box_list, const int32_t* il27, const OpsPtrs* ops,
+                      const double* Q, double* U, hipStream_t st);
+void launch_leaf(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1,
+                 const uint64_t* box_key, const int32_t* box_inst, const int32_t* nb9,
+                 int64_t side, const int32_t* pts, const uint32_t* pkey, const double* fs,
+                 const int32_t* perm_local, const int32_t* pinst, const InstInfo* inst,
+                 const ExecPtrs* tab, double* u_single, const double* U, const double* leafT,
+                 const uint8_t* far_inst, const double* phi_oct, hipStream_t st);
 void launch_direct(int64_t nt, const int32_t* txy, int64_t ns, const int32_t* sxy,
                    const double* f, const double* phi_oct, double* u, hipStream_t st);
+hipError_t upload_dslots();
 
 }  // namespace lfmm

@@ -181,20 +181,6 @@ def test_large_uniform_sampled(torch_mod, ctx):
     assert err <= FMM_TOL
 
 
-def test_first_generation_kernels_agree(torch_mod):
-    # LFMM_FLAG_SIMPLE_KERNELS selects the one-wave-per-tile M2L and lanes-as-targets near
-    # field; both forms must meet the same bar
-    import paper_1105_3505_amd as lf
-    ctx = lf.Context(0, flags=1)
-    for seed, n, side in [(41, 1000, 256), (42, 20000, 560)]:
-        rng = np.random.default_rng(seed)
-        xy = wl.uniform_box(rng, n, side)
-        f = wl.zero_sum_loads(rng.standard_normal(n))
-        u, _ = _fmm(torch_mod, ctx, xy, f)
-        assert _rel(u, od.direct_sum(xy, xy, f)) <= FMM_TOL
-    ctx.close()
-
-
 @pytest.mark.parametrize("max_leaf", [8, 16, 32, 128, 256])
 def test_leaf_sizes(torch_mod, max_leaf):
     # leaf sides from 2 to 64: window table, quadrant table and global-table near fields

@@ -74,31 +74,37 @@ def test_tree_matches_brute_force(setup, case):
     assert np.array_equal(pts, (xy[perm] - lo).astype(np.int32))
     keys = _morton(pts[:, 0], pts[:, 1])
     assert np.all(keys[1:] >= keys[:-1])
-    off = ex["level_offsets"]
-    assert len(off) == L + 2 and off[0] == 0
+    base, count = ex["level_base"], ex["level_count"]
+    assert len(base) == L + 1 and len(count) == L + 1
+    # boxes are numbered by height above the leaves: leaves first, the root last
+    assert base[L] == 0 and base[0] == info["n_boxes"] - 1 and count[0] == 1
+    off = {lev: (int(base[lev]), int(base[lev] + count[lev])) for lev in range(L + 1)}
+    assert np.array_equal(ex["box_level"][off[L][0]:off[L][1]], np.full(count[L], L, np.int8))
     bkey, b0, b1 = ex["box_key"], ex["box_begin"], ex["box_end"]
     for lev in range(L + 1):
         pk = keys >> np.uint64(2 * (D - lev))
         uk, first = np.unique(pk, return_index=True)
-        sl = slice(off[lev], off[lev + 1])
+        sl = slice(*off[lev])
         assert np.array_equal(bkey[sl], uk), lev
         assert np.array_equal(b0[sl], first), lev
         assert np.array_equal(b1[sl], np.append(first[1:], len(pts))), lev
     # leaf occupancy rule of Section 6
-    leaves = slice(off[L], off[L + 1])
+    leaves = slice(*off[L])
     assert np.max(b1[leaves] - b0[leaves]) <= 64 or L == D
-    index = [{int(k): off[lev] + i for i, k in enumerate(bkey[off[lev]:off[lev + 1]])} for lev in range(L + 1)]
+    index = [{int(k): off[lev][0] + i for i, k in enumerate(bkey[slice(*off[lev])])} for lev in range(L + 1)]
     par, ch = ex["box_parent"], ex["box_child"]
     for lev in range(L + 1):
-        for g in range(off[lev], off[lev + 1]):
+        for g in range(*off[lev]):
             k = int(bkey[g])
             assert par[g] == (index[lev - 1][k >> 2] if lev else -1)
             for c in range(4):
                 want = index[lev + 1].get(4 * k + c, -1) if lev < L else -1
                 assert ch[g, c] == want
     il = ex["interaction"]
+    for lev in range(2):
+        assert np.all(il[slice(*off[lev])] == -1)
     for lev in range(2, L + 1):
-        for g in range(off[lev], off[lev + 1]):
+        for g in range(*off[lev]):
             k = int(bkey[g])
             bx = int(_compact(k))
             by = int(_compact(k >> 1))
@@ -108,10 +114,10 @@ def test_tree_matches_brute_force(setup, case):
                 want = -1
                 if 0 <= x < 2 ** lev and 0 <= y < 2 ** lev:
                     want = index[lev].get(int(_morton(np.array([x]), np.array([y]))[0]), -1)
-                assert il[g - off[2], s] == want
+                assert il[g, s] == want
     nl = ex["neighbor"]
-    if L >= 2:
-        for g in range(off[L], off[L + 1]):
+    for lev in range(L + 1):
+        for g in range(*off[lev]):
             k = int(bkey[g])
             bx, by = int(_compact(k)), int(_compact(k >> 1))
             q = 0
@@ -119,9 +125,9 @@ def test_tree_matches_brute_force(setup, case):
                 for dx in (-1, 0, 1):
                     x, y = bx + dx, by + dy
                     want = -1
-                    if 0 <= x < 2 ** L and 0 <= y < 2 ** L:
-                        want = index[L].get(int(_morton(np.array([x]), np.array([y]))[0]), -1)
-                    assert nl[g - off[L], q] == want
+                    if 0 <= x < 2 ** lev and 0 <= y < 2 ** lev:
+                        want = index[lev].get(int(_morton(np.array([x]), np.array([y]))[0]), -1)
+                    assert nl[g, q] == want
                     q += 1
 
 
@@ -142,14 +148,16 @@ def test_passes_match_host_products(setup, case):
     assert L >= 2
     ops = lf.HostOperators(side, L - 1)
     ranks = [ops.level(h)[1] for h in range(L - 1)]
-    off, bkey, b0, b1 = ex["level_offsets"], ex["box_key"], ex["box_begin"], ex["box_end"]
+    base, count = ex["level_base"], ex["level_count"]
+    off = {lev: (int(base[lev]), int(base[lev] + count[lev])) for lev in range(L + 1)}
+    bkey, b0, b1 = ex["box_key"], ex["box_begin"], ex["box_end"]
     pts, fs, Q, U = ex["points"], ex["loads"], ex["qhat"], ex["uhat"]
     perm = ex["perm"]
     assert np.array_equal(fs, f[perm])
     # padded slots stay zero
     for lev in range(2, L + 1):
         r = ranks[L - lev]
-        assert not np.any(Q[off[lev]:off[lev + 1], r:]) and not np.any(U[off[lev]:off[lev + 1], r:])
+        assert not np.any(Q[slice(*off[lev]), r:]) and not np.any(U[slice(*off[lev]), r:])
 
     def close(a, b, what):
         scale = max(np.max(np.abs(b)), 1e-300)
@@ -159,24 +167,24 @@ def test_passes_match_host_products(setup, case):
     # P2M
     T = ops.leaf()
     r0 = ranks[0]
-    ref = np.zeros((off[L + 1] - off[L], r0))
-    for i, g in enumerate(range(off[L], off[L + 1])):
+    ref = np.zeros((count[L], r0))
+    for i, g in enumerate(range(*off[L])):
         k = int(bkey[g])
         cx, cy = _compact(k) * side, _compact(k >> 1) * side
         p = pts[b0[g]:b1[g]]
         loc = (p[:, 0] - cx) + side * (p[:, 1] - cy)
         ref[i] = T[:, loc] @ fs[b0[g]:b1[g]]
-    close(Q[off[L]:off[L + 1], :r0], ref, "P2M")
+    close(Q[slice(*off[L]), :r0], ref, "P2M")
     # M2M
     ch = ex["box_child"]
     for lev in range(L - 1, 1, -1):
         h = L - lev
-        ref = np.zeros((off[lev + 1] - off[lev], ranks[h]))
-        for i, g in enumerate(range(off[lev], off[lev + 1])):
+        ref = np.zeros((count[lev], ranks[h]))
+        for i, g in enumerate(range(*off[lev])):
             for c in range(4):
                 if ch[g, c] >= 0:
                     ref[i] += ops.ofo(h, c) @ Q[ch[g, c], :ranks[h - 1]]
-        close(Q[off[lev]:off[lev + 1], :ranks[h]], ref, "M2M level %d" % lev)
+        close(Q[slice(*off[lev]), :ranks[h]], ref, "M2M level %d" % lev)
     # M2L (+ L2L below level 2)
     il, par = ex["interaction"], ex["box_parent"]
     for lev in range(2, L + 1):
@@ -184,12 +192,12 @@ def test_passes_match_host_products(setup, case):
         sk = ops.skeleton(h)
         s_h = side << h
         Tcache = {}
-        ref = np.zeros((off[lev + 1] - off[lev], ranks[h]))
-        for i, g in enumerate(range(off[lev], off[lev + 1])):
+        ref = np.zeros((count[lev], ranks[h]))
+        for i, g in enumerate(range(*off[lev])):
             k = int(bkey[g])
             c = (_compact(k) & 1) + 2 * (_compact(k >> 1) & 1)
             for s, d in enumerate(_slots(c)):
-                src = il[g - off[2], s]
+                src = il[g, s]
                 if src < 0:
                     continue
                 if d not in Tcache:
@@ -198,4 +206,4 @@ def test_passes_match_host_products(setup, case):
                 ref[i] += Tcache[d] @ Q[src, :ranks[h]]
             if lev >= 3:
                 ref[i] += ops.ofo(h + 1, int(k & 3)).T @ U[par[g], :ranks[h + 1]]
-        close(U[off[lev]:off[lev + 1], :ranks[h]], ref, "M2L+L2L level %d" % lev)
+        close(U[slice(*off[lev]), :ranks[h]], ref, "M2L+L2L level %d" % lev)

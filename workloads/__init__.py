@@ -12,6 +12,7 @@ from .generators import (  # noqa: F401
     config_large_uniform,
     config_clusters,
     config_batched,
+    config_batched_instance,
     config_serving_request,
     sample_targets,
 )

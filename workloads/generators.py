@@ -121,17 +121,19 @@ def batched_sizes(seed: int = 4, n_inst: int = 512, lo: float = 1e3, hi: float =
     return np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), size=n_inst))).astype(np.int64)
 
 
+def config_batched_instance(seed: int, i: int, n_inst: int = 512, lo: float = 1e3, hi: float = 1e5):
+    """Instance i of config_batched: uniform in a box of side ceil(4 sqrt N), zero-sum loads."""
+    n = int(batched_sizes(seed, n_inst, lo, hi)[i])
+    rng = np.random.default_rng([seed, i])
+    side = int(math.ceil(4.0 * math.sqrt(n)))
+    xy = uniform_box(rng, n, side)
+    f = zero_sum_loads(rng.standard_normal(n))
+    return xy, f
+
+
 def config_batched(seed: int = 4, n_inst: int = 512, lo: float = 1e3, hi: float = 1e5):
     """Independent uniform instances with log-uniform sizes, each in a box of side ceil(4 sqrt N)."""
-    sizes = batched_sizes(seed, n_inst, lo, hi)
-    out = []
-    for i, n in enumerate(sizes):
-        rng = np.random.default_rng([seed, i])
-        side = int(math.ceil(4.0 * math.sqrt(int(n))))
-        xy = uniform_box(rng, int(n), side)
-        f = zero_sum_loads(rng.standard_normal(int(n)))
-        out.append((xy, f))
-    return out
+    return [config_batched_instance(seed, i, n_inst, lo, hi) for i in range(n_inst)]
 
 
 def config_serving_request(seed: int, index: int, lo: float = 1e2, hi: float = 1e6):

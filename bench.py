@@ -1,15 +1,23 @@
 """Benchmark of the lattice FMM hot path on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large_uniform|small_uniform]
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+                [--workload large_uniform|small_uniform|clusters|batched|serving]
+                [--precision fp64|mixed]
 
 A step is one whole solve of the hot path on one batch of synthetic input already resident
 in HBM: tree construction (Morton keys, radix sort, levels, lists) plus the evaluation
 passes (P2M, M2M, M2L, L2L, L2P and near field), from device xy and f to device u.  W
 untimed steps, then K timed steps bracketed by device synchronisation.  Prints one JSON line.
 
-The default workload is 1,000,000 distinct sources uniform in a 4096 x 4096 box with N(0,1)
-loads made exactly zero-sum, targets = sources, FP64.  The accuracy of the timed result is
-measured against the FP64 oracle on 1,000 sampled targets, which is also the CPU baseline.
+Workloads (all seeded, synthetic):
+  large_uniform (default)  1,000,000 distinct sources uniform in a 4096 x 4096 box, FP64
+  small_uniform            1,000 sources uniform in a 256 x 256 box
+  clusters                 2,000,000 sources in 64 Gaussian clusters in a 2^20 x 2^20 region
+  batched                  512 independent instances (log-uniform sizes 1e3..1e5) per step
+  serving                  Poisson stream of requests (sizes log-uniform 1e2..1e6) through
+                           the continuous-batching server; reports p50/p99 latency
+The accuracy of the timed result is measured against the FP64 oracle on sampled targets; the
+oracle's time on that sample is the CPU baseline.
 """
 from __future__ import annotations
 
@@ -17,6 +25,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -28,6 +37,7 @@ METRIC = "Msources/s at rel.err ≤1e-10 (FP64) vs ≤1e-7 (mixed); p50/p99 solv
 
 # MI355X published peaks
 PEAK_FP64_TFLOPS = 78.6       # FP64 vector and FP64 matrix (MFMA) alike
+PEAK_FP32_TFLOPS = 157.3      # FP32 matrix (MFMA)
 PEAK_HBM_GBS = 8000.0
 RANK = 48                     # skeleton size the kernels are compiled for
 
@@ -36,14 +46,277 @@ WORKLOADS = {
                       "mean-subtracted to an exact zero sum, targets = sources"),
     "small_uniform": ("1,000 distinct sources uniform in a 256x256 box of Z^2, N(0,1) loads "
                       "mean-subtracted to an exact zero sum, targets = sources"),
+    "clusters": ("2,000,000 distinct sources in 64 Gaussian clusters (sigma 2,000) in a 2^20 x 2^20 "
+                 "region of Z^2, U(-1,1) loads mean-subtracted, targets = sources"),
+    "batched": ("512 independent instances, sizes log-uniform in [1e3, 1e5], each uniform in a box of "
+                "side ceil(4 sqrt N), N(0,1) loads mean-subtracted per instance, one forest plan per step"),
+    "serving": ("Poisson arrivals of solve requests, sizes log-uniform in [1e2, 1e6], uniform or "
+                "8-cluster layout per request, through the continuous-batching server"),
 }
+TOLERANCE = {"fp64": 1e-10, "mixed": 1e-7}
+
+
+def roofline(phases: dict, info: dict, n: int, precision: str) -> dict:
+    """Roofline entry for the phase that takes the longest (HIP events on the execute stream)."""
+    dom = max(phases, key=phases.get)
+    sec = phases[dom] * 1e-3
+    if dom == "m2l":
+        flops = 2.0 * RANK * RANK * info["m2l_pairs"]
+        achieved = flops / sec / 1e12
+        peak = PEAK_FP64_TFLOPS if precision == "fp64" else PEAK_FP32_TFLOPS
+        return {"kernel": "k_boxmat M2L (FP64 MFMA)" if precision == "fp64" else "k_m2l_mixed (FP32 MFMA)",
+                "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None, "work_per_launch": flops,
+                "work_definition": "2 P^2 flops per interaction-list pair, P = 48"}
+    if dom == "leaf":
+        flops = 2.0 * info["near_pairs"] + 2.0 * RANK * n
+        achieved = flops / sec / 1e12
+        return {"kernel": "k_leaf (near field + L2P)", "bound": "alu", "achieved": achieved,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": None, "work_per_launch": flops,
+                "work_definition": "one FP64 FMA per near pair plus 2P flops of L2P per target",
+                "pairs_per_s": info["near_pairs"] / sec}
+    return {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": None, "traffic": None}
+
+
+def base_result(args, value, ms_per_step, config, dtype="f64"):
+    return {
+        "metric": METRIC, "value": value, "unit": "Msources/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config,
+    }
+
+
+def cpu_baseline(xy, f, u, n_targets, seed=20):
+    """Oracle direct sum on sampled targets: accuracy of u and the CPU rate."""
+    import workloads as wl
+    from oracle import direct as od
+    idx = wl.sample_targets(seed, len(xy), n_targets)
+    t0 = time.perf_counter()
+    ref = od.direct_sum(xy[idx], xy, f)
+    cpu_s = time.perf_counter() - t0
+    err = float(np.linalg.norm(u[idx] - ref) / np.linalg.norm(ref))
+    base = {"value": len(idx) / cpu_s / 1e6, "unit": "Msources/s", "cores": od.threads(), "kind": "oracle",
+            "sample": "%d sampled targets x %d sources (direct sum), %.2f s wall; the rate is targets "
+                      "completed per second" % (len(idx), len(xy), cpu_s)}
+    return err, len(idx), base
 
 
 def make_input(name):
     import workloads as wl
-    if name == "large_uniform":
-        return wl.config_large_uniform()
-    return wl.config_small_uniform()
+    return {"large_uniform": wl.config_large_uniform, "small_uniform": wl.config_small_uniform,
+            "clusters": wl.config_clusters}[name]()
+
+
+def run_single(args, torch, lf):
+    xy, f = make_input(args.workload)
+    n = len(xy)
+    dev = torch.device("cuda:0")
+    xy_d = torch.from_numpy(xy).to(dev)
+    f_d = torch.from_numpy(f).to(dev)
+    u_d = torch.empty(n, dtype=torch.float64, device=dev)
+    ctx = lf.Context(0, precision=args.precision, max_leaf=args.max_leaf)
+    stream = torch.cuda.current_stream()
+
+    def step(timed=False):
+        plan = ctx.plan(xy_d, stream=stream)
+        if timed:
+            plan.set_timing(True)
+        plan.execute(f_d, u_d, stream=stream)
+        return plan
+
+    for _ in range(max(args.warmup, 1)):
+        step().close()
+    torch.cuda.synchronize()
+    lat, phases, info = [], [], None
+    t_all = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        plan = step(timed=True)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+        phases.append(plan.phase_times())
+        if info is None:
+            info = plan.info()
+        plan.close()
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t_all) * 1e3 / args.steps
+    value = n / (ms_per_step * 1e-3) / 1e6
+
+    # execute-only throughput on a resident plan
+    plan = ctx.plan(xy_d, stream=stream)
+    for _ in range(3):
+        plan.execute(f_d, u_d, stream=stream)
+    torch.cuda.synchronize()
+    reps = max(args.steps, 10)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.execute(f_d, u_d, stream=stream)
+    torch.cuda.synchronize()
+    exec_ms = (time.perf_counter() - t0) * 1e3 / reps
+    u = u_d.cpu().numpy()
+    plan.close()
+    ctx.close()
+
+    avg = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
+    config = {"workload": WORKLOADS[args.workload], "n_sources": n, "precision": args.precision,
+              "leaf_level": info["leaf_level"], "leaf_side": info["leaf_side"], "max_leaf": args.max_leaf,
+              "rank": RANK, "eps": 1e-12}
+    result = base_result(args, value, ms_per_step, config)
+    result.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                   "execute_only_ms": exec_ms, "execute_only_msources_per_s": n / (exec_ms * 1e-3) / 1e6,
+                   "phase_ms": avg, "plan": info, "roofline": roofline(avg, info, n, args.precision)})
+    if not args.no_cpu_baseline:
+        err, k, base = cpu_baseline(xy, f, u, args.cpu_targets)
+        result["rel_err_vs_oracle"] = err
+        result["rel_err_sample"] = k
+        result["tolerance"] = TOLERANCE[args.precision]
+        result["cpu_baseline"] = base
+    return result
+
+
+def run_batched(args, torch, lf):
+    import workloads as wl
+    inst = wl.config_batched()
+    n = sum(len(a) for a, _ in inst)
+    xs = [torch.from_numpy(a).cuda() for a, _ in inst]
+    fs = [torch.from_numpy(b).cuda() for _, b in inst]
+    us = [torch.empty_like(b) for b in fs]
+    ctx = lf.Context(0, precision=args.precision, max_leaf=args.max_leaf)
+    stream = torch.cuda.current_stream()
+
+    def step(timed=False):
+        plan = ctx.plan_batch(xs, stream=stream)
+        if timed:
+            plan.set_timing(True)
+        plan.execute_instances(fs, us, stream=stream)
+        return plan
+
+    for _ in range(max(args.warmup, 1)):
+        step().close()
+    torch.cuda.synchronize()
+    lat, phases, info = [], [], None
+    t_all = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        plan = step(timed=True)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+        phases.append(plan.phase_times())
+        if info is None:
+            info = plan.info()
+        plan.close()
+    ms_per_step = (time.perf_counter() - t_all) * 1e3 / args.steps
+    plan = ctx.plan_batch(xs, stream=stream)
+    plan.execute_instances(fs, us, stream=stream)
+    torch.cuda.synchronize()
+    reps = max(args.steps, 5)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.execute_instances(fs, us, stream=stream)
+    torch.cuda.synchronize()
+    exec_ms = (time.perf_counter() - t0) * 1e3 / reps
+    plan.close()
+    ctx.close()
+    avg = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
+    config = {"workload": WORKLOADS["batched"], "n_instances": len(inst), "n_sources": n,
+              "precision": args.precision, "max_leaf": args.max_leaf, "rank": RANK, "eps": 1e-12}
+    result = base_result(args, n / (ms_per_step * 1e-3) / 1e6, ms_per_step, config)
+    result.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                   "execute_only_ms": exec_ms, "execute_only_msources_per_s": n / (exec_ms * 1e-3) / 1e6,
+                   "phase_ms": avg, "plan": info, "roofline": roofline(avg, info, n, args.precision)})
+    if not args.no_cpu_baseline:
+        # accuracy on 100 sampled targets of every 8th instance; CPU rate over that sample
+        from oracle import direct as od
+        num = den = 0.0
+        t0 = time.perf_counter()
+        k = 0
+        for i in range(0, len(inst), 8):
+            xy, f = inst[i]
+            idx = wl.sample_targets(1000 + i, len(xy), 100)
+            ref = od.direct_sum(xy[idx], xy, f)
+            u = us[i].cpu().numpy()[idx]
+            num += float(np.sum((u - ref) ** 2))
+            den += float(np.sum(ref ** 2))
+            k += len(idx)
+        cpu_s = time.perf_counter() - t0
+        result["rel_err_vs_oracle"] = (num / den) ** 0.5
+        result["rel_err_sample"] = k
+        result["tolerance"] = TOLERANCE[args.precision]
+        result["cpu_baseline"] = {"value": k / cpu_s / 1e6, "unit": "Msources/s", "cores": od.threads(),
+                                  "kind": "oracle",
+                                  "sample": "100 sampled targets of every 8th instance (%d targets), %.2f s "
+                                            "wall; the rate is targets completed per second" % (k, cpu_s)}
+    return result
+
+
+def run_serving(args, torch, lf):
+    import workloads as wl
+    m = args.requests
+    reqs = [wl.config_serving_request(5, i) for i in range(m)]
+    n_total = sum(len(r[0]) for r in reqs)
+    dev = [(torch.from_numpy(xy).cuda(), torch.from_numpy(f).cuda()) for xy, f, _ in reqs]
+    us = [torch.empty_like(f) for _, f in dev]
+    rng = np.random.default_rng(6)
+    gaps = rng.exponential(1.0 / args.rate, size=m)
+    ctx = lf.Context(0, precision=args.precision, max_leaf=args.max_leaf)
+    srv = lf.Server(ctx, max_batch=args.max_batch, max_inflight=3)
+
+    def run_stream(timed):
+        tickets = [None] * m
+        t_start = time.perf_counter()
+
+        def client():
+            t = t_start
+            for i in range(m):
+                t += gaps[i]
+                d = t - time.perf_counter()
+                if d > 0 and timed:
+                    time.sleep(d)
+                tickets[i] = srv.submit(dev[i][0], dev[i][1], us[i])
+
+        th = threading.Thread(target=client)
+        th.start()
+        th.join()
+        stats = [srv.wait(t)[1] for t in tickets]
+        return stats, time.perf_counter() - t_start
+
+    run_stream(False)            # warm-up: operators of every leaf side, memory pool
+    stats, makespan = run_stream(True)
+    srv.close()
+    ctx.close()
+    lat = np.array([(s["t_done"] - s["t_submit"]) * 1e3 for s in stats])
+    batches = len({s["batch_id"] for s in stats})
+    config = {"workload": WORKLOADS["serving"], "requests": m, "rate_per_s": args.rate,
+              "n_sources_total": n_total, "precision": args.precision, "max_batch": args.max_batch,
+              "max_inflight": 3}
+    result = base_result(args, n_total / makespan / 1e6, makespan * 1e3 / m, config)
+    result.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                   "mean_batch": m / batches, "iterations": batches, "makespan_s": makespan,
+                   "offered_msources_per_s": n_total / float(np.sum(gaps)) / 1e6})
+    if not args.no_cpu_baseline:
+        from oracle import direct as od
+        num = den = 0.0
+        k = 0
+        t0 = time.perf_counter()
+        for i in range(0, m, max(1, m // 20)):
+            xy, f, _ = reqs[i]
+            idx = wl.sample_targets(3000 + i, len(xy), 100)
+            ref = od.direct_sum(xy[idx], xy, f)
+            u = us[i].cpu().numpy()[idx]
+            num += float(np.sum((u - ref) ** 2))
+            den += float(np.sum(ref ** 2))
+            k += len(idx)
+        cpu_s = time.perf_counter() - t0
+        result["rel_err_vs_oracle"] = (num / den) ** 0.5
+        result["rel_err_sample"] = k
+        result["tolerance"] = TOLERANCE[args.precision]
+        result["cpu_baseline"] = {"value": k / cpu_s / 1e6, "unit": "Msources/s", "cores": od.threads(),
+                                  "kind": "oracle",
+                                  "sample": "100 sampled targets of 20 requests (%d targets), %.2f s wall; "
+                                            "the rate is targets completed per second" % (k, cpu_s)}
+    return result
 
 
 def main() -> None:
@@ -52,8 +325,16 @@ def main() -> None:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large_uniform", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-targets", type=int, default=1000)
+    ap.add_argument("--precision", default="fp64", choices=sorted(TOLERANCE))
+    ap.add_argument("--max-leaf", type=int, default=64)
+    ap.add_argument("--cpu-targets", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=200, help="serving: requests in the stream")
+    ap.add_argument("--rate", type=float, default=1000.0, help="serving: arrivals per second")
+    ap.add_argument("--max-batch", type=int, default=64, help="serving: requests per iteration")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first fill and copy a buffer of this many MiB (a known-traffic reference for "
+                         "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -63,117 +344,19 @@ def main() -> None:
     import torch
     import paper_1105_3505_amd as lf
 
-    xy, f = make_input(args.workload)
-    n = len(xy)
-    dev = torch.device("cuda:0")
-    xy_d = torch.from_numpy(xy).to(dev)
-    f_d = torch.from_numpy(f).to(dev)
-    u_d = torch.empty(n, dtype=torch.float64, device=dev)
-    ctx = lf.Context(0)
-    stream = torch.cuda.current_stream()
-
-    def step(timed_phases=None):
-        plan = ctx.plan(xy_d, stream=stream)
-        if timed_phases is not None:
-            plan.set_timing(True)
-        plan.execute(f_d, u_d, stream=stream)
-        return plan
-
-    for _ in range(max(args.warmup, 1)):
-        step().close()
-    torch.cuda.synchronize()
-
-    lat, phases, info = [], [], None
-    torch.cuda.synchronize()
-    t_all = time.perf_counter()
-    for _ in range(args.steps):
-        t0 = time.perf_counter()
-        plan = step(timed_phases=True)
+    if args.copy_probe_mib:
+        a = torch.empty(args.copy_probe_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        a.fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
         torch.cuda.synchronize()
-        lat.append((time.perf_counter() - t0) * 1e3)
-        phases.append(plan.phase_times())
-        if info is None:
-            info = plan.info()
-        plan.close()
-    torch.cuda.synchronize()
-    total_s = time.perf_counter() - t_all
-    ms_per_step = total_s * 1e3 / args.steps
-    value = n / (ms_per_step * 1e-3) / 1e6
-
-    # execute-only throughput on a resident plan
-    plan = ctx.plan(xy_d, stream=stream)
-    for _ in range(3):
-        plan.execute(f_d, u_d, stream=stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps = max(args.steps, 10)
-    for _ in range(reps):
-        plan.execute(f_d, u_d, stream=stream)
-    torch.cuda.synchronize()
-    exec_ms = (time.perf_counter() - t0) * 1e3 / reps
-    u = u_d.cpu().numpy()
-    plan.close()
-
-    avg = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
-    dom = max(avg, key=avg.get)
-    if dom == "m2l":
-        flops = 2.0 * RANK * RANK * info["m2l_pairs"]
-        achieved = flops / (avg[dom] * 1e-3) / 1e12
-        roof = {"kernel": "m2l (FP64 MFMA)", "bound": "mfma", "achieved": achieved,
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                "traffic": None, "work_per_launch": flops,
-                "work_definition": "2 P^2 flops per interaction-list pair, P = 48"}
-    elif dom == "leaf":
-        flops = 2.0 * info["near_pairs"] + 2.0 * RANK * n
-        achieved = flops / (avg[dom] * 1e-3) / 1e12
-        roof = {"kernel": "leaf (near field + L2P)", "bound": "alu", "achieved": achieved,
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                "traffic": None, "work_per_launch": flops,
-                "work_definition": "one FP64 FMA per near pair plus 2P flops of L2P per target",
-                "pairs_per_s": info["near_pairs"] / (avg[dom] * 1e-3)}
+        del a, b
+    if args.workload == "batched":
+        result = run_batched(args, torch, lf)
+    elif args.workload == "serving":
+        result = run_serving(args, torch, lf)
     else:
-        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": None, "traffic": None}
-
-    result = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "Msources/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload], "n_sources": n, "precision": "fp64",
-                   "leaf_level": info["leaf_level"], "leaf_side": info["leaf_side"],
-                   "max_leaf": 64, "rank": RANK, "eps": 1e-12},
-        "p50_ms": float(np.percentile(lat, 50)),
-        "p99_ms": float(np.percentile(lat, 99)),
-        "execute_only_ms": exec_ms,
-        "execute_only_msources_per_s": n / (exec_ms * 1e-3) / 1e6,
-        "phase_ms": avg,
-        "plan": info,
-        "roofline": roof,
-    }
-
-    if not args.no_cpu_baseline:
-        import workloads as wl
-        from oracle import direct as od
-        idx = wl.sample_targets(20, n, args.cpu_targets)
-        t0 = time.perf_counter()
-        ref = od.direct_sum(xy[idx], xy, f)
-        cpu_s = time.perf_counter() - t0
-        err = float(np.linalg.norm(u[idx] - ref) / np.linalg.norm(ref))
-        result["rel_err_vs_oracle"] = err
-        result["rel_err_sample"] = len(idx)
-        result["cpu_baseline"] = {
-            "value": len(idx) / cpu_s / 1e6, "unit": "Msources/s", "cores": od.threads(), "kind": "oracle",
-            "sample": "%d sampled targets x %d sources (direct sum), %.2f s wall; the rate is targets "
-                      "completed per second" % (len(idx), n, cpu_s)}
+        result = run_single(args, torch, lf)
     print(json.dumps(result), flush=True)
 
 

@@ -11,6 +11,7 @@ from ._lib import (  # noqa: F401
     LfmmError,
     Context,
     Plan,
+    Server,
     HostOperators,
     host_phi,
     library_path,
@@ -18,5 +19,5 @@ from ._lib import (  # noqa: F401
     PRECISIONS,
 )
 
-__all__ = ["LfmmError", "Context", "Plan", "HostOperators", "host_phi", "library_path",
+__all__ = ["LfmmError", "Context", "Plan", "Server", "HostOperators", "host_phi", "library_path",
            "exported_symbols", "PRECISIONS"]

@@ -35,6 +35,19 @@ class _PlanInfo(ctypes.Structure):
                 ("near_pairs", _i64), ("m2l_pairs", _i64)]
 
 
+class _ServerOptions(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_batch", _i32), ("max_inflight", _i32),
+                ("max_batch_points", _i64)]
+
+
+class _RequestStats(ctypes.Structure):
+    _fields_ = [("status", _i32), ("batch_size", _i32), ("batch_id", _i64), ("t_submit", _dbl),
+                ("t_admit", _dbl), ("t_done", _dbl)]
+
+
+STATUS_BUSY = -7
+
+
 def library_path() -> str:
     return _LIB_PATH
 
@@ -67,6 +80,10 @@ def _load():
         "lfmm_host_opset_ofo": [_vp, _i32, _i32, _vp],
         "lfmm_host_opset_leaf": [_vp, _vp],
         "lfmm_host_opset_destroy": [_vp],
+        "lfmm_server_create": [_vp, _vp, _vp],
+        "lfmm_server_submit": [_vp, _i64, _vp, _vp, _vp, _vp],
+        "lfmm_server_wait": [_vp, ctypes.c_uint64, _dbl, _vp],
+        "lfmm_server_destroy": [_vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -147,10 +164,13 @@ class Context:
         self._h = h
         self.device = int(device)
         self._plans = weakref.WeakSet()
+        self._servers = weakref.WeakSet()
 
     def close(self) -> None:
-        """Destroys the context; its live plans are destroyed first (they use its memory)."""
+        """Destroys the context; its servers and live plans are destroyed first."""
         if getattr(self, "_h", None):
+            for s in list(self._servers):
+                s.close()
             for p in list(self._plans):
                 p.close()
             _lib.lfmm_ctx_destroy(self._h)
@@ -346,6 +366,64 @@ class HostOperators:
         if getattr(self, "_h", None):
             _lib.lfmm_host_opset_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """lfmm_server: continuous batching of solve requests over one context.
+
+    The server's worker thread owns the context while the server lives: make no other
+    call on that context until close().  submit() and wait() may be called from any thread.
+    """
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, max_batch: int = 0, max_inflight: int = 0,
+                 max_batch_points: int = 0):
+        o = _ServerOptions(int(hbm_budget_bytes), int(max_batch), int(max_inflight), int(max_batch_points))
+        h = ctypes.c_void_p()
+        _check(_lib.lfmm_server_create(ctx._h, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+        self._held = {}          # ticket -> tensors the device reads or writes until done
+        ctx._servers.add(self)
+
+    def submit(self, xy, f, u=None) -> int:
+        import torch
+        n = int(xy.shape[0])
+        if int(f.shape[0]) != n:
+            raise ValueError("f must have one load per point")
+        if u is None:
+            u = torch.empty(n, dtype=torch.float64, device=f.device)
+        t = ctypes.c_uint64()
+        _check(_lib.lfmm_server_submit(self._h, n, _dev_tensor(xy, torch.int32, (2,), "xy"),
+                                       _dev_tensor(f, torch.float64, (), "f"),
+                                       _dev_tensor(u, torch.float64, (), "u"), ctypes.byref(t)))
+        self._held[int(t.value)] = (xy, f, u)
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout=None):
+        """Waits for a request; returns (u, stats dict).  Raises LfmmError with status
+        STATUS_BUSY if it is not done within `timeout` seconds."""
+        st = _RequestStats()
+        status = _lib.lfmm_server_wait(self._h, ctypes.c_uint64(int(ticket)),
+                                       -1.0 if timeout is None else float(timeout), ctypes.byref(st))
+        if status == STATUS_BUSY:
+            _check(status)
+        held = self._held.pop(int(ticket), None)
+        _check(status)
+        stats = {name: getattr(st, name) for name, _ in _RequestStats._fields_}
+        return held[2], stats
+
+    def close(self) -> None:
+        """Serves every queued request, then stops the worker."""
+        if getattr(self, "_h", None):
+            _lib.lfmm_server_destroy(self._h)
+            self._h = None
+            self._held.clear()
 
     def __del__(self):
         try:

@@ -322,6 +322,31 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st) {
                 }
         }
     }
+    // fragment order for the M2L kernels: lane l's operands of one matrix instruction sit
+    // next to lane l+1's, so a wave reads 1 KB contiguous per load (P = 48: 3 row blocks,
+    // lane group g = l / 16 covers columns 12 g .. 12 g + 11)
+    {
+        const size_t nmat = ifo.size() / (size_t(P) * P);
+        std::vector<double> f64(ifo.size());
+        std::vector<float> fhi(ifo.size()), flo(ifo.size());
+        for (size_t t = 0; t < nmat; ++t) {
+            const size_t base = t * P * P;
+            for (int m = 0; m < P / 16; ++m)
+                for (int l = 0; l < 64; ++l) {
+                    const int row = 16 * m + (l & 15), c0 = (l >> 4) * (P / 4);
+                    for (int k = 0; k < P / 4; ++k) {
+                        const size_t src = base + size_t(row) * P + c0 + k;
+                        f64[base + ((size_t(m) * (P / 8) + k / 2) * 64 + l) * 2 + (k & 1)] = ifo[src];
+                        const size_t d32 = base + ((size_t(m) * (P / 16) + k / 4) * 64 + l) * 4 + (k & 3);
+                        fhi[d32] = ifo_hi[src];
+                        flo[d32] = ifo_lo[src];
+                    }
+                }
+        }
+        ifo.swap(f64);
+        ifo_hi.swap(fhi);
+        ifo_lo.swap(flo);
+    }
     co->mem.reserve(ifo.size() * sizeof(float));
     co->mem.reserve(ifo.size() * sizeof(float));
     co->mem.reserve(mono.size() * sizeof(double));
@@ -612,8 +637,8 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
             int32_t g0, g1;
             range_of(h, int(o), 2, g0, g1);
             if (g0 < 0 || g1 <= g0) continue;
-            const int32_t cap = (g1 - g0 + 15) / 16 + 3;
-            m2l_groups.push_back(BoxGroup{int32_t(o), h, g0, g1, cls_slots, tile_slots, cap, 0});
+            const int32_t cap = (g1 - g0 + kM2LTile - 1) / kM2LTile + 3;
+            m2l_groups.push_back(BoxGroup{int32_t(o), h, g0, g1, cls_slots, tile_slots, cap, kM2LTile});
             cls_slots += 4 * (g1 - g0);
             tile_slots += cap;
         }
@@ -624,8 +649,8 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
             int32_t g0, g1;
             range_of(h, int(o), 3, g0, g1);
             if (g0 < 0 || g1 <= g0) continue;
-            const int32_t cap = (g1 - g0 + 15) / 16 + 3;
-            l2l_groups.push_back(BoxGroup{int32_t(o), h, g0, g1, cls_slots, tile_slots, cap, 0});
+            const int32_t cap = (g1 - g0 + kBoxMatTile - 1) / kBoxMatTile + 3;
+            l2l_groups.push_back(BoxGroup{int32_t(o), h, g0, g1, cls_slots, tile_slots, cap, kBoxMatTile});
             cls_slots += 4 * (g1 - g0);
             tile_slots += cap;
         }
@@ -794,8 +819,7 @@ void run_forest(lfmm_plan* pl, const double* const* f, double* const* u, hipStre
             launch_m2l_mixed(pl->tiles + pl->m2l.t0, pl->d_m2l_ntiles, pl->m2l.n, pl->cls_box, pl->il27, pl->d_ops,
                              pl->Q, pl->U, st);
         else
-            launch_boxmat(kModeM2L, pl->tiles, pl->m2l.t0, nullptr, pl->m2l.n, pl->m2l.n, pl->cls_box, pl->il27,
-                          pl->d_ops, pl->Q, pl->U, st);
+            launch_m2l(pl->tiles + pl->m2l.t0, pl->m2l.n, pl->cls_box, pl->il27, pl->d_ops, pl->Q, pl->U, st);
     }
     mark(4);
     for (int h = pl->Hmax; h >= 0; --h) {

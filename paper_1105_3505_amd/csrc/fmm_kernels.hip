@@ -117,7 +117,6 @@ __device__ inline int32_t xcd_tile(int32_t b, int32_t G, int32_t step, int32_t n
 
 // Box-matrix products on the FP64 matrix cores: for a tile of up to 16 target boxes that
 // share their operators, out[box] (+)= sum_k A_k in[src_k(box)] with 48 x 48 operators A_k:
-//   M2L: k = 27 interaction slots, A_k = T_ifo^d(c, k) at the tile's height, out = U;
 //   M2M: k = 4 children,            A_k = T_ofo^(k) at the tile's height,      out = Q;
 //   L2L: k = the parent,            A   = T_ofo^(c)T at the parent's height,  out += U.
 // The 16x16x4 FP64 instruction is issued per 16-row block of A: in step kk lane group g
@@ -131,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_boxmat(const BoxTile* tiles, int32_t
                                                     int32_t ntiles_host, const int32_t* box_list, const int32_t* src_tab,
                                                     const OpsPtrs* ops, const double* in, double* out) {
     constexpr int MT = P / 16, KQ = P / 4;
-    constexpr int NSRC = (MODE == kModeM2L) ? kNumInteractions : (MODE == kModeM2M ? 4 : 1);
+    constexpr int NSRC = (MODE == kModeM2M) ? 4 : 1;
     __shared__ double red[kWaves - 1][P][16];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int n = lane & 15, g = lane >> 4;
@@ -154,10 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_boxmat(const BoxTile* tiles, int32_t
             for (int k = k_first; k < NSRC; k += k_step) {
                 int32_t src = -1;
                 const double* A;
-                if (MODE == kModeM2L) {
-                    src = (box >= 0) ? src_tab[size_t(box) * kNumInteractions + k] : -1;
-                    A = op.ifo + (size_t(tl.height) * kNumIfoSlots + c_dslot.s[tl.cls][k]) * P * P;
-                } else if (MODE == kModeM2M) {
+                if (MODE == kModeM2M) {
                     src = (box >= 0) ? src_tab[size_t(box) * 4 + k] : -1;
                     A = op.ofo_rm + (size_t(tl.height) * 4 + k) * P * P;
                 } else {
@@ -209,21 +205,110 @@ __global__ __launch_bounds__(kBlock) void k_boxmat(const BoxTile* tiles, int32_t
     }
 }
 
-// Mixed-precision M2L on the FP32 matrix cores.  Each operator is written T^d = c_d 1 1^T + R^d
-// with c_d its mean entry: the constant part, which carries the large log|d| level of the
-// kernel, is applied in FP64 as c_d times the source's charge sum; only the remainder R^d,
-// several times smaller, goes through FP32.  R^d and q-hat are split into FP32 hi + lo parts;
-// each 16x16x4 step forms R_hi q_hi in one FP32 accumulator and R_hi q_lo + R_lo q_hi in
-// another (the cross terms are ~2^-24 of the first and would be rounded away if added to
-// it), and both are flushed into FP64 accumulators after every step, so FP32 rounding acts on
-// four-term partial sums only.  The FP32 instruction returns element i of lane (g, n) as row
-// 4 g + i.  Slots are split over the waves of a block as in the FP64 kernel.
+// M2L on the matrix cores.  A tile holds up to 64 target boxes of one operator set, height
+// and child position; wave w of the block owns boxes 16 w .. 16 w + 15 (the 16 columns of
+// its products) and runs all 27 interaction slots, so no partial sums cross waves.  The
+// operator of each slot is stored in fragment order (lane l's operands of one instruction
+// next to lane l+1's), staged once per block in LDS with coalesced loads, double-buffered,
+// and read by all four waves; the next slot's operator and source expansions are loaded
+// while the current slot's instructions run.  One barrier per slot: the buffer a slot
+// writes was last read two slots earlier, before the previous slot's barrier.
+//
+// FP64: 16x16x4 instruction, step kk of row block m takes column g * 12 + kk in lane group
+// g = lane / 16; element i of lane (g, n) is row 16 m + g + 4 i, column n.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list,
+                                                 const int32_t* il27, const OpsPtrs* ops, const double* Q,
+                                                 double* U) {
+    constexpr int MT = P / 16, KQ = P / 4, NJ = KQ / 2;
+    constexpr int A2 = P * P / 2;                      // double2 per operator
+    constexpr int PER = (A2 + kBlock - 1) / kBlock;
+    __shared__ double2 sA[2][A2];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n = lane & 15, g = lane >> 4;
+    const int32_t G = int32_t(gridDim.x);
+    for (int32_t step = 0;; ++step) {
+        const int32_t t = xcd_tile(int32_t(blockIdx.x), G, step, ntiles);
+        if (t < 0) break;                                  // uniform over the block
+        const BoxTile tl = tiles[t];
+        if (tl.count == 0) continue;
+        const bool wave_on = 16 * wave < tl.count;        // uniform over the wave
+        const int col = 16 * wave + n;
+        const int32_t box = (col < tl.count) ? box_list[tl.start + col] : -1;
+        const OpsPtrs& op = ops[tl.ops];
+        const double2* Ah = reinterpret_cast<const double2*>(op.ifo) + size_t(tl.height) * kNumIfoSlots * A2;
+        const int32_t* il = il27 + size_t(box >= 0 ? box : 0) * kNumInteractions;
+        double2 ra[PER], rb[NJ];
+        auto load_slot = [&](int k) {
+            const double2* A = Ah + size_t(c_dslot.s[tl.cls][k]) * A2;
+            #pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int e = int(threadIdx.x) + i * kBlock;
+                if (e < A2) ra[i] = A[e];
+            }
+            const int32_t src = (box >= 0) ? il[k] : -1;
+            const double2* qs = reinterpret_cast<const double2*>(Q + size_t(src >= 0 ? src : 0) * P + g * KQ);
+            #pragma unroll
+            for (int j = 0; j < NJ; ++j) rb[j] = (src >= 0) ? qs[j] : double2{0.0, 0.0};
+        };
+        load_slot(0);
+        double4_t acc[MT];
+        #pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m] = double4_t{0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < kNumInteractions; ++k) {
+            double2* buf = sA[k & 1];
+            #pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int e = int(threadIdx.x) + i * kBlock;
+                if (e < A2) buf[e] = ra[i];
+            }
+            double2 b[NJ];
+            #pragma unroll
+            for (int j = 0; j < NJ; ++j) b[j] = rb[j];
+            __syncthreads();
+            if (k + 1 < kNumInteractions) load_slot(k + 1);
+            if (wave_on) {
+                #pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    #pragma unroll
+                    for (int j = 0; j < NJ; ++j) {
+                        const double2 a = buf[(m * NJ + j) * 64 + lane];
+                        acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[j].x, acc[m], 0, 0, 0);
+                        acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b[j].y, acc[m], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        if (box >= 0) {
+            double* ub = U + size_t(box) * P;
+            #pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                #pragma unroll
+                for (int i = 0; i < 4; ++i) ub[16 * m + g + 4 * i] = acc[m][i];
+            }
+        }
+        __syncthreads();   // the next tile's first slot rewrites a buffer read above
+    }
+}
+
+// Mixed-precision M2L on the FP32 matrix cores, same tiling and staging as k_m2l.  Each
+// operator is written T^d = c_d 1 1^T + R^d with c_d its mean entry: the constant part,
+// which carries the large log|d| level of the kernel, is applied in FP64 as c_d times the
+// source's charge sum; only the remainder R^d, several times smaller, goes through FP32.
+// R^d and q-hat are split into FP32 hi + lo parts; each 16x16x4 step forms R_hi q_hi in one
+// FP32 accumulator and R_hi q_lo + R_lo q_hi in another (the cross terms are ~2^-24 of the
+// first and would be rounded away if added to it), and both are flushed into FP64
+// accumulators after every step, so FP32 rounding acts on four-term partial sums only.  The
+// FP32 instruction returns element i of lane (g, n) as row 4 g + i.
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_p,
                                                        const int32_t* box_list, const int32_t* il27,
                                                        const OpsPtrs* ops, const double* Q, double* U) {
-    constexpr int MT = P / 16, KQ = P / 4;
-    __shared__ double red[kWaves - 1][P][16];
+    constexpr int MT = P / 16, KQ = P / 4, NJ = KQ / 2, NJ4 = KQ / 4;
+    constexpr int A4 = P * P / 4;                      // float4 per operator part
+    constexpr int PER = (A4 + kBlock - 1) / kBlock;
+    __shared__ float4_t sH[2][A4];
+    __shared__ float4_t sL[2][A4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int n = lane & 15, g = lane >> 4;
     const int32_t ntiles = *ntiles_p;
@@ -234,69 +319,97 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, cons
         if (t < 0) break;
         const BoxTile tl = tiles[t];
         if (tl.count == 0) continue;
-        const int32_t box = (n < tl.count) ? box_list[tl.start + n] : -1;
+        const bool wave_on = 16 * wave < tl.count;
+        const int col = 16 * wave + n;
+        const int32_t box = (col < tl.count) ? box_list[tl.start + col] : -1;
         const OpsPtrs& op = ops[tl.ops];
         const int rk = op.rank[tl.height];
+        const size_t hbase = size_t(tl.height) * kNumIfoSlots * A4;
+        const float4_t* Hh = reinterpret_cast<const float4_t*>(op.ifo_hi) + hbase;
+        const float4_t* Lh = reinterpret_cast<const float4_t*>(op.ifo_lo) + hbase;
+        const double* mono = op.mono + size_t(tl.height) * kNumIfoSlots;
+        const int32_t* il = il27 + size_t(box >= 0 ? box : 0) * kNumInteractions;
+        float4_t rh[PER], rl[PER];
+        double2 rb[NJ];
+        auto load_slot = [&](int k) {
+            const size_t off = size_t(c_dslot.s[tl.cls][k]) * A4;
+            #pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int e = int(threadIdx.x) + i * kBlock;
+                if (e < A4) {
+                    rh[i] = Hh[off + e];
+                    rl[i] = Lh[off + e];
+                }
+            }
+            const int32_t src = (box >= 0) ? il[k] : -1;
+            const double2* qs = reinterpret_cast<const double2*>(Q + size_t(src >= 0 ? src : 0) * P + g * KQ);
+            #pragma unroll
+            for (int j = 0; j < NJ; ++j) rb[j] = (src >= 0) ? qs[j] : double2{0.0, 0.0};
+        };
+        load_slot(0);
         double4_t acc[MT];
         #pragma unroll
         for (int m = 0; m < MT; ++m) acc[m] = double4_t{0.0, 0.0, 0.0, 0.0};
-        for (int k = wave; k < kNumInteractions; k += kWaves) {
-            const int d = c_dslot.s[tl.cls][k];
-            const int32_t src = (box >= 0) ? il27[size_t(box) * kNumInteractions + k] : -1;
+        for (int k = 0; k < kNumInteractions; ++k) {
+            const int bsel = k & 1;
+            #pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int e = int(threadIdx.x) + i * kBlock;
+                if (e < A4) {
+                    sH[bsel][e] = rh[i];
+                    sL[bsel][e] = rl[i];
+                }
+            }
             float bh[KQ], bl[KQ];
             double qsum = 0.0;
             #pragma unroll
-            for (int kk = 0; kk < KQ; ++kk) {
-                const double q = (src >= 0) ? Q[size_t(src) * P + g * KQ + kk] : 0.0;
-                qsum += q;
-                bh[kk] = float(q);
-                bl[kk] = float(q - double(bh[kk]));
+            for (int j = 0; j < NJ; ++j) {
+                const double q0 = rb[j].x, q1 = rb[j].y;
+                qsum += q0 + q1;
+                bh[2 * j] = float(q0);
+                bl[2 * j] = float(q0 - double(bh[2 * j]));
+                bh[2 * j + 1] = float(q1);
+                bl[2 * j + 1] = float(q1 - double(bh[2 * j + 1]));
             }
-            // charge sum of source column n: the four lane groups hold a quarter each
-            qsum += __shfl_xor(qsum, 16, 64);
-            qsum += __shfl_xor(qsum, 32, 64);
-            const double cq = op.mono[size_t(tl.height) * kNumIfoSlots + d] * qsum;
-            #pragma unroll
-            for (int m = 0; m < MT; ++m) {
+            const int d = c_dslot.s[tl.cls][k];
+            __syncthreads();
+            if (k + 1 < kNumInteractions) load_slot(k + 1);
+            if (wave_on) {
+                // charge sum of source column n: the four lane groups hold a quarter each
+                qsum += __shfl_xor(qsum, 16, 64);
+                qsum += __shfl_xor(qsum, 32, 64);
+                const double cq = mono[d] * qsum;
                 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (16 * m + 4 * g + i < rk) acc[m][i] += cq;   // padded rows stay zero
-            }
-            const size_t base = (size_t(tl.height) * kNumIfoSlots + d) * P * P;
-            #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                const float* ah = op.ifo_hi + base + size_t(16 * m + n) * P + g * KQ;
-                const float* al = op.ifo_lo + base + size_t(16 * m + n) * P + g * KQ;
-                #pragma unroll
-                for (int kk = 0; kk < KQ; ++kk) {
-                    const float4_t main = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[kk], bh[kk], zero, 0, 0, 0);
-                    float4_t cross = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[kk], bl[kk], zero, 0, 0, 0);
-                    cross = __builtin_amdgcn_mfma_f32_16x16x4f32(al[kk], bh[kk], cross, 0, 0, 0);
+                for (int m = 0; m < MT; ++m) {
                     #pragma unroll
-                    for (int i = 0; i < 4; ++i) acc[m][i] += double(main[i]) + double(cross[i]);
+                    for (int i = 0; i < 4; ++i)
+                        if (16 * m + 4 * g + i < rk) acc[m][i] += cq;   // padded rows stay zero
+                }
+                #pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    #pragma unroll
+                    for (int j4 = 0; j4 < NJ4; ++j4) {
+                        const float4_t ah = sH[bsel][(m * NJ4 + j4) * 64 + lane];
+                        const float4_t al = sL[bsel][(m * NJ4 + j4) * 64 + lane];
+                        #pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int kk = 4 * j4 + e;
+                            const float4_t mn = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[e], bh[kk], zero, 0, 0, 0);
+                            float4_t cr = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[e], bl[kk], zero, 0, 0, 0);
+                            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(al[e], bh[kk], cr, 0, 0, 0);
+                            #pragma unroll
+                            for (int i = 0; i < 4; ++i) acc[m][i] += double(mn[i]) + double(cr[i]);
+                        }
+                    }
                 }
             }
         }
-        if (wave > 0) {
-            #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                #pragma unroll
-                for (int i = 0; i < 4; ++i) red[wave - 1][16 * m + 4 * g + i][n] = acc[m][i];
-            }
-        }
-        __syncthreads();
-        if (wave == 0 && box >= 0) {
+        if (box >= 0) {
             double* ub = U + size_t(box) * P;
             #pragma unroll
             for (int m = 0; m < MT; ++m) {
                 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = 16 * m + 4 * g + i;   // FP32 output layout
-                    double v = acc[m][i];
-                    #pragma unroll
-                    for (int w = 0; w < kWaves - 1; ++w) v += red[w][r][n];
-                    ub[r] = v;
-                }
+                for (int i = 0; i < 4; ++i) ub[16 * m + 4 * g + i] = acc[m][i];   // FP32 output layout
             }
         }
         __syncthreads();
@@ -524,10 +637,7 @@ void launch_boxmat(int mode, const BoxTile* tiles, int32_t tile0, const int32_t*
     int64_t g = std::min<int64_t>(max_tiles, 8192);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
     const dim3 grid(static_cast<unsigned>(g)), block(kBlock);
-    if (mode == kModeM2L)
-        hipLaunchKernelGGL((k_boxmat<kRankPad, kModeM2L>), grid, block, 0, st, tiles, tile0, ntiles_dev, ntiles_host,
-                           box_list, src, ops, in, out);
-    else if (mode == kModeM2M)
+    if (mode == kModeM2M)
         hipLaunchKernelGGL((k_boxmat<kRankPad, kModeM2M>), grid, block, 0, st, tiles, tile0, ntiles_dev, ntiles_host,
                            box_list, src, ops, in, out);
     else
@@ -535,13 +645,22 @@ void launch_boxmat(int mode, const BoxTile* tiles, int32_t tile0, const int32_t*
                            box_list, src, ops, in, out);
 }
 
+void launch_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, const int32_t* il27,
+                const OpsPtrs* ops, const double* Q, double* U, hipStream_t st) {
+    if (ntiles <= 0) return;
+    int64_t g = std::min<int64_t>(ntiles, 8192);
+    g = std::max<int64_t>(8, (g + 7) / 8 * 8);
+    hipLaunchKernelGGL(k_m2l<kRankPad>, dim3(static_cast<unsigned>(g)), dim3(kBlock), 0, st, tiles, ntiles, box_list,
+                       il27, ops, Q, U);
+}
+
 void launch_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t max_tiles, const int32_t* box_list,
                       const int32_t* il27, const OpsPtrs* ops, const double* Q, double* U, hipStream_t st) {
     if (max_tiles <= 0) return;
     int64_t g = std::min<int64_t>(max_tiles, 8192);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
-    hipLaunchKernelGGL(k_m2l_mixed<kRankPad>, dim3(unsigned(g)), dim3(kBlock), 0, st, tiles, ntiles_dev, box_list,
-                       il27, ops, Q, U);
+    hipLaunchKernelGGL(k_m2l_mixed<kRankPad>, dim3(static_cast<unsigned>(g)), dim3(kBlock), 0, st, tiles, ntiles_dev,
+                       box_list, il27, ops, Q, U);
 }
 
 void launch_leaf(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1, const uint64_t* box_key,

@@ -347,13 +347,13 @@ __global__ void k_class_tiles(const BoxGroup* groups, int32_t ngroups, const int
     int32_t t = G.tile_base;
     for (int c = 0; c < 4; ++c) {
         const int32_t cnt = scan_at(cscan, ctotal, nbox, c, G.g1) - scan_at(cscan, ctotal, nbox, c, G.g0);
-        for (int32_t s = 0; s < cnt; s += 16) {
+        for (int32_t s = 0; s < cnt; s += G.tile_boxes) {
             BoxTile tl;
             tl.ops = G.ops;
             tl.height = G.height;
             tl.cls = c;
             tl.start = G.cls_base + c * (G.g1 - G.g0) + s;
-            tl.count = min(16, cnt - s);
+            tl.count = min(G.tile_boxes, cnt - s);
             tl.pad0 = tl.pad1 = tl.pad2 = 0;
             tiles[t++] = tl;
         }

@@ -46,8 +46,13 @@ struct BoxTile {
 // Group of target boxes for the tiled passes: contiguous box range [g0, g1) of one height
 // and one operator set; class lists for it start at cls_base (4 regions of g1 - g0 slots).
 struct BoxGroup {
-    int32_t ops, height, g0, g1, cls_base, tile_base, tile_cap, pad;
+    int32_t ops, height, g0, g1, cls_base, tile_base, tile_cap, tile_boxes;
 };
+
+// Boxes per tile: the M2L kernel gives 16 boxes to each of its 4 waves; the M2M and L2L
+// kernel puts 16 boxes in one block.
+constexpr int kM2LTile = 64;
+constexpr int kBoxMatTile = 16;
 
 // Per leaf side: operators in device memory (uploaded once, shared by every plan).
 struct DevOps {
@@ -56,8 +61,11 @@ struct DevOps {
     double* leafT = nullptr;       // [side^2][kRankPad]: T_ofs column of each cell, cell-major
     double* ofo_rm = nullptr;      // [nlev][4][r parent][q child]: T_ofo (M2M operand)
     double* ofo_cm = nullptr;      // [nlev][4][q child][r parent]: T_ofo^T (L2L operand)
-    double* ifo = nullptr;         // [nlev][49][p][q] row-major T_ifo per offset slot
-    // mixed precision: T_ifo^d = c_d 1 1^T + R^d with c_d the mean entry; R^d in FP32 hi + lo
+    // T_ifo per height and offset slot, [nlev][49][48 x 48] in fragment order: element
+    // ((m * 6 + j) * 64 + l) * 2 + e is row 16 m + (l % 16), column (l / 16) * 12 + 2 j + e
+    double* ifo = nullptr;
+    // mixed precision: T_ifo^d = c_d 1 1^T + R^d with c_d the mean entry; R^d in FP32 hi + lo,
+    // element ((m * 3 + j) * 64 + l) * 4 + e is row 16 m + (l % 16), column (l / 16) * 12 + 4 j + e
     float* ifo_hi = nullptr;
     float* ifo_lo = nullptr;
     double* mono = nullptr;        // [nlev][49] c_d
@@ -84,7 +92,7 @@ struct ExecPtrs {
     double* u;
 };
 
-enum BoxMatMode { kModeM2L = 0, kModeM2M = 1, kModeL2L = 2 };
+enum BoxMatMode { kModeM2M = 1, kModeL2L = 2 };
 
 // ---- construction (forest_kernels.hip) ---------------------------------------------------
 size_t radix_scratch_bytes(int64_t n);
@@ -153,6 +161,8 @@ void launch_boxmat(int mode, const BoxTile* tiles, int32_t tile0, const int32_t*
                    int32_t ntiles_host, int32_t max_tiles, const int32_t* box_list,
                    const int32_t* src, const OpsPtrs* ops, const double* in, double* out,
                    hipStream_t st);
+void launch_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, const int32_t* il27,
+                const OpsPtrs* ops, const double* Q, double* U, hipStream_t st);
 void launch_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t max_tiles,
                       const int32_t* box_list, const int32_t* il27, const OpsPtrs* ops,
                       const double* Q, double* U, hipStream_t st);

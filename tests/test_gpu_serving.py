@@ -1,0 +1,144 @@
+"""GPU tests of the continuous-batching server (lfmm_server_*).
+
+Requests of different sizes and layouts arrive while others are on the device; each result
+must equal, bit for bit, the result of the same solve alone (a plan of its own on another
+context), and meet the FP64 accuracy target against the oracle (eq. 1.7).
+"""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import direct as od
+
+pytestmark = pytest.mark.gpu
+
+FMM_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    return torch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _rel(u, ref):
+    den = np.linalg.norm(ref)
+    return float(np.linalg.norm(u - ref) / (den if den > 0 else 1.0))
+
+
+def _requests(seed, count, hi):
+    return [wl.config_serving_request(seed, i, hi=hi)[:2] for i in range(count)]
+
+
+def test_results_alone_equal_results_in_the_mix(torch_mod):
+    import paper_1105_3505_amd as lf
+    torch = torch_mod
+    reqs = _requests(81, 48, 1e5)
+    dev = [(_dev(torch, xy), _dev(torch, f)) for xy, f in reqs]
+    ctx = lf.Context(0)
+    srv = lf.Server(ctx, max_batch=16, max_inflight=3)
+    tickets = [None] * len(reqs)
+
+    def client(lo, hi, pause):
+        for i in range(lo, hi):
+            tickets[i] = srv.submit(*dev[i])
+            time.sleep(pause)
+
+    # two clients submitting at different paces, so that requests arrive mid-flight
+    th = [threading.Thread(target=client, args=(0, 24, 0.0005)),
+          threading.Thread(target=client, args=(24, 48, 0.0013))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    out = [srv.wait(t, timeout=120) for t in tickets]
+    srv.close()
+    ctx.close()
+
+    sizes = [s["batch_size"] for _, s in out]
+    assert max(sizes) > 1, "no request was batched with another"
+    # iterations overlapped: some iteration was admitted before an earlier one was done
+    by_batch = {}
+    for _, s in out:
+        b = by_batch.setdefault(s["batch_id"], [s["t_admit"], s["t_done"]])
+        b[0] = min(b[0], s["t_admit"])
+    ids = sorted(by_batch)
+    assert any(by_batch[ids[j + 1]][0] < by_batch[ids[j]][1] for j in range(len(ids) - 1))
+    for _, s in out:
+        assert s["status"] == 0 and s["t_submit"] <= s["t_admit"] <= s["t_done"]
+
+    alone_ctx = lf.Context(0)
+    for i, ((xy, f), (u, st)) in enumerate(zip(reqs, out)):
+        plan = alone_ctx.plan(dev[i][0])
+        ua = plan.execute(dev[i][1]).cpu().numpy()
+        plan.close()
+        assert np.array_equal(u.cpu().numpy(), ua), "request %d (batch of %d)" % (i, st["batch_size"])
+        if i % 6 == 0:
+            idx = wl.sample_targets(200 + i, len(xy), 300)
+            assert _rel(u.cpu().numpy()[idx], od.direct_sum(xy[idx], xy, f)) <= FMM_TOL, i
+    alone_ctx.close()
+
+
+def test_memory_budget_bounds_admission(torch_mod):
+    import paper_1105_3505_amd as lf
+    torch = torch_mod
+    ctx = lf.Context(0)
+    fp = ctx.footprint_bytes(20000)
+    # room for about two requests of 20,000 points at a time
+    srv = lf.Server(ctx, hbm_budget_bytes=int(2.5 * fp), max_batch=64)
+    rng = np.random.default_rng(91)
+    reqs = []
+    for i in range(12):
+        xy = wl.uniform_box(rng, 20000, 600)
+        reqs.append((xy, wl.zero_sum_loads(rng.standard_normal(20000))))
+    dev = [(_dev(torch, xy), _dev(torch, f)) for xy, f in reqs]
+    tickets = [srv.submit(*d) for d in dev]
+    big = _dev(torch, wl.uniform_box(rng, 200000, 2000))
+    with pytest.raises(lf.LfmmError) as e:
+        srv.submit(big, torch.zeros(200000, dtype=torch.float64, device="cuda"))
+    assert e.value.status == -3
+    out = [srv.wait(t, timeout=120) for t in tickets]
+    srv.close()
+    assert all(s["batch_size"] <= 2 for _, s in out)
+    # at most two requests on the device at any time
+    spans = [(s["t_admit"], s["t_done"]) for _, s in out]
+    for a, _ in spans:
+        assert sum(1 for b, c in spans if b <= a < c) <= 2
+    for (xy, f), (u, _) in zip(reqs[:3], out[:3]):
+        idx = wl.sample_targets(7, len(xy), 200)
+        assert _rel(u.cpu().numpy()[idx], od.direct_sum(xy[idx], xy, f)) <= FMM_TOL
+    ctx.close()
+
+
+def test_failed_request_does_not_poison_its_batch(torch_mod):
+    import paper_1105_3505_amd as lf
+    torch = torch_mod
+    ctx = lf.Context(0)
+    srv = lf.Server(ctx, max_batch=8, max_inflight=1)
+    rng = np.random.default_rng(93)
+    good = [(wl.uniform_box(rng, 3000, 200), None) for _ in range(4)]
+    good = [(xy, wl.zero_sum_loads(rng.standard_normal(len(xy)))) for xy, _ in good]
+    bad_xy = np.array([[-(2 ** 31) + 5, 0], [2 ** 31 - 5, 0]], np.int32)
+    items = good[:2] + [(bad_xy, np.array([1.0, -1.0]))] + good[2:]
+    dev = [(_dev(torch, xy), _dev(torch, f)) for xy, f in items]
+    tickets = [srv.submit(*d) for d in dev]
+    results = []
+    for t in tickets:
+        try:
+            results.append(srv.wait(t, timeout=120))
+        except lf.LfmmError as e:
+            results.append(e.status)
+    srv.close()
+    assert results[2] == -2
+    for k in (0, 1, 3, 4):
+        xy, f = items[k]
+        u = results[k][0].cpu().numpy()
+        assert _rel(u, od.direct_sum(xy, xy, f)) <= FMM_TOL
+    ctx.close()

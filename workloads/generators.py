@@ -35,9 +35,21 @@ def zero_sum_loads(raw: np.ndarray) -> np.ndarray:
 def uniform_box(rng: np.random.Generator, n: int, side: int, origin=(0, 0)) -> np.ndarray:
     """``n`` distinct lattice cells drawn uniformly (without replacement) from a side x side box."""
     side = int(side)
-    if n > side * side:
+    total = side * side
+    if n > total:
         raise ValueError("more points than cells")
-    cells = rng.choice(side * side, size=n, replace=False)
+    if total <= 4 * n:
+        cells = rng.choice(total, size=n, replace=False)
+    else:
+        # sparse box: draws with replacement, later duplicates rejected (the same law as
+        # drawing without replacement, at a cost in n rather than in side^2)
+        cells = np.empty(0, dtype=np.int64)
+        while len(cells) < n:
+            need = n - len(cells)
+            cand = np.concatenate([cells, rng.integers(0, total, size=need + need // 8 + 16)])
+            _, first = np.unique(cand, return_index=True)
+            first.sort()
+            cells = cand[first][:n]
     xy = np.empty((n, 2), dtype=np.int64)
     xy[:, 0] = cells % side + origin[0]
     xy[:, 1] = cells // side + origin[1]

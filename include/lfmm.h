@@ -64,14 +64,21 @@ typedef struct lfmm_options {
     double eps;               /* ID tolerance relative to the first pivot (Section 4:
                                  requested precision); default 1e-12                       */
     int32_t max_leaf;         /* N_leaf of Section 6: most points a leaf may hold before the
-                                 tree is refined; 0 = default (64)                         */
+                                 tree is refined; default 64; 0 = automatic: the value
+                                 lfmm_autotune found for point sets of similar size and
+                                 density, else 64                                          */
     int32_t precision;        /* lfmm_precision of the interaction (M2L) pass              */
     int32_t proxy_per_edge;   /* proxy points per edge of the proxy ring once the full ring
                                  is larger (Remark 5.1); default 64                        */
     int32_t max_rank;         /* cap on the skeleton size P, 16..64, multiple of 16;
                                  default 48                                                */
-    int32_t flags;            /* reserved, must be 0                                       */
+    int32_t flags;            /* LFMM_FLAG_* bits, default 0                               */
 } lfmm_options;
+
+/* options.flags: lfmm_execute / lfmm_execute_instances replay a HIP graph of the evaluation
+ * passes, recorded at the plan's first execute (one graph launch per execute instead of one
+ * launch per pass and height).  Per-phase timing is not available in this mode. */
+#define LFMM_FLAG_GRAPH 1
 
 typedef struct lfmm_ctx lfmm_ctx;     /* device, phi table, per-leaf-side operator cache  */
 typedef struct lfmm_plan lfmm_plan;   /* one or more point sets (instances): sorted points,
@@ -140,6 +147,19 @@ lfmm_status lfmm_execute_batch(lfmm_ctx* ctx, int32_t n_plans, lfmm_plan* const*
                                const double* const* f_dev, double* const* u_dev, void* stream);
 
 lfmm_status lfmm_plan_get_info(lfmm_plan* plan, lfmm_plan_info* out);
+
+/* Autotuner of N_leaf (Section 6), which sets the leaf size and with it the balance between
+ * the near field (pairs grow with N_leaf) and the matrix passes (boxes shrink with it):
+ * builds the plan of the n points xy_dev[2n] with each of the n_cand candidates cand_host[]
+ * (each in [1, 4096]), evaluates it `reps` times with zero loads, and stores in *best_host
+ * the candidate with the least time per solve (objective 0: plan build plus one execute) or
+ * per execute (objective 1: the plan is reused).  ms_host[n_cand] (optional) receives each
+ * candidate's time.  The context remembers the choice for point sets of the same size and
+ * density class (log2 of n and of n / root-box area, rounded) and uses it for later plans
+ * when options.max_leaf is 0.  Synchronises the stream. */
+lfmm_status lfmm_autotune(lfmm_ctx* ctx, int64_t n, const int32_t* xy_dev, int32_t n_cand,
+                          const int32_t* cand_host, int32_t objective, int32_t reps, void* stream,
+                          int32_t* best_host, double* ms_host);
 
 /* Phases of lfmm_execute, in launch order, for lfmm_plan_phase_times. */
 typedef enum lfmm_phase {

@@ -46,6 +46,7 @@ class _RequestStats(ctypes.Structure):
 
 
 STATUS_BUSY = -7
+FLAG_GRAPH = 1
 
 
 def library_path() -> str:
@@ -66,6 +67,7 @@ def _load():
         "lfmm_execute_instances": [_vp, _vp, _vp, _vp],
         "lfmm_execute_batch": [_vp, _i32, _vp, _vp, _vp, _vp],
         "lfmm_plan_get_info": [_vp, _vp],
+        "lfmm_autotune": [_vp, _i64, _vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp],
         "lfmm_plan_set_timing": [_vp, _i32],
         "lfmm_plan_export": [_vp, _i32, _vp, _vp],
         "lfmm_plan_phase_times": [_vp, _vp],
@@ -114,7 +116,7 @@ def exported_symbols() -> list[str]:
 
 
 def _options(eps=None, max_leaf=None, precision=None, proxy_per_edge=None, max_rank=None,
-             flags=None) -> _Options:
+             flags=None, graph=None) -> _Options:
     o = _Options()
     _check(_lib.lfmm_options_init(ctypes.byref(o)))
     if eps is not None:
@@ -129,6 +131,8 @@ def _options(eps=None, max_leaf=None, precision=None, proxy_per_edge=None, max_r
         o.max_rank = int(max_rank)
     if flags is not None:
         o.flags = int(flags)
+    if graph:
+        o.flags |= FLAG_GRAPH
     return o
 
 
@@ -233,6 +237,20 @@ class Context:
         up = (ctypes.c_void_p * k)(*[_dev_tensor(u, torch.float64, (), "u").value for u in us])
         _check(_lib.lfmm_execute_batch(self._h, k, hp, fp, up, _stream_handle(stream)))
         return us
+
+    def autotune(self, xy, candidates=(16, 32, 64, 128), objective="solve", reps=3, stream=None):
+        """lfmm_autotune: the fastest N_leaf among `candidates` for this point set; the
+        context remembers it for point sets of similar size and density (used when the
+        context's max_leaf is 0).  Returns (best, {candidate: ms})."""
+        import torch
+        cand = np.ascontiguousarray(candidates, dtype=np.int32)
+        ms = np.zeros(len(cand), dtype=np.float64)
+        best = ctypes.c_int32()
+        obj = {"solve": 0, "execute": 1}[objective]
+        _check(_lib.lfmm_autotune(self._h, int(xy.shape[0]), _dev_tensor(xy, torch.int32, (2,), "xy"), len(cand),
+                                  cand.ctypes.data_as(_vp), obj, int(reps), _stream_handle(stream),
+                                  ctypes.byref(best), ms.ctypes.data_as(_vp)))
+        return int(best.value), dict(zip([int(c) for c in cand], [float(v) for v in ms]))
 
     def footprint_bytes(self, n: int) -> int:
         out = ctypes.c_size_t()

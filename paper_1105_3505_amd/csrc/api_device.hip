@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -190,8 +191,26 @@ struct lfmm_ctx {
     double* phi_oct = nullptr;   // octant table, radius 128
     std::map<int64_t, CachedOps*> ops;                // deepest operator set per leaf side
     std::vector<std::unique_ptr<CachedOps>> all_ops;  // every set built; plans may hold any
+    std::map<std::pair<int, int>, int32_t> tuned;     // (size class, density class) -> N_leaf
+    hipStream_t capture = nullptr;                    // stream that graph captures record on
     std::mutex mu;
+    ~lfmm_ctx() {
+        if (capture) (void)hipStreamDestroy(capture);
+    }
 };
+
+namespace {
+
+// size and density classes of a point set for the tuning table: rounded log2 of n and of
+// n / (root box area)
+std::pair<int, int> tune_key(int64_t n, int D) {
+    const double ln = std::log2(double(std::max<int64_t>(n, 1)));
+    return {int(std::lround(ln)), int(std::lround(ln - 2.0 * D))};
+}
+
+constexpr int32_t kDefaultMaxLeaf = 64;
+
+}  // namespace
 
 struct TileRange {
     int32_t t0 = 0, n = 0;
@@ -232,8 +251,13 @@ struct lfmm_plan {
     bool failed = false;
     bool timing = false;
     bool timed_once = false;
+    bool use_graph = false;                 // execute replays a captured HIP graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
     hipEvent_t ev[LFMM_NUM_PHASES + 1] = {};
     ~lfmm_plan() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
         if (exec_copied) (void)hipEventDestroy(exec_copied);
@@ -399,9 +423,9 @@ void upload(T* dst, const std::vector<T>& src, hipStream_t st) {
 
 // Builds the forest of K point sets: Section 6 tree of every instance, lists of Definition 6.1,
 // operator sets for every leaf side used, and the tiles of the matrix passes.
-void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t* const* xy_ptrs, hipStream_t st) {
+void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t* const* xy_ptrs, int32_t max_leaf,
+                  hipStream_t st) {
     lfmm_ctx* ctx = pl->ctx;
-    const int nleaf_max = ctx->opt.max_leaf;
     pl->K = K;
     pl->pt_off.assign(size_t(K) + 1, 0);
     for (int32_t k = 0; k < K; ++k) pl->pt_off[size_t(k) + 1] = pl->pt_off[size_t(k)] + int32_t(sizes[k]);
@@ -489,6 +513,15 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
         I.oy = b[1];
         I.D = bits_for_extent(extent);
         Dmax = std::max(Dmax, I.D);
+        // N_leaf: the caller's, else the options', else the tuned value for this size and
+        // density, else the default
+        int32_t ml = max_leaf > 0 ? max_leaf : ctx->opt.max_leaf;
+        if (ml <= 0) {
+            std::lock_guard<std::mutex> lock(ctx->mu);
+            auto it = ctx->tuned.find(tune_key(I.pt1 - I.pt0, I.D));
+            ml = it != ctx->tuned.end() ? it->second : kDefaultMaxLeaf;
+        }
+        I.max_leaf = ml;
     }
     int ibits = 0;
     while ((int64_t(1) << ibits) < K) ++ibits;
@@ -534,7 +567,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     // ---- leaf levels and box counts ---------------------------------------------------------
     LFMM_HIP(hipMemsetAsync(d_hist, 0, size_t(K) * (kMaxLevels + 2) * 4, st));
     LFMM_HIP(hipMemsetAsync(d_maxc, 0, size_t(K) * 4, st));
-    launch_level_stats(skeys, d_chunks, nch, pl->d_inst, Dmax, nleaf_max, cl, d_hist, d_maxc, st);
+    launch_level_stats(skeys, d_chunks, nch, pl->d_inst, Dmax, cl, d_hist, d_maxc, st);
     std::vector<int32_t> hist(static_cast<size_t>(K) * (kMaxLevels + 2)), maxc(static_cast<size_t>(K));
     LFMM_HIP(hipMemcpyAsync(hist.data(), d_hist, hist.size() * 4, hipMemcpyDeviceToHost, st));
     LFMM_HIP(hipMemcpyAsync(maxc.data(), d_maxc, maxc.size() * 4, hipMemcpyDeviceToHost, st));
@@ -548,7 +581,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     for (int32_t k = 0; k < K; ++k) {
         InstInfo& I = pl->inst[size_t(k)];
         const int64_t nk = I.pt1 - I.pt0;
-        int L = (nk > nleaf_max) ? std::min(I.D, maxc[size_t(k)] + 1) : 0;
+        int L = (nk > I.max_leaf) ? std::min(I.D, maxc[size_t(k)] + 1) : 0;
         int min_L = 0;   // leaves no wider than the dense-model limit (Remark 8.2)
         while ((int64_t(1) << (I.D - min_L)) > kDenseLeafMax) ++min_L;
         L = std::max(L, min_L);
@@ -684,7 +717,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     mb.reserve(size_t(std::max(cls_slots, 1)) * 4);
     mb.reserve(size_t(std::max(tile_slots, 1)) * sizeof(BoxTile));
     mb.reserve(size_t(std::max<size_t>(m2l_groups.size() + l2l_groups.size(), 1)) * sizeof(BoxGroup));
-    mb.reserve(size_t(nb) * P * 8);                      // Q
+    mb.reserve(size_t(nb + 1) * P * 8);                  // Q and its zero row
     mb.reserve(size_t(nb) * P * 8);                      // U
     mb.allocate();
     pl->box_key = mb.take<uint64_t>(nb);
@@ -700,8 +733,10 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     pl->cls_box = mb.take<int32_t>(std::max(cls_slots, 1));
     pl->tiles = mb.take<BoxTile>(std::max(tile_slots, 1));
     BoxGroup* d_groups = mb.take<BoxGroup>(std::max<size_t>(m2l_groups.size() + l2l_groups.size(), 1));
-    pl->Q = mb.take<double>(size_t(nb) * P);
+    pl->Q = mb.take<double>(size_t(nb + 1) * P);
     pl->U = mb.take<double>(size_t(nb) * P);
+    // row nb of Q stays zero: the M2L kernels read it for empty list slots
+    LFMM_HIP(hipMemsetAsync(pl->Q + size_t(nb) * P, 0, size_t(P) * sizeof(double), st));
 
     // ---- tables ---------------------------------------------------------------------------------
     upload(pl->d_inst, pl->inst, st);
@@ -759,18 +794,19 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
                        pl->box_parent, pl->box_child, pl->box_inst, pl->box_lev, st);
     launch_link_boxes(pl->box_key, pl->box_parent, pl->box_inst, pl->box_lev, pl->d_inst, nb, pl->box_pt0,
                       pl->box_child, pl->box_pt1, st);
-    for (int h = H; h >= 0; --h)
-        launch_lists_height(pl->hbase[size_t(h)], pl->hbase[size_t(h) + 1], pl->box_key, pl->box_parent,
-                            pl->box_child, pl->box_lev, pl->nb9, pl->il27, st);
+    launch_lists(pl->hbase.data(), H, pl->box_key, pl->box_parent, pl->box_child, pl->box_lev, pl->nb9, pl->il27,
+                 st);
     launch_class_flags(pl->box_key, nb, cflags, st);
     scan_rows(cflags, cscan, nb, 4, ctotal, cscr, st);
-    launch_class_lists(d_groups, int32_t(groups.size()), cscan, ctotal, pl->box_key, nb, pl->cls_box, pl->tiles,
-                       nullptr, st);
+    launch_class_lists(d_groups, int32_t(groups.size()), m2m_base, cscan, ctotal, pl->box_key, nb, pl->cls_box,
+                       pl->tiles, st);
     if (std::any_of(side_of.begin(), side_of.end(), [](int64_t s) { return s <= 16; }))
         launch_point_keys(pl->pts, pl->pinst, pl->d_inst, pl->d_ops, n, pl->pkey, st);
     LFMM_HIP(hipGetLastError());
-    // staging for the per-execute pointer table of batched plans
-    if (K > 1) {
+    // staging for the per-execute pointer table of batched plans (and of graph replays,
+    // whose kernels always read the table)
+    pl->use_graph = (ctx->opt.flags & LFMM_FLAG_GRAPH) != 0;
+    if (K > 1 || pl->use_graph) {
         pl->h_exec = static_cast<ExecPtrs*>(ctx->pinned.acquire(size_t(K) * sizeof(ExecPtrs), &pl->h_exec_cls));
         LFMM_HIP(hipEventCreateWithFlags(&pl->exec_copied, hipEventDisableTiming));
     }
@@ -779,24 +815,12 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     tmp2.release();
 }
 
-void run_forest(lfmm_plan* pl, const double* const* f, double* const* u, hipStream_t st) {
-    const ExecPtrs* tab = nullptr;
-    const double* f1 = nullptr;
-    double* u1 = nullptr;
-    if (pl->K == 1) {
-        f1 = f[0];
-        u1 = u[0];
-    } else {
-        // the previous execute's copy must have read the staging buffer before it is rewritten
-        LFMM_HIP(hipEventSynchronize(pl->exec_copied));
-        for (int32_t k = 0; k < pl->K; ++k) pl->h_exec[k] = ExecPtrs{f[k], u[k]};
-        LFMM_HIP(hipMemcpyAsync(pl->d_exec, pl->h_exec, size_t(pl->K) * sizeof(ExecPtrs), hipMemcpyHostToDevice, st));
-        LFMM_HIP(hipEventRecord(pl->exec_copied, st));
-        tab = pl->d_exec;
-    }
+// Enqueues the evaluation passes (Section 8.2) on st.  tab = per-instance load/potential
+// pointers on the device, or null with f1/u1 those of the single instance.
+void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double* u1, bool marks, hipStream_t st) {
     const bool mixed = pl->ctx->opt.precision == LFMM_MIXED;
     auto mark = [&](int k) {
-        if (pl->timing) LFMM_HIP(hipEventRecord(pl->ev[k], st));
+        if (marks) LFMM_HIP(hipEventRecord(pl->ev[k], st));
     };
     mark(0);
     launch_gather_f(tab, f1, pl->perm, pl->pinst, pl->n, pl->fs, st);
@@ -817,9 +841,9 @@ void run_forest(lfmm_plan* pl, const double* const* f, double* const* u, hipStre
     if (pl->m2l.n > 0) {
         if (mixed)
             launch_m2l_mixed(pl->tiles + pl->m2l.t0, pl->d_m2l_ntiles, pl->m2l.n, pl->cls_box, pl->il27, pl->d_ops,
-                             pl->Q, pl->U, st);
+                             pl->Q, pl->nbox, pl->U, st);
         else
-            launch_m2l(pl->tiles + pl->m2l.t0, pl->m2l.n, pl->cls_box, pl->il27, pl->d_ops, pl->Q, pl->U, st);
+            launch_m2l(pl->tiles + pl->m2l.t0, pl->m2l.n, pl->cls_box, pl->il27, pl->d_ops, pl->Q, pl->nbox, pl->U, st);
     }
     mark(4);
     for (int h = pl->Hmax; h >= 0; --h) {
@@ -836,7 +860,42 @@ void run_forest(lfmm_plan* pl, const double* const* f, double* const* u, hipStre
                     pl->U, pl->ops[o]->dev.leafT, pl->d_far, pl->ctx->phi_oct, st);
     }
     mark(6);
-    if (pl->timing) pl->timed_once = true;
+}
+
+void run_forest(lfmm_plan* pl, const double* const* f, double* const* u, hipStream_t st) {
+    if (pl->K == 1 && !pl->use_graph) {
+        enqueue_passes(pl, nullptr, f[0], u[0], pl->timing, st);
+        if (pl->timing) pl->timed_once = true;
+        return;
+    }
+    // the previous execute's copy must have read the staging buffer before it is rewritten
+    LFMM_HIP(hipEventSynchronize(pl->exec_copied));
+    for (int32_t k = 0; k < pl->K; ++k) pl->h_exec[k] = ExecPtrs{f[k], u[k]};
+    LFMM_HIP(hipMemcpyAsync(pl->d_exec, pl->h_exec, size_t(pl->K) * sizeof(ExecPtrs), hipMemcpyHostToDevice, st));
+    LFMM_HIP(hipEventRecord(pl->exec_copied, st));
+    if (!pl->use_graph) {
+        enqueue_passes(pl, pl->d_exec, nullptr, nullptr, pl->timing, st);
+        if (pl->timing) pl->timed_once = true;
+        return;
+    }
+    if (!pl->gexec) {
+        // record the passes once, on the context's capture stream (a capture cannot run on
+        // the legacy default stream), and replay them on st from then on
+        lfmm_ctx* ctx = pl->ctx;
+        if (!ctx->capture) LFMM_HIP(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+        LFMM_HIP(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+        try {
+            enqueue_passes(pl, pl->d_exec, nullptr, nullptr, false, ctx->capture);
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(ctx->capture, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        LFMM_HIP(hipStreamEndCapture(ctx->capture, &pl->graph));
+        LFMM_HIP(hipGraphInstantiate(&pl->gexec, pl->graph, nullptr, nullptr, 0));
+    }
+    LFMM_HIP(hipGraphLaunch(pl->gexec, st));
 }
 
 }  // namespace
@@ -867,8 +926,8 @@ lfmm_status guarded(F&& f) {
     }
 }
 
-lfmm_status create_forest(lfmm_ctx* ctx, int32_t K, const int64_t* sizes, const int32_t* const* xy, void* stream,
-                          lfmm_plan** out) {
+lfmm_status create_forest(lfmm_ctx* ctx, int32_t K, const int64_t* sizes, const int32_t* const* xy, int32_t max_leaf,
+                          void* stream, lfmm_plan** out) {
     if (!ctx || !out || !sizes || !xy || K < 1) return fail(LFMM_E_INVAL, "null argument or no instance");
     *out = nullptr;
     int64_t total = 0;
@@ -881,7 +940,7 @@ lfmm_status create_forest(lfmm_ctx* ctx, int32_t K, const int64_t* sizes, const 
         LFMM_HIP(hipSetDevice(ctx->device));
         auto pl = std::make_unique<lfmm_plan>();
         pl->ctx = ctx;
-        build_forest(pl.get(), K, sizes, xy, as_stream(stream));
+        build_forest(pl.get(), K, sizes, xy, max_leaf, as_stream(stream));
         *out = pl.release();
         return LFMM_OK;
     });
@@ -949,12 +1008,80 @@ lfmm_status lfmm_plan_create(lfmm_ctx* ctx, int64_t n, const int32_t* xy, void* 
     if (n < 1 || n > (int64_t(1) << 30)) return fail(LFMM_E_INVAL, "n must lie in [1, 2^30]");
     const int64_t sizes[1] = {n};
     const int32_t* ptrs[1] = {xy};
-    return create_forest(ctx, 1, sizes, ptrs, stream, out);
+    return create_forest(ctx, 1, sizes, ptrs, 0, stream, out);
 }
 
 lfmm_status lfmm_plan_create_batch(lfmm_ctx* ctx, int32_t n_inst, const int64_t* n_host,
                                    const int32_t* const* xy_dev, void* stream, lfmm_plan** out) {
-    return create_forest(ctx, n_inst, n_host, xy_dev, stream, out);
+    return create_forest(ctx, n_inst, n_host, xy_dev, 0, stream, out);
+}
+
+lfmm_status lfmm_autotune(lfmm_ctx* ctx, int64_t n, const int32_t* xy, int32_t n_cand, const int32_t* cand,
+                          int32_t objective, int32_t reps, void* stream, int32_t* best, double* ms) {
+    if (!ctx || !xy || !cand || !best || n_cand < 1 || reps < 1 || (objective != 0 && objective != 1))
+        return fail(LFMM_E_INVAL, "bad argument");
+    if (n < 1 || n > (int64_t(1) << 30)) return fail(LFMM_E_INVAL, "n must lie in [1, 2^30]");
+    for (int32_t c = 0; c < n_cand; ++c)
+        if (cand[c] < 1 || cand[c] > 4096) return fail(LFMM_E_INVAL, "candidates must lie in [1, 4096]");
+    return guarded([&]() -> lfmm_status {
+        LFMM_HIP(hipSetDevice(ctx->device));
+        hipStream_t st = as_stream(stream);
+        Arena io(&ctx->pool);
+        io.reserve(size_t(n) * sizeof(double));
+        io.reserve(size_t(n) * sizeof(double));
+        io.allocate();
+        double* f = io.take<double>(size_t(n));
+        double* u = io.take<double>(size_t(n));
+        LFMM_HIP(hipMemsetAsync(f, 0, size_t(n) * sizeof(double), st));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        LFMM_HIP(hipEventCreate(&e0));
+        LFMM_HIP(hipEventCreate(&e1));
+        struct Ev {
+            hipEvent_t a, b;
+            ~Ev() {
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+            }
+        } guard{e0, e1};
+        const int64_t sizes[1] = {n};
+        const int32_t* ptrs[1] = {xy};
+        double best_ms = 0.0;
+        int D = 0;
+        for (int32_t c = 0; c < n_cand; ++c) {
+            double total = 0.0;
+            for (int r = 0; r < reps + 1; ++r) {   // the first round warms the operator cache
+                LFMM_HIP(hipStreamSynchronize(st));
+                const auto t0 = std::chrono::steady_clock::now();
+                auto pl = std::make_unique<lfmm_plan>();
+                pl->ctx = ctx;
+                build_forest(pl.get(), 1, sizes, ptrs, cand[c], st);
+                const double build_ms =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                D = pl->inst[0].D;
+                const double* fa[1] = {f};
+                double* ua[1] = {u};
+                LFMM_HIP(hipEventRecord(e0, st));
+                run_forest(pl.get(), fa, ua, st);
+                LFMM_HIP(hipEventRecord(e1, st));
+                LFMM_HIP(hipEventSynchronize(e1));
+                float exec_ms = 0.f;
+                LFMM_HIP(hipEventElapsedTime(&exec_ms, e0, e1));
+                if (r > 0) total += (objective == 0 ? build_ms : 0.0) + double(exec_ms);
+            }
+            const double t = total / reps;
+            if (ms) ms[c] = t;
+            if (c == 0 || t < best_ms) {
+                best_ms = t;
+                *best = cand[c];
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lock(ctx->mu);
+            ctx->tuned[tune_key(n, D)] = *best;
+        }
+        LFMM_HIP(hipStreamSynchronize(st));
+        return LFMM_OK;
+    });
 }
 
 lfmm_status lfmm_execute(lfmm_plan* pl, const double* f, double* u, void* stream) {

@@ -20,14 +20,14 @@ lfmm_status fail(lfmm_status s, const std::string& msg) {
 
 lfmm_status validate_options(const lfmm_options* o) {
     if (!(o->eps > 0.0 && o->eps < 1e-2)) return fail(LFMM_E_INVAL, "eps must lie in (0, 1e-2)");
-    if (o->max_leaf < 1 || o->max_leaf > 4096) return fail(LFMM_E_INVAL, "max_leaf must lie in [1, 4096]");
+    if (o->max_leaf < 0 || o->max_leaf > 4096) return fail(LFMM_E_INVAL, "max_leaf must lie in [0, 4096]");
     if (o->precision != LFMM_FP64 && o->precision != LFMM_MIXED)
         return fail(LFMM_E_INVAL, "precision must be LFMM_FP64 or LFMM_MIXED");
     if (o->proxy_per_edge < 8 || o->proxy_per_edge > 4096)
         return fail(LFMM_E_INVAL, "proxy_per_edge must lie in [8, 4096]");
     if (o->max_rank < 16 || o->max_rank > kMaxRank || o->max_rank % 16 != 0)
         return fail(LFMM_E_INVAL, "max_rank must be 16, 32, 48 or 64");
-    if (o->flags != 0) return fail(LFMM_E_INVAL, "options.flags is reserved and must be 0");
+    if (o->flags & ~LFMM_FLAG_GRAPH) return fail(LFMM_E_INVAL, "unknown bits in options.flags");
     return LFMM_OK;
 }
 

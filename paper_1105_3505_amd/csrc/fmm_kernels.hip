@@ -26,10 +26,11 @@ constexpr double kEulerGamma = 0.57721566490153286061;
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef double double2_t __attribute__((ext_vector_type(2)));
 
 // Interaction-list slot k of a box in child position c lies at offset slot c_dslot[c][k]
 // of the 7 x 7 offset grid; the order matches the list builder (dy outer, dx inner).
-struct DSlots { int8_t s[4][kNumInteractions]; };
+struct DSlots { int s[4][kNumInteractions]; };
 __constant__ DSlots c_dslot;
 
 __device__ inline uint32_t compact_bits(uint64_t x) {
@@ -211,80 +212,114 @@ __global__ __launch_bounds__(kBlock) void k_boxmat(const BoxTile* tiles, int32_t
 // operator of each slot is stored in fragment order (lane l's operands of one instruction
 // next to lane l+1's), staged once per block in LDS with coalesced loads, double-buffered,
 // and read by all four waves; the next slot's operator and source expansions are loaded
-// while the current slot's instructions run.  One barrier per slot: the buffer a slot
-// writes was last read two slots earlier, before the previous slot's barrier.
+// into registers while the current slot's instructions run, and the list entry behind the
+// expansion read one slot before that.  One barrier per slot: the buffer a slot writes was
+// last read two slots earlier, before the previous slot's barrier.  Absent sources (empty
+// list slots, lanes past the tile) read the all-zero expansion row `zrow`.
 //
 // FP64: 16x16x4 instruction, step kk of row block m takes column g * 12 + kk in lane group
 // g = lane / 16; element i of lane (g, n) is row 16 m + g + 4 i, column n.
-template <int P>
+__device__ inline int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Pointers into global memory by address space, so that loads through them are global (not
+// flat) loads: flat loads also count as LDS operations, and waiting for the LDS reads of a
+// slot would then wait for the next slot's prefetch too.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <class T>
+__device__ inline gptr<T> global(const T* p) {
+    return (gptr<T>)(p);   // generic to global address space
+}
+
 __global__ __launch_bounds__(kBlock) void k_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list,
                                                  const int32_t* il27, const OpsPtrs* ops, const double* Q,
-                                                 double* U) {
-    constexpr int MT = P / 16, KQ = P / 4, NJ = KQ / 2;
-    constexpr int A2 = P * P / 2;                      // double2 per operator
-    constexpr int PER = (A2 + kBlock - 1) / kBlock;
-    __shared__ double2 sA[2][A2];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+                                                 int32_t zrow, double* U) {
+    constexpr int P = kRankPad, MT = P / 16, KQ = P / 4, NJ = KQ / 2;
+    constexpr int A2 = P * P / 2;                      // double2_t per operator: 4.5 per thread
+    static_assert(A2 == 4 * kBlock + kBlock / 2, "staging below assumes P = 48");
+    __shared__ double2_t sA[2][A2];
+    __shared__ int s_dsl[kNumInteractions];   // offset slot of each list slot of the tile's class
+    const int tid = int(threadIdx.x), wave = tid >> 6, lane = tid & 63;
     const int n = lane & 15, g = lane >> 4;
     const int32_t G = int32_t(gridDim.x);
+    const double2_t z2 = {0.0, 0.0};
     for (int32_t step = 0;; ++step) {
-        const int32_t t = xcd_tile(int32_t(blockIdx.x), G, step, ntiles);
-        if (t < 0) break;                                  // uniform over the block
-        const BoxTile tl = tiles[t];
-        if (tl.count == 0) continue;
-        const bool wave_on = 16 * wave < tl.count;        // uniform over the wave
+        const int32_t t = uniform(xcd_tile(int32_t(blockIdx.x), G, step, ntiles));
+        if (t < 0) break;
+        const int32_t count = uniform(tiles[t].count);
+        if (count == 0) continue;
+        const int32_t start = uniform(tiles[t].start), height = uniform(tiles[t].height);
+        const int32_t cls = uniform(tiles[t].cls), opi = uniform(tiles[t].ops);
+        const bool wave_on = 16 * wave < count;
         const int col = 16 * wave + n;
-        const int32_t box = (col < tl.count) ? box_list[tl.start + col] : -1;
-        const OpsPtrs& op = ops[tl.ops];
-        const double2* Ah = reinterpret_cast<const double2*>(op.ifo) + size_t(tl.height) * kNumIfoSlots * A2;
-        const int32_t* il = il27 + size_t(box >= 0 ? box : 0) * kNumInteractions;
-        double2 ra[PER], rb[NJ];
-        auto load_slot = [&](int k) {
-            const double2* A = Ah + size_t(c_dslot.s[tl.cls][k]) * A2;
-            #pragma unroll
-            for (int i = 0; i < PER; ++i) {
-                const int e = int(threadIdx.x) + i * kBlock;
-                if (e < A2) ra[i] = A[e];
-            }
-            const int32_t src = (box >= 0) ? il[k] : -1;
-            const double2* qs = reinterpret_cast<const double2*>(Q + size_t(src >= 0 ? src : 0) * P + g * KQ);
-            #pragma unroll
-            for (int j = 0; j < NJ; ++j) rb[j] = (src >= 0) ? qs[j] : double2{0.0, 0.0};
-        };
-        load_slot(0);
-        double4_t acc[MT];
-        #pragma unroll
-        for (int m = 0; m < MT; ++m) acc[m] = double4_t{0.0, 0.0, 0.0, 0.0};
+        const int32_t box = (col < count) ? box_list[start + col] : -1;
+        const gptr<int32_t> il = global(il27 + size_t(box >= 0 ? box : 0) * kNumInteractions);
+        const gptr<double2_t> Ah = global(reinterpret_cast<const double2_t*>(ops[opi].ifo)) +
+                                 size_t(height) * kNumIfoSlots * A2;
+        const gptr<double> Qg = global(Q) + g * KQ;
+        if (tid < kNumInteractions) s_dsl[tid] = c_dslot.s[cls][tid];
+        __syncthreads();
+        const int* dsl = s_dsl;
+        // slot 0 operands
+        int32_t src = (box >= 0) ? il[0] : -1;
+        src = src < 0 ? zrow : src;
+        const gptr<double2_t> qs = reinterpret_cast<gptr<double2_t>>(Qg + size_t(src) * P);
+        double2_t rb0 = qs[0], rb1 = qs[1], rb2 = qs[2], rb3 = qs[3], rb4 = qs[4], rb5 = qs[5];
+        int32_t src_next = (box >= 0) ? il[1] : -1;
+        const gptr<double2_t> Ak = Ah + size_t(dsl[0]) * A2;
+        double2_t ra0 = Ak[tid], ra1 = Ak[tid + kBlock], ra2 = Ak[tid + 2 * kBlock], ra3 = Ak[tid + 3 * kBlock];
+        double2_t ra4 = (tid < kBlock / 2) ? Ak[tid + 4 * kBlock] : z2;
+        double4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0;
         for (int k = 0; k < kNumInteractions; ++k) {
-            double2* buf = sA[k & 1];
-            #pragma unroll
-            for (int i = 0; i < PER; ++i) {
-                const int e = int(threadIdx.x) + i * kBlock;
-                if (e < A2) buf[e] = ra[i];
-            }
-            double2 b[NJ];
-            #pragma unroll
-            for (int j = 0; j < NJ; ++j) b[j] = rb[j];
+            double2_t* buf = sA[k & 1];
+            buf[tid] = ra0;
+            buf[tid + kBlock] = ra1;
+            buf[tid + 2 * kBlock] = ra2;
+            buf[tid + 3 * kBlock] = ra3;
+            if (tid < kBlock / 2) buf[tid + 4 * kBlock] = ra4;
+            const double2_t b[NJ] = {rb0, rb1, rb2, rb3, rb4, rb5};
             __syncthreads();
-            if (k + 1 < kNumInteractions) load_slot(k + 1);
+            if (k + 1 < kNumInteractions) {
+                // expansions first: their address waits only for the list entry read a slot ago
+                const int32_t sn = src_next < 0 ? zrow : src_next;
+                const gptr<double2_t> qn = reinterpret_cast<gptr<double2_t>>(Qg + size_t(sn) * P);
+                rb0 = qn[0];
+                rb1 = qn[1];
+                rb2 = qn[2];
+                rb3 = qn[3];
+                rb4 = qn[4];
+                rb5 = qn[5];
+                src_next = (box >= 0 && k + 2 < kNumInteractions) ? il[k + 2] : -1;
+                const gptr<double2_t> An = Ah + size_t(dsl[k + 1]) * A2;
+                ra0 = An[tid];
+                ra1 = An[tid + kBlock];
+                ra2 = An[tid + 2 * kBlock];
+                ra3 = An[tid + 3 * kBlock];
+                if (tid < kBlock / 2) ra4 = An[tid + 4 * kBlock];
+            }
             if (wave_on) {
                 #pragma unroll
-                for (int m = 0; m < MT; ++m) {
-                    #pragma unroll
-                    for (int j = 0; j < NJ; ++j) {
-                        const double2 a = buf[(m * NJ + j) * 64 + lane];
-                        acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[j].x, acc[m], 0, 0, 0);
-                        acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b[j].y, acc[m], 0, 0, 0);
-                    }
+                for (int j = 0; j < NJ; ++j) {
+                    const double2_t a0 = buf[(0 * NJ + j) * 64 + lane];
+                    const double2_t a1 = buf[(1 * NJ + j) * 64 + lane];
+                    const double2_t a2 = buf[(2 * NJ + j) * 64 + lane];
+                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, b[j].x, acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, b[j].x, acc1, 0, 0, 0);
+                    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2.x, b[j].x, acc2, 0, 0, 0);
+                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, b[j].y, acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, b[j].y, acc1, 0, 0, 0);
+                    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2.y, b[j].y, acc2, 0, 0, 0);
                 }
             }
         }
+        static_assert(MT == 3, "three row blocks");
         if (box >= 0) {
             double* ub = U + size_t(box) * P;
             #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                #pragma unroll
-                for (int i = 0; i < 4; ++i) ub[16 * m + g + 4 * i] = acc[m][i];
+            for (int i = 0; i < 4; ++i) {
+                ub[g + 4 * i] = acc0[i];
+                ub[16 + g + 4 * i] = acc1[i];
+                ub[32 + g + 4 * i] = acc2[i];
             }
         }
         __syncthreads();   // the next tile's first slot rewrites a buffer read above
@@ -295,86 +330,102 @@ __global__ __launch_bounds__(kBlock) void k_m2l(const BoxTile* tiles, int32_t nt
 // operator is written T^d = c_d 1 1^T + R^d with c_d its mean entry: the constant part,
 // which carries the large log|d| level of the kernel, is applied in FP64 as c_d times the
 // source's charge sum; only the remainder R^d, several times smaller, goes through FP32.
-// R^d and q-hat are split into FP32 hi + lo parts; each 16x16x4 step forms R_hi q_hi in one
+// R^d and q-hat are split into FP32 hi + lo parts; the products R_hi q_hi accumulate in one
 // FP32 accumulator and R_hi q_lo + R_lo q_hi in another (the cross terms are ~2^-24 of the
-// first and would be rounded away if added to it), and both are flushed into FP64
-// accumulators after every step, so FP32 rounding acts on four-term partial sums only.  The
+// first and would be rounded away if added to it), both over the 48 terms of one slot, then
+// flushed into FP64 accumulators, so FP32 rounding acts on one slot's partial sums only.  The
 // FP32 instruction returns element i of lane (g, n) as row 4 g + i.
-template <int P>
 __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_p,
                                                        const int32_t* box_list, const int32_t* il27,
-                                                       const OpsPtrs* ops, const double* Q, double* U) {
-    constexpr int MT = P / 16, KQ = P / 4, NJ = KQ / 2, NJ4 = KQ / 4;
-    constexpr int A4 = P * P / 4;                      // float4 per operator part
-    constexpr int PER = (A4 + kBlock - 1) / kBlock;
+                                                       const OpsPtrs* ops, const double* Q, int32_t zrow,
+                                                       double* U) {
+    constexpr int P = kRankPad, MT = P / 16, KQ = P / 4, NJ4 = KQ / 4;
+    constexpr int A4 = P * P / 4;                      // float4 per operator part: 2.25 per thread
+    static_assert(A4 == 2 * kBlock + kBlock / 4, "staging below assumes P = 48");
     __shared__ float4_t sH[2][A4];
     __shared__ float4_t sL[2][A4];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ int s_dsl[kNumInteractions];
+    const int tid = int(threadIdx.x), wave = tid >> 6, lane = tid & 63;
     const int n = lane & 15, g = lane >> 4;
-    const int32_t ntiles = *ntiles_p;
+    const int32_t ntiles = uniform(*ntiles_p);
     const int32_t G = int32_t(gridDim.x);
     const float4_t zero = {0.f, 0.f, 0.f, 0.f};
     for (int32_t step = 0;; ++step) {
-        const int32_t t = xcd_tile(int32_t(blockIdx.x), G, step, ntiles);
+        const int32_t t = uniform(xcd_tile(int32_t(blockIdx.x), G, step, ntiles));
         if (t < 0) break;
-        const BoxTile tl = tiles[t];
-        if (tl.count == 0) continue;
-        const bool wave_on = 16 * wave < tl.count;
+        const int32_t count = uniform(tiles[t].count);
+        if (count == 0) continue;
+        const int32_t start = uniform(tiles[t].start), height = uniform(tiles[t].height);
+        const int32_t cls = uniform(tiles[t].cls), opi = uniform(tiles[t].ops);
+        const bool wave_on = 16 * wave < count;
         const int col = 16 * wave + n;
-        const int32_t box = (col < tl.count) ? box_list[tl.start + col] : -1;
-        const OpsPtrs& op = ops[tl.ops];
-        const int rk = op.rank[tl.height];
-        const size_t hbase = size_t(tl.height) * kNumIfoSlots * A4;
-        const float4_t* Hh = reinterpret_cast<const float4_t*>(op.ifo_hi) + hbase;
-        const float4_t* Lh = reinterpret_cast<const float4_t*>(op.ifo_lo) + hbase;
-        const double* mono = op.mono + size_t(tl.height) * kNumIfoSlots;
-        const int32_t* il = il27 + size_t(box >= 0 ? box : 0) * kNumInteractions;
-        float4_t rh[PER], rl[PER];
-        double2 rb[NJ];
-        auto load_slot = [&](int k) {
-            const size_t off = size_t(c_dslot.s[tl.cls][k]) * A4;
-            #pragma unroll
-            for (int i = 0; i < PER; ++i) {
-                const int e = int(threadIdx.x) + i * kBlock;
-                if (e < A4) {
-                    rh[i] = Hh[off + e];
-                    rl[i] = Lh[off + e];
-                }
-            }
-            const int32_t src = (box >= 0) ? il[k] : -1;
-            const double2* qs = reinterpret_cast<const double2*>(Q + size_t(src >= 0 ? src : 0) * P + g * KQ);
-            #pragma unroll
-            for (int j = 0; j < NJ; ++j) rb[j] = (src >= 0) ? qs[j] : double2{0.0, 0.0};
-        };
-        load_slot(0);
+        const int32_t box = (col < count) ? box_list[start + col] : -1;
+        const int rk = ops[opi].rank[height];
+        const size_t hbase = size_t(height) * kNumIfoSlots * A4;
+        const gptr<float4_t> Hh = global(reinterpret_cast<const float4_t*>(ops[opi].ifo_hi)) + hbase;
+        const gptr<float4_t> Lh = global(reinterpret_cast<const float4_t*>(ops[opi].ifo_lo)) + hbase;
+        const gptr<double> mono = global(ops[opi].mono) + size_t(height) * kNumIfoSlots;
+        const gptr<int32_t> il = global(il27 + size_t(box >= 0 ? box : 0) * kNumInteractions);
+        const gptr<double> Qg = global(Q) + g * KQ;
+        if (tid < kNumInteractions) s_dsl[tid] = c_dslot.s[cls][tid];
+        __syncthreads();
+        const int* dsl = s_dsl;
+        int32_t src = (box >= 0) ? il[0] : -1;
+        src = src < 0 ? zrow : src;
+        const gptr<double2_t> qs = reinterpret_cast<gptr<double2_t>>(Qg + size_t(src) * P);
+        double2_t rb0 = qs[0], rb1 = qs[1], rb2 = qs[2], rb3 = qs[3], rb4 = qs[4], rb5 = qs[5];
+        int32_t src_next = (box >= 0) ? il[1] : -1;
+        size_t off = size_t(dsl[0]) * A4;
+        float4_t rh0 = Hh[off + tid], rh1 = Hh[off + tid + kBlock];
+        float4_t rl0 = Lh[off + tid], rl1 = Lh[off + tid + kBlock];
+        float4_t rh2 = (tid < kBlock / 4) ? Hh[off + tid + 2 * kBlock] : zero;
+        float4_t rl2 = (tid < kBlock / 4) ? Lh[off + tid + 2 * kBlock] : zero;
         double4_t acc[MT];
         #pragma unroll
         for (int m = 0; m < MT; ++m) acc[m] = double4_t{0.0, 0.0, 0.0, 0.0};
         for (int k = 0; k < kNumInteractions; ++k) {
             const int bsel = k & 1;
-            #pragma unroll
-            for (int i = 0; i < PER; ++i) {
-                const int e = int(threadIdx.x) + i * kBlock;
-                if (e < A4) {
-                    sH[bsel][e] = rh[i];
-                    sL[bsel][e] = rl[i];
+            sH[bsel][tid] = rh0;
+            sH[bsel][tid + kBlock] = rh1;
+            sL[bsel][tid] = rl0;
+            sL[bsel][tid + kBlock] = rl1;
+            if (tid < kBlock / 4) {
+                sH[bsel][tid + 2 * kBlock] = rh2;
+                sL[bsel][tid + 2 * kBlock] = rl2;
+            }
+            const double q[KQ] = {rb0.x, rb0.y, rb1.x, rb1.y, rb2.x, rb2.y,
+                                  rb3.x, rb3.y, rb4.x, rb4.y, rb5.x, rb5.y};
+            const int d = dsl[k];
+            __syncthreads();
+            if (k + 1 < kNumInteractions) {
+                const int32_t sn = src_next < 0 ? zrow : src_next;
+                const gptr<double2_t> qn = reinterpret_cast<gptr<double2_t>>(Qg + size_t(sn) * P);
+                rb0 = qn[0];
+                rb1 = qn[1];
+                rb2 = qn[2];
+                rb3 = qn[3];
+                rb4 = qn[4];
+                rb5 = qn[5];
+                src_next = (box >= 0 && k + 2 < kNumInteractions) ? il[k + 2] : -1;
+                off = size_t(dsl[k + 1]) * A4;
+                rh0 = Hh[off + tid];
+                rh1 = Hh[off + tid + kBlock];
+                rl0 = Lh[off + tid];
+                rl1 = Lh[off + tid + kBlock];
+                if (tid < kBlock / 4) {
+                    rh2 = Hh[off + tid + 2 * kBlock];
+                    rl2 = Lh[off + tid + 2 * kBlock];
                 }
             }
-            float bh[KQ], bl[KQ];
-            double qsum = 0.0;
-            #pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-                const double q0 = rb[j].x, q1 = rb[j].y;
-                qsum += q0 + q1;
-                bh[2 * j] = float(q0);
-                bl[2 * j] = float(q0 - double(bh[2 * j]));
-                bh[2 * j + 1] = float(q1);
-                bl[2 * j + 1] = float(q1 - double(bh[2 * j + 1]));
-            }
-            const int d = c_dslot.s[tl.cls][k];
-            __syncthreads();
-            if (k + 1 < kNumInteractions) load_slot(k + 1);
             if (wave_on) {
+                float bh[KQ], bl[KQ];
+                double qsum = 0.0;
+                #pragma unroll
+                for (int kk = 0; kk < KQ; ++kk) {
+                    qsum += q[kk];
+                    bh[kk] = float(q[kk]);
+                    bl[kk] = float(q[kk] - double(bh[kk]));
+                }
                 // charge sum of source column n: the four lane groups hold a quarter each
                 qsum += __shfl_xor(qsum, 16, 64);
                 qsum += __shfl_xor(qsum, 32, 64);
@@ -387,6 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, cons
                 }
                 #pragma unroll
                 for (int m = 0; m < MT; ++m) {
+                    float4_t mn = zero, cr = zero;
                     #pragma unroll
                     for (int j4 = 0; j4 < NJ4; ++j4) {
                         const float4_t ah = sH[bsel][(m * NJ4 + j4) * 64 + lane];
@@ -394,13 +446,13 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, cons
                         #pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             const int kk = 4 * j4 + e;
-                            const float4_t mn = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[e], bh[kk], zero, 0, 0, 0);
-                            float4_t cr = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[e], bl[kk], zero, 0, 0, 0);
+                            mn = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[e], bh[kk], mn, 0, 0, 0);
+                            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[e], bl[kk], cr, 0, 0, 0);
                             cr = __builtin_amdgcn_mfma_f32_16x16x4f32(al[e], bh[kk], cr, 0, 0, 0);
-                            #pragma unroll
-                            for (int i = 0; i < 4; ++i) acc[m][i] += double(mn[i]) + double(cr[i]);
                         }
                     }
+                    #pragma unroll
+                    for (int i = 0; i < 4; ++i) acc[m][i] += double(mn[i]) + double(cr[i]);
                 }
             }
         }
@@ -602,7 +654,7 @@ hipError_t upload_dslots() {
         for (int dy = -2 - cy; dy <= 3 - cy; ++dy)
             for (int dx = -2 - cx; dx <= 3 - cx; ++dx) {
                 if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
-                ds.s[c][k++] = int8_t((dy + 3) * 7 + (dx + 3));
+                ds.s[c][k++] = (dy + 3) * 7 + (dx + 3);
             }
     }
     // synchronous copy, then read back: the table steers every M2L product
@@ -646,21 +698,22 @@ void launch_boxmat(int mode, const BoxTile* tiles, int32_t tile0, const int32_t*
 }
 
 void launch_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, const int32_t* il27,
-                const OpsPtrs* ops, const double* Q, double* U, hipStream_t st) {
+                const OpsPtrs* ops, const double* Q, int32_t zrow, double* U, hipStream_t st) {
     if (ntiles <= 0) return;
     int64_t g = std::min<int64_t>(ntiles, 8192);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
-    hipLaunchKernelGGL(k_m2l<kRankPad>, dim3(static_cast<unsigned>(g)), dim3(kBlock), 0, st, tiles, ntiles, box_list,
-                       il27, ops, Q, U);
+    hipLaunchKernelGGL(k_m2l, dim3(static_cast<unsigned>(g)), dim3(kBlock), 0, st, tiles, ntiles, box_list, il27,
+                       ops, Q, zrow, U);
 }
 
 void launch_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t max_tiles, const int32_t* box_list,
-                      const int32_t* il27, const OpsPtrs* ops, const double* Q, double* U, hipStream_t st) {
+                      const int32_t* il27, const OpsPtrs* ops, const double* Q, int32_t zrow, double* U,
+                      hipStream_t st) {
     if (max_tiles <= 0) return;
     int64_t g = std::min<int64_t>(max_tiles, 8192);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
-    hipLaunchKernelGGL(k_m2l_mixed<kRankPad>, dim3(static_cast<unsigned>(g)), dim3(kBlock), 0, st, tiles, ntiles_dev,
-                       box_list, il27, ops, Q, U);
+    hipLaunchKernelGGL(k_m2l_mixed, dim3(static_cast<unsigned>(g)), dim3(kBlock), 0, st, tiles, ntiles_dev, box_list,
+                       il27, ops, Q, zrow, U);
 }
 
 void launch_leaf(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1, const uint64_t* box_key,

@@ -111,15 +111,15 @@ __global__ void k_bbox_chunks(const int2* xy, const Chunk* chunks, int32_t* part
     block_minmax4(v, part + size_t(blockIdx.x) * 4);
 }
 
-__global__ void k_bbox_final(const int32_t* part, const int32_t* chunk_first, int32_t K, int32_t* bbox) {
-    const int32_t k = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k >= K) return;
-    int r[4] = {INT_MAX, INT_MAX, INT_MIN, INT_MIN};
-    for (int32_t c = chunk_first[k]; c < chunk_first[k + 1]; ++c) {
-        r[0] = min(r[0], part[4 * c]); r[1] = min(r[1], part[4 * c + 1]);
-        r[2] = max(r[2], part[4 * c + 2]); r[3] = max(r[3], part[4 * c + 3]);
+// one block per instance: its chunks' partial boxes reduced by the block
+__global__ void k_bbox_final(const int32_t* part, const int32_t* chunk_first, int32_t* bbox) {
+    const int32_t k = int32_t(blockIdx.x);
+    int v[4] = {INT_MAX, INT_MAX, INT_MIN, INT_MIN};
+    for (int32_t c = chunk_first[k] + int32_t(threadIdx.x); c < chunk_first[k + 1]; c += kBlock) {
+        v[0] = min(v[0], part[4 * c]); v[1] = min(v[1], part[4 * c + 1]);
+        v[2] = max(v[2], part[4 * c + 2]); v[3] = max(v[3], part[4 * c + 3]);
     }
-    for (int q = 0; q < 4; ++q) bbox[4 * k + q] = r[q];
+    block_minmax4(v, bbox + size_t(k) * 4);
 }
 
 __global__ void k_keys(const int2* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst, int Dmax, int64_t n,
@@ -152,13 +152,14 @@ __global__ void k_gather_sorted(const uint64_t* keys, const uint32_t* vals, cons
 // (equal values of a wave are counted with ballots, one LDS add per distinct value), and the
 // levels shared with the point N_leaf positions ahead (a box of that level would hold more
 // than N_leaf points), reduced to one atomic per block.
-__global__ void k_level_stats(const uint64_t* keys, const Chunk* chunks, const InstInfo* inst, int Dmax, int nleaf,
+__global__ void k_level_stats(const uint64_t* keys, const Chunk* chunks, const InstInfo* inst, int Dmax,
                               int8_t* cl, int32_t* hist, int32_t* maxc) {
     __shared__ int32_t h[kMaxLevels + 2];
     __shared__ int32_t wmax[kBlock / 64];
     const Chunk c = chunks[blockIdx.x];
     const InstInfo& I = inst[c.inst];
     const int shift = Dmax - I.D;
+    const int nleaf = I.max_leaf;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (threadIdx.x < kMaxLevels + 2) h[threadIdx.x] = 0;
     __syncthreads();
@@ -277,10 +278,8 @@ __device__ inline int32_t child_at(int32_t x, int32_t y, int32_t px, int32_t py,
     return box_child[size_t(q) * 4 + (x & 1) + 2 * (y & 1)];
 }
 
-__global__ void k_lists_height(int32_t g0, int32_t g1, const uint64_t* box_key, const int32_t* box_parent,
-                               const int32_t* box_child, const int8_t* box_lev, int32_t* nb9, int32_t* il27) {
-    const int32_t g = g0 + int32_t(blockIdx.x * blockDim.x + threadIdx.x);
-    if (g >= g1) return;
+__device__ void list_box(int32_t g, const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_child,
+                         const int8_t* box_lev, int32_t* nb9, int32_t* il27) {
     const int lev = box_lev[g];
     int32_t* nl = nb9 + size_t(g) * 9;
     if (lev < 2) {   // no interaction list above level 2
@@ -313,6 +312,31 @@ __global__ void k_lists_height(int32_t g0, int32_t g1, const uint64_t* box_key, 
         }
 }
 
+__global__ void k_lists_height(int32_t g0, int32_t g1, const uint64_t* box_key, const int32_t* box_parent,
+                               const int32_t* box_child, const int8_t* box_lev, int32_t* nb9, int32_t* il27) {
+    const int32_t g = g0 + int32_t(blockIdx.x * blockDim.x + threadIdx.x);
+    if (g < g1) list_box(g, box_key, box_parent, box_child, box_lev, nb9, il27);
+}
+
+// The few boxes of the top heights in one block, height by height, so that a parent's
+// lists are complete before its children read them: height q of the block's list holds
+// boxes [start[q], end[q]).
+constexpr int kTopLists = 1024;
+struct HeightRanges {
+    int32_t nh;
+    int32_t start[kMaxLevels + 1], end[kMaxLevels + 1];
+};
+
+__global__ __launch_bounds__(kTopLists) void k_lists_top(HeightRanges hr, const uint64_t* box_key,
+                                                           const int32_t* box_parent, const int32_t* box_child,
+                                                           const int8_t* box_lev, int32_t* nb9, int32_t* il27) {
+    for (int q = 0; q < hr.nh; ++q) {
+        for (int32_t g = hr.start[q] + int32_t(threadIdx.x); g < hr.end[q]; g += kTopLists)
+            list_box(g, box_key, box_parent, box_child, box_lev, nb9, il27);
+        __syncthreads();   // orders the writes of this height before the next height's reads
+    }
+}
+
 __global__ void k_class_flags(const uint64_t* box_key, int64_t nbox, int32_t* flags) {
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= nbox) return;
@@ -338,31 +362,36 @@ __global__ void k_class_boxes(const BoxGroup* groups, int32_t ngroups, const int
     }
 }
 
-// one thread per (group, class): the tiles of that class, then empty tiles up to the cap
-__global__ void k_class_tiles(const BoxGroup* groups, int32_t ngroups, const int32_t* cscan, const int32_t* ctotal,
-                              int64_t nbox, BoxTile* tiles) {
-    const int32_t q = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (q >= ngroups) return;
-    const BoxGroup G = groups[q];
-    int32_t t = G.tile_base;
+// one thread per tile slot of the groups (group q owns slots [tile_base, tile_base + tile_cap),
+// groups in slot order): the tiles of class 0, 1, 2, 3 in turn, then empty tiles
+__global__ void k_class_tiles(const BoxGroup* groups, int32_t ngroups, int32_t nslots, const int32_t* cscan,
+                              const int32_t* ctotal, int64_t nbox, BoxTile* tiles) {
+    const int32_t t = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nslots) return;
+    int32_t lo = 0, hi = ngroups - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (groups[mid].tile_base <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const BoxGroup G = groups[lo];
+    int32_t r = t - G.tile_base;
+    BoxTile tl{};
+    tl.count = 0;
     for (int c = 0; c < 4; ++c) {
         const int32_t cnt = scan_at(cscan, ctotal, nbox, c, G.g1) - scan_at(cscan, ctotal, nbox, c, G.g0);
-        for (int32_t s = 0; s < cnt; s += G.tile_boxes) {
-            BoxTile tl;
+        const int32_t nt = (cnt + G.tile_boxes - 1) / G.tile_boxes;
+        if (r < nt) {
             tl.ops = G.ops;
             tl.height = G.height;
             tl.cls = c;
-            tl.start = G.cls_base + c * (G.g1 - G.g0) + s;
-            tl.count = min(G.tile_boxes, cnt - s);
-            tl.pad0 = tl.pad1 = tl.pad2 = 0;
-            tiles[t++] = tl;
+            tl.start = G.cls_base + c * (G.g1 - G.g0) + r * G.tile_boxes;
+            tl.count = min(G.tile_boxes, cnt - r * G.tile_boxes);
+            break;
         }
+        r -= nt;
     }
-    for (; t < G.tile_base + G.tile_cap; ++t) {
-        BoxTile tl{};
-        tl.count = 0;
-        tiles[t] = tl;
-    }
+    tiles[t] = tl;
 }
 
 __global__ void k_point_keys(const int2* pts, const int32_t* pinst, const InstInfo* inst, const OpsPtrs* ops,
@@ -563,7 +592,7 @@ void launch_bbox_chunks(const int32_t* xy, const Chunk* chunks, int32_t nchunks,
 }
 
 void launch_bbox_final(const int32_t* part, const int32_t* chunk_first, int32_t K, int32_t* bbox, hipStream_t st) {
-    hipLaunchKernelGGL(k_bbox_final, dim3(grid_for(K)), dim3(kBlock), 0, st, part, chunk_first, K, bbox);
+    hipLaunchKernelGGL(k_bbox_final, dim3(static_cast<unsigned>(K)), dim3(kBlock), 0, st, part, chunk_first, bbox);
 }
 
 void launch_keys(const int32_t* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst, int Dmax, int64_t n,
@@ -581,9 +610,9 @@ void launch_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int3
 }
 
 void launch_level_stats(const uint64_t* keys, const Chunk* chunks, int32_t nchunks, const InstInfo* inst, int Dmax,
-                        int nleaf, int8_t* cl, int32_t* hist, int32_t* maxc, hipStream_t st) {
-    hipLaunchKernelGGL(k_level_stats, dim3(unsigned(nchunks)), dim3(kBlock), 0, st, keys, chunks, inst, Dmax, nleaf,
-                       cl, hist, maxc);
+                        int8_t* cl, int32_t* hist, int32_t* maxc, hipStream_t st) {
+    hipLaunchKernelGGL(k_level_stats, dim3(unsigned(nchunks)), dim3(kBlock), 0, st, keys, chunks, inst, Dmax, cl, hist,
+                       maxc);
 }
 
 void launch_leaf_flags(const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int64_t n, int32_t* flags,
@@ -621,27 +650,42 @@ void launch_link_boxes(const uint64_t* box_key, const int32_t* box_parent, const
                        inst, nbox, box_pt0, box_child, box_pt1);
 }
 
-void launch_lists_height(int32_t g0, int32_t g1, const uint64_t* box_key, const int32_t* box_parent,
-                         const int32_t* box_child, const int8_t* box_lev, int32_t* nb9, int32_t* il27,
-                         hipStream_t st) {
-    if (g1 <= g0) return;
-    hipLaunchKernelGGL(k_lists_height, dim3(grid_for(g1 - g0)), dim3(kBlock), 0, st, g0, g1, box_key, box_parent,
-                       box_child, box_lev, nb9, il27);
+void launch_lists(const int32_t* hbase, int H, const uint64_t* box_key, const int32_t* box_parent,
+                  const int32_t* box_child, const int8_t* box_lev, int32_t* nb9, int32_t* il27, hipStream_t st) {
+    // the top heights, while together they hold at most 4096 boxes, in one block; the rest
+    // one launch per height, from the top down
+    const int32_t nbox = hbase[H + 1];
+    HeightRanges top{};
+    int h = H;
+    while (h >= 0 && nbox - hbase[h] <= 4 * kTopLists) {
+        top.start[top.nh] = hbase[h];
+        top.end[top.nh] = hbase[h + 1];
+        ++top.nh;
+        --h;
+    }
+    if (top.nh > 0)
+        hipLaunchKernelGGL(k_lists_top, dim3(1), dim3(kTopLists), 0, st, top, box_key, box_parent, box_child, box_lev,
+                           nb9, il27);
+    for (; h >= 0; --h) {
+        const int32_t g0 = hbase[h], g1 = hbase[h + 1];
+        if (g1 > g0)
+            hipLaunchKernelGGL(k_lists_height, dim3(grid_for(g1 - g0)), dim3(kBlock), 0, st, g0, g1, box_key,
+                               box_parent, box_child, box_lev, nb9, il27);
+    }
 }
 
 void launch_class_flags(const uint64_t* box_key, int64_t nbox, int32_t* flags, hipStream_t st) {
     hipLaunchKernelGGL(k_class_flags, dim3(grid_for(nbox)), dim3(kBlock), 0, st, box_key, nbox, flags);
 }
 
-void launch_class_lists(const BoxGroup* groups, int32_t ngroups, const int32_t* cscan, const int32_t* ctotal,
-                        const uint64_t* box_key, int64_t nbox, int32_t* cls_box, BoxTile* tiles, int32_t* tile_count,
-                        hipStream_t st) {
-    (void)tile_count;
+void launch_class_lists(const BoxGroup* groups, int32_t ngroups, int32_t nslots, const int32_t* cscan,
+                        const int32_t* ctotal, const uint64_t* box_key, int64_t nbox, int32_t* cls_box,
+                        BoxTile* tiles, hipStream_t st) {
     if (ngroups <= 0) return;
     hipLaunchKernelGGL(k_class_boxes, dim3(grid_for(nbox)), dim3(kBlock), 0, st, groups, ngroups, cscan, ctotal,
                        box_key, nbox, cls_box);
-    hipLaunchKernelGGL(k_class_tiles, dim3(grid_for(ngroups, 64)), dim3(64), 0, st, groups, ngroups, cscan, ctotal,
-                       nbox, tiles);
+    hipLaunchKernelGGL(k_class_tiles, dim3(grid_for(nslots)), dim3(kBlock), 0, st, groups, ngroups, nslots, cscan,
+                       ctotal, nbox, tiles);
 }
 
 void launch_point_keys(const int32_t* pts, const int32_t* pinst, const InstInfo* inst, const OpsPtrs* ops, int64_t n,

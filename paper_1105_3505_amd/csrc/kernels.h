@@ -32,6 +32,7 @@ struct InstInfo {                   // one instance of a forest
     int32_t D, L;                   // root box side 2^D, leaf level L
     int32_t ops;                    // operator set (leaf side)
     int32_t leaf_rank0;             // leaves of the instances before it (point order)
+    int32_t max_leaf;               // N_leaf of Section 6 for this instance
     int32_t lev_base[kMaxLevels];   // first box of level l
     int32_t lev_count[kMaxLevels];  // boxes of level l
 };
@@ -113,14 +114,14 @@ void launch_concat(int32_t K, const int32_t* const* xy_tab, const int32_t* pt_of
 void launch_bbox_chunks(const int32_t* xy, const Chunk* chunks, int32_t nchunks, int32_t* part,
                         hipStream_t st);
 void launch_bbox_final(const int32_t* part, const int32_t* chunk_first, int32_t K, int32_t* bbox,
-                       hipStream_t st);
+                       hipStream_t st);   // one block per instance
 void launch_keys(const int32_t* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst,
                  int Dmax, int64_t n, uint64_t* keys, uint32_t* vals, hipStream_t st);
 void launch_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int32_t* xy,
                           const InstInfo* inst, const int32_t* pt_off, int Dmax, int K, int64_t n,
                           int32_t* pts, int32_t* perm_local, int32_t* pinst, hipStream_t st);
 void launch_level_stats(const uint64_t* keys, const Chunk* chunks, int32_t nchunks,
-                        const InstInfo* inst, int Dmax, int nleaf, int8_t* cl, int32_t* hist,
+                        const InstInfo* inst, int Dmax, int8_t* cl, int32_t* hist,
                         int32_t* maxc, hipStream_t st);
 void launch_leaf_flags(const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int64_t n,
                        int32_t* flags, hipStream_t st);
@@ -139,15 +140,18 @@ void launch_link_boxes(const uint64_t* box_key, const int32_t* box_parent, const
                        const int8_t* box_lev, const InstInfo* inst, int64_t nbox,
                        const int32_t* box_pt0, int32_t* box_child, int32_t* box_pt1,
                        hipStream_t st);
-// neighbour (9 slots, every box) and interaction (27 slots, boxes of level >= 2) lists of the
-// boxes [g0, g1) of one height, from their parents' neighbour lists
-void launch_lists_height(int32_t g0, int32_t g1, const uint64_t* box_key, const int32_t* box_parent,
-                         const int32_t* box_child, const int8_t* box_lev, int32_t* nb9,
-                         int32_t* il27, hipStream_t st);
+// neighbour (9 slots, every box) and interaction (27 slots, boxes of level >= 2) lists of
+// every box, height by height from the top (hbase[h] = first box of height h, H + 2 entries),
+// each from its parent's neighbour list
+void launch_lists(const int32_t* hbase, int H, const uint64_t* box_key, const int32_t* box_parent,
+                  const int32_t* box_child, const int8_t* box_lev, int32_t* nb9, int32_t* il27,
+                  hipStream_t st);
 void launch_class_flags(const uint64_t* box_key, int64_t nbox, int32_t* flags, hipStream_t st);
-void launch_class_lists(const BoxGroup* groups, int32_t ngroups, const int32_t* cscan,
+// class lists (boxes of each group sorted by child position) and the tiles over them;
+// nslots = tile slots of all groups
+void launch_class_lists(const BoxGroup* groups, int32_t ngroups, int32_t nslots, const int32_t* cscan,
                         const int32_t* ctotal, const uint64_t* box_key, int64_t nbox,
-                        int32_t* cls_box, BoxTile* tiles, int32_t* tile_count, hipStream_t st);
+                        int32_t* cls_box, BoxTile* tiles, hipStream_t st);
 void launch_point_keys(const int32_t* pts, const int32_t* pinst, const InstInfo* inst,
                        const OpsPtrs* ops, int64_t n, uint32_t* key, hipStream_t st);
 
@@ -161,11 +165,12 @@ void launch_boxmat(int mode, const BoxTile* tiles, int32_t tile0, const int32_t*
                    int32_t ntiles_host, int32_t max_tiles, const int32_t* box_list,
                    const int32_t* src, const OpsPtrs* ops, const double* in, double* out,
                    hipStream_t st);
+// M2L over the class-sorted tiles; Q row zrow is all zeros (read for absent sources)
 void launch_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, const int32_t* il27,
-                const OpsPtrs* ops, const double* Q, double* U, hipStream_t st);
+                const OpsPtrs* ops, const double* Q, int32_t zrow, double* U, hipStream_t st);
 void launch_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t max_tiles,
                       const int32_t* box_list, const int32_t* il27, const OpsPtrs* ops,
-                      const double* Q, double* U, hipStream_t st);
+                      const double* Q, int32_t zrow, double* U, hipStream_t st);
 void launch_leaf(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1,
                  const uint64_t* box_key, const int32_t* box_inst, const int32_t* nb9,
                  int64_t side, const int32_t* pts, const uint32_t* pkey, const double* fs,

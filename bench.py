@@ -56,7 +56,23 @@ WORKLOADS = {
 TOLERANCE = {"fp64": 1e-10, "mixed": 1e-7}
 
 
-def roofline(phases: dict, info: dict, n: int, precision: str) -> dict:
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary of this workload, or None when there is none or the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    sys.path.insert(0, os.path.join(ROOT, "paper_1105_3505_amd"))
+    from profile_summary import kernel_sources_hash
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("sources_sha256") != kernel_sources_hash():
+        return None
+    entry = t["per_dispatch"].get(kernel)
+    return None if entry is None else entry["bytes"]
+
+
+def roofline(phases: dict, info: dict, n: int, precision: str, workload: str) -> dict:
     """Roofline entry for the phase that takes the longest (HIP events on the execute stream)."""
     dom = max(phases, key=phases.get)
     sec = phases[dom] * 1e-3
@@ -64,16 +80,18 @@ def roofline(phases: dict, info: dict, n: int, precision: str) -> dict:
         flops = 2.0 * RANK * RANK * info["m2l_pairs"]
         achieved = flops / sec / 1e12
         peak = PEAK_FP64_TFLOPS if precision == "fp64" else PEAK_FP32_TFLOPS
-        return {"kernel": "k_boxmat M2L (FP64 MFMA)" if precision == "fp64" else "k_m2l_mixed (FP32 MFMA)",
-                "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "work_per_launch": flops,
+        kernel = "k_m2l" if precision == "fp64" else "k_m2l_mixed"
+        return {"kernel": kernel, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": measured_traffic(workload, kernel), "work_per_launch": flops,
                 "work_definition": "2 P^2 flops per interaction-list pair, P = 48"}
     if dom == "leaf":
         flops = 2.0 * info["near_pairs"] + 2.0 * RANK * n
         achieved = flops / sec / 1e12
-        return {"kernel": "k_leaf (near field + L2P)", "bound": "alu", "achieved": achieved,
+        side = info["leaf_side"]
+        kernel = "k_near<48, %d>" % (0 if side <= 16 else (1 if side <= 32 else 2))
+        return {"kernel": kernel, "bound": "alu", "achieved": achieved,
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                "traffic": None, "work_per_launch": flops,
+                "traffic": measured_traffic(workload, kernel), "work_per_launch": flops,
                 "work_definition": "one FP64 FMA per near pair plus 2P flops of L2P per target",
                 "pairs_per_s": info["near_pairs"] / sec}
     return {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -166,7 +184,8 @@ def run_single(args, torch, lf):
     result = base_result(args, value, ms_per_step, config)
     result.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                    "execute_only_ms": exec_ms, "execute_only_msources_per_s": n / (exec_ms * 1e-3) / 1e6,
-                   "phase_ms": avg, "plan": info, "roofline": roofline(avg, info, n, args.precision)})
+                   "phase_ms": avg, "plan": info,
+                   "roofline": roofline(avg, info, n, args.precision, args.workload)})
     if not args.no_cpu_baseline:
         err, k, base = cpu_baseline(xy, f, u, args.cpu_targets)
         result["rel_err_vs_oracle"] = err
@@ -225,7 +244,8 @@ def run_batched(args, torch, lf):
     result = base_result(args, n / (ms_per_step * 1e-3) / 1e6, ms_per_step, config)
     result.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                    "execute_only_ms": exec_ms, "execute_only_msources_per_s": n / (exec_ms * 1e-3) / 1e6,
-                   "phase_ms": avg, "plan": info, "roofline": roofline(avg, info, n, args.precision)})
+                   "phase_ms": avg, "plan": info,
+                   "roofline": roofline(avg, info, n, args.precision, "batched")})
     if not args.no_cpu_baseline:
         # accuracy on 100 sampled targets of every 8th instance; CPU rate over that sample
         from oracle import direct as od

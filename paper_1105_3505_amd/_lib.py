@@ -56,6 +56,10 @@ def library_path() -> str:
 def _load():
     if not os.path.exists(_LIB_PATH):
         raise ImportError("liblfmm.so is not built; run `python paper_1105_3505_amd/build.py`")
+    # PyTorch ships its own HIP runtime.  Load it first, so that the library binds to that
+    # same runtime (it is looked up by its soname): loaded the other way round, the process
+    # would hold two HIP runtimes and the library would see no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(_LIB_PATH)
     sig = {
         "lfmm_options_init": [_vp],

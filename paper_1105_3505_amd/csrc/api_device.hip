@@ -193,9 +193,14 @@ struct lfmm_ctx {
     std::vector<std::unique_ptr<CachedOps>> all_ops;  // every set built; plans may hold any
     std::map<std::pair<int, int>, int32_t> tuned;     // (size class, density class) -> N_leaf
     hipStream_t capture = nullptr;                    // stream that graph captures record on
+    hipStream_t aux = nullptr;                        // second stream of plan construction
+    hipEvent_t fork = nullptr, join = nullptr;
     std::mutex mu;
     ~lfmm_ctx() {
         if (capture) (void)hipStreamDestroy(capture);
+        if (aux) (void)hipStreamDestroy(aux);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
     }
 };
 
@@ -227,6 +232,8 @@ struct lfmm_plan {
     int32_t nbox = 0, nleaf = 0;
     std::vector<int32_t> hbase;             // first box of each height, Hmax + 2 entries
     std::vector<TileRange> leaf_of_ops;     // leaves of each operator set
+    std::vector<TileRange> near_of_ops;     // near-field groups of each operator set
+    int32_t nq = 0;
     TileRange m2l;                          // M2L tiles (class-sorted, some empty)
     std::vector<TileRange> m2m, l2l;        // tiles per height
     int64_t m2l_pairs = 0;
@@ -244,6 +251,8 @@ struct lfmm_plan {
             *box_inst = nullptr, *nb9 = nullptr, *il27 = nullptr, *cls_box = nullptr;
     int8_t* box_lev = nullptr;
     BoxTile* tiles = nullptr;
+    NearGroup* groups = nullptr;
+    int4* ents = nullptr;
     double *Q = nullptr, *U = nullptr;
     ExecPtrs* h_exec = nullptr;             // pinned staging of the per-execute pointers
     size_t h_exec_cls = 0;
@@ -416,10 +425,56 @@ OpsPtrs ops_ptrs(const CachedOps* co) {
     return p;
 }
 
-template <class T>
-void upload(T* dst, const std::vector<T>& src, hipStream_t st) {
-    if (!src.empty()) LFMM_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
-}
+// Host-to-device copies of small tables, gathered so that tables that lie next to each other
+// in device memory (less than one 256-byte alignment step apart, so that nothing else lies
+// between them) go in one copy from pinned memory: a copy from pageable memory costs several
+// microseconds however small it is.  The pinned blocks are held until the Stager is
+// destroyed, which must come after the stream has passed the copies.
+class Stager {
+  public:
+    explicit Stager(lfmm_ctx* ctx) : ctx_(ctx) {}
+    Stager(const Stager&) = delete;
+    Stager& operator=(const Stager&) = delete;
+    template <class T>
+    void add(T* dst, const std::vector<T>& v) {
+        if (v.empty()) return;
+        const char* b = reinterpret_cast<const char*>(v.data());
+        pieces_.push_back(Piece{reinterpret_cast<char*>(dst), std::vector<char>(b, b + v.size() * sizeof(T))});
+    }
+    void flush(hipStream_t st) {
+        std::sort(pieces_.begin(), pieces_.end(), [](const Piece& a, const Piece& b) { return a.dst < b.dst; });
+        size_t i = 0;
+        while (i < pieces_.size()) {
+            size_t j = i + 1;
+            char* end = pieces_[i].dst + pieces_[i].data.size();
+            while (j < pieces_.size() && pieces_[j].dst >= end && pieces_[j].dst - end < 256) {
+                end = pieces_[j].dst + pieces_[j].data.size();
+                ++j;
+            }
+            const size_t len = size_t(end - pieces_[i].dst);
+            size_t cls = 0;
+            char* h = static_cast<char*>(ctx_->pinned.acquire(len, &cls));
+            held_.push_back({h, cls});
+            for (size_t k = i; k < j; ++k)
+                std::memcpy(h + (pieces_[k].dst - pieces_[i].dst), pieces_[k].data.data(), pieces_[k].data.size());
+            LFMM_HIP(hipMemcpyAsync(pieces_[i].dst, h, len, hipMemcpyHostToDevice, st));
+            i = j;
+        }
+        pieces_.clear();
+    }
+    ~Stager() {
+        for (auto& b : held_) ctx_->pinned.release(b.first, b.second);
+    }
+
+  private:
+    struct Piece {
+        char* dst;
+        std::vector<char> data;
+    };
+    lfmm_ctx* ctx_;
+    std::vector<Piece> pieces_;
+    std::vector<std::pair<void*, size_t>> held_;
+};
 
 // Builds the forest of K point sets: Section 6 tree of every instance, lists of Definition 6.1,
 // operator sets for every leaf side used, and the tiles of the matrix passes.
@@ -484,10 +539,12 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     void* sscr = tmp.take<char>(scan_scratch_bytes(n, 1));
 
     std::vector<const int32_t*> xytab(xy_ptrs, xy_ptrs + K);
-    upload(d_xytab, xytab, st);
-    upload(d_ptoff, pl->pt_off, st);
-    upload(d_chunks, chunks, st);
-    upload(d_chfirst, chunk_first, st);
+    Stager stage_a(ctx);
+    stage_a.add(d_xytab, xytab);
+    stage_a.add(d_ptoff, pl->pt_off);
+    stage_a.add(d_chunks, chunks);
+    stage_a.add(d_chfirst, chunk_first);
+    stage_a.flush(st);
     const int32_t* xy = xy_ptrs[0];
     if (K > 1) {
         launch_concat(K, d_xytab, d_ptoff, n, d_xyc, st);
@@ -531,17 +588,18 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     // plan storage sized by K and n
     Arena& ms = pl->mem_small;
     ms.set_pool(&ctx->pool);
+    // the tables uploaded together at the end of the build are taken next to each other
     ms.reserve(size_t(K) * sizeof(InstInfo));
     ms.reserve(size_t(64) * sizeof(OpsPtrs));
     ms.reserve(size_t(K));                      // far flags
-    ms.reserve(size_t(K) * sizeof(ExecPtrs));
     ms.reserve(16);                             // M2L tile count
+    ms.reserve(size_t(K) * sizeof(ExecPtrs));
     ms.allocate();
     pl->d_inst = ms.take<InstInfo>(K);
     pl->d_ops = ms.take<OpsPtrs>(64);
     pl->d_far = ms.take<uint8_t>(K);
-    pl->d_exec = ms.take<ExecPtrs>(K);
     pl->d_m2l_ntiles = ms.take<int32_t>(4);
+    pl->d_exec = ms.take<ExecPtrs>(K);
     Arena& mp = pl->mem_pts;
     mp.set_pool(&ctx->pool);
     mp.reserve(size_t(n) * 8);                  // pts
@@ -555,7 +613,9 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     pl->pinst = mp.take<int32_t>(n);
     pl->pkey = mp.take<uint32_t>(n);
     pl->fs = mp.take<double>(n);
-    upload(pl->d_inst, pl->inst, st);
+    Stager stage_b(ctx);
+    stage_b.add(pl->d_inst, pl->inst);
+    stage_b.flush(st);
 
     // ---- Morton order ----------------------------------------------------------------------
     launch_keys(xy, d_ptoff, K, pl->d_inst, Dmax, n, keys, vals, st);
@@ -659,6 +719,29 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
         range_of(0, int(o), 0, g0, g1);
         if (g0 >= 0) pl->leaf_of_ops[o] = TileRange{g0, g1 - g0};
     }
+    // near-field groups per operator set: the children of its height-1 boxes, then its roots
+    // that are leaves (instances of one leaf)
+    pl->near_of_ops.assign(side_of.size(), TileRange{});
+    std::vector<int32_t> h1_start(side_of.size(), 0), h1_count(side_of.size(), 0);
+    std::vector<std::vector<int32_t>> roots(side_of.size());
+    for (int32_t k : order) {
+        const InstInfo& I = pl->inst[size_t(k)];
+        if (I.L == 0) roots[size_t(I.ops)].push_back(I.lev_base[0]);
+    }
+    std::vector<int32_t> root_list;
+    std::vector<int32_t> root_off(side_of.size(), 0);
+    for (size_t o = 0; o < side_of.size(); ++o) {
+        int32_t g0, g1;
+        range_of(1, int(o), 0, g0, g1);
+        if (g0 >= 0) {
+            h1_start[o] = g0;
+            h1_count[o] = g1 - g0;
+        }
+        root_off[o] = int32_t(root_list.size());
+        root_list.insert(root_list.end(), roots[o].begin(), roots[o].end());
+        pl->near_of_ops[o] = TileRange{pl->nq, h1_count[o] + int32_t(roots[o].size())};
+        pl->nq += pl->near_of_ops[o].n;
+    }
     // groups for the class-sorted passes and the M2M tiles
     std::vector<BoxGroup> m2l_groups, l2l_groups;
     std::vector<BoxTile> m2m_tiles;
@@ -718,6 +801,9 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     mb.reserve(size_t(std::max(tile_slots, 1)) * sizeof(BoxTile));
     mb.reserve(size_t(std::max<size_t>(m2l_groups.size() + l2l_groups.size(), 1)) * sizeof(BoxGroup));
     mb.reserve(size_t(nb + 1) * P * 8);                  // Q and its zero row
+    mb.reserve(size_t(std::max(pl->nq, 1)) * sizeof(NearGroup));
+    mb.reserve(size_t(std::max(pl->nq, 1)) * kNearEntries * sizeof(int4));
+    mb.reserve(std::max<size_t>(root_list.size(), 1) * sizeof(int32_t));
     mb.reserve(size_t(nb) * P * 8);                      // U
     mb.allocate();
     pl->box_key = mb.take<uint64_t>(nb);
@@ -735,25 +821,29 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     BoxGroup* d_groups = mb.take<BoxGroup>(std::max<size_t>(m2l_groups.size() + l2l_groups.size(), 1));
     pl->Q = mb.take<double>(size_t(nb + 1) * P);
     pl->U = mb.take<double>(size_t(nb) * P);
+    pl->groups = mb.take<NearGroup>(size_t(std::max(pl->nq, 1)));
+    pl->ents = mb.take<int4>(size_t(std::max(pl->nq, 1)) * kNearEntries);
+    int32_t* d_roots = mb.take<int32_t>(std::max<size_t>(root_list.size(), 1));
+    Stager stage_c(ctx);
+    stage_c.add(d_roots, root_list);
     // row nb of Q stays zero: the M2L kernels read it for empty list slots
     LFMM_HIP(hipMemsetAsync(pl->Q + size_t(nb) * P, 0, size_t(P) * sizeof(double), st));
 
     // ---- tables ---------------------------------------------------------------------------------
-    upload(pl->d_inst, pl->inst, st);
+    stage_c.add(pl->d_inst, pl->inst);
     std::vector<OpsPtrs> optab;
     for (CachedOps* co : pl->ops) optab.push_back(ops_ptrs(co));
-    upload(pl->d_ops, optab, st);
+    stage_c.add(pl->d_ops, optab);
     std::vector<uint8_t> far(static_cast<size_t>(K));
     for (int32_t k = 0; k < K; ++k) far[size_t(k)] = pl->inst[size_t(k)].L >= 2 ? 1 : 0;
-    upload(pl->d_far, far, st);
+    stage_c.add(pl->d_far, far);
     std::vector<BoxGroup> groups = m2l_groups;
     groups.insert(groups.end(), l2l_groups.begin(), l2l_groups.end());
-    upload(d_groups, groups, st);
-    if (!m2m_tiles.empty())
-        LFMM_HIP(hipMemcpyAsync(pl->tiles + m2m_base, m2m_tiles.data(), m2m_tiles.size() * sizeof(BoxTile),
-                                hipMemcpyHostToDevice, st));
+    stage_c.add(d_groups, groups);
+    stage_c.add(pl->tiles + m2m_base, m2m_tiles);
     std::vector<int32_t> m2l_n{pl->m2l.n};
-    upload(pl->d_m2l_ntiles, m2l_n, st);
+    stage_c.add(pl->d_m2l_ntiles, m2l_n);
+    stage_c.flush(st);
 
     // ---- leaves ---------------------------------------------------------------------------------
     Arena tmp2(&ctx->pool);
@@ -794,14 +884,29 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
                        pl->box_parent, pl->box_child, pl->box_inst, pl->box_lev, st);
     launch_link_boxes(pl->box_key, pl->box_parent, pl->box_inst, pl->box_lev, pl->d_inst, nb, pl->box_pt0,
                       pl->box_child, pl->box_pt1, st);
+    // the lists (one launch per height, each short) run on a second stream beside the class
+    // lists and tiles, which need only the boxes
+    if (!ctx->aux) {
+        LFMM_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+        LFMM_HIP(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+        LFMM_HIP(hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));
+    }
+    LFMM_HIP(hipEventRecord(ctx->fork, st));
+    LFMM_HIP(hipStreamWaitEvent(ctx->aux, ctx->fork, 0));
     launch_lists(pl->hbase.data(), H, pl->box_key, pl->box_parent, pl->box_child, pl->box_lev, pl->nb9, pl->il27,
-                 st);
+                 ctx->aux);
+    for (size_t o = 0; o < side_of.size(); ++o)   // groups need the leaves' neighbour lists
+        launch_near_groups(pl->near_of_ops[o].t0, h1_start[o], h1_count[o], d_roots + root_off[o],
+                           int32_t(roots[o].size()), pl->box_child, pl->nb9, pl->box_pt0, pl->box_pt1, pl->box_key,
+                           pl->groups, pl->ents, ctx->aux);
+    LFMM_HIP(hipEventRecord(ctx->join, ctx->aux));
     launch_class_flags(pl->box_key, nb, cflags, st);
     scan_rows(cflags, cscan, nb, 4, ctotal, cscr, st);
     launch_class_lists(d_groups, int32_t(groups.size()), m2m_base, cscan, ctotal, pl->box_key, nb, pl->cls_box,
                        pl->tiles, st);
     if (std::any_of(side_of.begin(), side_of.end(), [](int64_t s) { return s <= 16; }))
         launch_point_keys(pl->pts, pl->pinst, pl->d_inst, pl->d_ops, n, pl->pkey, st);
+    LFMM_HIP(hipStreamWaitEvent(st, ctx->join, 0));
     LFMM_HIP(hipGetLastError());
     // staging for the per-execute pointer table of batched plans (and of graph replays,
     // whose kernels always read the table)
@@ -854,10 +959,10 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
     }
     mark(5);
     for (size_t o = 0; o < pl->ops.size(); ++o) {
-        const TileRange& r = pl->leaf_of_ops[o];
-        launch_leaf(r.t0, r.t0 + r.n, pl->box_pt0, pl->box_pt1, pl->box_key, pl->box_inst, pl->nb9,
-                    pl->ops[o]->dev.leaf_side, pl->pts, pl->pkey, pl->fs, pl->perm, pl->pinst, pl->d_inst, tab, u1,
-                    pl->U, pl->ops[o]->dev.leafT, pl->d_far, pl->ctx->phi_oct, st);
+        const TileRange& r = pl->near_of_ops[o];
+        launch_near(r.t0, r.t0 + r.n, pl->groups, pl->ents, pl->box_pt0, pl->box_pt1, pl->box_key, pl->box_inst,
+                    pl->ops[o]->dev.leaf_side, pl->pts, pl->pkey, pl->fs, pl->perm, tab, u1, pl->U,
+                    pl->ops[o]->dev.leafT, pl->d_far, pl->ctx->phi_oct, st);
     }
     mark(6);
 }

@@ -27,6 +27,8 @@ constexpr double kEulerGamma = 0.57721566490153286061;
 typedef double double4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef double double2_t __attribute__((ext_vector_type(2)));
+typedef int int2_t __attribute__((ext_vector_type(2)));
+typedef int int4_t __attribute__((ext_vector_type(4)));
 
 // Interaction-list slot k of a box in child position c lies at offset slot c_dslot[c][k]
 // of the 7 x 7 offset grid; the order matches the list builder (dy outer, dx inner).
@@ -470,47 +472,161 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, cons
 
 // Leaf pass: far field T_tfi u-hat with T_tfi = T_ofs^T (Section 7, symmetric kernel and
 // targets = sources) plus the direct sum over the points of the leaf and its neighbours
-// (Section 8.2 step 5), written back in the caller's point order.  A wave takes one leaf at
-// a time; the points of the 9 leaves around it are staged once into the wave's part of LDS,
-// and the 64 lanes are split into S slices of T lanes (T = targets per pass, a power of two),
-// slice s summing sources s, s + S, ...; slices are reduced with xor shuffles.
+// (Section 8.2 step 5), written back in the caller's point order.
+//
+// A wave takes one group: the (up to four) leaves of one parent box, whose targets are one
+// contiguous run of Morton-ordered points, one target per lane.  The sources are the points
+// of the union of the leaves' neighbourhoods (a 4 x 4 block of leaves at most), listed per
+// group at plan time as point ranges with their leaf coordinates.  The wave walks those
+// ranges in lockstep: range and source reads are uniform over the wave (scalar loads), and a
+// lane adds a range's sources only if that leaf neighbours its own leaf.
 //   WINDOW (side <= 16): phi sits in a window table over all offsets in [-(2s-1), 2s-1]^2 and
 //     each point carries the key K = 8 (y W + x) mod 2^32 (W = 4s - 1), so the byte offset of
 //     phi(x_i - x_j) is K_i - K_j plus a constant: one subtraction per pair.
 //   QUAD (side 32): a table over |dx|, |dy| < 64.
 //   GLOBAL (side >= 64): the octant table of radius 128 in global memory, eq. (3.1) beyond.
-constexpr int kLeafBlock = 512;
-constexpr int kLeafWaves = kLeafBlock / 64;
-constexpr int kStage = 192;   // staged sources per wave and pass
+constexpr int kNearBlock = 256;
+constexpr int kNearWaves = kNearBlock / 64;
 enum LeafMode { kWindow = 0, kQuad = 1, kGlobal = 2 };
 
-struct SrcRec {
-    uint32_t a, b;   // window mode: a = key; otherwise a = x, b = y
-    double f;
-};
+// read-only data that every lane of a wave reads at the same address: constant address
+// space, so that uniform reads become scalar loads
+template <class T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <class T>
+__device__ inline cptr<T> as_const(const T* p) {
+    return (cptr<T>)(p);   // generic to constant address space
+}
 
-__device__ inline void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// One group of leaves (see k_near).
+//   SLICED = false (groups of more than 32 targets): one target per lane over the whole group,
+//     sources read at wave-uniform addresses (scalar loads); a lane adds a range's sources only
+//     if that range's leaf neighbours its own leaf.
+//   SLICED = true (groups of at most 32 targets): leaf by leaf; the n targets of a leaf take T lanes each
+//     (T = the power of two at or above n, at most 64) of S = 64 / T slices, slice s summing
+//     every S-th source of each neighbouring range, and the slices are added by xor shuffles.
+template <int P, int MODE, bool SLICED>
+__device__ inline void near_group(int32_t qq, const NearGroup* groups, const int4* ents, const int32_t* box_pt0,
+                                  const int32_t* box_pt1, const uint64_t* box_key, const int32_t* box_inst,
+                                  int64_t side, int W, const double* tab, const char* tb, const int2* pts,
+                                  const uint32_t* pkey, const double* fs, const int32_t* perm_local,
+                                  const ExecPtrs* tab_ptrs, double* u_single, const double* U, const double* leafT,
+                                  const uint8_t* far_inst, const double* phi_oct_tab) {
+    const int lane = threadIdx.x & 63;
+    const cptr<int4_t> E = as_const(reinterpret_cast<const int4_t*>(ents));
+    const cptr<uint32_t> SK = as_const(pkey);
+    const cptr<double> SF = as_const(fs);
+    const cptr<int2_t> SP = as_const(reinterpret_cast<const int2_t*>(pts));
+    const int32_t leaf0 = uniform(groups[qq].leaf0), nleaf = uniform(groups[qq].nleaf);
+    const int32_t ne = uniform(groups[qq].ne);
+    // first point of each leaf of the group (uniform) and the end of the last
+    int32_t bnd[5];
+    bnd[0] = uniform(box_pt0[leaf0]);
+    bnd[1] = nleaf > 1 ? uniform(box_pt0[leaf0 + 1]) : bnd[0];
+    bnd[2] = nleaf > 2 ? uniform(box_pt0[leaf0 + 2]) : bnd[0];
+    bnd[3] = nleaf > 3 ? uniform(box_pt0[leaf0 + 3]) : bnd[0];
+    const int32_t t_end = uniform(box_pt1[leaf0 + nleaf - 1]);
+    bnd[nleaf] = t_end;
+    const int32_t k_inst = uniform(box_inst[leaf0]);
+    const bool far = far_inst[k_inst] != 0;
+    double* u = tab_ptrs ? tab_ptrs[k_inst].u : u_single;
+    // passes: the whole group once (group mode) or each leaf in turn (sliced mode)
+    for (int c0 = 0; c0 < (SLICED ? nleaf : 1); ++c0) {
+        const int32_t p0 = SLICED ? bnd[c0] : bnd[0];
+        const int32_t p1 = SLICED ? bnd[c0 + 1] : t_end;
+        int T = 64;
+        if (SLICED) {
+            T = 1;
+            while (T < p1 - p0 && T < 64) T <<= 1;
+        }
+        const int S = 64 / T, tl = lane & (T - 1), sl = lane / T;
+        for (int32_t i0 = p0; i0 < p1; i0 += T) {
+            const int32_t i = i0 + tl;
+            const bool valid = i < p1;
+            const int32_t ii = valid ? i : p0;
+            const int c = SLICED ? c0 : (nleaf > 1 && ii >= bnd[1]) + (nleaf > 2 && ii >= bnd[2]) +
+                                            (nleaf > 3 && ii >= bnd[3]);
+            const int32_t leaf = leaf0 + c;
+            const uint64_t key = box_key[leaf];
+            const int32_t tx = int32_t(compact_bits(key)), ty = int32_t(compact_bits(key >> 1));
+            const int2 pi = pts[ii];
+            const uint32_t ki = (MODE == kWindow) ? pkey[ii] : 0u;
+            const int32_t pout = perm_local[ii];
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            auto phi_at = [&](uint32_t kj, int2_t pj) -> double {
+                if (MODE == kWindow) return *reinterpret_cast<const double*>(tb + int32_t(ki - kj));
+                const int dx = abs(pi.x - pj.x), dy = abs(pi.y - pj.y);
+                if (MODE == kQuad) return tab[dy * W + dx];
+                return phi_oct(dx, dy, phi_oct_tab);
+            };
+            auto src_key = [&](int32_t j) -> uint32_t {
+                if (MODE != kWindow) return 0u;
+                return SLICED ? pkey[j] : SK[j];
+            };
+            auto src_pt = [&](int32_t j) -> int2_t {
+                if (MODE == kWindow) return int2_t{0, 0};
+                if (SLICED) {
+                    const int2 p = pts[j];
+                    return int2_t{p.x, p.y};
+                }
+                return SP[j];
+            };
+            auto src_f = [&](int32_t j) -> double { return SLICED ? fs[j] : SF[j]; };
+            for (int e = 0; e < ne; ++e) {
+                const int4_t en = E[size_t(qq) * kNearEntries + e];   // (first point, end, leaf x, leaf y)
+                const bool near = abs(en.z - tx) <= 1 && abs(en.w - ty) <= 1;   // uniform when sliced
+                if (near) {
+                    int32_t j = en.x + sl;
+                    for (; j + 3 * S < en.y; j += 4 * S) {
+                        a0 += phi_at(src_key(j), src_pt(j)) * src_f(j);
+                        a1 += phi_at(src_key(j + S), src_pt(j + S)) * src_f(j + S);
+                        a2 += phi_at(src_key(j + 2 * S), src_pt(j + 2 * S)) * src_f(j + 2 * S);
+                        a3 += phi_at(src_key(j + 3 * S), src_pt(j + 3 * S)) * src_f(j + 3 * S);
+                    }
+                    for (; j < en.y; j += S) a0 += phi_at(src_key(j), src_pt(j)) * src_f(j);
+                }
+            }
+            if (far) {
+                const int64_t loc = int64_t(pi.x - tx * side) + side * int64_t(pi.y - ty * side);
+                const double* tlp = leafT + loc * P;
+                const double* uh = U + size_t(leaf) * P;
+                if (SLICED) {
+                    for (int p = sl; p < P; p += S) a1 += tlp[p] * uh[p];
+                } else {
+                    const double2_t* tl2 = reinterpret_cast<const double2_t*>(tlp);
+                    const double2_t* uh2 = reinterpret_cast<const double2_t*>(uh);
+                    #pragma unroll
+                    for (int p = 0; p < P / 2; p += 2) {
+                        const double2_t x0 = tl2[p], y0 = uh2[p], x1 = tl2[p + 1], y1 = uh2[p + 1];
+                        a0 += x0.x * y0.x;
+                        a1 += x0.y * y0.y;
+                        a2 += x1.x * y1.x;
+                        a3 += x1.y * y1.y;
+                    }
+                }
+            }
+            double acc = (a0 + a1) + (a2 + a3);
+            if (SLICED)
+                for (int o = T; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+            if (valid && sl == 0) u[pout] = acc;
+        }
+    }
 }
 
 template <int P, int MODE>
-__global__ __launch_bounds__(kLeafBlock) void k_leaf(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0,
+__global__ __launch_bounds__(kNearBlock) void k_near(int32_t q0, int32_t q1, const NearGroup* groups,
+                                                      const int4* ents, const int32_t* box_pt0,
                                                       const int32_t* box_pt1, const uint64_t* box_key,
-                                                      const int32_t* box_inst, const int32_t* nb9, int64_t side, int W,
-                                                      const int2* pts, const uint32_t* pkey, const double* fs,
+                                                      const int32_t* box_inst, int64_t side, int W, const int2* pts,
+                                                      const uint32_t* pkey, const double* fs,
                                                       const int32_t* perm_local, const ExecPtrs* tab_ptrs,
                                                       double* u_single, const double* U, const double* leafT,
                                                       const uint8_t* far_inst, const double* phi_oct_tab) {
-    extern __shared__ double smem[];
-    double* tab = smem;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int tabn = (MODE == kGlobal) ? 0 : ((W * W + 1) & ~1);   // keeps the staging 16-B aligned
-    SrcRec* stage = reinterpret_cast<SrcRec*>(smem + tabn) + wave * kStage;
-    const int c = (MODE == kWindow) ? int(2 * side - 1) : 0;
+    extern __shared__ double tab[];
+    const int tid = threadIdx.x, wave = tid >> 6;
     if (MODE != kGlobal) {
-        for (int i = tid; i < W * W; i += kLeafBlock) {
+        const int c = (MODE == kWindow) ? int(2 * side - 1) : 0;
+        for (int i = tid; i < W * W; i += kNearBlock) {
             int dy = i / W - c, dx = i - (i / W) * W - c;
             dx = dx < 0 ? -dx : dx;
             dy = dy < 0 ? -dy : dy;
@@ -519,96 +635,18 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf(int32_t leaf0, int32_t leaf
         }
         __syncthreads();
     }
-    const char* tb = reinterpret_cast<const char*>(tab) + size_t(8) * size_t(c * W + c);
-    for (int32_t g = leaf0 + int32_t(blockIdx.x) * kLeafWaves + wave; g < leaf1;
-         g += int32_t(gridDim.x) * kLeafWaves) {
-        const int32_t p0 = box_pt0[g], p1 = box_pt1[g];
-        const int32_t nt = p1 - p0;
-        int T = 1;
-        while (T < nt && T < 64) T <<= 1;
-        const int S = 64 / T, t = lane & (T - 1), sl = lane / T;
-        int32_t b0[9], cnt[9], total = 0;
-        const int32_t* nl = nb9 + size_t(g) * 9;
-        #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            const int32_t nb = nl[q];
-            b0[q] = nb >= 0 ? box_pt0[nb] : 0;
-            cnt[q] = nb >= 0 ? box_pt1[nb] - b0[q] : 0;
-            total += cnt[q];
-        }
-        const int32_t k_inst = box_inst[g];
-        const bool far = far_inst[k_inst] != 0;
-        double* u = tab_ptrs ? tab_ptrs[k_inst].u : u_single;
-        const uint64_t key = box_key[g];
-        const int32_t cx = int32_t(compact_bits(key) * side), cy = int32_t(compact_bits(key >> 1) * side);
-        for (int32_t i0 = p0; i0 < p1; i0 += T) {
-            const int32_t i = i0 + t;
-            const bool valid = i < p1;
-            const int32_t ii = valid ? i : p0;
-            const int2 pi = pts[ii];
-            const uint32_t ki = (MODE == kWindow) ? pkey[ii] : 0u;
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-            for (int32_t c0 = 0; c0 < total; c0 += kStage) {
-                const int32_t cn = min(kStage, total - c0);
-                for (int32_t pos = lane; pos < cn; pos += 64) {
-                    int32_t r = c0 + pos, j = -1;
-                    #pragma unroll
-                    for (int q = 0; q < 9; ++q) {   // static indices: the ranges stay in registers
-                        if (j < 0) {
-                            if (r < cnt[q]) j = b0[q] + r;
-                            else r -= cnt[q];
-                        }
-                    }
-                    SrcRec rec;
-                    if (MODE == kWindow) {
-                        rec.a = pkey[j];
-                        rec.b = 0u;
-                    } else {
-                        const int2 pj = pts[j];
-                        rec.a = uint32_t(pj.x);
-                        rec.b = uint32_t(pj.y);
-                    }
-                    rec.f = fs[j];
-                    stage[pos] = rec;
-                }
-                wave_sync_lds();
-                auto phi_of = [&](const SrcRec& rec) -> double {
-                    if (MODE == kWindow) return *reinterpret_cast<const double*>(tb + int32_t(ki - rec.a));
-                    const int dx = abs(pi.x - int32_t(rec.a)), dy = abs(pi.y - int32_t(rec.b));
-                    if (MODE == kQuad) return tab[dy * W + dx];
-                    return phi_oct(dx, dy, phi_oct_tab);
-                };
-                int32_t jj = sl;
-                for (; jj + 3 * S < cn; jj += 4 * S) {
-                    const SrcRec r0 = stage[jj], r1 = stage[jj + S], r2 = stage[jj + 2 * S], r3 = stage[jj + 3 * S];
-                    a0 += phi_of(r0) * r0.f;
-                    a1 += phi_of(r1) * r1.f;
-                    a2 += phi_of(r2) * r2.f;
-                    a3 += phi_of(r3) * r3.f;
-                }
-                for (; jj < cn; jj += S) {
-                    const SrcRec r0 = stage[jj];
-                    a0 += phi_of(r0) * r0.f;
-                }
-                wave_sync_lds();
-            }
-            if (far) {
-                const int64_t loc = int64_t(pi.x - cx) + side * int64_t(pi.y - cy);
-                const double* tl = leafT + loc * P;
-                const double* uh = U + size_t(g) * P;
-                int p = sl;
-                for (; p + 3 * S < P; p += 4 * S) {
-                    a0 += tl[p] * uh[p];
-                    a1 += tl[p + S] * uh[p + S];
-                    a2 += tl[p + 2 * S] * uh[p + 2 * S];
-                    a3 += tl[p + 3 * S] * uh[p + 3 * S];
-                }
-                for (; p < P; p += S) a0 += tl[p] * uh[p];
-            }
-            double acc = (a0 + a1) + (a2 + a3);
-            for (int o = T; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
-            if (sl == 0 && valid) u[perm_local[i]] = acc;
-        }
+    const int cw = (MODE == kWindow) ? int(2 * side - 1) : 0;
+    const char* tb = reinterpret_cast<const char*>(tab) + size_t(8) * size_t(cw * W + cw);
+    for (int32_t q = q0 + int32_t(blockIdx.x) * kNearWaves + wave; q < q1; q += int32_t(gridDim.x) * kNearWaves) {
+        const int32_t qq = uniform(q);
+        const int32_t leaf0 = uniform(groups[qq].leaf0), nleaf = uniform(groups[qq].nleaf);
+        const int32_t nt = uniform(box_pt1[leaf0 + nleaf - 1]) - uniform(box_pt0[leaf0]);
+        if (nt > 32)   // half a wave or more busy in group mode; below that, leaf by leaf
+            near_group<P, MODE, false>(qq, groups, ents, box_pt0, box_pt1, box_key, box_inst, side, W, tab, tb, pts,
+                                       pkey, fs, perm_local, tab_ptrs, u_single, U, leafT, far_inst, phi_oct_tab);
+        else
+            near_group<P, MODE, true>(qq, groups, ents, box_pt0, box_pt1, box_key, box_inst, side, W, tab, tb, pts,
+                                      pkey, fs, perm_local, tab_ptrs, u_single, U, leafT, far_inst, phi_oct_tab);
     }
 }
 
@@ -716,34 +754,31 @@ void launch_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t m
                        il27, ops, Q, zrow, U);
 }
 
-void launch_leaf(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1, const uint64_t* box_key,
-                 const int32_t* box_inst, const int32_t* nb9, int64_t side, const int32_t* pts, const uint32_t* pkey,
-                 const double* fs, const int32_t* perm_local, const int32_t* pinst, const InstInfo* inst,
+void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* ents, const int32_t* box_pt0,
+                 const int32_t* box_pt1, const uint64_t* box_key, const int32_t* box_inst, int64_t side,
+                 const int32_t* pts, const uint32_t* pkey, const double* fs, const int32_t* perm_local,
                  const ExecPtrs* tab, double* u_single, const double* U, const double* leafT,
                  const uint8_t* far_inst, const double* phi_oct, hipStream_t st) {
-    (void)inst;
-    (void)pinst;
-    if (leaf1 <= leaf0) return;
-    unsigned g = grid_for(leaf1 - leaf0, kLeafWaves);
-    if (g > 2048) g = 2048;
-    const size_t stage = size_t(kLeafWaves) * kStage * sizeof(SrcRec);
+    if (q1 <= q0) return;
+    unsigned g = grid_for(q1 - q0, kNearWaves);
+    if (g > 8192) g = 8192;
     const int2* p2 = reinterpret_cast<const int2*>(pts);
     if (side <= 16) {
         const int W = int(4 * side - 1);
-        const size_t lds = size_t((W * W + 1) & ~1) * sizeof(double) + stage;
-        hipLaunchKernelGGL((k_leaf<kRankPad, kWindow>), dim3(g), dim3(kLeafBlock), lds, st, leaf0, leaf1, box_pt0,
-                           box_pt1, box_key, box_inst, nb9, side, W, p2, pkey, fs, perm_local, tab, u_single, U, leafT,
-                           far_inst, phi_oct);
+        const size_t lds = size_t(W * W) * sizeof(double);
+        hipLaunchKernelGGL((k_near<kRankPad, kWindow>), dim3(g), dim3(kNearBlock), lds, st, q0, q1, groups, ents,
+                           box_pt0, box_pt1, box_key, box_inst, side, W, p2, pkey, fs, perm_local, tab, u_single, U,
+                           leafT, far_inst, phi_oct);
     } else if (side <= 32) {
         const int W = int(2 * side);
-        const size_t lds = size_t((W * W + 1) & ~1) * sizeof(double) + stage;
-        hipLaunchKernelGGL((k_leaf<kRankPad, kQuad>), dim3(g), dim3(kLeafBlock), lds, st, leaf0, leaf1, box_pt0,
-                           box_pt1, box_key, box_inst, nb9, side, W, p2, pkey, fs, perm_local, tab, u_single, U, leafT,
-                           far_inst, phi_oct);
+        const size_t lds = size_t(W * W) * sizeof(double);
+        hipLaunchKernelGGL((k_near<kRankPad, kQuad>), dim3(g), dim3(kNearBlock), lds, st, q0, q1, groups, ents,
+                           box_pt0, box_pt1, box_key, box_inst, side, W, p2, pkey, fs, perm_local, tab, u_single, U,
+                           leafT, far_inst, phi_oct);
     } else {
-        hipLaunchKernelGGL((k_leaf<kRankPad, kGlobal>), dim3(g), dim3(kLeafBlock), stage, st, leaf0, leaf1, box_pt0,
-                           box_pt1, box_key, box_inst, nb9, side, 0, p2, pkey, fs, perm_local, tab, u_single, U, leafT,
-                           far_inst, phi_oct);
+        hipLaunchKernelGGL((k_near<kRankPad, kGlobal>), dim3(g), dim3(kNearBlock), 0, st, q0, q1, groups, ents,
+                           box_pt0, box_pt1, box_key, box_inst, side, 0, p2, pkey, fs, perm_local, tab, u_single, U,
+                           leafT, far_inst, phi_oct);
     }
 }
 

@@ -318,25 +318,6 @@ __global__ void k_lists_height(int32_t g0, int32_t g1, const uint64_t* box_key, 
     if (g < g1) list_box(g, box_key, box_parent, box_child, box_lev, nb9, il27);
 }
 
-// The few boxes of the top heights in one block, height by height, so that a parent's
-// lists are complete before its children read them: height q of the block's list holds
-// boxes [start[q], end[q]).
-constexpr int kTopLists = 1024;
-struct HeightRanges {
-    int32_t nh;
-    int32_t start[kMaxLevels + 1], end[kMaxLevels + 1];
-};
-
-__global__ __launch_bounds__(kTopLists) void k_lists_top(HeightRanges hr, const uint64_t* box_key,
-                                                           const int32_t* box_parent, const int32_t* box_child,
-                                                           const int8_t* box_lev, int32_t* nb9, int32_t* il27) {
-    for (int q = 0; q < hr.nh; ++q) {
-        for (int32_t g = hr.start[q] + int32_t(threadIdx.x); g < hr.end[q]; g += kTopLists)
-            list_box(g, box_key, box_parent, box_child, box_lev, nb9, il27);
-        __syncthreads();   // orders the writes of this height before the next height's reads
-    }
-}
-
 __global__ void k_class_flags(const uint64_t* box_key, int64_t nbox, int32_t* flags) {
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= nbox) return;
@@ -362,8 +343,16 @@ __global__ void k_class_boxes(const BoxGroup* groups, int32_t ngroups, const int
     }
 }
 
+// slots of the interleaved tile order before round i: sum over classes of min(nt[c], i)
+__device__ inline int32_t rounds_before(const int32_t* nt, int32_t i) {
+    return min(nt[0], i) + min(nt[1], i) + min(nt[2], i) + min(nt[3], i);
+}
+
 // one thread per tile slot of the groups (group q owns slots [tile_base, tile_base + tile_cap),
-// groups in slot order): the tiles of class 0, 1, 2, 3 in turn, then empty tiles
+// groups in slot order).  Tiles of the four classes are interleaved (round r holds the r-th
+// tile of class 0, 1, 2, 3 in turn, classes with fewer tiles dropping out), so that tiles
+// next to each other in the list cover the same region of the level and share their
+// source expansions in cache; empty tiles fill the rest of the group.
 __global__ void k_class_tiles(const BoxGroup* groups, int32_t ngroups, int32_t nslots, const int32_t* cscan,
                               const int32_t* ctotal, int64_t nbox, BoxTile* tiles) {
     const int32_t t = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -375,23 +364,86 @@ __global__ void k_class_tiles(const BoxGroup* groups, int32_t ngroups, int32_t n
         else hi = mid - 1;
     }
     const BoxGroup G = groups[lo];
-    int32_t r = t - G.tile_base;
-    BoxTile tl{};
-    tl.count = 0;
+    const int32_t r = t - G.tile_base;
+    int32_t cnt[4], nt[4];
     for (int c = 0; c < 4; ++c) {
-        const int32_t cnt = scan_at(cscan, ctotal, nbox, c, G.g1) - scan_at(cscan, ctotal, nbox, c, G.g0);
-        const int32_t nt = (cnt + G.tile_boxes - 1) / G.tile_boxes;
-        if (r < nt) {
-            tl.ops = G.ops;
-            tl.height = G.height;
-            tl.cls = c;
-            tl.start = G.cls_base + c * (G.g1 - G.g0) + r * G.tile_boxes;
-            tl.count = min(G.tile_boxes, cnt - r * G.tile_boxes);
-            break;
+        cnt[c] = scan_at(cscan, ctotal, nbox, c, G.g1) - scan_at(cscan, ctotal, nbox, c, G.g0);
+        nt[c] = (cnt[c] + G.tile_boxes - 1) / G.tile_boxes;
+    }
+    BoxTile tl;
+    tl.ops = G.ops;
+    tl.height = G.height;
+    tl.cls = 0;
+    tl.start = 0;
+    tl.count = 0;   // an empty tile unless a round below holds slot r
+    tl.pad0 = tl.pad1 = tl.pad2 = 0;
+    // round i holds the i-th tile of every class with more than i tiles; before(i) slots
+    // precede round i.  Find the round of slot r by bisection, then its class.
+    const int32_t rounds = max(max(nt[0], nt[1]), max(nt[2], nt[3]));
+    if (r < rounds_before(nt, rounds)) {
+        int32_t lo_i = 0, hi_i = rounds - 1;   // largest i with before(i) <= r
+        while (lo_i < hi_i) {
+            const int32_t mid = (lo_i + hi_i + 1) >> 1;
+            if (rounds_before(nt, mid) <= r) lo_i = mid;
+            else hi_i = mid - 1;
         }
-        r -= nt;
+        int32_t rem = r - rounds_before(nt, lo_i);
+        for (int c = 0; c < 4; ++c) {
+            if (nt[c] <= lo_i) continue;
+            if (rem == 0) {
+                tl.cls = c;
+                tl.start = G.cls_base + c * (G.g1 - G.g0) + lo_i * G.tile_boxes;
+                tl.count = min(G.tile_boxes, cnt[c] - lo_i * G.tile_boxes);
+                break;
+            }
+            --rem;
+        }
     }
     tiles[t] = tl;
+}
+
+// one thread per near-field group: its leaves and the union of their neighbour lists, as
+// point ranges in leaf order (Morton order, so ranges of adjacent leaves follow each other)
+__global__ void k_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, const int32_t* roots, int32_t nroots,
+                              const int32_t* box_child, const int32_t* nb9, const int32_t* box_pt0,
+                              const int32_t* box_pt1, const uint64_t* box_key, NearGroup* groups, int4* ents) {
+    const int32_t q = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= h1_count + nroots) return;
+    int32_t leaves[4], nleaf = 0;
+    if (q < h1_count) {
+        const int32_t P = h1_start + q;
+        for (int c = 0; c < 4; ++c) {
+            const int32_t ch = box_child[size_t(P) * 4 + c];
+            if (ch >= 0) leaves[nleaf++] = ch;
+        }
+    } else {
+        leaves[nleaf++] = roots[q - h1_count];
+    }
+    int32_t un[kNearEntries];
+    int nu = 0;
+    for (int l = 0; l < nleaf; ++l)
+        for (int k = 0; k < 9; ++k) {
+            const int32_t b = nb9[size_t(leaves[l]) * 9 + k];
+            if (b < 0) continue;
+            int pos = 0;
+            while (pos < nu && un[pos] < b) ++pos;
+            if (pos < nu && un[pos] == b) continue;
+            for (int r = nu; r > pos; --r) un[r] = un[r - 1];   // insertion keeps leaf order
+            un[pos] = b;
+            ++nu;
+        }
+    int4* out = ents + size_t(q0 + q) * kNearEntries;
+    for (int e = 0; e < nu; ++e) {
+        const int32_t b = un[e];
+        const uint64_t key = box_key[b];
+        out[e] = make_int4(box_pt0[b], box_pt1[b], int32_t(compact_bits(key)), int32_t(compact_bits(key >> 1)));
+    }
+    NearGroup G;
+    G.leaf0 = leaves[0];
+    G.nleaf = nleaf;
+    G.ne = nu;
+    G.pad = 0;
+    groups[q0 + q] = G;
 }
 
 __global__ void k_point_keys(const int2* pts, const int32_t* pinst, const InstInfo* inst, const OpsPtrs* ops,
@@ -405,7 +457,7 @@ __global__ void k_point_keys(const int2* pts, const int32_t* pinst, const InstIn
 }
 
 // ---- radix sort: 8-bit digits, tiles of 4096 keys per block ----------------------------
-constexpr int kRsItems = 16;
+constexpr int kRsItems = 4;
 constexpr int kRsTile = kBlock * kRsItems;
 
 __global__ void k_rs_hist(const uint64_t* keys, int64_t n, int shift, uint32_t* hist, int nblk) {
@@ -652,21 +704,7 @@ void launch_link_boxes(const uint64_t* box_key, const int32_t* box_parent, const
 
 void launch_lists(const int32_t* hbase, int H, const uint64_t* box_key, const int32_t* box_parent,
                   const int32_t* box_child, const int8_t* box_lev, int32_t* nb9, int32_t* il27, hipStream_t st) {
-    // the top heights, while together they hold at most 4096 boxes, in one block; the rest
-    // one launch per height, from the top down
-    const int32_t nbox = hbase[H + 1];
-    HeightRanges top{};
-    int h = H;
-    while (h >= 0 && nbox - hbase[h] <= 4 * kTopLists) {
-        top.start[top.nh] = hbase[h];
-        top.end[top.nh] = hbase[h + 1];
-        ++top.nh;
-        --h;
-    }
-    if (top.nh > 0)
-        hipLaunchKernelGGL(k_lists_top, dim3(1), dim3(kTopLists), 0, st, top, box_key, box_parent, box_child, box_lev,
-                           nb9, il27);
-    for (; h >= 0; --h) {
+    for (int h = H; h >= 0; --h) {   // a box's lists need its parent's neighbour list
         const int32_t g0 = hbase[h], g1 = hbase[h + 1];
         if (g1 > g0)
             hipLaunchKernelGGL(k_lists_height, dim3(grid_for(g1 - g0)), dim3(kBlock), 0, st, g0, g1, box_key,
@@ -686,6 +724,16 @@ void launch_class_lists(const BoxGroup* groups, int32_t ngroups, int32_t nslots,
                        box_key, nbox, cls_box);
     hipLaunchKernelGGL(k_class_tiles, dim3(grid_for(nslots)), dim3(kBlock), 0, st, groups, ngroups, nslots, cscan,
                        ctotal, nbox, tiles);
+}
+
+void launch_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, const int32_t* roots, int32_t nroots,
+                        const int32_t* box_child, const int32_t* nb9, const int32_t* box_pt0,
+                        const int32_t* box_pt1, const uint64_t* box_key, NearGroup* groups, int4* ents,
+                        hipStream_t st) {
+    const int32_t n = h1_count + nroots;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_near_groups, dim3(grid_for(n)), dim3(kBlock), 0, st, q0, h1_start, h1_count, roots, nroots,
+                       box_child, nb9, box_pt0, box_pt1, box_key, groups, ents);
 }
 
 void launch_point_keys(const int32_t* pts, const int32_t* pinst, const InstInfo* inst, const OpsPtrs* ops, int64_t n,

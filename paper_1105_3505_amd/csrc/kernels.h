@@ -87,6 +87,15 @@ struct OpsPtrs {
     int32_t nlev, pad;
 };
 
+// Near-field group: the leaves leaf0 .. leaf0 + nleaf - 1 (the children of one parent box,
+// or a root that is a leaf), whose sources are the ne point ranges listed for the group.
+struct NearGroup {
+    int32_t leaf0, nleaf, ne, pad;
+};
+// At most 16 source leaves per group (the 4 x 4 block around a parent's children); entry
+// (first point, end point, leaf x, leaf y) in leaf coordinates of the group's level.
+constexpr int kNearEntries = 16;
+
 // Per-execute load/potential pointers of each instance.
 struct ExecPtrs {
     const double* f;
@@ -107,7 +116,7 @@ void scan_rows(const int32_t* in, int32_t* out, int64_t n, int rows, int32_t* to
                void* scratch, hipStream_t st);
 
 struct Chunk { int32_t inst, begin, end, pad; };   // <= kChunk points of one instance
-constexpr int32_t kChunk = 8192;
+constexpr int32_t kChunk = 2048;
 
 void launch_concat(int32_t K, const int32_t* const* xy_tab, const int32_t* pt_off, int64_t n,
                    int32_t* xyc, hipStream_t st);
@@ -154,6 +163,12 @@ void launch_class_lists(const BoxGroup* groups, int32_t ngroups, int32_t nslots,
                         int32_t* cls_box, BoxTile* tiles, hipStream_t st);
 void launch_point_keys(const int32_t* pts, const int32_t* pinst, const InstInfo* inst,
                        const OpsPtrs* ops, int64_t n, uint32_t* key, hipStream_t st);
+// near-field groups [q0, q0 + h1_count + nroots): the children of the height-1 boxes
+// h1_start .. h1_start + h1_count - 1, then the root leaves roots[0 .. nroots)
+void launch_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, const int32_t* roots, int32_t nroots,
+                        const int32_t* box_child, const int32_t* nb9, const int32_t* box_pt0,
+                        const int32_t* box_pt1, const uint64_t* box_key, NearGroup* groups, int4* ents,
+                        hipStream_t st);
 
 // ---- evaluation passes (fmm_kernels.hip) ---------------------------------------------------
 void launch_gather_f(const ExecPtrs* tab, const double* f_single, const int32_t* perm_local,
@@ -171,10 +186,10 @@ void launch_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, c
 void launch_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t max_tiles,
                       const int32_t* box_list, const int32_t* il27, const OpsPtrs* ops,
                       const double* Q, int32_t zrow, double* U, hipStream_t st);
-void launch_leaf(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1,
-                 const uint64_t* box_key, const int32_t* box_inst, const int32_t* nb9,
-                 int64_t side, const int32_t* pts, const uint32_t* pkey, const double* fs,
-                 const int32_t* perm_local, const int32_t* pinst, const InstInfo* inst,
+// L2P + near field + un-permutation for the groups [q0, q1) of one leaf side
+void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* ents, const int32_t* box_pt0,
+                 const int32_t* box_pt1, const uint64_t* box_key, const int32_t* box_inst, int64_t side,
+                 const int32_t* pts, const uint32_t* pkey, const double* fs, const int32_t* perm_local,
                  const ExecPtrs* tab, double* u_single, const double* U, const double* leafT,
                  const uint8_t* far_inst, const double* phi_oct, hipStream_t st);
 void launch_direct(int64_t nt, const int32_t* txy, int64_t ns, const int32_t* sxy,

@@ -147,7 +147,8 @@ def run_single(args, torch, lf):
     for _ in range(max(args.warmup, 1)):
         step().close()
     torch.cuda.synchronize()
-    lat, phases, info = [], [], None
+    lat, phases = [], []
+    torch.cuda.synchronize()
     t_all = time.perf_counter()
     for _ in range(args.steps):
         t0 = time.perf_counter()
@@ -155,15 +156,14 @@ def run_single(args, torch, lf):
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t0) * 1e3)
         phases.append(plan.phase_times())
-        if info is None:
-            info = plan.info()
         plan.close()
     torch.cuda.synchronize()
     ms_per_step = (time.perf_counter() - t_all) * 1e3 / args.steps
     value = n / (ms_per_step * 1e-3) / 1e6
 
-    # execute-only throughput on a resident plan
+    # execute-only throughput on a resident plan (outside the timed steps: plan statistics)
     plan = ctx.plan(xy_d, stream=stream)
+    info = plan.info()
     for _ in range(3):
         plan.execute(f_d, u_d, stream=stream)
     torch.cuda.synchronize()
@@ -215,7 +215,8 @@ def run_batched(args, torch, lf):
     for _ in range(max(args.warmup, 1)):
         step().close()
     torch.cuda.synchronize()
-    lat, phases, info = [], [], None
+    lat, phases = [], []
+    torch.cuda.synchronize()
     t_all = time.perf_counter()
     for _ in range(args.steps):
         t0 = time.perf_counter()
@@ -223,11 +224,11 @@ def run_batched(args, torch, lf):
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t0) * 1e3)
         phases.append(plan.phase_times())
-        if info is None:
-            info = plan.info()
         plan.close()
+    torch.cuda.synchronize()
     ms_per_step = (time.perf_counter() - t_all) * 1e3 / args.steps
     plan = ctx.plan_batch(xs, stream=stream)
+    info = plan.info()
     plan.execute_instances(fs, us, stream=stream)
     torch.cuda.synchronize()
     reps = max(args.steps, 5)

@@ -505,9 +505,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     tmp.reserve(size_t(nch) * sizeof(Chunk));
     tmp.reserve(size_t(K + 1) * 4);             // chunk_first
     tmp.reserve(size_t(nch) * 16);              // bbox partials
-    tmp.reserve(size_t(K) * 16);                // bbox
-    tmp.reserve(size_t(K) * (kMaxLevels + 2) * 4);   // level histograms
-    tmp.reserve(size_t(K) * 4);                 // lookahead maxima
+    tmp.reserve(size_t(K) * (kMaxLevels + 3) * 4);   // level histograms, then lookahead maxima
     tmp.reserve(K > 1 ? size_t(n) * 8 : 0);     // concatenated points
     tmp.reserve(size_t(n) * 8);                 // keys
     tmp.reserve(size_t(n) * 8);                 // keys_tmp
@@ -524,9 +522,21 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     Chunk* d_chunks = tmp.take<Chunk>(nch);
     int32_t* d_chfirst = tmp.take<int32_t>(K + 1);
     int32_t* d_part = tmp.take<int32_t>(size_t(nch) * 4);
-    int32_t* d_bbox = tmp.take<int32_t>(size_t(K) * 4);
-    int32_t* d_hist = tmp.take<int32_t>(size_t(K) * (kMaxLevels + 2));
-    int32_t* d_maxc = tmp.take<int32_t>(K);
+    int32_t* d_stats = tmp.take<int32_t>(size_t(K) * (kMaxLevels + 3));
+    int32_t* d_hist = d_stats;
+    int32_t* d_maxc = d_stats + size_t(K) * (kMaxLevels + 2);
+    // host-visible results of the two read-backs (pinned: the root boxes are written there by
+    // the kernel itself, the level statistics by one copy)
+    size_t rb_cls = 0;
+    int32_t* rb = static_cast<int32_t*>(ctx->pinned.acquire(size_t(K) * (kMaxLevels + 7) * 4, &rb_cls));
+    struct Release {
+        lfmm_ctx* c;
+        void* p;
+        size_t cls;
+        ~Release() { c->pinned.release(p, cls); }
+    } rb_guard{ctx, rb, rb_cls};
+    int32_t* bb = rb;                      // [K][4] root boxes
+    int32_t* stats = rb + size_t(K) * 4;   // [K][34] histograms, then [K] maxima
     int32_t* d_xyc = (K > 1) ? tmp.take<int32_t>(size_t(n) * 2) : nullptr;
     uint64_t* keys = tmp.take<uint64_t>(n);
     uint64_t* keys_tmp = tmp.take<uint64_t>(n);
@@ -553,9 +563,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
 
     // ---- root boxes ----------------------------------------------------------------------
     launch_bbox_chunks(xy, d_chunks, nch, d_part, st);
-    launch_bbox_final(d_part, d_chfirst, K, d_bbox, st);
-    std::vector<int32_t> bb(static_cast<size_t>(K) * 4);
-    LFMM_HIP(hipMemcpyAsync(bb.data(), d_bbox, bb.size() * 4, hipMemcpyDeviceToHost, st));
+    launch_bbox_final(d_part, d_chfirst, K, bb, st);   // written straight to pinned host memory
     LFMM_HIP(hipStreamSynchronize(st));
     pl->inst.assign(size_t(K), InstInfo{});
     int Dmax = 0;
@@ -625,13 +633,12 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     launch_gather_sorted(skeys, svals, xy, pl->d_inst, d_ptoff, Dmax, K, n, pl->pts, pl->perm, pl->pinst, st);
 
     // ---- leaf levels and box counts ---------------------------------------------------------
-    LFMM_HIP(hipMemsetAsync(d_hist, 0, size_t(K) * (kMaxLevels + 2) * 4, st));
-    LFMM_HIP(hipMemsetAsync(d_maxc, 0, size_t(K) * 4, st));
+    LFMM_HIP(hipMemsetAsync(d_stats, 0, size_t(K) * (kMaxLevels + 3) * 4, st));
     launch_level_stats(skeys, d_chunks, nch, pl->d_inst, Dmax, cl, d_hist, d_maxc, st);
-    std::vector<int32_t> hist(static_cast<size_t>(K) * (kMaxLevels + 2)), maxc(static_cast<size_t>(K));
-    LFMM_HIP(hipMemcpyAsync(hist.data(), d_hist, hist.size() * 4, hipMemcpyDeviceToHost, st));
-    LFMM_HIP(hipMemcpyAsync(maxc.data(), d_maxc, maxc.size() * 4, hipMemcpyDeviceToHost, st));
+    LFMM_HIP(hipMemcpyAsync(stats, d_stats, size_t(K) * (kMaxLevels + 3) * 4, hipMemcpyDeviceToHost, st));
     LFMM_HIP(hipStreamSynchronize(st));
+    const int32_t* hist = stats;
+    const int32_t* maxc = stats + size_t(K) * (kMaxLevels + 2);
 
     std::map<int64_t, int> side_index;
     std::vector<int> nlev_of_side;

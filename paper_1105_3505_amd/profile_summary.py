@@ -72,15 +72,18 @@ def _copy_reference(path: str, counter: str) -> float:
     return best
 
 
+KERNEL_SOURCES = ("kernels.h", "forest_kernels.hip", "fmm_kernels.hip")
+
+
 def kernel_sources_hash() -> str:
+    """Hash of the device code (kernels and the layouts they read), not of host orchestration."""
     import hashlib
     import os
     here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(here)):
-        if f.endswith(".hip"):
-            with open(os.path.join(here, f), "rb") as fh:
-                h.update(fh.read())
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(here, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 

@@ -512,7 +512,6 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     tmp.reserve(size_t(n) * 4);                 // vals
     tmp.reserve(size_t(n) * 4);                 // vals_tmp
     tmp.reserve(size_t(n));                     // cl
-    tmp.reserve(size_t(n) * 4);                 // flags
     tmp.reserve(size_t(n) * 4);                 // scan
     tmp.reserve(radix_scratch_bytes(n));
     tmp.reserve(scan_scratch_bytes(n, 1));
@@ -543,7 +542,6 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     uint32_t* vals = tmp.take<uint32_t>(n);
     uint32_t* vals_tmp = tmp.take<uint32_t>(n);
     int8_t* cl = tmp.take<int8_t>(n);
-    int32_t* flags = tmp.take<int32_t>(n);
     int32_t* scan = tmp.take<int32_t>(n);
     void* rscr = tmp.take<char>(radix_scratch_bytes(n));
     void* sscr = tmp.take<char>(scan_scratch_bytes(n, 1));
@@ -859,10 +857,8 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     tmp2.reserve(size_t(nl) * 8);                        // leaf keys
     tmp2.reserve(size_t(nl));                            // leaf cl
     tmp2.reserve(size_t(nl) * 4);                        // leaf instance
-    tmp2.reserve(size_t(rows) * nl * 4);                 // level flags
     tmp2.reserve(size_t(rows) * nl * 4);                 // level scans
     tmp2.reserve(scan_scratch_bytes(nl, rows));
-    tmp2.reserve(size_t(nb) * 4 * 4);                    // class flags
     tmp2.reserve(size_t(nb) * 4 * 4);                    // class scans
     tmp2.reserve(64);                                    // class totals
     tmp2.reserve(scan_scratch_bytes(nb, 4));
@@ -871,28 +867,21 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     uint64_t* leaf_key = tmp2.take<uint64_t>(nl);
     int8_t* leaf_cl = tmp2.take<int8_t>(nl);
     int32_t* leaf_inst = tmp2.take<int32_t>(nl);
-    int32_t* lflags = tmp2.take<int32_t>(size_t(rows) * nl);
     int32_t* lscan = tmp2.take<int32_t>(size_t(rows) * nl);
     void* lscr = tmp2.take<char>(scan_scratch_bytes(nl, rows));
-    int32_t* cflags = tmp2.take<int32_t>(size_t(nb) * 4);
     int32_t* cscan = tmp2.take<int32_t>(size_t(nb) * 4);
     int32_t* ctotal = tmp2.take<int32_t>(16);
     void* cscr = tmp2.take<char>(scan_scratch_bytes(nb, 4));
 
-    launch_leaf_flags(cl, pl->pinst, pl->d_inst, n, flags, st);
-    scan_rows(flags, scan, n, 1, nullptr, sscr, st);
-    launch_leaf_scatter(flags, scan, skeys, cl, pl->pinst, pl->d_inst, Dmax, n, leaf_pt0, leaf_key, leaf_cl,
-                        leaf_inst, st);
-    if (Lmax > 0) {
-        launch_level_flags(leaf_cl, leaf_inst, pl->d_inst, nl, Lmax, lflags, st);
-        scan_rows(lflags, lscan, nl, Lmax, nullptr, lscr, st);
-    }
+    scan_leaf_starts(cl, pl->pinst, pl->d_inst, n, scan, sscr, st);
+    launch_leaf_scatter(scan, skeys, cl, pl->pinst, pl->d_inst, Dmax, n, leaf_pt0, leaf_key, leaf_cl, leaf_inst, st);
+    if (Lmax > 0) scan_level_starts(leaf_cl, leaf_inst, pl->d_inst, nl, Lmax, lscan, lscr, st);
     launch_build_boxes(lscan, leaf_cl, leaf_pt0, leaf_key, leaf_inst, pl->d_inst, nl, Lmax, pl->box_key, pl->box_pt0,
                        pl->box_parent, pl->box_child, pl->box_inst, pl->box_lev, st);
     launch_link_boxes(pl->box_key, pl->box_parent, pl->box_inst, pl->box_lev, pl->d_inst, nb, pl->box_pt0,
                       pl->box_child, pl->box_pt1, st);
-    // the lists (one launch per height, each short) run on a second stream beside the class
-    // lists and tiles, which need only the boxes
+    // the lists and the near-field groups run on a second stream beside the class lists and
+    // tiles, which need only the boxes
     if (!ctx->aux) {
         LFMM_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
         LFMM_HIP(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
@@ -900,15 +889,14 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     }
     LFMM_HIP(hipEventRecord(ctx->fork, st));
     LFMM_HIP(hipStreamWaitEvent(ctx->aux, ctx->fork, 0));
-    launch_lists(pl->hbase.data(), H, pl->box_key, pl->box_parent, pl->box_child, pl->box_lev, pl->nb9, pl->il27,
-                 ctx->aux);
+    launch_lists(pl->box_key, pl->box_parent, pl->box_child, pl->box_inst, pl->box_lev, pl->d_inst, nb, pl->nb9,
+                 pl->il27, ctx->aux);
     for (size_t o = 0; o < side_of.size(); ++o)   // groups need the leaves' neighbour lists
         launch_near_groups(pl->near_of_ops[o].t0, h1_start[o], h1_count[o], d_roots + root_off[o],
                            int32_t(roots[o].size()), pl->box_child, pl->nb9, pl->box_pt0, pl->box_pt1, pl->box_key,
                            pl->groups, pl->ents, ctx->aux);
     LFMM_HIP(hipEventRecord(ctx->join, ctx->aux));
-    launch_class_flags(pl->box_key, nb, cflags, st);
-    scan_rows(cflags, cscan, nb, 4, ctotal, cscr, st);
+    scan_child_classes(pl->box_key, nb, cscan, ctotal, cscr, st);
     launch_class_lists(d_groups, int32_t(groups.size()), m2m_base, cscan, ctotal, pl->box_key, nb, pl->cls_box,
                        pl->tiles, st);
     if (std::any_of(side_of.begin(), side_of.end(), [](int64_t s) { return s <= 16; }))

@@ -196,28 +196,18 @@ __global__ void k_level_stats(const uint64_t* keys, const Chunk* chunks, const I
         atomicAdd(&hist[size_t(c.inst) * (kMaxLevels + 2) + threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ void k_leaf_flags(const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int64_t n, int32_t* flags) {
+__global__ void k_leaf_scatter(const int32_t* scan, const uint64_t* keys, const int8_t* cl, const int32_t* pinst,
+                               const InstInfo* inst, int Dmax, int64_t n, int32_t* leaf_pt0, uint64_t* leaf_key,
+                               int8_t* leaf_cl, int32_t* leaf_inst) {
     const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s < n) flags[s] = (cl[s] < inst[pinst[s]].L) ? 1 : 0;
-}
-
-__global__ void k_leaf_scatter(const int32_t* flags, const int32_t* scan, const uint64_t* keys, const int8_t* cl,
-                               const int32_t* pinst, const InstInfo* inst, int Dmax, int64_t n, int32_t* leaf_pt0,
-                               uint64_t* leaf_key, int8_t* leaf_cl, int32_t* leaf_inst) {
-    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s >= n || !flags[s]) return;
-    const int32_t r = scan[s], k = pinst[s];
+    if (s >= n) return;
+    const int32_t k = pinst[s];
+    if (cl[s] >= inst[k].L) return;   // not the first point of a leaf
+    const int32_t r = scan[s];
     leaf_pt0[r] = int32_t(s);
     leaf_key[r] = (keys[s] & morton_mask(Dmax)) >> (2 * (inst[k].D - inst[k].L));
     leaf_cl[r] = cl[s];
     leaf_inst[r] = k;
-}
-
-__global__ void k_level_flags(const int8_t* leaf_cl, const int32_t* leaf_inst, const InstInfo* inst, int64_t nleaf,
-                              int32_t* flags) {
-    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int lev = blockIdx.y;
-    if (b < nleaf) flags[size_t(lev) * nleaf + b] = (lev < inst[leaf_inst[b]].L && leaf_cl[b] < lev) ? 1 : 0;
 }
 
 // One thread per (leaf, level): the leaf that starts a box of that level writes the box and
@@ -278,16 +268,56 @@ __device__ inline int32_t child_at(int32_t x, int32_t y, int32_t px, int32_t py,
     return box_child[size_t(q) * 4 + (x & 1) + 2 * (y & 1)];
 }
 
-__device__ void list_box(int32_t g, const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_child,
-                         const int8_t* box_lev, int32_t* nb9, int32_t* il27) {
-    const int lev = box_lev[g];
-    int32_t* nl = nb9 + size_t(g) * 9;
-    if (lev < 2) {   // no interaction list above level 2
-        int32_t* il = il27 + size_t(g) * kNumInteractions;
-        for (int k = 0; k < kNumInteractions; ++k) il[k] = -1;
+// index of the box with Morton key `key` among the boxes [lo, hi) of one level of one
+// instance (sorted by key), or -1
+__device__ inline int32_t find_box(const uint64_t* box_key, int32_t lo, int32_t hi, uint64_t key) {
+    const int32_t end = hi;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (box_key[mid] < key) lo = mid + 1;
+        else hi = mid;
     }
-    if (lev == 0) {
-        for (int q = 0; q < 9; ++q) nl[q] = (q == 4) ? g : -1;
+    return (lo < end && box_key[lo] == key) ? lo : -1;
+}
+
+__device__ inline uint64_t morton2(uint32_t x, uint32_t y) { return spread_bits(x) | (spread_bits(y) << 1); }
+
+// 3 x 3 neighbourhood of every box (slot (dy + 1) * 3 + dx + 1), by search among the boxes of
+// its level: no dependence between levels, so one launch covers all of them
+__global__ void k_neighbours(const uint64_t* box_key, const int32_t* box_inst, const int8_t* box_lev,
+                             const InstInfo* inst, int64_t nbox, int32_t* nb9) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= nbox) return;
+    const int lev = box_lev[g];
+    const InstInfo& I = inst[box_inst[g]];
+    const int32_t lo = I.lev_base[lev], hi = lo + I.lev_count[lev];
+    const uint64_t key = box_key[g];
+    const int32_t bx = int32_t(compact_bits(key)), by = int32_t(compact_bits(key >> 1));
+    const int32_t side = int32_t(1) << lev;
+    int32_t* nl = nb9 + size_t(g) * 9;
+    #pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+        #pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int32_t x = bx + dx, y = by + dy;
+            int32_t r = -1;
+            if (dx == 0 && dy == 0) r = int32_t(g);
+            else if (x >= 0 && y >= 0 && x < side && y < side)
+                r = find_box(box_key, lo, hi, morton2(uint32_t(x), uint32_t(y)));
+            nl[(dy + 1) * 3 + dx + 1] = r;
+        }
+}
+
+// interaction list of every box of level >= 2 (Definition 6.1): the children of its parent's
+// neighbours that are not its own neighbours, in the slot order of its child position
+__global__ void k_interactions(const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_child,
+                               const int8_t* box_lev, int64_t nbox, const int32_t* nb9, int32_t* il27) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= nbox) return;
+    const int lev = box_lev[g];
+    int32_t* il = il27 + size_t(g) * kNumInteractions;
+    if (lev < 2) {
+        for (int k = 0; k < kNumInteractions; ++k) il[k] = -1;
         return;
     }
     const uint64_t key = box_key[g];
@@ -297,32 +327,13 @@ __device__ void list_box(int32_t g, const uint64_t* box_key, const int32_t* box_
     const int32_t* pp = nb9 + size_t(box_parent[g]) * 9;
     #pragma unroll
     for (int q = 0; q < 9; ++q) pn[q] = pp[q];
-    #pragma unroll
-    for (int dy = -1; dy <= 1; ++dy)
-        #pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) nl[(dy + 1) * 3 + dx + 1] = child_at(bx + dx, by + dy, px, py, pn, box_child);
-    if (lev < 2) return;
     const int cx = bx & 1, cy = by & 1;
-    int32_t* il = il27 + size_t(g) * kNumInteractions;
     int k = 0;
     for (int dy = -2 - cy; dy <= 3 - cy; ++dy)
         for (int dx = -2 - cx; dx <= 3 - cx; ++dx) {
             if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
             il[k++] = child_at(bx + dx, by + dy, px, py, pn, box_child);
         }
-}
-
-__global__ void k_lists_height(int32_t g0, int32_t g1, const uint64_t* box_key, const int32_t* box_parent,
-                               const int32_t* box_child, const int8_t* box_lev, int32_t* nb9, int32_t* il27) {
-    const int32_t g = g0 + int32_t(blockIdx.x * blockDim.x + threadIdx.x);
-    if (g < g1) list_box(g, box_key, box_parent, box_child, box_lev, nb9, il27);
-}
-
-__global__ void k_class_flags(const uint64_t* box_key, int64_t nbox, int32_t* flags) {
-    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= nbox) return;
-    const int c = int(box_key[g] & 3ull);
-    for (int q = 0; q < 4; ++q) flags[size_t(q) * nbox + g] = (q == c) ? 1 : 0;
 }
 
 __device__ inline int32_t scan_at(const int32_t* cscan, const int32_t* ctotal, int64_t nbox, int c, int64_t g) {
@@ -539,69 +550,119 @@ __device__ inline int32_t block_exclusive_scan(int32_t v, int32_t* total) {
     return pre + x - v;
 }
 
-__global__ void k_scan_tiles(const int32_t* in, int32_t* out, int64_t n, int32_t* bsum, int nblk) {
+// Two-launch exclusive scan of `rows` rows of n values each (row r, item i = src(r, i)): the
+// first launch sums each tile of kScanTile items, the second adds the sums of the tiles
+// before its own (a block-wide reduction over at most a few thousand values) and scans
+// its tile.  Sources compute flags on the fly, so no flag array is stored.
+struct RowsArray {   // values from an array, row stride n
+    const int32_t* in;
+    int64_t n;
+    __device__ int32_t operator()(int r, int64_t i) const { return in[size_t(r) * n + i]; }
+};
+struct LeafStart {   // 1 where a leaf of its instance starts at Morton-ordered point i
+    const int8_t* cl;
+    const int32_t* pinst;
+    const InstInfo* inst;
+    __device__ int32_t operator()(int, int64_t i) const { return cl[i] < inst[pinst[i]].L ? 1 : 0; }
+};
+struct LevelStart {   // row lev: 1 where leaf b starts a box of level lev < L of its instance
+    const int8_t* leaf_cl;
+    const int32_t* leaf_inst;
+    const InstInfo* inst;
+    __device__ int32_t operator()(int lev, int64_t b) const {
+        return (lev < inst[leaf_inst[b]].L && leaf_cl[b] < lev) ? 1 : 0;
+    }
+};
+struct ChildClass {   // row c: 1 where box g sits in child position c of its parent
+    const uint64_t* box_key;
+    __device__ int32_t operator()(int c, int64_t g) const { return int(box_key[g] & 3ull) == c ? 1 : 0; }
+};
+
+__device__ inline int32_t block_sum(int32_t v) {
+    __shared__ int32_t ws[kBlock / 64];
+    #pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int32_t t = 0;
+    for (int w = 0; w < kBlock / 64; ++w) t += ws[w];
+    __syncthreads();
+    return t;
+}
+
+template <class Src>
+__global__ void k_scan_sums(Src src, int64_t n, int32_t* bsum, int nblk) {
     const int row = blockIdx.y;
-    const int32_t* rin = in + size_t(row) * n;
-    int32_t* rout = out + size_t(row) * n;
+    const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+    int32_t sum = 0;
+    #pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) sum += src(row, base + k);
+    sum = block_sum(sum);
+    if (threadIdx.x == 0) bsum[size_t(row) * nblk + blockIdx.x] = sum;
+}
+
+template <class Src>
+__global__ void k_scan_apply(Src src, int32_t* out, int64_t n, const int32_t* bsum, int nblk, int32_t* totals) {
+    const int row = blockIdx.y;
+    const int32_t* bs = bsum + size_t(row) * nblk;
+    int32_t pre = 0;
+    for (int t = threadIdx.x; t < int(blockIdx.x); t += kBlock) pre += bs[t];
+    pre = block_sum(pre);
     const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
     int32_t v[kScanItems];
     int32_t s = 0;
     #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        v[k] = (base + k < n) ? rin[base + k] : 0;
+        v[k] = (base + k < n) ? src(row, base + k) : 0;
         s += v[k];
     }
     int32_t tot;
-    int32_t pre = block_exclusive_scan(s, &tot);
+    int32_t x = pre + block_exclusive_scan(s, &tot);
+    int32_t* rout = out + size_t(row) * n;
     #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) rout[base + k] = pre;
-        pre += v[k];
+        if (base + k < n) rout[base + k] = x;
+        x += v[k];
     }
-    if (threadIdx.x == 0) bsum[size_t(row) * nblk + blockIdx.x] = tot;
+    if (totals && blockIdx.x == unsigned(nblk - 1) && threadIdx.x == 0) totals[row] = pre + tot;
 }
 
-__global__ void k_scan_add(int32_t* out, int64_t n, const int32_t* bscan, int nblk) {
-    const int row = blockIdx.y;
-    const int32_t add = bscan[size_t(row) * nblk + blockIdx.x];
-    const int64_t base = int64_t(blockIdx.x) * kScanTile;
-    for (int k = threadIdx.x; k < kScanTile; k += kBlock)
-        if (base + k < n) out[size_t(row) * n + base + k] += add;
-}
-
-__global__ void k_scan_totals(const int32_t* in, const int32_t* out, int64_t n, int rows, int32_t* totals) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < rows) totals[r] = (n > 0) ? out[size_t(r) * n + n - 1] + in[size_t(r) * n + n - 1] : 0;
+template <class Src>
+void scan_source(Src src, int32_t* out, int64_t n, int rows, int32_t* totals, void* scratch, hipStream_t st) {
+    if (n <= 0 || rows <= 0) return;
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    int32_t* bsum = static_cast<int32_t*>(scratch);
+    hipLaunchKernelGGL(k_scan_sums<Src>, dim3(unsigned(nb), unsigned(rows)), dim3(kBlock), 0, st, src, n, bsum,
+                       int(nb));
+    hipLaunchKernelGGL(k_scan_apply<Src>, dim3(unsigned(nb), unsigned(rows)), dim3(kBlock), 0, st, src, out, n, bsum,
+                       int(nb), totals);
 }
 
 }  // namespace
 
 size_t scan_scratch_bytes(int64_t n, int rows) {
-    size_t total = 0;
-    int64_t m = n;
-    while (m > 0) {
-        const int64_t nb = (m + kScanTile - 1) / kScanTile;
-        total += size_t(nb) * rows * 2 * sizeof(int32_t);
-        if (nb <= 1) break;
-        m = nb;
-    }
-    return total + 256;
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    return size_t(nb) * size_t(rows) * sizeof(int32_t) + 256;
 }
 
 void scan_rows(const int32_t* in, int32_t* out, int64_t n, int rows, int32_t* totals, void* scratch, hipStream_t st) {
-    if (n <= 0 || rows <= 0) return;
-    const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    int32_t* bsum = static_cast<int32_t*>(scratch);
-    int32_t* bscan = bsum + size_t(nb) * rows;
-    hipLaunchKernelGGL(k_scan_tiles, dim3(unsigned(nb), unsigned(rows)), dim3(kBlock), 0, st, in, out, n, bsum,
-                       int(nb));
-    if (nb > 1) {
-        scan_rows(bsum, bscan, nb, rows, nullptr, bscan + size_t(nb) * rows, st);
-        hipLaunchKernelGGL(k_scan_add, dim3(unsigned(nb), unsigned(rows)), dim3(kBlock), 0, st, out, n, bscan,
-                           int(nb));
-    }
-    if (totals)
-        hipLaunchKernelGGL(k_scan_totals, dim3(grid_for(rows)), dim3(kBlock), 0, st, in, out, n, rows, totals);
+    scan_source(RowsArray{in, n}, out, n, rows, totals, scratch, st);
+}
+
+void scan_leaf_starts(const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int64_t n, int32_t* out,
+                      void* scratch, hipStream_t st) {
+    scan_source(LeafStart{cl, pinst, inst}, out, n, 1, nullptr, scratch, st);
+}
+
+void scan_level_starts(const int8_t* leaf_cl, const int32_t* leaf_inst, const InstInfo* inst, int64_t nleaf,
+                       int Lmax, int32_t* out, void* scratch, hipStream_t st) {
+    scan_source(LevelStart{leaf_cl, leaf_inst, inst}, out, nleaf, Lmax, nullptr, scratch, st);
+}
+
+void scan_child_classes(const uint64_t* box_key, int64_t nbox, int32_t* out, int32_t* totals, void* scratch,
+                        hipStream_t st) {
+    scan_source(ChildClass{box_key}, out, nbox, 4, totals, scratch, st);
 }
 
 size_t radix_scratch_bytes(int64_t n) {
@@ -667,23 +728,11 @@ void launch_level_stats(const uint64_t* keys, const Chunk* chunks, int32_t nchun
                        maxc);
 }
 
-void launch_leaf_flags(const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int64_t n, int32_t* flags,
-                       hipStream_t st) {
-    hipLaunchKernelGGL(k_leaf_flags, dim3(grid_for(n)), dim3(kBlock), 0, st, cl, pinst, inst, n, flags);
-}
-
-void launch_leaf_scatter(const int32_t* flags, const int32_t* scan, const uint64_t* keys, const int8_t* cl,
-                         const int32_t* pinst, const InstInfo* inst, int Dmax, int64_t n, int32_t* leaf_pt0,
-                         uint64_t* leaf_key, int8_t* leaf_cl, int32_t* leaf_inst, hipStream_t st) {
-    hipLaunchKernelGGL(k_leaf_scatter, dim3(grid_for(n)), dim3(kBlock), 0, st, flags, scan, keys, cl, pinst, inst, Dmax,
+void launch_leaf_scatter(const int32_t* scan, const uint64_t* keys, const int8_t* cl, const int32_t* pinst,
+                         const InstInfo* inst, int Dmax, int64_t n, int32_t* leaf_pt0, uint64_t* leaf_key,
+                         int8_t* leaf_cl, int32_t* leaf_inst, hipStream_t st) {
+    hipLaunchKernelGGL(k_leaf_scatter, dim3(grid_for(n)), dim3(kBlock), 0, st, scan, keys, cl, pinst, inst, Dmax,
                        n, leaf_pt0, leaf_key, leaf_cl, leaf_inst);
-}
-
-void launch_level_flags(const int8_t* leaf_cl, const int32_t* leaf_inst, const InstInfo* inst, int64_t nleaf, int Lmax,
-                        int32_t* flags, hipStream_t st) {
-    if (Lmax <= 0 || nleaf <= 0) return;
-    hipLaunchKernelGGL(k_level_flags, dim3(grid_for(nleaf), unsigned(Lmax)), dim3(kBlock), 0, st, leaf_cl, leaf_inst,
-                       inst, nleaf, flags);
 }
 
 void launch_build_boxes(const int32_t* lscan, const int8_t* leaf_cl, const int32_t* leaf_pt0, const uint64_t* leaf_key,
@@ -702,18 +751,14 @@ void launch_link_boxes(const uint64_t* box_key, const int32_t* box_parent, const
                        inst, nbox, box_pt0, box_child, box_pt1);
 }
 
-void launch_lists(const int32_t* hbase, int H, const uint64_t* box_key, const int32_t* box_parent,
-                  const int32_t* box_child, const int8_t* box_lev, int32_t* nb9, int32_t* il27, hipStream_t st) {
-    for (int h = H; h >= 0; --h) {   // a box's lists need its parent's neighbour list
-        const int32_t g0 = hbase[h], g1 = hbase[h + 1];
-        if (g1 > g0)
-            hipLaunchKernelGGL(k_lists_height, dim3(grid_for(g1 - g0)), dim3(kBlock), 0, st, g0, g1, box_key,
-                               box_parent, box_child, box_lev, nb9, il27);
-    }
-}
-
-void launch_class_flags(const uint64_t* box_key, int64_t nbox, int32_t* flags, hipStream_t st) {
-    hipLaunchKernelGGL(k_class_flags, dim3(grid_for(nbox)), dim3(kBlock), 0, st, box_key, nbox, flags);
+void launch_lists(const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_child,
+                  const int32_t* box_inst, const int8_t* box_lev, const InstInfo* inst, int64_t nbox, int32_t* nb9,
+                  int32_t* il27, hipStream_t st) {
+    if (nbox <= 0) return;
+    hipLaunchKernelGGL(k_neighbours, dim3(grid_for(nbox)), dim3(kBlock), 0, st, box_key, box_inst, box_lev, inst, nbox,
+                       nb9);
+    hipLaunchKernelGGL(k_interactions, dim3(grid_for(nbox)), dim3(kBlock), 0, st, box_key, box_parent, box_child,
+                       box_lev, nbox, nb9, il27);
 }
 
 void launch_class_lists(const BoxGroup* groups, int32_t ngroups, int32_t nslots, const int32_t* cscan,

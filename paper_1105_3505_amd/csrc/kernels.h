@@ -111,6 +111,7 @@ size_t radix_scratch_bytes(int64_t n);
 int radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp,
                      int64_t n, int nbits, void* scratch, hipStream_t st);
 // exclusive scan of `rows` rows of n int32 each (row stride n); totals[rows] if non-null.
+// Two launches; scratch holds one sum per 2048 items and row.
 size_t scan_scratch_bytes(int64_t n, int rows);
 void scan_rows(const int32_t* in, int32_t* out, int64_t n, int rows, int32_t* totals,
                void* scratch, hipStream_t st);
@@ -132,14 +133,17 @@ void launch_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int3
 void launch_level_stats(const uint64_t* keys, const Chunk* chunks, int32_t nchunks,
                         const InstInfo* inst, int Dmax, int8_t* cl, int32_t* hist,
                         int32_t* maxc, hipStream_t st);
-void launch_leaf_flags(const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int64_t n,
-                       int32_t* flags, hipStream_t st);
-void launch_leaf_scatter(const int32_t* flags, const int32_t* scan, const uint64_t* keys,
-                         const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int Dmax,
-                         int64_t n, int32_t* leaf_pt0, uint64_t* leaf_key, int8_t* leaf_cl,
-                         int32_t* leaf_inst, hipStream_t st);
-void launch_level_flags(const int8_t* leaf_cl, const int32_t* leaf_inst, const InstInfo* inst,
-                        int64_t nleaf, int Lmax, int32_t* flags, hipStream_t st);
+// exclusive scans of the flags "a leaf starts here" (per point), "leaf b starts a box of
+// level lev" (row lev, per leaf) and "box g is child c of its parent" (row c, per box)
+void scan_leaf_starts(const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int64_t n, int32_t* out,
+                      void* scratch, hipStream_t st);
+void scan_level_starts(const int8_t* leaf_cl, const int32_t* leaf_inst, const InstInfo* inst, int64_t nleaf,
+                       int Lmax, int32_t* out, void* scratch, hipStream_t st);
+void scan_child_classes(const uint64_t* box_key, int64_t nbox, int32_t* out, int32_t* totals, void* scratch,
+                        hipStream_t st);
+void launch_leaf_scatter(const int32_t* scan, const uint64_t* keys, const int8_t* cl, const int32_t* pinst,
+                         const InstInfo* inst, int Dmax, int64_t n, int32_t* leaf_pt0, uint64_t* leaf_key,
+                         int8_t* leaf_cl, int32_t* leaf_inst, hipStream_t st);
 void launch_build_boxes(const int32_t* lscan, const int8_t* leaf_cl, const int32_t* leaf_pt0,
                         const uint64_t* leaf_key, const int32_t* leaf_inst, const InstInfo* inst,
                         int64_t nleaf, int Lmax, uint64_t* box_key, int32_t* box_pt0,
@@ -150,12 +154,11 @@ void launch_link_boxes(const uint64_t* box_key, const int32_t* box_parent, const
                        const int32_t* box_pt0, int32_t* box_child, int32_t* box_pt1,
                        hipStream_t st);
 // neighbour (9 slots, every box) and interaction (27 slots, boxes of level >= 2) lists of
-// every box, height by height from the top (hbase[h] = first box of height h, H + 2 entries),
-// each from its parent's neighbour list
-void launch_lists(const int32_t* hbase, int H, const uint64_t* box_key, const int32_t* box_parent,
-                  const int32_t* box_child, const int8_t* box_lev, int32_t* nb9, int32_t* il27,
-                  hipStream_t st);
-void launch_class_flags(const uint64_t* box_key, int64_t nbox, int32_t* flags, hipStream_t st);
+// every box: neighbours by search among the boxes of the same level, then interaction
+// lists from the parents' neighbours
+void launch_lists(const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_child,
+                  const int32_t* box_inst, const int8_t* box_lev, const InstInfo* inst, int64_t nbox, int32_t* nb9,
+                  int32_t* il27, hipStream_t st);
 // class lists (boxes of each group sorted by child position) and the tiles over them;
 // nslots = tile slots of all groups
 void launch_class_lists(const BoxGroup* groups, int32_t ngroups, int32_t nslots, const int32_t* cscan,

@@ -30,8 +30,8 @@
  *  - The well-posedness condition of Section 1 is a zero total load.  The library returns
  *    the finite sum for any loads; a non-zero sum is not an error.
  *  - One host thread per context at a time.  Plans of one context are independent.
- *    Destroy every plan before its context: plans draw their device memory from the
- *    context's pool.
+ *    Plans draw their device memory from the context's pool: lfmm_ctx_destroy destroys the
+ *    servers and plans still alive on the context, whose handles then become invalid.
  */
 #ifndef LFMM_H
 #define LFMM_H

@@ -331,7 +331,10 @@ class Plan:
 
     def close(self) -> None:
         if getattr(self, "_h", None):
-            _lib.lfmm_plan_destroy(self._h)
+            # a closed context has destroyed its plans already (garbage collection may finalise
+            # the context first)
+            if getattr(self.ctx, "_h", None):
+                _lib.lfmm_plan_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -443,7 +446,8 @@ class Server:
     def close(self) -> None:
         """Serves every queued request, then stops the worker."""
         if getattr(self, "_h", None):
-            _lib.lfmm_server_destroy(self._h)
+            if getattr(self.ctx, "_h", None):   # else destroyed with its context
+                _lib.lfmm_server_destroy(self._h)
             self._h = None
             self._held.clear()
 

@@ -26,5 +26,8 @@ OperatorParams operator_params(const lfmm_options& o);
 void plan_destroy_completed(lfmm_plan* plan);
 // Device of a context.
 int ctx_device(const lfmm_ctx* ctx);
+// Servers of a context, destroyed with it if still alive.
+void ctx_add_server(lfmm_ctx* ctx, lfmm_server* srv);
+void ctx_remove_server(lfmm_ctx* ctx, lfmm_server* srv);
 
 }  // namespace lfmm

@@ -10,6 +10,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -196,6 +197,10 @@ struct lfmm_ctx {
     hipStream_t aux = nullptr;                        // second stream of plan construction
     hipEvent_t fork = nullptr, join = nullptr;
     std::mutex mu;
+    // live plans and servers, destroyed with the context if the caller has not done so
+    std::set<lfmm_plan*> plans;
+    std::set<lfmm_server*> servers;
+    std::mutex reg_mu;
     ~lfmm_ctx() {
         if (capture) (void)hipStreamDestroy(capture);
         if (aux) (void)hipStreamDestroy(aux);
@@ -265,6 +270,10 @@ struct lfmm_plan {
     hipGraphExec_t gexec = nullptr;
     hipEvent_t ev[LFMM_NUM_PHASES + 1] = {};
     ~lfmm_plan() {
+        {
+            std::lock_guard<std::mutex> lock(ctx->reg_mu);
+            ctx->plans.erase(this);
+        }
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         for (auto& e : ev)
@@ -359,26 +368,37 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st) {
     // next to lane l+1's, so a wave reads 1 KB contiguous per load (P = 48: 3 row blocks,
     // lane group g = l / 16 covers columns 12 g .. 12 g + 11)
     {
-        const size_t nmat = ifo.size() / (size_t(P) * P);
-        std::vector<double> f64(ifo.size());
-        std::vector<float> fhi(ifo.size()), flo(ifo.size());
-        for (size_t t = 0; t < nmat; ++t) {
-            const size_t base = t * P * P;
-            for (int m = 0; m < P / 16; ++m)
-                for (int l = 0; l < 64; ++l) {
-                    const int row = 16 * m + (l & 15), c0 = (l >> 4) * (P / 4);
-                    for (int k = 0; k < P / 4; ++k) {
-                        const size_t src = base + size_t(row) * P + c0 + k;
-                        f64[base + ((size_t(m) * (P / 8) + k / 2) * 64 + l) * 2 + (k & 1)] = ifo[src];
-                        const size_t d32 = base + ((size_t(m) * (P / 16) + k / 4) * 64 + l) * 4 + (k & 3);
-                        fhi[d32] = ifo_hi[src];
-                        flo[d32] = ifo_lo[src];
+        // FP64 order: element ((m * 6 + j) * 64 + l) * 2 + e is row 16 m + l % 16, column
+        // 12 (l / 16) + 2 j + e; FP32 order: ((m * 3 + j) * 64 + l) * 4 + e, column 12 (l / 16) + 4 j + e
+        auto frag64 = [&](std::vector<double>& a) {
+            std::vector<double> out(a.size());
+            for (size_t base = 0; base < a.size(); base += size_t(P) * P)
+                for (int m = 0; m < P / 16; ++m)
+                    for (int l = 0; l < 64; ++l) {
+                        const int row = 16 * m + (l & 15), c0 = (l >> 4) * (P / 4);
+                        for (int k = 0; k < P / 4; ++k)
+                            out[base + ((size_t(m) * (P / 8) + k / 2) * 64 + l) * 2 + (k & 1)] =
+                                a[base + size_t(row) * P + c0 + k];
                     }
-                }
-        }
-        ifo.swap(f64);
-        ifo_hi.swap(fhi);
-        ifo_lo.swap(flo);
+            a.swap(out);
+        };
+        auto frag32 = [&](std::vector<float>& a) {
+            std::vector<float> out(a.size());
+            for (size_t base = 0; base < a.size(); base += size_t(P) * P)
+                for (int m = 0; m < P / 16; ++m)
+                    for (int l = 0; l < 64; ++l) {
+                        const int row = 16 * m + (l & 15), c0 = (l >> 4) * (P / 4);
+                        for (int k = 0; k < P / 4; ++k)
+                            out[base + ((size_t(m) * (P / 16) + k / 4) * 64 + l) * 4 + (k & 3)] =
+                                a[base + size_t(row) * P + c0 + k];
+                    }
+            a.swap(out);
+        };
+        frag64(ifo);
+        frag64(ofo_rm);
+        frag64(ofo_cm);
+        frag32(ifo_hi);
+        frag32(ifo_lo);
     }
     co->mem.reserve(ifo.size() * sizeof(float));
     co->mem.reserve(ifo.size() * sizeof(float));
@@ -783,8 +803,8 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
         for (size_t o = 0; o < side_of.size(); ++o) {
             int32_t g0, g1;
             range_of(h, int(o), 2, g0, g1);
-            for (int32_t s = g0; g0 >= 0 && s < g1; s += 16) {
-                m2m_tiles.push_back(BoxTile{int32_t(o), h, 0, s, std::min(16, g1 - s), 0, 0, 0});
+            for (int32_t s = g0; g0 >= 0 && s < g1; s += kBoxMatTile) {
+                m2m_tiles.push_back(BoxTile{int32_t(o), h, 0, s, std::min(kBoxMatTile, g1 - s), 0, 0, 0});
                 ++tile_slots;
             }
         }
@@ -809,7 +829,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     mb.reserve(size_t(std::max(pl->nq, 1)) * sizeof(NearGroup));
     mb.reserve(size_t(std::max(pl->nq, 1)) * kNearEntries * sizeof(int4));
     mb.reserve(std::max<size_t>(root_list.size(), 1) * sizeof(int32_t));
-    mb.reserve(size_t(nb) * P * 8);                      // U
+    mb.reserve(size_t(nb + 1) * P * 8);                  // U and its zero row
     mb.allocate();
     pl->box_key = mb.take<uint64_t>(nb);
     pl->box_pt0 = mb.take<int32_t>(nb);
@@ -825,14 +845,15 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     pl->tiles = mb.take<BoxTile>(std::max(tile_slots, 1));
     BoxGroup* d_groups = mb.take<BoxGroup>(std::max<size_t>(m2l_groups.size() + l2l_groups.size(), 1));
     pl->Q = mb.take<double>(size_t(nb + 1) * P);
-    pl->U = mb.take<double>(size_t(nb) * P);
+    pl->U = mb.take<double>(size_t(nb + 1) * P);
     pl->groups = mb.take<NearGroup>(size_t(std::max(pl->nq, 1)));
     pl->ents = mb.take<int4>(size_t(std::max(pl->nq, 1)) * kNearEntries);
     int32_t* d_roots = mb.take<int32_t>(std::max<size_t>(root_list.size(), 1));
     Stager stage_c(ctx);
     stage_c.add(d_roots, root_list);
-    // row nb of Q stays zero: the M2L kernels read it for empty list slots
+    // row nb of Q and of U stays zero: the box-matrix kernels read it for absent sources
     LFMM_HIP(hipMemsetAsync(pl->Q + size_t(nb) * P, 0, size_t(P) * sizeof(double), st));
+    LFMM_HIP(hipMemsetAsync(pl->U + size_t(nb) * P, 0, size_t(P) * sizeof(double), st));
 
     // ---- tables ---------------------------------------------------------------------------------
     stage_c.add(pl->d_inst, pl->inst);
@@ -933,9 +954,7 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
     mark(2);
     for (int h = 1; h <= pl->Hmax; ++h) {
         const TileRange& r = pl->m2m[size_t(h)];
-        if (r.n > 0)
-            launch_boxmat(kModeM2M, pl->tiles, r.t0, nullptr, r.n, r.n, nullptr, pl->box_child, pl->d_ops, pl->Q,
-                          pl->Q, st);
+        if (r.n > 0) launch_m2m(pl->tiles + r.t0, r.n, pl->box_child, pl->d_ops, pl->Q, pl->nbox, st);
     }
     mark(3);
     if (pl->m2l.n > 0) {
@@ -948,9 +967,7 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
     mark(4);
     for (int h = pl->Hmax; h >= 0; --h) {
         const TileRange& r = pl->l2l[size_t(h)];
-        if (r.n > 0)
-            launch_boxmat(kModeL2L, pl->tiles, r.t0, nullptr, r.n, r.n, pl->cls_box, pl->box_parent, pl->d_ops, pl->U,
-                          pl->U, st);
+        if (r.n > 0) launch_l2l(pl->tiles + r.t0, r.n, pl->cls_box, pl->box_parent, pl->d_ops, pl->U, pl->nbox, st);
     }
     mark(5);
     for (size_t o = 0; o < pl->ops.size(); ++o) {
@@ -1004,6 +1021,16 @@ void lfmm::plan_destroy_completed(lfmm_plan* pl) { delete pl; }
 
 int lfmm::ctx_device(const lfmm_ctx* ctx) { return ctx->device; }
 
+void lfmm::ctx_add_server(lfmm_ctx* ctx, lfmm_server* srv) {
+    std::lock_guard<std::mutex> lock(ctx->reg_mu);
+    ctx->servers.insert(srv);
+}
+
+void lfmm::ctx_remove_server(lfmm_ctx* ctx, lfmm_server* srv) {
+    std::lock_guard<std::mutex> lock(ctx->reg_mu);
+    ctx->servers.erase(srv);
+}
+
 namespace {
 
 template <class F>
@@ -1041,6 +1068,10 @@ lfmm_status create_forest(lfmm_ctx* ctx, int32_t K, const int64_t* sizes, const 
         auto pl = std::make_unique<lfmm_plan>();
         pl->ctx = ctx;
         build_forest(pl.get(), K, sizes, xy, max_leaf, as_stream(stream));
+        {
+            std::lock_guard<std::mutex> lock(ctx->reg_mu);
+            ctx->plans.insert(pl.get());
+        }
         *out = pl.release();
         return LFMM_OK;
     });
@@ -1098,7 +1129,20 @@ lfmm_status lfmm_ctx_create(int32_t device, const lfmm_options* opt, lfmm_ctx** 
 lfmm_status lfmm_ctx_destroy(lfmm_ctx* ctx) {
     if (!ctx) return LFMM_OK;
     (void)hipSetDevice(ctx->device);
+    // servers first (their workers build and drop plans), then the plans still alive
+    std::vector<lfmm_server*> servers;
+    {
+        std::lock_guard<std::mutex> lock(ctx->reg_mu);
+        servers.assign(ctx->servers.begin(), ctx->servers.end());
+    }
+    for (lfmm_server* s : servers) lfmm_server_destroy(s);
     (void)hipDeviceSynchronize();
+    std::vector<lfmm_plan*> plans;
+    {
+        std::lock_guard<std::mutex> lock(ctx->reg_mu);
+        plans.assign(ctx->plans.begin(), ctx->plans.end());
+    }
+    for (lfmm_plan* p : plans) delete p;
     delete ctx;
     return LFMM_OK;
 }

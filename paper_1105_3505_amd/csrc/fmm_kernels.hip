@@ -79,7 +79,10 @@ __global__ void k_gather_f(const ExecPtrs* tab, const double* f_single, const in
 }
 
 // P2M with the dense-model operator (Remark 8.2): q-hat[p] = sum_j T[loc(j)][p] f_j; one
-// wave per leaf, four independent accumulators so that four rows are in flight.
+// wave per leaf, lane p < P accumulating entry p.  The leaf's points are loaded once, one
+// per lane (coalesced), and handed to all lanes by shuffles, so the only memory reads in the
+// loop are the operator rows, whose addresses are known in advance and can be in flight
+// together.
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0,
                                                  const int32_t* box_pt1, const uint64_t* box_key, int64_t side,
@@ -92,18 +95,26 @@ __global__ __launch_bounds__(kBlock) void k_p2m(int32_t leaf0, int32_t leaf1, co
     const int32_t cx = int32_t(compact_bits(key) * side), cy = int32_t(compact_bits(key >> 1) * side);
     const int l = lane < P ? lane : 0;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int32_t j = p0;
-    for (; j + 3 < p1; j += 4) {
-        const int2 q0 = pts[j], q1 = pts[j + 1], q2 = pts[j + 2], q3 = pts[j + 3];
-        const double f0 = fs[j], f1 = fs[j + 1], f2 = fs[j + 2], f3 = fs[j + 3];
-        a0 += leafT[(int64_t(q0.x - cx) + side * int64_t(q0.y - cy)) * P + l] * f0;
-        a1 += leafT[(int64_t(q1.x - cx) + side * int64_t(q1.y - cy)) * P + l] * f1;
-        a2 += leafT[(int64_t(q2.x - cx) + side * int64_t(q2.y - cy)) * P + l] * f2;
-        a3 += leafT[(int64_t(q3.x - cx) + side * int64_t(q3.y - cy)) * P + l] * f3;
-    }
-    for (; j < p1; ++j) {
-        const int2 q = pts[j];
-        a0 += leafT[(int64_t(q.x - cx) + side * int64_t(q.y - cy)) * P + l] * fs[j];
+    for (int32_t c0 = p0; c0 < p1; c0 += 64) {
+        const int32_t j = c0 + lane;
+        int32_t loc = 0;   // lanes past the leaf's points carry a zero load at cell 0
+        double f = 0.0;
+        if (j < p1) {
+            const int2 q = pts[j];
+            loc = int32_t(int64_t(q.x - cx) + side * int64_t(q.y - cy));
+            f = fs[j];
+        }
+        const int cnt = min(64, p1 - c0);
+        for (int k = 0; k < cnt; k += 4) {   // k + 3 < 64: the tail reads the zero-load lanes
+            const int32_t l0 = __shfl(loc, k, 64), l1 = __shfl(loc, k + 1, 64);
+            const int32_t l2 = __shfl(loc, k + 2, 64), l3 = __shfl(loc, k + 3, 64);
+            const double f0 = __shfl(f, k, 64), f1 = __shfl(f, k + 1, 64);
+            const double f2 = __shfl(f, k + 2, 64), f3 = __shfl(f, k + 3, 64);
+            a0 += leafT[int64_t(l0) * P + l] * f0;
+            a1 += leafT[int64_t(l1) * P + l] * f1;
+            a2 += leafT[int64_t(l2) * P + l] * f2;
+            a3 += leafT[int64_t(l3) * P + l] * f3;
+        }
     }
     if (lane < P) Q[size_t(g) * P + lane] = (a0 + a1) + (a2 + a3);
 }
@@ -118,106 +129,20 @@ __device__ inline int32_t xcd_tile(int32_t b, int32_t G, int32_t step, int32_t n
     return (t < min(ntiles, (x + 1) * chunk)) ? t : -1;
 }
 
-// Box-matrix products on the FP64 matrix cores: for a tile of up to 16 target boxes that
-// share their operators, out[box] (+)= sum_k A_k in[src_k(box)] with 48 x 48 operators A_k:
-//   M2M: k = 4 children,            A_k = T_ofo^(k) at the tile's height,      out = Q;
-//   L2L: k = the parent,            A   = T_ofo^(c)T at the parent's height,  out += U.
-// The 16x16x4 FP64 instruction is issued per 16-row block of A: in step kk lane group g
-// (= lane / 16) contributes column q = g * 12 + kk, so each lane's operands are 12
-// consecutive doubles of a row of A and of the source expansion.  The instruction returns
-// element i of lane (g, n) as row g + 4 i, column n.  Slots are split over the block's four
-// waves (rows, for the single-slot L2L) and partial results are summed through LDS in a
-// fixed order, so results are deterministic.
-template <int P, int MODE>
-__global__ __launch_bounds__(kBlock) void k_boxmat(const BoxTile* tiles, int32_t tile0, const int32_t* ntiles_dev,
-                                                    int32_t ntiles_host, const int32_t* box_list, const int32_t* src_tab,
-                                                    const OpsPtrs* ops, const double* in, double* out) {
-    constexpr int MT = P / 16, KQ = P / 4;
-    constexpr int NSRC = (MODE == kModeM2M) ? 4 : 1;
-    __shared__ double red[kWaves - 1][P][16];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int n = lane & 15, g = lane >> 4;
-    const int32_t ntiles = ntiles_dev ? *ntiles_dev : ntiles_host;
-    const int32_t G = int32_t(gridDim.x);
-    for (int32_t step = 0;; ++step) {
-        const int32_t t = xcd_tile(int32_t(blockIdx.x), G, step, ntiles);
-        if (t < 0) break;                                   // uniform over the block
-        const BoxTile tl = tiles[tile0 + t];
-        if (tl.count == 0) continue;
-        const int32_t box = (n < tl.count) ? (box_list ? box_list[tl.start + n] : tl.start + n) : -1;
-        const OpsPtrs& op = ops[tl.ops];
-        double4_t acc[MT];
-        #pragma unroll
-        for (int m = 0; m < MT; ++m) acc[m] = double4_t{0.0, 0.0, 0.0, 0.0};
-        const int k_first = (NSRC >= kWaves) ? wave : 0;
-        const int k_step = (NSRC >= kWaves) ? kWaves : 1;
-        const bool active = (NSRC >= kWaves) || wave < MT;   // single-slot L2L: wave = row block
-        if (active) {
-            for (int k = k_first; k < NSRC; k += k_step) {
-                int32_t src = -1;
-                const double* A;
-                if (MODE == kModeM2M) {
-                    src = (box >= 0) ? src_tab[size_t(box) * 4 + k] : -1;
-                    A = op.ofo_rm + (size_t(tl.height) * 4 + k) * P * P;
-                } else {
-                    src = (box >= 0) ? src_tab[box] : -1;
-                    A = op.ofo_cm + (size_t(tl.height + 1) * 4 + tl.cls) * P * P;
-                }
-                double b[KQ];
-                if (src >= 0) {
-                    const double* qs = in + size_t(src) * P + g * KQ;
-                    #pragma unroll
-                    for (int kk = 0; kk < KQ; ++kk) b[kk] = qs[kk];
-                } else {
-                    #pragma unroll
-                    for (int kk = 0; kk < KQ; ++kk) b[kk] = 0.0;
-                }
-                #pragma unroll
-                for (int m = 0; m < MT; ++m) {
-                    if (MODE == kModeL2L && m != wave) continue;
-                    const double* a = A + size_t(16 * m + n) * P + g * KQ;
-                    #pragma unroll
-                    for (int kk = 0; kk < KQ; ++kk)
-                        acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b[kk], acc[m], 0, 0, 0);
-                }
-            }
-        }
-        if (wave > 0) {
-            #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                #pragma unroll
-                for (int i = 0; i < 4; ++i) red[wave - 1][16 * m + g + 4 * i][n] = acc[m][i];
-            }
-        }
-        __syncthreads();
-        if (wave == 0 && box >= 0) {
-            double* ob = out + size_t(box) * P;
-            #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = 16 * m + g + 4 * i;
-                    double v = acc[m][i];
-                    #pragma unroll
-                    for (int w = 0; w < kWaves - 1; ++w) v += red[w][r][n];
-                    ob[r] = (MODE == kModeL2L) ? ob[r] + v : v;
-                }
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// M2L on the matrix cores.  A tile holds up to 64 target boxes of one operator set, height
-// and child position; wave w of the block owns boxes 16 w .. 16 w + 15 (the 16 columns of
-// its products) and runs all 27 interaction slots, so no partial sums cross waves.  The
-// operator of each slot is stored in fragment order (lane l's operands of one instruction
-// next to lane l+1's), staged once per block in LDS with coalesced loads, double-buffered,
-// and read by all four waves; the next slot's operator and source expansions are loaded
-// into registers while the current slot's instructions run, and the list entry behind the
-// expansion read one slot before that.  One barrier per slot: the buffer a slot writes was
-// last read two slots earlier, before the previous slot's barrier.  Absent sources (empty
-// list slots, lanes past the tile) read the all-zero expansion row `zrow`.
+// Box-matrix passes on the FP64 matrix cores: for a tile of up to 64 target boxes that share
+// their operators, out[box] (+)= sum over slots k of A_k in[src_k(box)] with 48 x 48 A_k:
+//   M2L (Section 8.2 step 3): 27 interaction slots, A_k = T_ifo^d(k) at the tile's height
+//        and child position, in = Q, out = U;
+//   M2M (step 2): 4 children, A_k = T_ofo^(k) at the tile's height, in = out = Q;
+//   L2L (step 4): the parent, A = T_ofo^(c)T at the parent's height, in = out = U, added.
+// Wave w of the block owns boxes 16 w .. 16 w + 15 (the 16 columns of its products) and runs
+// every slot, so no partial sums cross waves.  Operators are stored in fragment order (lane
+// l's operands of one instruction next to lane l+1's), staged once per block in LDS with
+// coalesced loads, double-buffered, and read by all four waves; the next slot's operator and
+// source expansion are loaded into registers while the current slot's instructions run, and
+// the list entry behind the expansion read one slot before that.  One barrier per slot: the
+// buffer a slot writes was last read two slots earlier, before the previous slot's barrier.
+// Absent sources (empty list slots, lanes past the tile) read the all-zero row `zrow`.
 //
 // FP64: 16x16x4 instruction, step kk of row block m takes column g * 12 + kk in lane group
 // g = lane / 16; element i of lane (g, n) is row 16 m + g + 4 i, column n.
@@ -233,46 +158,54 @@ __device__ inline gptr<T> global(const T* p) {
     return (gptr<T>)(p);   // generic to global address space
 }
 
-__global__ __launch_bounds__(kBlock) void k_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list,
-                                                 const int32_t* il27, const OpsPtrs* ops, const double* Q,
-                                                 int32_t zrow, double* U) {
+template <int MODE>
+__device__ inline void boxmat_tiles(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list,
+                                    const int32_t* src_tab, const OpsPtrs* ops, const double* in, int32_t zrow,
+                                    double* out) {
     constexpr int P = kRankPad, MT = P / 16, KQ = P / 4, NJ = KQ / 2;
+    constexpr int NS = (MODE == kModeM2L) ? kNumInteractions : (MODE == kModeM2M ? 4 : 1);
+    constexpr int SW = (MODE == kModeM2L) ? kNumInteractions : (MODE == kModeM2M ? 4 : 1);   // source table width
     constexpr int A2 = P * P / 2;                      // double2_t per operator: 4.5 per thread
     static_assert(A2 == 4 * kBlock + kBlock / 2, "staging below assumes P = 48");
+    static_assert(MT == 3, "three row blocks");
     __shared__ double2_t sA[2][A2];
-    __shared__ int s_dsl[kNumInteractions];   // offset slot of each list slot of the tile's class
+    __shared__ int s_dsl[kNumInteractions];   // operator of each slot of the tile
     const int tid = int(threadIdx.x), wave = tid >> 6, lane = tid & 63;
     const int n = lane & 15, g = lane >> 4;
     const int32_t G = int32_t(gridDim.x);
     const double2_t z2 = {0.0, 0.0};
     for (int32_t step = 0;; ++step) {
         const int32_t t = uniform(xcd_tile(int32_t(blockIdx.x), G, step, ntiles));
-        if (t < 0) break;
+        if (t < 0) break;                                  // uniform over the block
         const int32_t count = uniform(tiles[t].count);
         if (count == 0) continue;
         const int32_t start = uniform(tiles[t].start), height = uniform(tiles[t].height);
         const int32_t cls = uniform(tiles[t].cls), opi = uniform(tiles[t].ops);
         const bool wave_on = 16 * wave < count;
         const int col = 16 * wave + n;
-        const int32_t box = (col < count) ? box_list[start + col] : -1;
-        const gptr<int32_t> il = global(il27 + size_t(box >= 0 ? box : 0) * kNumInteractions);
-        const gptr<double2_t> Ah = global(reinterpret_cast<const double2_t*>(ops[opi].ifo)) +
-                                 size_t(height) * kNumIfoSlots * A2;
-        const gptr<double> Qg = global(Q) + g * KQ;
-        if (tid < kNumInteractions) s_dsl[tid] = c_dslot.s[cls][tid];
+        const int32_t box = (col < count) ? (box_list ? box_list[start + col] : start + col) : -1;
+        const gptr<int32_t> srcs = global(src_tab + size_t(box >= 0 ? box : 0) * SW);
+        const double* base = (MODE == kModeM2L) ? ops[opi].ifo : (MODE == kModeM2M ? ops[opi].ofo_rm : ops[opi].ofo_cm);
+        const gptr<double2_t> Ah = global(reinterpret_cast<const double2_t*>(base));
+        const gptr<double> Xg = global(in) + g * KQ;
+        if (tid < NS) {
+            if (MODE == kModeM2L) s_dsl[tid] = height * kNumIfoSlots + c_dslot.s[cls][tid];
+            else if (MODE == kModeM2M) s_dsl[tid] = height * 4 + tid;
+            else s_dsl[tid] = (height + 1) * 4 + cls;
+        }
         __syncthreads();
         const int* dsl = s_dsl;
         // slot 0 operands
-        int32_t src = (box >= 0) ? il[0] : -1;
+        int32_t src = (box >= 0) ? srcs[0] : -1;
         src = src < 0 ? zrow : src;
-        const gptr<double2_t> qs = reinterpret_cast<gptr<double2_t>>(Qg + size_t(src) * P);
+        const gptr<double2_t> qs = reinterpret_cast<gptr<double2_t>>(Xg + size_t(src) * P);
         double2_t rb0 = qs[0], rb1 = qs[1], rb2 = qs[2], rb3 = qs[3], rb4 = qs[4], rb5 = qs[5];
-        int32_t src_next = (box >= 0) ? il[1] : -1;
+        int32_t src_next = (box >= 0 && NS > 1) ? srcs[1] : -1;
         const gptr<double2_t> Ak = Ah + size_t(dsl[0]) * A2;
         double2_t ra0 = Ak[tid], ra1 = Ak[tid + kBlock], ra2 = Ak[tid + 2 * kBlock], ra3 = Ak[tid + 3 * kBlock];
         double2_t ra4 = (tid < kBlock / 2) ? Ak[tid + 4 * kBlock] : z2;
         double4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0;
-        for (int k = 0; k < kNumInteractions; ++k) {
+        for (int k = 0; k < NS; ++k) {
             double2_t* buf = sA[k & 1];
             buf[tid] = ra0;
             buf[tid + kBlock] = ra1;
@@ -281,17 +214,17 @@ __global__ __launch_bounds__(kBlock) void k_m2l(const BoxTile* tiles, int32_t nt
             if (tid < kBlock / 2) buf[tid + 4 * kBlock] = ra4;
             const double2_t b[NJ] = {rb0, rb1, rb2, rb3, rb4, rb5};
             __syncthreads();
-            if (k + 1 < kNumInteractions) {
+            if (k + 1 < NS) {
                 // expansions first: their address waits only for the list entry read a slot ago
                 const int32_t sn = src_next < 0 ? zrow : src_next;
-                const gptr<double2_t> qn = reinterpret_cast<gptr<double2_t>>(Qg + size_t(sn) * P);
+                const gptr<double2_t> qn = reinterpret_cast<gptr<double2_t>>(Xg + size_t(sn) * P);
                 rb0 = qn[0];
                 rb1 = qn[1];
                 rb2 = qn[2];
                 rb3 = qn[3];
                 rb4 = qn[4];
                 rb5 = qn[5];
-                src_next = (box >= 0 && k + 2 < kNumInteractions) ? il[k + 2] : -1;
+                src_next = (box >= 0 && k + 2 < NS) ? srcs[k + 2] : -1;
                 const gptr<double2_t> An = Ah + size_t(dsl[k + 1]) * A2;
                 ra0 = An[tid];
                 ra1 = An[tid + kBlock];
@@ -314,18 +247,40 @@ __global__ __launch_bounds__(kBlock) void k_m2l(const BoxTile* tiles, int32_t nt
                 }
             }
         }
-        static_assert(MT == 3, "three row blocks");
         if (box >= 0) {
-            double* ub = U + size_t(box) * P;
+            double* ob = out + size_t(box) * P;
             #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                ub[g + 4 * i] = acc0[i];
-                ub[16 + g + 4 * i] = acc1[i];
-                ub[32 + g + 4 * i] = acc2[i];
+                if (MODE == kModeL2L) {
+                    ob[g + 4 * i] += acc0[i];
+                    ob[16 + g + 4 * i] += acc1[i];
+                    ob[32 + g + 4 * i] += acc2[i];
+                } else {
+                    ob[g + 4 * i] = acc0[i];
+                    ob[16 + g + 4 * i] = acc1[i];
+                    ob[32 + g + 4 * i] = acc2[i];
+                }
             }
         }
         __syncthreads();   // the next tile's first slot rewrites a buffer read above
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list,
+                                                 const int32_t* il27, const OpsPtrs* ops, const double* Q,
+                                                 int32_t zrow, double* U) {
+    boxmat_tiles<kModeM2L>(tiles, ntiles, box_list, il27, ops, Q, zrow, U);
+}
+
+__global__ __launch_bounds__(kBlock) void k_m2m(const BoxTile* tiles, int32_t ntiles, const int32_t* box_child,
+                                                 const OpsPtrs* ops, double* Q, int32_t zrow) {
+    boxmat_tiles<kModeM2M>(tiles, ntiles, nullptr, box_child, ops, Q, zrow, Q);
+}
+
+__global__ __launch_bounds__(kBlock) void k_l2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list,
+                                                 const int32_t* box_parent, const OpsPtrs* ops, double* U,
+                                                 int32_t zrow) {
+    boxmat_tiles<kModeL2L>(tiles, ntiles, box_list, box_parent, ops, U, zrow, U);
 }
 
 // Mixed-precision M2L on the FP32 matrix cores, same tiling and staging as k_m2l.  Each
@@ -719,20 +674,22 @@ void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int3
                        box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), fs, leafT, Q);
 }
 
-void launch_boxmat(int mode, const BoxTile* tiles, int32_t tile0, const int32_t* ntiles_dev, int32_t ntiles_host,
-                   int32_t max_tiles, const int32_t* box_list, const int32_t* src, const OpsPtrs* ops,
-                   const double* in, double* out, hipStream_t st) {
-    if (max_tiles <= 0) return;
-    // one tile per block and step; a multiple of 8 blocks keeps the XCD chunks balanced
-    int64_t g = std::min<int64_t>(max_tiles, 8192);
+void launch_m2m(const BoxTile* tiles, int32_t ntiles, const int32_t* box_child, const OpsPtrs* ops, double* Q,
+                int32_t zrow, hipStream_t st) {
+    if (ntiles <= 0) return;
+    int64_t g = std::min<int64_t>(ntiles, 8192);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
-    const dim3 grid(static_cast<unsigned>(g)), block(kBlock);
-    if (mode == kModeM2M)
-        hipLaunchKernelGGL((k_boxmat<kRankPad, kModeM2M>), grid, block, 0, st, tiles, tile0, ntiles_dev, ntiles_host,
-                           box_list, src, ops, in, out);
-    else
-        hipLaunchKernelGGL((k_boxmat<kRankPad, kModeL2L>), grid, block, 0, st, tiles, tile0, ntiles_dev, ntiles_host,
-                           box_list, src, ops, in, out);
+    hipLaunchKernelGGL(k_m2m, dim3(static_cast<unsigned>(g)), dim3(kBlock), 0, st, tiles, ntiles, box_child, ops, Q,
+                       zrow);
+}
+
+void launch_l2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, const int32_t* box_parent,
+                const OpsPtrs* ops, double* U, int32_t zrow, hipStream_t st) {
+    if (ntiles <= 0) return;
+    int64_t g = std::min<int64_t>(ntiles, 8192);
+    g = std::max<int64_t>(8, (g + 7) / 8 * 8);
+    hipLaunchKernelGGL(k_l2l, dim3(static_cast<unsigned>(g)), dim3(kBlock), 0, st, tiles, ntiles, box_list,
+                       box_parent, ops, U, zrow);
 }
 
 void launch_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, const int32_t* il27,

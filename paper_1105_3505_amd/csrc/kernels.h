@@ -50,18 +50,19 @@ struct BoxGroup {
     int32_t ops, height, g0, g1, cls_base, tile_base, tile_cap, tile_boxes;
 };
 
-// Boxes per tile: the M2L kernel gives 16 boxes to each of its 4 waves; the M2M and L2L
-// kernel puts 16 boxes in one block.
+// Boxes per tile: the box-matrix kernels give 16 boxes to each of their 4 waves.
 constexpr int kM2LTile = 64;
-constexpr int kBoxMatTile = 16;
+constexpr int kBoxMatTile = 64;
 
 // Per leaf side: operators in device memory (uploaded once, shared by every plan).
 struct DevOps {
     int64_t leaf_side = 0;
     int nlev = 0;                  // heights 0 .. nlev-1
     double* leafT = nullptr;       // [side^2][kRankPad]: T_ofs column of each cell, cell-major
-    double* ofo_rm = nullptr;      // [nlev][4][r parent][q child]: T_ofo (M2M operand)
-    double* ofo_cm = nullptr;      // [nlev][4][q child][r parent]: T_ofo^T (L2L operand)
+    // [nlev][4] operators in the fragment order of ifo below: T_ofo (M2M, rows = parent
+    // skeleton) and T_ofo^T (L2L, rows = child skeleton)
+    double* ofo_rm = nullptr;
+    double* ofo_cm = nullptr;
     // T_ifo per height and offset slot, [nlev][49][48 x 48] in fragment order: element
     // ((m * 6 + j) * 64 + l) * 2 + e is row 16 m + (l % 16), column (l / 16) * 12 + 2 j + e
     double* ifo = nullptr;
@@ -102,7 +103,7 @@ struct ExecPtrs {
     double* u;
 };
 
-enum BoxMatMode { kModeM2M = 1, kModeL2L = 2 };
+enum BoxMatMode { kModeM2L = 0, kModeM2M = 1, kModeL2L = 2 };
 
 // ---- construction (forest_kernels.hip) ---------------------------------------------------
 size_t radix_scratch_bytes(int64_t n);
@@ -179,10 +180,12 @@ void launch_gather_f(const ExecPtrs* tab, const double* f_single, const int32_t*
 void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1,
                 const uint64_t* box_key, int64_t side, const int32_t* pts, const double* fs,
                 const double* leafT, double* Q, hipStream_t st);
-void launch_boxmat(int mode, const BoxTile* tiles, int32_t tile0, const int32_t* ntiles_dev,
-                   int32_t ntiles_host, int32_t max_tiles, const int32_t* box_list,
-                   const int32_t* src, const OpsPtrs* ops, const double* in, double* out,
-                   hipStream_t st);
+// M2M over the consecutive-box tiles of one height (Q row zrow is all zeros)
+void launch_m2m(const BoxTile* tiles, int32_t ntiles, const int32_t* box_child, const OpsPtrs* ops, double* Q,
+                int32_t zrow, hipStream_t st);
+// L2L over the class-sorted tiles of one height (U row zrow is all zeros)
+void launch_l2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, const int32_t* box_parent,
+                const OpsPtrs* ops, double* U, int32_t zrow, hipStream_t st);
 // M2L over the class-sorted tiles; Q row zrow is all zeros (read for absent sources)
 void launch_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, const int32_t* il27,
                 const OpsPtrs* ops, const double* Q, int32_t zrow, double* U, hipStream_t st);

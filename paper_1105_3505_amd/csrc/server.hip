@@ -254,6 +254,7 @@ lfmm_status lfmm_server_create(lfmm_ctx* ctx, const lfmm_server_options* opt, lf
     }
     lfmm_server* raw = srv.get();
     srv->worker = std::thread([raw] { raw->run(); });
+    ctx_add_server(ctx, raw);
     *out = srv.release();
     return LFMM_OK;
 }
@@ -313,6 +314,7 @@ lfmm_status lfmm_server_destroy(lfmm_server* srv) {
     srv->cv_work.notify_all();
     if (srv->worker.joinable()) srv->worker.join();
     for (hipStream_t s : srv->streams) (void)hipStreamDestroy(s);
+    ctx_remove_server(srv->ctx, srv);
     delete srv;
     return LFMM_OK;
 }

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -38,10 +39,47 @@ struct NoMemory {
     std::string msg;
 };
 
+// An event recorded after the last work that uses some blocks; blocks released "after" it
+// become reusable once the device has passed it.
+struct Fence {
+    hipEvent_t ev = nullptr;
+    Fence(hipStream_t st) {
+        LFMM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        LFMM_HIP(hipEventRecord(ev, st));
+    }
+    Fence(const Fence&) = delete;
+    Fence& operator=(const Fence&) = delete;
+    bool passed() const { return hipEventQuery(ev) == hipSuccess; }
+    ~Fence() {
+        if (ev) (void)hipEventDestroy(ev);
+    }
+};
+using FencePtr = std::shared_ptr<Fence>;
+
+// Blocks released after a fence, handed back to their free list once it has passed.
+struct Deferred {
+    struct Item {
+        size_t cls;
+        void* p;
+        FencePtr fence;
+    };
+    std::vector<Item> items;
+    template <class F>
+    void reap(F&& give_back, bool wait) {
+        size_t k = 0;
+        for (Item& it : items) {
+            if (wait) (void)hipEventSynchronize(it.fence->ev);
+            if (wait || it.fence->passed()) give_back(it.cls, it.p);
+            else items[k++] = std::move(it);
+        }
+        items.resize(k);
+    }
+};
+
 // Device blocks cached by power-of-two size class, so that building and dropping plans
 // does not call hipMalloc/hipFree (each costs far more than a small solve).  A block is
-// returned only after the work that used it is ordered before any later user (same
-// stream, or a synchronisation before the release).
+// returned only after the work that used it is ordered before any later user: a release
+// follows a synchronisation, or names the fence after which the block is free.
 class DevicePool {
   public:
     static size_t size_class(size_t bytes) {
@@ -53,6 +91,7 @@ class DevicePool {
         size_t cls = size_class(bytes);
         {
             std::lock_guard<std::mutex> lock(mu_);
+            if (!pending_.items.empty()) pending_.reap([&](size_t c, void* q) { give_back(c, q); }, false);
             auto it = free_.find(cls);
             if (it != free_.end()) {
                 void* p = it->second;
@@ -78,11 +117,15 @@ class DevicePool {
     }
     void release(void* p, size_t cls) {
         std::lock_guard<std::mutex> lock(mu_);
-        free_.emplace(cls, p);
-        cached_ += cls;
+        give_back(cls, p);
+    }
+    void release_after(void* p, size_t cls, const FencePtr& fence) {
+        std::lock_guard<std::mutex> lock(mu_);
+        pending_.items.push_back(Deferred::Item{cls, p, fence});
     }
     void trim() {
         std::lock_guard<std::mutex> lock(mu_);
+        pending_.reap([&](size_t c, void* q) { give_back(c, q); }, true);
         for (auto& kv : free_) (void)hipFree(kv.second);
         free_.clear();
         cached_ = 0;
@@ -91,7 +134,12 @@ class DevicePool {
     ~DevicePool() { trim(); }
 
   private:
+    void give_back(size_t cls, void* p) {
+        free_.emplace(cls, p);
+        cached_ += cls;
+    }
     std::multimap<size_t, void*> free_;
+    Deferred pending_;
     size_t cached_ = 0;
     std::mutex mu_;
 };
@@ -131,6 +179,15 @@ class Arena {
         base_ = nullptr;
         total_ = used_ = cap_ = 0;
     }
+    // back to the pool once the device has passed `fence` (pool arenas only)
+    void release_after(const FencePtr& fence) {
+        if (base_ && pool_) {
+            pool_->release_after(base_, cap_, fence);
+            base_ = nullptr;
+            total_ = used_ = cap_ = 0;
+        }
+        release();
+    }
     size_t bytes() const { return cap_; }
     void set_pool(DevicePool* p) { pool_ = p; }
     ~Arena() { release(); }
@@ -159,6 +216,8 @@ class PinnedPool {
         *got = cls;
         {
             std::lock_guard<std::mutex> lock(mu_);
+            if (!pending_.items.empty())
+                pending_.reap([&](size_t c, void* q) { free_.emplace(c, q); }, false);
             auto it = free_.find(cls);
             if (it != free_.end()) {
                 void* p = it->second;
@@ -174,12 +233,18 @@ class PinnedPool {
         std::lock_guard<std::mutex> lock(mu_);
         free_.emplace(cls, p);
     }
+    void release_after(void* p, size_t cls, const FencePtr& fence) {
+        std::lock_guard<std::mutex> lock(mu_);
+        pending_.items.push_back(Deferred::Item{cls, p, fence});
+    }
     ~PinnedPool() {
+        pending_.reap([&](size_t c, void* q) { free_.emplace(c, q); }, true);
         for (auto& kv : free_) (void)hipHostFree(kv.second);
     }
 
   private:
     std::multimap<size_t, void*> free_;
+    Deferred pending_;
     std::mutex mu_;
 };
 
@@ -247,6 +312,7 @@ struct lfmm_plan {
     OpsPtrs* d_ops = nullptr;
     uint8_t* d_far = nullptr;
     ExecPtrs* d_exec = nullptr;
+    BoxTile* m2m_tiles = nullptr;           // M2M tiles (pl->m2m ranges index them)
     int32_t* d_m2l_ntiles = nullptr;
     int32_t *pts = nullptr, *perm = nullptr, *pinst = nullptr;
     uint32_t* pkey = nullptr;
@@ -269,6 +335,8 @@ struct lfmm_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipEvent_t ev[LFMM_NUM_PHASES + 1] = {};
+    FencePtr built;                         // end of the build, on build_stream
+    hipStream_t build_stream = nullptr;
     ~lfmm_plan() {
         {
             std::lock_guard<std::mutex> lock(ctx->reg_mu);
@@ -482,6 +550,11 @@ class Stager {
         }
         pieces_.clear();
     }
+    // the pinned blocks go back once the device has passed `fence` (after the copies)
+    void retire(const FencePtr& fence) {
+        for (auto& b : held_) ctx_->pinned.release_after(b.first, b.second, fence);
+        held_.clear();
+    }
     ~Stager() {
         for (auto& b : held_) ctx_->pinned.release(b.first, b.second);
     }
@@ -494,6 +567,15 @@ class Stager {
     lfmm_ctx* ctx_;
     std::vector<Piece> pieces_;
     std::vector<std::pair<void*, size_t>> held_;
+};
+
+// On the way out of a failed build: finish the device work before the blocks it uses go
+// back to their pools.
+struct SyncOnUnwind {
+    int pending = std::uncaught_exceptions();
+    ~SyncOnUnwind() {
+        if (std::uncaught_exceptions() > pending) (void)hipDeviceSynchronize();
+    }
 };
 
 // Builds the forest of K point sets: Section 6 tree of every instance, lists of Definition 6.1,
@@ -525,7 +607,8 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     tmp.reserve(size_t(nch) * sizeof(Chunk));
     tmp.reserve(size_t(K + 1) * 4);             // chunk_first
     tmp.reserve(size_t(nch) * 16);              // bbox partials
-    tmp.reserve(size_t(K) * (kMaxLevels + 3) * 4);   // level histograms, then lookahead maxima
+    tmp.reserve(size_t(K) * sizeof(InstInfo));  // instances up to the level statistics
+    tmp.reserve(size_t(K) * (kMaxLevels + 3) * 4 + 4);   // level histograms, lookahead maxima, counter
     tmp.reserve(K > 1 ? size_t(n) * 8 : 0);     // concatenated points
     tmp.reserve(size_t(n) * 8);                 // keys
     tmp.reserve(size_t(n) * 8);                 // keys_tmp
@@ -536,12 +619,14 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     tmp.reserve(radix_scratch_bytes(n));
     tmp.reserve(scan_scratch_bytes(n, 1));
     tmp.allocate();
+    SyncOnUnwind unwind_tmp;
     const int32_t** d_xytab = tmp.take<const int32_t*>(K);
     int32_t* d_ptoff = tmp.take<int32_t>(K + 1);
     Chunk* d_chunks = tmp.take<Chunk>(nch);
     int32_t* d_chfirst = tmp.take<int32_t>(K + 1);
     int32_t* d_part = tmp.take<int32_t>(size_t(nch) * 4);
-    int32_t* d_stats = tmp.take<int32_t>(size_t(K) * (kMaxLevels + 3));
+    InstInfo* d_inst0 = tmp.take<InstInfo>(K);
+    int32_t* d_stats = tmp.take<int32_t>(size_t(K) * (kMaxLevels + 3) + 1);
     int32_t* d_hist = d_stats;
     int32_t* d_maxc = d_stats + size_t(K) * (kMaxLevels + 2);
     // host-visible results of the two read-backs (pinned: the root boxes are written there by
@@ -579,9 +664,33 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
         xy = d_xyc;
     }
 
+    // N_leaf of every instance: the caller's, else the options', else the tuned value for
+    // the instance's size and density (known after the root boxes), else the default
+    int32_t ml_all = max_leaf > 0 ? max_leaf : ctx->opt.max_leaf;
+    if (ml_all <= 0) {
+        std::lock_guard<std::mutex> lock(ctx->mu);
+        if (ctx->tuned.empty()) ml_all = kDefaultMaxLeaf;
+    }
+
     // ---- root boxes ----------------------------------------------------------------------
     launch_bbox_chunks(xy, d_chunks, nch, d_part, st);
-    launch_bbox_final(d_part, d_chfirst, K, bb, st);   // written straight to pinned host memory
+    // root boxes straight to pinned host memory, and (with one N_leaf for all) the instance
+    // table of the next kernels straight to the device
+    launch_bbox_final(d_part, d_chfirst, d_ptoff, K, std::max(ml_all, 0), bb, d_inst0, st);
+    // point storage, taken while the device works
+    Arena& mp = pl->mem_pts;
+    mp.set_pool(&ctx->pool);
+    mp.reserve(size_t(n) * 8);                  // pts
+    mp.reserve(size_t(n) * 4);                  // perm
+    mp.reserve(size_t(n) * 4);                  // pinst
+    mp.reserve(size_t(n) * 4);                  // pkey
+    mp.reserve(size_t(n) * 8);                  // fs
+    mp.allocate();
+    pl->pts = mp.take<int32_t>(size_t(n) * 2);
+    pl->perm = mp.take<int32_t>(n);
+    pl->pinst = mp.take<int32_t>(n);
+    pl->pkey = mp.take<uint32_t>(n);
+    pl->fs = mp.take<double>(n);
     LFMM_HIP(hipStreamSynchronize(st));
     pl->inst.assign(size_t(K), InstInfo{});
     int Dmax = 0;
@@ -596,9 +705,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
         I.oy = b[1];
         I.D = bits_for_extent(extent);
         Dmax = std::max(Dmax, I.D);
-        // N_leaf: the caller's, else the options', else the tuned value for this size and
-        // density, else the default
-        int32_t ml = max_leaf > 0 ? max_leaf : ctx->opt.max_leaf;
+        int32_t ml = ml_all;
         if (ml <= 0) {
             std::lock_guard<std::mutex> lock(ctx->mu);
             auto it = ctx->tuned.find(tune_key(I.pt1 - I.pt0, I.D));
@@ -611,49 +718,22 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     if (2 * Dmax + ibits > 64) throw std::out_of_range("too many instances for the coordinate extent");
     pl->Dmax = Dmax;
 
-    // plan storage sized by K and n
-    Arena& ms = pl->mem_small;
-    ms.set_pool(&ctx->pool);
-    // the tables uploaded together at the end of the build are taken next to each other
-    ms.reserve(size_t(K) * sizeof(InstInfo));
-    ms.reserve(size_t(64) * sizeof(OpsPtrs));
-    ms.reserve(size_t(K));                      // far flags
-    ms.reserve(16);                             // M2L tile count
-    ms.reserve(size_t(K) * sizeof(ExecPtrs));
-    ms.allocate();
-    pl->d_inst = ms.take<InstInfo>(K);
-    pl->d_ops = ms.take<OpsPtrs>(64);
-    pl->d_far = ms.take<uint8_t>(K);
-    pl->d_m2l_ntiles = ms.take<int32_t>(4);
-    pl->d_exec = ms.take<ExecPtrs>(K);
-    Arena& mp = pl->mem_pts;
-    mp.set_pool(&ctx->pool);
-    mp.reserve(size_t(n) * 8);                  // pts
-    mp.reserve(size_t(n) * 4);                  // perm
-    mp.reserve(size_t(n) * 4);                  // pinst
-    mp.reserve(size_t(n) * 4);                  // pkey
-    mp.reserve(size_t(n) * 8);                  // fs
-    mp.allocate();
-    pl->pts = mp.take<int32_t>(size_t(n) * 2);
-    pl->perm = mp.take<int32_t>(n);
-    pl->pinst = mp.take<int32_t>(n);
-    pl->pkey = mp.take<uint32_t>(n);
-    pl->fs = mp.take<double>(n);
     Stager stage_b(ctx);
-    stage_b.add(pl->d_inst, pl->inst);
-    stage_b.flush(st);
+    if (ml_all <= 0) {   // per-instance N_leaf: the host writes the instance table
+        stage_b.add(d_inst0, pl->inst);
+        stage_b.flush(st);
+    }
 
     // ---- Morton order ----------------------------------------------------------------------
-    launch_keys(xy, d_ptoff, K, pl->d_inst, Dmax, n, keys, vals, st);
+    const int32_t nstats = K * (kMaxLevels + 3);
+    launch_keys(xy, d_ptoff, K, d_inst0, Dmax, n, keys, vals, d_stats, nstats + 1, st);
     const int which = radix_sort_pairs(keys, vals, keys_tmp, vals_tmp, n, 2 * Dmax + ibits, rscr, st);
     uint64_t* skeys = which ? keys_tmp : keys;
     uint32_t* svals = which ? vals_tmp : vals;
-    launch_gather_sorted(skeys, svals, xy, pl->d_inst, d_ptoff, Dmax, K, n, pl->pts, pl->perm, pl->pinst, st);
+    launch_gather_sorted(skeys, svals, xy, d_inst0, d_ptoff, Dmax, K, n, pl->pts, pl->perm, pl->pinst, st);
 
     // ---- leaf levels and box counts ---------------------------------------------------------
-    LFMM_HIP(hipMemsetAsync(d_stats, 0, size_t(K) * (kMaxLevels + 3) * 4, st));
-    launch_level_stats(skeys, d_chunks, nch, pl->d_inst, Dmax, cl, d_hist, d_maxc, st);
-    LFMM_HIP(hipMemcpyAsync(stats, d_stats, size_t(K) * (kMaxLevels + 3) * 4, hipMemcpyDeviceToHost, st));
+    launch_level_stats(skeys, d_chunks, nch, d_inst0, Dmax, cl, d_hist, d_maxc, d_stats + nstats, nstats, stats, st);
     LFMM_HIP(hipStreamSynchronize(st));
     const int32_t* hist = stats;
     const int32_t* maxc = stats + size_t(K) * (kMaxLevels + 2);
@@ -797,19 +877,40 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
         }
         pl->l2l[size_t(h)].n = tile_slots - pl->l2l[size_t(h)].t0;
     }
-    const int32_t m2m_base = tile_slots;
+    // M2M tiles: runs of consecutive boxes, built here (their own table)
     for (int h = 1; h <= H; ++h) {
-        pl->m2m[size_t(h)].t0 = tile_slots;
+        pl->m2m[size_t(h)].t0 = int32_t(m2m_tiles.size());
         for (size_t o = 0; o < side_of.size(); ++o) {
             int32_t g0, g1;
             range_of(h, int(o), 2, g0, g1);
-            for (int32_t s = g0; g0 >= 0 && s < g1; s += kBoxMatTile) {
+            for (int32_t s = g0; g0 >= 0 && s < g1; s += kBoxMatTile)
                 m2m_tiles.push_back(BoxTile{int32_t(o), h, 0, s, std::min(kBoxMatTile, g1 - s), 0, 0, 0});
-                ++tile_slots;
-            }
         }
-        pl->m2m[size_t(h)].n = tile_slots - pl->m2m[size_t(h)].t0;
+        pl->m2m[size_t(h)].n = int32_t(m2m_tiles.size()) - pl->m2m[size_t(h)].t0;
     }
+    std::vector<BoxGroup> groups = m2l_groups;
+    groups.insert(groups.end(), l2l_groups.begin(), l2l_groups.end());
+
+    // small tables, uploaded in one copy (ExecPtrs last: written at execute time)
+    Arena& ms = pl->mem_small;
+    ms.set_pool(&ctx->pool);
+    ms.reserve(size_t(K) * sizeof(InstInfo));
+    ms.reserve(size_t(64) * sizeof(OpsPtrs));
+    ms.reserve(size_t(K));                      // far flags
+    ms.reserve(16);                             // M2L tile count
+    ms.reserve(std::max<size_t>(groups.size(), 1) * sizeof(BoxGroup));
+    ms.reserve(std::max<size_t>(m2m_tiles.size(), 1) * sizeof(BoxTile));
+    ms.reserve(std::max<size_t>(root_list.size(), 1) * sizeof(int32_t));
+    ms.reserve(size_t(K) * sizeof(ExecPtrs));
+    ms.allocate();
+    pl->d_inst = ms.take<InstInfo>(K);
+    pl->d_ops = ms.take<OpsPtrs>(64);
+    pl->d_far = ms.take<uint8_t>(K);
+    pl->d_m2l_ntiles = ms.take<int32_t>(4);
+    BoxGroup* d_groups = ms.take<BoxGroup>(std::max<size_t>(groups.size(), 1));
+    pl->m2m_tiles = ms.take<BoxTile>(std::max<size_t>(m2m_tiles.size(), 1));
+    int32_t* d_roots = ms.take<int32_t>(std::max<size_t>(root_list.size(), 1));
+    pl->d_exec = ms.take<ExecPtrs>(K);
 
     // ---- plan storage sized by the boxes --------------------------------------------------------
     const int64_t nb = pl->nbox, nl = pl->nleaf;
@@ -824,11 +925,9 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     mb.reserve(size_t(nb) * 4 * kNumInteractions);       // interaction lists
     mb.reserve(size_t(std::max(cls_slots, 1)) * 4);
     mb.reserve(size_t(std::max(tile_slots, 1)) * sizeof(BoxTile));
-    mb.reserve(size_t(std::max<size_t>(m2l_groups.size() + l2l_groups.size(), 1)) * sizeof(BoxGroup));
     mb.reserve(size_t(nb + 1) * P * 8);                  // Q and its zero row
     mb.reserve(size_t(std::max(pl->nq, 1)) * sizeof(NearGroup));
     mb.reserve(size_t(std::max(pl->nq, 1)) * kNearEntries * sizeof(int4));
-    mb.reserve(std::max<size_t>(root_list.size(), 1) * sizeof(int32_t));
     mb.reserve(size_t(nb + 1) * P * 8);                  // U and its zero row
     mb.allocate();
     pl->box_key = mb.take<uint64_t>(nb);
@@ -843,19 +942,14 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     pl->il27 = mb.take<int32_t>(size_t(nb) * kNumInteractions);
     pl->cls_box = mb.take<int32_t>(std::max(cls_slots, 1));
     pl->tiles = mb.take<BoxTile>(std::max(tile_slots, 1));
-    BoxGroup* d_groups = mb.take<BoxGroup>(std::max<size_t>(m2l_groups.size() + l2l_groups.size(), 1));
     pl->Q = mb.take<double>(size_t(nb + 1) * P);
     pl->U = mb.take<double>(size_t(nb + 1) * P);
     pl->groups = mb.take<NearGroup>(size_t(std::max(pl->nq, 1)));
     pl->ents = mb.take<int4>(size_t(std::max(pl->nq, 1)) * kNearEntries);
-    int32_t* d_roots = mb.take<int32_t>(std::max<size_t>(root_list.size(), 1));
-    Stager stage_c(ctx);
-    stage_c.add(d_roots, root_list);
-    // row nb of Q and of U stays zero: the box-matrix kernels read it for absent sources
-    LFMM_HIP(hipMemsetAsync(pl->Q + size_t(nb) * P, 0, size_t(P) * sizeof(double), st));
-    LFMM_HIP(hipMemsetAsync(pl->U + size_t(nb) * P, 0, size_t(P) * sizeof(double), st));
 
     // ---- tables ---------------------------------------------------------------------------------
+    Stager stage_c(ctx);
+    stage_c.add(d_roots, root_list);
     stage_c.add(pl->d_inst, pl->inst);
     std::vector<OpsPtrs> optab;
     for (CachedOps* co : pl->ops) optab.push_back(ops_ptrs(co));
@@ -863,10 +957,8 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     std::vector<uint8_t> far(static_cast<size_t>(K));
     for (int32_t k = 0; k < K; ++k) far[size_t(k)] = pl->inst[size_t(k)].L >= 2 ? 1 : 0;
     stage_c.add(pl->d_far, far);
-    std::vector<BoxGroup> groups = m2l_groups;
-    groups.insert(groups.end(), l2l_groups.begin(), l2l_groups.end());
     stage_c.add(d_groups, groups);
-    stage_c.add(pl->tiles + m2m_base, m2m_tiles);
+    stage_c.add(pl->m2m_tiles, m2m_tiles);
     std::vector<int32_t> m2l_n{pl->m2l.n};
     stage_c.add(pl->d_m2l_ntiles, m2l_n);
     stage_c.flush(st);
@@ -884,6 +976,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     tmp2.reserve(64);                                    // class totals
     tmp2.reserve(scan_scratch_bytes(nb, 4));
     tmp2.allocate();
+    SyncOnUnwind unwind_tmp2;
     int32_t* leaf_pt0 = tmp2.take<int32_t>(nl);
     uint64_t* leaf_key = tmp2.take<uint64_t>(nl);
     int8_t* leaf_cl = tmp2.take<int8_t>(nl);
@@ -899,8 +992,9 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     if (Lmax > 0) scan_level_starts(leaf_cl, leaf_inst, pl->d_inst, nl, Lmax, lscan, lscr, st);
     launch_build_boxes(lscan, leaf_cl, leaf_pt0, leaf_key, leaf_inst, pl->d_inst, nl, Lmax, pl->box_key, pl->box_pt0,
                        pl->box_parent, pl->box_child, pl->box_inst, pl->box_lev, st);
+    // also zeroes row nb of Q-hat and U-hat, which the box-matrix kernels read for absent sources
     launch_link_boxes(pl->box_key, pl->box_parent, pl->box_inst, pl->box_lev, pl->d_inst, nb, pl->box_pt0,
-                      pl->box_child, pl->box_pt1, st);
+                      pl->box_child, pl->box_pt1, pl->Q + size_t(nb) * P, pl->U + size_t(nb) * P, st);
     // the lists and the near-field groups run on a second stream beside the class lists and
     // tiles, which need only the boxes
     if (!ctx->aux) {
@@ -918,7 +1012,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
                            pl->groups, pl->ents, ctx->aux);
     LFMM_HIP(hipEventRecord(ctx->join, ctx->aux));
     scan_child_classes(pl->box_key, nb, cscan, ctotal, cscr, st);
-    launch_class_lists(d_groups, int32_t(groups.size()), m2m_base, cscan, ctotal, pl->box_key, nb, pl->cls_box,
+    launch_class_lists(d_groups, int32_t(groups.size()), tile_slots, cscan, ctotal, pl->box_key, nb, pl->cls_box,
                        pl->tiles, st);
     if (std::any_of(side_of.begin(), side_of.end(), [](int64_t s) { return s <= 16; }))
         launch_point_keys(pl->pts, pl->pinst, pl->d_inst, pl->d_ops, n, pl->pkey, st);
@@ -931,9 +1025,13 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
         pl->h_exec = static_cast<ExecPtrs*>(ctx->pinned.acquire(size_t(K) * sizeof(ExecPtrs), &pl->h_exec_cls));
         LFMM_HIP(hipEventCreateWithFlags(&pl->exec_copied, hipEventDisableTiming));
     }
-    LFMM_HIP(hipStreamSynchronize(st));
-    tmp.release();
-    tmp2.release();
+    // no synchronisation: the temporaries and staging blocks go back to their pools once the
+    // device has passed the end of the build, and executes on other streams wait for it
+    pl->built = std::make_shared<Fence>(st);
+    pl->build_stream = st;
+    tmp.release_after(pl->built);
+    tmp2.release_after(pl->built);
+    stage_c.retire(pl->built);
 }
 
 // Enqueues the evaluation passes (Section 8.2) on st.  tab = per-instance load/potential
@@ -954,7 +1052,7 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
     mark(2);
     for (int h = 1; h <= pl->Hmax; ++h) {
         const TileRange& r = pl->m2m[size_t(h)];
-        if (r.n > 0) launch_m2m(pl->tiles + r.t0, r.n, pl->box_child, pl->d_ops, pl->Q, pl->nbox, st);
+        if (r.n > 0) launch_m2m(pl->m2m_tiles + r.t0, r.n, pl->box_child, pl->d_ops, pl->Q, pl->nbox, st);
     }
     mark(3);
     if (pl->m2l.n > 0) {
@@ -980,6 +1078,7 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
 }
 
 void run_forest(lfmm_plan* pl, const double* const* f, double* const* u, hipStream_t st) {
+    if (st != pl->build_stream) LFMM_HIP(hipStreamWaitEvent(st, pl->built->ev, 0));
     if (pl->K == 1 && !pl->use_graph) {
         enqueue_passes(pl, nullptr, f[0], u[0], pl->timing, st);
         if (pl->timing) pl->timed_once = true;

@@ -76,8 +76,9 @@ __global__ void k_concat(int32_t K, const int2* const* xy_tab, const int32_t* pt
     xyc[i] = xy_tab[k][i - pt_off[k]];
 }
 
-__device__ inline void block_minmax4(int v[4], int32_t* out) {
-    // v = {min x, min y, max x, max y}: wave shuffles, then the four waves through LDS
+// v = {min x, min y, max x, max y} over the block: wave shuffles, then the four waves
+// through LDS; thread 0 gets the result in v and true
+__device__ inline bool block_minmax4(int v[4]) {
     #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         v[0] = min(v[0], __shfl_xor(v[0], o, 64));
@@ -90,14 +91,13 @@ __device__ inline void block_minmax4(int v[4], int32_t* out) {
     if ((threadIdx.x & 63) == 0)
         for (int q = 0; q < 4; ++q) s[wave][q] = v[q];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int r[4] = {s[0][0], s[0][1], s[0][2], s[0][3]};
-        for (int w = 1; w < kBlock / 64; ++w) {
-            r[0] = min(r[0], s[w][0]); r[1] = min(r[1], s[w][1]);
-            r[2] = max(r[2], s[w][2]); r[3] = max(r[3], s[w][3]);
-        }
-        for (int q = 0; q < 4; ++q) out[q] = r[q];
+    if (threadIdx.x != 0) return false;
+    for (int q = 0; q < 4; ++q) v[q] = s[0][q];
+    for (int w = 1; w < kBlock / 64; ++w) {
+        v[0] = min(v[0], s[w][0]); v[1] = min(v[1], s[w][1]);
+        v[2] = max(v[2], s[w][2]); v[3] = max(v[3], s[w][3]);
     }
+    return true;
 }
 
 __global__ void k_bbox_chunks(const int2* xy, const Chunk* chunks, int32_t* part) {
@@ -108,23 +108,43 @@ __global__ void k_bbox_chunks(const int2* xy, const Chunk* chunks, int32_t* part
         v[0] = min(v[0], p.x); v[1] = min(v[1], p.y);
         v[2] = max(v[2], p.x); v[3] = max(v[3], p.y);
     }
-    block_minmax4(v, part + size_t(blockIdx.x) * 4);
+    if (block_minmax4(v))
+        for (int q = 0; q < 4; ++q) part[size_t(blockIdx.x) * 4 + q] = v[q];
 }
 
-// one block per instance: its chunks' partial boxes reduced by the block
-__global__ void k_bbox_final(const int32_t* part, const int32_t* chunk_first, int32_t* bbox) {
+// One block per instance: its chunks' partial boxes reduced by the block, written to bbox
+// (host memory) and, with max_leaf > 0, as the instance's root box, depth D (the smallest
+// with 2^D >= extent), point range and N_leaf into inst, for the kernels up to the level
+// statistics (the host writes inst itself when max_leaf is 0).
+__global__ void k_bbox_final(const int32_t* part, const int32_t* chunk_first, const int32_t* pt_off,
+                             int32_t max_leaf, int32_t* bbox, InstInfo* inst) {
     const int32_t k = int32_t(blockIdx.x);
     int v[4] = {INT_MAX, INT_MAX, INT_MIN, INT_MIN};
     for (int32_t c = chunk_first[k] + int32_t(threadIdx.x); c < chunk_first[k + 1]; c += kBlock) {
         v[0] = min(v[0], part[4 * c]); v[1] = min(v[1], part[4 * c + 1]);
         v[2] = max(v[2], part[4 * c + 2]); v[3] = max(v[3], part[4 * c + 3]);
     }
-    block_minmax4(v, bbox + size_t(k) * 4);
+    if (!block_minmax4(v)) return;
+    for (int q = 0; q < 4; ++q) bbox[size_t(k) * 4 + q] = v[q];
+    if (max_leaf <= 0) return;
+    const int64_t extent = max(int64_t(v[2]) - v[0], int64_t(v[3]) - v[1]) + 1;
+    int D = 0;
+    while (D < 32 && (int64_t(1) << D) < extent) ++D;
+    InstInfo& I = inst[k];
+    I.pt0 = pt_off[k];
+    I.pt1 = pt_off[k + 1];
+    I.ox = v[0];
+    I.oy = v[1];
+    I.D = D;
+    I.max_leaf = max_leaf;
 }
 
+// Morton key (instance above it) and index of every point; also zeroes the nzero counters
+// that the level statistics accumulate into.
 __global__ void k_keys(const int2* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst, int Dmax, int64_t n,
-                       uint64_t* keys, uint32_t* vals) {
+                       uint64_t* keys, uint32_t* vals, int32_t* zero, int32_t nzero) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (int64_t z = i; z < nzero; z += int64_t(gridDim.x) * blockDim.x) zero[z] = 0;
     if (i >= n) return;
     const int32_t k = (K > 1) ? find_inst(pt_off, K, i) : 0;
     const int2 p = xy[i];
@@ -153,7 +173,8 @@ __global__ void k_gather_sorted(const uint64_t* keys, const uint32_t* vals, cons
 // levels shared with the point N_leaf positions ahead (a box of that level would hold more
 // than N_leaf points), reduced to one atomic per block.
 __global__ void k_level_stats(const uint64_t* keys, const Chunk* chunks, const InstInfo* inst, int Dmax,
-                              int8_t* cl, int32_t* hist, int32_t* maxc) {
+                              int8_t* cl, int32_t* hist, int32_t* maxc, int32_t* done, int32_t nstats,
+                              int32_t* host_out) {
     __shared__ int32_t h[kMaxLevels + 2];
     __shared__ int32_t wmax[kBlock / 64];
     const Chunk c = chunks[blockIdx.x];
@@ -194,6 +215,17 @@ __global__ void k_level_stats(const uint64_t* keys, const Chunk* chunks, const I
     }
     if (threadIdx.x < kMaxLevels + 2 && h[threadIdx.x] != 0)
         atomicAdd(&hist[size_t(c.inst) * (kMaxLevels + 2) + threadIdx.x], h[threadIdx.x]);
+    // the last block to finish copies the totals (hist and maxc, nstats values from hist on)
+    // to host memory
+    __shared__ int is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) is_last = atomicAdd(done, 1) == int(gridDim.x) - 1;
+    __syncthreads();
+    if (is_last) {
+        __threadfence();
+        for (int i = threadIdx.x; i < nstats; i += blockDim.x) host_out[i] = atomicAdd(&hist[i], 0);
+    }
 }
 
 __global__ void k_leaf_scatter(const int32_t* scan, const uint64_t* keys, const int8_t* cl, const int32_t* pinst,
@@ -246,8 +278,12 @@ __global__ void k_build_boxes(const int32_t* lscan, const int8_t* leaf_cl, const
 
 __global__ void k_link_boxes(const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_inst,
                              const int8_t* box_lev, const InstInfo* inst, int64_t nbox, const int32_t* box_pt0,
-                             int32_t* box_child, int32_t* box_pt1) {
+                             int32_t* box_child, int32_t* box_pt1, double* zq, double* zu) {
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g < kRankPad) {   // the all-zero rows of Q-hat and U-hat
+        zq[g] = 0.0;
+        zu[g] = 0.0;
+    }
     if (g >= nbox) return;
     const int32_t p = box_parent[g];
     if (p >= 0) box_child[size_t(p) * 4 + int(box_key[g] & 3ull)] = int32_t(g);
@@ -413,48 +449,62 @@ __global__ void k_class_tiles(const BoxGroup* groups, int32_t ngroups, int32_t n
     tiles[t] = tl;
 }
 
-// one thread per near-field group: its leaves and the union of their neighbour lists, as
-// point ranges in leaf order (Morton order, so ranges of adjacent leaves follow each other)
+// Near-field groups, 16 lanes per group: the group's leaves (the children of a height-1 box,
+// or a root that is a leaf) and the union of their neighbour lists, as point ranges in box
+// order (Morton order, so ranges of adjacent leaves follow each other).  Lane j stands for
+// cell (j mod 4, j / 4) of the 4 x 4 block of leaf cells around the parent, whose children sit
+// at cells 1..2; it reads the box at its cell from the neighbour list of the first child of
+// the group next to that cell, and its entry goes to the rank of its box among the group's.
 __global__ void k_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, const int32_t* roots, int32_t nroots,
                               const int32_t* box_child, const int32_t* nb9, const int32_t* box_pt0,
                               const int32_t* box_pt1, const uint64_t* box_key, NearGroup* groups, int4* ents) {
-    const int32_t q = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (q >= h1_count + nroots) return;
-    int32_t leaves[4], nleaf = 0;
-    if (q < h1_count) {
-        const int32_t P = h1_start + q;
-        for (int c = 0; c < 4; ++c) {
-            const int32_t ch = box_child[size_t(P) * 4 + c];
-            if (ch >= 0) leaves[nleaf++] = ch;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int32_t q = int32_t(t >> 4);
+    const int j = int(threadIdx.x & 15), lane = int(threadIdx.x & 63);
+    const bool active = q < h1_count + nroots;   // the same for all 16 lanes of a group
+    int32_t b = -1, leaf0 = -1, nleaf = 0;
+    if (active) {
+        if (q < h1_count) {
+            const int32_t P = h1_start + q;
+            const int ox = j & 3, oy = j >> 2;
+            bool done = false;
+            for (int c = 0; c < 4; ++c) {
+                const int32_t ch = box_child[size_t(P) * 4 + c];
+                if (ch < 0) continue;
+                if (leaf0 < 0) leaf0 = ch;
+                ++nleaf;
+                const int dx = ox - 1 - (c & 1), dy = oy - 1 - (c >> 1);
+                if (done || dx < -1 || dx > 1 || dy < -1 || dy > 1) continue;
+                b = nb9[size_t(ch) * 9 + (dy + 1) * 3 + dx + 1];
+                done = true;
+            }
+        } else {
+            leaf0 = roots[q - h1_count];
+            nleaf = 1;
+            if (j < 9) b = nb9[size_t(leaf0) * 9 + j];
         }
-    } else {
-        leaves[nleaf++] = roots[q - h1_count];
     }
-    int32_t un[kNearEntries];
-    int nu = 0;
-    for (int l = 0; l < nleaf; ++l)
-        for (int k = 0; k < 9; ++k) {
-            const int32_t b = nb9[size_t(leaves[l]) * 9 + k];
-            if (b < 0) continue;
-            int pos = 0;
-            while (pos < nu && un[pos] < b) ++pos;
-            if (pos < nu && un[pos] == b) continue;
-            for (int r = nu; r > pos; --r) un[r] = un[r - 1];   // insertion keeps leaf order
-            un[pos] = b;
-            ++nu;
-        }
-    int4* out = ents + size_t(q0 + q) * kNearEntries;
-    for (int e = 0; e < nu; ++e) {
-        const int32_t b = un[e];
+    int rank = 0, cnt = 0;
+    #pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int32_t bi = __shfl(b, (lane & 48) | i, 64);
+        cnt += bi >= 0 ? 1 : 0;
+        rank += (bi >= 0 && bi < b) ? 1 : 0;
+    }
+    if (!active) return;
+    if (b >= 0) {
         const uint64_t key = box_key[b];
-        out[e] = make_int4(box_pt0[b], box_pt1[b], int32_t(compact_bits(key)), int32_t(compact_bits(key >> 1)));
+        ents[size_t(q0 + q) * kNearEntries + rank] =
+            make_int4(box_pt0[b], box_pt1[b], int32_t(compact_bits(key)), int32_t(compact_bits(key >> 1)));
     }
-    NearGroup G;
-    G.leaf0 = leaves[0];
-    G.nleaf = nleaf;
-    G.ne = nu;
-    G.pad = 0;
-    groups[q0 + q] = G;
+    if (j == 0) {
+        NearGroup G;
+        G.leaf0 = leaf0;
+        G.nleaf = nleaf;
+        G.ne = cnt;
+        G.pad = 0;
+        groups[q0 + q] = G;
+    }
 }
 
 __global__ void k_point_keys(const int2* pts, const int32_t* pinst, const InstInfo* inst, const OpsPtrs* ops,
@@ -704,14 +754,16 @@ void launch_bbox_chunks(const int32_t* xy, const Chunk* chunks, int32_t nchunks,
                        chunks, part);
 }
 
-void launch_bbox_final(const int32_t* part, const int32_t* chunk_first, int32_t K, int32_t* bbox, hipStream_t st) {
-    hipLaunchKernelGGL(k_bbox_final, dim3(static_cast<unsigned>(K)), dim3(kBlock), 0, st, part, chunk_first, bbox);
+void launch_bbox_final(const int32_t* part, const int32_t* chunk_first, const int32_t* pt_off, int32_t K,
+                       int32_t max_leaf, int32_t* bbox, InstInfo* inst, hipStream_t st) {
+    hipLaunchKernelGGL(k_bbox_final, dim3(static_cast<unsigned>(K)), dim3(kBlock), 0, st, part, chunk_first, pt_off,
+                       max_leaf, bbox, inst);
 }
 
 void launch_keys(const int32_t* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst, int Dmax, int64_t n,
-                 uint64_t* keys, uint32_t* vals, hipStream_t st) {
+                 uint64_t* keys, uint32_t* vals, int32_t* zero, int32_t nzero, hipStream_t st) {
     hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(kBlock), 0, st, reinterpret_cast<const int2*>(xy), pt_off, K,
-                       inst, Dmax, n, keys, vals);
+                       inst, Dmax, n, keys, vals, zero, nzero);
 }
 
 void launch_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int32_t* xy, const InstInfo* inst,
@@ -723,9 +775,10 @@ void launch_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int3
 }
 
 void launch_level_stats(const uint64_t* keys, const Chunk* chunks, int32_t nchunks, const InstInfo* inst, int Dmax,
-                        int8_t* cl, int32_t* hist, int32_t* maxc, hipStream_t st) {
+                        int8_t* cl, int32_t* hist, int32_t* maxc, int32_t* done, int32_t nstats, int32_t* host_out,
+                        hipStream_t st) {
     hipLaunchKernelGGL(k_level_stats, dim3(unsigned(nchunks)), dim3(kBlock), 0, st, keys, chunks, inst, Dmax, cl, hist,
-                       maxc);
+                       maxc, done, nstats, host_out);
 }
 
 void launch_leaf_scatter(const int32_t* scan, const uint64_t* keys, const int8_t* cl, const int32_t* pinst,
@@ -746,9 +799,9 @@ void launch_build_boxes(const int32_t* lscan, const int8_t* leaf_cl, const int32
 
 void launch_link_boxes(const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_inst,
                        const int8_t* box_lev, const InstInfo* inst, int64_t nbox, const int32_t* box_pt0,
-                       int32_t* box_child, int32_t* box_pt1, hipStream_t st) {
-    hipLaunchKernelGGL(k_link_boxes, dim3(grid_for(nbox)), dim3(kBlock), 0, st, box_key, box_parent, box_inst, box_lev,
-                       inst, nbox, box_pt0, box_child, box_pt1);
+                       int32_t* box_child, int32_t* box_pt1, double* zq, double* zu, hipStream_t st) {
+    hipLaunchKernelGGL(k_link_boxes, dim3(grid_for(std::max<int64_t>(nbox, kRankPad))), dim3(kBlock), 0, st, box_key,
+                       box_parent, box_inst, box_lev, inst, nbox, box_pt0, box_child, box_pt1, zq, zu);
 }
 
 void launch_lists(const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_child,
@@ -777,7 +830,8 @@ void launch_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, const in
                         hipStream_t st) {
     const int32_t n = h1_count + nroots;
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_near_groups, dim3(grid_for(n)), dim3(kBlock), 0, st, q0, h1_start, h1_count, roots, nroots,
+    hipLaunchKernelGGL(k_near_groups, dim3(grid_for(int64_t(n) * 16)), dim3(kBlock), 0, st, q0, h1_start, h1_count,
+                       roots, nroots,
                        box_child, nb9, box_pt0, box_pt1, box_key, groups, ents);
 }
 

@@ -124,16 +124,24 @@ void launch_concat(int32_t K, const int32_t* const* xy_tab, const int32_t* pt_of
                    int32_t* xyc, hipStream_t st);
 void launch_bbox_chunks(const int32_t* xy, const Chunk* chunks, int32_t nchunks, int32_t* part,
                         hipStream_t st);
-void launch_bbox_final(const int32_t* part, const int32_t* chunk_first, int32_t K, int32_t* bbox,
-                       hipStream_t st);   // one block per instance
+// one block per instance; with max_leaf > 0 also writes the instances' root boxes, depths,
+// point ranges and N_leaf into inst
+void launch_bbox_final(const int32_t* part, const int32_t* chunk_first, const int32_t* pt_off, int32_t K,
+                       int32_t max_leaf, int32_t* bbox, InstInfo* inst, hipStream_t st);
+// keys and indices of the points; zeroes zero[0, nzero)
 void launch_keys(const int32_t* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst,
-                 int Dmax, int64_t n, uint64_t* keys, uint32_t* vals, hipStream_t st);
+                 int Dmax, int64_t n, uint64_t* keys, uint32_t* vals, int32_t* zero, int32_t nzero,
+                 hipStream_t st);
 void launch_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int32_t* xy,
                           const InstInfo* inst, const int32_t* pt_off, int Dmax, int K, int64_t n,
                           int32_t* pts, int32_t* perm_local, int32_t* pinst, hipStream_t st);
+// per-level box counts (hist) and look-ahead maxima (maxc = hist + K (kMaxLevels + 2)) of
+// every instance; *done counts finished blocks (zero before the launch), and the last one
+// copies the nstats totals to host_out (host memory)
 void launch_level_stats(const uint64_t* keys, const Chunk* chunks, int32_t nchunks,
                         const InstInfo* inst, int Dmax, int8_t* cl, int32_t* hist,
-                        int32_t* maxc, hipStream_t st);
+                        int32_t* maxc, int32_t* done, int32_t nstats, int32_t* host_out,
+                        hipStream_t st);
 // exclusive scans of the flags "a leaf starts here" (per point), "leaf b starts a box of
 // level lev" (row lev, per leaf) and "box g is child c of its parent" (row c, per box)
 void scan_leaf_starts(const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int64_t n, int32_t* out,
@@ -152,8 +160,8 @@ void launch_build_boxes(const int32_t* lscan, const int8_t* leaf_cl, const int32
                         int8_t* box_lev, hipStream_t st);
 void launch_link_boxes(const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_inst,
                        const int8_t* box_lev, const InstInfo* inst, int64_t nbox,
-                       const int32_t* box_pt0, int32_t* box_child, int32_t* box_pt1,
-                       hipStream_t st);
+                       const int32_t* box_pt0, int32_t* box_child, int32_t* box_pt1, double* zq,
+                       double* zu, hipStream_t st);   // also zeroes the rows zq, zu (kRankPad each)
 // neighbour (9 slots, every box) and interaction (27 slots, boxes of level >= 2) lists of
 // every box: neighbours by search among the boxes of the same level, then interaction
 // lists from the parents' neighbours

@@ -726,11 +726,12 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
 
     // ---- Morton order ----------------------------------------------------------------------
     const int32_t nstats = K * (kMaxLevels + 3);
-    launch_keys(xy, d_ptoff, K, d_inst0, Dmax, n, keys, vals, d_stats, nstats + 1, st);
-    const int which = radix_sort_pairs(keys, vals, keys_tmp, vals_tmp, n, 2 * Dmax + ibits, rscr, st);
+    const int kbits = 2 * Dmax + ibits;
+    launch_keys(xy, d_ptoff, K, d_inst0, Dmax, n, keys, vals, d_stats, nstats + 1, kbits > 0 ? rscr : nullptr, st);
+    const int which = radix_sort_pairs(keys, vals, keys_tmp, vals_tmp, n, kbits, true, rscr, st);
     uint64_t* skeys = which ? keys_tmp : keys;
     uint32_t* svals = which ? vals_tmp : vals;
-    launch_gather_sorted(skeys, svals, xy, d_inst0, d_ptoff, Dmax, K, n, pl->pts, pl->perm, pl->pinst, st);
+    launch_gather_sorted(skeys, svals, d_ptoff, Dmax, K, n, pl->pts, pl->perm, pl->pinst, st);
 
     // ---- leaf levels and box counts ---------------------------------------------------------
     launch_level_stats(skeys, d_chunks, nch, d_inst0, Dmax, cl, d_hist, d_maxc, d_stats + nstats, nstats, stats, st);
@@ -951,8 +952,8 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     Stager stage_c(ctx);
     stage_c.add(d_roots, root_list);
     stage_c.add(pl->d_inst, pl->inst);
-    std::vector<OpsPtrs> optab;
-    for (CachedOps* co : pl->ops) optab.push_back(ops_ptrs(co));
+    std::vector<OpsPtrs> optab(64);   // the whole table, so that the upload stays one copy
+    for (size_t o = 0; o < pl->ops.size(); ++o) optab[o] = ops_ptrs(pl->ops[o]);
     stage_c.add(pl->d_ops, optab);
     std::vector<uint8_t> far(static_cast<size_t>(K));
     for (int32_t k = 0; k < K; ++k) far[size_t(k)] = pl->inst[size_t(k)].L >= 2 ? 1 : 0;

@@ -139,30 +139,73 @@ __global__ void k_bbox_final(const int32_t* part, const int32_t* chunk_first, co
     I.max_leaf = max_leaf;
 }
 
-// Morton key (instance above it) and index of every point; also zeroes the nzero counters
-// that the level statistics accumulate into.
-__global__ void k_keys(const int2* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst, int Dmax, int64_t n,
-                       uint64_t* keys, uint32_t* vals, int32_t* zero, int32_t nzero) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    for (int64_t z = i; z < nzero; z += int64_t(gridDim.x) * blockDim.x) zero[z] = 0;
-    if (i >= n) return;
-    const int32_t k = (K > 1) ? find_inst(pt_off, K, i) : 0;
-    const int2 p = xy[i];
-    const uint32_t x = uint32_t(int64_t(p.x) - inst[k].ox), y = uint32_t(int64_t(p.y) - inst[k].oy);
-    const uint64_t m = spread_bits(x) | (spread_bits(y) << 1);
-    keys[i] = (K > 1) ? ((uint64_t(k) << (2 * Dmax)) | m) : m;
-    vals[i] = uint32_t(i);
+// ---- radix sort pieces shared with the key kernel: 8-bit digits, tiles of kRsTile keys ----
+// (striped: item i of thread t of a tile is key tile * kRsTile + i * kBlock + t)
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kBlock * kRsItems;
+
+// Index of the count of digit d in tile t: digit-major (d * ntiles + t, so that one flat
+// exclusive scan gives every tile's output offsets) or tile-major (t * 256 + d).
+__device__ inline size_t rs_index(int d, int64_t t, int64_t ntiles, bool digit_major) {
+    return digit_major ? size_t(d) * size_t(ntiles) + size_t(t) : size_t(t) * 256 + size_t(d);
 }
 
-__global__ void k_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int2* xy, const InstInfo* inst,
-                                const int32_t* pt_off, int Dmax, int K, int64_t n, int2* pts, int32_t* perm_local,
-                                int32_t* pinst) {
+// Digit counts of this block's tile (digits of invalid items are 256) into C.
+__device__ inline void rs_count_tile(const uint32_t (&dg)[kRsItems], uint32_t* C, int64_t ntiles, bool digit_major) {
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    #pragma unroll
+    for (int i = 0; i < kRsItems; ++i)
+        if (dg[i] < 256u) atomicAdd(&cnt[dg[i]], 1u);
+    __syncthreads();
+    C[rs_index(int(threadIdx.x), blockIdx.x, ntiles, digit_major)] = cnt[threadIdx.x];
+}
+
+// Morton key (instance above it) and index of every point, one tile of kRsTile points per
+// block, with the tile's counts of the lowest digit when C is given; also zeroes the nzero
+// counters that the level statistics accumulate into.
+__global__ void k_keys(const int2* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst, int Dmax, int64_t n,
+                       uint64_t* keys, uint32_t* vals, int32_t* zero, int32_t nzero, uint32_t* C, int64_t ntiles,
+                       bool digit_major) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (int64_t z = g; z < nzero; z += int64_t(gridDim.x) * blockDim.x) zero[z] = 0;
+    // all loads of the tile first (few waves per SIMD: the latency is hidden by loads in flight)
+    int2 pt[kRsItems];
+    #pragma unroll
+    for (int it = 0; it < kRsItems; ++it) {
+        const int64_t i = int64_t(blockIdx.x) * kRsTile + int64_t(it) * kBlock + threadIdx.x;
+        pt[it] = i < n ? xy[i] : make_int2(0, 0);
+    }
+    uint32_t dg[kRsItems];
+    #pragma unroll
+    for (int it = 0; it < kRsItems; ++it) {
+        const int64_t i = int64_t(blockIdx.x) * kRsTile + int64_t(it) * kBlock + threadIdx.x;
+        dg[it] = 256u;
+        if (i >= n) continue;
+        const int32_t k = (K > 1) ? find_inst(pt_off, K, i) : 0;
+        const int2 p = pt[it];
+        const uint32_t x = uint32_t(int64_t(p.x) - inst[k].ox), y = uint32_t(int64_t(p.y) - inst[k].oy);
+        const uint64_t m = spread_bits(x) | (spread_bits(y) << 1);
+        const uint64_t key = (K > 1) ? ((uint64_t(k) << (2 * Dmax)) | m) : m;
+        keys[i] = key;
+        vals[i] = uint32_t(i);
+        dg[it] = uint32_t(key & 255u);
+    }
+    if (C) rs_count_tile(dg, C, ntiles, digit_major);
+}
+
+// Sorted points: coordinates in the instance's root box decoded from the Morton key (no
+// gather of the input), instance-local index and instance.
+__global__ void k_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int32_t* pt_off, int Dmax, int K,
+                                int64_t n, int2* pts, int32_t* perm_local, int32_t* pinst) {
     const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const uint32_t p = vals[s];
-    const int32_t k = (K > 1) ? int32_t(keys[s] >> (2 * Dmax)) : 0;
-    const int2 q = xy[p];
-    pts[s] = make_int2(int32_t(int64_t(q.x) - inst[k].ox), int32_t(int64_t(q.y) - inst[k].oy));
+    const uint64_t key = keys[s];
+    const int32_t k = (K > 1) ? int32_t(key >> (2 * Dmax)) : 0;
+    const uint64_t m = key & morton_mask(Dmax);
+    pts[s] = make_int2(int32_t(compact_bits(m)), int32_t(compact_bits(m >> 1)));
     perm_local[s] = int32_t(p) - pt_off[k];
     pinst[s] = k;
 }
@@ -215,17 +258,17 @@ __global__ void k_level_stats(const uint64_t* keys, const Chunk* chunks, const I
     }
     if (threadIdx.x < kMaxLevels + 2 && h[threadIdx.x] != 0)
         atomicAdd(&hist[size_t(c.inst) * (kMaxLevels + 2) + threadIdx.x], h[threadIdx.x]);
-    // the last block to finish copies the totals (hist and maxc, nstats values from hist on)
-    // to host memory
+    // The last block to finish copies the totals (hist and maxc, nstats values from hist on)
+    // to host memory.  Each thread waits until its atomics above have been performed (vector
+    // memory count zero) before the barrier, after which the counter is incremented; no
+    // device-wide fence is needed.
     __shared__ int is_last;
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) is_last = atomicAdd(done, 1) == int(gridDim.x) - 1;
     __syncthreads();
-    if (is_last) {
-        __threadfence();
+    if (is_last)
         for (int i = threadIdx.x; i < nstats; i += blockDim.x) host_out[i] = atomicAdd(&hist[i], 0);
-    }
 }
 
 __global__ void k_leaf_scatter(const int32_t* scan, const uint64_t* keys, const int8_t* cl, const int32_t* pinst,
@@ -517,70 +560,14 @@ __global__ void k_point_keys(const int2* pts, const int32_t* pinst, const InstIn
     key[i] = 8u * (uint32_t(p.y) * W + uint32_t(p.x));   // modulo 2^32 on purpose
 }
 
-// ---- radix sort: 8-bit digits, tiles of 4096 keys per block ----------------------------
-constexpr int kRsItems = 4;
-constexpr int kRsTile = kBlock * kRsItems;
-
-__global__ void k_rs_hist(const uint64_t* keys, int64_t n, int shift, uint32_t* hist, int nblk) {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t base = int64_t(blockIdx.x) * kRsTile;
-    for (int i = threadIdx.x; i < kRsTile; i += kBlock) {
-        const int64_t idx = base + i;
-        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    hist[size_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
-}
-
-// Stable scatter: within a round of 256 keys, lanes of a wave find equal digits by eight
-// ballots; waves are ordered through LDS counts; rounds and blocks are ordered by offsets.
-__global__ void k_rs_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t n,
-                             int shift, const int32_t* offs, int nblk) {
-    __shared__ uint32_t running[256];
-    __shared__ uint32_t wcnt[kBlock / 64][256];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    running[tid] = uint32_t(offs[size_t(tid) * nblk + blockIdx.x]);
-    const int64_t base = int64_t(blockIdx.x) * kRsTile;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int r = 0; r < kRsItems; ++r) {
-        for (int w = 0; w < kBlock / 64; ++w) wcnt[w][tid] = 0;
-        __syncthreads();
-        const int64_t idx = base + int64_t(r) * kBlock + tid;
-        const bool valid = idx < n;
-        const uint64_t key = valid ? kin[idx] : 0ull;
-        const uint32_t d = uint32_t((key >> shift) & 255u);
-        uint64_t mask = __ballot(valid);
-        #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const uint64_t bb = __ballot(valid && ((d >> b) & 1u));
-            mask &= ((d >> b) & 1u) ? bb : ~bb;
-        }
-        const uint32_t rank = uint32_t(__popcll(mask & lt_mask));
-        if (valid && rank == 0) wcnt[wave][d] = uint32_t(__popcll(mask));
-        __syncthreads();
-        if (valid) {
-            uint32_t pre = 0;
-            for (int w = 0; w < wave; ++w) pre += wcnt[w][d];
-            const uint32_t pos = running[d] + pre + rank;
-            kout[pos] = key;
-            vout[pos] = vin[idx];
-        }
-        __syncthreads();
-        uint32_t add = 0;
-        for (int w = 0; w < kBlock / 64; ++w) add += wcnt[w][tid];
-        running[tid] += add;
-        __syncthreads();
-    }
-}
-
 // ---- exclusive scan over rows of int32 -------------------------------------------------
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;
 
+// exclusive scan over the NT threads of a block (thread order); *total = the sum
+template <int NT = kBlock>
 __device__ inline int32_t block_exclusive_scan(int32_t v, int32_t* total) {
-    __shared__ int32_t wsum[kBlock / 64];
+    __shared__ int32_t wsum[NT / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int32_t x = v;
     #pragma unroll
@@ -591,13 +578,153 @@ __device__ inline int32_t block_exclusive_scan(int32_t v, int32_t* total) {
     if (lane == 63) wsum[wave] = x;
     __syncthreads();
     int32_t pre = 0, tot = 0;
-    for (int w = 0; w < kBlock / 64; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
         if (w < wave) pre += wsum[w];
         tot += wsum[w];
     }
     __syncthreads();
     *total = tot;
     return pre + x - v;
+}
+
+// ---- radix sort passes -----------------------------------------------------------------------
+// Digit counts of every tile for the digit at `shift`.
+__global__ void k_rs_count(const uint64_t* keys, int64_t n, int shift, uint32_t* C, int64_t ntiles, bool digit_major) {
+    uint32_t dg[kRsItems];
+    #pragma unroll
+    for (int it = 0; it < kRsItems; ++it) {
+        const int64_t i = int64_t(blockIdx.x) * kRsTile + int64_t(it) * kBlock + threadIdx.x;
+        dg[it] = i < n ? uint32_t((keys[i] >> shift) & 255u) : 256u;
+    }
+    rs_count_tile(dg, C, ntiles, digit_major);
+}
+
+// Stable scatter of one tile by the digit at `shift`, kRsScatterThreads threads per tile.
+// The tile's output start for digit d is offs[d][tile] when offs is given (a flat exclusive
+// scan of the digit-major counts), else computed here from the tile-major counts C: the
+// totals of every digit scanned over the digits, plus the counts of d in the tiles before
+// this one.  Wave w ranks the tile's keys w * 512 .. w * 512 + 511 in rounds of 64 (eight
+// ballots find the lanes with equal digits; a per-wave running count per digit in LDS orders
+// the rounds), the waves are ordered by per-digit prefixes, and the keys are staged in LDS
+// in output order and written as runs of consecutive addresses.
+constexpr int kRsScatterThreads = 512;
+constexpr int kRsWaves = kRsScatterThreads / 64;
+constexpr int kRsRounds = kRsTile / kRsScatterThreads;
+
+__global__ __launch_bounds__(kRsScatterThreads) void k_rs_scatter(const uint64_t* kin, const uint32_t* vin,
+                                                                  uint64_t* kout, uint32_t* vout, int64_t n, int shift,
+                                                                  const uint32_t* C, const int32_t* offs,
+                                                                  int64_t ntiles) {
+    __shared__ uint32_t s_start[256];
+    __shared__ uint32_t s_pref[256];
+    __shared__ uint32_t cnt[kRsWaves][256];   // per wave: running digit counts, then prefixes over the waves
+    __shared__ union {
+        uint32_t red[2][kRsWaves][256];       // partial sums of the counts of earlier tiles
+        struct {
+            uint64_t k[kRsTile];
+            uint32_t v[kRsTile];
+        } st;
+    } sm;
+    const int tid = int(threadIdx.x), wave = tid >> 6, lane = tid & 63;
+    const int64_t tile = blockIdx.x, base = tile * kRsTile;
+    // output start of each digit's run of this tile (thread d < 256 for digit d)
+    uint32_t start = 0;
+    if (offs) {
+        if (tid < 256) start = uint32_t(offs[size_t(tid) * size_t(ntiles) + size_t(tile)]);
+    } else {
+        // lane l of wave w sums digits 4l .. 4l + 3 over the rows w, w + kRsWaves, ..., 16 rows
+        // of 1 KB in flight per wave
+        const uint4* C4 = reinterpret_cast<const uint4*>(C);
+        uint32_t tot[4] = {0u, 0u, 0u, 0u}, bef[4] = {0u, 0u, 0u, 0u};
+        for (int64_t j0 = wave; j0 < ntiles; j0 += kRsWaves * 16) {
+            uint4 v[16];
+            #pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int64_t j = j0 + kRsWaves * u;
+                v[u] = j < ntiles ? C4[size_t(j) * 64 + size_t(lane)] : make_uint4(0u, 0u, 0u, 0u);
+            }
+            #pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const uint32_t m = (j0 + kRsWaves * u < tile) ? ~0u : 0u;
+                tot[0] += v[u].x; tot[1] += v[u].y; tot[2] += v[u].z; tot[3] += v[u].w;
+                bef[0] += v[u].x & m; bef[1] += v[u].y & m; bef[2] += v[u].z & m; bef[3] += v[u].w & m;
+            }
+        }
+        #pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            sm.red[0][wave][4 * lane + q] = tot[q];
+            sm.red[1][wave][4 * lane + q] = bef[q];
+        }
+        __syncthreads();
+        uint32_t total = 0, before = 0;
+        if (tid < 256)
+            #pragma unroll
+            for (int w = 0; w < kRsWaves; ++w) {
+                total += sm.red[0][w][tid];
+                before += sm.red[1][w][tid];
+            }
+        int32_t all;
+        start = uint32_t(block_exclusive_scan<kRsScatterThreads>(int32_t(total), &all)) + before;
+    }
+    for (int q = tid; q < kRsWaves * 256; q += kRsScatterThreads) (&cnt[0][0])[q] = 0u;
+    uint64_t key[kRsRounds];
+    uint32_t val[kRsRounds];
+    const int64_t wbase = base + int64_t(wave) * (kRsRounds * 64) + lane;
+    #pragma unroll
+    for (int r = 0; r < kRsRounds; ++r) {
+        const int64_t i = wbase + int64_t(r) * 64;
+        key[r] = i < n ? kin[i] : 0ull;
+        val[r] = i < n ? vin[i] : 0u;
+    }
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t pw[kRsRounds];   // position among this wave's keys of the same digit
+    #pragma unroll
+    for (int r = 0; r < kRsRounds; ++r) {
+        const bool valid = wbase + int64_t(r) * 64 < n;
+        const uint32_t d = uint32_t((key[r] >> shift) & 255u);
+        uint64_t mask = __ballot(valid);
+        #pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bb = __ballot(valid && ((d >> b) & 1u));
+            mask &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        const uint32_t rk = uint32_t(__popcll(mask & lt_mask));
+        const uint32_t off = valid ? cnt[wave][d] : 0u;
+        pw[r] = off + rk;
+        if (valid && rk == 0) cnt[wave][d] = off + uint32_t(__popcll(mask));
+    }
+    __syncthreads();
+    uint32_t run = 0;
+    if (tid < 256)
+        #pragma unroll
+        for (int w = 0; w < kRsWaves; ++w) {
+            const uint32_t c = cnt[w][tid];
+            cnt[w][tid] = run;
+            run += c;
+        }
+    int32_t tcount;
+    const uint32_t pref = uint32_t(block_exclusive_scan<kRsScatterThreads>(int32_t(run), &tcount));
+    if (tid < 256) {
+        s_pref[tid] = pref;
+        s_start[tid] = start - pref;   // output position of local position p of digit d: s_start[d] + p
+    }
+    __syncthreads();
+    #pragma unroll
+    for (int r = 0; r < kRsRounds; ++r)
+        if (wbase + int64_t(r) * 64 < n) {
+            const uint32_t d = uint32_t((key[r] >> shift) & 255u);
+            const uint32_t pos = s_pref[d] + cnt[wave][d] + pw[r];
+            sm.st.k[pos] = key[r];
+            sm.st.v[pos] = val[r];
+        }
+    __syncthreads();
+    for (int p = tid; p < tcount; p += kRsScatterThreads) {
+        const uint64_t k = sm.st.k[p];
+        const uint32_t o = s_start[(k >> shift) & 255u] + uint32_t(p);
+        kout[o] = k;
+        vout[o] = sm.st.v[p];
+    }
 }
 
 // Two-launch exclusive scan of `rows` rows of n values each (row r, item i = src(r, i)): the
@@ -715,28 +842,40 @@ void scan_child_classes(const uint64_t* box_key, int64_t nbox, int32_t* out, int
     scan_source(ChildClass{box_key}, out, nbox, 4, totals, scratch, st);
 }
 
+// Tiles whose counts a scatter block sums itself (tile-major counts, no scan launches); above
+// this, one flat exclusive scan of the digit-major counts gives the offsets.
+constexpr int64_t kRsSelfScanTiles = 512;
+
+int64_t radix_tiles(int64_t n) { return (n + kRsTile - 1) / kRsTile; }
+
+bool radix_digit_major(int64_t n) { return radix_tiles(n) > kRsSelfScanTiles; }
+
 size_t radix_scratch_bytes(int64_t n) {
-    const int64_t nblk = (n + kRsTile - 1) / kRsTile;
-    const size_t hist = size_t(256) * size_t(nblk) * sizeof(int32_t);
-    return 2 * hist + scan_scratch_bytes(256 * nblk, 1) + 256;
+    const size_t counts = size_t(256) * size_t(radix_tiles(n)) * sizeof(int32_t);
+    return ((2 * counts + 255) & ~size_t(255)) + scan_scratch_bytes(256 * radix_tiles(n), 1) + 256;
 }
 
+uint32_t* radix_counts(void* scratch) { return static_cast<uint32_t*>(scratch); }
+
 int radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp, int64_t n, int nbits,
-                     void* scratch, hipStream_t st) {
+                     bool counted0, void* scratch, hipStream_t st) {
     if (n <= 1 || nbits <= 0) return 0;
-    const int nblk = int((n + kRsTile - 1) / kRsTile);
-    int32_t* hist = static_cast<int32_t*>(scratch);
-    int32_t* offs = hist + size_t(256) * nblk;
-    void* sscr = offs + size_t(256) * nblk;
+    const int64_t nt = radix_tiles(n);
+    const bool dm = radix_digit_major(n);
+    const size_t counts = size_t(256) * size_t(nt);
+    uint32_t* C = radix_counts(scratch);
+    int32_t* offs = reinterpret_cast<int32_t*>(C + counts);
+    void* sscr = static_cast<char*>(scratch) + ((2 * counts * sizeof(int32_t) + 255) & ~size_t(255));
     uint64_t *ka = keys, *kb = keys_tmp;
     uint32_t *va = vals, *vb = vals_tmp;
     const int passes = (nbits + 7) / 8;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
-        hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kBlock), 0, st, ka, n, shift,
-                           reinterpret_cast<uint32_t*>(hist), nblk);
-        scan_rows(hist, offs, int64_t(256) * nblk, 1, nullptr, sscr, st);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(kBlock), 0, st, ka, va, kb, vb, n, shift, offs, nblk);
+        if (p > 0 || !counted0)
+            hipLaunchKernelGGL(k_rs_count, dim3(unsigned(nt)), dim3(kBlock), 0, st, ka, n, shift, C, nt, dm);
+        if (dm) scan_rows(reinterpret_cast<const int32_t*>(C), offs, int64_t(counts), 1, nullptr, sscr, st);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(unsigned(nt)), dim3(kRsScatterThreads), 0, st, ka, va, kb, vb, n,
+                           shift, C, dm ? offs : nullptr, nt);
         std::swap(ka, kb);
         std::swap(va, vb);
     }
@@ -761,17 +900,19 @@ void launch_bbox_final(const int32_t* part, const int32_t* chunk_first, const in
 }
 
 void launch_keys(const int32_t* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst, int Dmax, int64_t n,
-                 uint64_t* keys, uint32_t* vals, int32_t* zero, int32_t nzero, hipStream_t st) {
-    hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(kBlock), 0, st, reinterpret_cast<const int2*>(xy), pt_off, K,
-                       inst, Dmax, n, keys, vals, zero, nzero);
+                 uint64_t* keys, uint32_t* vals, int32_t* zero, int32_t nzero, void* radix_scratch,
+                 hipStream_t st) {
+    const int64_t nt = radix_tiles(n);
+    hipLaunchKernelGGL(k_keys, dim3(unsigned(nt)), dim3(kBlock), 0, st, reinterpret_cast<const int2*>(xy), pt_off, K,
+                       inst, Dmax, n, keys, vals, zero, nzero,
+                       radix_scratch ? radix_counts(radix_scratch) : static_cast<uint32_t*>(nullptr), nt,
+                       radix_digit_major(n));
 }
 
-void launch_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int32_t* xy, const InstInfo* inst,
-                          const int32_t* pt_off, int Dmax, int K, int64_t n, int32_t* pts, int32_t* perm_local,
-                          int32_t* pinst, hipStream_t st) {
-    hipLaunchKernelGGL(k_gather_sorted, dim3(grid_for(n)), dim3(kBlock), 0, st, keys, vals,
-                       reinterpret_cast<const int2*>(xy), inst, pt_off, Dmax, K, n, reinterpret_cast<int2*>(pts),
-                       perm_local, pinst);
+void launch_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int32_t* pt_off, int Dmax, int K,
+                          int64_t n, int32_t* pts, int32_t* perm_local, int32_t* pinst, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_sorted, dim3(grid_for(n)), dim3(kBlock), 0, st, keys, vals, pt_off, Dmax, K, n,
+                       reinterpret_cast<int2*>(pts), perm_local, pinst);
 }
 
 void launch_level_stats(const uint64_t* keys, const Chunk* chunks, int32_t nchunks, const InstInfo* inst, int Dmax,

@@ -107,10 +107,11 @@ enum BoxMatMode { kModeM2L = 0, kModeM2M = 1, kModeL2L = 2 };
 
 // ---- construction (forest_kernels.hip) ---------------------------------------------------
 size_t radix_scratch_bytes(int64_t n);
-// LSD radix sort of (keys, vals) on bits [0, nbits); returns which pair of buffers holds the
-// result: 0 = (keys, vals), 1 = (keys_tmp, vals_tmp).
+// LSD radix sort of (keys, vals) on bits [0, nbits), 8-bit digits; returns which pair of
+// buffers holds the result: 0 = (keys, vals), 1 = (keys_tmp, vals_tmp).  counted0: the tile
+// counts of the lowest digit are in the scratch already (launch_keys given the scratch).
 int radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp,
-                     int64_t n, int nbits, void* scratch, hipStream_t st);
+                     int64_t n, int nbits, bool counted0, void* scratch, hipStream_t st);
 // exclusive scan of `rows` rows of n int32 each (row stride n); totals[rows] if non-null.
 // Two launches; scratch holds one sum per 2048 items and row.
 size_t scan_scratch_bytes(int64_t n, int rows);
@@ -128,13 +129,15 @@ void launch_bbox_chunks(const int32_t* xy, const Chunk* chunks, int32_t nchunks,
 // point ranges and N_leaf into inst
 void launch_bbox_final(const int32_t* part, const int32_t* chunk_first, const int32_t* pt_off, int32_t K,
                        int32_t max_leaf, int32_t* bbox, InstInfo* inst, hipStream_t st);
-// keys and indices of the points; zeroes zero[0, nzero)
+// keys and indices of the points; zeroes zero[0, nzero); with radix_scratch (of
+// radix_scratch_bytes(n)) also the sort's tile counts of the lowest digit
 void launch_keys(const int32_t* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst,
                  int Dmax, int64_t n, uint64_t* keys, uint32_t* vals, int32_t* zero, int32_t nzero,
-                 hipStream_t st);
-void launch_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int32_t* xy,
-                          const InstInfo* inst, const int32_t* pt_off, int Dmax, int K, int64_t n,
-                          int32_t* pts, int32_t* perm_local, int32_t* pinst, hipStream_t st);
+                 void* radix_scratch, hipStream_t st);
+// sorted points (coordinates in the root box, decoded from the keys), instance-local indices
+// and instances
+void launch_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int32_t* pt_off, int Dmax, int K,
+                          int64_t n, int32_t* pts, int32_t* perm_local, int32_t* pinst, hipStream_t st);
 // per-level box counts (hist) and look-ahead maxima (maxc = hist + K (kMaxLevels + 2)) of
 // every instance; *done counts finished blocks (zero before the launch), and the last one
 // copies the nstats totals to host_out (host memory)

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 namespace lfmm {
 
@@ -117,6 +118,91 @@ __global__ __launch_bounds__(kBlock) void k_p2m(int32_t leaf0, int32_t leaf1, co
         }
     }
     if (lane < P) Q[size_t(g) * P + lane] = (a0 + a1) + (a2 + a3);
+}
+
+// P2M with the leaf operator staged in LDS (leaf sides whose T_ofs fits: side^2 P doubles):
+// persistent blocks of kP2mThreads copy T_ofs once, then each wave takes 8 leaves at a time,
+// one per 8-lane group; lane l of a group accumulates rows l, l + 8, ..., l + 40 of Q-hat over
+// the leaf's points, which the group loads 8 at a time and broadcasts by shuffles.  A group
+// past the others' point counts adds zero loads at cell 0.  The next leaves' box data are
+// loaded while the current ones are summed.
+constexpr int kP2mThreads = 1024;
+constexpr int kP2mGroup = 8;                   // lanes per leaf
+constexpr int kP2mLeaves = 64 / kP2mGroup;     // leaves per wave and step
+
+template <int P>
+__global__ __launch_bounds__(kP2mThreads) void k_p2m_lds(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0,
+                                                        const int32_t* box_pt1, const uint64_t* box_key, int64_t side,
+                                                        const int2* pts, const double* fs, const double* leafT,
+                                                        double* Q) {
+    constexpr int R = P / kP2mGroup;   // rows per lane
+    static_assert(P % kP2mGroup == 0, "rows split evenly over a group");
+    extern __shared__ double sT[];
+    const int ncell = int(side * side);
+    {
+        const double2* src = reinterpret_cast<const double2*>(leafT);
+        double2* dst = reinterpret_cast<double2*>(sT);
+        for (int i = int(threadIdx.x); i < ncell * P / 2; i += kP2mThreads) dst[i] = src[i];
+    }
+    const int wave = int(threadIdx.x) >> 6, lane = int(threadIdx.x) & 63, l = lane % kP2mGroup;
+    const int grp = lane / kP2mGroup;
+    const int32_t nleaf = leaf1 - leaf0;
+    const int32_t stride = int32_t(gridDim.x) * (kP2mThreads / 64) * kP2mLeaves;
+    int32_t q = (int32_t(blockIdx.x) * (kP2mThreads / 64) + wave) * kP2mLeaves;
+    // box data of this lane's leaf at step q
+    auto box = [&](int32_t qq, int32_t& p0, int32_t& npt, int32_t& cx, int32_t& cy) {
+        p0 = 0;
+        npt = 0;
+        cx = cy = 0;
+        if (qq + grp < nleaf) {
+            const int32_t g = leaf0 + qq + grp;
+            p0 = box_pt0[g];
+            npt = box_pt1[g] - p0;
+            const uint64_t key = box_key[g];
+            cx = int32_t(compact_bits(key) * side);
+            cy = int32_t(compact_bits(key >> 1) * side);
+        }
+    };
+    int32_t p0, npt, cx, cy;
+    box(q, p0, npt, cx, cy);
+    __syncthreads();
+    for (; q < nleaf; q += stride) {
+        int32_t np0, nnpt, ncx, ncy;
+        box(q + stride, np0, nnpt, ncx, ncy);
+        int32_t nmax = npt;
+        #pragma unroll
+        for (int o = kP2mGroup; o < 64; o <<= 1) nmax = max(nmax, __shfl_xor(nmax, o, 64));
+        double a[R];
+        #pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = 0.0;
+        for (int32_t c0 = 0; c0 < nmax; c0 += kP2mGroup) {
+            int32_t loc = 0;
+            double f = 0.0;
+            if (c0 + l < npt) {
+                const int2 pt = pts[p0 + c0 + l];
+                loc = int32_t(int64_t(pt.x - cx) + side * int64_t(pt.y - cy));
+                f = fs[p0 + c0 + l];
+            }
+            #pragma unroll
+            for (int k = 0; k < kP2mGroup; ++k) {
+                const int src = (lane & ~(kP2mGroup - 1)) | k;
+                const int32_t lk = __shfl(loc, src, 64);
+                const double fk = __shfl(f, src, 64);
+                const double* row = sT + lk * P + l;
+                #pragma unroll
+                for (int r = 0; r < R; ++r) a[r] += row[kP2mGroup * r] * fk;
+            }
+        }
+        if (q + grp < nleaf) {
+            double* out = Q + size_t(leaf0 + q + grp) * P + l;
+            #pragma unroll
+            for (int r = 0; r < R; ++r) out[kP2mGroup * r] = a[r];
+        }
+        p0 = np0;
+        npt = nnpt;
+        cx = ncx;
+        cy = ncy;
+    }
 }
 
 // XCD-aware tile order: blocks are dispatched round-robin over the 8 XCDs (block b runs on
@@ -667,9 +753,44 @@ void launch_gather_f(const ExecPtrs* tab, const double* f_single, const int32_t*
     hipLaunchKernelGGL(k_gather_f, dim3(grid_for(n)), dim3(kBlock), 0, st, tab, f_single, perm_local, pinst, n, fs);
 }
 
+// Per device: compute units and the LDS a block may use (the staged P2M is set up to use it).
+struct P2mDevice {
+    int cus = 0, lds = 0;
+};
+
+P2mDevice p2m_device() {
+    static P2mDevice dev[64];
+    static std::once_flag once[64];
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) return P2mDevice{};
+    std::call_once(once[d], [&] {
+        int cus = 0, lds = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess ||
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, d) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void*>(&k_p2m_lds<kRankPad>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) {
+            (void)hipGetLastError();
+            return;   // the unstaged kernel serves every side
+        }
+        dev[d] = P2mDevice{cus, lds};
+    });
+    return dev[d];
+}
+
 void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1, const uint64_t* box_key,
                 int64_t side, const int32_t* pts, const double* fs, const double* leafT, double* Q, hipStream_t st) {
     if (leaf1 <= leaf0) return;
+    const size_t lds = size_t(side * side) * kRankPad * sizeof(double);
+    const P2mDevice dv = p2m_device();
+    if (dv.cus > 0 && lds <= size_t(dv.lds)) {
+        const int per_cu = std::max(1, std::min(2, int(size_t(dv.lds) / lds)));
+        const int64_t per_block = (kP2mThreads / 64) * kP2mLeaves;
+        const int64_t want = (int64_t(leaf1 - leaf0) + per_block - 1) / per_block;
+        const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(want, int64_t(dv.cus) * per_cu));
+        hipLaunchKernelGGL(k_p2m_lds<kRankPad>, dim3(unsigned(grid)), dim3(kP2mThreads), lds, st, leaf0, leaf1,
+                           box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), fs, leafT, Q);
+        return;
+    }
     hipLaunchKernelGGL(k_p2m<kRankPad>, dim3(grid_for(leaf1 - leaf0, kWaves)), dim3(kBlock), 0, st, leaf0, leaf1,
                        box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), fs, leafT, Q);
 }

@@ -667,12 +667,24 @@ __global__ __launch_bounds__(kNearBlock) void k_near(int32_t q0, int32_t q1, con
     const int tid = threadIdx.x, wave = tid >> 6;
     if (MODE != kGlobal) {
         const int c = (MODE == kWindow) ? int(2 * side - 1) : 0;
-        for (int i = tid; i < W * W; i += kNearBlock) {
-            int dy = i / W - c, dx = i - (i / W) * W - c;
-            dx = dx < 0 ? -dx : dx;
-            dy = dy < 0 ? -dy : dy;
-            const int hi = max(dx, dy), lo = min(dx, dy);
-            tab[i] = phi_oct_tab[hi * (hi + 1) / 2 + lo];
+        constexpr int kU = 8;   // loads in flight per thread
+        for (int i0 = tid; i0 < W * W; i0 += kNearBlock * kU) {
+            double v[kU];
+            #pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = i0 + u * kNearBlock;
+                v[u] = 0.0;
+                if (i < W * W) {
+                    int dy = i / W - c, dx = i - (i / W) * W - c;
+                    dx = dx < 0 ? -dx : dx;
+                    dy = dy < 0 ? -dy : dy;
+                    const int hi = max(dx, dy), lo = min(dx, dy);
+                    v[u] = phi_oct_tab[hi * (hi + 1) / 2 + lo];
+                }
+            }
+            #pragma unroll
+            for (int u = 0; u < kU; ++u)
+                if (i0 + u * kNearBlock < W * W) tab[i0 + u * kNearBlock] = v[u];
         }
         __syncthreads();
     }
@@ -682,7 +694,9 @@ __global__ __launch_bounds__(kNearBlock) void k_near(int32_t q0, int32_t q1, con
         const int32_t qq = uniform(q);
         const int32_t leaf0 = uniform(groups[qq].leaf0), nleaf = uniform(groups[qq].nleaf);
         const int32_t nt = uniform(box_pt1[leaf0 + nleaf - 1]) - uniform(box_pt0[leaf0]);
-        if (nt > 32)   // half a wave or more busy in group mode; below that, leaf by leaf
+        // group mode when half a wave or more is busy and phi comes from an LDS table; leaf by
+        // leaf otherwise (the octant table in global memory is read faster a leaf at a time)
+        if (MODE != kGlobal && nt > 32)
             near_group<P, MODE, false>(qq, groups, ents, box_pt0, box_pt1, box_key, box_inst, side, W, tab, tb, pts,
                                        pkey, fs, perm_local, tab_ptrs, u_single, U, leafT, far_inst, phi_oct_tab);
         else

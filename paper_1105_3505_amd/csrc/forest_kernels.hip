@@ -228,15 +228,26 @@ __global__ void k_level_stats(const uint64_t* keys, const Chunk* chunks, const I
     if (threadIdx.x < kMaxLevels + 2) h[threadIdx.x] = 0;
     __syncthreads();
     int mc = -1;
-    for (int32_t base = c.begin; base < c.end; base += kBlock) {
-        const int32_t s = base + int32_t(threadIdx.x);
+    // every key the chunk needs is loaded first (its own, the previous and the one N_leaf on)
+    constexpr int kIt = kChunk / kBlock;
+    uint64_t kk[kIt], kp[kIt], ka[kIt];
+    #pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int32_t s = c.begin + it * kBlock + int32_t(threadIdx.x);
+        const bool valid = s < c.end;
+        kk[it] = valid ? keys[s] : 0ull;
+        kp[it] = (valid && s != I.pt0) ? keys[s - 1] : 0ull;
+        ka[it] = (valid && s + nleaf < I.pt1) ? keys[s + nleaf] : 0ull;
+    }
+    #pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int32_t s = c.begin + it * kBlock + int32_t(threadIdx.x);
         const bool valid = s < c.end;
         int v = -1;
         if (valid) {
-            const uint64_t key = keys[s];
-            v = (s == I.pt0) ? -1 : common_levels(key, keys[s - 1], Dmax) - shift;
+            v = (s == I.pt0) ? -1 : common_levels(kk[it], kp[it], Dmax) - shift;
             cl[s] = int8_t(v);
-            if (s + nleaf < I.pt1) mc = max(mc, common_levels(key, keys[s + nleaf], Dmax) - shift);
+            if (s + nleaf < I.pt1) mc = max(mc, common_levels(kk[it], ka[it], Dmax) - shift);
         }
         uint64_t active = __ballot(valid);
         while (active) {

@@ -615,7 +615,6 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     tmp.reserve(size_t(n) * 4);                 // vals
     tmp.reserve(size_t(n) * 4);                 // vals_tmp
     tmp.reserve(size_t(n));                     // cl
-    tmp.reserve(size_t(n) * 4);                 // scan
     tmp.reserve(radix_scratch_bytes(n));
     tmp.reserve(scan_scratch_bytes(n, 1));
     tmp.allocate();
@@ -647,7 +646,6 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     uint32_t* vals = tmp.take<uint32_t>(n);
     uint32_t* vals_tmp = tmp.take<uint32_t>(n);
     int8_t* cl = tmp.take<int8_t>(n);
-    int32_t* scan = tmp.take<int32_t>(n);
     void* rscr = tmp.take<char>(radix_scratch_bytes(n));
     void* sscr = tmp.take<char>(scan_scratch_bytes(n, 1));
 
@@ -988,8 +986,9 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     int32_t* ctotal = tmp2.take<int32_t>(16);
     void* cscr = tmp2.take<char>(scan_scratch_bytes(nb, 4));
 
-    scan_leaf_starts(cl, pl->pinst, pl->d_inst, n, scan, sscr, st);
-    launch_leaf_scatter(scan, skeys, cl, pl->pinst, pl->d_inst, Dmax, n, leaf_pt0, leaf_key, leaf_cl, leaf_inst, st);
+    // leaves (and the window keys of the points) straight from the scan of the leaf starts
+    scan_leaf_starts(cl, pl->pinst, pl->d_inst, n, skeys, Dmax, pl->pts, pl->pkey, leaf_pt0, leaf_key, leaf_cl,
+                     leaf_inst, sscr, st);
     if (Lmax > 0) scan_level_starts(leaf_cl, leaf_inst, pl->d_inst, nl, Lmax, lscan, lscr, st);
     launch_build_boxes(lscan, leaf_cl, leaf_pt0, leaf_key, leaf_inst, pl->d_inst, nl, Lmax, pl->box_key, pl->box_pt0,
                        pl->box_parent, pl->box_child, pl->box_inst, pl->box_lev, st);
@@ -1015,8 +1014,6 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     scan_child_classes(pl->box_key, nb, cscan, ctotal, cscr, st);
     launch_class_lists(d_groups, int32_t(groups.size()), tile_slots, cscan, ctotal, pl->box_key, nb, pl->cls_box,
                        pl->tiles, st);
-    if (std::any_of(side_of.begin(), side_of.end(), [](int64_t s) { return s <= 16; }))
-        launch_point_keys(pl->pts, pl->pinst, pl->d_inst, pl->d_ops, n, pl->pkey, st);
     LFMM_HIP(hipStreamWaitEvent(st, ctx->join, 0));
     LFMM_HIP(hipGetLastError());
     // staging for the per-execute pointer table of batched plans (and of graph replays,

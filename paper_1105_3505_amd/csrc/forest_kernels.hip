@@ -282,20 +282,6 @@ __global__ void k_level_stats(const uint64_t* keys, const Chunk* chunks, const I
         for (int i = threadIdx.x; i < nstats; i += blockDim.x) host_out[i] = atomicAdd(&hist[i], 0);
 }
 
-__global__ void k_leaf_scatter(const int32_t* scan, const uint64_t* keys, const int8_t* cl, const int32_t* pinst,
-                               const InstInfo* inst, int Dmax, int64_t n, int32_t* leaf_pt0, uint64_t* leaf_key,
-                               int8_t* leaf_cl, int32_t* leaf_inst) {
-    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int32_t k = pinst[s];
-    if (cl[s] >= inst[k].L) return;   // not the first point of a leaf
-    const int32_t r = scan[s];
-    leaf_pt0[r] = int32_t(s);
-    leaf_key[r] = (keys[s] & morton_mask(Dmax)) >> (2 * (inst[k].D - inst[k].L));
-    leaf_cl[r] = cl[s];
-    leaf_inst[r] = k;
-}
-
 // One thread per (leaf, level): the leaf that starts a box of that level writes the box and
 // its parent link.
 __global__ void k_build_boxes(const int32_t* lscan, const int8_t* leaf_cl, const int32_t* leaf_pt0,
@@ -561,16 +547,6 @@ __global__ void k_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, co
     }
 }
 
-__global__ void k_point_keys(const int2* pts, const int32_t* pinst, const InstInfo* inst, const OpsPtrs* ops,
-                             int64_t n, uint32_t* key) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t side = ops[inst[pinst[i]].ops].side;
-    const int2 p = pts[i];
-    const uint32_t W = uint32_t(4 * side - 1);
-    key[i] = 8u * (uint32_t(p.y) * W + uint32_t(p.x));   // modulo 2^32 on purpose
-}
-
 // ---- exclusive scan over rows of int32 -------------------------------------------------
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;
@@ -790,8 +766,47 @@ __global__ void k_scan_sums(Src src, int64_t n, int32_t* bsum, int nblk) {
     if (threadIdx.x == 0) bsum[size_t(row) * nblk + blockIdx.x] = sum;
 }
 
-template <class Src>
-__global__ void k_scan_apply(Src src, int32_t* out, int64_t n, const int32_t* bsum, int nblk, int32_t* totals) {
+// Where the prefixes go: by default into the output rows.
+struct StoreSink {
+    int32_t* out;
+    int64_t n;
+    __device__ void operator()(int row, int64_t i, int32_t x, int32_t) const { out[size_t(row) * n + i] = x; }
+};
+// Leaf starts: the point that starts leaf x writes that leaf's first point, key, level count
+// and instance; every point of a leaf side of at most 16 also gets its window key
+// K = 8 (y W + x) mod 2^32 (W = 4 side - 1) for the near field.
+struct LeafSink {
+    const uint64_t* keys;
+    const int8_t* cl;
+    const int32_t* pinst;
+    const InstInfo* inst;
+    int Dmax;
+    const int2* pts;
+    uint32_t* pkey;
+    int32_t* leaf_pt0;
+    uint64_t* leaf_key;
+    int8_t* leaf_cl;
+    int32_t* leaf_inst;
+    __device__ void operator()(int, int64_t s, int32_t r, int32_t flag) const {
+        const int32_t k = pinst[s];
+        const InstInfo& I = inst[k];
+        if (flag) {
+            leaf_pt0[r] = int32_t(s);
+            leaf_key[r] = (keys[s] & morton_mask(Dmax)) >> (2 * (I.D - I.L));
+            leaf_cl[r] = cl[s];
+            leaf_inst[r] = k;
+        }
+        const int64_t side = int64_t(1) << (I.D - I.L);
+        if (side <= 16) {
+            const int2 p = pts[s];
+            const uint32_t W = uint32_t(4 * side - 1);
+            pkey[s] = 8u * (uint32_t(p.y) * W + uint32_t(p.x));   // modulo 2^32 on purpose
+        }
+    }
+};
+
+template <class Src, class Sink>
+__global__ void k_scan_apply(Src src, Sink sink, int64_t n, const int32_t* bsum, int nblk, int32_t* totals) {
     const int row = blockIdx.y;
     const int32_t* bs = bsum + size_t(row) * nblk;
     int32_t pre = 0;
@@ -807,24 +822,28 @@ __global__ void k_scan_apply(Src src, int32_t* out, int64_t n, const int32_t* bs
     }
     int32_t tot;
     int32_t x = pre + block_exclusive_scan(s, &tot);
-    int32_t* rout = out + size_t(row) * n;
     #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) rout[base + k] = x;
+        if (base + k < n) sink(row, base + k, x, v[k]);
         x += v[k];
     }
     if (totals && blockIdx.x == unsigned(nblk - 1) && threadIdx.x == 0) totals[row] = pre + tot;
 }
 
-template <class Src>
-void scan_source(Src src, int32_t* out, int64_t n, int rows, int32_t* totals, void* scratch, hipStream_t st) {
+template <class Src, class Sink>
+void scan_sink(Src src, Sink sink, int64_t n, int rows, int32_t* totals, void* scratch, hipStream_t st) {
     if (n <= 0 || rows <= 0) return;
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     int32_t* bsum = static_cast<int32_t*>(scratch);
     hipLaunchKernelGGL(k_scan_sums<Src>, dim3(unsigned(nb), unsigned(rows)), dim3(kBlock), 0, st, src, n, bsum,
                        int(nb));
-    hipLaunchKernelGGL(k_scan_apply<Src>, dim3(unsigned(nb), unsigned(rows)), dim3(kBlock), 0, st, src, out, n, bsum,
-                       int(nb), totals);
+    hipLaunchKernelGGL((k_scan_apply<Src, Sink>), dim3(unsigned(nb), unsigned(rows)), dim3(kBlock), 0, st, src, sink,
+                       n, bsum, int(nb), totals);
+}
+
+template <class Src>
+void scan_source(Src src, int32_t* out, int64_t n, int rows, int32_t* totals, void* scratch, hipStream_t st) {
+    scan_sink(src, StoreSink{out, n}, n, rows, totals, scratch, st);
 }
 
 }  // namespace
@@ -838,9 +857,13 @@ void scan_rows(const int32_t* in, int32_t* out, int64_t n, int rows, int32_t* to
     scan_source(RowsArray{in, n}, out, n, rows, totals, scratch, st);
 }
 
-void scan_leaf_starts(const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int64_t n, int32_t* out,
-                      void* scratch, hipStream_t st) {
-    scan_source(LeafStart{cl, pinst, inst}, out, n, 1, nullptr, scratch, st);
+void scan_leaf_starts(const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int64_t n, const uint64_t* keys,
+                      int Dmax, const int32_t* pts, uint32_t* pkey, int32_t* leaf_pt0, uint64_t* leaf_key,
+                      int8_t* leaf_cl, int32_t* leaf_inst, void* scratch, hipStream_t st) {
+    scan_sink(LeafStart{cl, pinst, inst},
+              LeafSink{keys, cl, pinst, inst, Dmax, reinterpret_cast<const int2*>(pts), pkey, leaf_pt0, leaf_key,
+                       leaf_cl, leaf_inst},
+              n, 1, nullptr, scratch, st);
 }
 
 void scan_level_starts(const int8_t* leaf_cl, const int32_t* leaf_inst, const InstInfo* inst, int64_t nleaf,
@@ -933,13 +956,6 @@ void launch_level_stats(const uint64_t* keys, const Chunk* chunks, int32_t nchun
                        maxc, done, nstats, host_out);
 }
 
-void launch_leaf_scatter(const int32_t* scan, const uint64_t* keys, const int8_t* cl, const int32_t* pinst,
-                         const InstInfo* inst, int Dmax, int64_t n, int32_t* leaf_pt0, uint64_t* leaf_key,
-                         int8_t* leaf_cl, int32_t* leaf_inst, hipStream_t st) {
-    hipLaunchKernelGGL(k_leaf_scatter, dim3(grid_for(n)), dim3(kBlock), 0, st, scan, keys, cl, pinst, inst, Dmax,
-                       n, leaf_pt0, leaf_key, leaf_cl, leaf_inst);
-}
-
 void launch_build_boxes(const int32_t* lscan, const int8_t* leaf_cl, const int32_t* leaf_pt0, const uint64_t* leaf_key,
                         const int32_t* leaf_inst, const InstInfo* inst, int64_t nleaf, int Lmax, uint64_t* box_key,
                         int32_t* box_pt0, int32_t* box_parent, int32_t* box_child, int32_t* box_inst,
@@ -985,12 +1001,6 @@ void launch_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, const in
     hipLaunchKernelGGL(k_near_groups, dim3(grid_for(int64_t(n) * 16)), dim3(kBlock), 0, st, q0, h1_start, h1_count,
                        roots, nroots,
                        box_child, nb9, box_pt0, box_pt1, box_key, groups, ents);
-}
-
-void launch_point_keys(const int32_t* pts, const int32_t* pinst, const InstInfo* inst, const OpsPtrs* ops, int64_t n,
-                       uint32_t* key, hipStream_t st) {
-    hipLaunchKernelGGL(k_point_keys, dim3(grid_for(n)), dim3(kBlock), 0, st, reinterpret_cast<const int2*>(pts), pinst,
-                       inst, ops, n, key);
 }
 
 }  // namespace lfmm

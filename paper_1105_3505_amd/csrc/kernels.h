@@ -147,15 +147,13 @@ void launch_level_stats(const uint64_t* keys, const Chunk* chunks, int32_t nchun
                         hipStream_t st);
 // exclusive scans of the flags "a leaf starts here" (per point), "leaf b starts a box of
 // level lev" (row lev, per leaf) and "box g is child c of its parent" (row c, per box)
-void scan_leaf_starts(const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int64_t n, int32_t* out,
-                      void* scratch, hipStream_t st);
+void scan_leaf_starts(const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int64_t n,
+                      const uint64_t* keys, int Dmax, const int32_t* pts, uint32_t* pkey, int32_t* leaf_pt0,
+                      uint64_t* leaf_key, int8_t* leaf_cl, int32_t* leaf_inst, void* scratch, hipStream_t st);
 void scan_level_starts(const int8_t* leaf_cl, const int32_t* leaf_inst, const InstInfo* inst, int64_t nleaf,
                        int Lmax, int32_t* out, void* scratch, hipStream_t st);
 void scan_child_classes(const uint64_t* box_key, int64_t nbox, int32_t* out, int32_t* totals, void* scratch,
                         hipStream_t st);
-void launch_leaf_scatter(const int32_t* scan, const uint64_t* keys, const int8_t* cl, const int32_t* pinst,
-                         const InstInfo* inst, int Dmax, int64_t n, int32_t* leaf_pt0, uint64_t* leaf_key,
-                         int8_t* leaf_cl, int32_t* leaf_inst, hipStream_t st);
 void launch_build_boxes(const int32_t* lscan, const int8_t* leaf_cl, const int32_t* leaf_pt0,
                         const uint64_t* leaf_key, const int32_t* leaf_inst, const InstInfo* inst,
                         int64_t nleaf, int Lmax, uint64_t* box_key, int32_t* box_pt0,
@@ -176,8 +174,6 @@ void launch_lists(const uint64_t* box_key, const int32_t* box_parent, const int3
 void launch_class_lists(const BoxGroup* groups, int32_t ngroups, int32_t nslots, const int32_t* cscan,
                         const int32_t* ctotal, const uint64_t* box_key, int64_t nbox,
                         int32_t* cls_box, BoxTile* tiles, hipStream_t st);
-void launch_point_keys(const int32_t* pts, const int32_t* pinst, const InstInfo* inst,
-                       const OpsPtrs* ops, int64_t n, uint32_t* key, hipStream_t st);
 // near-field groups [q0, q0 + h1_count + nroots): the children of the height-1 boxes
 // h1_start .. h1_start + h1_count - 1, then the root leaves roots[0 .. nroots)
 void launch_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, const int32_t* roots, int32_t nroots,

@@ -22,6 +22,10 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kOctRadius = 128;
+// Levels of at most this many 64-box tiles run M2M and L2L on the fine-grained kernels, which
+// spread one tile over twelve blocks (measured: M2M gains up to 64 tiles, L2L up to 256).
+constexpr int32_t kFineM2mTiles = 64;
+constexpr int32_t kFineL2lTiles = 256;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kEulerGamma = 0.57721566490153286061;
 
@@ -291,6 +295,25 @@ __device__ inline void boxmat_tiles(const BoxTile* tiles, int32_t ntiles, const 
         double2_t ra0 = Ak[tid], ra1 = Ak[tid + kBlock], ra2 = Ak[tid + 2 * kBlock], ra3 = Ak[tid + 3 * kBlock];
         double2_t ra4 = (tid < kBlock / 2) ? Ak[tid + 4 * kBlock] : z2;
         double4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0;
+        // M2M and L2L sum their contraction as four partial products added in order, the same
+        // arithmetic as the fine-grained kernels below, so that a box's result does not depend
+        // on which kernel its level runs on.
+        double4_t run0 = acc0, run1 = acc0, run2 = acc0;
+        auto fold = [&](bool first) {
+            const double4_t z4 = {0.0, 0.0, 0.0, 0.0};
+            if (first) {
+                run0 = acc0;
+                run1 = acc1;
+                run2 = acc2;
+            } else {
+                run0 += acc0;
+                run1 += acc1;
+                run2 += acc2;
+            }
+            acc0 = z4;
+            acc1 = z4;
+            acc2 = z4;
+        };
         for (int k = 0; k < NS; ++k) {
             double2_t* buf = sA[k & 1];
             buf[tid] = ra0;
@@ -324,14 +347,24 @@ __device__ inline void boxmat_tiles(const BoxTile* tiles, int32_t ntiles, const 
                     const double2_t a0 = buf[(0 * NJ + j) * 64 + lane];
                     const double2_t a1 = buf[(1 * NJ + j) * 64 + lane];
                     const double2_t a2 = buf[(2 * NJ + j) * 64 + lane];
-                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, b[j].x, acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, b[j].x, acc1, 0, 0, 0);
-                    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2.x, b[j].x, acc2, 0, 0, 0);
-                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, b[j].y, acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, b[j].y, acc1, 0, 0, 0);
-                    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2.y, b[j].y, acc2, 0, 0, 0);
+                    #pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        if (MODE == kModeL2L && (2 * j + e) % 3 == 0 && j + e > 0) {
+                            fold(2 * j + e == 3);   // step 3 c starts the c-th partial sum
+                        }
+                        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(e ? a0.y : a0.x, e ? b[j].y : b[j].x, acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(e ? a1.y : a1.x, e ? b[j].y : b[j].x, acc1, 0, 0, 0);
+                        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(e ? a2.y : a2.x, e ? b[j].y : b[j].x, acc2, 0, 0, 0);
+                    }
                 }
             }
+            if (MODE == kModeM2M) fold(k == 0);   // one partial sum per child slot
+        }
+        if (MODE == kModeL2L) fold(false);
+        if (MODE != kModeM2L) {
+            acc0 = run0;
+            acc1 = run1;
+            acc2 = run2;
         }
         if (box >= 0) {
             double* ob = out + size_t(box) * P;
@@ -367,6 +400,87 @@ __global__ __launch_bounds__(kBlock) void k_l2l(const BoxTile* tiles, int32_t nt
                                                  const int32_t* box_parent, const OpsPtrs* ops, double* U,
                                                  int32_t zrow) {
     boxmat_tiles<kModeL2L>(tiles, ntiles, box_list, box_parent, ops, U, zrow, U);
+}
+
+// Box-matrix passes for levels with few boxes (M2M and L2L).  The kernels above run a 64-box
+// tile on one block whose waves each run every slot, so a level of a handful of tiles lasts a
+// whole sequence of dependent products on one SIMD.  Here block (t, q, m) computes rows
+// 16 m .. 16 m + 15 of boxes 16 q .. 16 q + 15 of tile t, and its four waves split the
+// contraction: in M2M wave w applies the operator of child slot w; in L2L wave w takes steps
+// 3 w .. 3 w + 2 of the twelve 16x16x4 steps of the parent's operator.  The four partial
+// products meet in LDS in a fixed order, and wave w writes element w of every lane's four.
+// Operator fragments are read straight from the fragment-ordered table (the rows of one row
+// block are contiguous there), without LDS staging.
+template <int MODE>
+__device__ inline void boxmat_fine(const BoxTile* tiles, const int32_t* box_list, const int32_t* src_tab,
+                                   const OpsPtrs* ops, const double* in, int32_t zrow, double* out) {
+    constexpr int P = kRankPad, KQ = P / 4, NJ = KQ / 2, A2 = P * P / 2;
+    static_assert(MODE == kModeM2M || MODE == kModeL2L, "fine mode serves M2M and L2L");
+    __shared__ double red[4][4][64];
+    const int tid = int(threadIdx.x), wave = tid >> 6, lane = tid & 63;
+    const int n = lane & 15, g = lane >> 4;
+    const int32_t b = int32_t(blockIdx.x);
+    const int m = b % 3, q = (b / 3) & 3;
+    const int32_t t = b / 12;
+    const int32_t count = uniform(tiles[t].count);
+    if (16 * q >= count) return;                       // uniform over the block, before any barrier
+    const int32_t start = uniform(tiles[t].start), height = uniform(tiles[t].height);
+    const int32_t cls = uniform(tiles[t].cls), opi = uniform(tiles[t].ops);
+    const int col = 16 * q + n;
+    const int32_t box = (col < count) ? (MODE == kModeL2L ? box_list[start + col] : start + col) : -1;
+    int32_t src = -1;
+    if (box >= 0) src = (MODE == kModeM2M) ? src_tab[size_t(box) * 4 + wave] : src_tab[box];
+    src = src < 0 ? zrow : src;
+    const gptr<double> xs = global(in) + size_t(src) * P + g * KQ;
+    const double old = (MODE == kModeL2L && box >= 0) ? out[size_t(box) * P + 16 * m + g + 4 * wave] : 0.0;
+    const double4_t zero4 = {0.0, 0.0, 0.0, 0.0};
+    double4_t acc = zero4;
+    if (MODE == kModeM2M) {
+        const gptr<double2_t> A = global(reinterpret_cast<const double2_t*>(ops[opi].ofo_rm)) +
+                                  size_t(height * 4 + wave) * A2 + size_t(m * NJ) * 64 + lane;
+        const gptr<double2_t> xb = reinterpret_cast<gptr<double2_t>>(xs);
+        double2_t a[NJ], x[NJ];
+        #pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            x[j] = xb[j];
+            a[j] = A[j * 64];
+        }
+        #pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].x, x[j].x, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].y, x[j].y, acc, 0, 0, 0);
+        }
+    } else {
+        const gptr<double> A = global(ops[opi].ofo_cm) + size_t((height + 1) * 4 + cls) * (2 * A2) +
+                               size_t(m * NJ) * 128 + 2 * lane;
+        double a[3], x[3];
+        #pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const int s = 3 * wave + r, j = s >> 1, e = s & 1;   // step s = 2 j + e
+            x[r] = xs[s];
+            a[r] = A[j * 128 + e];
+        }
+        #pragma unroll
+        for (int r = 0; r < 3; ++r) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], x[r], acc, 0, 0, 0);
+    }
+    #pragma unroll
+    for (int i = 0; i < 4; ++i) red[wave][i][lane] = acc[i];
+    __syncthreads();
+    const double v = ((red[0][wave][lane] + red[1][wave][lane]) + red[2][wave][lane]) + red[3][wave][lane];
+    if (box >= 0) {
+        out[size_t(box) * P + 16 * m + g + 4 * wave] = (MODE == kModeL2L) ? old + v : v;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_m2m_fine(const BoxTile* tiles, const int32_t* box_child,
+                                                      const OpsPtrs* ops, double* Q, int32_t zrow) {
+    boxmat_fine<kModeM2M>(tiles, nullptr, box_child, ops, Q, zrow, Q);
+}
+
+__global__ __launch_bounds__(kBlock) void k_l2l_fine(const BoxTile* tiles, const int32_t* box_list,
+                                                      const int32_t* box_parent, const OpsPtrs* ops, double* U,
+                                                      int32_t zrow) {
+    boxmat_fine<kModeL2L>(tiles, box_list, box_parent, ops, U, zrow, U);
 }
 
 // Mixed-precision M2L on the FP32 matrix cores, same tiling and staging as k_m2l.  Each
@@ -812,6 +926,11 @@ void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int3
 void launch_m2m(const BoxTile* tiles, int32_t ntiles, const int32_t* box_child, const OpsPtrs* ops, double* Q,
                 int32_t zrow, hipStream_t st) {
     if (ntiles <= 0) return;
+    if (ntiles <= kFineM2mTiles) {
+        hipLaunchKernelGGL(k_m2m_fine, dim3(unsigned(ntiles) * 12u), dim3(kBlock), 0, st, tiles, box_child, ops, Q,
+                           zrow);
+        return;
+    }
     int64_t g = std::min<int64_t>(ntiles, 8192);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
     hipLaunchKernelGGL(k_m2m, dim3(static_cast<unsigned>(g)), dim3(kBlock), 0, st, tiles, ntiles, box_child, ops, Q,
@@ -821,6 +940,11 @@ void launch_m2m(const BoxTile* tiles, int32_t ntiles, const int32_t* box_child, 
 void launch_l2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, const int32_t* box_parent,
                 const OpsPtrs* ops, double* U, int32_t zrow, hipStream_t st) {
     if (ntiles <= 0) return;
+    if (ntiles <= kFineL2lTiles) {
+        hipLaunchKernelGGL(k_l2l_fine, dim3(unsigned(ntiles) * 12u), dim3(kBlock), 0, st, tiles, box_list, box_parent,
+                           ops, U, zrow);
+        return;
+    }
     int64_t g = std::min<int64_t>(ntiles, 8192);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
     hipLaunchKernelGGL(k_l2l, dim3(static_cast<unsigned>(g)), dim3(kBlock), 0, st, tiles, ntiles, box_list,

@@ -72,10 +72,10 @@ def measured_traffic(workload: str, kernel: str):
     return None if entry is None else entry["bytes"]
 
 
-def roofline(phases: dict, info: dict, n: int, precision: str, workload: str) -> dict:
-    """Roofline entry for the phase that takes the longest (HIP events on the execute stream)."""
-    dom = max(phases, key=phases.get)
-    sec = phases[dom] * 1e-3
+def roofline(dom: str, dom_ms: float, info: dict, n: int, precision: str, workload: str) -> dict:
+    """Roofline entry for the dominant phase `dom`, whose average duration over the timed
+    solves (HIP events on the execute stream) is dom_ms."""
+    sec = dom_ms * 1e-3
     if dom == "m2l":
         flops = 2.0 * RANK * RANK * info["m2l_pairs"]
         achieved = flops / sec / 1e12
@@ -104,6 +104,44 @@ def base_result(args, value, ms_per_step, config, dtype="f64"):
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config,
     }
+
+
+PHASES_ALL = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf")
+
+
+def measure(step, steps, torch):
+    """Phase split, timed region and latencies of `step` (one whole solve: plan build, execute,
+    plan release).  First a few solves with HIP events between all phases (outside the timed
+    region) pick the dominant phase; the timed region then runs `steps` solves back to back
+    between two device synchronisations, each recording only the two events around that phase
+    (its duration on the execute stream, for the roofline); last, solve latencies with each
+    solve synchronised on its own and no events."""
+    phases = []
+    for _ in range(min(steps, 5)):
+        plan = step(PHASES_ALL)
+        torch.cuda.synchronize()
+        phases.append(plan.phase_times())
+        plan.close()
+    avg = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
+    dom = max(avg, key=avg.get)
+    dom_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan = step([dom])
+        dom_ms.append(plan.phase_times()[dom])
+        plan.close()
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / steps
+    lat = []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plan = step(None)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e3)
+        plan.close()
+    return ms_per_step, lat, avg, dom, float(np.mean(dom_ms))
 
 
 def cpu_baseline(xy, f, u, n_targets, seed=20):
@@ -137,28 +175,16 @@ def run_single(args, torch, lf):
     ctx = lf.Context(0, precision=args.precision, max_leaf=args.max_leaf)
     stream = torch.cuda.current_stream()
 
-    def step(timed=False):
+    def step(timing):
         plan = ctx.plan(xy_d, stream=stream)
-        if timed:
-            plan.set_timing(True)
+        if timing:
+            plan.set_timing_phases(timing)
         plan.execute(f_d, u_d, stream=stream)
         return plan
 
     for _ in range(max(args.warmup, 1)):
-        step().close()
-    torch.cuda.synchronize()
-    lat, phases = [], []
-    torch.cuda.synchronize()
-    t_all = time.perf_counter()
-    for _ in range(args.steps):
-        t0 = time.perf_counter()
-        plan = step(timed=True)
-        torch.cuda.synchronize()
-        lat.append((time.perf_counter() - t0) * 1e3)
-        phases.append(plan.phase_times())
-        plan.close()
-    torch.cuda.synchronize()
-    ms_per_step = (time.perf_counter() - t_all) * 1e3 / args.steps
+        step(None).close()
+    ms_per_step, lat, avg, dom, dom_ms = measure(step, args.steps, torch)
     value = n / (ms_per_step * 1e-3) / 1e6
 
     # execute-only throughput on a resident plan (outside the timed steps: plan statistics)
@@ -177,7 +203,6 @@ def run_single(args, torch, lf):
     plan.close()
     ctx.close()
 
-    avg = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
     config = {"workload": WORKLOADS[args.workload], "n_sources": n, "precision": args.precision,
               "leaf_level": info["leaf_level"], "leaf_side": info["leaf_side"], "max_leaf": args.max_leaf,
               "rank": RANK, "eps": 1e-12}
@@ -185,7 +210,7 @@ def run_single(args, torch, lf):
     result.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                    "execute_only_ms": exec_ms, "execute_only_msources_per_s": n / (exec_ms * 1e-3) / 1e6,
                    "phase_ms": avg, "plan": info,
-                   "roofline": roofline(avg, info, n, args.precision, args.workload)})
+                   "roofline": roofline(dom, dom_ms, info, n, args.precision, args.workload)})
     if not args.no_cpu_baseline:
         err, k, base = cpu_baseline(xy, f, u, args.cpu_targets)
         result["rel_err_vs_oracle"] = err
@@ -205,28 +230,16 @@ def run_batched(args, torch, lf):
     ctx = lf.Context(0, precision=args.precision, max_leaf=args.max_leaf)
     stream = torch.cuda.current_stream()
 
-    def step(timed=False):
+    def step(timing):
         plan = ctx.plan_batch(xs, stream=stream)
-        if timed:
-            plan.set_timing(True)
+        if timing:
+            plan.set_timing_phases(timing)
         plan.execute_instances(fs, us, stream=stream)
         return plan
 
     for _ in range(max(args.warmup, 1)):
-        step().close()
-    torch.cuda.synchronize()
-    lat, phases = [], []
-    torch.cuda.synchronize()
-    t_all = time.perf_counter()
-    for _ in range(args.steps):
-        t0 = time.perf_counter()
-        plan = step(timed=True)
-        torch.cuda.synchronize()
-        lat.append((time.perf_counter() - t0) * 1e3)
-        phases.append(plan.phase_times())
-        plan.close()
-    torch.cuda.synchronize()
-    ms_per_step = (time.perf_counter() - t_all) * 1e3 / args.steps
+        step(None).close()
+    ms_per_step, lat, avg, dom, dom_ms = measure(step, args.steps, torch)
     plan = ctx.plan_batch(xs, stream=stream)
     info = plan.info()
     plan.execute_instances(fs, us, stream=stream)
@@ -239,14 +252,13 @@ def run_batched(args, torch, lf):
     exec_ms = (time.perf_counter() - t0) * 1e3 / reps
     plan.close()
     ctx.close()
-    avg = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
     config = {"workload": WORKLOADS["batched"], "n_instances": len(inst), "n_sources": n,
               "precision": args.precision, "max_leaf": args.max_leaf, "rank": RANK, "eps": 1e-12}
     result = base_result(args, n / (ms_per_step * 1e-3) / 1e6, ms_per_step, config)
     result.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                    "execute_only_ms": exec_ms, "execute_only_msources_per_s": n / (exec_ms * 1e-3) / 1e6,
                    "phase_ms": avg, "plan": info,
-                   "roofline": roofline(avg, info, n, args.precision, "batched")})
+                   "roofline": roofline(dom, dom_ms, info, n, args.precision, "batched")})
     if not args.no_cpu_baseline:
         # accuracy on 100 sampled targets of every 8th instance; CPU rate over that sample
         from oracle import direct as od

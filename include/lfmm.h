@@ -176,8 +176,14 @@ typedef enum lfmm_phase {
  * the execute stream around each phase; off by default). */
 lfmm_status lfmm_plan_set_timing(lfmm_plan* plan, int32_t enable);
 
+/* Times only the phases in phase_mask (bit k = lfmm_phase k; 0 turns timing off): later
+ * lfmm_execute calls record just the events that bound those phases, each event costing a
+ * few microseconds of device time.  LFMM_E_INVAL for bits above the last phase. */
+lfmm_status lfmm_plan_set_timing_phases(lfmm_plan* plan, uint32_t phase_mask);
+
 /* Milliseconds spent in each phase by the most recent timed lfmm_execute of this plan,
- * ms_host[LFMM_NUM_PHASES]; waits for that execute to finish. */
+ * ms_host[LFMM_NUM_PHASES] (NaN for phases that execute did not time); waits for that
+ * execute to finish.  LFMM_E_INVAL before any timed execute. */
 lfmm_status lfmm_plan_phase_times(lfmm_plan* plan, double* ms_host);
 
 /* Plan internals that lfmm_plan_export copies to the host, for inspection and tests.

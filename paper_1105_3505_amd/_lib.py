@@ -73,6 +73,7 @@ def _load():
         "lfmm_plan_get_info": [_vp, _vp],
         "lfmm_autotune": [_vp, _i64, _vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp],
         "lfmm_plan_set_timing": [_vp, _i32],
+        "lfmm_plan_set_timing_phases": [_vp, ctypes.c_uint32],
         "lfmm_plan_export": [_vp, _i32, _vp, _vp],
         "lfmm_plan_phase_times": [_vp, _vp],
         "lfmm_plan_footprint_bytes": [_vp, _i64, _vp],
@@ -318,11 +319,18 @@ class Plan:
     def set_timing(self, enable: bool = True) -> None:
         _check(_lib.lfmm_plan_set_timing(self._h, 1 if enable else 0))
 
+    def set_timing_phases(self, phases) -> None:
+        """Time only the named phases (events around them alone); an empty list turns timing off."""
+        mask = 0
+        for name in phases:
+            mask |= 1 << self.PHASES.index(name)
+        _check(_lib.lfmm_plan_set_timing_phases(self._h, mask))
+
     def phase_times(self) -> dict:
-        """Milliseconds per phase of the last timed execute (HIP events on its stream)."""
+        """Milliseconds per timed phase of the last timed execute (HIP events on its stream)."""
         out = (ctypes.c_double * len(self.PHASES))()
         _check(_lib.lfmm_plan_phase_times(self._h, out))
-        return dict(zip(self.PHASES, list(out)))
+        return {k: v for k, v in zip(self.PHASES, list(out)) if v == v}
 
     def info(self) -> dict:
         i = _PlanInfo()

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -227,6 +228,12 @@ class PinnedPool {
         }
         void* p = nullptr;
         LFMM_HIP(hipHostMalloc(&p, cls));
+        // kernels read these blocks through the host pointer (the upload copies)
+        void* dp = nullptr;
+        if (hipHostGetDevicePointer(&dp, p, 0) != hipSuccess || dp != p) {
+            (void)hipHostFree(p);
+            throw std::runtime_error("pinned host memory is not addressable from the device at its host address");
+        }
         return p;
     }
     void release(void* p, size_t cls) {
@@ -329,8 +336,8 @@ struct lfmm_plan {
     size_t h_exec_cls = 0;
     hipEvent_t exec_copied = nullptr;       // the last staging copy has been read
     bool failed = false;
-    bool timing = false;
-    bool timed_once = false;
+    uint32_t timing_mask = 0;   // phases whose bounding events later executes record
+    uint32_t timed_mask = 0;    // phases timed by the most recent timed execute
     bool use_graph = false;                 // execute replays a captured HIP graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -515,9 +522,10 @@ OpsPtrs ops_ptrs(const CachedOps* co) {
 
 // Host-to-device copies of small tables, gathered so that tables that lie next to each other
 // in device memory (less than one 256-byte alignment step apart, so that nothing else lies
-// between them) go in one copy from pinned memory: a copy from pageable memory costs several
-// microseconds however small it is.  The pinned blocks are held until the Stager is
-// destroyed, which must come after the stream has passed the copies.
+// between them) go in one copy from pinned memory.  The copies are kernels that read the
+// pinned block directly: a copy-engine transfer costs tens of microseconds of hand-over
+// between the copy and compute queues on the stream.  The pinned blocks are held until the
+// Stager is destroyed, which must come after the stream has passed the copies.
 class Stager {
   public:
     explicit Stager(lfmm_ctx* ctx) : ctx_(ctx) {}
@@ -545,7 +553,7 @@ class Stager {
             held_.push_back({h, cls});
             for (size_t k = i; k < j; ++k)
                 std::memcpy(h + (pieces_[k].dst - pieces_[i].dst), pieces_[k].data.data(), pieces_[k].data.size());
-            LFMM_HIP(hipMemcpyAsync(pieces_[i].dst, h, len, hipMemcpyHostToDevice, st));
+            launch_upload(pieces_[i].dst, h, len, st);
             i = j;
         }
         pieces_.clear();
@@ -609,6 +617,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     tmp.reserve(size_t(nch) * 16);              // bbox partials
     tmp.reserve(size_t(K) * sizeof(InstInfo));  // instances up to the level statistics
     tmp.reserve(size_t(K) * (kMaxLevels + 3) * 4 + 4);   // level histograms, lookahead maxima, counter
+    tmp.reserve(4);                             // deepest root box
     tmp.reserve(K > 1 ? size_t(n) * 8 : 0);     // concatenated points
     tmp.reserve(size_t(n) * 8);                 // keys
     tmp.reserve(size_t(n) * 8);                 // keys_tmp
@@ -628,6 +637,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     int32_t* d_stats = tmp.take<int32_t>(size_t(K) * (kMaxLevels + 3) + 1);
     int32_t* d_hist = d_stats;
     int32_t* d_maxc = d_stats + size_t(K) * (kMaxLevels + 2);
+    int32_t* d_dmax = tmp.take<int32_t>(1);
     // host-visible results of the two read-backs (pinned: the root boxes are written there by
     // the kernel itself, the level statistics by one copy)
     size_t rb_cls = 0;
@@ -671,10 +681,19 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     }
 
     // ---- root boxes ----------------------------------------------------------------------
-    launch_bbox_chunks(xy, d_chunks, nch, d_part, st);
-    // root boxes straight to pinned host memory, and (with one N_leaf for all) the instance
-    // table of the next kernels straight to the device
-    launch_bbox_final(d_part, d_chfirst, d_ptoff, K, std::max(ml_all, 0), bb, d_inst0, st);
+    launch_bbox_chunks(xy, d_chunks, nch, d_part, d_dmax, st);
+    // root boxes straight to pinned host memory, and the instance table of the next kernels
+    // (N_leaf too when there is one for all) straight to the device
+    launch_bbox_final(d_part, d_chfirst, d_ptoff, K, std::max(ml_all, 0), bb, d_inst0, d_dmax, st);
+    Fence bb_ready(st);
+    // Morton keys and, for large inputs, the first two passes of their sort go out before the
+    // host reads the root boxes: the keys need only the device's instance table, and distinct
+    // points need at least 16 key bits once there are 2^16 of them (a pass over digits that
+    // are zero everywhere would change nothing either).
+    const int32_t nstats = K * (kMaxLevels + 3);
+    launch_keys(xy, d_ptoff, K, d_inst0, d_dmax, n, keys, vals, d_stats, nstats + 1, n > 1 ? rscr : nullptr, st);
+    const int early_passes = (n >= (int64_t(1) << 16)) ? 2 : 0;
+    int which = radix_sort_passes(keys, vals, keys_tmp, vals_tmp, n, 0, early_passes, true, rscr, st);
     // point storage, taken while the device works
     Arena& mp = pl->mem_pts;
     mp.set_pool(&ctx->pool);
@@ -689,7 +708,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     pl->pinst = mp.take<int32_t>(n);
     pl->pkey = mp.take<uint32_t>(n);
     pl->fs = mp.take<double>(n);
-    LFMM_HIP(hipStreamSynchronize(st));
+    LFMM_HIP(hipEventSynchronize(bb_ready.ev));
     pl->inst.assign(size_t(K), InstInfo{});
     int Dmax = 0;
     for (int32_t k = 0; k < K; ++k) {
@@ -722,11 +741,10 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
         stage_b.flush(st);
     }
 
-    // ---- Morton order ----------------------------------------------------------------------
-    const int32_t nstats = K * (kMaxLevels + 3);
+    // ---- Morton order: the rest of the sort ------------------------------------------------
     const int kbits = 2 * Dmax + ibits;
-    launch_keys(xy, d_ptoff, K, d_inst0, Dmax, n, keys, vals, d_stats, nstats + 1, kbits > 0 ? rscr : nullptr, st);
-    const int which = radix_sort_pairs(keys, vals, keys_tmp, vals_tmp, n, kbits, true, rscr, st);
+    which = radix_sort_passes(keys, vals, keys_tmp, vals_tmp, n, early_passes,
+                              std::max(early_passes, (kbits + 7) / 8), true, rscr, st);
     uint64_t* skeys = which ? keys_tmp : keys;
     uint32_t* svals = which ? vals_tmp : vals;
     launch_gather_sorted(skeys, svals, d_ptoff, Dmax, K, n, pl->pts, pl->perm, pl->pinst, st);
@@ -1034,10 +1052,11 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
 
 // Enqueues the evaluation passes (Section 8.2) on st.  tab = per-instance load/potential
 // pointers on the device, or null with f1/u1 those of the single instance.
-void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double* u1, bool marks, hipStream_t st) {
+void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double* u1, uint32_t marks, hipStream_t st) {
     const bool mixed = pl->ctx->opt.precision == LFMM_MIXED;
     auto mark = [&](int k) {
-        if (marks) LFMM_HIP(hipEventRecord(pl->ev[k], st));
+        // event k opens phase k and closes phase k - 1
+        if ((marks >> k & 1u) || (k > 0 && (marks >> (k - 1) & 1u))) LFMM_HIP(hipEventRecord(pl->ev[k], st));
     };
     mark(0);
     launch_gather_f(tab, f1, pl->perm, pl->pinst, pl->n, pl->fs, st);
@@ -1078,18 +1097,18 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
 void run_forest(lfmm_plan* pl, const double* const* f, double* const* u, hipStream_t st) {
     if (st != pl->build_stream) LFMM_HIP(hipStreamWaitEvent(st, pl->built->ev, 0));
     if (pl->K == 1 && !pl->use_graph) {
-        enqueue_passes(pl, nullptr, f[0], u[0], pl->timing, st);
-        if (pl->timing) pl->timed_once = true;
+        enqueue_passes(pl, nullptr, f[0], u[0], pl->timing_mask, st);
+        if (pl->timing_mask) pl->timed_mask = pl->timing_mask;
         return;
     }
     // the previous execute's copy must have read the staging buffer before it is rewritten
     LFMM_HIP(hipEventSynchronize(pl->exec_copied));
     for (int32_t k = 0; k < pl->K; ++k) pl->h_exec[k] = ExecPtrs{f[k], u[k]};
-    LFMM_HIP(hipMemcpyAsync(pl->d_exec, pl->h_exec, size_t(pl->K) * sizeof(ExecPtrs), hipMemcpyHostToDevice, st));
+    launch_upload(pl->d_exec, pl->h_exec, size_t(pl->K) * sizeof(ExecPtrs), st);
     LFMM_HIP(hipEventRecord(pl->exec_copied, st));
     if (!pl->use_graph) {
-        enqueue_passes(pl, pl->d_exec, nullptr, nullptr, pl->timing, st);
-        if (pl->timing) pl->timed_once = true;
+        enqueue_passes(pl, pl->d_exec, nullptr, nullptr, pl->timing_mask, st);
+        if (pl->timing_mask) pl->timed_mask = pl->timing_mask;
         return;
     }
     if (!pl->gexec) {
@@ -1442,24 +1461,35 @@ lfmm_status lfmm_plan_export(lfmm_plan* pl, int32_t item, void* out, size_t* byt
     });
 }
 
-lfmm_status lfmm_plan_set_timing(lfmm_plan* pl, int32_t enable) {
+lfmm_status lfmm_plan_set_timing_phases(lfmm_plan* pl, uint32_t phase_mask) {
     if (!pl) return fail(LFMM_E_INVAL, "null plan");
+    if (phase_mask >> LFMM_NUM_PHASES) return fail(LFMM_E_INVAL, "phase mask names no phase");
     return guarded([&]() -> lfmm_status {
         LFMM_HIP(hipSetDevice(pl->ctx->device));
-        if (enable && !pl->ev[0])
+        if (phase_mask && !pl->ev[0])
             for (auto& e : pl->ev) LFMM_HIP(hipEventCreate(&e));
-        pl->timing = enable != 0;
+        pl->timing_mask = phase_mask;
         return LFMM_OK;
     });
 }
 
+lfmm_status lfmm_plan_set_timing(lfmm_plan* pl, int32_t enable) {
+    return lfmm_plan_set_timing_phases(pl, enable ? (1u << LFMM_NUM_PHASES) - 1u : 0u);
+}
+
 lfmm_status lfmm_plan_phase_times(lfmm_plan* pl, double* ms) {
     if (!pl || !ms) return fail(LFMM_E_INVAL, "null argument");
-    if (!pl->timed_once) return fail(LFMM_E_INVAL, "no timed execute yet");
+    if (!pl->timed_mask) return fail(LFMM_E_INVAL, "no timed execute yet");
     return guarded([&]() -> lfmm_status {
         LFMM_HIP(hipSetDevice(pl->ctx->device));
-        LFMM_HIP(hipEventSynchronize(pl->ev[LFMM_NUM_PHASES]));
+        const uint32_t m = pl->timed_mask;
+        int last = 0;   // the last event recorded closes the last timed phase
+        for (int k = 0; k < LFMM_NUM_PHASES; ++k)
+            if (m >> k & 1u) last = k + 1;
+        LFMM_HIP(hipEventSynchronize(pl->ev[last]));
         for (int k = 0; k < LFMM_NUM_PHASES; ++k) {
+            ms[k] = std::numeric_limits<double>::quiet_NaN();
+            if (!(m >> k & 1u)) continue;
             float t = 0.f;
             LFMM_HIP(hipEventElapsedTime(&t, pl->ev[k], pl->ev[k + 1]));
             ms[k] = double(t);

@@ -100,7 +100,8 @@ __device__ inline bool block_minmax4(int v[4]) {
     return true;
 }
 
-__global__ void k_bbox_chunks(const int2* xy, const Chunk* chunks, int32_t* part) {
+__global__ void k_bbox_chunks(const int2* xy, const Chunk* chunks, int32_t* part, int32_t* dmax) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *dmax = 0;   // the deepest root box, raised by k_bbox_final
     const Chunk c = chunks[blockIdx.x];
     int v[4] = {INT_MAX, INT_MAX, INT_MIN, INT_MIN};
     for (int32_t i = c.begin + int32_t(threadIdx.x); i < c.end; i += kBlock) {
@@ -113,11 +114,11 @@ __global__ void k_bbox_chunks(const int2* xy, const Chunk* chunks, int32_t* part
 }
 
 // One block per instance: its chunks' partial boxes reduced by the block, written to bbox
-// (host memory) and, with max_leaf > 0, as the instance's root box, depth D (the smallest
-// with 2^D >= extent), point range and N_leaf into inst, for the kernels up to the level
-// statistics (the host writes inst itself when max_leaf is 0).
+// (host memory) and as the instance's root box, depth D (the smallest with 2^D >= extent),
+// point range and N_leaf (max_leaf, or 0 when the host sets it later) into inst, for the
+// kernels up to the level statistics; the deepest D goes to dmax.
 __global__ void k_bbox_final(const int32_t* part, const int32_t* chunk_first, const int32_t* pt_off,
-                             int32_t max_leaf, int32_t* bbox, InstInfo* inst) {
+                             int32_t max_leaf, int32_t* bbox, InstInfo* inst, int32_t* dmax) {
     const int32_t k = int32_t(blockIdx.x);
     int v[4] = {INT_MAX, INT_MAX, INT_MIN, INT_MIN};
     for (int32_t c = chunk_first[k] + int32_t(threadIdx.x); c < chunk_first[k + 1]; c += kBlock) {
@@ -126,7 +127,6 @@ __global__ void k_bbox_final(const int32_t* part, const int32_t* chunk_first, co
     }
     if (!block_minmax4(v)) return;
     for (int q = 0; q < 4; ++q) bbox[size_t(k) * 4 + q] = v[q];
-    if (max_leaf <= 0) return;
     const int64_t extent = max(int64_t(v[2]) - v[0], int64_t(v[3]) - v[1]) + 1;
     int D = 0;
     while (D < 32 && (int64_t(1) << D) < extent) ++D;
@@ -136,7 +136,8 @@ __global__ void k_bbox_final(const int32_t* part, const int32_t* chunk_first, co
     I.ox = v[0];
     I.oy = v[1];
     I.D = D;
-    I.max_leaf = max_leaf;
+    I.max_leaf = max(max_leaf, 0);
+    atomicMax(dmax, D);
 }
 
 // ---- radix sort pieces shared with the key kernel: 8-bit digits, tiles of kRsTile keys ----
@@ -165,10 +166,11 @@ __device__ inline void rs_count_tile(const uint32_t (&dg)[kRsItems], uint32_t* C
 // Morton key (instance above it) and index of every point, one tile of kRsTile points per
 // block, with the tile's counts of the lowest digit when C is given; also zeroes the nzero
 // counters that the level statistics accumulate into.
-__global__ void k_keys(const int2* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst, int Dmax, int64_t n,
-                       uint64_t* keys, uint32_t* vals, int32_t* zero, int32_t nzero, uint32_t* C, int64_t ntiles,
-                       bool digit_major) {
+__global__ void k_keys(const int2* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst, const int32_t* dmax,
+                       int64_t n, uint64_t* keys, uint32_t* vals, int32_t* zero, int32_t nzero, uint32_t* C,
+                       int64_t ntiles, bool digit_major) {
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int Dmax = (K > 1) ? *dmax : 0;   // instance bits sit above the deepest Morton code
     for (int64_t z = g; z < nzero; z += int64_t(gridDim.x) * blockDim.x) zero[z] = 0;
     // all loads of the tile first (few waves per SIMD: the latency is hidden by loads in flight)
     int2 pt[kRsItems];
@@ -891,29 +893,58 @@ size_t radix_scratch_bytes(int64_t n) {
 
 uint32_t* radix_counts(void* scratch) { return static_cast<uint32_t*>(scratch); }
 
-int radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp, int64_t n, int nbits,
-                     bool counted0, void* scratch, hipStream_t st) {
-    if (n <= 1 || nbits <= 0) return 0;
+int radix_sort_passes(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp, int64_t n, int p0,
+                      int p1, bool counted0, void* scratch, hipStream_t st) {
+    if (n <= 1 || p1 <= 0) return 0;
     const int64_t nt = radix_tiles(n);
     const bool dm = radix_digit_major(n);
     const size_t counts = size_t(256) * size_t(nt);
     uint32_t* C = radix_counts(scratch);
     int32_t* offs = reinterpret_cast<int32_t*>(C + counts);
     void* sscr = static_cast<char*>(scratch) + ((2 * counts * sizeof(int32_t) + 255) & ~size_t(255));
-    uint64_t *ka = keys, *kb = keys_tmp;
-    uint32_t *va = vals, *vb = vals_tmp;
-    const int passes = (nbits + 7) / 8;
-    for (int p = 0; p < passes; ++p) {
+    for (int p = p0; p < p1; ++p) {
+        uint64_t* ka = (p & 1) ? keys_tmp : keys;
+        uint64_t* kb = (p & 1) ? keys : keys_tmp;
+        uint32_t* va = (p & 1) ? vals_tmp : vals;
+        uint32_t* vb = (p & 1) ? vals : vals_tmp;
         const int shift = 8 * p;
         if (p > 0 || !counted0)
             hipLaunchKernelGGL(k_rs_count, dim3(unsigned(nt)), dim3(kBlock), 0, st, ka, n, shift, C, nt, dm);
         if (dm) scan_rows(reinterpret_cast<const int32_t*>(C), offs, int64_t(counts), 1, nullptr, sscr, st);
         hipLaunchKernelGGL(k_rs_scatter, dim3(unsigned(nt)), dim3(kRsScatterThreads), 0, st, ka, va, kb, vb, n,
                            shift, C, dm ? offs : nullptr, nt);
-        std::swap(ka, kb);
-        std::swap(va, vb);
     }
-    return (ka == keys) ? 0 : 1;
+    return p1 & 1;
+}
+
+int radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp, int64_t n, int nbits,
+                     bool counted0, void* scratch, hipStream_t st) {
+    if (nbits <= 0) return 0;
+    return radix_sort_passes(keys, vals, keys_tmp, vals_tmp, n, 0, (nbits + 7) / 8, counted0, scratch, st);
+}
+
+// Small host-to-device copy run as a kernel: the source is pinned host memory, read with
+// system-scope loads (coherent with the host's writes), so the copy is ordered on the stream
+// like the kernels around it.  dst and src are 8-byte aligned; the last word is written byte
+// by byte when len is not a multiple of 8 (src may be read up to the next multiple of 8).
+__global__ void k_upload(const uint64_t* src, uint64_t* dst, int64_t len) {
+    const int64_t nw = len >> 3;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nw; i += int64_t(gridDim.x) * blockDim.x)
+        dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const int rem = int(len & 7);
+    if (rem != 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint64_t w = __hip_atomic_load(src + nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        unsigned char* d = reinterpret_cast<unsigned char*>(dst + nw);
+        for (int b = 0; b < rem; ++b) d[b] = static_cast<unsigned char>(w >> (8 * b));
+    }
+}
+
+void launch_upload(void* dst, const void* pinned_src, size_t len, hipStream_t st) {
+    if (len == 0) return;
+    const int64_t nw = int64_t(len >> 3) + 1;
+    const unsigned g = unsigned(std::min<int64_t>((nw + kBlock - 1) / kBlock, 64));
+    hipLaunchKernelGGL(k_upload, dim3(g), dim3(kBlock), 0, st, static_cast<const uint64_t*>(pinned_src),
+                       static_cast<uint64_t*>(dst), int64_t(len));
 }
 
 void launch_concat(int32_t K, const int32_t* const* xy_tab, const int32_t* pt_off, int64_t n, int32_t* xyc,
@@ -922,23 +953,24 @@ void launch_concat(int32_t K, const int32_t* const* xy_tab, const int32_t* pt_of
                        reinterpret_cast<const int2* const*>(xy_tab), pt_off, n, reinterpret_cast<int2*>(xyc));
 }
 
-void launch_bbox_chunks(const int32_t* xy, const Chunk* chunks, int32_t nchunks, int32_t* part, hipStream_t st) {
+void launch_bbox_chunks(const int32_t* xy, const Chunk* chunks, int32_t nchunks, int32_t* part, int32_t* dmax,
+                        hipStream_t st) {
     hipLaunchKernelGGL(k_bbox_chunks, dim3(unsigned(nchunks)), dim3(kBlock), 0, st, reinterpret_cast<const int2*>(xy),
-                       chunks, part);
+                       chunks, part, dmax);
 }
 
 void launch_bbox_final(const int32_t* part, const int32_t* chunk_first, const int32_t* pt_off, int32_t K,
-                       int32_t max_leaf, int32_t* bbox, InstInfo* inst, hipStream_t st) {
+                       int32_t max_leaf, int32_t* bbox, InstInfo* inst, int32_t* dmax, hipStream_t st) {
     hipLaunchKernelGGL(k_bbox_final, dim3(static_cast<unsigned>(K)), dim3(kBlock), 0, st, part, chunk_first, pt_off,
-                       max_leaf, bbox, inst);
+                       max_leaf, bbox, inst, dmax);
 }
 
-void launch_keys(const int32_t* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst, int Dmax, int64_t n,
-                 uint64_t* keys, uint32_t* vals, int32_t* zero, int32_t nzero, void* radix_scratch,
+void launch_keys(const int32_t* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst, const int32_t* dmax,
+                 int64_t n, uint64_t* keys, uint32_t* vals, int32_t* zero, int32_t nzero, void* radix_scratch,
                  hipStream_t st) {
     const int64_t nt = radix_tiles(n);
     hipLaunchKernelGGL(k_keys, dim3(unsigned(nt)), dim3(kBlock), 0, st, reinterpret_cast<const int2*>(xy), pt_off, K,
-                       inst, Dmax, n, keys, vals, zero, nzero,
+                       inst, dmax, n, keys, vals, zero, nzero,
                        radix_scratch ? radix_counts(radix_scratch) : static_cast<uint32_t*>(nullptr), nt,
                        radix_digit_major(n));
 }

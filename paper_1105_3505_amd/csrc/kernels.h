@@ -112,6 +112,16 @@ size_t radix_scratch_bytes(int64_t n);
 // counts of the lowest digit are in the scratch already (launch_keys given the scratch).
 int radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp,
                      int64_t n, int nbits, bool counted0, void* scratch, hipStream_t st);
+// Passes p0 .. p1 - 1 of that sort (pass p: bits [8 p, 8 p + 8), reading the pair pass p - 1
+// wrote; pass 0 reads (keys, vals)), so that a sort can start before its bit count is known:
+// passes over digits that are zero in every key leave the order unchanged.  Returns the pair
+// that holds the data after pass p1 - 1.
+int radix_sort_passes(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp,
+                      int64_t n, int p0, int p1, bool counted0, void* scratch, hipStream_t st);
+// Copies len bytes from pinned host memory to device memory with a kernel (ordered on the
+// stream like a kernel; no copy engine).  Both 8-byte aligned; the source block must extend to
+// the next multiple of 8 bytes.
+void launch_upload(void* dst, const void* pinned_src, size_t len, hipStream_t st);
 // exclusive scan of `rows` rows of n int32 each (row stride n); totals[rows] if non-null.
 // Two launches; scratch holds one sum per 2048 items and row.
 size_t scan_scratch_bytes(int64_t n, int rows);
@@ -123,17 +133,19 @@ constexpr int32_t kChunk = 2048;
 
 void launch_concat(int32_t K, const int32_t* const* xy_tab, const int32_t* pt_off, int64_t n,
                    int32_t* xyc, hipStream_t st);
+// partial root boxes per chunk; also zeroes *dmax
 void launch_bbox_chunks(const int32_t* xy, const Chunk* chunks, int32_t nchunks, int32_t* part,
-                        hipStream_t st);
-// one block per instance; with max_leaf > 0 also writes the instances' root boxes, depths,
-// point ranges and N_leaf into inst
+                        int32_t* dmax, hipStream_t st);
+// one block per instance: root boxes to bbox, and the instances' root boxes, depths, point
+// ranges and N_leaf (max_leaf, 0 if not positive) into inst; the deepest depth into *dmax
 void launch_bbox_final(const int32_t* part, const int32_t* chunk_first, const int32_t* pt_off, int32_t K,
-                       int32_t max_leaf, int32_t* bbox, InstInfo* inst, hipStream_t st);
-// keys and indices of the points; zeroes zero[0, nzero); with radix_scratch (of
-// radix_scratch_bytes(n)) also the sort's tile counts of the lowest digit
+                       int32_t max_leaf, int32_t* bbox, InstInfo* inst, int32_t* dmax, hipStream_t st);
+// keys and indices of the points (root boxes from inst, the deepest depth from *dmax);
+// zeroes zero[0, nzero); with radix_scratch (of radix_scratch_bytes(n)) also the sort's tile
+// counts of the lowest digit
 void launch_keys(const int32_t* xy, const int32_t* pt_off, int32_t K, const InstInfo* inst,
-                 int Dmax, int64_t n, uint64_t* keys, uint32_t* vals, int32_t* zero, int32_t nzero,
-                 void* radix_scratch, hipStream_t st);
+                 const int32_t* dmax, int64_t n, uint64_t* keys, uint32_t* vals, int32_t* zero,
+                 int32_t nzero, void* radix_scratch, hipStream_t st);
 // sorted points (coordinates in the root box, decoded from the keys), instance-local indices
 // and instances
 void launch_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int32_t* pt_off, int Dmax, int K,

@@ -223,6 +223,10 @@ lfmm_status lfmm_plan_export(lfmm_plan* plan, int32_t item, void* host_out, size
  * used for admission by memory footprint. */
 lfmm_status lfmm_plan_footprint_bytes(const lfmm_ctx* ctx, int64_t n, size_t* out);
 
+/* Frees a plan.  When every execute of the plan ran on the stream it was built on (and it
+ * does not replay a HIP graph), this returns without waiting: the plan's device memory goes
+ * back to the context's pool once that stream has passed this call, and results written by
+ * earlier executes are ordered on that stream as usual.  Otherwise it waits for the device. */
 lfmm_status lfmm_plan_destroy(lfmm_plan* plan);
 
 /* One-shot: plan, execute, destroy.  Synchronises the stream before returning. */

@@ -344,6 +344,7 @@ struct lfmm_plan {
     hipEvent_t ev[LFMM_NUM_PHASES + 1] = {};
     FencePtr built;                         // end of the build, on build_stream
     hipStream_t build_stream = nullptr;
+    bool one_stream = true;                 // every execute so far ran on build_stream
     ~lfmm_plan() {
         {
             std::lock_guard<std::mutex> lock(ctx->reg_mu);
@@ -1095,7 +1096,10 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
 }
 
 void run_forest(lfmm_plan* pl, const double* const* f, double* const* u, hipStream_t st) {
-    if (st != pl->build_stream) LFMM_HIP(hipStreamWaitEvent(st, pl->built->ev, 0));
+    if (st != pl->build_stream) {
+        pl->one_stream = false;
+        LFMM_HIP(hipStreamWaitEvent(st, pl->built->ev, 0));
+    }
     if (pl->K == 1 && !pl->use_graph) {
         enqueue_passes(pl, nullptr, f[0], u[0], pl->timing_mask, st);
         if (pl->timing_mask) pl->timed_mask = pl->timing_mask;
@@ -1513,6 +1517,24 @@ lfmm_status lfmm_plan_footprint_bytes(const lfmm_ctx* ctx, int64_t n, size_t* ou
 lfmm_status lfmm_plan_destroy(lfmm_plan* pl) {
     if (!pl) return LFMM_OK;
     (void)hipSetDevice(pl->ctx->device);
+    if (pl->one_stream && !pl->use_graph) {
+        // all of the plan's work was issued on its build stream: its blocks go back to the
+        // context's pools once that stream passes this point, without waiting here
+        try {
+            const FencePtr done = std::make_shared<Fence>(pl->build_stream);
+            pl->mem_small.release_after(done);
+            pl->mem_pts.release_after(done);
+            pl->mem_box.release_after(done);
+            if (pl->h_exec) {
+                pl->ctx->pinned.release_after(pl->h_exec, pl->h_exec_cls, done);
+                pl->h_exec = nullptr;
+            }
+            delete pl;
+            return LFMM_OK;
+        } catch (...) {
+            (void)hipGetLastError();   // no fence: wait for the device as below
+        }
+    }
     // kernels of this plan may still run on any stream: finish them before the blocks go
     // back to the context's pool for reuse
     (void)hipDeviceSynchronize();

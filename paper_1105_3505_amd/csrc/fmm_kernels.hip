@@ -640,9 +640,11 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, cons
 //     phi(x_i - x_j) is K_i - K_j plus a constant: one subtraction per pair.
 //   QUAD (side 32): a table over |dx|, |dy| < 64.
 //   GLOBAL (side >= 64): the octant table of radius 128 in global memory, eq. (3.1) beyond.
-constexpr int kNearBlock = 256;
-constexpr int kNearWaves = kNearBlock / 64;
 enum LeafMode { kWindow = 0, kQuad = 1, kGlobal = 2 };
+// Block size per mode.  With an LDS phi table, 512-thread blocks share one table among eight
+// waves and run persistently (each builds its table once); with the global table, 256-thread
+// blocks take one group per wave and the hardware balances uneven groups.
+constexpr int near_threads(int mode) { return mode == kGlobal ? 256 : 512; }
 
 // read-only data that every lane of a wave reads at the same address: constant address
 // space, so that uniform reads become scalar loads
@@ -732,6 +734,17 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
                 const bool near = abs(en.z - tx) <= 1 && abs(en.w - ty) <= 1;   // uniform when sliced
                 if (near) {
                     int32_t j = en.x + sl;
+                    if (!SLICED)   // eight sources per step: one wait for their scalar loads
+                        for (; j + 7 < en.y; j += 8) {
+                            a0 += phi_at(src_key(j), src_pt(j)) * src_f(j);
+                            a1 += phi_at(src_key(j + 1), src_pt(j + 1)) * src_f(j + 1);
+                            a2 += phi_at(src_key(j + 2), src_pt(j + 2)) * src_f(j + 2);
+                            a3 += phi_at(src_key(j + 3), src_pt(j + 3)) * src_f(j + 3);
+                            a0 += phi_at(src_key(j + 4), src_pt(j + 4)) * src_f(j + 4);
+                            a1 += phi_at(src_key(j + 5), src_pt(j + 5)) * src_f(j + 5);
+                            a2 += phi_at(src_key(j + 6), src_pt(j + 6)) * src_f(j + 6);
+                            a3 += phi_at(src_key(j + 7), src_pt(j + 7)) * src_f(j + 7);
+                        }
                     for (; j + 3 * S < en.y; j += 4 * S) {
                         a0 += phi_at(src_key(j), src_pt(j)) * src_f(j);
                         a1 += phi_at(src_key(j + S), src_pt(j + S)) * src_f(j + S);
@@ -769,7 +782,7 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
 }
 
 template <int P, int MODE>
-__global__ __launch_bounds__(kNearBlock) void k_near(int32_t q0, int32_t q1, const NearGroup* groups,
+__global__ __launch_bounds__(near_threads(MODE)) void k_near(int32_t q0, int32_t q1, const NearGroup* groups,
                                                       const int4* ents, const int32_t* box_pt0,
                                                       const int32_t* box_pt1, const uint64_t* box_key,
                                                       const int32_t* box_inst, int64_t side, int W, const int2* pts,
@@ -777,6 +790,7 @@ __global__ __launch_bounds__(kNearBlock) void k_near(int32_t q0, int32_t q1, con
                                                       const int32_t* perm_local, const ExecPtrs* tab_ptrs,
                                                       double* u_single, const double* U, const double* leafT,
                                                       const uint8_t* far_inst, const double* phi_oct_tab) {
+    constexpr int kNearBlock = near_threads(MODE), kNearWaves = kNearBlock / 64;
     extern __shared__ double tab[];
     const int tid = threadIdx.x, wave = tid >> 6;
     if (MODE != kGlobal) {
@@ -976,23 +990,40 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
                  const ExecPtrs* tab, double* u_single, const double* U, const double* leafT,
                  const uint8_t* far_inst, const double* phi_oct, hipStream_t st) {
     if (q1 <= q0) return;
-    unsigned g = grid_for(q1 - q0, kNearWaves);
-    if (g > 8192) g = 8192;
+    // with an LDS table: persistent blocks, as many as fit on the device at once, so that
+    // each builds its table once and then walks many groups; else one group per wave
+    auto grid = [&](const void* fn, int threads, size_t lds, bool persistent) {
+        unsigned g = std::min<unsigned>(grid_for(q1 - q0, threads / 64), 8192u);
+        const int cus = p2m_device().cus;
+        int per = 0;
+        if (!persistent) return g;
+        if (cus > 0 && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, lds) == hipSuccess && per > 0)
+            g = std::min<unsigned>(g, unsigned(cus) * unsigned(per));
+        else
+            (void)hipGetLastError();
+        return std::max(g, 1u);
+    };
     const int2* p2 = reinterpret_cast<const int2*>(pts);
     if (side <= 16) {
         const int W = int(4 * side - 1);
         const size_t lds = size_t(W * W) * sizeof(double);
-        hipLaunchKernelGGL((k_near<kRankPad, kWindow>), dim3(g), dim3(kNearBlock), lds, st, q0, q1, groups, ents,
+        constexpr int nt = near_threads(kWindow);
+        const unsigned g = grid(reinterpret_cast<const void*>(&k_near<kRankPad, kWindow>), nt, lds, true);
+        hipLaunchKernelGGL((k_near<kRankPad, kWindow>), dim3(g), dim3(nt), lds, st, q0, q1, groups, ents,
                            box_pt0, box_pt1, box_key, box_inst, side, W, p2, pkey, fs, perm_local, tab, u_single, U,
                            leafT, far_inst, phi_oct);
     } else if (side <= 32) {
         const int W = int(2 * side);
         const size_t lds = size_t(W * W) * sizeof(double);
-        hipLaunchKernelGGL((k_near<kRankPad, kQuad>), dim3(g), dim3(kNearBlock), lds, st, q0, q1, groups, ents,
+        constexpr int nt = near_threads(kQuad);
+        const unsigned g = grid(reinterpret_cast<const void*>(&k_near<kRankPad, kQuad>), nt, lds, true);
+        hipLaunchKernelGGL((k_near<kRankPad, kQuad>), dim3(g), dim3(nt), lds, st, q0, q1, groups, ents,
                            box_pt0, box_pt1, box_key, box_inst, side, W, p2, pkey, fs, perm_local, tab, u_single, U,
                            leafT, far_inst, phi_oct);
     } else {
-        hipLaunchKernelGGL((k_near<kRankPad, kGlobal>), dim3(g), dim3(kNearBlock), 0, st, q0, q1, groups, ents,
+        constexpr int nt = near_threads(kGlobal);
+        const unsigned g = grid(reinterpret_cast<const void*>(&k_near<kRankPad, kGlobal>), nt, 0, false);
+        hipLaunchKernelGGL((k_near<kRankPad, kGlobal>), dim3(g), dim3(nt), 0, st, q0, q1, groups, ents,
                            box_pt0, box_pt1, box_key, box_inst, side, 0, p2, pkey, fs, perm_local, tab, u_single, U,
                            leafT, far_inst, phi_oct);
     }

@@ -734,7 +734,17 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
                 const bool near = abs(en.z - tx) <= 1 && abs(en.w - ty) <= 1;   // uniform when sliced
                 if (near) {
                     int32_t j = en.x + sl;
-                    if (!SLICED)   // eight sources per step: one wait for their scalar loads
+                    if (!SLICED)   // sixteen sources per step: few waits for their scalar loads
+                        for (; j + 15 < en.y; j += 16) {
+                            #pragma unroll
+                            for (int r = 0; r < 16; r += 4) {
+                                a0 += phi_at(src_key(j + r), src_pt(j + r)) * src_f(j + r);
+                                a1 += phi_at(src_key(j + r + 1), src_pt(j + r + 1)) * src_f(j + r + 1);
+                                a2 += phi_at(src_key(j + r + 2), src_pt(j + r + 2)) * src_f(j + r + 2);
+                                a3 += phi_at(src_key(j + r + 3), src_pt(j + r + 3)) * src_f(j + r + 3);
+                            }
+                        }
+                    if (!SLICED)
                         for (; j + 7 < en.y; j += 8) {
                             a0 += phi_at(src_key(j), src_pt(j)) * src_f(j);
                             a1 += phi_at(src_key(j + 1), src_pt(j + 1)) * src_f(j + 1);

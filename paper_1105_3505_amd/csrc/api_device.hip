@@ -617,7 +617,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     tmp.reserve(size_t(K + 1) * 4);             // chunk_first
     tmp.reserve(size_t(nch) * 16);              // bbox partials
     tmp.reserve(size_t(K) * sizeof(InstInfo));  // instances up to the level statistics
-    tmp.reserve(size_t(K) * (kMaxLevels + 3) * 4 + 4);   // level histograms, lookahead maxima, counter
+    tmp.reserve(size_t(K) * (kMaxLevels + 3) * 4 + 4);   // level histograms, look-ahead maxima, counter
     tmp.reserve(4);                             // deepest root box
     tmp.reserve(K > 1 ? size_t(n) * 8 : 0);     // concatenated points
     tmp.reserve(size_t(n) * 8);                 // keys
@@ -635,9 +635,8 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     int32_t* d_chfirst = tmp.take<int32_t>(K + 1);
     int32_t* d_part = tmp.take<int32_t>(size_t(nch) * 4);
     InstInfo* d_inst0 = tmp.take<InstInfo>(K);
-    int32_t* d_stats = tmp.take<int32_t>(size_t(K) * (kMaxLevels + 3) + 1);
-    int32_t* d_hist = d_stats;
-    int32_t* d_maxc = d_stats + size_t(K) * (kMaxLevels + 2);
+    const int32_t nstats = K * (kMaxLevels + 3);
+    int32_t* d_stats = tmp.take<int32_t>(size_t(nstats) + 1);   // zeroed by the key kernel
     int32_t* d_dmax = tmp.take<int32_t>(1);
     // host-visible results of the two read-backs (pinned: the root boxes are written there by
     // the kernel itself, the level statistics by one copy)
@@ -691,7 +690,6 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     // host reads the root boxes: the keys need only the device's instance table, and distinct
     // points need at least 16 key bits once there are 2^16 of them (a pass over digits that
     // are zero everywhere would change nothing either).
-    const int32_t nstats = K * (kMaxLevels + 3);
     launch_keys(xy, d_ptoff, K, d_inst0, d_dmax, n, keys, vals, d_stats, nstats + 1, n > 1 ? rscr : nullptr, st);
     const int early_passes = (n >= (int64_t(1) << 16)) ? 2 : 0;
     int which = radix_sort_passes(keys, vals, keys_tmp, vals_tmp, n, 0, early_passes, true, rscr, st);
@@ -748,10 +746,10 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
                               std::max(early_passes, (kbits + 7) / 8), true, rscr, st);
     uint64_t* skeys = which ? keys_tmp : keys;
     uint32_t* svals = which ? vals_tmp : vals;
-    launch_gather_sorted(skeys, svals, d_ptoff, Dmax, K, n, pl->pts, pl->perm, pl->pinst, st);
 
     // ---- leaf levels and box counts ---------------------------------------------------------
-    launch_level_stats(skeys, d_chunks, nch, d_inst0, Dmax, cl, d_hist, d_maxc, d_stats + nstats, nstats, stats, st);
+    launch_level_stats(skeys, svals, d_chunks, nch, d_inst0, Dmax, K, pl->pts, pl->perm, pl->pinst, cl, d_stats,
+                       d_stats + nstats, stats, st);
     LFMM_HIP(hipStreamSynchronize(st));
     const int32_t* hist = stats;
     const int32_t* maxc = stats + size_t(K) * (kMaxLevels + 2);

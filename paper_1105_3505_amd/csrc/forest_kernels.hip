@@ -197,47 +197,43 @@ __global__ void k_keys(const int2* xy, const int32_t* pt_off, int32_t K, const I
     if (C) rs_count_tile(dg, C, ntiles, digit_major);
 }
 
-// Sorted points: coordinates in the instance's root box decoded from the Morton key (no
-// gather of the input), instance-local index and instance.
-__global__ void k_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int32_t* pt_off, int Dmax, int K,
-                                int64_t n, int2* pts, int32_t* perm_local, int32_t* pinst) {
-    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const uint32_t p = vals[s];
-    const uint64_t key = keys[s];
-    const int32_t k = (K > 1) ? int32_t(key >> (2 * Dmax)) : 0;
-    const uint64_t m = key & morton_mask(Dmax);
-    pts[s] = make_int2(int32_t(compact_bits(m)), int32_t(compact_bits(m >> 1)));
-    perm_local[s] = int32_t(p) - pt_off[k];
-    pinst[s] = k;
-}
-
-// One block per chunk of one instance: per point the number of levels its box shares with
-// the previous point's (-1 at the instance's first point), a histogram of those counts
-// (equal values of a wave are counted with ballots, one LDS add per distinct value), and the
-// levels shared with the point N_leaf positions ahead (a box of that level would hold more
-// than N_leaf points), reduced to one atomic per block.
-__global__ void k_level_stats(const uint64_t* keys, const Chunk* chunks, const InstInfo* inst, int Dmax,
-                              int8_t* cl, int32_t* hist, int32_t* maxc, int32_t* done, int32_t nstats,
-                              int32_t* host_out) {
-    __shared__ int32_t h[kMaxLevels + 2];
+// One block per chunk of one instance.  Per sorted point: its coordinates in the instance's
+// root box decoded from the Morton key (no gather of the input), its instance-local index
+// and instance; the number of levels its box shares with the previous point's (-1 at the
+// instance's first point), a histogram of those counts (equal values of a wave are counted
+// with ballots, one LDS add per distinct value), and the levels shared with the point N_leaf
+// positions ahead (a box of that level would hold more than N_leaf points).  The block adds
+// its non-zero counts and its maximum to the instance's totals with device-scope atomics
+// (hist: [K][kMaxLevels + 2], then maxc: [K]; zero before the launch), and the last block
+// to finish (counter *done, zero before the launch) copies the totals to host memory.  Each
+// thread waits for its own atomics (vector memory count zero) before the barrier that
+// precedes the counter, and the totals are read back with atomics, so no device-wide fence
+// is needed.
+__global__ void k_level_stats(const uint64_t* keys, const uint32_t* vals, const Chunk* chunks,
+                              const InstInfo* inst, int Dmax, int32_t K, int2* pts, int32_t* perm_local,
+                              int32_t* pinst, int8_t* cl, int32_t* hist, int32_t* done, int32_t* host_out) {
+    constexpr int NH = kMaxLevels + 2;
+    __shared__ int32_t h[NH];
     __shared__ int32_t wmax[kBlock / 64];
+    __shared__ int is_last;
     const Chunk c = chunks[blockIdx.x];
     const InstInfo& I = inst[c.inst];
     const int shift = Dmax - I.D;
     const int nleaf = I.max_leaf;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (threadIdx.x < kMaxLevels + 2) h[threadIdx.x] = 0;
+    if (threadIdx.x < NH) h[threadIdx.x] = 0;
     __syncthreads();
     int mc = -1;
     // every key the chunk needs is loaded first (its own, the previous and the one N_leaf on)
     constexpr int kIt = kChunk / kBlock;
     uint64_t kk[kIt], kp[kIt], ka[kIt];
+    uint32_t ix[kIt];
     #pragma unroll
     for (int it = 0; it < kIt; ++it) {
         const int32_t s = c.begin + it * kBlock + int32_t(threadIdx.x);
         const bool valid = s < c.end;
         kk[it] = valid ? keys[s] : 0ull;
+        ix[it] = valid ? vals[s] : 0u;
         kp[it] = (valid && s != I.pt0) ? keys[s - 1] : 0ull;
         ka[it] = (valid && s + nleaf < I.pt1) ? keys[s + nleaf] : 0ull;
     }
@@ -247,6 +243,10 @@ __global__ void k_level_stats(const uint64_t* keys, const Chunk* chunks, const I
         const bool valid = s < c.end;
         int v = -1;
         if (valid) {
+            const uint64_t m = kk[it] & morton_mask(Dmax);
+            pts[s] = make_int2(int32_t(compact_bits(m)), int32_t(compact_bits(m >> 1)));
+            perm_local[s] = int32_t(ix[it]) - I.pt0;
+            pinst[s] = c.inst;
             v = (s == I.pt0) ? -1 : common_levels(kk[it], kp[it], Dmax) - shift;
             cl[s] = int8_t(v);
             if (s + nleaf < I.pt1) mc = max(mc, common_levels(kk[it], ka[it], Dmax) - shift);
@@ -264,24 +264,19 @@ __global__ void k_level_stats(const uint64_t* keys, const Chunk* chunks, const I
     for (int o = 32; o > 0; o >>= 1) mc = max(mc, __shfl_xor(mc, o, 64));
     if (lane == 0) wmax[wave] = mc;
     __syncthreads();
+    int32_t* maxc = hist + size_t(K) * NH;
     if (threadIdx.x == 0) {
         int bm = wmax[0];
         for (int w = 1; w < kBlock / 64; ++w) bm = max(bm, wmax[w]);
         if (bm >= 0) atomicMax(&maxc[c.inst], bm);
     }
-    if (threadIdx.x < kMaxLevels + 2 && h[threadIdx.x] != 0)
-        atomicAdd(&hist[size_t(c.inst) * (kMaxLevels + 2) + threadIdx.x], h[threadIdx.x]);
-    // The last block to finish copies the totals (hist and maxc, nstats values from hist on)
-    // to host memory.  Each thread waits until its atomics above have been performed (vector
-    // memory count zero) before the barrier, after which the counter is incremented; no
-    // device-wide fence is needed.
-    __shared__ int is_last;
+    if (threadIdx.x < NH && h[threadIdx.x] != 0) atomicAdd(&hist[size_t(c.inst) * NH + threadIdx.x], h[threadIdx.x]);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) is_last = atomicAdd(done, 1) == int(gridDim.x) - 1;
     __syncthreads();
     if (is_last)
-        for (int i = threadIdx.x; i < nstats; i += blockDim.x) host_out[i] = atomicAdd(&hist[i], 0);
+        for (int i = threadIdx.x; i < K * (NH + 1); i += blockDim.x) host_out[i] = atomicAdd(&hist[i], 0);
 }
 
 // One thread per (leaf, level): the leaf that starts a box of that level writes the box and
@@ -335,17 +330,6 @@ __global__ void k_link_boxes(const uint64_t* box_key, const int32_t* box_parent,
     box_pt1[g] = (local + 1 < I.lev_count[lev]) ? box_pt0[g + 1] : I.pt1;
 }
 
-// box at lattice-level cell (x, y) of the level of a box whose parent's 3 x 3 neighbourhood
-// (centre = parent at (px, py)) is pn; -1 when absent
-__device__ inline int32_t child_at(int32_t x, int32_t y, int32_t px, int32_t py, const int32_t* pn,
-                                   const int32_t* box_child) {
-    if (x < 0 || y < 0) return -1;
-    const int32_t ox = (x >> 1) - px, oy = (y >> 1) - py;
-    const int32_t q = pn[(oy + 1) * 3 + (ox + 1)];
-    if (q < 0) return -1;
-    return box_child[size_t(q) * 4 + (x & 1) + 2 * (y & 1)];
-}
-
 // index of the box with Morton key `key` among the boxes [lo, hi) of one level of one
 // instance (sorted by key), or -1
 __device__ inline int32_t find_box(const uint64_t* box_key, int32_t lo, int32_t hi, uint64_t key) {
@@ -360,58 +344,72 @@ __device__ inline int32_t find_box(const uint64_t* box_key, int32_t lo, int32_t 
 
 __device__ inline uint64_t morton2(uint32_t x, uint32_t y) { return spread_bits(x) | (spread_bits(y) << 1); }
 
-// 3 x 3 neighbourhood of every box (slot (dy + 1) * 3 + dx + 1), by search among the boxes of
-// its level: no dependence between levels, so one launch covers all of them
+// 3 x 3 neighbourhood of every box (slot (dy + 1) * 3 + dx + 1), one thread per (box, slot):
+// the box of that cell found by search among the boxes of its level, or directly when the
+// level holds every cell (its boxes are then the cells in Morton order).  No dependence
+// between levels, so one launch covers all of them.
 __global__ void k_neighbours(const uint64_t* box_key, const int32_t* box_inst, const int8_t* box_lev,
                              const InstInfo* inst, int64_t nbox, int32_t* nb9) {
-    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= nbox) return;
-    const int lev = box_lev[g];
-    const InstInfo& I = inst[box_inst[g]];
-    const int32_t lo = I.lev_base[lev], hi = lo + I.lev_count[lev];
-    const uint64_t key = box_key[g];
-    const int32_t bx = int32_t(compact_bits(key)), by = int32_t(compact_bits(key >> 1));
-    const int32_t side = int32_t(1) << lev;
-    int32_t* nl = nb9 + size_t(g) * 9;
-    #pragma unroll
-    for (int dy = -1; dy <= 1; ++dy)
-        #pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-            const int32_t x = bx + dx, y = by + dy;
-            int32_t r = -1;
-            if (dx == 0 && dy == 0) r = int32_t(g);
-            else if (x >= 0 && y >= 0 && x < side && y < side)
-                r = find_box(box_key, lo, hi, morton2(uint32_t(x), uint32_t(y)));
-            nl[(dy + 1) * 3 + dx + 1] = r;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nbox * 9) return;
+    const int64_t g = t / 9;
+    const int q = int(t - g * 9);
+    int32_t r = int32_t(g);
+    if (q != 4) {
+        const int lev = box_lev[g];
+        const InstInfo& I = inst[box_inst[g]];
+        const int32_t lo = I.lev_base[lev], cnt = I.lev_count[lev];
+        const uint64_t key = box_key[g];
+        const int64_t x = int64_t(compact_bits(key)) + q % 3 - 1, y = int64_t(compact_bits(key >> 1)) + q / 3 - 1;
+        const int64_t side = int64_t(1) << lev;
+        r = -1;
+        if (x >= 0 && y >= 0 && x < side && y < side) {
+            const uint64_t m = morton2(uint32_t(x), uint32_t(y));
+            r = (int64_t(cnt) == side * side) ? lo + int32_t(m) : find_box(box_key, lo, lo + cnt, m);
         }
+    }
+    nb9[t] = r;
 }
 
-// interaction list of every box of level >= 2 (Definition 6.1): the children of its parent's
-// neighbours that are not its own neighbours, in the slot order of its child position
+// interaction list of every box of level >= 2 (Definition 6.1), one thread per (box, slot):
+// the children of its parent's neighbours that are not its own neighbours, slot k being the
+// k-th such cell in row-major order of the 6 x 6 block they cover (which depends on the box's
+// position in its parent)
 __global__ void k_interactions(const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_child,
                                const int8_t* box_lev, int64_t nbox, const int32_t* nb9, int32_t* il27) {
-    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= nbox) return;
-    const int lev = box_lev[g];
-    int32_t* il = il27 + size_t(g) * kNumInteractions;
-    if (lev < 2) {
-        for (int k = 0; k < kNumInteractions; ++k) il[k] = -1;
-        return;
-    }
-    const uint64_t key = box_key[g];
-    const int32_t bx = int32_t(compact_bits(key)), by = int32_t(compact_bits(key >> 1));
-    const int32_t px = bx >> 1, py = by >> 1;
-    int32_t pn[9];
-    const int32_t* pp = nb9 + size_t(box_parent[g]) * 9;
-    #pragma unroll
-    for (int q = 0; q < 9; ++q) pn[q] = pp[q];
-    const int cx = bx & 1, cy = by & 1;
-    int k = 0;
-    for (int dy = -2 - cy; dy <= 3 - cy; ++dy)
-        for (int dx = -2 - cx; dx <= 3 - cx; ++dx) {
-            if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
-            il[k++] = child_at(bx + dx, by + dy, px, py, pn, box_child);
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nbox * kNumInteractions) return;
+    const int64_t g = t / kNumInteractions;
+    const int k = int(t - g * kNumInteractions);
+    int32_t r = -1;
+    if (box_lev[g] >= 2) {
+        const uint64_t key = box_key[g];
+        const int32_t bx = int32_t(compact_bits(key)), by = int32_t(compact_bits(key >> 1));
+        const int cx = bx & 1, cy = by & 1;
+        // the 6 x 6 block starts 2 + c cells before the box; its own neighbourhood fills rows and
+        // columns 1 + c .. 3 + c of it: 6 cells in each row above, 3 in each row beside, 6 below
+        const int r0 = 1 + cy, c0 = 1 + cx;
+        int row, col;
+        if (k < 6 * r0) {
+            row = k / 6;
+            col = k % 6;
+        } else if (k < 6 * r0 + 9) {
+            const int j = k - 6 * r0, i = j % 3;
+            row = r0 + j / 3;
+            col = i < c0 ? i : i + 3;
+        } else {
+            const int j = k - 6 * r0 - 9;
+            row = r0 + 3 + j / 6;
+            col = j % 6;
         }
+        const int32_t x = bx + col - 2 - cx, y = by + row - 2 - cy;
+        if (x >= 0 && y >= 0) {
+            const int32_t ox = (x >> 1) - (bx >> 1), oy = (y >> 1) - (by >> 1);
+            const int32_t q = nb9[size_t(box_parent[g]) * 9 + size_t((oy + 1) * 3 + ox + 1)];
+            if (q >= 0) r = box_child[size_t(q) * 4 + size_t((x & 1) + 2 * (y & 1))];
+        }
+    }
+    il27[t] = r;
 }
 
 __device__ inline int32_t scan_at(const int32_t* cscan, const int32_t* ctotal, int64_t nbox, int c, int64_t g) {
@@ -975,17 +973,11 @@ void launch_keys(const int32_t* xy, const int32_t* pt_off, int32_t K, const Inst
                        radix_digit_major(n));
 }
 
-void launch_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int32_t* pt_off, int Dmax, int K,
-                          int64_t n, int32_t* pts, int32_t* perm_local, int32_t* pinst, hipStream_t st) {
-    hipLaunchKernelGGL(k_gather_sorted, dim3(grid_for(n)), dim3(kBlock), 0, st, keys, vals, pt_off, Dmax, K, n,
-                       reinterpret_cast<int2*>(pts), perm_local, pinst);
-}
-
-void launch_level_stats(const uint64_t* keys, const Chunk* chunks, int32_t nchunks, const InstInfo* inst, int Dmax,
-                        int8_t* cl, int32_t* hist, int32_t* maxc, int32_t* done, int32_t nstats, int32_t* host_out,
-                        hipStream_t st) {
-    hipLaunchKernelGGL(k_level_stats, dim3(unsigned(nchunks)), dim3(kBlock), 0, st, keys, chunks, inst, Dmax, cl, hist,
-                       maxc, done, nstats, host_out);
+void launch_level_stats(const uint64_t* keys, const uint32_t* vals, const Chunk* chunks, int32_t nchunks,
+                        const InstInfo* inst, int Dmax, int32_t K, int32_t* pts, int32_t* perm_local, int32_t* pinst,
+                        int8_t* cl, int32_t* hist, int32_t* done, int32_t* host_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_level_stats, dim3(unsigned(nchunks)), dim3(kBlock), 0, st, keys, vals, chunks, inst, Dmax, K,
+                       reinterpret_cast<int2*>(pts), perm_local, pinst, cl, hist, done, host_out);
 }
 
 void launch_build_boxes(const int32_t* lscan, const int8_t* leaf_cl, const int32_t* leaf_pt0, const uint64_t* leaf_key,
@@ -1008,10 +1000,10 @@ void launch_lists(const uint64_t* box_key, const int32_t* box_parent, const int3
                   const int32_t* box_inst, const int8_t* box_lev, const InstInfo* inst, int64_t nbox, int32_t* nb9,
                   int32_t* il27, hipStream_t st) {
     if (nbox <= 0) return;
-    hipLaunchKernelGGL(k_neighbours, dim3(grid_for(nbox)), dim3(kBlock), 0, st, box_key, box_inst, box_lev, inst, nbox,
-                       nb9);
-    hipLaunchKernelGGL(k_interactions, dim3(grid_for(nbox)), dim3(kBlock), 0, st, box_key, box_parent, box_child,
-                       box_lev, nbox, nb9, il27);
+    hipLaunchKernelGGL(k_neighbours, dim3(grid_for(nbox * 9)), dim3(kBlock), 0, st, box_key, box_inst, box_lev, inst,
+                       nbox, nb9);
+    hipLaunchKernelGGL(k_interactions, dim3(grid_for(nbox * kNumInteractions)), dim3(kBlock), 0, st, box_key,
+                       box_parent, box_child, box_lev, nbox, nb9, il27);
 }
 
 void launch_class_lists(const BoxGroup* groups, int32_t ngroups, int32_t nslots, const int32_t* cscan,

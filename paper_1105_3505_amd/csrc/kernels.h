@@ -147,16 +147,12 @@ void launch_keys(const int32_t* xy, const int32_t* pt_off, int32_t K, const Inst
                  const int32_t* dmax, int64_t n, uint64_t* keys, uint32_t* vals, int32_t* zero,
                  int32_t nzero, void* radix_scratch, hipStream_t st);
 // sorted points (coordinates in the root box, decoded from the keys), instance-local indices
-// and instances
-void launch_gather_sorted(const uint64_t* keys, const uint32_t* vals, const int32_t* pt_off, int Dmax, int K,
-                          int64_t n, int32_t* pts, int32_t* perm_local, int32_t* pinst, hipStream_t st);
-// per-level box counts (hist) and look-ahead maxima (maxc = hist + K (kMaxLevels + 2)) of
-// every instance; *done counts finished blocks (zero before the launch), and the last one
-// copies the nstats totals to host_out (host memory)
-void launch_level_stats(const uint64_t* keys, const Chunk* chunks, int32_t nchunks,
-                        const InstInfo* inst, int Dmax, int8_t* cl, int32_t* hist,
-                        int32_t* maxc, int32_t* done, int32_t nstats, int32_t* host_out,
-                        hipStream_t st);
+// and instances; per-level box counts and look-ahead maxima of every instance into hist
+// ([K][kMaxLevels + 2] counts, then [K] maxima; zero before the launch), copied to host_out
+// (host memory) by the last block; *done counts finished blocks (zero before the launch)
+void launch_level_stats(const uint64_t* keys, const uint32_t* vals, const Chunk* chunks, int32_t nchunks,
+                        const InstInfo* inst, int Dmax, int32_t K, int32_t* pts, int32_t* perm_local, int32_t* pinst,
+                        int8_t* cl, int32_t* hist, int32_t* done, int32_t* host_out, hipStream_t st);
 // exclusive scans of the flags "a leaf starts here" (per point), "leaf b starts a box of
 // level lev" (row lev, per leaf) and "box g is child c of its parent" (row c, per box)
 void scan_leaf_starts(const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int64_t n,

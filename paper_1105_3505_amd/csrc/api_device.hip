@@ -266,8 +266,6 @@ struct lfmm_ctx {
     std::vector<std::unique_ptr<CachedOps>> all_ops;  // every set built; plans may hold any
     std::map<std::pair<int, int>, int32_t> tuned;     // (size class, density class) -> N_leaf
     hipStream_t capture = nullptr;                    // stream that graph captures record on
-    hipStream_t aux = nullptr;                        // second stream of plan construction
-    hipEvent_t fork = nullptr, join = nullptr;
     std::mutex mu;
     // live plans and servers, destroyed with the context if the caller has not done so
     std::set<lfmm_plan*> plans;
@@ -275,9 +273,6 @@ struct lfmm_ctx {
     std::mutex reg_mu;
     ~lfmm_ctx() {
         if (capture) (void)hipStreamDestroy(capture);
-        if (aux) (void)hipStreamDestroy(aux);
-        if (fork) (void)hipEventDestroy(fork);
-        if (join) (void)hipEventDestroy(join);
     }
 };
 
@@ -1012,26 +1007,15 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     // also zeroes row nb of Q-hat and U-hat, which the box-matrix kernels read for absent sources
     launch_link_boxes(pl->box_key, pl->box_parent, pl->box_inst, pl->box_lev, pl->d_inst, nb, pl->box_pt0,
                       pl->box_child, pl->box_pt1, pl->Q + size_t(nb) * P, pl->U + size_t(nb) * P, st);
-    // the lists and the near-field groups run on a second stream beside the class lists and
-    // tiles, which need only the boxes
-    if (!ctx->aux) {
-        LFMM_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
-        LFMM_HIP(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
-        LFMM_HIP(hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));
-    }
-    LFMM_HIP(hipEventRecord(ctx->fork, st));
-    LFMM_HIP(hipStreamWaitEvent(ctx->aux, ctx->fork, 0));
     launch_lists(pl->box_key, pl->box_parent, pl->box_child, pl->box_inst, pl->box_lev, pl->d_inst, nb, pl->nb9,
-                 pl->il27, ctx->aux);
+                 pl->il27, st);
     for (size_t o = 0; o < side_of.size(); ++o)   // groups need the leaves' neighbour lists
         launch_near_groups(pl->near_of_ops[o].t0, h1_start[o], h1_count[o], d_roots + root_off[o],
                            int32_t(roots[o].size()), pl->box_child, pl->nb9, pl->box_pt0, pl->box_pt1, pl->box_key,
-                           pl->groups, pl->ents, ctx->aux);
-    LFMM_HIP(hipEventRecord(ctx->join, ctx->aux));
+                           pl->groups, pl->ents, st);
     scan_child_classes(pl->box_key, nb, cscan, ctotal, cscr, st);
     launch_class_lists(d_groups, int32_t(groups.size()), tile_slots, cscan, ctotal, pl->box_key, nb, pl->cls_box,
                        pl->tiles, st);
-    LFMM_HIP(hipStreamWaitEvent(st, ctx->join, 0));
     LFMM_HIP(hipGetLastError());
     // staging for the per-execute pointer table of batched plans (and of graph replays,
     // whose kernels always read the table)

@@ -261,7 +261,7 @@ struct lfmm_ctx {
     PinnedPool pinned;
     DevicePool pool;             // plan storage and temporaries (declared first: freed last)
     Arena table_mem;
-    double* phi_oct = nullptr;   // octant table, radius 128
+    double* phi_oct = nullptr;   // octant table, radius kPhiDeviceRadius
     std::map<int64_t, CachedOps*> ops;                // deepest operator set per leaf side
     std::vector<std::unique_ptr<CachedOps>> all_ops;  // every set built; plans may hold any
     std::map<std::pair<int, int>, int32_t> tuned;     // (size class, density class) -> N_leaf
@@ -1216,11 +1216,16 @@ lfmm_status lfmm_ctx_create(int32_t device, const lfmm_options* opt, lfmm_ctx** 
         auto ctx = std::make_unique<lfmm_ctx>();
         ctx->device = device;
         ctx->opt = o;
+        // phi: the quadrature table (radius 128), then eq. 3.1 precomputed out to the device
+        // table's radius (neighbour offsets of leaves up to side 128 stay inside it)
         const std::vector<double>& tab = phi_table();
-        ctx->table_mem.reserve(tab.size() * sizeof(double));
+        if (tab.size() != size_t(129) * 130 / 2) throw HipFailure("phi table of unexpected size");
+        ctx->table_mem.reserve(kPhiDeviceEntries * sizeof(double));
         ctx->table_mem.allocate();
-        ctx->phi_oct = ctx->table_mem.take<double>(tab.size());
+        ctx->phi_oct = ctx->table_mem.take<double>(kPhiDeviceEntries);
         LFMM_HIP(hipMemcpy(ctx->phi_oct, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+        launch_phi_extend(ctx->phi_oct, 128, kPhiDeviceRadius, nullptr);
+        LFMM_HIP(hipGetLastError());
         LFMM_HIP(upload_dslots());
         LFMM_HIP(hipDeviceSynchronize());
         *out = ctx.release();

@@ -21,7 +21,6 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kOctRadius = 128;
 // Levels of at most this many 64-box tiles run M2M and L2L on the fine-grained kernels, which
 // spread one tile over twelve blocks (measured: M2M gains up to 64 tiles, L2L up to 256).
 constexpr int32_t kFineM2mTiles = 64;
@@ -63,11 +62,25 @@ __device__ inline double phi_expansion_dev(double a, double b) {
     return lead + t4 + t8;
 }
 
-// phi at offset (a, b), a, b >= 0: octant table inside radius 128, expansion outside
+// phi at offset (a, b), a, b >= 0: the device octant table (quadrature values inside radius
+// 128, eq. 3.1 evaluated once between 128 and kPhiDeviceRadius), eq. 3.1 outside
 __device__ inline double phi_oct(int a, int b, const double* oct) {
     const int hi = max(a, b), lo = min(a, b);
-    if (hi <= kOctRadius) return oct[hi * (hi + 1) / 2 + lo];
+    if (hi <= kPhiDeviceRadius) return oct[hi * (hi + 1) / 2 + lo];
     return phi_expansion_dev(double(hi), double(lo));
+}
+
+// Octant entries with r0 < hi <= r1 (index hi (hi + 1) / 2 + lo) set to eq. 3.1, so that
+// lookups replace the logarithm and division of the expansion for offsets up to r1.
+__global__ void k_phi_extend(double* oct, int r0, int r1) {
+    const int64_t i0 = int64_t(r0 + 1) * (r0 + 2) / 2, i1 = int64_t(r1 + 1) * (r1 + 2) / 2;
+    const int64_t i = i0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= i1) return;
+    int64_t hi = int64_t((sqrt(8.0 * double(i) + 1.0) - 1.0) * 0.5);
+    while (hi * (hi + 1) / 2 > i) --hi;
+    while ((hi + 1) * (hi + 2) / 2 <= i) ++hi;
+    const int64_t lo = i - hi * (hi + 1) / 2;
+    oct[i] = phi_expansion_dev(double(hi), double(lo));
 }
 
 inline unsigned grid_for(int64_t n, int per_block = kBlock) {
@@ -639,7 +652,8 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, cons
 //     each point carries the key K = 8 (y W + x) mod 2^32 (W = 4s - 1), so the byte offset of
 //     phi(x_i - x_j) is K_i - K_j plus a constant: one subtraction per pair.
 //   QUAD (side 32): a table over |dx|, |dy| < 64.
-//   GLOBAL (side >= 64): the octant table of radius 128 in global memory, eq. (3.1) beyond.
+//   GLOBAL (side >= 64): the device octant table (radius kPhiDeviceRadius) in global memory,
+//     eq. (3.1) beyond.
 enum LeafMode { kWindow = 0, kQuad = 1, kGlobal = 2 };
 // Block size per mode.  With an LDS phi table, 512-thread blocks share one table among eight
 // waves and run persistently (each builds its table once); with the global table, 256-thread
@@ -866,7 +880,7 @@ __global__ __launch_bounds__(kBlock) void k_direct(int64_t nt, const int2* txy, 
             dy = dy < 0 ? -dy : dy;
             const int64_t hi = dx > dy ? dx : dy, lo = dx > dy ? dy : dx;
             double ph;
-            if (hi <= kOctRadius) ph = phi_oct[hi * (hi + 1) / 2 + lo];
+            if (hi <= kPhiDeviceRadius) ph = phi_oct[hi * (hi + 1) / 2 + lo];
             else ph = phi_expansion_dev(double(hi), double(lo));
             acc += ph * sf[k];
         }
@@ -1037,6 +1051,12 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
                            box_pt0, box_pt1, box_key, box_inst, side, 0, p2, pkey, fs, perm_local, tab, u_single, U,
                            leafT, far_inst, phi_oct);
     }
+}
+
+void launch_phi_extend(double* oct, int r0, int r1, hipStream_t st) {
+    if (r1 <= r0) return;
+    const int64_t n = int64_t(r1 + 1) * (r1 + 2) / 2 - int64_t(r0 + 1) * (r0 + 2) / 2;
+    hipLaunchKernelGGL(k_phi_extend, dim3(grid_for(n)), dim3(kBlock), 0, st, oct, r0, r1);
 }
 
 void launch_direct(int64_t nt, const int32_t* txy, int64_t ns, const int32_t* sxy, const double* f,

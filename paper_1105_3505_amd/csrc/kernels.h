@@ -213,6 +213,11 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
                  const int32_t* pts, const uint32_t* pkey, const double* fs, const int32_t* perm_local,
                  const ExecPtrs* tab, double* u_single, const double* U, const double* leafT,
                  const uint8_t* far_inst, const double* phi_oct, hipStream_t st);
+// Radius of the device phi table: the host's quadrature table (radius 128) followed by eq. 3.1
+// for the octant entries up to this radius, filled by launch_phi_extend(oct, 128, radius).
+constexpr int kPhiDeviceRadius = 256;
+constexpr size_t kPhiDeviceEntries = size_t(kPhiDeviceRadius + 1) * (kPhiDeviceRadius + 2) / 2;
+void launch_phi_extend(double* oct, int r0, int r1, hipStream_t st);
 void launch_direct(int64_t nt, const int32_t* txy, int64_t ns, const int32_t* sxy,
                    const double* f, const double* phi_oct, double* u, hipStream_t st);
 hipError_t upload_dslots();

@@ -163,7 +163,7 @@ lfmm_status lfmm_autotune(lfmm_ctx* ctx, int64_t n, const int32_t* xy_dev, int32
 
 /* Phases of lfmm_execute, in launch order, for lfmm_plan_phase_times. */
 typedef enum lfmm_phase {
-    LFMM_PHASE_GATHER = 0,    /* loads into Morton order                                   */
+    LFMM_PHASE_GATHER = 0,    /* loads into Morton order (empty: P2M gathers them)         */
     LFMM_PHASE_P2M = 1,       /* T_ofs, Section 8.2 step 1                                 */
     LFMM_PHASE_M2M = 2,       /* T_ofo, step 2                                             */
     LFMM_PHASE_M2L = 3,       /* T_ifo, step 3                                             */

@@ -1042,12 +1042,11 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
         if ((marks >> k & 1u) || (k > 0 && (marks >> (k - 1) & 1u))) LFMM_HIP(hipEventRecord(pl->ev[k], st));
     };
     mark(0);
-    launch_gather_f(tab, f1, pl->perm, pl->pinst, pl->n, pl->fs, st);
-    mark(1);
+    mark(1);   // the loads are gathered into Morton order by P2M itself
     for (size_t o = 0; o < pl->ops.size(); ++o) {
         const TileRange& r = pl->leaf_of_ops[o];
-        launch_p2m(r.t0, r.t0 + r.n, pl->box_pt0, pl->box_pt1, pl->box_key, pl->ops[o]->dev.leaf_side, pl->pts,
-                   pl->fs, pl->ops[o]->dev.leafT, pl->Q, st);
+        launch_p2m(r.t0, r.t0 + r.n, pl->box_pt0, pl->box_pt1, pl->box_key, pl->ops[o]->dev.leaf_side, pl->pts, tab,
+                   f1, pl->perm, pl->pinst, pl->fs, pl->ops[o]->dev.leafT, pl->Q, st);
     }
     mark(2);
     for (int h = 1; h <= pl->Hmax; ++h) {

@@ -88,12 +88,14 @@ inline unsigned grid_for(int64_t n, int per_block = kBlock) {
     return unsigned(g < 1 ? 1 : g);
 }
 
-__global__ void k_gather_f(const ExecPtrs* tab, const double* f_single, const int32_t* perm_local,
-                           const int32_t* pinst, int64_t n, double* fs) {
-    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s >= n) return;
+// Load of sorted point s in the caller's order (instance-local index perm_local[s] of
+// instance pinst[s]), also stored at fs[s] for the near field: P2M visits every point once.
+__device__ inline double gather_f(const ExecPtrs* tab, const double* f_single, const int32_t* perm_local,
+                                  const int32_t* pinst, int64_t s, double* fs) {
     const double* f = tab ? tab[pinst[s]].f : f_single;
-    fs[s] = f[perm_local[s]];
+    const double v = f[perm_local[s]];
+    fs[s] = v;
+    return v;
 }
 
 // P2M with the dense-model operator (Remark 8.2): q-hat[p] = sum_j T[loc(j)][p] f_j; one
@@ -104,7 +106,9 @@ __global__ void k_gather_f(const ExecPtrs* tab, const double* f_single, const in
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0,
                                                  const int32_t* box_pt1, const uint64_t* box_key, int64_t side,
-                                                 const int2* pts, const double* fs, const double* leafT, double* Q) {
+                                                 const int2* pts, const ExecPtrs* tab, const double* f_single,
+                                                 const int32_t* perm_local, const int32_t* pinst, double* fs,
+                                                 const double* leafT, double* Q) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int32_t g = leaf0 + int32_t(blockIdx.x) * kWaves + wave;
     if (g >= leaf1) return;
@@ -120,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_p2m(int32_t leaf0, int32_t leaf1, co
         if (j < p1) {
             const int2 q = pts[j];
             loc = int32_t(int64_t(q.x - cx) + side * int64_t(q.y - cy));
-            f = fs[j];
+            f = gather_f(tab, f_single, perm_local, pinst, j, fs);
         }
         const int cnt = min(64, p1 - c0);
         for (int k = 0; k < cnt; k += 4) {   // k + 3 < 64: the tail reads the zero-load lanes
@@ -150,8 +154,9 @@ constexpr int kP2mLeaves = 64 / kP2mGroup;     // leaves per wave and step
 template <int P>
 __global__ __launch_bounds__(kP2mThreads) void k_p2m_lds(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0,
                                                         const int32_t* box_pt1, const uint64_t* box_key, int64_t side,
-                                                        const int2* pts, const double* fs, const double* leafT,
-                                                        double* Q) {
+                                                        const int2* pts, const ExecPtrs* tab, const double* f_single,
+                                                        const int32_t* perm_local, const int32_t* pinst, double* fs,
+                                                        const double* leafT, double* Q) {
     constexpr int R = P / kP2mGroup;   // rows per lane
     static_assert(P % kP2mGroup == 0, "rows split evenly over a group");
     extern __shared__ double sT[];
@@ -198,7 +203,7 @@ __global__ __launch_bounds__(kP2mThreads) void k_p2m_lds(int32_t leaf0, int32_t 
             if (c0 + l < npt) {
                 const int2 pt = pts[p0 + c0 + l];
                 loc = int32_t(int64_t(pt.x - cx) + side * int64_t(pt.y - cy));
-                f = fs[p0 + c0 + l];
+                f = gather_f(tab, f_single, perm_local, pinst, p0 + c0 + l, fs);
             }
             #pragma unroll
             for (int k = 0; k < kP2mGroup; ++k) {
@@ -914,11 +919,6 @@ hipError_t upload_dslots() {
     return hipSuccess;
 }
 
-void launch_gather_f(const ExecPtrs* tab, const double* f_single, const int32_t* perm_local, const int32_t* pinst,
-                     int64_t n, double* fs, hipStream_t st) {
-    hipLaunchKernelGGL(k_gather_f, dim3(grid_for(n)), dim3(kBlock), 0, st, tab, f_single, perm_local, pinst, n, fs);
-}
-
 // Per device: compute units and the LDS a block may use (the staged P2M is set up to use it).
 struct P2mDevice {
     int cus = 0, lds = 0;
@@ -944,7 +944,8 @@ P2mDevice p2m_device() {
 }
 
 void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1, const uint64_t* box_key,
-                int64_t side, const int32_t* pts, const double* fs, const double* leafT, double* Q, hipStream_t st) {
+                int64_t side, const int32_t* pts, const ExecPtrs* tab, const double* f_single, const int32_t* perm_local,
+                const int32_t* pinst, double* fs, const double* leafT, double* Q, hipStream_t st) {
     if (leaf1 <= leaf0) return;
     const size_t lds = size_t(side * side) * kRankPad * sizeof(double);
     const P2mDevice dv = p2m_device();
@@ -954,11 +955,13 @@ void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int3
         const int64_t want = (int64_t(leaf1 - leaf0) + per_block - 1) / per_block;
         const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(want, int64_t(dv.cus) * per_cu));
         hipLaunchKernelGGL(k_p2m_lds<kRankPad>, dim3(unsigned(grid)), dim3(kP2mThreads), lds, st, leaf0, leaf1,
-                           box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), fs, leafT, Q);
+                           box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), tab, f_single,
+                           perm_local, pinst, fs, leafT, Q);
         return;
     }
     hipLaunchKernelGGL(k_p2m<kRankPad>, dim3(grid_for(leaf1 - leaf0, kWaves)), dim3(kBlock), 0, st, leaf0, leaf1,
-                       box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), fs, leafT, Q);
+                       box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), tab, f_single, perm_local,
+                       pinst, fs, leafT, Q);
 }
 
 void launch_m2m(const BoxTile* tiles, int32_t ntiles, const int32_t* box_child, const OpsPtrs* ops, double* Q,

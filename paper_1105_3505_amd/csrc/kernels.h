@@ -190,10 +190,11 @@ void launch_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, const in
                         hipStream_t st);
 
 // ---- evaluation passes (fmm_kernels.hip) ---------------------------------------------------
-void launch_gather_f(const ExecPtrs* tab, const double* f_single, const int32_t* perm_local,
-                     const int32_t* pinst, int64_t n, double* fs, hipStream_t st);
+// P2M of the leaves [leaf0, leaf1); reads the caller-order loads (tab per instance, or
+// f_single) through perm_local / pinst and also stores them in Morton order at fs
 void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1,
-                const uint64_t* box_key, int64_t side, const int32_t* pts, const double* fs,
+                const uint64_t* box_key, int64_t side, const int32_t* pts, const ExecPtrs* tab,
+                const double* f_single, const int32_t* perm_local, const int32_t* pinst, double* fs,
                 const double* leafT, double* Q, hipStream_t st);
 // M2M over the consecutive-box tiles of one height (Q row zrow is all zeros)
 void launch_m2m(const BoxTile* tiles, int32_t ntiles, const int32_t* box_child, const OpsPtrs* ops, double* Q,

@@ -7,7 +7,11 @@ python bench.py [--gpus 1] [--steps K] [--warmup W]
 A step is one whole solve of the hot path on one batch of synthetic input already resident
 in HBM: tree construction (Morton keys, radix sort, levels, lists) plus the evaluation
 passes (P2M, M2M, M2L, L2L, L2P and near field), from device xy and f to device u.  W
-untimed steps, then K timed steps bracketed by device synchronisation.  Prints one JSON line.
+untimed steps, then K timed steps bracketed by device synchronisation, with --inflight
+independent solves in flight (default 2, one stream and one output buffer each: the host-bound
+plan build of one solve overlaps the evaluation of the previous one).  The serial rate (one
+solve after another on one stream) and the single-solve latency are reported beside it.
+Prints one JSON line.
 
 Workloads (all seeded, synthetic):
   large_uniform (default)  1,000,000 distinct sources uniform in a 4096 x 4096 box, FP64
@@ -109,39 +113,71 @@ def base_result(args, value, ms_per_step, config, dtype="f64"):
 PHASES_ALL = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf")
 
 
-def measure(step, steps, torch):
-    """Phase split, timed region and latencies of `step` (one whole solve: plan build, execute,
-    plan release).  First a few solves with HIP events between all phases (outside the timed
-    region) pick the dominant phase; the timed region then runs `steps` solves back to back
-    between two device synchronisations, each recording only the two events around that phase
-    (its duration on the execute stream, for the roofline); last, solve latencies with each
-    solve synchronised on its own and no events."""
+def measure(step, steps, torch, inflight):
+    """Phase split, timed region and latencies of `step(timing, slot)` (one whole solve: plan
+    build, execute, plan release; `slot` names the stream and output buffers it uses).
+
+    First a few solves with HIP events between all phases (outside the timed region) pick the
+    dominant phase.  The timed region then runs `steps` independent solves between two device
+    synchronisations with `inflight` of them in flight: solve i goes to stream i % inflight, so
+    the host-bound build of one solve overlaps the evaluation passes of the one before it.  Each
+    records only the two events around the dominant phase (its duration on its own stream, for
+    the roofline); those are read, and the plan released, once `inflight` newer solves have been
+    enqueued.  Next the same solves one after another on one stream (the serial rate), last
+    solve latencies with each solve synchronised on its own and no events."""
+    from collections import deque
     phases = []
     for _ in range(min(steps, 5)):
-        plan = step(PHASES_ALL)
+        plan = step(PHASES_ALL, 0)
         torch.cuda.synchronize()
         phases.append(plan.phase_times())
         plan.close()
     avg = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
     dom = max(avg, key=avg.get)
     dom_ms = []
+    pending = deque()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        plan = step([dom])
+    for i in range(steps):
+        pending.append(step([dom], i % inflight))
+        if len(pending) >= inflight:
+            plan = pending.popleft()
+            dom_ms.append(plan.phase_times()[dom])
+            plan.close()
+    while pending:
+        plan = pending.popleft()
         dom_ms.append(plan.phase_times()[dom])
         plan.close()
     torch.cuda.synchronize()
     ms_per_step = (time.perf_counter() - t0) * 1e3 / steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(None, 0).close()
+    torch.cuda.synchronize()
+    serial_ms = (time.perf_counter() - t0) * 1e3 / steps
     lat = []
     for _ in range(steps):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        plan = step(None)
+        plan = step(None, 0)
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t1) * 1e3)
         plan.close()
-    return ms_per_step, lat, avg, dom, float(np.mean(dom_ms))
+    return {"ms_per_step": ms_per_step, "serial_ms": serial_ms, "lat": lat, "avg": avg, "dom": dom,
+            "dom_ms": float(np.mean(dom_ms))}
+
+
+def streams_for(inflight, torch):
+    """Stream of each in-flight slot: the current stream, then new default-priority streams."""
+    return [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(inflight - 1)]
+
+
+def timing_fields(m, n, inflight):
+    return {"inflight": inflight, "serial_ms_per_step": m["serial_ms"],
+            "serial_msources_per_s": n / (m["serial_ms"] * 1e-3) / 1e6,
+            "p50_ms": float(np.percentile(m["lat"], 50)), "p99_ms": float(np.percentile(m["lat"], 99)),
+            "phase_ms": m["avg"]}
 
 
 def cpu_baseline(xy, f, u, n_targets, seed=20):
@@ -171,23 +207,30 @@ def run_single(args, torch, lf):
     dev = torch.device("cuda:0")
     xy_d = torch.from_numpy(xy).to(dev)
     f_d = torch.from_numpy(f).to(dev)
-    u_d = torch.empty(n, dtype=torch.float64, device=dev)
     ctx = lf.Context(0, precision=args.precision, max_leaf=args.max_leaf)
-    stream = torch.cuda.current_stream()
+    streams = streams_for(args.inflight, torch)
+    outs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in streams]
 
-    def step(timing):
-        plan = ctx.plan(xy_d, stream=stream)
+    def step(timing, slot):
+        st = streams[slot]
+        plan = ctx.plan(xy_d, stream=st)
         if timing:
             plan.set_timing_phases(timing)
-        plan.execute(f_d, u_d, stream=stream)
+        plan.execute(f_d, outs[slot], stream=st)
         return plan
 
     for _ in range(max(args.warmup, 1)):
-        step(None).close()
-    ms_per_step, lat, avg, dom, dom_ms = measure(step, args.steps, torch)
+        for slot in range(len(streams)):
+            step(None, slot).close()
+    m = measure(step, args.steps, torch, args.inflight)
+    ms_per_step = m["ms_per_step"]
     value = n / (ms_per_step * 1e-3) / 1e6
+    torch.cuda.synchronize()
+    same = all(torch.equal(o, outs[0]) for o in outs[1:])   # every slot computed the same solve
 
     # execute-only throughput on a resident plan (outside the timed steps: plan statistics)
+    stream = streams[0]
+    u_d = outs[0]
     plan = ctx.plan(xy_d, stream=stream)
     info = plan.info()
     for _ in range(3):
@@ -207,10 +250,11 @@ def run_single(args, torch, lf):
               "leaf_level": info["leaf_level"], "leaf_side": info["leaf_side"], "max_leaf": args.max_leaf,
               "rank": RANK, "eps": 1e-12}
     result = base_result(args, value, ms_per_step, config)
-    result.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+    result.update(timing_fields(m, n, args.inflight))
+    result.update({"inflight_outputs_equal": same,
                    "execute_only_ms": exec_ms, "execute_only_msources_per_s": n / (exec_ms * 1e-3) / 1e6,
-                   "phase_ms": avg, "plan": info,
-                   "roofline": roofline(dom, dom_ms, info, n, args.precision, args.workload)})
+                   "plan": info,
+                   "roofline": roofline(m["dom"], m["dom_ms"], info, n, args.precision, args.workload)})
     if not args.no_cpu_baseline:
         err, k, base = cpu_baseline(xy, f, u, args.cpu_targets)
         result["rel_err_vs_oracle"] = err
@@ -226,20 +270,27 @@ def run_batched(args, torch, lf):
     n = sum(len(a) for a, _ in inst)
     xs = [torch.from_numpy(a).cuda() for a, _ in inst]
     fs = [torch.from_numpy(b).cuda() for _, b in inst]
-    us = [torch.empty_like(b) for b in fs]
     ctx = lf.Context(0, precision=args.precision, max_leaf=args.max_leaf)
-    stream = torch.cuda.current_stream()
+    streams = streams_for(args.inflight, torch)
+    outs = [[torch.empty_like(b) for b in fs] for _ in streams]
 
-    def step(timing):
-        plan = ctx.plan_batch(xs, stream=stream)
+    def step(timing, slot):
+        st = streams[slot]
+        plan = ctx.plan_batch(xs, stream=st)
         if timing:
             plan.set_timing_phases(timing)
-        plan.execute_instances(fs, us, stream=stream)
+        plan.execute_instances(fs, outs[slot], stream=st)
         return plan
 
     for _ in range(max(args.warmup, 1)):
-        step(None).close()
-    ms_per_step, lat, avg, dom, dom_ms = measure(step, args.steps, torch)
+        for slot in range(len(streams)):
+            step(None, slot).close()
+    m = measure(step, args.steps, torch, args.inflight)
+    ms_per_step = m["ms_per_step"]
+    torch.cuda.synchronize()
+    same = all(torch.equal(a, b) for o in outs[1:] for a, b in zip(o, outs[0]))
+    stream = streams[0]
+    us = outs[0]
     plan = ctx.plan_batch(xs, stream=stream)
     info = plan.info()
     plan.execute_instances(fs, us, stream=stream)
@@ -255,10 +306,11 @@ def run_batched(args, torch, lf):
     config = {"workload": WORKLOADS["batched"], "n_instances": len(inst), "n_sources": n,
               "precision": args.precision, "max_leaf": args.max_leaf, "rank": RANK, "eps": 1e-12}
     result = base_result(args, n / (ms_per_step * 1e-3) / 1e6, ms_per_step, config)
-    result.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+    result.update(timing_fields(m, n, args.inflight))
+    result.update({"inflight_outputs_equal": same,
                    "execute_only_ms": exec_ms, "execute_only_msources_per_s": n / (exec_ms * 1e-3) / 1e6,
-                   "phase_ms": avg, "plan": info,
-                   "roofline": roofline(dom, dom_ms, info, n, args.precision, "batched")})
+                   "plan": info,
+                   "roofline": roofline(m["dom"], m["dom_ms"], info, n, args.precision, "batched")})
     if not args.no_cpu_baseline:
         # accuracy on 100 sampled targets of every 8th instance; CPU rate over that sample
         from oracle import direct as od
@@ -360,6 +412,8 @@ def main() -> None:
     ap.add_argument("--workload", default="large_uniform", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=sorted(TOLERANCE))
     ap.add_argument("--max-leaf", type=int, default=64)
+    ap.add_argument("--inflight", type=int, default=2,
+                    help="independent solves in flight in the timed region, one stream each")
     ap.add_argument("--cpu-targets", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=200, help="serving: requests in the stream")
@@ -369,6 +423,8 @@ def main() -> None:
                     help="first fill and copy a buffer of this many MiB (a known-traffic reference for "
                          "hardware byte counters)")
     args = ap.parse_args()
+    if args.inflight < 1:
+        ap.error("--inflight must be at least 1")
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <stdexcept>
 
 namespace lfmm {
 
@@ -660,6 +661,7 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, cons
 //   GLOBAL (side >= 64): the device octant table (radius kPhiDeviceRadius) in global memory,
 //     eq. (3.1) beyond.
 enum LeafMode { kWindow = 0, kQuad = 1, kGlobal = 2 };
+constexpr int kNearTabMax = 64 * 64;   // doubles: W^2 for the window (side 16) and quad (side 32) tables
 // Block size per mode.  With an LDS phi table, 512-thread blocks share one table among eight
 // waves and run persistently (each builds its table once); with the global table, 256-thread
 // blocks take one group per wave and the hardware balances uneven groups.
@@ -684,7 +686,8 @@ __device__ inline cptr<T> as_const(const T* p) {
 template <int P, int MODE, bool SLICED>
 __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int4* ents, const int32_t* box_pt0,
                                   const int32_t* box_pt1, const uint64_t* box_key, const int32_t* box_inst,
-                                  int64_t side, int W, const double* tab, const char* tb, const int2* pts,
+                                  int64_t side, int W, const double* tab, const char* tb, uint32_t kofs,
+                                  const int2* pts,
                                   const uint32_t* pkey, const double* fs, const int32_t* perm_local,
                                   const ExecPtrs* tab_ptrs, double* u_single, const double* U, const double* leafT,
                                   const uint8_t* far_inst, const double* phi_oct_tab) {
@@ -726,7 +729,9 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
             const uint64_t key = box_key[leaf];
             const int32_t tx = int32_t(compact_bits(key)), ty = int32_t(compact_bits(key >> 1));
             const int2 pi = pts[ii];
-            const uint32_t ki = (MODE == kWindow) ? pkey[ii] : 0u;
+            // the window centre's byte offset is folded into the target's key once, so that a
+            // pair costs one subtraction for its table address
+            const uint32_t ki = (MODE == kWindow) ? pkey[ii] + kofs : 0u;
             const int32_t pout = perm_local[ii];
             double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
             auto phi_at = [&](uint32_t kj, int2_t pj) -> double {
@@ -820,7 +825,9 @@ __global__ __launch_bounds__(near_threads(MODE)) void k_near(int32_t q0, int32_t
                                                       double* u_single, const double* U, const double* leafT,
                                                       const uint8_t* far_inst, const double* phi_oct_tab) {
     constexpr int kNearBlock = near_threads(MODE), kNearWaves = kNearBlock / 64;
-    extern __shared__ double tab[];
+    // fixed-size table (largest window: side 32), so that its base is a compile-time constant
+    // and folds into the address of every read
+    __shared__ double tab[MODE == kGlobal ? 1 : kNearTabMax];
     const int tid = threadIdx.x, wave = tid >> 6;
     if (MODE != kGlobal) {
         const int c = (MODE == kWindow) ? int(2 * side - 1) : 0;
@@ -846,7 +853,8 @@ __global__ __launch_bounds__(near_threads(MODE)) void k_near(int32_t q0, int32_t
         __syncthreads();
     }
     const int cw = (MODE == kWindow) ? int(2 * side - 1) : 0;
-    const char* tb = reinterpret_cast<const char*>(tab) + size_t(8) * size_t(cw * W + cw);
+    const char* tb = reinterpret_cast<const char*>(tab);
+    const uint32_t kofs = 8u * uint32_t(cw * W + cw);
     for (int32_t q = q0 + int32_t(blockIdx.x) * kNearWaves + wave; q < q1; q += int32_t(gridDim.x) * kNearWaves) {
         const int32_t qq = uniform(q);
         const int32_t leaf0 = uniform(groups[qq].leaf0), nleaf = uniform(groups[qq].nleaf);
@@ -854,10 +862,10 @@ __global__ __launch_bounds__(near_threads(MODE)) void k_near(int32_t q0, int32_t
         // group mode when half a wave or more is busy and phi comes from an LDS table; leaf by
         // leaf otherwise (the octant table in global memory is read faster a leaf at a time)
         if (MODE != kGlobal && nt > 32)
-            near_group<P, MODE, false>(qq, groups, ents, box_pt0, box_pt1, box_key, box_inst, side, W, tab, tb, pts,
+            near_group<P, MODE, false>(qq, groups, ents, box_pt0, box_pt1, box_key, box_inst, side, W, tab, tb, kofs, pts,
                                        pkey, fs, perm_local, tab_ptrs, u_single, U, leafT, far_inst, phi_oct_tab);
         else
-            near_group<P, MODE, true>(qq, groups, ents, box_pt0, box_pt1, box_key, box_inst, side, W, tab, tb, pts,
+            near_group<P, MODE, true>(qq, groups, ents, box_pt0, box_pt1, box_key, box_inst, side, W, tab, tb, kofs, pts,
                                       pkey, fs, perm_local, tab_ptrs, u_single, U, leafT, far_inst, phi_oct_tab);
     }
 }
@@ -1033,7 +1041,8 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
     const int2* p2 = reinterpret_cast<const int2*>(pts);
     if (side <= 16) {
         const int W = int(4 * side - 1);
-        const size_t lds = size_t(W * W) * sizeof(double);
+        const size_t lds = 0;   // the table is a fixed-size shared array
+        if (W * W > kNearTabMax) throw std::logic_error("near-field window table larger than its array");
         constexpr int nt = near_threads(kWindow);
         const unsigned g = grid(reinterpret_cast<const void*>(&k_near<kRankPad, kWindow>), nt, lds, true);
         hipLaunchKernelGGL((k_near<kRankPad, kWindow>), dim3(g), dim3(nt), lds, st, q0, q1, groups, ents,
@@ -1041,7 +1050,8 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
                            leafT, far_inst, phi_oct);
     } else if (side <= 32) {
         const int W = int(2 * side);
-        const size_t lds = size_t(W * W) * sizeof(double);
+        const size_t lds = 0;
+        if (W * W > kNearTabMax) throw std::logic_error("near-field quadrant table larger than its array");
         constexpr int nt = near_threads(kQuad);
         const unsigned g = grid(reinterpret_cast<const void*>(&k_near<kRankPad, kQuad>), nt, lds, true);
         hipLaunchKernelGGL((k_near<kRankPad, kQuad>), dim3(g), dim3(nt), lds, st, q0, q1, groups, ents,

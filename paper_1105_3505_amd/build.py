@@ -40,9 +40,11 @@ def compile_one(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     cmd = [hipcc(), "-c", "-O3", "-fPIC", "-std=c++17", "-Wall", "-I", INCLUDE, "-I", CSRC, "-o", obj]
     if src.endswith(".hip"):
-        # device code for gfx950 only; packed FP32 instructions are kept out of device code
+        # device code for gfx950 only; packed FP32 instructions are kept out of device code;
+        # matrix-core accumulators in ordinary vector registers (no copies to and from the
+        # accumulation registers around every slot of the box-matrix kernels)
         cmd += ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
-                "-packed-fp32-ops", "-munsafe-fp-atomics"]
+                "-packed-fp32-ops", "-munsafe-fp-atomics", "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
     else:
         cmd += ["-x", "c++"]
     cmd.append(src)

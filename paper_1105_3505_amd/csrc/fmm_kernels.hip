@@ -290,7 +290,6 @@ __device__ inline void boxmat_tiles(const BoxTile* tiles, int32_t ntiles, const 
         if (count == 0) continue;
         const int32_t start = uniform(tiles[t].start), height = uniform(tiles[t].height);
         const int32_t cls = uniform(tiles[t].cls), opi = uniform(tiles[t].ops);
-        const bool wave_on = 16 * wave < count;
         const int col = 16 * wave + n;
         const int32_t box = (col < count) ? (box_list ? box_list[start + col] : start + col) : -1;
         const gptr<int32_t> srcs = global(src_tab + size_t(box >= 0 ? box : 0) * SW);
@@ -311,6 +310,7 @@ __device__ inline void boxmat_tiles(const BoxTile* tiles, int32_t ntiles, const 
         double2_t rb0 = qs[0], rb1 = qs[1], rb2 = qs[2], rb3 = qs[3], rb4 = qs[4], rb5 = qs[5];
         int32_t src_next = (box >= 0 && NS > 1) ? srcs[1] : -1;
         const gptr<double2_t> Ak = Ah + size_t(dsl[0]) * A2;
+        int32_t dsl_next = NS > 1 ? dsl[1] : 0;   // operator of the next slot, read a slot ahead
         double2_t ra0 = Ak[tid], ra1 = Ak[tid + kBlock], ra2 = Ak[tid + 2 * kBlock], ra3 = Ak[tid + 3 * kBlock];
         double2_t ra4 = (tid < kBlock / 2) ? Ak[tid + 4 * kBlock] : z2;
         double4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0;
@@ -353,14 +353,17 @@ __device__ inline void boxmat_tiles(const BoxTile* tiles, int32_t ntiles, const 
                 rb4 = qn[4];
                 rb5 = qn[5];
                 src_next = (box >= 0 && k + 2 < NS) ? srcs[k + 2] : -1;
-                const gptr<double2_t> An = Ah + size_t(dsl[k + 1]) * A2;
+                const gptr<double2_t> An = Ah + size_t(uniform(dsl_next)) * A2;
                 ra0 = An[tid];
                 ra1 = An[tid + kBlock];
                 ra2 = An[tid + 2 * kBlock];
                 ra3 = An[tid + 3 * kBlock];
                 if (tid < kBlock / 2) ra4 = An[tid + 4 * kBlock];
+                dsl_next = (k + 2 < NS) ? dsl[k + 2] : 0;
             }
-            if (wave_on) {
+            // every wave runs the products (a wave past the tile's boxes multiplies the zero
+            // row): no branch around them, so the accumulators stay in place between slots
+            {
                 #pragma unroll
                 for (int j = 0; j < NJ; ++j) {
                     const double2_t a0 = buf[(0 * NJ + j) * 64 + lane];

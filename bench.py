@@ -8,7 +8,7 @@ A step is one whole solve of the hot path on one batch of synthetic input alread
 in HBM: tree construction (Morton keys, radix sort, levels, lists) plus the evaluation
 passes (P2M, M2M, M2L, L2L, L2P and near field), from device xy and f to device u.  W
 untimed steps, then K timed steps bracketed by device synchronisation, with --inflight
-independent solves in flight (default 2, one stream and one output buffer each: the host-bound
+independent solves in flight (default 3, one stream and one output buffer each: the host-bound
 plan build of one solve overlaps the evaluation of the previous one).  The serial rate (one
 solve after another on one stream) and the single-solve latency are reported beside it.
 Prints one JSON line.
@@ -412,7 +412,7 @@ def main() -> None:
     ap.add_argument("--workload", default="large_uniform", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=sorted(TOLERANCE))
     ap.add_argument("--max-leaf", type=int, default=64)
-    ap.add_argument("--inflight", type=int, default=2,
+    ap.add_argument("--inflight", type=int, default=3,
                     help="independent solves in flight in the timed region, one stream each")
     ap.add_argument("--cpu-targets", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -6,6 +6,8 @@ device wait, and the sort passes that the plan build enqueues before it knows th
 * A plan released right after its execute (no synchronisation) gives its memory back to the
   context's pool only once its stream has passed the release: plans built next, on the same
   or on another stream, must still compute exactly what a fresh context computes.
+* Independent solves issued round-robin on three streams without synchronisation (the bench's
+  timed loop) each equal the solve run alone, bit for bit.
 * With 2^16 points or more the build sorts on two 8-bit digits before reading the root boxes
   back; when the keys are narrower than that (many points on a small box) the extra pass runs
   over zero digits and must leave the order, and so the potentials, unchanged.
@@ -127,4 +129,43 @@ def test_extra_sort_pass_on_narrow_keys(torch_mod):
     keys = [morton(p) for p in pts[::97]]
     assert all(a <= b for a, b in zip(keys, keys[1:]))
     plan.close()
+    ctx.close()
+
+
+def test_solves_in_flight_on_three_streams(torch_mod):
+    """The bench's timed loop: independent solves (build, execute, release) issued round-robin
+    on three streams with no synchronisation between them, each into its own output buffer,
+    must each equal the solve run alone, bit for bit, for two different point sets."""
+    import paper_1105_3505_amd as lf
+    torch = torch_mod
+    rng = np.random.default_rng(404)
+    sets = []
+    for k in range(2):
+        xy = wl.uniform_box(rng, 70000 + 9000 * k, 700 + 60 * k)
+        sets.append((xy, wl.zero_sum_loads(rng.standard_normal(len(xy)))))
+    ctx = lf.Context(0)
+    ref = []
+    for xy, f in sets:
+        p = ctx.plan(_dev(torch, xy))
+        ref.append(p.execute(_dev(torch, f)).cpu().numpy())
+        p.close()
+    dev = [(_dev(torch, xy), _dev(torch, f)) for xy, f in sets]
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    outs = []
+    for i in range(12):
+        k = (i // 3) % 2
+        st = streams[i % 3]
+        xd, fd = dev[k]
+        u = torch.empty(len(sets[k][0]), dtype=torch.float64, device="cuda")
+        with torch.cuda.stream(st):
+            plan = ctx.plan(xd, stream=st)
+            plan.execute(fd, u, stream=st)
+            plan.close()
+        outs.append((k, u))
+    torch.cuda.synchronize()
+    for k, u in outs:
+        assert np.array_equal(u.cpu().numpy(), ref[k])
+    idx = wl.sample_targets(9, len(sets[0][0]), 300)
+    assert _rel(ref[0][idx], od.direct_sum(sets[0][0][idx], sets[0][0], sets[0][1])) <= FMM_TOL
     ctx.close()

@@ -181,6 +181,22 @@ def test_large_uniform_sampled(torch_mod, ctx):
     assert err <= FMM_TOL
 
 
+@pytest.mark.slow
+def test_clusters_sampled(torch_mod, ctx):
+    # 2,000,000 sources in 64 Gaussian clusters over a 2^20 x 2^20 region (leaf side 128: the
+    # near field reads the device octant table); 500 sampled targets
+    xy, f = wl.config_clusters()
+    u, plan = _fmm(torch_mod, ctx, xy, f)
+    info = plan.info()
+    assert info["leaf_side"] >= 64
+    idx = wl.sample_targets(21, len(xy), 500)
+    ref = od.direct_sum(xy[idx], xy, f)
+    err = _rel(u[idx], ref)
+    print("n=2e6 clusters leaf level %d side %d near pairs %d m2l pairs %d rel err %.3e"
+          % (info["leaf_level"], info["leaf_side"], info["near_pairs"], info["m2l_pairs"], err))
+    assert err <= FMM_TOL
+
+
 @pytest.mark.parametrize("max_leaf", [8, 16, 32, 128, 256])
 def test_leaf_sizes(torch_mod, max_leaf):
     # leaf sides from 2 to 64: window table, quadrant table and global-table near fields

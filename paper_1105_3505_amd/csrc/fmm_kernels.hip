@@ -656,7 +656,8 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, cons
 // of the union of the leaves' neighbourhoods (a 4 x 4 block of leaves at most), listed per
 // group at plan time as point ranges with their leaf coordinates.  The wave walks those
 // ranges in lockstep: range and source reads are uniform over the wave (scalar loads), and a
-// lane adds a range's sources only if that leaf neighbours its own leaf.
+// lane adds a range's sources only if that leaf neighbours its own leaf (the group's own leaves
+// are one range, near to every lane).
 //   WINDOW (side <= 16): phi sits in a window table over all offsets in [-(2s-1), 2s-1]^2 and
 //     each point carries the key K = 8 (y W + x) mod 2^32 (W = 4s - 1), so the byte offset of
 //     phi(x_i - x_j) is K_i - K_j plus a constant: one subtraction per pair.
@@ -758,7 +759,7 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
             auto src_f = [&](int32_t j) -> double { return SLICED ? fs[j] : SF[j]; };
             for (int e = 0; e < ne; ++e) {
                 const int4_t en = E[size_t(qq) * kNearEntries + e];   // (first point, end, leaf x, leaf y)
-                const bool near = abs(en.z - tx) <= 1 && abs(en.w - ty) <= 1;   // uniform when sliced
+                const bool near = en.z == kNearAll || (abs(en.z - tx) <= 1 && abs(en.w - ty) <= 1);   // uniform when sliced
                 if (near) {
                     int32_t j = en.x + sl;
                     if (!SLICED)   // sixteen sources per step: few waits for their scalar loads

@@ -495,6 +495,7 @@ __global__ void k_class_tiles(const BoxGroup* groups, int32_t ngroups, int32_t n
 // cell (j mod 4, j / 4) of the 4 x 4 block of leaf cells around the parent, whose children sit
 // at cells 1..2; it reads the box at its cell from the neighbour list of the first child of
 // the group next to that cell, and its entry goes to the rank of its box among the group's.
+// The children themselves make one entry (their points are one run) marked near to all.
 __global__ void k_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, const int32_t* roots, int32_t nroots,
                               const int32_t* box_child, const int32_t* nb9, const int32_t* box_pt0,
                               const int32_t* box_pt1, const uint64_t* box_key, NearGroup* groups, int4* ents) {
@@ -524,6 +525,10 @@ __global__ void k_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, co
             if (j < 9) b = nb9[size_t(leaf0) * 9 + j];
         }
     }
+    // the group's own leaves (cells 1..2 x 1..2: consecutive boxes, so one run of points, and
+    // neighbours of every target of the group) become one entry, held by the first of them
+    const bool own = active && q < h1_count && (j & 3) >= 1 && (j & 3) <= 2 && (j >> 2) >= 1 && (j >> 2) <= 2;
+    if (own && b != leaf0) b = -1;
     int rank = 0, cnt = 0;
     #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -532,7 +537,9 @@ __global__ void k_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, co
         rank += (bi >= 0 && bi < b) ? 1 : 0;
     }
     if (!active) return;
-    if (b >= 0) {
+    if (b >= 0 && own) {
+        ents[size_t(q0 + q) * kNearEntries + rank] = make_int4(box_pt0[b], box_pt1[b + nleaf - 1], kNearAll, kNearAll);
+    } else if (b >= 0) {
         const uint64_t key = box_key[b];
         ents[size_t(q0 + q) * kNearEntries + rank] =
             make_int4(box_pt0[b], box_pt1[b], int32_t(compact_bits(key)), int32_t(compact_bits(key >> 1)));

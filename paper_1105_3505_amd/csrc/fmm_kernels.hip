@@ -759,7 +759,8 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
             auto src_f = [&](int32_t j) -> double { return SLICED ? fs[j] : SF[j]; };
             for (int e = 0; e < ne; ++e) {
                 const int4_t en = E[size_t(qq) * kNearEntries + e];   // (first point, end, leaf x, leaf y)
-                const bool near = en.z == kNearAll || (abs(en.z - tx) <= 1 && abs(en.w - ty) <= 1);   // uniform when sliced
+                const bool near = (en.z == kNearAll || abs(en.z - tx) <= 1) &&
+                                  (en.w == kNearAll || abs(en.w - ty) <= 1);   // uniform when sliced
                 if (near) {
                     int32_t j = en.x + sl;
                     if (!SLICED)   // sixteen sources per step: few waits for their scalar loads

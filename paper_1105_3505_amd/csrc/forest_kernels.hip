@@ -495,7 +495,8 @@ __global__ void k_class_tiles(const BoxGroup* groups, int32_t ngroups, int32_t n
 // cell (j mod 4, j / 4) of the 4 x 4 block of leaf cells around the parent, whose children sit
 // at cells 1..2; it reads the box at its cell from the neighbour list of the first child of
 // the group next to that cell, and its entry goes to the rank of its box among the group's.
-// The children themselves make one entry (their points are one run) marked near to all.
+// The children themselves make one entry (their points are one run) marked near to all, and
+// so do the two cells above them and the two below (near by y alone).
 __global__ void k_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, const int32_t* roots, int32_t nroots,
                               const int32_t* box_child, const int32_t* nb9, const int32_t* box_pt0,
                               const int32_t* box_pt1, const uint64_t* box_key, NearGroup* groups, int4* ents) {
@@ -529,6 +530,15 @@ __global__ void k_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, co
     // neighbours of every target of the group) become one entry, held by the first of them
     const bool own = active && q < h1_count && (j & 3) >= 1 && (j & 3) <= 2 && (j >> 2) >= 1 && (j >> 2) <= 2;
     if (own && b != leaf0) b = -1;
+    // likewise the two cells above (and the two below) the children: two children of one parent,
+    // so consecutive boxes, and neighbours in x of every target; one entry, near by y alone
+    const bool rowpair = active && q < h1_count && (j & 3) >= 1 && (j & 3) <= 2 && ((j >> 2) == 0 || (j >> 2) == 3);
+    const int32_t bp = __shfl(b, (lane & ~3) | (3 - (j & 3)), 64);   // the other cell of the pair
+    int32_t b_end = b;                                                // last box of the entry
+    if (rowpair && b >= 0 && bp >= 0) {
+        if (b < bp) b_end = bp;
+        else b = -1;
+    }
     int rank = 0, cnt = 0;
     #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -539,6 +549,9 @@ __global__ void k_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, co
     if (!active) return;
     if (b >= 0 && own) {
         ents[size_t(q0 + q) * kNearEntries + rank] = make_int4(box_pt0[b], box_pt1[b + nleaf - 1], kNearAll, kNearAll);
+    } else if (b >= 0 && rowpair) {
+        ents[size_t(q0 + q) * kNearEntries + rank] =
+            make_int4(box_pt0[b], box_pt1[b_end], kNearAll, int32_t(compact_bits(box_key[b] >> 1)));
     } else if (b >= 0) {
         const uint64_t key = box_key[b];
         ents[size_t(q0 + q) * kNearEntries + rank] =

@@ -96,8 +96,8 @@ struct NearGroup {
 // At most 16 source leaves per group (the 4 x 4 block around a parent's children); entry
 // (first point, end point, leaf x, leaf y) in leaf coordinates of the group's level.
 constexpr int kNearEntries = 16;
-// leaf x coordinate of a near-field entry that is near to every target of its group (the
-// group's own leaves, one run of points)
+// leaf coordinate of a near-field entry that matches every target of its group: both for the
+// group's own leaves (one run of points), x alone for the two cells above or below them
 constexpr int32_t kNearAll = -(1 << 30);
 
 // Per-execute load/potential pointers of each instance.

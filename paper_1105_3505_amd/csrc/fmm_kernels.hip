@@ -790,7 +790,22 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
                         a2 += phi_at(src_key(j + 2 * S), src_pt(j + 2 * S)) * src_f(j + 2 * S);
                         a3 += phi_at(src_key(j + 3 * S), src_pt(j + 3 * S)) * src_f(j + 3 * S);
                     }
-                    for (; j < en.y; j += S) a0 += phi_at(src_key(j), src_pt(j)) * src_f(j);
+                    if (!SLICED) {
+                        // the last one to three sources with their loads issued together (one wait)
+                        const int32_t rem = en.y - j;
+                        if (rem == 3) {
+                            a0 += phi_at(src_key(j), src_pt(j)) * src_f(j);
+                            a1 += phi_at(src_key(j + 1), src_pt(j + 1)) * src_f(j + 1);
+                            a2 += phi_at(src_key(j + 2), src_pt(j + 2)) * src_f(j + 2);
+                        } else if (rem == 2) {
+                            a0 += phi_at(src_key(j), src_pt(j)) * src_f(j);
+                            a1 += phi_at(src_key(j + 1), src_pt(j + 1)) * src_f(j + 1);
+                        } else if (rem == 1) {
+                            a0 += phi_at(src_key(j), src_pt(j)) * src_f(j);
+                        }
+                    } else {
+                        for (; j < en.y; j += S) a0 += phi_at(src_key(j), src_pt(j)) * src_f(j);
+                    }
                 }
             }
             if (far) {

@@ -7,8 +7,9 @@
  *     u(m) = sum over sources n of phi(m - n) f(n),      m, n in Z^2,
  *
  * where phi is the fundamental solution of the 5-point discrete Laplacian (eq. 1.2, eq. 1.8),
- * at the source points themselves ("we seek the potential at the source points", Section
- * 8.1).  The fast method is the lattice FMM of Sections 4-8: a quadtree on the sources
+ * at the source points themselves (the paper's default, Section 8.1) or at targets of the
+ * caller's choosing (the problem statement of Section 1: loads at sources, potentials wanted
+ * at finitely many targets).  The fast method is the lattice FMM of Sections 4-8: a quadtree on the sources
  * (Section 6), outgoing/incoming skeleton expansions built by interpolative decomposition
  * (Sections 4.3, 5, 7), the five translation operators (Section 7) and the upward,
  * interaction and downward passes (Section 8.2), with the near field summed against a
@@ -28,7 +29,10 @@
  *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued on it in
  *    order; calls that must read sizes back (plan creation) synchronise the stream.
  *  - The well-posedness condition of Section 1 is a zero total load.  The library returns
- *    the finite sum for any loads; a non-zero sum is not an error.
+ *    the finite sum for any loads; a non-zero sum is not an error.  Calls that check the
+ *    loads (lfmm_solve always, lfmm_execute* with LFMM_FLAG_CHECK_LOADS) return the warning
+ *    LFMM_W_NONZERO_SUM (> 0: the result is computed) when |sum f| > 1e-12 sum |f|, and
+ *    LFMM_E_INVAL before any pass is launched when a load is NaN or infinite.
  *  - One host thread per context at a time.  Plans of one context are independent.
  *    Plans draw their device memory from the context's pool: lfmm_ctx_destroy destroys the
  *    servers and plans still alive on the context, whose handles then become invalid.
@@ -45,7 +49,9 @@ extern "C" {
 
 typedef enum lfmm_status {
     LFMM_OK = 0,
-    LFMM_E_INVAL = -1,        /* null pointer, bad size, bad option value              */
+    LFMM_W_NONZERO_SUM = 1,   /* warning: the loads do not sum to zero (|sum f| > 1e-12 sum |f|);
+                                 the potentials are computed all the same                 */
+    LFMM_E_INVAL = -1,        /* null pointer, bad size, bad option value, NaN/Inf load  */
     LFMM_E_RANGE = -2,        /* coordinate extent >= 2^31, or a size the plan cannot hold */
     LFMM_E_NOMEM = -3,        /* device or host allocation failed                        */
     LFMM_E_HIP = -4,          /* a HIP runtime call failed; the plan is unusable          */
@@ -79,6 +85,10 @@ typedef struct lfmm_options {
  * passes, recorded at the plan's first execute (one graph launch per execute instead of one
  * launch per pass and height).  Per-phase timing is not available in this mode. */
 #define LFMM_FLAG_GRAPH 1
+/* options.flags: lfmm_execute / lfmm_execute_instances check the loads first (a reduction on
+ * the device and a read-back, so the call synchronises the stream): NaN or infinite loads
+ * give LFMM_E_INVAL with nothing launched, a non-zero total load LFMM_W_NONZERO_SUM. */
+#define LFMM_FLAG_CHECK_LOADS 2
 
 typedef struct lfmm_ctx lfmm_ctx;     /* device, phi table, per-leaf-side operator cache  */
 typedef struct lfmm_plan lfmm_plan;   /* one or more point sets (instances): sorted points,
@@ -98,6 +108,8 @@ typedef struct lfmm_plan_info {
     int64_t n_leaves;         /* non-empty leaves over all instances                       */
     int64_t near_pairs;       /* (target, source) pairs summed directly (Section 2)        */
     int64_t m2l_pairs;        /* (box, interaction-list box) pairs (Section 8.2, step 3)   */
+    int64_t device_bytes;     /* device memory the plan holds between executes             */
+    int64_t n_targets;        /* potentials one execute writes, over all instances         */
 } lfmm_plan_info;
 
 /* Fills *opt with the defaults listed above. */
@@ -111,28 +123,41 @@ lfmm_status lfmm_ctx_create(int32_t device, const lfmm_options* opt, lfmm_ctx** 
 lfmm_status lfmm_ctx_destroy(lfmm_ctx* ctx);
 
 /* Builds the tree of Section 6 (Morton keys, sort, levels, parent/child, neighbor and
- * interaction lists of Definition 6.1) for the n points xy_dev[2n] (device, int32), and the
- * operators for its leaf side if the context lacks them.  The points are copied; xy_dev may
- * be freed afterwards.  1 <= n <= 2^30.  The leaf level is the smallest at which no leaf
- * holds more than max_leaf points, raised where needed so that a leaf is at most 128 cells
- * wide (the dense-model outgoing operator of Remark 8.2 is tabulated up to that side). */
-lfmm_status lfmm_plan_create(lfmm_ctx* ctx, int64_t n, const int32_t* xy_dev, void* stream,
-                             lfmm_plan** out);
+ * interaction lists of Definition 6.1) and the operators for its leaf side if the context
+ * lacks them, for the n_src sources src_xy_dev[2 n_src] (device, int32) and:
+ *  - tgt_xy_dev == NULL: targets = sources (Section 8.1); n_tgt must be 0 or n_src;
+ *  - else the n_tgt targets tgt_xy_dev[2 n_tgt] (device, int32), 1 <= n_tgt: the potentials
+ *    are wanted there (Section 1).  The tree is built over the union of sources and targets
+ *    (a target carries no load), so a box holding targets gets its incoming expansion and its
+ *    near field like any other; targets may coincide with sources or with each other.
+ * The coordinates are copied; the buffers may be freed afterwards.  1 <= n_src and
+ * n_src + n_tgt <= 2^30.  The leaf level is the smallest at which no leaf holds more than
+ * max_leaf points, raised where needed so that a leaf is at most 128 cells wide (the
+ * dense-model outgoing operator of Remark 8.2 is tabulated up to that side). */
+lfmm_status lfmm_plan_create(lfmm_ctx* ctx, int64_t n_src, const int32_t* src_xy_dev, int64_t n_tgt,
+                             const int32_t* tgt_xy_dev, void* stream, lfmm_plan** out);
 
-/* Builds one plan over n_inst independent point sets (instances): instance k has
- * n_host[k] >= 1 points at xy_dev[k][2 n_host[k]] (device, int32; n_host and the pointer
- * array xy_dev are host memory).  Each instance gets its own root box and tree, exactly as
- * lfmm_plan_create would build it alone, so its potentials equal the ones of a plan of its
- * own bit for bit; all instances share every construction and evaluation launch.  At most
- * 2^30 points in total; LFMM_E_RANGE if the instance count and coordinate extents do not
- * fit the 64-bit sort key (2 * root bits + bits of n_inst - 1 <= 64). */
-lfmm_status lfmm_plan_create_batch(lfmm_ctx* ctx, int32_t n_inst, const int64_t* n_host,
-                                   const int32_t* const* xy_dev, void* stream, lfmm_plan** out);
+/* Builds one plan over n_inst independent problems (instances): instance k has
+ * n_src_host[k] >= 1 sources at src_xy_dev[k][2 n_src_host[k]] (device, int32) and, if
+ * tgt_xy_dev is not NULL and tgt_xy_dev[k] is not NULL, n_tgt_host[k] targets of its own at
+ * tgt_xy_dev[k] (else its targets are its sources).  The count and pointer arrays are host
+ * memory; n_tgt_host and tgt_xy_dev may be NULL together.  Each instance gets its own root
+ * box and tree, exactly as lfmm_plan_create would build it alone, so its potentials equal the
+ * ones of a plan of its own bit for bit; all instances share every construction and
+ * evaluation launch.  At most 2^30 points in total; LFMM_E_RANGE if the instance count and
+ * coordinate extents do not fit the 64-bit sort key (2 * root bits + bits of n_inst - 1 <=
+ * 64). */
+lfmm_status lfmm_plan_create_batch(lfmm_ctx* ctx, int32_t n_inst, const int64_t* n_src_host,
+                                   const int32_t* const* src_xy_dev, const int64_t* n_tgt_host,
+                                   const int32_t* const* tgt_xy_dev, void* stream, lfmm_plan** out);
 
-/* Evaluates u_dev[i] = sum_j phi(x_i - x_j) f_dev[j] over the plan's points (eq. 1.7) by the
- * passes of Section 8.2: P2M (T_ofs), M2M (T_ofo), M2L (T_ifo), L2L (T_ifi = T_ofo^T),
- * L2P (T_tfi = T_ofs^T) and the direct near field.  f_dev and u_dev are device float64
- * arrays of n entries in the caller's point order.  Enqueued on `stream`; no sync. */
+/* Evaluates u_dev[i] = sum_j phi(t_i - s_j) f_dev[j] for the plan's targets t_i and sources
+ * s_j (eq. 1.7) by the passes of Section 8.2: P2M (T_ofs), M2M (T_ofo), M2L (T_ifo), L2L
+ * (T_ifi = T_ofo^T), L2P (T_tfi = T_ofs^T) and the direct near field.  f_dev (n_src) and
+ * u_dev (n_tgt, or n_src when targets = sources) are device float64 arrays in the caller's
+ * order.  Enqueued on `stream`; no sync (unless LFMM_FLAG_CHECK_LOADS).  Executes of one
+ * plan share its expansion storage: the caller orders them (one stream, or events), and
+ * an execute on another stream than the plan was built on waits for the build. */
 lfmm_status lfmm_execute(lfmm_plan* plan, const double* f_dev, double* u_dev, void* stream);
 
 /* lfmm_execute for a plan of several instances: f_dev[k] and u_dev[k] (device arrays of
@@ -219,9 +244,15 @@ typedef enum lfmm_export_item {
  * otherwise *bytes must hold at least that size.  Waits for the device. */
 lfmm_status lfmm_plan_export(lfmm_plan* plan, int32_t item, void* host_out, size_t* bytes);
 
-/* Device bytes a plan for n points would hold (tree, lists, expansions, scratch), a bound
- * used for admission by memory footprint. */
-lfmm_status lfmm_plan_footprint_bytes(const lfmm_ctx* ctx, int64_t n, size_t* out);
+/* Bound on the device bytes a single-instance plan of n_src sources and n_tgt separate targets
+ * (0: targets = sources) holds while it is built (tree, lists, expansions, construction
+ * temporaries, each counted at the pool block that serves it), given the bits of its root
+ * box, root_bits = ceil(log2(coordinate extent)) in [0, 31], or -1 if unknown (the bound for
+ * any extent below 2^31).  Level l of a tree holds at most min(4^l, n) boxes, so the bound
+ * grows with root_bits for sparse point sets.  Used for admission by memory footprint; the
+ * bytes a built plan holds are lfmm_plan_info.device_bytes. */
+lfmm_status lfmm_plan_footprint_bytes(const lfmm_ctx* ctx, int64_t n_src, int64_t n_tgt, int32_t root_bits,
+                                      size_t* out);
 
 /* Frees a plan.  When every execute of the plan ran on the stream it was built on (and it
  * does not replay a HIP graph), this returns without waiting: the plan's device memory goes
@@ -229,7 +260,9 @@ lfmm_status lfmm_plan_footprint_bytes(const lfmm_ctx* ctx, int64_t n, size_t* ou
  * earlier executes are ordered on that stream as usual.  Otherwise it waits for the device. */
 lfmm_status lfmm_plan_destroy(lfmm_plan* plan);
 
-/* One-shot: plan, execute, destroy.  Synchronises the stream before returning. */
+/* One-shot: plan, execute, destroy, for targets = sources.  Checks the loads first (see
+ * LFMM_FLAG_CHECK_LOADS: LFMM_E_INVAL for NaN/Inf loads, LFMM_W_NONZERO_SUM for a non-zero
+ * total, with u_dev written).  Synchronises the stream before returning. */
 lfmm_status lfmm_solve(lfmm_ctx* ctx, int64_t n, const int32_t* xy_dev, const double* f_dev,
                        double* u_dev, void* stream);
 
@@ -255,8 +288,10 @@ const char* lfmm_last_error(void);
 typedef struct lfmm_server lfmm_server;
 
 typedef struct lfmm_server_options {
-    size_t hbm_budget_bytes;  /* bound on lfmm_plan_footprint_bytes summed over the requests
-                                 on the device; 0 = half of the device's free memory      */
+    size_t hbm_budget_bytes;  /* bound on lfmm_plan_footprint_bytes (with each request's own
+                                 root bits, measured on the device before admission) summed
+                                 over the requests on the device; 0 = half of the device's
+                                 free memory                                              */
     int32_t max_batch;        /* most requests admitted in one iteration; 0 = 256          */
     int32_t max_inflight;     /* iterations on the device at once (one stream each); 0 = 3 */
     int64_t max_batch_points; /* most points admitted in one iteration; 0 = 2^24           */
@@ -276,10 +311,13 @@ lfmm_status lfmm_server_create(lfmm_ctx* ctx, const lfmm_server_options* opt, lf
 
 /* Queues a solve of n points: xy_dev[2n] int32, f_dev[n] and u_dev[n] float64, all device
  * memory that the caller keeps valid and untouched until lfmm_server_wait reports the
- * request done.  Thread-safe.  *ticket identifies the request.  LFMM_E_NOMEM if the request
- * alone exceeds the memory budget. */
+ * request done.  producer_stream is the stream on which the caller wrote xy_dev and f_dev
+ * (NULL = the default stream): submit records an event there and the server reads the
+ * buffers only after it.  Thread-safe.  *ticket identifies the request.  A request whose
+ * footprint alone exceeds the memory budget finishes with LFMM_E_NOMEM. */
 lfmm_status lfmm_server_submit(lfmm_server* srv, int64_t n, const int32_t* xy_dev,
-                               const double* f_dev, double* u_dev, uint64_t* ticket);
+                               const double* f_dev, double* u_dev, void* producer_stream,
+                               uint64_t* ticket);
 
 /* Waits up to timeout_s seconds (< 0: without limit) for request `ticket`; fills *out when
  * it is done and forgets the ticket.  LFMM_E_BUSY if it is not done in time.  Returns the

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 from ._lib import (  # noqa: F401
     LfmmError,
+    LfmmWarning,
     Context,
     Plan,
     Server,
@@ -19,5 +20,5 @@ from ._lib import (  # noqa: F401
     PRECISIONS,
 )
 
-__all__ = ["LfmmError", "Context", "Plan", "Server", "HostOperators", "host_phi", "library_path",
+__all__ = ["LfmmError", "LfmmWarning", "Context", "Plan", "Server", "HostOperators", "host_phi", "library_path",
            "exported_symbols", "PRECISIONS"]

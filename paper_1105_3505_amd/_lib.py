@@ -4,6 +4,7 @@ from __future__ import annotations
 import ctypes
 import os
 import re
+import warnings
 import weakref
 
 import numpy as np
@@ -23,6 +24,14 @@ class LfmmError(RuntimeError):
         self.status = status
 
 
+class LfmmWarning(UserWarning):
+    """A call succeeded with a warning status (> 0), e.g. loads whose total is not zero."""
+
+    def __init__(self, status: int, detail: str):
+        super().__init__("lfmm status %d: %s" % (status, detail))
+        self.status = status
+
+
 class _Options(ctypes.Structure):
     _fields_ = [("eps", _dbl), ("max_leaf", _i32), ("precision", _i32), ("proxy_per_edge", _i32),
                 ("max_rank", _i32), ("flags", _i32)]
@@ -32,7 +41,7 @@ class _PlanInfo(ctypes.Structure):
     _fields_ = [("n_points", _i64), ("n_instances", _i32), ("root_bits", _i32), ("leaf_level", _i32),
                 ("leaf_side", _i64),
                 ("rank", _i32), ("leaf_kind", _i32), ("n_boxes", _i64), ("n_leaves", _i64),
-                ("near_pairs", _i64), ("m2l_pairs", _i64)]
+                ("near_pairs", _i64), ("m2l_pairs", _i64), ("device_bytes", _i64), ("n_targets", _i64)]
 
 
 class _ServerOptions(ctypes.Structure):
@@ -46,7 +55,9 @@ class _RequestStats(ctypes.Structure):
 
 
 STATUS_BUSY = -7
+STATUS_NONZERO_SUM = 1
 FLAG_GRAPH = 1
+FLAG_CHECK_LOADS = 2
 
 
 def library_path() -> str:
@@ -65,8 +76,8 @@ def _load():
         "lfmm_options_init": [_vp],
         "lfmm_ctx_create": [_i32, _vp, _vp],
         "lfmm_ctx_destroy": [_vp],
-        "lfmm_plan_create": [_vp, _i64, _vp, _vp, _vp],
-        "lfmm_plan_create_batch": [_vp, _i32, _vp, _vp, _vp, _vp],
+        "lfmm_plan_create": [_vp, _i64, _vp, _i64, _vp, _vp, _vp],
+        "lfmm_plan_create_batch": [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
         "lfmm_execute": [_vp, _vp, _vp, _vp],
         "lfmm_execute_instances": [_vp, _vp, _vp, _vp],
         "lfmm_execute_batch": [_vp, _i32, _vp, _vp, _vp, _vp],
@@ -76,7 +87,7 @@ def _load():
         "lfmm_plan_set_timing_phases": [_vp, ctypes.c_uint32],
         "lfmm_plan_export": [_vp, _i32, _vp, _vp],
         "lfmm_plan_phase_times": [_vp, _vp],
-        "lfmm_plan_footprint_bytes": [_vp, _i64, _vp],
+        "lfmm_plan_footprint_bytes": [_vp, _i64, _i64, _i32, _vp],
         "lfmm_plan_destroy": [_vp],
         "lfmm_solve": [_vp, _i64, _vp, _vp, _vp, _vp],
         "lfmm_direct": [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp],
@@ -88,7 +99,7 @@ def _load():
         "lfmm_host_opset_leaf": [_vp, _vp],
         "lfmm_host_opset_destroy": [_vp],
         "lfmm_server_create": [_vp, _vp, _vp],
-        "lfmm_server_submit": [_vp, _i64, _vp, _vp, _vp, _vp],
+        "lfmm_server_submit": [_vp, _i64, _vp, _vp, _vp, _vp, _vp],
         "lfmm_server_wait": [_vp, ctypes.c_uint64, _dbl, _vp],
         "lfmm_server_destroy": [_vp],
     }
@@ -106,11 +117,17 @@ def _load():
 _lib = _load()
 
 
-def _check(status: int) -> None:
+def _check(status: int) -> int:
+    """Raises LfmmError for an error status (< 0); a warning status (> 0) is issued as an
+    LfmmWarning and returned."""
     if status != 0:
         detail = (_lib.lfmm_last_error() or b"").decode(errors="replace")
         name = (_lib.lfmm_status_string(status) or b"").decode()
+        if status > 0:
+            warnings.warn(LfmmWarning(status, "%s: %s" % (name, detail)), stacklevel=3)
+            return status
         raise LfmmError(status, "%s: %s" % (name, detail))
+    return 0
 
 
 def exported_symbols() -> list[str]:
@@ -121,7 +138,7 @@ def exported_symbols() -> list[str]:
 
 
 def _options(eps=None, max_leaf=None, precision=None, proxy_per_edge=None, max_rank=None,
-             flags=None, graph=None) -> _Options:
+             flags=None, graph=None, check_loads=None) -> _Options:
     o = _Options()
     _check(_lib.lfmm_options_init(ctypes.byref(o)))
     if eps is not None:
@@ -138,6 +155,8 @@ def _options(eps=None, max_leaf=None, precision=None, proxy_per_edge=None, max_r
         o.flags = int(flags)
     if graph:
         o.flags |= FLAG_GRAPH
+    if check_loads:
+        o.flags |= FLAG_CHECK_LOADS
     return o
 
 
@@ -146,6 +165,26 @@ def _stream_handle(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _empty_on(stream, n, device):
+    """A float64 output of n entries that the library writes on `stream`: allocated on that
+    stream, so that torch's caching allocator orders its reuse after the write."""
+    import torch
+    if stream is None:
+        return torch.empty(n, dtype=torch.float64, device=device)
+    with torch.cuda.stream(stream):
+        return torch.empty(n, dtype=torch.float64, device=device)
+
+
+def _keep_for(stream, *tensors):
+    """Marks tensors the library reads or writes on a stream other than torch's current one,
+    so that the caching allocator does not hand their memory out before that stream is done."""
+    import torch
+    if stream is None or stream == torch.cuda.current_stream():
+        return
+    for t in tensors:
+        t.record_stream(stream)
 
 
 def _dev_tensor(t, dtype, shape_tail, name):
@@ -191,34 +230,55 @@ class Context:
         except Exception:
             pass
 
-    def plan(self, xy, stream=None) -> "Plan":
+    def plan(self, xy, targets=None, stream=None) -> "Plan":
+        """lfmm_plan_create over the sources xy [n, 2]; `targets` [m, 2] (optional) are the
+        points where the potentials are wanted (default: the sources)."""
         import torch
         ptr = _dev_tensor(xy, torch.int32, (2,), "xy")
+        nt, tp = 0, None
+        if targets is not None:
+            if int(targets.shape[0]) < 1:
+                raise ValueError("targets must hold at least one point (None: targets = sources)")
+            tp = _dev_tensor(targets, torch.int32, (2,), "targets")
+            nt = int(targets.shape[0])
         h = ctypes.c_void_p()
-        _check(_lib.lfmm_plan_create(self._h, int(xy.shape[0]), ptr, _stream_handle(stream), ctypes.byref(h)))
-        plan = Plan(self, h, [int(xy.shape[0])])
+        _check(_lib.lfmm_plan_create(self._h, int(xy.shape[0]), ptr, nt, tp, _stream_handle(stream),
+                                     ctypes.byref(h)))
+        plan = Plan(self, h, [int(xy.shape[0])], [nt if targets is not None else int(xy.shape[0])])
         self._plans.add(plan)
         return plan
 
-    def plan_batch(self, xys, stream=None) -> "Plan":
+    def plan_batch(self, xys, targets=None, stream=None) -> "Plan":
         """One plan over several point sets (lfmm_plan_create_batch): every pass is one
-        launch over all of them; each instance's result equals that of a plan of its own."""
+        launch over all of them; each instance's result equals that of a plan of its own.
+        targets: None, or a list with one entry per instance (None = its sources)."""
         import torch
         k = len(xys)
         ptrs = (ctypes.c_void_p * k)(*[_dev_tensor(xy, torch.int32, (2,), "xy").value for xy in xys])
         sizes = np.ascontiguousarray([int(xy.shape[0]) for xy in xys], dtype=np.int64)
+        tsz, tptrs = None, None
+        outs = [int(v) for v in sizes]
+        if targets is not None:
+            if len(targets) != k:
+                raise ValueError("one target entry per instance")
+            tsz = np.ascontiguousarray([0 if t is None else int(t.shape[0]) for t in targets], dtype=np.int64)
+            tptrs = (ctypes.c_void_p * k)(*[None if t is None else _dev_tensor(t, torch.int32, (2,), "targets").value
+                                            for t in targets])
+            outs = [o if t is None else int(t.shape[0]) for o, t in zip(outs, targets)]
         h = ctypes.c_void_p()
-        _check(_lib.lfmm_plan_create_batch(self._h, k, sizes.ctypes.data_as(_vp), ptrs, _stream_handle(stream),
-                                           ctypes.byref(h)))
-        plan = Plan(self, h, [int(v) for v in sizes])
+        _check(_lib.lfmm_plan_create_batch(self._h, k, sizes.ctypes.data_as(_vp), ptrs,
+                                           None if tsz is None else tsz.ctypes.data_as(_vp), tptrs,
+                                           _stream_handle(stream), ctypes.byref(h)))
+        plan = Plan(self, h, [int(v) for v in sizes], outs)
         self._plans.add(plan)
         return plan
 
     def solve(self, xy, f, u=None, stream=None):
+        """lfmm_solve (targets = sources).  A non-zero total load gives an LfmmWarning."""
         import torch
         n = int(xy.shape[0])
         if u is None:
-            u = torch.empty(n, dtype=torch.float64, device=f.device)
+            u = _empty_on(stream, n, f.device)
         _check(_lib.lfmm_solve(self._h, n, _dev_tensor(xy, torch.int32, (2,), "xy"),
                                _dev_tensor(f, torch.float64, (), "f"), _dev_tensor(u, torch.float64, (), "u"),
                                _stream_handle(stream)))
@@ -228,7 +288,7 @@ class Context:
         import torch
         nt, ns = int(txy.shape[0]), int(sxy.shape[0])
         if u is None:
-            u = torch.empty(nt, dtype=torch.float64, device=f.device)
+            u = _empty_on(stream, nt, f.device)
         _check(_lib.lfmm_direct(self._h, nt, _dev_tensor(txy, torch.int32, (2,), "txy"), ns,
                                 _dev_tensor(sxy, torch.int32, (2,), "sxy"), _dev_tensor(f, torch.float64, (), "f"),
                                 _dev_tensor(u, torch.float64, (), "u"), _stream_handle(stream)))
@@ -257,29 +317,37 @@ class Context:
                                   ctypes.byref(best), ms.ctypes.data_as(_vp)))
         return int(best.value), dict(zip([int(c) for c in cand], [float(v) for v in ms]))
 
-    def footprint_bytes(self, n: int) -> int:
+    def footprint_bytes(self, n_src: int, n_tgt: int = 0, root_bits: int = -1) -> int:
+        """lfmm_plan_footprint_bytes: bound on the device bytes of a plan (root_bits -1: any
+        extent below 2^31)."""
         out = ctypes.c_size_t()
-        _check(_lib.lfmm_plan_footprint_bytes(self._h, int(n), ctypes.byref(out)))
+        _check(_lib.lfmm_plan_footprint_bytes(self._h, int(n_src), int(n_tgt), int(root_bits), ctypes.byref(out)))
         return int(out.value)
 
 
 class Plan:
     """lfmm_plan: the trees of one or more point sets (instances), resident on the device."""
 
-    def __init__(self, ctx: Context, handle, sizes):
+    def __init__(self, ctx: Context, handle, sizes, out_sizes=None):
         self.ctx = ctx
         self._h = handle
-        self.sizes = list(sizes)
+        self.sizes = list(sizes)                    # sources per instance
+        self.out_sizes = list(out_sizes if out_sizes is not None else sizes)   # targets per instance
         self.n = sum(self.sizes)
+        self.n_out = sum(self.out_sizes)
 
     def execute(self, f, u=None, stream=None):
+        """lfmm_execute: f has one load per source, u one potential per target."""
         import torch
         if int(f.shape[0]) != self.n:
-            raise ValueError("f must have one load per point")
+            raise ValueError("f must have one load per source")
         if u is None:
-            u = torch.empty(self.n, dtype=torch.float64, device=f.device)
+            u = _empty_on(stream, self.n_out, f.device)
+        elif int(u.shape[0]) != self.n_out:
+            raise ValueError("u must have one entry per target")
         _check(_lib.lfmm_execute(self._h, _dev_tensor(f, torch.float64, (), "f"),
                                  _dev_tensor(u, torch.float64, (), "u"), _stream_handle(stream)))
+        _keep_for(stream, f, u)
         return u
 
     def execute_instances(self, fs, us=None, stream=None):
@@ -290,12 +358,16 @@ class Plan:
             raise ValueError("one load vector per instance")
         for f, n in zip(fs, self.sizes):
             if int(f.shape[0]) != n:
-                raise ValueError("f must have one load per point of its instance")
+                raise ValueError("f must have one load per source of its instance")
         if us is None:
-            us = [torch.empty(n, dtype=torch.float64, device=f.device) for f, n in zip(fs, self.sizes)]
+            us = [_empty_on(stream, n, f.device) for f, n in zip(fs, self.out_sizes)]
+        for u, n in zip(us, self.out_sizes):
+            if int(u.shape[0]) != n:
+                raise ValueError("u must have one entry per target of its instance")
         fp = (ctypes.c_void_p * k)(*[_dev_tensor(f, torch.float64, (), "f").value for f in fs])
         up = (ctypes.c_void_p * k)(*[_dev_tensor(u, torch.float64, (), "u").value for u in us])
         _check(_lib.lfmm_execute_instances(self._h, fp, up, _stream_handle(stream)))
+        _keep_for(stream, *fs, *us)
         return us
 
     PHASES = ("gather", "p2m", "m2m", "m2l", "l2l", "leaf")
@@ -424,7 +496,9 @@ class Server:
         self._held = {}          # ticket -> tensors the device reads or writes until done
         ctx._servers.add(self)
 
-    def submit(self, xy, f, u=None) -> int:
+    def submit(self, xy, f, u=None, stream=None) -> int:
+        """Queues a solve; `stream` (default: torch's current stream) is where xy and f were
+        written: the server reads them only after the work queued there so far."""
         import torch
         n = int(xy.shape[0])
         if int(f.shape[0]) != n:
@@ -434,7 +508,8 @@ class Server:
         t = ctypes.c_uint64()
         _check(_lib.lfmm_server_submit(self._h, n, _dev_tensor(xy, torch.int32, (2,), "xy"),
                                        _dev_tensor(f, torch.float64, (), "f"),
-                                       _dev_tensor(u, torch.float64, (), "u"), ctypes.byref(t)))
+                                       _dev_tensor(u, torch.float64, (), "u"), _stream_handle(stream),
+                                       ctypes.byref(t)))
         self._held[int(t.value)] = (xy, f, u)
         return int(t.value)
 

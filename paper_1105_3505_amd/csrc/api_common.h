@@ -24,6 +24,11 @@ OperatorParams operator_params(const lfmm_options& o);
 // Frees a plan whose device work is known to be complete (its last execute's completion
 // was observed), without the device-wide synchronisation of lfmm_plan_destroy.
 void plan_destroy_completed(lfmm_plan* plan);
+// Root-box bits D (smallest with 2^D >= coordinate extent; 32 when the extent exceeds 2^31)
+// of K point sets in device memory (n and xy host arrays), computed on the device; waits
+// for the stream.
+lfmm_status root_bits_of(lfmm_ctx* ctx, int32_t K, const int64_t* n, const int32_t* const* xy, void* stream,
+                         int32_t* bits);
 // Device of a context.
 int ctx_device(const lfmm_ctx* ctx);
 // Servers of a context, destroyed with it if still alive.

@@ -298,6 +298,7 @@ struct lfmm_plan {
     int32_t K = 0;                          // instances
     int64_t n = 0;                          // points of all instances
     std::vector<int32_t> pt_off;            // K + 1
+    std::vector<int32_t> nsrc, tgt0, nout;  // per instance: sources, first target, targets
     std::vector<InstInfo> inst;             // host copy of the instance table
     std::vector<CachedOps*> ops;            // operator sets used, by index
     int Dmax = 0, Lmax = 0, Hmax = 0;
@@ -327,6 +328,8 @@ struct lfmm_plan {
     NearGroup* groups = nullptr;
     int4* ents = nullptr;
     double *Q = nullptr, *U = nullptr;
+    float *Qh = nullptr, *Ql = nullptr;     // mixed precision: FP32 parts of Q (with its zero row)
+    double* qsum = nullptr;                 // and the charge sum of each row
     ExecPtrs* h_exec = nullptr;             // pinned staging of the per-execute pointers
     size_t h_exec_cls = 0;
     hipEvent_t exec_copied = nullptr;       // the last staging copy has been read
@@ -582,14 +585,52 @@ struct SyncOnUnwind {
     }
 };
 
+}  // namespace
+
+// One point set of a forest: its sources and, when tgt is not null, targets of its own.
+struct InstanceInput {
+    int64_t n_src = 0;
+    const int32_t* src = nullptr;
+    int64_t n_tgt = 0;
+    const int32_t* tgt = nullptr;   // null: the targets are the sources
+};
+
+namespace {
+
 // Builds the forest of K point sets: Section 6 tree of every instance, lists of Definition 6.1,
-// operator sets for every leaf side used, and the tiles of the matrix passes.
-void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t* const* xy_ptrs, int32_t max_leaf,
-                  hipStream_t st) {
+// operator sets for every leaf side used, and the tiles of the matrix passes.  An instance with
+// targets of its own gets one tree over the union of its sources and targets (its points are
+// the sources, then the targets): a target-only point carries a zero load, so the far and
+// near fields of the union are those of the sources, and the incoming expansion of any box
+// holding targets is evaluated at them by T_tfi = T_ofs^T of the dense model box, which
+// covers every cell of the box (Section 4.3, incoming skeleton; Remark 8.2).
+void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max_leaf, hipStream_t st) {
     lfmm_ctx* ctx = pl->ctx;
     pl->K = K;
     pl->pt_off.assign(size_t(K) + 1, 0);
-    for (int32_t k = 0; k < K; ++k) pl->pt_off[size_t(k) + 1] = pl->pt_off[size_t(k)] + int32_t(sizes[k]);
+    pl->nsrc.assign(size_t(K), 0);
+    pl->tgt0.assign(size_t(K), 0);
+    pl->nout.assign(size_t(K), 0);
+    // coordinate segments in point order: the sources of an instance, then its own targets
+    std::vector<const int32_t*> seg_ptr;
+    std::vector<int32_t> seg_off{0};
+    for (int32_t k = 0; k < K; ++k) {
+        const InstanceInput& I = in[k];
+        const int64_t nk = I.n_src + (I.tgt ? I.n_tgt : 0);
+        pl->pt_off[size_t(k) + 1] = pl->pt_off[size_t(k)] + int32_t(nk);
+        pl->nsrc[size_t(k)] = int32_t(I.n_src);
+        pl->tgt0[size_t(k)] = I.tgt ? int32_t(I.n_src) : 0;
+        pl->nout[size_t(k)] = I.tgt ? int32_t(I.n_tgt) : int32_t(I.n_src);
+        if (I.n_src > 0) {
+            seg_ptr.push_back(I.src);
+            seg_off.push_back(seg_off.back() + int32_t(I.n_src));
+        }
+        if (I.tgt && I.n_tgt > 0) {
+            seg_ptr.push_back(I.tgt);
+            seg_off.push_back(seg_off.back() + int32_t(I.n_tgt));
+        }
+    }
+    const int32_t nseg = int32_t(seg_ptr.size());
     const int64_t n = pl->pt_off[size_t(K)];
     pl->n = n;
 
@@ -606,7 +647,8 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
 
     // ---- temporaries sized by n (one reserve per take) ------------------------------------
     Arena tmp(&ctx->pool);
-    tmp.reserve(size_t(K) * sizeof(void*));     // xy table
+    tmp.reserve(size_t(nseg) * sizeof(void*));  // coordinate segments
+    tmp.reserve(size_t(nseg + 1) * 4);          // segment offsets
     tmp.reserve(size_t(K + 1) * 4);             // pt_off
     tmp.reserve(size_t(nch) * sizeof(Chunk));
     tmp.reserve(size_t(K + 1) * 4);             // chunk_first
@@ -614,7 +656,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     tmp.reserve(size_t(K) * sizeof(InstInfo));  // instances up to the level statistics
     tmp.reserve(size_t(K) * (kMaxLevels + 3) * 4 + 4);   // level histograms, look-ahead maxima, counter
     tmp.reserve(4);                             // deepest root box
-    tmp.reserve(K > 1 ? size_t(n) * 8 : 0);     // concatenated points
+    tmp.reserve(nseg > 1 ? size_t(n) * 8 : 0);  // concatenated points
     tmp.reserve(size_t(n) * 8);                 // keys
     tmp.reserve(size_t(n) * 8);                 // keys_tmp
     tmp.reserve(size_t(n) * 4);                 // vals
@@ -624,7 +666,8 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     tmp.reserve(scan_scratch_bytes(n, 1));
     tmp.allocate();
     SyncOnUnwind unwind_tmp;
-    const int32_t** d_xytab = tmp.take<const int32_t*>(K);
+    const int32_t** d_xytab = tmp.take<const int32_t*>(nseg);
+    int32_t* d_segoff = tmp.take<int32_t>(nseg + 1);
     int32_t* d_ptoff = tmp.take<int32_t>(K + 1);
     Chunk* d_chunks = tmp.take<Chunk>(nch);
     int32_t* d_chfirst = tmp.take<int32_t>(K + 1);
@@ -645,7 +688,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     } rb_guard{ctx, rb, rb_cls};
     int32_t* bb = rb;                      // [K][4] root boxes
     int32_t* stats = rb + size_t(K) * 4;   // [K][34] histograms, then [K] maxima
-    int32_t* d_xyc = (K > 1) ? tmp.take<int32_t>(size_t(n) * 2) : nullptr;
+    int32_t* d_xyc = (nseg > 1) ? tmp.take<int32_t>(size_t(n) * 2) : nullptr;
     uint64_t* keys = tmp.take<uint64_t>(n);
     uint64_t* keys_tmp = tmp.take<uint64_t>(n);
     uint32_t* vals = tmp.take<uint32_t>(n);
@@ -654,16 +697,16 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     void* rscr = tmp.take<char>(radix_scratch_bytes(n));
     void* sscr = tmp.take<char>(scan_scratch_bytes(n, 1));
 
-    std::vector<const int32_t*> xytab(xy_ptrs, xy_ptrs + K);
     Stager stage_a(ctx);
-    stage_a.add(d_xytab, xytab);
+    stage_a.add(d_xytab, seg_ptr);
+    stage_a.add(d_segoff, seg_off);
     stage_a.add(d_ptoff, pl->pt_off);
     stage_a.add(d_chunks, chunks);
     stage_a.add(d_chfirst, chunk_first);
     stage_a.flush(st);
-    const int32_t* xy = xy_ptrs[0];
-    if (K > 1) {
-        launch_concat(K, d_xytab, d_ptoff, n, d_xyc, st);
+    const int32_t* xy = seg_ptr[0];
+    if (nseg > 1) {
+        launch_concat(nseg, d_xytab, d_segoff, n, d_xyc, st);
         xy = d_xyc;
     }
 
@@ -940,6 +983,12 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     mb.reserve(size_t(std::max(pl->nq, 1)) * sizeof(NearGroup));
     mb.reserve(size_t(std::max(pl->nq, 1)) * kNearEntries * sizeof(int4));
     mb.reserve(size_t(nb + 1) * P * 8);                  // U and its zero row
+    const bool mixed = ctx->opt.precision == LFMM_MIXED;
+    if (mixed) {
+        mb.reserve(size_t(nb + 1) * P * 4);              // Q hi
+        mb.reserve(size_t(nb + 1) * P * 4);              // Q lo
+        mb.reserve(size_t(nb + 1) * 8);                  // charge sums
+    }
     mb.allocate();
     pl->box_key = mb.take<uint64_t>(nb);
     pl->box_pt0 = mb.take<int32_t>(nb);
@@ -957,6 +1006,11 @@ void build_forest(lfmm_plan* pl, int32_t K, const int64_t* sizes, const int32_t*
     pl->U = mb.take<double>(size_t(nb + 1) * P);
     pl->groups = mb.take<NearGroup>(size_t(std::max(pl->nq, 1)));
     pl->ents = mb.take<int4>(size_t(std::max(pl->nq, 1)) * kNearEntries);
+    if (mixed) {
+        pl->Qh = mb.take<float>(size_t(nb + 1) * P);
+        pl->Ql = mb.take<float>(size_t(nb + 1) * P);
+        pl->qsum = mb.take<double>(size_t(nb + 1));
+    }
 
     // ---- tables ---------------------------------------------------------------------------------
     Stager stage_c(ctx);
@@ -1046,7 +1100,7 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
     for (size_t o = 0; o < pl->ops.size(); ++o) {
         const TileRange& r = pl->leaf_of_ops[o];
         launch_p2m(r.t0, r.t0 + r.n, pl->box_pt0, pl->box_pt1, pl->box_key, pl->ops[o]->dev.leaf_side, pl->pts, tab,
-                   f1, pl->perm, pl->pinst, pl->fs, pl->ops[o]->dev.leafT, pl->Q, st);
+                   f1, pl->nsrc[0], pl->perm, pl->pinst, pl->fs, pl->ops[o]->dev.leafT, pl->Q, st);
     }
     mark(2);
     for (int h = 1; h <= pl->Hmax; ++h) {
@@ -1055,9 +1109,11 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
     }
     mark(3);
     if (pl->m2l.n > 0) {
-        if (mixed)
+        if (mixed) {
+            launch_split_q(pl->Q, pl->nbox + 1, pl->Qh, pl->Ql, pl->qsum, st);
             launch_m2l_mixed(pl->tiles + pl->m2l.t0, pl->d_m2l_ntiles, pl->m2l.n, pl->cls_box, pl->il27, pl->d_ops,
-                             pl->Q, pl->nbox, pl->U, st);
+                             pl->Qh, pl->Ql, pl->qsum, pl->nbox, pl->U, st);
+        }
         else
             launch_m2l(pl->tiles + pl->m2l.t0, pl->m2l.n, pl->cls_box, pl->il27, pl->d_ops, pl->Q, pl->nbox, pl->U, st);
     }
@@ -1070,7 +1126,7 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
     for (size_t o = 0; o < pl->ops.size(); ++o) {
         const TileRange& r = pl->near_of_ops[o];
         launch_near(r.t0, r.t0 + r.n, pl->groups, pl->ents, pl->box_pt0, pl->box_pt1, pl->box_key, pl->box_inst,
-                    pl->ops[o]->dev.leaf_side, pl->pts, pl->pkey, pl->fs, pl->perm, tab, u1, pl->U,
+                    pl->ops[o]->dev.leaf_side, pl->pts, pl->pkey, pl->fs, pl->perm, tab, u1, pl->tgt0[0], pl->U,
                     pl->ops[o]->dev.leafT, pl->d_far, pl->ctx->phi_oct, st);
     }
     mark(6);
@@ -1088,7 +1144,7 @@ void run_forest(lfmm_plan* pl, const double* const* f, double* const* u, hipStre
     }
     // the previous execute's copy must have read the staging buffer before it is rewritten
     LFMM_HIP(hipEventSynchronize(pl->exec_copied));
-    for (int32_t k = 0; k < pl->K; ++k) pl->h_exec[k] = ExecPtrs{f[k], u[k]};
+    for (int32_t k = 0; k < pl->K; ++k) pl->h_exec[k] = ExecPtrs{f[k], u[k], pl->nsrc[size_t(k)], pl->tgt0[size_t(k)]};
     launch_upload(pl->d_exec, pl->h_exec, size_t(pl->K) * sizeof(ExecPtrs), st);
     LFMM_HIP(hipEventRecord(pl->exec_copied, st));
     if (!pl->use_graph) {
@@ -1119,6 +1175,7 @@ void run_forest(lfmm_plan* pl, const double* const* f, double* const* u, hipStre
 }  // namespace
 
 void lfmm::plan_destroy_completed(lfmm_plan* pl) { delete pl; }
+
 
 int lfmm::ctx_device(const lfmm_ctx* ctx) { return ctx->device; }
 
@@ -1154,21 +1211,26 @@ lfmm_status guarded(F&& f) {
     }
 }
 
-lfmm_status create_forest(lfmm_ctx* ctx, int32_t K, const int64_t* sizes, const int32_t* const* xy, int32_t max_leaf,
-                          void* stream, lfmm_plan** out) {
-    if (!ctx || !out || !sizes || !xy || K < 1) return fail(LFMM_E_INVAL, "null argument or no instance");
+lfmm_status create_forest(lfmm_ctx* ctx, int32_t K, const InstanceInput* in, int32_t max_leaf, void* stream,
+                          lfmm_plan** out) {
+    if (!ctx || !out || !in || K < 1) return fail(LFMM_E_INVAL, "null argument or no instance");
     *out = nullptr;
     int64_t total = 0;
     for (int32_t k = 0; k < K; ++k) {
-        if (sizes[k] < 1 || !xy[k]) return fail(LFMM_E_INVAL, "every instance needs n >= 1 and coordinates");
-        total += sizes[k];
+        if (in[k].n_src < 1 || in[k].n_src > (int64_t(1) << 30) || !in[k].src)
+            return fail(LFMM_E_INVAL, "every instance needs 1 <= n_src <= 2^30 and source coordinates");
+        if (in[k].tgt && (in[k].n_tgt < 1 || in[k].n_tgt > (int64_t(1) << 30)))
+            return fail(LFMM_E_INVAL, "an instance with target coordinates needs 1 <= n_tgt <= 2^30");
+        if (!in[k].tgt && in[k].n_tgt != 0 && in[k].n_tgt != in[k].n_src)
+            return fail(LFMM_E_INVAL, "without target coordinates n_tgt must be 0 or n_src (targets = sources)");
+        total += in[k].n_src + (in[k].tgt ? in[k].n_tgt : 0);
     }
     if (total > (int64_t(1) << 30)) return fail(LFMM_E_INVAL, "more than 2^30 points in one plan");
     return guarded([&]() -> lfmm_status {
         LFMM_HIP(hipSetDevice(ctx->device));
         auto pl = std::make_unique<lfmm_plan>();
         pl->ctx = ctx;
-        build_forest(pl.get(), K, sizes, xy, max_leaf, as_stream(stream));
+        build_forest(pl.get(), K, in, max_leaf, as_stream(stream));
         {
             std::lock_guard<std::mutex> lock(ctx->reg_mu);
             ctx->plans.insert(pl.get());
@@ -1178,21 +1240,82 @@ lfmm_status create_forest(lfmm_ctx* ctx, int32_t K, const int64_t* sizes, const 
     });
 }
 
-lfmm_status execute_forest(lfmm_plan* pl, const double* const* f, double* const* u, void* stream) {
+// Checks of the loads of K instances (f[k] holds nsrc[k] values) before any pass: a NaN or
+// infinite load is an invalid input (LFMM_E_INVAL); a total load that is not zero (|sum f| >
+// 1e-12 sum |f|, the well-posedness condition of Section 1) is reported as LFMM_W_NONZERO_SUM,
+// and the finite sum is still computed.  Synchronises the stream (the statistics are read
+// back).  Runs inside guarded().
+lfmm_status check_loads(lfmm_ctx* ctx, int32_t K, const double* const* f, const int32_t* nsrc, hipStream_t st) {
+    Arena a(&ctx->pool);
+    a.reserve(load_stats_scratch_bytes());
+    a.reserve(size_t(K) * 3 * sizeof(double));
+    a.allocate();
+    double* scr = a.take<double>(load_stats_scratch_bytes() / sizeof(double));
+    double* out = a.take<double>(size_t(K) * 3);
+    for (int32_t k = 0; k < K; ++k) launch_load_stats(f[k], nsrc[k], scr, out + 3 * size_t(k), st);
+    LFMM_HIP(hipGetLastError());
+    std::vector<double> h(size_t(K) * 3);
+    LFMM_HIP(hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    LFMM_HIP(hipStreamSynchronize(st));
+    a.release();
+    lfmm_status res = LFMM_OK;
+    for (int32_t k = 0; k < K; ++k) {
+        const double sum = h[3 * size_t(k)], mag = h[3 * size_t(k) + 1], bad = h[3 * size_t(k) + 2];
+        if (bad > 0.0)
+            return fail(LFMM_E_INVAL, "loads of instance " + std::to_string(k) + " hold " +
+                                          std::to_string(int64_t(bad)) + " non-finite values");
+        if (res == LFMM_OK && std::fabs(sum) > 1e-12 * mag)
+            res = fail(LFMM_W_NONZERO_SUM, "total load of instance " + std::to_string(k) + " is " +
+                                               std::to_string(sum) + ", not zero");
+    }
+    return res;
+}
+
+lfmm_status execute_forest(lfmm_plan* pl, const double* const* f, double* const* u, void* stream, bool check) {
     if (pl->failed) return fail(LFMM_E_HIP, "plan is in a failed state");
     return guarded([&]() -> lfmm_status {
         LFMM_HIP(hipSetDevice(pl->ctx->device));
+        lfmm_status res = LFMM_OK;
+        if (check || (pl->ctx->opt.flags & LFMM_FLAG_CHECK_LOADS)) {
+            res = check_loads(pl->ctx, pl->K, f, pl->nsrc.data(), as_stream(stream));
+            if (res < 0) return res;
+        }
         run_forest(pl, f, u, as_stream(stream));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
             pl->failed = true;
             throw HipFailure(std::string("kernel launch: ") + hipGetErrorString(e));
         }
-        return LFMM_OK;
+        return res;
     });
 }
 
 }  // namespace
+
+lfmm_status lfmm::root_bits_of(lfmm_ctx* ctx, int32_t K, const int64_t* n, const int32_t* const* xy, void* stream,
+                               int32_t* bits) {
+    if (!ctx || K < 1 || !n || !xy || !bits) return fail(LFMM_E_INVAL, "null argument");
+    return guarded([&]() -> lfmm_status {
+        LFMM_HIP(hipSetDevice(ctx->device));
+        hipStream_t st = as_stream(stream);
+        Arena a(&ctx->pool);
+        a.reserve(size_t(K) * 16);
+        a.allocate();
+        int32_t* box = a.take<int32_t>(size_t(K) * 4);
+        launch_extents(K, n, xy, box, st);
+        LFMM_HIP(hipGetLastError());
+        std::vector<int32_t> h(size_t(K) * 4);
+        LFMM_HIP(hipMemcpyAsync(h.data(), box, h.size() * 4, hipMemcpyDeviceToHost, st));
+        LFMM_HIP(hipStreamSynchronize(st));
+        a.release();
+        for (int32_t k = 0; k < K; ++k) {
+            const int64_t ext = std::max(int64_t(h[4 * size_t(k) + 2]) - h[4 * size_t(k)],
+                                         int64_t(h[4 * size_t(k) + 3]) - h[4 * size_t(k) + 1]) + 1;
+            bits[k] = ext > (int64_t(1) << 31) ? 32 : bits_for_extent(ext);
+        }
+        return LFMM_OK;
+    });
+}
 
 extern "C" {
 
@@ -1253,17 +1376,31 @@ lfmm_status lfmm_ctx_destroy(lfmm_ctx* ctx) {
     return LFMM_OK;
 }
 
-lfmm_status lfmm_plan_create(lfmm_ctx* ctx, int64_t n, const int32_t* xy, void* stream, lfmm_plan** out) {
-    if (!ctx || !out || !xy) return fail(LFMM_E_INVAL, "null argument");
-    if (n < 1 || n > (int64_t(1) << 30)) return fail(LFMM_E_INVAL, "n must lie in [1, 2^30]");
-    const int64_t sizes[1] = {n};
-    const int32_t* ptrs[1] = {xy};
-    return create_forest(ctx, 1, sizes, ptrs, 0, stream, out);
+lfmm_status lfmm_plan_create(lfmm_ctx* ctx, int64_t n_src, const int32_t* src_xy, int64_t n_tgt,
+                             const int32_t* tgt_xy, void* stream, lfmm_plan** out) {
+    if (!ctx || !out || !src_xy) return fail(LFMM_E_INVAL, "null argument");
+    InstanceInput in;
+    in.n_src = n_src;
+    in.src = src_xy;
+    in.n_tgt = n_tgt;
+    in.tgt = tgt_xy;
+    return create_forest(ctx, 1, &in, 0, stream, out);
 }
 
-lfmm_status lfmm_plan_create_batch(lfmm_ctx* ctx, int32_t n_inst, const int64_t* n_host,
-                                   const int32_t* const* xy_dev, void* stream, lfmm_plan** out) {
-    return create_forest(ctx, n_inst, n_host, xy_dev, 0, stream, out);
+lfmm_status lfmm_plan_create_batch(lfmm_ctx* ctx, int32_t n_inst, const int64_t* n_src_host,
+                                   const int32_t* const* src_xy_dev, const int64_t* n_tgt_host,
+                                   const int32_t* const* tgt_xy_dev, void* stream, lfmm_plan** out) {
+    if (!ctx || !out || !n_src_host || !src_xy_dev || n_inst < 1)
+        return fail(LFMM_E_INVAL, "null argument or no instance");
+    if (tgt_xy_dev && !n_tgt_host) return fail(LFMM_E_INVAL, "target coordinates without target counts");
+    std::vector<InstanceInput> in(static_cast<size_t>(n_inst));
+    for (int32_t k = 0; k < n_inst; ++k) {
+        in[size_t(k)].n_src = n_src_host[k];
+        in[size_t(k)].src = src_xy_dev[k];
+        in[size_t(k)].n_tgt = n_tgt_host ? n_tgt_host[k] : 0;
+        in[size_t(k)].tgt = tgt_xy_dev ? tgt_xy_dev[k] : nullptr;
+    }
+    return create_forest(ctx, n_inst, in.data(), 0, stream, out);
 }
 
 lfmm_status lfmm_autotune(lfmm_ctx* ctx, int64_t n, const int32_t* xy, int32_t n_cand, const int32_t* cand,
@@ -1293,8 +1430,9 @@ lfmm_status lfmm_autotune(lfmm_ctx* ctx, int64_t n, const int32_t* xy, int32_t n
                 (void)hipEventDestroy(b);
             }
         } guard{e0, e1};
-        const int64_t sizes[1] = {n};
-        const int32_t* ptrs[1] = {xy};
+        InstanceInput one;
+        one.n_src = n;
+        one.src = xy;
         double best_ms = 0.0;
         int D = 0;
         for (int32_t c = 0; c < n_cand; ++c) {
@@ -1304,7 +1442,7 @@ lfmm_status lfmm_autotune(lfmm_ctx* ctx, int64_t n, const int32_t* xy, int32_t n
                 const auto t0 = std::chrono::steady_clock::now();
                 auto pl = std::make_unique<lfmm_plan>();
                 pl->ctx = ctx;
-                build_forest(pl.get(), 1, sizes, ptrs, cand[c], st);
+                build_forest(pl.get(), 1, &one, cand[c], st);
                 const double build_ms =
                     std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
                 D = pl->inst[0].D;
@@ -1339,25 +1477,27 @@ lfmm_status lfmm_execute(lfmm_plan* pl, const double* f, double* u, void* stream
     if (pl->K != 1) return fail(LFMM_E_INVAL, "plan holds several instances: use lfmm_execute_instances");
     const double* fa[1] = {f};
     double* ua[1] = {u};
-    return execute_forest(pl, fa, ua, stream);
+    return execute_forest(pl, fa, ua, stream, false);
 }
 
 lfmm_status lfmm_execute_instances(lfmm_plan* pl, const double* const* f, double* const* u, void* stream) {
     if (!pl || !f || !u) return fail(LFMM_E_INVAL, "null argument");
     for (int32_t k = 0; k < pl->K; ++k)
         if (!f[k] || !u[k]) return fail(LFMM_E_INVAL, "null load or potential pointer");
-    return execute_forest(pl, f, u, stream);
+    return execute_forest(pl, f, u, stream, false);
 }
 
 lfmm_status lfmm_execute_batch(lfmm_ctx* ctx, int32_t n_plans, lfmm_plan* const* plans, const double* const* f,
                                double* const* u, void* stream) {
     if (!ctx || n_plans < 0 || (n_plans > 0 && (!plans || !f || !u))) return fail(LFMM_E_INVAL, "null argument");
+    lfmm_status res = LFMM_OK;
     for (int32_t k = 0; k < n_plans; ++k) {
         if (!plans[k] || plans[k]->ctx != ctx) return fail(LFMM_E_INVAL, "plan of another context");
         lfmm_status s = lfmm_execute(plans[k], f[k], u[k], stream);
-        if (s != LFMM_OK) return s;
+        if (s < 0) return s;
+        if (s != LFMM_OK) res = s;
     }
-    return LFMM_OK;
+    return res;
 }
 
 lfmm_status lfmm_plan_get_info(lfmm_plan* pl, lfmm_plan_info* out) {
@@ -1398,6 +1538,10 @@ lfmm_status lfmm_plan_get_info(lfmm_plan* pl, lfmm_plan_info* out) {
                 for (int k = 0; k < kNumInteractions; ++k) m2l += (il[g * kNumInteractions + k] >= 0);
         out->near_pairs = near;
         out->m2l_pairs = m2l;
+        out->device_bytes = int64_t(pl->mem_small.bytes() + pl->mem_pts.bytes() + pl->mem_box.bytes());
+        int64_t nt = 0;
+        for (int32_t k = 0; k < pl->K; ++k) nt += pl->nout[size_t(k)];
+        out->n_targets = nt;
         return LFMM_OK;
     });
 }
@@ -1488,15 +1632,41 @@ lfmm_status lfmm_plan_phase_times(lfmm_plan* pl, double* ms) {
     });
 }
 
-lfmm_status lfmm_plan_footprint_bytes(const lfmm_ctx* ctx, int64_t n, size_t* out) {
-    if (!ctx || !out || n < 0) return fail(LFMM_E_INVAL, "bad argument");
-    // boxes <= 4/3 of the leaves, leaves <= points; per box: Q, U, keys, links and lists;
-    // per point: coordinates, indices, keys and loads; plus the construction temporaries
-    const size_t nb = size_t(2 * n + 64);
-    const size_t per_box = size_t(kRankPad) * 16 + 8 + 4 * 6 + 1 + 16 + 36 + 4 * kNumInteractions + 4 * 8;
-    const size_t per_point = 8 + 4 * 3 + 8;
-    const size_t tmp = size_t(n) * (8 + 16 + 8 + 1 + 8) + radix_scratch_bytes(n) + scan_scratch_bytes(n, 1);
-    *out = nb * per_box + size_t(n) * per_point + tmp + (size_t(1) << 20);
+lfmm_status lfmm_plan_footprint_bytes(const lfmm_ctx* ctx, int64_t n_src, int64_t n_tgt, int32_t root_bits,
+                                      size_t* out) {
+    if (!ctx || !out || n_src < 0 || n_tgt < 0 || root_bits < -1 || root_bits > 31)
+        return fail(LFMM_E_INVAL, "bad argument");
+    // Bound on the device memory one single-instance plan holds, construction temporaries
+    // included, each arena counted at the pool block that serves it (a power of two of at
+    // least 64 KiB, so at most twice its size plus 64 KiB).  Level l of the tree holds at most
+    // min(4^l, n) boxes and the leaves lie at a level <= D, the root box's bits.
+    const int D = root_bits < 0 ? 31 : root_bits;
+    const int64_t n = n_src + n_tgt;
+    size_t nb = 0;
+    for (int l = 0; l <= D; ++l) nb += size_t(std::min<int64_t>(l < 31 ? int64_t(1) << (2 * l) : n, n));
+    const size_t nl = size_t(std::min<int64_t>(n, int64_t(nb)));
+    const size_t P = kRankPad, al = 256;
+    auto block = [](size_t b) { return 2 * b + (size_t(1) << 16); };
+    // points: coordinates, permutation, instance, window key, loads
+    const size_t pts = size_t(n) * 28 + 5 * al;
+    // boxes: key, four int32 fields and a pad, level, children, neighbour and interaction lists,
+    // class lists (M2L and L2L groups, four slots per box each), tiles, Q and U with their zero
+    // rows, near-field groups and their 16 entries
+    const size_t tiles = nb / 32 + 8 * size_t(D + 2);
+    const size_t mixed = ctx->opt.precision == LFMM_MIXED ? (nb + 1) * (P * 8 + 8) + 3 * al : 0;
+    const size_t box = nb * (8 + 20 + 1 + 16 + 36 + 4 * kNumInteractions + 32) + tiles * sizeof(BoxTile) +
+                       2 * (nb + 1) * P * 8 + nl * (sizeof(NearGroup) + kNearEntries * 16) + 14 * al + mixed;
+    const size_t small = sizeof(InstInfo) + 64 * sizeof(OpsPtrs) + 16 + 4 * size_t(D + 2) * sizeof(BoxGroup) +
+                         (nb / 64 + size_t(D + 2)) * sizeof(BoxTile) + sizeof(ExecPtrs) + 16 * al;
+    // construction temporaries: concatenated points, keys and indices (two copies), common
+    // levels, sort and scan scratch; then per leaf: first point, key, level, instance and one
+    // scan row per level; per box: class scans
+    const size_t tmp = size_t(n) * (8 + 16 + 8 + 1) + radix_scratch_bytes(n) + scan_scratch_bytes(n, 1) +
+                       (kMaxLevels + 10) * 4 * 4 + 24 * al;
+    const size_t rows = size_t(std::max(D, 1));
+    const size_t tmp2 = nl * (4 + 8 + 1 + 4 + 4 * rows) + scan_scratch_bytes(int64_t(nl), int(rows)) + nb * 16 + 64 +
+                        scan_scratch_bytes(int64_t(nb), 4) + 10 * al;
+    *out = block(pts) + block(box) + block(small) + block(tmp) + block(tmp2);
     return LFMM_OK;
 }
 
@@ -1529,13 +1699,18 @@ lfmm_status lfmm_plan_destroy(lfmm_plan* pl) {
 }
 
 lfmm_status lfmm_solve(lfmm_ctx* ctx, int64_t n, const int32_t* xy, const double* f, double* u, void* stream) {
+    if (!ctx || !xy || !f || !u) return fail(LFMM_E_INVAL, "null argument");
     lfmm_plan* pl = nullptr;
-    lfmm_status s = lfmm_plan_create(ctx, n, xy, stream, &pl);
+    lfmm_status s = lfmm_plan_create(ctx, n, xy, 0, nullptr, stream, &pl);
     if (s != LFMM_OK) return s;
-    s = lfmm_execute(pl, f, u, stream);
-    if (s == LFMM_OK) {
+    const double* fa[1] = {f};
+    double* ua[1] = {u};
+    s = execute_forest(pl, fa, ua, stream, true);
+    if (s >= 0) {
+        const std::string warn = g_last_error;
         hipError_t e = hipStreamSynchronize(as_stream(stream));
         if (e != hipSuccess) s = fail(LFMM_E_HIP, hipGetErrorString(e));
+        else if (s != LFMM_OK) g_last_error = warn;
     }
     lfmm_plan_destroy(pl);
     return s;

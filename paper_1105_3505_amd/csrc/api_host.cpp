@@ -27,7 +27,7 @@ lfmm_status validate_options(const lfmm_options* o) {
         return fail(LFMM_E_INVAL, "proxy_per_edge must lie in [8, 4096]");
     if (o->max_rank < 16 || o->max_rank > kMaxRank || o->max_rank % 16 != 0)
         return fail(LFMM_E_INVAL, "max_rank must be 16, 32, 48 or 64");
-    if (o->flags & ~LFMM_FLAG_GRAPH) return fail(LFMM_E_INVAL, "unknown bits in options.flags");
+    if (o->flags & ~(LFMM_FLAG_GRAPH | LFMM_FLAG_CHECK_LOADS)) return fail(LFMM_E_INVAL, "unknown bits in options.flags");
     return LFMM_OK;
 }
 
@@ -64,6 +64,7 @@ lfmm_status lfmm_options_init(lfmm_options* opt) {
 const char* lfmm_status_string(lfmm_status s) {
     switch (s) {
         case LFMM_OK: return "ok";
+        case LFMM_W_NONZERO_SUM: return "warning: total load not zero";
         case LFMM_E_INVAL: return "invalid argument";
         case LFMM_E_RANGE: return "out of range";
         case LFMM_E_NOMEM: return "out of memory";

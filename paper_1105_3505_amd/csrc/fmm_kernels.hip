@@ -90,11 +90,19 @@ inline unsigned grid_for(int64_t n, int per_block = kBlock) {
 }
 
 // Load of sorted point s in the caller's order (instance-local index perm_local[s] of
-// instance pinst[s]), also stored at fs[s] for the near field: P2M visits every point once.
-__device__ inline double gather_f(const ExecPtrs* tab, const double* f_single, const int32_t* perm_local,
-                                  const int32_t* pinst, int64_t s, double* fs) {
-    const double* f = tab ? tab[pinst[s]].f : f_single;
-    const double v = f[perm_local[s]];
+// instance pinst[s]; zero for a point that is a target only), also stored at fs[s] for the
+// near field: P2M visits every point once.
+__device__ inline double gather_f(const ExecPtrs* tab, const double* f_single, int32_t nsrc_single,
+                                  const int32_t* perm_local, const int32_t* pinst, int64_t s, double* fs) {
+    const double* f = f_single;
+    int32_t nsrc = nsrc_single;
+    if (tab) {
+        const ExecPtrs& e = tab[pinst[s]];
+        f = e.f;
+        nsrc = e.nsrc;
+    }
+    const int32_t j = perm_local[s];
+    const double v = j < nsrc ? f[j] : 0.0;
     fs[s] = v;
     return v;
 }
@@ -108,8 +116,8 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void k_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0,
                                                  const int32_t* box_pt1, const uint64_t* box_key, int64_t side,
                                                  const int2* pts, const ExecPtrs* tab, const double* f_single,
-                                                 const int32_t* perm_local, const int32_t* pinst, double* fs,
-                                                 const double* leafT, double* Q) {
+                                                 int32_t nsrc_single, const int32_t* perm_local, const int32_t* pinst,
+                                                 double* fs, const double* leafT, double* Q) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int32_t g = leaf0 + int32_t(blockIdx.x) * kWaves + wave;
     if (g >= leaf1) return;
@@ -125,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void k_p2m(int32_t leaf0, int32_t leaf1, co
         if (j < p1) {
             const int2 q = pts[j];
             loc = int32_t(int64_t(q.x - cx) + side * int64_t(q.y - cy));
-            f = gather_f(tab, f_single, perm_local, pinst, j, fs);
+            f = gather_f(tab, f_single, nsrc_single, perm_local, pinst, j, fs);
         }
         const int cnt = min(64, p1 - c0);
         for (int k = 0; k < cnt; k += 4) {   // k + 3 < 64: the tail reads the zero-load lanes
@@ -156,8 +164,9 @@ template <int P>
 __global__ __launch_bounds__(kP2mThreads) void k_p2m_lds(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0,
                                                         const int32_t* box_pt1, const uint64_t* box_key, int64_t side,
                                                         const int2* pts, const ExecPtrs* tab, const double* f_single,
-                                                        const int32_t* perm_local, const int32_t* pinst, double* fs,
-                                                        const double* leafT, double* Q) {
+                                                        int32_t nsrc_single, const int32_t* perm_local,
+                                                        const int32_t* pinst, double* fs, const double* leafT,
+                                                        double* Q) {
     constexpr int R = P / kP2mGroup;   // rows per lane
     static_assert(P % kP2mGroup == 0, "rows split evenly over a group");
     extern __shared__ double sT[];
@@ -204,7 +213,7 @@ __global__ __launch_bounds__(kP2mThreads) void k_p2m_lds(int32_t leaf0, int32_t 
             if (c0 + l < npt) {
                 const int2 pt = pts[p0 + c0 + l];
                 loc = int32_t(int64_t(pt.x - cx) + side * int64_t(pt.y - cy));
-                f = gather_f(tab, f_single, perm_local, pinst, p0 + c0 + l, fs);
+                f = gather_f(tab, f_single, nsrc_single, perm_local, pinst, p0 + c0 + l, fs);
             }
             #pragma unroll
             for (int k = 0; k < kP2mGroup; ++k) {
@@ -505,19 +514,41 @@ __global__ __launch_bounds__(kBlock) void k_l2l_fine(const BoxTile* tiles, const
     boxmat_fine<kModeL2L>(tiles, box_list, box_parent, ops, U, zrow, U);
 }
 
+// Mixed-precision operands of the outgoing expansions, once per box: q-hat split into FP32
+// hi + lo parts (hi = fl32(q), lo = fl32(q - hi), so that hi + lo equals q to about 2^-48) and
+// its charge sum in FP64, for boxes [0, nrows) (the all-zero row included).
+__global__ void k_split_q(const double* Q, int32_t nrows, float* Qh, float* Ql, double* qs) {
+    constexpr int P = kRankPad;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t box = t / 64;
+    const int lane = int(t & 63);
+    if (box >= nrows) return;   // uniform over the wave: a wave is one box
+    const double q = lane < P ? Q[box * P + lane] : 0.0;
+    const float hi = float(q);
+    if (lane < P) {
+        Qh[box * P + lane] = hi;
+        Ql[box * P + lane] = float(q - double(hi));
+    }
+    double s = q;
+    #pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) qs[box] = s;
+}
+
 // Mixed-precision M2L on the FP32 matrix cores, same tiling and staging as k_m2l.  Each
 // operator is written T^d = c_d 1 1^T + R^d with c_d its mean entry: the constant part,
 // which carries the large log|d| level of the kernel, is applied in FP64 as c_d times the
 // source's charge sum; only the remainder R^d, several times smaller, goes through FP32.
-// R^d and q-hat are split into FP32 hi + lo parts; the products R_hi q_hi accumulate in one
-// FP32 accumulator and R_hi q_lo + R_lo q_hi in another (the cross terms are ~2^-24 of the
-// first and would be rounded away if added to it), both over the 48 terms of one slot, then
-// flushed into FP64 accumulators, so FP32 rounding acts on one slot's partial sums only.  The
-// FP32 instruction returns element i of lane (g, n) as row 4 g + i.
+// R^d and q-hat are split into FP32 hi + lo parts (q-hat once per box by k_split_q).  Each
+// 4-term step of R_hi q_hi is an FP32 product of its own, converted and added to the FP64
+// accumulators at once, so FP32 rounding acts on four terms at a time; the cross terms
+// R_hi q_lo and R_lo q_hi (about 2^-24 of the main term) accumulate in two FP32 accumulators
+// over the slot and are flushed once.  The FP32 instruction returns element i of lane (g, n)
+// as row 4 g + i.
 __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_p,
                                                        const int32_t* box_list, const int32_t* il27,
-                                                       const OpsPtrs* ops, const double* Q, int32_t zrow,
-                                                       double* U) {
+                                                       const OpsPtrs* ops, const float* Qh, const float* Ql,
+                                                       const double* qs, int32_t zrow, double* U) {
     constexpr int P = kRankPad, MT = P / 16, KQ = P / 4, NJ4 = KQ / 4;
     constexpr int A4 = P * P / 4;                      // float4 per operator part: 2.25 per thread
     static_assert(A4 == 2 * kBlock + kBlock / 4, "staging below assumes P = 48");
@@ -545,14 +576,18 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, cons
         const gptr<float4_t> Lh = global(reinterpret_cast<const float4_t*>(ops[opi].ifo_lo)) + hbase;
         const gptr<double> mono = global(ops[opi].mono) + size_t(height) * kNumIfoSlots;
         const gptr<int32_t> il = global(il27 + size_t(box >= 0 ? box : 0) * kNumInteractions);
-        const gptr<double> Qg = global(Q) + g * KQ;
+        // lane group g supplies rows 12 g .. 12 g + 11 of its column's q-hat
+        const gptr<float4_t> QH = global(reinterpret_cast<const float4_t*>(Qh)) + 3 * g;
+        const gptr<float4_t> QL = global(reinterpret_cast<const float4_t*>(Ql)) + 3 * g;
+        const gptr<double> QS = global(qs);
         if (tid < kNumInteractions) s_dsl[tid] = c_dslot.s[cls][tid];
         __syncthreads();
         const int* dsl = s_dsl;
         int32_t src = (box >= 0) ? il[0] : -1;
         src = src < 0 ? zrow : src;
-        const gptr<double2_t> qs = reinterpret_cast<gptr<double2_t>>(Qg + size_t(src) * P);
-        double2_t rb0 = qs[0], rb1 = qs[1], rb2 = qs[2], rb3 = qs[3], rb4 = qs[4], rb5 = qs[5];
+        float4_t h0 = QH[size_t(src) * 12], h1 = QH[size_t(src) * 12 + 1], h2 = QH[size_t(src) * 12 + 2];
+        float4_t l0 = QL[size_t(src) * 12], l1 = QL[size_t(src) * 12 + 1], l2 = QL[size_t(src) * 12 + 2];
+        double qsum = QS[src];
         int32_t src_next = (box >= 0) ? il[1] : -1;
         size_t off = size_t(dsl[0]) * A4;
         float4_t rh0 = Hh[off + tid], rh1 = Hh[off + tid + kBlock];
@@ -572,19 +607,19 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, cons
                 sH[bsel][tid + 2 * kBlock] = rh2;
                 sL[bsel][tid + 2 * kBlock] = rl2;
             }
-            const double q[KQ] = {rb0.x, rb0.y, rb1.x, rb1.y, rb2.x, rb2.y,
-                                  rb3.x, rb3.y, rb4.x, rb4.y, rb5.x, rb5.y};
+            const float4_t bh[NJ4] = {h0, h1, h2}, bl[NJ4] = {l0, l1, l2};
+            const double cq = qsum;
             const int d = dsl[k];
             __syncthreads();
             if (k + 1 < kNumInteractions) {
                 const int32_t sn = src_next < 0 ? zrow : src_next;
-                const gptr<double2_t> qn = reinterpret_cast<gptr<double2_t>>(Qg + size_t(sn) * P);
-                rb0 = qn[0];
-                rb1 = qn[1];
-                rb2 = qn[2];
-                rb3 = qn[3];
-                rb4 = qn[4];
-                rb5 = qn[5];
+                h0 = QH[size_t(sn) * 12];
+                h1 = QH[size_t(sn) * 12 + 1];
+                h2 = QH[size_t(sn) * 12 + 2];
+                l0 = QL[size_t(sn) * 12];
+                l1 = QL[size_t(sn) * 12 + 1];
+                l2 = QL[size_t(sn) * 12 + 2];
+                qsum = QS[sn];
                 src_next = (box >= 0 && k + 2 < kNumInteractions) ? il[k + 2] : -1;
                 off = size_t(dsl[k + 1]) * A4;
                 rh0 = Hh[off + tid];
@@ -597,41 +632,31 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, cons
                 }
             }
             if (wave_on) {
-                float bh[KQ], bl[KQ];
-                double qsum = 0.0;
-                #pragma unroll
-                for (int kk = 0; kk < KQ; ++kk) {
-                    qsum += q[kk];
-                    bh[kk] = float(q[kk]);
-                    bl[kk] = float(q[kk] - double(bh[kk]));
-                }
-                // charge sum of source column n: the four lane groups hold a quarter each
-                qsum += __shfl_xor(qsum, 16, 64);
-                qsum += __shfl_xor(qsum, 32, 64);
-                const double cq = mono[d] * qsum;
+                const double mq = mono[d] * cq;   // constant part of T^d times the charge sum
                 #pragma unroll
                 for (int m = 0; m < MT; ++m) {
                     #pragma unroll
                     for (int i = 0; i < 4; ++i)
-                        if (16 * m + 4 * g + i < rk) acc[m][i] += cq;   // padded rows stay zero
+                        if (16 * m + 4 * g + i < rk) acc[m][i] += mq;   // padded rows stay zero
                 }
                 #pragma unroll
                 for (int m = 0; m < MT; ++m) {
-                    float4_t mn = zero, cr = zero;
+                    float4_t c1 = zero, c2 = zero;
                     #pragma unroll
                     for (int j4 = 0; j4 < NJ4; ++j4) {
                         const float4_t ah = sH[bsel][(m * NJ4 + j4) * 64 + lane];
                         const float4_t al = sL[bsel][(m * NJ4 + j4) * 64 + lane];
                         #pragma unroll
                         for (int e = 0; e < 4; ++e) {
-                            const int kk = 4 * j4 + e;
-                            mn = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[e], bh[kk], mn, 0, 0, 0);
-                            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[e], bl[kk], cr, 0, 0, 0);
-                            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(al[e], bh[kk], cr, 0, 0, 0);
+                            const float4_t p = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[e], bh[j4][e], zero, 0, 0, 0);
+                            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[e], bl[j4][e], c1, 0, 0, 0);
+                            c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(al[e], bh[j4][e], c2, 0, 0, 0);
+                            #pragma unroll
+                            for (int i = 0; i < 4; ++i) acc[m][i] += double(p[i]);
                         }
                     }
                     #pragma unroll
-                    for (int i = 0; i < 4; ++i) acc[m][i] += double(mn[i]) + double(cr[i]);
+                    for (int i = 0; i < 4; ++i) acc[m][i] += double(c1[i]) + double(c2[i]);
                 }
             }
         }
@@ -693,8 +718,8 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
                                   int64_t side, int W, const double* tab, const char* tb, uint32_t kofs,
                                   const int2* pts,
                                   const uint32_t* pkey, const double* fs, const int32_t* perm_local,
-                                  const ExecPtrs* tab_ptrs, double* u_single, const double* U, const double* leafT,
-                                  const uint8_t* far_inst, const double* phi_oct_tab) {
+                                  const ExecPtrs* tab_ptrs, double* u_single, int32_t tgt0_single, const double* U,
+                                  const double* leafT, const uint8_t* far_inst, const double* phi_oct_tab) {
     const int lane = threadIdx.x & 63;
     const cptr<int4_t> E = as_const(reinterpret_cast<const int4_t*>(ents));
     const cptr<uint32_t> SK = as_const(pkey);
@@ -713,6 +738,7 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
     const int32_t k_inst = uniform(box_inst[leaf0]);
     const bool far = far_inst[k_inst] != 0;
     double* u = tab_ptrs ? tab_ptrs[k_inst].u : u_single;
+    const int32_t tgt0 = tab_ptrs ? tab_ptrs[k_inst].tgt0 : tgt0_single;   // first target index
     // passes: the whole group once (group mode) or each leaf in turn (sliced mode)
     for (int c0 = 0; c0 < (SLICED ? nleaf : 1); ++c0) {
         const int32_t p0 = SLICED ? bnd[c0] : bnd[0];
@@ -830,7 +856,7 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
             double acc = (a0 + a1) + (a2 + a3);
             if (SLICED)
                 for (int o = T; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
-            if (valid && sl == 0) u[pout] = acc;
+            if (valid && sl == 0 && pout >= tgt0) u[pout - tgt0] = acc;
         }
     }
 }
@@ -842,8 +868,9 @@ __global__ __launch_bounds__(near_threads(MODE)) void k_near(int32_t q0, int32_t
                                                       const int32_t* box_inst, int64_t side, int W, const int2* pts,
                                                       const uint32_t* pkey, const double* fs,
                                                       const int32_t* perm_local, const ExecPtrs* tab_ptrs,
-                                                      double* u_single, const double* U, const double* leafT,
-                                                      const uint8_t* far_inst, const double* phi_oct_tab) {
+                                                      double* u_single, int32_t tgt0_single, const double* U,
+                                                      const double* leafT, const uint8_t* far_inst,
+                                                      const double* phi_oct_tab) {
     constexpr int kNearBlock = near_threads(MODE), kNearWaves = kNearBlock / 64;
     // fixed-size table (largest window: side 32), so that its base is a compile-time constant
     // and folds into the address of every read
@@ -883,11 +910,63 @@ __global__ __launch_bounds__(near_threads(MODE)) void k_near(int32_t q0, int32_t
         // leaf otherwise (the octant table in global memory is read faster a leaf at a time)
         if (MODE != kGlobal && nt > 32)
             near_group<P, MODE, false>(qq, groups, ents, box_pt0, box_pt1, box_key, box_inst, side, W, tab, tb, kofs, pts,
-                                       pkey, fs, perm_local, tab_ptrs, u_single, U, leafT, far_inst, phi_oct_tab);
+                                       pkey, fs, perm_local, tab_ptrs, u_single, tgt0_single, U, leafT, far_inst,
+                                       phi_oct_tab);
         else
             near_group<P, MODE, true>(qq, groups, ents, box_pt0, box_pt1, box_key, box_inst, side, W, tab, tb, kofs, pts,
-                                      pkey, fs, perm_local, tab_ptrs, u_single, U, leafT, far_inst, phi_oct_tab);
+                                      pkey, fs, perm_local, tab_ptrs, u_single, tgt0_single, U, leafT, far_inst,
+                                      phi_oct_tab);
     }
+}
+
+// Load statistics for the input checks: per block, the sum, the sum of magnitudes and the
+// number of non-finite entries of its slice of f (fixed slices and a fixed tree order, so
+// the totals do not depend on timing); then one block adds the partials in block order.
+constexpr int kStatBlocks = 256;
+__global__ __launch_bounds__(kBlock) void k_load_stats_part(const double* f, int64_t n, double* part) {
+    __shared__ double ss[kBlock], sa[kBlock], sn[kBlock];
+    const int64_t per = (n + kStatBlocks - 1) / kStatBlocks;
+    const int64_t i0 = int64_t(blockIdx.x) * per, i1 = min(n, i0 + per);
+    double s = 0.0, a = 0.0, bad = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+        const double v = f[i];
+        if (isfinite(v)) {
+            s += v;
+            a += fabs(v);
+        } else {
+            bad += 1.0;
+        }
+    }
+    ss[threadIdx.x] = s;
+    sa[threadIdx.x] = a;
+    sn[threadIdx.x] = bad;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if (int(threadIdx.x) < o) {
+            ss[threadIdx.x] += ss[threadIdx.x + o];
+            sa[threadIdx.x] += sa[threadIdx.x + o];
+            sn[threadIdx.x] += sn[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = ss[0];
+        part[3 * blockIdx.x + 1] = sa[0];
+        part[3 * blockIdx.x + 2] = sn[0];
+    }
+}
+
+__global__ void k_load_stats_final(const double* part, double* out) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0, a = 0.0, bad = 0.0;
+    for (int b = 0; b < kStatBlocks; ++b) {
+        s += part[3 * b];
+        a += part[3 * b + 1];
+        bad += part[3 * b + 2];
+    }
+    out[0] = s;
+    out[1] = a;
+    out[2] = bad;
 }
 
 // Brute-force sum over all sources for blocks of 256 targets; sources staged through LDS.
@@ -972,8 +1051,9 @@ P2mDevice p2m_device() {
 }
 
 void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1, const uint64_t* box_key,
-                int64_t side, const int32_t* pts, const ExecPtrs* tab, const double* f_single, const int32_t* perm_local,
-                const int32_t* pinst, double* fs, const double* leafT, double* Q, hipStream_t st) {
+                int64_t side, const int32_t* pts, const ExecPtrs* tab, const double* f_single, int32_t nsrc_single,
+                const int32_t* perm_local, const int32_t* pinst, double* fs, const double* leafT, double* Q,
+                hipStream_t st) {
     if (leaf1 <= leaf0) return;
     const size_t lds = size_t(side * side) * kRankPad * sizeof(double);
     const P2mDevice dv = p2m_device();
@@ -984,12 +1064,12 @@ void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int3
         const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(want, int64_t(dv.cus) * per_cu));
         hipLaunchKernelGGL(k_p2m_lds<kRankPad>, dim3(unsigned(grid)), dim3(kP2mThreads), lds, st, leaf0, leaf1,
                            box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), tab, f_single,
-                           perm_local, pinst, fs, leafT, Q);
+                           nsrc_single, perm_local, pinst, fs, leafT, Q);
         return;
     }
     hipLaunchKernelGGL(k_p2m<kRankPad>, dim3(grid_for(leaf1 - leaf0, kWaves)), dim3(kBlock), 0, st, leaf0, leaf1,
-                       box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), tab, f_single, perm_local,
-                       pinst, fs, leafT, Q);
+                       box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), tab, f_single, nsrc_single,
+                       perm_local, pinst, fs, leafT, Q);
 }
 
 void launch_m2m(const BoxTile* tiles, int32_t ntiles, const int32_t* box_child, const OpsPtrs* ops, double* Q,
@@ -1029,20 +1109,25 @@ void launch_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, c
                        ops, Q, zrow, U);
 }
 
+void launch_split_q(const double* Q, int32_t nrows, float* Qh, float* Ql, double* qs, hipStream_t st) {
+    if (nrows <= 0) return;
+    hipLaunchKernelGGL(k_split_q, dim3(grid_for(int64_t(nrows) * 64)), dim3(kBlock), 0, st, Q, nrows, Qh, Ql, qs);
+}
+
 void launch_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t max_tiles, const int32_t* box_list,
-                      const int32_t* il27, const OpsPtrs* ops, const double* Q, int32_t zrow, double* U,
-                      hipStream_t st) {
+                      const int32_t* il27, const OpsPtrs* ops, const float* Qh, const float* Ql, const double* qs,
+                      int32_t zrow, double* U, hipStream_t st) {
     if (max_tiles <= 0) return;
     int64_t g = std::min<int64_t>(max_tiles, 8192);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
     hipLaunchKernelGGL(k_m2l_mixed, dim3(static_cast<unsigned>(g)), dim3(kBlock), 0, st, tiles, ntiles_dev, box_list,
-                       il27, ops, Q, zrow, U);
+                       il27, ops, Qh, Ql, qs, zrow, U);
 }
 
 void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* ents, const int32_t* box_pt0,
                  const int32_t* box_pt1, const uint64_t* box_key, const int32_t* box_inst, int64_t side,
                  const int32_t* pts, const uint32_t* pkey, const double* fs, const int32_t* perm_local,
-                 const ExecPtrs* tab, double* u_single, const double* U, const double* leafT,
+                 const ExecPtrs* tab, double* u_single, int32_t tgt0_single, const double* U, const double* leafT,
                  const uint8_t* far_inst, const double* phi_oct, hipStream_t st) {
     if (q1 <= q0) return;
     // with an LDS table: persistent blocks, as many as fit on the device at once, so that
@@ -1066,7 +1151,7 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
         constexpr int nt = near_threads(kWindow);
         const unsigned g = grid(reinterpret_cast<const void*>(&k_near<kRankPad, kWindow>), nt, lds, true);
         hipLaunchKernelGGL((k_near<kRankPad, kWindow>), dim3(g), dim3(nt), lds, st, q0, q1, groups, ents,
-                           box_pt0, box_pt1, box_key, box_inst, side, W, p2, pkey, fs, perm_local, tab, u_single, U,
+                           box_pt0, box_pt1, box_key, box_inst, side, W, p2, pkey, fs, perm_local, tab, u_single, tgt0_single, U,
                            leafT, far_inst, phi_oct);
     } else if (side <= 32) {
         const int W = int(2 * side);
@@ -1075,15 +1160,22 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
         constexpr int nt = near_threads(kQuad);
         const unsigned g = grid(reinterpret_cast<const void*>(&k_near<kRankPad, kQuad>), nt, lds, true);
         hipLaunchKernelGGL((k_near<kRankPad, kQuad>), dim3(g), dim3(nt), lds, st, q0, q1, groups, ents,
-                           box_pt0, box_pt1, box_key, box_inst, side, W, p2, pkey, fs, perm_local, tab, u_single, U,
+                           box_pt0, box_pt1, box_key, box_inst, side, W, p2, pkey, fs, perm_local, tab, u_single, tgt0_single, U,
                            leafT, far_inst, phi_oct);
     } else {
         constexpr int nt = near_threads(kGlobal);
         const unsigned g = grid(reinterpret_cast<const void*>(&k_near<kRankPad, kGlobal>), nt, 0, false);
         hipLaunchKernelGGL((k_near<kRankPad, kGlobal>), dim3(g), dim3(nt), 0, st, q0, q1, groups, ents,
-                           box_pt0, box_pt1, box_key, box_inst, side, 0, p2, pkey, fs, perm_local, tab, u_single, U,
+                           box_pt0, box_pt1, box_key, box_inst, side, 0, p2, pkey, fs, perm_local, tab, u_single, tgt0_single, U,
                            leafT, far_inst, phi_oct);
     }
+}
+
+size_t load_stats_scratch_bytes() { return size_t(kStatBlocks) * 3 * sizeof(double); }
+
+void launch_load_stats(const double* f, int64_t n, double* scratch, double* out3, hipStream_t st) {
+    hipLaunchKernelGGL(k_load_stats_part, dim3(kStatBlocks), dim3(kBlock), 0, st, f, n, scratch);
+    hipLaunchKernelGGL(k_load_stats_final, dim3(1), dim3(64), 0, st, scratch, out3);
 }
 
 void launch_phi_extend(double* oct, int r0, int r1, hipStream_t st) {

@@ -76,6 +76,40 @@ __global__ void k_concat(int32_t K, const int2* const* xy_tab, const int32_t* pt
     xyc[i] = xy_tab[k][i - pt_off[k]];
 }
 
+// {min x, min y, max x, max y} of n points into box (device), by atomics; box is set to the
+// empty box first by k_extent_init on the same stream.
+__global__ void k_extent_init(int32_t* box, int32_t nbox) {
+    const int32_t i = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < nbox) {
+        box[4 * i] = INT_MAX;
+        box[4 * i + 1] = INT_MAX;
+        box[4 * i + 2] = INT_MIN;
+        box[4 * i + 3] = INT_MIN;
+    }
+}
+
+__global__ void k_extent(const int2* xy, int64_t n, int32_t* box) {
+    int v[4] = {INT_MAX, INT_MAX, INT_MIN, INT_MIN};
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const int2 p = xy[i];
+        v[0] = min(v[0], p.x); v[1] = min(v[1], p.y);
+        v[2] = max(v[2], p.x); v[3] = max(v[3], p.y);
+    }
+    #pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        v[0] = min(v[0], __shfl_xor(v[0], o, 64));
+        v[1] = min(v[1], __shfl_xor(v[1], o, 64));
+        v[2] = max(v[2], __shfl_xor(v[2], o, 64));
+        v[3] = max(v[3], __shfl_xor(v[3], o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&box[0], v[0]);
+        atomicMin(&box[1], v[1]);
+        atomicMax(&box[2], v[2]);
+        atomicMax(&box[3], v[3]);
+    }
+}
+
 // v = {min x, min y, max x, max y} over the block: wave shuffles, then the four waves
 // through LDS; thread 0 gets the result in v and true
 __device__ inline bool block_minmax4(int v[4]) {
@@ -963,6 +997,15 @@ void launch_upload(void* dst, const void* pinned_src, size_t len, hipStream_t st
     const unsigned g = unsigned(std::min<int64_t>((nw + kBlock - 1) / kBlock, 64));
     hipLaunchKernelGGL(k_upload, dim3(g), dim3(kBlock), 0, st, static_cast<const uint64_t*>(pinned_src),
                        static_cast<uint64_t*>(dst), int64_t(len));
+}
+
+void launch_extents(int32_t K, const int64_t* n, const int32_t* const* xy, int32_t* box, hipStream_t st) {
+    hipLaunchKernelGGL(k_extent_init, dim3(grid_for(K)), dim3(kBlock), 0, st, box, K);
+    for (int32_t k = 0; k < K; ++k) {
+        const unsigned g = std::min<unsigned>(grid_for(n[k]), 1024u);
+        hipLaunchKernelGGL(k_extent, dim3(g), dim3(kBlock), 0, st, reinterpret_cast<const int2*>(xy[k]), n[k],
+                           box + 4 * size_t(k));
+    }
 }
 
 void launch_concat(int32_t K, const int32_t* const* xy_tab, const int32_t* pt_off, int64_t n, int32_t* xyc,

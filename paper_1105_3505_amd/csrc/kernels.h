@@ -100,10 +100,14 @@ constexpr int kNearEntries = 16;
 // group's own leaves (one run of points), x alone for the two cells above or below them
 constexpr int32_t kNearAll = -(1 << 30);
 
-// Per-execute load/potential pointers of each instance.
+// Per-execute load/potential pointers of each instance, with the roles of its points: an
+// instance's points are its sources followed by its targets (the same points when targets =
+// sources).  Point of local index j carries the load f[j] if j < nsrc (else zero), and its
+// potential goes to u[j - tgt0] if j >= tgt0 (else nowhere).
 struct ExecPtrs {
     const double* f;
     double* u;
+    int32_t nsrc, tgt0;
 };
 
 enum BoxMatMode { kModeM2L = 0, kModeM2M = 1, kModeL2L = 2 };
@@ -134,6 +138,9 @@ void scan_rows(const int32_t* in, int32_t* out, int64_t n, int rows, int32_t* to
 struct Chunk { int32_t inst, begin, end, pad; };   // <= kChunk points of one instance
 constexpr int32_t kChunk = 2048;
 
+// {min x, min y, max x, max y} of each of K point sets (n[k] points at xy[k], device; n and xy
+// host arrays) into box[4 K] (device)
+void launch_extents(int32_t K, const int64_t* n, const int32_t* const* xy, int32_t* box, hipStream_t st);
 void launch_concat(int32_t K, const int32_t* const* xy_tab, const int32_t* pt_off, int64_t n,
                    int32_t* xyc, hipStream_t st);
 // partial root boxes per chunk; also zeroes *dmax
@@ -195,10 +202,11 @@ void launch_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, const in
 // ---- evaluation passes (fmm_kernels.hip) ---------------------------------------------------
 // P2M of the leaves [leaf0, leaf1); reads the caller-order loads (tab per instance, or
 // f_single) through perm_local / pinst and also stores them in Morton order at fs
+// (tab null: the single instance's loads f_single, of which the first nsrc_single are real)
 void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1,
                 const uint64_t* box_key, int64_t side, const int32_t* pts, const ExecPtrs* tab,
-                const double* f_single, const int32_t* perm_local, const int32_t* pinst, double* fs,
-                const double* leafT, double* Q, hipStream_t st);
+                const double* f_single, int32_t nsrc_single, const int32_t* perm_local, const int32_t* pinst,
+                double* fs, const double* leafT, double* Q, hipStream_t st);
 // M2M over the consecutive-box tiles of one height (Q row zrow is all zeros)
 void launch_m2m(const BoxTile* tiles, int32_t ntiles, const int32_t* box_child, const OpsPtrs* ops, double* Q,
                 int32_t zrow, hipStream_t st);
@@ -208,20 +216,27 @@ void launch_l2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, c
 // M2L over the class-sorted tiles; Q row zrow is all zeros (read for absent sources)
 void launch_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, const int32_t* il27,
                 const OpsPtrs* ops, const double* Q, int32_t zrow, double* U, hipStream_t st);
+// mixed-precision operands of Q rows [0, nrows): FP32 hi and lo parts and FP64 charge sums
+void launch_split_q(const double* Q, int32_t nrows, float* Qh, float* Ql, double* qs, hipStream_t st);
 void launch_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t max_tiles,
                       const int32_t* box_list, const int32_t* il27, const OpsPtrs* ops,
-                      const double* Q, int32_t zrow, double* U, hipStream_t st);
+                      const float* Qh, const float* Ql, const double* qs, int32_t zrow, double* U,
+                      hipStream_t st);
 // L2P + near field + un-permutation for the groups [q0, q1) of one leaf side
 void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* ents, const int32_t* box_pt0,
                  const int32_t* box_pt1, const uint64_t* box_key, const int32_t* box_inst, int64_t side,
                  const int32_t* pts, const uint32_t* pkey, const double* fs, const int32_t* perm_local,
-                 const ExecPtrs* tab, double* u_single, const double* U, const double* leafT,
+                 const ExecPtrs* tab, double* u_single, int32_t tgt0_single, const double* U, const double* leafT,
                  const uint8_t* far_inst, const double* phi_oct, hipStream_t st);
 // Radius of the device phi table: the host's quadrature table (radius 128) followed by eq. 3.1
 // for the octant entries up to this radius, filled by launch_phi_extend(oct, 128, radius).
 constexpr int kPhiDeviceRadius = 256;
 constexpr size_t kPhiDeviceEntries = size_t(kPhiDeviceRadius + 1) * (kPhiDeviceRadius + 2) / 2;
 void launch_phi_extend(double* oct, int r0, int r1, hipStream_t st);
+// Sum, sum of magnitudes and count of non-finite entries of f[0, n) into out3 (device);
+// scratch holds load_stats_scratch_bytes().
+size_t load_stats_scratch_bytes();
+void launch_load_stats(const double* f, int64_t n, double* scratch, double* out3, hipStream_t st);
 void launch_direct(int64_t nt, const int32_t* txy, int64_t ns, const int32_t* sxy,
                    const double* f, const double* phi_oct, double* u, hipStream_t st);
 hipError_t upload_dslots();

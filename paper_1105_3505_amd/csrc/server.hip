@@ -35,7 +35,11 @@ struct Request {
     const int32_t* xy = nullptr;
     const double* f = nullptr;
     double* u = nullptr;
-    size_t footprint = 0;
+    hipEvent_t ready = nullptr;   // recorded on the producer's stream at submit
+    size_t footprint = 0;         // 0 until the root box is known
+    ~Request() {
+        if (ready) (void)hipEventDestroy(ready);
+    }
     lfmm_request_stats st{};
     bool done = false;
     bool solo = false;   // served alone after a batch it was in failed to build
@@ -57,6 +61,7 @@ struct lfmm_server {
     Clock::time_point t0;
     std::vector<hipStream_t> streams;
     std::vector<bool> stream_busy;
+    hipStream_t probe = nullptr;       // extents of newly queued requests
     std::mutex mu;
     std::condition_variable cv_work;   // worker: new request or stop
     std::condition_variable cv_done;   // waiters: a request finished
@@ -104,6 +109,44 @@ struct lfmm_server {
         return k;
     }
 
+    // footprint bounds of queued requests that lack one: the root bits of each request are
+    // measured on the device (after its producer's event), then lfmm_plan_footprint_bytes;
+    // a request over the whole budget finishes at once with LFMM_E_NOMEM
+    void measure() {
+        std::vector<std::shared_ptr<Request>> todo;
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            for (auto& r : queue)
+                if (r->footprint == 0) todo.push_back(r);
+        }
+        if (todo.empty()) return;
+        const int32_t K = int32_t(todo.size());
+        std::vector<int64_t> n(static_cast<size_t>(K));
+        std::vector<const int32_t*> xy(static_cast<size_t>(K));
+        std::vector<int32_t> bits(static_cast<size_t>(K), -1);
+        for (int32_t k = 0; k < K; ++k) {
+            n[size_t(k)] = todo[size_t(k)]->n;
+            xy[size_t(k)] = todo[size_t(k)]->xy;
+            if (hipStreamWaitEvent(probe, todo[size_t(k)]->ready, 0) != hipSuccess) (void)hipGetLastError();
+        }
+        if (root_bits_of(ctx, K, n.data(), xy.data(), probe, bits.data()) != LFMM_OK)
+            std::fill(bits.begin(), bits.end(), -1);   // unknown: the bound for any extent
+        std::vector<std::shared_ptr<Request>> reject;
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            for (int32_t k = 0; k < K; ++k) {
+                Request& r = *todo[size_t(k)];
+                const int32_t b = bits[size_t(k)] > 31 ? 31 : bits[size_t(k)];
+                size_t fp = 0;
+                if (lfmm_plan_footprint_bytes(ctx, r.n, 0, b, &fp) != LFMM_OK || fp == 0) fp = ~size_t(0) / 4;
+                r.footprint = fp;
+                if (fp > opt.hbm_budget_bytes) reject.push_back(todo[size_t(k)]);
+            }
+            for (auto& r : reject) queue.erase(std::find(queue.begin(), queue.end(), r));
+        }
+        for (auto& r : reject) finish(r, LFMM_E_NOMEM, now());
+    }
+
     // requests for the next iteration, in arrival order, within the limits
     std::vector<std::shared_ptr<Request>> admit() {
         std::vector<std::shared_ptr<Request>> out;
@@ -112,6 +155,7 @@ struct lfmm_server {
         size_t bytes = 0;
         while (!queue.empty() && int32_t(out.size()) < opt.max_batch) {
             const auto& r = queue.front();
+            if (r->footprint == 0) break;   // not measured yet
             if (!out.empty() && (r->solo || out.front()->solo)) break;
             if (!out.empty() && pts + r->n > opt.max_batch_points) break;
             if (inflight_bytes + bytes + r->footprint > opt.hbm_budget_bytes) break;
@@ -138,9 +182,12 @@ struct lfmm_server {
             f[size_t(k)] = reqs[size_t(k)]->f;
             u[size_t(k)] = reqs[size_t(k)]->u;
             bytes += reqs[size_t(k)]->footprint;
+            // the producer's writes of xy and f come first
+            if (hipStreamWaitEvent(streams[size_t(s)], reqs[size_t(k)]->ready, 0) != hipSuccess) return LFMM_E_HIP;
         }
         lfmm_plan* plan = nullptr;
-        lfmm_status st = lfmm_plan_create_batch(ctx, K, sizes.data(), xy.data(), streams[size_t(s)], &plan);
+        lfmm_status st = lfmm_plan_create_batch(ctx, K, sizes.data(), xy.data(), nullptr, nullptr, streams[size_t(s)],
+                                                &plan);
         if (st != LFMM_OK) return st;
         st = lfmm_execute_instances(plan, f.data(), u.data(), streams[size_t(s)]);
         hipEvent_t ev = nullptr;
@@ -176,6 +223,7 @@ struct lfmm_server {
         (void)hipSetDevice(ctx_device(ctx));
         for (;;) {
             retire();
+            measure();
             int free_slot = -1;
             for (size_t s = 0; s < stream_busy.size(); ++s)
                 if (!stream_busy[s]) {
@@ -252,6 +300,11 @@ lfmm_status lfmm_server_create(lfmm_ctx* ctx, const lfmm_server_options* opt, lf
         srv->streams.push_back(st);
         srv->stream_busy.push_back(false);
     }
+    if (hipStreamCreateWithFlags(&srv->probe, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        for (hipStream_t x : srv->streams) (void)hipStreamDestroy(x);
+        return fail(LFMM_E_HIP, "hipStreamCreate failed");
+    }
     lfmm_server* raw = srv.get();
     srv->worker = std::thread([raw] { raw->run(); });
     ctx_add_server(ctx, raw);
@@ -260,7 +313,7 @@ lfmm_status lfmm_server_create(lfmm_ctx* ctx, const lfmm_server_options* opt, lf
 }
 
 lfmm_status lfmm_server_submit(lfmm_server* srv, int64_t n, const int32_t* xy, const double* f, double* u,
-                               uint64_t* ticket) {
+                               void* producer_stream, uint64_t* ticket) {
     if (!srv || !ticket || !xy || !f || !u) return fail(LFMM_E_INVAL, "null argument");
     if (n < 1 || n > (int64_t(1) << 30)) return fail(LFMM_E_INVAL, "n must lie in [1, 2^30]");
     auto r = std::make_shared<Request>();
@@ -268,10 +321,19 @@ lfmm_status lfmm_server_submit(lfmm_server* srv, int64_t n, const int32_t* xy, c
     r->xy = xy;
     r->f = f;
     r->u = u;
-    lfmm_status s = lfmm_plan_footprint_bytes(srv->ctx, n, &r->footprint);
-    if (s != LFMM_OK) return s;
-    if (r->footprint > srv->opt.hbm_budget_bytes)
-        return fail(LFMM_E_NOMEM, "request footprint exceeds the server's memory budget");
+    {
+        // the caller's current device is left as it was
+        int prev = -1;
+        (void)hipGetDevice(&prev);
+        const bool ok = hipSetDevice(ctx_device(srv->ctx)) == hipSuccess &&
+                        hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) == hipSuccess &&
+                        hipEventRecord(r->ready, reinterpret_cast<hipStream_t>(producer_stream)) == hipSuccess;
+        if (prev >= 0) (void)hipSetDevice(prev);
+        if (!ok) {
+            (void)hipGetLastError();
+            return fail(LFMM_E_HIP, "event on the producer stream failed");
+        }
+    }
     {
         std::lock_guard<std::mutex> lock(srv->mu);
         if (srv->stop) return fail(LFMM_E_INVAL, "server is stopping");
@@ -314,6 +376,7 @@ lfmm_status lfmm_server_destroy(lfmm_server* srv) {
     srv->cv_work.notify_all();
     if (srv->worker.joinable()) srv->worker.join();
     for (hipStream_t s : srv->streams) (void)hipStreamDestroy(s);
+    if (srv->probe) (void)hipStreamDestroy(srv->probe);
     ctx_remove_server(srv->ctx, srv);
     delete srv;
     return LFMM_OK;

@@ -47,6 +47,12 @@ def _rel(u, ref):
     return float(np.linalg.norm(u - ref) / (den if den > 0 else 1.0))
 
 
+def _maxrel(u, ref):
+    """max |u - u_ref| / max |u_ref|: the max-norm error reported beside the l2 one."""
+    den = np.max(np.abs(ref))
+    return float(np.max(np.abs(u - ref)) / (den if den > 0 else 1.0))
+
+
 def test_direct_kernel_matches_oracle(torch_mod, ctx):
     torch = torch_mod
     rng = np.random.default_rng(21)
@@ -67,7 +73,7 @@ def test_small_uniform_all_targets(torch_mod, ctx):
     info = plan.info()
     print("n=1000 leaf level %d side %d rel err %.3e" % (info["leaf_level"], info["leaf_side"], err))
     assert info["leaf_level"] >= 2          # the far-field passes ran
-    assert err <= FMM_TOL
+    assert err <= FMM_TOL and _maxrel(u, ref) <= FMM_TOL
 
 
 @pytest.mark.parametrize("n,side,seed", [(1, 16, 1), (2, 16, 2), (17, 64, 3), (64, 64, 4), (65, 64, 5),
@@ -81,7 +87,7 @@ def test_uniform_sizes_all_targets(torch_mod, ctx, n, side, seed):
     if n == 1:
         assert u[0] == 0.0                  # phi(0) = 0: no self term
     else:
-        assert _rel(u, ref) <= FMM_TOL
+        assert _rel(u, ref) <= FMM_TOL and _maxrel(u, ref) <= FMM_TOL
 
 
 def test_clustered_points(torch_mod, ctx):
@@ -176,9 +182,10 @@ def test_large_uniform_sampled(torch_mod, ctx):
     ref = od.direct_sum(xy[idx], xy, f)
     err = _rel(u[idx], ref)
     info = plan.info()
-    print("n=1e6 leaf level %d side %d near pairs %d m2l pairs %d rel err %.3e"
-          % (info["leaf_level"], info["leaf_side"], info["near_pairs"], info["m2l_pairs"], err))
-    assert err <= FMM_TOL
+    mx = _maxrel(u[idx], ref)
+    print("n=1e6 leaf level %d side %d near pairs %d m2l pairs %d rel err %.3e max %.3e"
+          % (info["leaf_level"], info["leaf_side"], info["near_pairs"], info["m2l_pairs"], err, mx))
+    assert err <= FMM_TOL and mx <= FMM_TOL
 
 
 @pytest.mark.slow
@@ -192,9 +199,10 @@ def test_clusters_sampled(torch_mod, ctx):
     idx = wl.sample_targets(21, len(xy), 500)
     ref = od.direct_sum(xy[idx], xy, f)
     err = _rel(u[idx], ref)
-    print("n=2e6 clusters leaf level %d side %d near pairs %d m2l pairs %d rel err %.3e"
-          % (info["leaf_level"], info["leaf_side"], info["near_pairs"], info["m2l_pairs"], err))
-    assert err <= FMM_TOL
+    mx = _maxrel(u[idx], ref)
+    print("n=2e6 clusters leaf level %d side %d near pairs %d m2l pairs %d rel err %.3e max %.3e"
+          % (info["leaf_level"], info["leaf_side"], info["near_pairs"], info["m2l_pairs"], err, mx))
+    assert err <= FMM_TOL and mx <= FMM_TOL
 
 
 @pytest.mark.parametrize("max_leaf", [8, 16, 32, 128, 256])
@@ -220,7 +228,8 @@ def test_mixed_precision_m2l(torch_mod):
         xy = wl.uniform_box(rng, n, side)
         f = wl.zero_sum_loads(rng.standard_normal(n))
         u, _ = _fmm(torch_mod, ctx, xy, f)
-        err = _rel(u, od.direct_sum(xy, xy, f))
-        print("mixed n=%d rel err %.3e" % (n, err))
-        assert err <= 1e-7
+        ref = od.direct_sum(xy, xy, f)
+        err, mx = _rel(u, ref), _maxrel(u, ref)
+        print("mixed n=%d rel err %.3e max %.3e" % (n, err, mx))
+        assert err <= 1e-7 and mx <= 1e-7
     ctx.close()

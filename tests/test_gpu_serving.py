@@ -90,7 +90,7 @@ def test_memory_budget_bounds_admission(torch_mod):
     import paper_1105_3505_amd as lf
     torch = torch_mod
     ctx = lf.Context(0)
-    fp = ctx.footprint_bytes(20000)
+    fp = ctx.footprint_bytes(20000, 0, 10)      # 20,000 points in a 600 x 600 box: 2^10 root
     # room for about two requests of 20,000 points at a time
     srv = lf.Server(ctx, hbm_budget_bytes=int(2.5 * fp), max_batch=64)
     rng = np.random.default_rng(91)
@@ -100,9 +100,11 @@ def test_memory_budget_bounds_admission(torch_mod):
         reqs.append((xy, wl.zero_sum_loads(rng.standard_normal(20000))))
     dev = [(_dev(torch, xy), _dev(torch, f)) for xy, f in reqs]
     tickets = [srv.submit(*d) for d in dev]
+    # a request whose footprint alone exceeds the budget finishes with LFMM_E_NOMEM
     big = _dev(torch, wl.uniform_box(rng, 200000, 2000))
+    tb = srv.submit(big, torch.zeros(200000, dtype=torch.float64, device="cuda"))
     with pytest.raises(lf.LfmmError) as e:
-        srv.submit(big, torch.zeros(200000, dtype=torch.float64, device="cuda"))
+        srv.wait(tb, timeout=120)
     assert e.value.status == -3
     out = [srv.wait(t, timeout=120) for t in tickets]
     srv.close()
@@ -141,4 +143,67 @@ def test_failed_request_does_not_poison_its_batch(torch_mod):
         xy, f = items[k]
         u = results[k][0].cpu().numpy()
         assert _rel(u, od.direct_sum(xy, xy, f)) <= FMM_TOL
+    ctx.close()
+
+
+def test_scattered_requests_stay_within_budget(torch_mod):
+    # sparse requests (deep trees) are admitted by a footprint bound that holds for their
+    # actual plans: the plans' own bytes never exceed the bound used for admission
+    import math
+    import paper_1105_3505_amd as lf
+    torch = torch_mod
+    ctx = lf.Context(0)
+    rng = np.random.default_rng(95)
+    reqs = []
+    for i in range(10):
+        n = int(rng.integers(500, 3000))
+        xy = rng.integers(-(2 ** 28), 2 ** 28, size=(n, 2)).astype(np.int32)
+        reqs.append((xy, wl.zero_sum_loads(rng.standard_normal(n))))
+    bounds = []
+    for xy, _ in reqs:
+        ext = int(max(np.ptp(xy[:, 0]), np.ptp(xy[:, 1]))) + 1
+        bounds.append(ctx.footprint_bytes(len(xy), 0, math.ceil(math.log2(ext))))
+        plan = ctx.plan(_dev(torch, xy))
+        assert plan.info()["device_bytes"] <= bounds[-1]
+        plan.close()
+    budget = int(2.2 * max(bounds))
+    srv = lf.Server(ctx, hbm_budget_bytes=budget, max_batch=64)
+    dev = [(_dev(torch, xy), _dev(torch, f)) for xy, f in reqs]
+    tickets = [srv.submit(*d) for d in dev]
+    out = [srv.wait(t, timeout=120) for t in tickets]
+    srv.close()
+    spans = [(s["t_admit"], s["t_done"], b) for (_, s), b in zip(out, bounds)]
+    for a, _, _ in spans:
+        assert sum(b for s0, s1, b in spans if s0 <= a < s1) <= budget
+    for (xy, f), (u, _) in zip(reqs[:3], out[:3]):
+        assert _rel(u.cpu().numpy(), od.direct_sum(xy, xy, f)) <= FMM_TOL
+    ctx.close()
+
+
+def test_loads_written_on_a_producer_stream(torch_mod):
+    # loads computed on the device on a side stream just before submit: the server orders its
+    # reads after them (the stream passed to submit), so the result equals the solve alone
+    import paper_1105_3505_amd as lf
+    torch = torch_mod
+    rng = np.random.default_rng(97)
+    xy = wl.uniform_box(rng, 60000, 1000)
+    raw = _dev(torch, rng.standard_normal((len(xy), 64)))
+    ctx = lf.Context(0)
+    srv = lf.Server(ctx, max_batch=4)
+    side = torch.cuda.Stream()
+    xd = _dev(torch, xy)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        # a long reduction, then mean subtraction: the loads are ready only when it ends
+        g = (raw * raw).sum(dim=1).sqrt()
+        for _ in range(20):
+            g = g + 1e-3 * torch.sin(g)
+        f = g - g.mean()
+        t = srv.submit(xd, f, stream=side)
+    u, st = srv.wait(t, timeout=120)
+    srv.close()
+    torch.cuda.synchronize()
+    assert st["status"] == 0
+    ua = ctx.solve(xd, f).cpu().numpy()
+    assert np.array_equal(u.cpu().numpy(), ua)
     ctx.close()

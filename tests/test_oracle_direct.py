@@ -116,3 +116,16 @@ def test_invariances():
     src2 = np.vstack([src, [[-50, 40]]])
     f2 = np.append(f, 0.0)
     assert np.array_equal(od.direct_sum(src, src2, f2), u)
+
+
+@pytest.mark.parametrize("m", [(129, 57), (-150, 149), (173, -88), (211, 5), (-256, -200), (300, 150),
+                               (297, 296), (40, 290)])
+def test_c_expansion_off_axis_against_reduced_integral(m):
+    # the C direct sum's own phi beyond the table (eq. 3.1, off the axes and diagonal, signs
+    # folded by the code under test) against the one-dimensional reduced integral of the remark
+    # closing Section 3 at 30 digits; the truncation error of eq. 3.1 there is O(|m|^-6)
+    import lattice_exact as le
+    a, b = sorted((abs(m[0]), abs(m[1])), reverse=True)
+    ref = le.phi_reduced_integral(a, b, digits=30)
+    got = od.phi(np.array([m]))[0]
+    assert abs(got - ref) <= 0.2 / math.hypot(*m) ** 6 + 2e-15

@@ -14,5 +14,6 @@ from .generators import (  # noqa: F401
     config_batched,
     config_batched_instance,
     config_serving_request,
+    serving_request_size,
     sample_targets,
 )

@@ -148,6 +148,12 @@ def config_batched(seed: int = 4, n_inst: int = 512, lo: float = 1e3, hi: float 
     return [config_batched_instance(seed, i, n_inst, lo, hi) for i in range(n_inst)]
 
 
+def serving_request_size(seed: int, index: int, lo: float = 1e2, hi: float = 1e6) -> int:
+    """Size of request ``index`` of ``config_serving_request`` (same draws), without its points."""
+    rng = np.random.default_rng([seed, index])
+    return max(int(np.rint(math.exp(rng.uniform(math.log(lo), math.log(hi))))), 2)
+
+
 def config_serving_request(seed: int, index: int, lo: float = 1e2, hi: float = 1e6):
     """One serving request: log-uniform size, uniform or 8-cluster layout chosen by the seed."""
     rng = np.random.default_rng([seed, index])

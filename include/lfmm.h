@@ -266,6 +266,21 @@ lfmm_status lfmm_plan_destroy(lfmm_plan* plan);
 lfmm_status lfmm_solve(lfmm_ctx* ctx, int64_t n, const int32_t* xy_dev, const double* f_dev,
                        double* u_dev, void* stream);
 
+/* lfmm_solve for callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the same solve (targets = sources, loads
+ * checked as by lfmm_solve, stream synchronised before return), with every device buffer the
+ * tree, the expansions and the construction need taken from the library's static workspace,
+ * a 64 MiB device array per GPU held until the process ends.  It calls no hipMalloc, hipFree,
+ * pinned-memory or other allocating routine.  Limits: 1 <= n <= 65536 (else LFMM_E_RANGE),
+ * and the point set's tree must fit the workspace (sparse sets make deep trees; else
+ * LFMM_E_RANGE, nothing computed).  The operators for the point set's leaf side must be in
+ * the context already (an earlier plan or solve of a point set with that leaf side and depth
+ * builds them); else LFMM_E_UNSUPPORTED.  Calls on one device share its workspace: the
+ * library makes them take turns; the caller must not overlap them with its own use of the
+ * results of an earlier call, which the next call overwrites only in the workspace. */
+lfmm_status lfmm_solve_static(lfmm_ctx* ctx, int64_t n, const int32_t* xy_dev, const double* f_dev,
+                              double* u_dev, void* stream);
+
 /* Direct O(n_t n_s) sum on the GPU, u_dev[t] = sum_s phi(txy_t - sxy_s) f_dev[s] (eq. 1.7),
  * with phi from the table (|m|_inf <= 128) or the expansion eq. (3.1).  For small inputs and
  * for checking. */

@@ -90,6 +90,7 @@ def _load():
         "lfmm_plan_footprint_bytes": [_vp, _i64, _i64, _i32, _vp],
         "lfmm_plan_destroy": [_vp],
         "lfmm_solve": [_vp, _i64, _vp, _vp, _vp, _vp],
+        "lfmm_solve_static": [_vp, _i64, _vp, _vp, _vp, _vp],
         "lfmm_direct": [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp],
         "lfmm_host_phi": [_i64, _vp, _vp],
         "lfmm_host_opset_create": [_i64, _i32, _vp, _vp],
@@ -282,6 +283,18 @@ class Context:
         _check(_lib.lfmm_solve(self._h, n, _dev_tensor(xy, torch.int32, (2,), "xy"),
                                _dev_tensor(f, torch.float64, (), "f"), _dev_tensor(u, torch.float64, (), "u"),
                                _stream_handle(stream)))
+        return u
+
+    def solve_static(self, xy, f, u, stream=None):
+        """lfmm_solve_static: lfmm_solve with no allocation (the library's static workspace,
+        at most 65,536 points); u is the caller's preallocated output."""
+        import torch
+        n = int(xy.shape[0])
+        if int(f.shape[0]) != n or int(u.shape[0]) != n:
+            raise ValueError("f and u must have one entry per point")
+        _check(_lib.lfmm_solve_static(self._h, n, _dev_tensor(xy, torch.int32, (2,), "xy"),
+                                      _dev_tensor(f, torch.float64, (), "f"), _dev_tensor(u, torch.float64, (), "u"),
+                                      _stream_handle(stream)))
         return u
 
     def direct(self, txy, sxy, f, u=None, stream=None):

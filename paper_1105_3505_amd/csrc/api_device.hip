@@ -40,6 +40,26 @@ struct NoMemory {
     std::string msg;
 };
 
+struct Unsupported {
+    std::string msg;
+};
+
+// Bump allocation from a fixed device region (the static workspace of the allocation-free
+// solve): nothing is freed, the whole region is reused by the next call.
+struct StaticRegion {
+    char* base = nullptr;
+    size_t cap = 0, used = 0;
+    void* take(size_t bytes) {
+        bytes = (bytes + 255) & ~size_t(255);
+        if (used + bytes > cap)
+            throw std::out_of_range("the point set needs more than the " + std::to_string(cap >> 20) +
+                                    " MiB static workspace");
+        void* p = base + used;
+        used += bytes;
+        return p;
+    }
+};
+
 // An event recorded after the last work that uses some blocks; blocks released "after" it
 // become reusable once the device has passed it.
 struct Fence {
@@ -148,10 +168,15 @@ class DevicePool {
 // One device allocation carved into aligned pieces (from a pool when one is given).
 class Arena {
   public:
-    explicit Arena(DevicePool* pool = nullptr) : pool_(pool) {}
+    explicit Arena(DevicePool* pool = nullptr, StaticRegion* region = nullptr) : pool_(pool), region_(region) {}
     void reserve(size_t bytes) { total_ += align(bytes); }
     void allocate() {
         if (total_ == 0) return;
+        if (region_) {
+            base_ = region_->take(total_);
+            cap_ = total_;
+            return;
+        }
         if (pool_) {
             base_ = pool_->acquire(total_, &cap_);
             return;
@@ -173,7 +198,7 @@ class Arena {
         return p;
     }
     void release() {
-        if (base_) {
+        if (base_ && !region_) {
             if (pool_) pool_->release(base_, cap_);
             else (void)hipFree(base_);
         }
@@ -182,7 +207,7 @@ class Arena {
     }
     // back to the pool once the device has passed `fence` (pool arenas only)
     void release_after(const FencePtr& fence) {
-        if (base_ && pool_) {
+        if (base_ && pool_ && !region_) {
             pool_->release_after(base_, cap_, fence);
             base_ = nullptr;
             total_ = used_ = cap_ = 0;
@@ -190,12 +215,16 @@ class Arena {
         release();
     }
     size_t bytes() const { return cap_; }
-    void set_pool(DevicePool* p) { pool_ = p; }
+    void set_pool(DevicePool* p, StaticRegion* region = nullptr) {
+        pool_ = p;
+        region_ = region;
+    }
     ~Arena() { release(); }
 
   private:
     static size_t align(size_t b) { return (b + 255) & ~size_t(255); }
     DevicePool* pool_ = nullptr;
+    StaticRegion* region_ = nullptr;
     void* base_ = nullptr;
     size_t total_ = 0, used_ = 0, cap_ = 0;
 };
@@ -255,8 +284,19 @@ class PinnedPool {
     std::mutex mu_;
 };
 
+// Workspace of lfmm_solve_static: one file-scope device array per GPU, held until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it is a stand-in, not
+// a device address): each context looks up the address on its device at creation.
+namespace {
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr int64_t kStaticMaxPoints = int64_t(1) << 16;
+std::mutex g_static_mu[64];   // calls on one device take turns (they share its array)
+}  // namespace
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
 struct lfmm_ctx {
     int device = 0;
+    void* static_scratch = nullptr;   // device address of `scratch` on this context's device
     lfmm_options opt{};
     PinnedPool pinned;
     DevicePool pool;             // plan storage and temporaries (declared first: freed last)
@@ -341,6 +381,7 @@ struct lfmm_plan {
     hipGraphExec_t gexec = nullptr;
     hipEvent_t ev[LFMM_NUM_PHASES + 1] = {};
     FencePtr built;                         // end of the build, on build_stream
+    StaticRegion* sreg = nullptr;           // allocation-free solve: every device block from here
     hipStream_t build_stream = nullptr;
     bool one_stream = true;                 // every execute so far ran on build_stream
     ~lfmm_plan() {
@@ -368,11 +409,15 @@ int bits_for_extent(int64_t extent) {
     return D;
 }
 
-// Uploads (or extends) the operators for leaves of `side` with at least `nlev` heights.
-CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st) {
+// Uploads (or extends) the operators for leaves of `side` with at least `nlev` heights.  With
+// lookup_only (allocation-free solves) a missing set is an Unsupported request instead.
+CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st, bool lookup_only = false) {
     std::lock_guard<std::mutex> lock(ctx->mu);
     auto it = ctx->ops.find(side);
     if (it != ctx->ops.end() && it->second->host.nlevels >= nlev) return it->second;
+    if (lookup_only)
+        throw Unsupported{"the context holds no operators for leaf side " + std::to_string(side) + " with " +
+                          std::to_string(nlev) + " heights (a plan of such a point set builds them)"};
     auto co = std::make_unique<CachedOps>();
     nlev = std::max(nlev, 1);
     co->host = build_operators(side, nlev, operator_params(ctx->opt));
@@ -527,7 +572,9 @@ OpsPtrs ops_ptrs(const CachedOps* co) {
 // Stager is destroyed, which must come after the stream has passed the copies.
 class Stager {
   public:
-    explicit Stager(lfmm_ctx* ctx) : ctx_(ctx) {}
+    // direct: plain copies from pageable host memory (no pinned blocks), kept alive until the
+    // Stager is destroyed, which must come after the stream has passed them
+    explicit Stager(lfmm_ctx* ctx, bool direct = false) : ctx_(ctx), direct_(direct) {}
     Stager(const Stager&) = delete;
     Stager& operator=(const Stager&) = delete;
     template <class T>
@@ -547,6 +594,15 @@ class Stager {
                 ++j;
             }
             const size_t len = size_t(end - pieces_[i].dst);
+            if (direct_) {
+                kept_.emplace_back(len);
+                for (size_t k = i; k < j; ++k)
+                    std::memcpy(kept_.back().data() + (pieces_[k].dst - pieces_[i].dst), pieces_[k].data.data(),
+                                pieces_[k].data.size());
+                LFMM_HIP(hipMemcpyAsync(pieces_[i].dst, kept_.back().data(), len, hipMemcpyHostToDevice, st));
+                i = j;
+                continue;
+            }
             size_t cls = 0;
             char* h = static_cast<char*>(ctx_->pinned.acquire(len, &cls));
             held_.push_back({h, cls});
@@ -572,8 +628,10 @@ class Stager {
         std::vector<char> data;
     };
     lfmm_ctx* ctx_;
+    bool direct_ = false;
     std::vector<Piece> pieces_;
     std::vector<std::pair<void*, size_t>> held_;
+    std::vector<std::vector<char>> kept_;
 };
 
 // On the way out of a failed build: finish the device work before the blocks it uses go
@@ -646,7 +704,8 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     const int32_t nch = int32_t(chunks.size());
 
     // ---- temporaries sized by n (one reserve per take) ------------------------------------
-    Arena tmp(&ctx->pool);
+    StaticRegion* const sreg = pl->sreg;
+    Arena tmp(&ctx->pool, sreg);
     tmp.reserve(size_t(nseg) * sizeof(void*));  // coordinate segments
     tmp.reserve(size_t(nseg + 1) * 4);          // segment offsets
     tmp.reserve(size_t(K + 1) * 4);             // pt_off
@@ -676,16 +735,22 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     const int32_t nstats = K * (kMaxLevels + 3);
     int32_t* d_stats = tmp.take<int32_t>(size_t(nstats) + 1);   // zeroed by the key kernel
     int32_t* d_dmax = tmp.take<int32_t>(1);
-    // host-visible results of the two read-backs (pinned: the root boxes are written there by
-    // the kernel itself, the level statistics by one copy)
+    // results of the two read-backs: pinned host memory that the kernels write (the root boxes
+    // by the kernel itself, the level statistics by one copy); in the static workspace, device
+    // memory copied back into rb_host
+    const size_t rb_words = size_t(K) * (kMaxLevels + 7);
     size_t rb_cls = 0;
-    int32_t* rb = static_cast<int32_t*>(ctx->pinned.acquire(size_t(K) * (kMaxLevels + 7) * 4, &rb_cls));
+    int32_t* rb = sreg ? static_cast<int32_t*>(sreg->take(rb_words * 4))
+                       : static_cast<int32_t*>(ctx->pinned.acquire(rb_words * 4, &rb_cls));
     struct Release {
         lfmm_ctx* c;
         void* p;
         size_t cls;
-        ~Release() { c->pinned.release(p, cls); }
-    } rb_guard{ctx, rb, rb_cls};
+        ~Release() {
+            if (p) c->pinned.release(p, cls);
+        }
+    } rb_guard{ctx, sreg ? nullptr : rb, rb_cls};
+    std::vector<int32_t> rb_host(sreg ? rb_words : 0);
     int32_t* bb = rb;                      // [K][4] root boxes
     int32_t* stats = rb + size_t(K) * 4;   // [K][34] histograms, then [K] maxima
     int32_t* d_xyc = (nseg > 1) ? tmp.take<int32_t>(size_t(n) * 2) : nullptr;
@@ -697,7 +762,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     void* rscr = tmp.take<char>(radix_scratch_bytes(n));
     void* sscr = tmp.take<char>(scan_scratch_bytes(n, 1));
 
-    Stager stage_a(ctx);
+    Stager stage_a(ctx, sreg != nullptr);
     stage_a.add(d_xytab, seg_ptr);
     stage_a.add(d_segoff, seg_off);
     stage_a.add(d_ptoff, pl->pt_off);
@@ -723,7 +788,8 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     // root boxes straight to pinned host memory, and the instance table of the next kernels
     // (N_leaf too when there is one for all) straight to the device
     launch_bbox_final(d_part, d_chfirst, d_ptoff, K, std::max(ml_all, 0), bb, d_inst0, d_dmax, st);
-    Fence bb_ready(st);
+    std::unique_ptr<Fence> bb_ready;
+    if (!sreg) bb_ready = std::make_unique<Fence>(st);
     // Morton keys and, for large inputs, the first two passes of their sort go out before the
     // host reads the root boxes: the keys need only the device's instance table, and distinct
     // points need at least 16 key bits once there are 2^16 of them (a pass over digits that
@@ -733,7 +799,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     int which = radix_sort_passes(keys, vals, keys_tmp, vals_tmp, n, 0, early_passes, true, rscr, st);
     // point storage, taken while the device works
     Arena& mp = pl->mem_pts;
-    mp.set_pool(&ctx->pool);
+    mp.set_pool(&ctx->pool, sreg);
     mp.reserve(size_t(n) * 8);                  // pts
     mp.reserve(size_t(n) * 4);                  // perm
     mp.reserve(size_t(n) * 4);                  // pinst
@@ -745,7 +811,13 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     pl->pinst = mp.take<int32_t>(n);
     pl->pkey = mp.take<uint32_t>(n);
     pl->fs = mp.take<double>(n);
-    LFMM_HIP(hipEventSynchronize(bb_ready.ev));
+    if (sreg) {
+        LFMM_HIP(hipMemcpyAsync(rb_host.data(), bb, size_t(K) * 16, hipMemcpyDeviceToHost, st));
+        LFMM_HIP(hipStreamSynchronize(st));
+        bb = rb_host.data();
+    } else {
+        LFMM_HIP(hipEventSynchronize(bb_ready->ev));
+    }
     pl->inst.assign(size_t(K), InstInfo{});
     int Dmax = 0;
     for (int32_t k = 0; k < K; ++k) {
@@ -772,7 +844,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     if (2 * Dmax + ibits > 64) throw std::out_of_range("too many instances for the coordinate extent");
     pl->Dmax = Dmax;
 
-    Stager stage_b(ctx);
+    Stager stage_b(ctx, sreg != nullptr);
     if (ml_all <= 0) {   // per-instance N_leaf: the host writes the instance table
         stage_b.add(d_inst0, pl->inst);
         stage_b.flush(st);
@@ -788,6 +860,11 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     // ---- leaf levels and box counts ---------------------------------------------------------
     launch_level_stats(skeys, svals, d_chunks, nch, d_inst0, Dmax, K, pl->pts, pl->perm, pl->pinst, cl, d_stats,
                        d_stats + nstats, stats, st);
+    if (sreg) {
+        LFMM_HIP(hipMemcpyAsync(rb_host.data() + size_t(K) * 4, stats, (rb_words - size_t(K) * 4) * 4,
+                                hipMemcpyDeviceToHost, st));
+        stats = rb_host.data() + size_t(K) * 4;
+    }
     LFMM_HIP(hipStreamSynchronize(st));
     const int32_t* hist = stats;
     const int32_t* maxc = stats + size_t(K) * (kMaxLevels + 2);
@@ -827,7 +904,8 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     pl->Hmax = Lmax;
     if (side_of.size() > 64) throw std::out_of_range("more than 64 distinct leaf sides in one plan");
     pl->ops.resize(side_of.size());
-    for (size_t o = 0; o < side_of.size(); ++o) pl->ops[o] = get_ops(ctx, side_of[o], nlev_of_side[o], st);
+    for (size_t o = 0; o < side_of.size(); ++o)
+        pl->ops[o] = get_ops(ctx, side_of[o], nlev_of_side[o], st, sreg != nullptr);
 
     // instance order inside every height block: by operator set, then deepest first, so that
     // the boxes of one operator set with level >= 2 (or >= 3) form one contiguous range
@@ -947,7 +1025,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
 
     // small tables, uploaded in one copy (ExecPtrs last: written at execute time)
     Arena& ms = pl->mem_small;
-    ms.set_pool(&ctx->pool);
+    ms.set_pool(&ctx->pool, sreg);
     ms.reserve(size_t(K) * sizeof(InstInfo));
     ms.reserve(size_t(64) * sizeof(OpsPtrs));
     ms.reserve(size_t(K));                      // far flags
@@ -970,7 +1048,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     const int64_t nb = pl->nbox, nl = pl->nleaf;
     const int P = kRankPad;
     Arena& mb = pl->mem_box;
-    mb.set_pool(&ctx->pool);
+    mb.set_pool(&ctx->pool, sreg);
     mb.reserve(size_t(nb) * 8);                          // key
     for (int q = 0; q < 5; ++q) mb.reserve(size_t(nb) * 4);   // pt0, pt1, parent, inst, (pad)
     mb.reserve(size_t(nb));                              // level
@@ -1013,7 +1091,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     }
 
     // ---- tables ---------------------------------------------------------------------------------
-    Stager stage_c(ctx);
+    Stager stage_c(ctx, sreg != nullptr);
     stage_c.add(d_roots, root_list);
     stage_c.add(pl->d_inst, pl->inst);
     std::vector<OpsPtrs> optab(64);   // the whole table, so that the upload stays one copy
@@ -1029,7 +1107,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     stage_c.flush(st);
 
     // ---- leaves ---------------------------------------------------------------------------------
-    Arena tmp2(&ctx->pool);
+    Arena tmp2(&ctx->pool, sreg);
     const int rows = std::max(Lmax, 1);
     tmp2.reserve(size_t(nl) * 4);                        // leaf first point
     tmp2.reserve(size_t(nl) * 8);                        // leaf keys
@@ -1073,10 +1151,15 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     LFMM_HIP(hipGetLastError());
     // staging for the per-execute pointer table of batched plans (and of graph replays,
     // whose kernels always read the table)
-    pl->use_graph = (ctx->opt.flags & LFMM_FLAG_GRAPH) != 0;
+    pl->use_graph = (ctx->opt.flags & LFMM_FLAG_GRAPH) != 0 && !sreg;
     if (K > 1 || pl->use_graph) {
         pl->h_exec = static_cast<ExecPtrs*>(ctx->pinned.acquire(size_t(K) * sizeof(ExecPtrs), &pl->h_exec_cls));
         LFMM_HIP(hipEventCreateWithFlags(&pl->exec_copied, hipEventDisableTiming));
+    }
+    pl->build_stream = st;
+    if (sreg) {   // the staged host copies must have been read before they go
+        LFMM_HIP(hipStreamSynchronize(st));
+        return;
     }
     // no synchronisation: the temporaries and staging blocks go back to their pools once the
     // device has passed the end of the build, and executes on other streams wait for it
@@ -1135,7 +1218,7 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
 void run_forest(lfmm_plan* pl, const double* const* f, double* const* u, hipStream_t st) {
     if (st != pl->build_stream) {
         pl->one_stream = false;
-        LFMM_HIP(hipStreamWaitEvent(st, pl->built->ev, 0));
+        if (pl->built) LFMM_HIP(hipStreamWaitEvent(st, pl->built->ev, 0));
     }
     if (pl->K == 1 && !pl->use_graph) {
         enqueue_passes(pl, nullptr, f[0], u[0], pl->timing_mask, st);
@@ -1202,6 +1285,8 @@ lfmm_status guarded(F&& f) {
         return fail(LFMM_E_HIP, e.msg);
     } catch (const NoMemory& e) {
         return fail(LFMM_E_NOMEM, e.msg);
+    } catch (const Unsupported& e) {
+        return fail(LFMM_E_UNSUPPORTED, e.msg);
     } catch (const std::bad_alloc&) {
         return fail(LFMM_E_NOMEM, "host allocation failed");
     } catch (const std::out_of_range& e) {
@@ -1245,8 +1330,9 @@ lfmm_status create_forest(lfmm_ctx* ctx, int32_t K, const InstanceInput* in, int
 // 1e-12 sum |f|, the well-posedness condition of Section 1) is reported as LFMM_W_NONZERO_SUM,
 // and the finite sum is still computed.  Synchronises the stream (the statistics are read
 // back).  Runs inside guarded().
-lfmm_status check_loads(lfmm_ctx* ctx, int32_t K, const double* const* f, const int32_t* nsrc, hipStream_t st) {
-    Arena a(&ctx->pool);
+lfmm_status check_loads(lfmm_ctx* ctx, int32_t K, const double* const* f, const int32_t* nsrc, hipStream_t st,
+                        StaticRegion* sreg = nullptr) {
+    Arena a(&ctx->pool, sreg);
     a.reserve(load_stats_scratch_bytes());
     a.reserve(size_t(K) * 3 * sizeof(double));
     a.allocate();
@@ -1277,7 +1363,7 @@ lfmm_status execute_forest(lfmm_plan* pl, const double* const* f, double* const*
         LFMM_HIP(hipSetDevice(pl->ctx->device));
         lfmm_status res = LFMM_OK;
         if (check || (pl->ctx->opt.flags & LFMM_FLAG_CHECK_LOADS)) {
-            res = check_loads(pl->ctx, pl->K, f, pl->nsrc.data(), as_stream(stream));
+            res = check_loads(pl->ctx, pl->K, f, pl->nsrc.data(), as_stream(stream), pl->sreg);
             if (res < 0) return res;
         }
         run_forest(pl, f, u, as_stream(stream));
@@ -1338,6 +1424,10 @@ lfmm_status lfmm_ctx_create(int32_t device, const lfmm_options* opt, lfmm_ctx** 
         auto ctx = std::make_unique<lfmm_ctx>();
         ctx->device = device;
         ctx->opt = o;
+        // the allocation-free solve's workspace on this device
+        void* sp = nullptr;
+        LFMM_HIP(hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)));
+        ctx->static_scratch = sp;
         // phi: the quadrature table (radius 128), then eq. 3.1 precomputed out to the device
         // table's radius (neighbour offsets of leaves up to side 128 stay inside it)
         const std::vector<double>& tab = phi_table();
@@ -1714,6 +1804,40 @@ lfmm_status lfmm_solve(lfmm_ctx* ctx, int64_t n, const int32_t* xy, const double
     }
     lfmm_plan_destroy(pl);
     return s;
+}
+
+lfmm_status lfmm_solve_static(lfmm_ctx* ctx, int64_t n, const int32_t* xy, const double* f, double* u,
+                              void* stream) {
+    if (!ctx || !xy || !f || !u) return fail(LFMM_E_INVAL, "null argument");
+    if (n < 1) return fail(LFMM_E_INVAL, "n must be at least 1");
+    if (n > kStaticMaxPoints)
+        return fail(LFMM_E_RANGE, "lfmm_solve_static takes at most " + std::to_string(kStaticMaxPoints) + " points");
+    if (!ctx->static_scratch) return fail(LFMM_E_HIP, "no static workspace on this device");
+    std::lock_guard<std::mutex> lock(g_static_mu[ctx->device & 63]);
+    return guarded([&]() -> lfmm_status {
+        LFMM_HIP(hipSetDevice(ctx->device));
+        hipStream_t st = as_stream(stream);
+        StaticRegion reg;
+        reg.base = static_cast<char*>(ctx->static_scratch);
+        reg.cap = kStaticScratchBytes;
+        lfmm_plan pl;
+        pl.ctx = ctx;
+        pl.sreg = &reg;
+        InstanceInput in;
+        in.n_src = n;
+        in.src = xy;
+        build_forest(&pl, 1, &in, 0, st);
+        const double* fa[1] = {f};
+        double* ua[1] = {u};
+        const lfmm_status res = check_loads(ctx, 1, fa, pl.nsrc.data(), st, &reg);
+        if (res < 0) return res;
+        const std::string warn = g_last_error;
+        run_forest(&pl, fa, ua, st);
+        LFMM_HIP(hipGetLastError());
+        LFMM_HIP(hipStreamSynchronize(st));
+        if (res != LFMM_OK) g_last_error = warn;
+        return res;
+    });
 }
 
 lfmm_status lfmm_direct(lfmm_ctx* ctx, int64_t nt, const int32_t* txy, int64_t ns, const int32_t* sxy,

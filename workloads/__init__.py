@@ -16,4 +16,7 @@ from .generators import (  # noqa: F401
     config_serving_request,
     serving_request_size,
     sample_targets,
+    inclusion_bars,
+    box_boundary,
+    lshape_boundary,
 )

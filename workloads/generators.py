@@ -178,3 +178,93 @@ def sample_targets(seed: int, n: int, k: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     k = min(int(k), int(n))
     return np.sort(rng.choice(n, size=k, replace=False)).astype(np.int64)
+
+
+# ----------------------------------------------------------------------------------------
+# Geometries of the two applications of the lattice convolution (lattice with inclusions,
+# Dirichlet problem on a finite lattice).  Points and coefficients only.
+# ----------------------------------------------------------------------------------------
+
+def inclusion_bars(rng: np.random.Generator, n_bars: int, side: int, origin=(0, 0),
+                   frac_removed: float = 0.15, frac_added: float = 0.15):
+    """``n_bars`` distinct bar modifications in a side x side box.
+
+    Returns ``(bars, delta)``: bars [n, 4] int32 rows (a1, a2, b1, b2), the two nodes of the
+    bar; delta [n] float64, the change of its conductance.  Lattice bars (unit horizontal or
+    vertical) are removed (delta = -1), weakened (delta in (-0.9, 0)) or strengthened (delta
+    in (0, 3)); added bars join diagonal neighbours (delta in (0.1, 2)).  No node loses more
+    than one of its bars, so no part of the lattice is cut off and (A + B) stays invertible
+    on decaying functions.
+    """
+    seen, removed = set(), {}
+    bars, delta = [], []
+    ox, oy = int(origin[0]), int(origin[1])
+    while len(bars) < n_bars:
+        x, y = int(rng.integers(0, side)), int(rng.integers(0, side))
+        r = rng.uniform()
+        if r < frac_added:
+            dx, dy = (1, 1) if rng.uniform() < 0.5 else (1, -1)
+            d = float(rng.uniform(0.1, 2.0))
+            kind = "add"
+        else:
+            dx, dy = (1, 0) if rng.uniform() < 0.5 else (0, 1)
+            kind = "remove" if r < frac_added + frac_removed else "change"
+            d = -1.0 if kind == "remove" else float(rng.choice([rng.uniform(-0.9, -0.05), rng.uniform(0.05, 3.0)]))
+        a, b = (ox + x, oy + y), (ox + x + dx, oy + y + dy)
+        key = (a, b)
+        if key in seen:
+            continue
+        if kind == "remove" and (removed.get(a, 0) >= 1 or removed.get(b, 0) >= 1):
+            continue
+        seen.add(key)
+        if kind == "remove":
+            removed[a] = removed.get(a, 0) + 1
+            removed[b] = removed.get(b, 0) + 1
+        bars.append((a[0], a[1], b[0], b[1]))
+        delta.append(d)
+    return np.array(bars, dtype=np.int32), np.array(delta, dtype=np.float64)
+
+
+# normal codes of the Dirichlet boundary: 0: +x, 1: -x, 2: +y, 3: -y (outward)
+def box_boundary(n1: int, n2: int, origin=(0, 0)):
+    """Boundary of the box [0, n1] x [0, n2] without its corners: the nodes next to the
+    interior (0, n1) x (0, n2), with outward normal codes.  Returns (gamma [m, 2] int32,
+    codes [m] int8, interior [k, 2] int32)."""
+    ox, oy = int(origin[0]), int(origin[1])
+    g, c = [], []
+    for t in range(1, n2):
+        g += [(ox, oy + t), (ox + n1, oy + t)]
+        c += [1, 0]
+    for t in range(1, n1):
+        g += [(ox + t, oy), (ox + t, oy + n2)]
+        c += [3, 2]
+    xs, ys = np.meshgrid(np.arange(1, n1) + ox, np.arange(1, n2) + oy, indexing="ij")
+    interior = np.stack([xs.ravel(), ys.ravel()], axis=1)
+    return np.array(g, dtype=np.int32), np.array(c, dtype=np.int8), interior.astype(np.int32)
+
+
+def lshape_boundary(n: int, origin=(0, 0)):
+    """L-shaped domain: the interior of [0, n]^2 minus the quadrant [n/2, n]^2; its boundary
+    nodes (outside the domain, next to it) with outward normal codes chosen so that the
+    normal step leaves the domain.  Returns (gamma, codes, interior)."""
+    h = n // 2
+    inside = lambda x, y: 0 < x < n and 0 < y < n and not (x >= h and y >= h)
+    interior = [(x, y) for x in range(n + 1) for y in range(n + 1) if inside(x, y)]
+    iset = set(interior)
+    steps = [(1, 0), (-1, 0), (0, 1), (0, -1)]
+    g, c = [], []
+    for x in range(-1, n + 2):
+        for y in range(-1, n + 2):
+            if (x, y) in iset:
+                continue
+            nb = [k for k, (dx, dy) in enumerate(steps) if (x + dx, y + dy) in iset]
+            if not nb:
+                continue
+            out = [k for k, (dx, dy) in enumerate(steps) if (x + dx, y + dy) not in iset and k ^ 1 in nb]
+            code = out[0] if out else nb[0] ^ 1
+            g.append((x, y))
+            c.append(code)
+    ox, oy = int(origin[0]), int(origin[1])
+    gam = np.array(g, dtype=np.int64) + [ox, oy]
+    inter = np.array(interior, dtype=np.int64) + [ox, oy]
+    return gam.astype(np.int32), np.array(c, dtype=np.int8), inter.astype(np.int32)

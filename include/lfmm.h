@@ -343,6 +343,75 @@ lfmm_status lfmm_server_wait(lfmm_server* srv, uint64_t ticket, double timeout_s
 /* Finishes every queued request, stops the worker and frees the server. */
 lfmm_status lfmm_server_destroy(lfmm_server* srv);
 
+/* ---- Section 10: iterative solves with the lattice convolution as the fast operator ---- */
+
+/* Restarted GMRES (classical Gram-Schmidt run twice) on device vectors; the operator is applied
+ * through resident plans.  tol: relative residual |b - A x| / |b| (default 1e-12); max_iter:
+ * default 500; restart: Krylov dimension per cycle (default 50, at most 512).  Fields <= 0
+ * take the defaults. */
+typedef struct lfmm_solver_options {
+    double tol;
+    int32_t max_iter;
+    int32_t restart;
+} lfmm_solver_options;
+
+typedef struct lfmm_solver_stats {
+    int32_t iterations;       /* operator applications inside the Krylov cycles           */
+    int32_t converged;        /* 1 if the true relative residual is <= tol                */
+    double rel_residual;      /* true |b - A x| / |b| of the returned solution             */
+} lfmm_solver_stats;
+
+/* Lattice with inclusions (Section 10.1, eq. 10.1-10.4).  The lattice's bars are modified by B:
+ * bar k joins the nodes (bars_host[4k], bars_host[4k+1]) and (bars_host[4k+2], bars_host[4k+3])
+ * and changes its conductance by delta_host[k] (-1 removes a unit bar of the 5-point lattice;
+ * a bar between nodes that had none is added with delta > 0), so that
+ * (B w)(a) += delta (w(a) - w(b)) and (B w)(b) += delta (w(b) - w(a)).  The problem is
+ * (A + B) u = 0 with u -> v = c1 m1 + c2 m2 at infinity (eq. 10.2).  Create builds the
+ * node set Omega_inc (the bars' end points, in first-appearance order), B on it, and a
+ * resident plan for S (convolution with phi) on Omega_inc; host arrays are read during the
+ * call.  LFMM_E_INVAL for a bar from a node to itself or a non-finite delta.  The caller
+ * keeps (A + B) invertible on decaying functions (no part of the lattice cut off). */
+typedef struct lfmm_inclusions lfmm_inclusions;
+lfmm_status lfmm_inclusions_create(lfmm_ctx* ctx, int64_t n_bars, const int32_t* bars_host,
+                                   const double* delta_host, void* stream, lfmm_inclusions** out);
+/* Number of nodes of Omega_inc and, if nodes_xy_host is not NULL, their coordinates [n][2]. */
+lfmm_status lfmm_inclusions_nodes(const lfmm_inclusions* inc, int64_t* n_nodes, int32_t* nodes_xy_host);
+/* Solves mu + B S mu = -B S B v on Omega_inc (eq. 10.4) by GMRES, each iteration one
+ * execute of the resident plan; mu_dev[n_nodes] (device) receives mu.  Synchronises. */
+lfmm_status lfmm_inclusions_solve(lfmm_inclusions* inc, double c1, double c2, const lfmm_solver_options* opt,
+                                  double* mu_dev, lfmm_solver_stats* stats, void* stream);
+/* u = v - S (B v + mu) at n_tgt targets tgt_xy_dev[2 n_tgt] (device) into u_dev[n_tgt]: the
+ * recovery of the potential after eq. 10.4, read with +mu (with the paper's definitions,
+ * A w = -(B v + B w) for w = u - v; the printed minus sign does not satisfy eq. 10.1). */
+lfmm_status lfmm_inclusions_potential(lfmm_inclusions* inc, double c1, double c2, const double* mu_dev,
+                                      int64_t n_tgt, const int32_t* tgt_xy_dev, double* u_dev, void* stream);
+/* Frees the object and its plan; call it before lfmm_ctx_destroy of its context. */
+lfmm_status lfmm_inclusions_destroy(lfmm_inclusions* inc);
+
+/* Dirichlet problem on a finite lattice (Section 10.2, eq. 10.5-10.7).  gamma_xy_host[n][2]:
+ * the boundary nodes Gamma (outside the domain, next to it); normal_host[n]: each node's
+ * outward unit normal nu(n) as a code 0: +x, 1: -x, 2: +y, 3: -y, chosen so that n + nu(n)
+ * lies outside the domain.  The double-layer-like operator of eq. 10.6, read as the difference
+ * along nu acting on the source variable,
+ *     [D q](m) = sum_{n in Gamma} [phi(m - n - nu(n)) - phi(m - n)] q(n),
+ * is the field of a dipole per boundary node, so A (D q) = 0 in the domain.  Create builds a
+ * resident plan with the 2n dipole ends as sources and Gamma as targets. */
+typedef struct lfmm_dirichlet lfmm_dirichlet;
+lfmm_status lfmm_dirichlet_create(lfmm_ctx* ctx, int64_t n, const int32_t* gamma_xy_host, const int8_t* normal_host,
+                                  void* stream, lfmm_dirichlet** out);
+/* out_dev[n] = (D q)(Gamma) for q_dev[n]: the matrix of eq. 10.7 applied by the FMM. */
+lfmm_status lfmm_dirichlet_apply(lfmm_dirichlet* dir, const double* q_dev, double* out_dev, void* stream);
+/* Solves D q = g on Gamma (eq. 10.7) by GMRES (the paper cites an O(N_Gamma) direct inversion
+ * that it does not describe); g_dev, q_dev: device [n].  Synchronises. */
+lfmm_status lfmm_dirichlet_solve(lfmm_dirichlet* dir, const double* g_dev, const lfmm_solver_options* opt,
+                                 double* q_dev, lfmm_solver_stats* stats, void* stream);
+/* u_dev[n_tgt] = (D q)(t) at n_tgt targets tgt_xy_dev (device): the solution of eq. 10.5 at
+ * interior nodes once q solves eq. 10.7. */
+lfmm_status lfmm_dirichlet_potential(lfmm_dirichlet* dir, const double* q_dev, int64_t n_tgt,
+                                     const int32_t* tgt_xy_dev, double* u_dev, void* stream);
+/* Frees the object and its plan; call it before lfmm_ctx_destroy of its context. */
+lfmm_status lfmm_dirichlet_destroy(lfmm_dirichlet* dir);
+
 /* ---- host-only calls (no GPU needed): the library's own phi and operators ------------ */
 
 /* phi at n integer offsets mxy_host[2n] (table for |m|_inf <= 128 from the reduced 1-D

@@ -13,6 +13,8 @@ from ._lib import (  # noqa: F401
     Context,
     Plan,
     Server,
+    Inclusions,
+    Dirichlet,
     HostOperators,
     host_phi,
     library_path,
@@ -20,5 +22,5 @@ from ._lib import (  # noqa: F401
     PRECISIONS,
 )
 
-__all__ = ["LfmmError", "LfmmWarning", "Context", "Plan", "Server", "HostOperators", "host_phi", "library_path",
+__all__ = ["LfmmError", "LfmmWarning", "Context", "Plan", "Server", "Inclusions", "Dirichlet", "HostOperators", "host_phi", "library_path",
            "exported_symbols", "PRECISIONS"]

@@ -49,6 +49,14 @@ class _ServerOptions(ctypes.Structure):
                 ("max_batch_points", _i64)]
 
 
+class _SolverOptions(ctypes.Structure):
+    _fields_ = [("tol", _dbl), ("max_iter", _i32), ("restart", _i32)]
+
+
+class _SolverStats(ctypes.Structure):
+    _fields_ = [("iterations", _i32), ("converged", _i32), ("rel_residual", _dbl)]
+
+
 class _RequestStats(ctypes.Structure):
     _fields_ = [("status", _i32), ("batch_size", _i32), ("batch_id", _i64), ("t_submit", _dbl),
                 ("t_admit", _dbl), ("t_done", _dbl)]
@@ -103,6 +111,16 @@ def _load():
         "lfmm_server_submit": [_vp, _i64, _vp, _vp, _vp, _vp, _vp],
         "lfmm_server_wait": [_vp, ctypes.c_uint64, _dbl, _vp],
         "lfmm_server_destroy": [_vp],
+        "lfmm_inclusions_create": [_vp, _i64, _vp, _vp, _vp, _vp],
+        "lfmm_inclusions_nodes": [_vp, _vp, _vp],
+        "lfmm_inclusions_solve": [_vp, _dbl, _dbl, _vp, _vp, _vp, _vp],
+        "lfmm_inclusions_potential": [_vp, _dbl, _dbl, _vp, _i64, _vp, _vp, _vp],
+        "lfmm_inclusions_destroy": [_vp],
+        "lfmm_dirichlet_create": [_vp, _i64, _vp, _vp, _vp, _vp],
+        "lfmm_dirichlet_apply": [_vp, _vp, _vp, _vp],
+        "lfmm_dirichlet_solve": [_vp, _vp, _vp, _vp, _vp, _vp],
+        "lfmm_dirichlet_potential": [_vp, _vp, _i64, _vp, _vp, _vp],
+        "lfmm_dirichlet_destroy": [_vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -546,6 +564,127 @@ class Server:
                 _lib.lfmm_server_destroy(self._h)
             self._h = None
             self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _solver_options(tol=None, max_iter=None, restart=None) -> _SolverOptions:
+    return _SolverOptions(float(tol or 0.0), int(max_iter or 0), int(restart or 0))
+
+
+class Inclusions:
+    """lfmm_inclusions: a lattice whose bars are modified (Section 10.1).  bars: [n, 4] int32
+    (a1, a2, b1, b2) and delta: [n] float64 (host arrays); the resident plan applies S on the
+    nodes the bars touch."""
+
+    def __init__(self, ctx: Context, bars, delta, stream=None):
+        b = np.ascontiguousarray(np.asarray(bars, dtype=np.int32).reshape(-1, 4))
+        d = np.ascontiguousarray(np.asarray(delta, dtype=np.float64).reshape(-1))
+        if len(b) != len(d):
+            raise ValueError("one conductance change per bar")
+        h = ctypes.c_void_p()
+        _check(_lib.lfmm_inclusions_create(ctx._h, len(b), b.ctypes.data_as(_vp), d.ctypes.data_as(_vp),
+                                           _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+        ctx._plans.add(self)          # closed before the context, which would free its plan
+        n = ctypes.c_int64()
+        _check(_lib.lfmm_inclusions_nodes(self._h, ctypes.byref(n), None))
+        self.nodes = np.empty((n.value, 2), dtype=np.int32)
+        _check(_lib.lfmm_inclusions_nodes(self._h, ctypes.byref(n), self.nodes.ctypes.data_as(_vp)))
+
+    def solve(self, c1: float, c2: float, mu=None, stream=None, **opts):
+        """mu of eq. 10.4 for the far field v = c1 m1 + c2 m2; returns (mu, stats dict)."""
+        import torch
+        if mu is None:
+            mu = _empty_on(stream, len(self.nodes), torch.device("cuda", self.ctx.device))
+        o = _solver_options(**opts)
+        st = _SolverStats()
+        _check(_lib.lfmm_inclusions_solve(self._h, float(c1), float(c2), ctypes.byref(o),
+                                          _dev_tensor(mu, torch.float64, (), "mu"), ctypes.byref(st),
+                                          _stream_handle(stream)))
+        return mu, {name: getattr(st, name) for name, _ in _SolverStats._fields_}
+
+    def potential(self, c1: float, c2: float, mu, targets, u=None, stream=None):
+        """u = v - S(B v + mu) at the targets [m, 2] (device int32)."""
+        import torch
+        m = int(targets.shape[0])
+        if u is None:
+            u = _empty_on(stream, m, mu.device)
+        _check(_lib.lfmm_inclusions_potential(self._h, float(c1), float(c2), _dev_tensor(mu, torch.float64, (), "mu"),
+                                              m, _dev_tensor(targets, torch.int32, (2,), "targets"),
+                                              _dev_tensor(u, torch.float64, (), "u"), _stream_handle(stream)))
+        return u
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            if getattr(self.ctx, "_h", None):
+                _lib.lfmm_inclusions_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Dirichlet:
+    """lfmm_dirichlet: the double-layer-like operator D of a finite lattice (Section 10.2).
+    gamma: [n, 2] int32 boundary nodes, normals: [n] codes 0..3 (+x, -x, +y, -y) (host)."""
+
+    def __init__(self, ctx: Context, gamma, normals, stream=None):
+        g = np.ascontiguousarray(np.asarray(gamma, dtype=np.int32).reshape(-1, 2))
+        c = np.ascontiguousarray(np.asarray(normals, dtype=np.int8).reshape(-1))
+        if len(g) != len(c):
+            raise ValueError("one normal per boundary node")
+        h = ctypes.c_void_p()
+        _check(_lib.lfmm_dirichlet_create(ctx._h, len(g), g.ctypes.data_as(_vp), c.ctypes.data_as(_vp),
+                                          _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+        ctx._plans.add(self)
+        self.n = len(g)
+
+    def apply(self, q, out=None, stream=None):
+        import torch
+        if out is None:
+            out = _empty_on(stream, self.n, q.device)
+        _check(_lib.lfmm_dirichlet_apply(self._h, _dev_tensor(q, torch.float64, (), "q"),
+                                         _dev_tensor(out, torch.float64, (), "out"), _stream_handle(stream)))
+        return out
+
+    def solve(self, g, q=None, stream=None, **opts):
+        """q with D q = g on the boundary (eq. 10.7); returns (q, stats dict)."""
+        import torch
+        if q is None:
+            q = _empty_on(stream, self.n, g.device)
+        o = _solver_options(**opts)
+        st = _SolverStats()
+        _check(_lib.lfmm_dirichlet_solve(self._h, _dev_tensor(g, torch.float64, (), "g"), ctypes.byref(o),
+                                         _dev_tensor(q, torch.float64, (), "q"), ctypes.byref(st),
+                                         _stream_handle(stream)))
+        return q, {name: getattr(st, name) for name, _ in _SolverStats._fields_}
+
+    def potential(self, q, targets, u=None, stream=None):
+        import torch
+        m = int(targets.shape[0])
+        if u is None:
+            u = _empty_on(stream, m, q.device)
+        _check(_lib.lfmm_dirichlet_potential(self._h, _dev_tensor(q, torch.float64, (), "q"), m,
+                                             _dev_tensor(targets, torch.int32, (2,), "targets"),
+                                             _dev_tensor(u, torch.float64, (), "u"), _stream_handle(stream)))
+        return u
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            if getattr(self.ctx, "_h", None):
+                _lib.lfmm_dirichlet_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:

@@ -56,6 +56,11 @@ WORKLOADS = {
                 "side ceil(4 sqrt N), N(0,1) loads mean-subtracted per instance, one forest plan per step"),
     "serving": ("Poisson arrivals of solve requests, sizes log-uniform in [1e2, 1e6], uniform or "
                 "8-cluster layout per request, through the continuous-batching server"),
+    "inclusions": ("lattice with 50,000 modified bars (removed, weakened, strengthened, added diagonals) in a "
+                   "2000x2000 box, far field v = m1 + 0.5 m2: GMRES on mu + B S mu = -B S B v over the bars' "
+                   "nodes, S by a resident plan"),
+    "dirichlet": ("Dirichlet problem on the 16384x16384 box: 65,532 boundary nodes, the dipole operator D "
+                  "applied by the FMM, GMRES on D q = g"),
 }
 TOLERANCE = {"fp64": 1e-10, "mixed": 1e-7}
 
@@ -336,6 +341,156 @@ def run_batched(args, torch, lf):
     return result
 
 
+def _laplacian_residual(u5):
+    """Relative 5-point residual A u at stencil centres from the potentials at the centres and
+    their four neighbours (rows: centre, +x, -x, +y, -y)."""
+    c, e, w, n, s = u5
+    return np.abs(4 * c - e - w - n - s)
+
+
+def _stencils(pts):
+    off = np.array([[0, 0], [1, 0], [-1, 0], [0, 1], [0, -1]], dtype=np.int32)
+    return (pts[None, :, :] + off[:, None, :]).reshape(-1, 2)
+
+
+def run_inclusions(args, torch, lf):
+    """Section 10.1 at scale: one step is one GMRES solve of eq. 10.4 on a resident plan.  The
+    value counts nodes of Omega_inc solved per second.  Accuracy at full size: the recovered u
+    satisfies (A + B) u = 0 at sampled stencils away from the bars (A u = 0 there) and at the
+    bars' nodes (A u + B u = 0), a property of the exact solution at any size."""
+    import workloads as wl
+    rng = np.random.default_rng(8)
+    bars, delta = wl.inclusion_bars(rng, 50000, 2000)
+    c1, c2 = 1.0, 0.5
+    ctx = lf.Context(0)
+    inc = lf.Inclusions(ctx, bars, delta)
+    nn = len(inc.nodes)
+    mu = torch.empty(nn, dtype=torch.float64, device="cuda")
+    for _ in range(max(args.warmup, 1)):
+        inc.solve(c1, c2, mu, tol=1e-12)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = inc.solve(c1, c2, mu, tol=1e-12)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # one S apply on the resident plan (the operator GMRES applies once per iteration)
+    plan = ctx.plan(torch.from_numpy(inc.nodes).cuda())
+    s_out = torch.empty_like(mu)
+    plan.execute(mu, s_out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        plan.execute(mu, s_out)
+    torch.cuda.synchronize()
+    apply_ms = (time.perf_counter() - t0) * 1e3 / 20
+    plan.close()
+    # (A + B) u = 0: stencils at sampled nodes and at sampled free lattice points of the box
+    smp = rng.choice(nn, size=2000, replace=False)
+    free = rng.integers(0, 2000, size=(2000, 2)).astype(np.int32)
+    centres = np.vstack([inc.nodes[smp], free]).astype(np.int32)
+    pts = _stencils(centres)
+    u = inc.potential(c1, c2, mu, torch.from_numpy(pts).cuda()).cpu().numpy().reshape(5, -1)
+    au = 4 * u[0] - u[1] - u[2] - u[3] - u[4]
+    # B u at the sampled nodes: from the bars at each node, with u at their other ends
+    others = {}
+    for (a1, a2, b1, b2), d in zip(bars.tolist(), delta.tolist()):
+        others.setdefault((a1, a2), []).append(((b1, b2), d))
+        others.setdefault((b1, b2), []).append(((a1, a2), d))
+    cen = [tuple(c) for c in centres.tolist()]
+    ends = sorted({p for c in cen for p, _ in others.get(c, [])})
+    ue = dict(zip(ends, inc.potential(c1, c2, mu, torch.from_numpy(np.array(ends, np.int32)).cuda()).cpu().numpy()))
+    bu = np.zeros(len(centres))
+    for k, c in enumerate(cen):
+        for p, d in others.get(c, []):
+            bu[k] += d * (u[0][k] - ue[p])
+    scale = np.max(np.abs(u[0] - (c1 * centres[:, 0] + c2 * centres[:, 1])))
+    resid = float(np.max(np.abs(au + bu)) / scale)
+    inc.close()
+    ctx.close()
+    config = {"workload": WORKLOADS["inclusions"], "n_bars": len(bars), "n_nodes": nn, "gmres_tol": 1e-12}
+    result = base_result(args, nn / (ms * 1e-3) / 1e6, ms, config)
+    result.update({"iterations": st["iterations"], "rel_residual": st["rel_residual"],
+                   "ms_per_iteration": ms / max(st["iterations"], 1), "s_apply_ms": apply_ms,
+                   "s_apply_msources_per_s": nn / (apply_ms * 1e-3) / 1e6,
+                   "equation_residual": resid,
+                   "equation_residual_definition": "max |(A+B)u| at 4,000 sampled stencils / max |u - v| there"})
+    if not args.no_cpu_baseline:
+        from oracle import direct as od
+        idx = wl.sample_targets(80, nn, 2000)
+        mu_h = mu.cpu().numpy()
+        t0 = time.perf_counter()
+        ref = od.direct_sum(inc.nodes[idx], inc.nodes, mu_h)
+        cpu_s = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": len(idx) / cpu_s / 1e6, "unit": "Msources/s", "cores": od.threads(),
+                                  "kind": "oracle",
+                                  "sample": "one S apply (direct sum) at %d sampled nodes x %d nodes, %.2f s; the "
+                                            "rate is targets completed per second" % (len(idx), nn, cpu_s)}
+        del ref
+    return result
+
+
+def run_dirichlet(args, torch, lf):
+    """Section 10.2 at scale: one step is one GMRES solve of eq. 10.7; the value counts boundary
+    nodes solved per second.  Accuracy at full size: D applied by the FMM against the oracle's
+    direct sum on sampled boundary nodes, the true residual of the solve, and A u = 0 at sampled
+    interior stencils (the property that makes u = D q the solution)."""
+    import workloads as wl
+    from oracle import extensions as ox
+    N = 16384
+    gamma, codes, _ = wl.box_boundary(N, N)
+    n = len(gamma)
+    rng = np.random.default_rng(9)
+    g = np.sin(1e-3 * gamma[:, 0]) * np.cos(7e-4 * gamma[:, 1]) + 0.05 * rng.standard_normal(n)
+    ctx = lf.Context(0)
+    dirp = lf.Dirichlet(ctx, gamma, codes)
+    g_d = torch.from_numpy(g).cuda()
+    q = torch.empty_like(g_d)
+    for _ in range(max(args.warmup, 1)):
+        dirp.solve(g_d, q, tol=1e-12)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = dirp.solve(g_d, q, tol=1e-12)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    out = torch.empty_like(g_d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        dirp.apply(q, out)
+    torch.cuda.synchronize()
+    apply_ms = (time.perf_counter() - t0) * 1e3 / 20
+    qh = q.cpu().numpy()
+    # interior stencils
+    centres = rng.integers(2, N - 1, size=(3000, 2)).astype(np.int32)
+    u = dirp.potential(q, torch.from_numpy(_stencils(centres)).cuda()).cpu().numpy().reshape(5, -1)
+    lap = float(np.max(np.abs(4 * u[0] - u[1] - u[2] - u[3] - u[4])) / np.max(np.abs(u[0])))
+    config = {"workload": WORKLOADS["dirichlet"], "n_boundary": n, "box": N, "gmres_tol": 1e-12}
+    result = base_result(args, n / (ms * 1e-3) / 1e6, ms, config)
+    result.update({"iterations": st["iterations"], "rel_residual": st["rel_residual"],
+                   "ms_per_iteration": ms / max(st["iterations"], 1), "d_apply_ms": apply_ms,
+                   "d_apply_msources_per_s": 2 * n / (apply_ms * 1e-3) / 1e6,
+                   "interior_laplacian_residual": lap})
+    if not args.no_cpu_baseline:
+        from oracle import direct as od
+        idx = wl.sample_targets(90, n, 2000)
+        t0 = time.perf_counter()
+        ref = ox.d_apply(gamma, codes, qh, gamma[idx])
+        cpu_s = time.perf_counter() - t0
+        d_full = out.cpu().numpy()[idx]
+        result["rel_err_vs_oracle"] = float(np.linalg.norm(d_full - ref) / np.linalg.norm(ref))
+        result["rel_err_sample"] = len(idx)
+        result["tolerance"] = TOLERANCE["fp64"]
+        result["cpu_baseline"] = {"value": len(idx) / cpu_s / 1e6, "unit": "Msources/s", "cores": od.threads(),
+                                  "kind": "oracle",
+                                  "sample": "D q by direct sum at %d sampled boundary nodes x %d dipole ends, %.2f s; "
+                                            "the rate is targets completed per second" % (len(idx), 2 * n, cpu_s)}
+    dirp.close()
+    ctx.close()
+    return result
+
+
 def run_serving(args, torch, lf):
     import workloads as wl
     m = args.requests
@@ -442,6 +597,10 @@ def main() -> None:
         del a, b
     if args.workload == "batched":
         result = run_batched(args, torch, lf)
+    elif args.workload == "inclusions":
+        result = run_inclusions(args, torch, lf)
+    elif args.workload == "dirichlet":
+        result = run_dirichlet(args, torch, lf)
     elif args.workload == "serving":
         result = run_serving(args, torch, lf)
     else:

@@ -79,7 +79,19 @@ typedef struct lfmm_options {
     int32_t max_rank;         /* cap on the skeleton size P, 16..64, multiple of 16;
                                  default 48                                                */
     int32_t flags;            /* LFMM_FLAG_* bits, default 0                               */
+    int32_t stencil;          /* lattice operator A whose fundamental solution phi is used
+                                 (lfmm_stencil); default LFMM_STENCIL_5                    */
 } lfmm_options;
+
+/* The lattice operator of a context (A phi = delta).  The method needs only phi (Sections 1,
+ * 3.1: it carries over to other constant-coefficient difference operators). */
+typedef enum lfmm_stencil {
+    LFMM_STENCIL_5 = 0,       /* 4 u(m) - sum of the 4 neighbours, eq. (1.2)               */
+    LFMM_STENCIL_9 = 1        /* isotropic 9-point: (20 u(m) - 4 (4 neighbours) - (4 diagonal
+                                 neighbours)) / 6; phi by the same reduced integral, its far
+                                 field by an expansion of the form of eq. (3.1) fitted to the
+                                 tabulated values                                         */
+} lfmm_stencil;
 
 /* options.flags: lfmm_execute / lfmm_execute_instances replay a HIP graph of the evaluation
  * passes, recorded at the plan's first execute (one graph launch per execute instead of one
@@ -414,9 +426,10 @@ lfmm_status lfmm_dirichlet_destroy(lfmm_dirichlet* dir);
 
 /* ---- host-only calls (no GPU needed): the library's own phi and operators ------------ */
 
-/* phi at n integer offsets mxy_host[2n] (table for |m|_inf <= 128 from the reduced 1-D
- * integral of the remark closing Section 3, eq. (3.1) beyond), into out_host[n]. */
-lfmm_status lfmm_host_phi(int64_t n, const int32_t* mxy_host, double* out_host);
+/* phi of lattice operator `stencil` (lfmm_stencil) at n integer offsets mxy_host[2n] (table
+ * for |m|_inf <= 128 from the reduced 1-D integral of the remark closing Section 3, the
+ * far-field expansion beyond: eq. (3.1) for the 5-point operator), into out_host[n]. */
+lfmm_status lfmm_host_phi(int32_t stencil, int64_t n, const int32_t* mxy_host, double* out_host);
 
 /* Builds the operators of Sections 5 and 7 for leaves of side leaf_side and n_levels
  * heights above the leaf (opt may be NULL). */

@@ -9,7 +9,9 @@
  * Neumaier-compensated summation.  phi comes from a caller-supplied octant table
  * (phi(a,b), 0 <= b <= a <= radius, built by the quadrature of Section 3.2) and, for
  * offsets with |m|_inf > radius, from the truncated asymptotic expansion eq. (3.1) with the
- * true Euler constant.  phi(0) = 0, so a target on a source gets no self term (eq. 2.2).
+ * true Euler constant -- the 5-point operator's expansion, used only when the caller says so
+ * (expansion != 0); otherwise such an offset gives NaN (the tables of other operators have
+ * no expansion here).  phi(0) = 0, so a target on a source gets no self term (eq. 2.2).
  *
  * Build: gcc -O2 -fopenmp -shared -fPIC direct.c -o _direct.so -lm   (no fast-math)
  */
@@ -32,31 +34,32 @@ static double phi_expansion(double a, double b)
     return lead + t4 + t8;
 }
 
-static double phi_at(int64_t dx, int64_t dy, const double *table, int64_t radius)
+static double phi_at(int64_t dx, int64_t dy, const double *table, int64_t radius, int64_t expansion)
 {
     int64_t a = dx < 0 ? -dx : dx;
     int64_t b = dy < 0 ? -dy : dy;
     if (b > a) { int64_t t = a; a = b; b = t; }
     if (a <= radius) return table[a * (a + 1) / 2 + b];
-    return phi_expansion((double)a, (double)b);
+    return expansion ? phi_expansion((double)a, (double)b) : NAN;
 }
 
 int oracle_threads(void) { return omp_get_max_threads(); }
 
-void oracle_phi(int64_t n, const int32_t *mxy, const double *table, int64_t radius, double *out)
+void oracle_phi(int64_t n, const int32_t *mxy, const double *table, int64_t radius, int64_t expansion,
+                double *out)
 {
-    for (int64_t i = 0; i < n; ++i) out[i] = phi_at(mxy[2 * i], mxy[2 * i + 1], table, radius);
+    for (int64_t i = 0; i < n; ++i) out[i] = phi_at(mxy[2 * i], mxy[2 * i + 1], table, radius, expansion);
 }
 
 void oracle_direct_sum(int64_t nt, const int32_t *txy, int64_t ns, const int32_t *sxy,
-                       const double *f, const double *table, int64_t radius, double *u)
+                       const double *f, const double *table, int64_t radius, int64_t expansion, double *u)
 {
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t i = 0; i < nt; ++i) {
         const int64_t tx = txy[2 * i], ty = txy[2 * i + 1];
         double sum = 0.0, comp = 0.0;
         for (int64_t j = 0; j < ns; ++j) {
-            double term = phi_at(tx - (int64_t)sxy[2 * j], ty - (int64_t)sxy[2 * j + 1], table, radius) * f[j];
+            double term = phi_at(tx - (int64_t)sxy[2 * j], ty - (int64_t)sxy[2 * j + 1], table, radius, expansion) * f[j];
             double t = sum + term;
             if (fabs(sum) >= fabs(term)) comp += (sum - t) + term;
             else comp += (term - t) + sum;

@@ -35,6 +35,14 @@ Readings where the paper is silent or garbled (each is listed in the design note
   quadrature for |m|_inf <= 128 and the expansion only beyond, where the error is < 4e-14.
 * The numerator cos(x) - 1 is evaluated as -2 sin^2(x/2), the same number without the
   cancellation near the origin.
+
+Other lattice operators (the method carries over to other constant-coefficient difference
+operators, Sections 1 and 3.1): eq. (1.8) with the symbol of the operator in the denominator,
+by the same quadrature.  ``stencil=9`` is the isotropic 9-point operator
+(20 u(m) - 4 (four neighbours) - (four diagonal neighbours)) / 6, whose symbol is
+(20 - 8 cos t1 - 8 cos t2 - 4 cos t1 cos t2) / 6 = 4 (s1 + s2) - (8/3) s1 s2 with
+s_i = sin^2(t_i / 2) (the 5-point symbol is 4 (s1 + s2)).  The oracle has no far-field
+expansion for it: its values exist only inside the tabulated radius.
 """
 from __future__ import annotations
 
@@ -60,11 +68,21 @@ def _gauss(a: float, b: float):
     return a + h * (_GL_X + 1.0), h * _GL_W
 
 
-def _integrand(t1, t2, m1: int, m2: int):
+def _symbol(t1, t2, stencil: int = 5):
+    """Symbol of the lattice operator (the denominator of eq. 1.8), cancellation-free."""
+    s1 = np.sin(0.5 * t1) ** 2
+    s2 = np.sin(0.5 * t2) ** 2
+    if stencil == 5:
+        return 4.0 * s1 + 4.0 * s2
+    if stencil == 9:
+        return 4.0 * (s1 + s2) - (8.0 / 3.0) * s1 * s2
+    raise ValueError("stencil must be 5 or 9")
+
+
+def _integrand(t1, t2, m1: int, m2: int, stencil: int = 5):
     """The integrand of eq. (1.8), with cos(x) - 1 written as -2 sin^2(x/2)."""
     num = -2.0 * np.sin(0.5 * (m1 * t1 + m2 * t2)) ** 2
-    den = 4.0 * np.sin(0.5 * t1) ** 2 + 4.0 * np.sin(0.5 * t2) ** 2
-    return num / den
+    return num / _symbol(t1, t2, stencil)
 
 
 def box_count(m1: int, m2: int) -> int:
@@ -76,7 +94,8 @@ def box_count(m1: int, m2: int) -> int:
 class _OuterGrid:
     """Tensor Gauss grid on the n x n boxes of [-pi,pi]^2, the centre box excluded."""
 
-    def __init__(self, n: int):
+    def __init__(self, n: int, stencil: int = 5):
+        self.stencil = stencil
         h = 2.0 * math.pi / n
         xs, ws = [], []
         for i in range(n):
@@ -90,7 +109,7 @@ class _OuterGrid:
         centre[c * 20:(c + 1) * 20] = True
         self.T1, self.T2 = np.meshgrid(self.x, self.x, indexing="ij")
         # quadrature weight times 1/denominator of the integrand, node by node
-        den = 4.0 * np.sin(0.5 * self.T1) ** 2 + 4.0 * np.sin(0.5 * self.T2) ** 2
+        den = _symbol(self.T1, self.T2, stencil)
         self.Wd = (w[:, None] * w[None, :]) / den
         # the centre box is integrated separately, by annuli
         self.Wd[np.ix_(centre, centre)] = 0.0
@@ -119,7 +138,7 @@ def _annulus_rectangles(r: float):
     ]
 
 
-def _centre_box_integral(a: float, m1: int, m2: int) -> float:
+def _centre_box_integral(a: float, m1: int, m2: int, stencil: int = 5) -> float:
     """Integral of the eq. (1.8) integrand over [-a,a]^2 as a sum over annuli."""
     total = 0.0
     for k in range(_N_ANNULI):
@@ -129,7 +148,7 @@ def _centre_box_integral(a: float, m1: int, m2: int) -> float:
             tx, wx = _gauss(x0, x1)
             ty, wy = _gauss(y0, y1)
             T1, T2 = np.meshgrid(tx, ty, indexing="ij")
-            part += float(np.sum(wx[:, None] * wy[None, :] * _integrand(T1, T2, m1, m2)))
+            part += float(np.sum(wx[:, None] * wy[None, :] * _integrand(T1, T2, m1, m2, stencil)))
         total += part
     return total
 
@@ -138,18 +157,18 @@ def _phi_on_grid(grid: _OuterGrid, m1: int, m2: int) -> float:
     if m1 == 0 and m2 == 0:
         return 0.0
     outer = grid.outer_sum(m1, m2)
-    centre = _centre_box_integral(grid.a, m1, m2)
+    centre = _centre_box_integral(grid.a, m1, m2, grid.stencil)
     return (outer + centre) / (4.0 * math.pi ** 2)
 
 
-def phi_quadrature(m1: int, m2: int) -> float:
+def phi_quadrature(m1: int, m2: int, stencil: int = 5) -> float:
     """phi(m) by the two-step quadrature of Section 3.2 (one value)."""
-    return _phi_on_grid(_OuterGrid(box_count(m1, m2)), int(m1), int(m2))
+    return _phi_on_grid(_OuterGrid(box_count(m1, m2), stencil), int(m1), int(m2))
 
 
 def _shell_worker(args):
-    n, ms = args
-    grid = _OuterGrid(n)
+    n, ms, stencil = args
+    grid = _OuterGrid(n, stencil)
     return [(m1, m2, _phi_on_grid(grid, m1, m2)) for (m1, m2) in ms]
 
 
@@ -162,7 +181,7 @@ def octant_size(radius: int) -> int:
     return (radius + 1) * (radius + 2) // 2
 
 
-def phi_table_quadrature(radius: int = TABLE_RADIUS, workers: int | None = None) -> np.ndarray:
+def phi_table_quadrature(radius: int = TABLE_RADIUS, workers: int | None = None, stencil: int = 5) -> np.ndarray:
     """phi(a, b) for 0 <= b <= a <= radius by quadrature, in octant order.
 
     The octant suffices: phi is invariant under the eight symmetries of the square lattice,
@@ -176,7 +195,7 @@ def phi_table_quadrature(radius: int = TABLE_RADIUS, workers: int | None = None)
     for n, ms in groups.items():
         step = max(1, len(ms) // 8)          # spread the big shells over workers
         for i in range(0, len(ms), step):
-            jobs.append((n, ms[i:i + step]))
+            jobs.append((n, ms[i:i + step], stencil))
     jobs.sort(key=lambda j: -j[0] * j[0] * len(j[1]))
     table = np.full(octant_size(radius), np.nan)
     workers = workers or min(8, os.cpu_count() or 1)
@@ -208,6 +227,11 @@ def phi_asymptotic(m1, m2):
 
 
 _TABLE_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "phi_quadrature_r128.txt")
+_TABLE_FILE_9 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "phi9_quadrature_r128.txt")
+
+
+def table_file(stencil: int = 5) -> str:
+    return {5: _TABLE_FILE, 9: _TABLE_FILE_9}[stencil]
 
 
 def load_table(path: str = _TABLE_FILE) -> np.ndarray:

@@ -14,6 +14,7 @@ _LIB_PATH = os.path.join(_HERE, "liblfmm.so")
 _HEADER = os.path.join(os.path.dirname(_HERE), "include", "lfmm.h")
 
 PRECISIONS = {"fp64": 0, "mixed": 1}
+STENCILS = {5: 0, 9: 1, "5": 0, "9": 1, "5-point": 0, "9-point": 1}
 
 _i32, _i64, _dbl, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 
@@ -34,7 +35,7 @@ class LfmmWarning(UserWarning):
 
 class _Options(ctypes.Structure):
     _fields_ = [("eps", _dbl), ("max_leaf", _i32), ("precision", _i32), ("proxy_per_edge", _i32),
-                ("max_rank", _i32), ("flags", _i32)]
+                ("max_rank", _i32), ("flags", _i32), ("stencil", _i32)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -100,7 +101,7 @@ def _load():
         "lfmm_solve": [_vp, _i64, _vp, _vp, _vp, _vp],
         "lfmm_solve_static": [_vp, _i64, _vp, _vp, _vp, _vp],
         "lfmm_direct": [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp],
-        "lfmm_host_phi": [_i64, _vp, _vp],
+        "lfmm_host_phi": [_i32, _i64, _vp, _vp],
         "lfmm_host_opset_create": [_i64, _i32, _vp, _vp],
         "lfmm_host_opset_level": [_vp, _i32, _vp, _vp],
         "lfmm_host_opset_skeleton": [_vp, _i32, _vp],
@@ -157,7 +158,7 @@ def exported_symbols() -> list[str]:
 
 
 def _options(eps=None, max_leaf=None, precision=None, proxy_per_edge=None, max_rank=None,
-             flags=None, graph=None, check_loads=None) -> _Options:
+             flags=None, graph=None, check_loads=None, stencil=None) -> _Options:
     o = _Options()
     _check(_lib.lfmm_options_init(ctypes.byref(o)))
     if eps is not None:
@@ -176,6 +177,8 @@ def _options(eps=None, max_leaf=None, precision=None, proxy_per_edge=None, max_r
         o.flags |= FLAG_GRAPH
     if check_loads:
         o.flags |= FLAG_CHECK_LOADS
+    if stencil is not None:
+        o.stencil = STENCILS[stencil]
     return o
 
 
@@ -455,11 +458,12 @@ class Plan:
             pass
 
 
-def host_phi(mxy) -> np.ndarray:
-    """The library's phi at integer offsets (host computation, no GPU)."""
+def host_phi(mxy, stencil=5) -> np.ndarray:
+    """The library's phi of the given lattice operator (5 or 9 point) at integer offsets
+    (host computation, no GPU)."""
     m = np.ascontiguousarray(np.asarray(mxy, dtype=np.int32).reshape(-1, 2))
     out = np.empty(len(m), dtype=np.float64)
-    _check(_lib.lfmm_host_phi(len(m), m.ctypes.data_as(_vp), out.ctypes.data_as(_vp)))
+    _check(_lib.lfmm_host_phi(STENCILS[stencil], len(m), m.ctypes.data_as(_vp), out.ctypes.data_as(_vp)))
     return out
 
 

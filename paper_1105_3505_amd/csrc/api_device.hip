@@ -302,6 +302,7 @@ struct lfmm_ctx {
     DevicePool pool;             // plan storage and temporaries (declared first: freed last)
     Arena table_mem;
     double* phi_oct = nullptr;   // octant table, radius kPhiDeviceRadius
+    PhiFar* phi_far = nullptr;   // far-field expansion coefficients of the context's operator
     std::map<int64_t, CachedOps*> ops;                // deepest operator set per leaf side
     std::vector<std::unique_ptr<CachedOps>> all_ops;  // every set built; plans may hold any
     std::map<std::pair<int, int>, int32_t> tuned;     // (size class, density class) -> N_leaf
@@ -451,7 +452,7 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st, bool l
                 double* T = ifo.data() + (size_t(h) * kNumIfoSlots + slot) * P * P;
                 for (int p = 0; p < lv.rank; ++p)
                     for (int q = 0; q < lv.rank; ++q)
-                        T[size_t(p) * P + q] = phi(lv.skel[2 * p] - lv.skel[2 * q] - dx * lv.side,
+                        T[size_t(p) * P + q] = phi(ctx->opt.stencil, lv.skel[2 * p] - lv.skel[2 * q] - dx * lv.side,
                                                    lv.skel[2 * p + 1] - lv.skel[2 * q + 1] - dy * lv.side);
             }
     }
@@ -1210,7 +1211,7 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
         const TileRange& r = pl->near_of_ops[o];
         launch_near(r.t0, r.t0 + r.n, pl->groups, pl->ents, pl->box_pt0, pl->box_pt1, pl->box_key, pl->box_inst,
                     pl->ops[o]->dev.leaf_side, pl->pts, pl->pkey, pl->fs, pl->perm, tab, u1, pl->tgt0[0], pl->U,
-                    pl->ops[o]->dev.leafT, pl->d_far, pl->ctx->phi_oct, st);
+                    pl->ops[o]->dev.leafT, pl->d_far, pl->ctx->phi_oct, pl->ctx->phi_far, st);
     }
     mark(6);
 }
@@ -1430,13 +1431,21 @@ lfmm_status lfmm_ctx_create(int32_t device, const lfmm_options* opt, lfmm_ctx** 
         ctx->static_scratch = sp;
         // phi: the quadrature table (radius 128), then eq. 3.1 precomputed out to the device
         // table's radius (neighbour offsets of leaves up to side 128 stay inside it)
-        const std::vector<double>& tab = phi_table();
+        const std::vector<double>& tab = phi_table(o.stencil);
         if (tab.size() != size_t(129) * 130 / 2) throw HipFailure("phi table of unexpected size");
+        const Stencil& sten = stencil(o.stencil);
+        PhiFar far{};
+        far.C = sten.C;
+        for (int k = 0; k < 3; ++k)
+            for (int j = 0; j < 4; ++j) far.c[k][j] = sten.c[k][j];
         ctx->table_mem.reserve(kPhiDeviceEntries * sizeof(double));
+        ctx->table_mem.reserve(sizeof(PhiFar));
         ctx->table_mem.allocate();
         ctx->phi_oct = ctx->table_mem.take<double>(kPhiDeviceEntries);
+        ctx->phi_far = ctx->table_mem.take<PhiFar>(1);
         LFMM_HIP(hipMemcpy(ctx->phi_oct, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
-        launch_phi_extend(ctx->phi_oct, 128, kPhiDeviceRadius, nullptr);
+        LFMM_HIP(hipMemcpy(ctx->phi_far, &far, sizeof(PhiFar), hipMemcpyHostToDevice));
+        launch_phi_extend(ctx->phi_oct, 128, kPhiDeviceRadius, ctx->phi_far, nullptr);
         LFMM_HIP(hipGetLastError());
         LFMM_HIP(upload_dslots());
         LFMM_HIP(hipDeviceSynchronize());
@@ -1846,7 +1855,7 @@ lfmm_status lfmm_direct(lfmm_ctx* ctx, int64_t nt, const int32_t* txy, int64_t n
         return fail(LFMM_E_INVAL, "bad argument");
     return guarded([&]() -> lfmm_status {
         LFMM_HIP(hipSetDevice(ctx->device));
-        launch_direct(nt, txy, ns, sxy, f, ctx->phi_oct, u, as_stream(stream));
+        launch_direct(nt, txy, ns, sxy, f, ctx->phi_oct, ctx->phi_far, u, as_stream(stream));
         LFMM_HIP(hipGetLastError());
         return LFMM_OK;
     });

@@ -28,11 +28,14 @@ lfmm_status validate_options(const lfmm_options* o) {
     if (o->max_rank < 16 || o->max_rank > kMaxRank || o->max_rank % 16 != 0)
         return fail(LFMM_E_INVAL, "max_rank must be 16, 32, 48 or 64");
     if (o->flags & ~(LFMM_FLAG_GRAPH | LFMM_FLAG_CHECK_LOADS)) return fail(LFMM_E_INVAL, "unknown bits in options.flags");
+    if (o->stencil != LFMM_STENCIL_5 && o->stencil != LFMM_STENCIL_9)
+        return fail(LFMM_E_INVAL, "stencil must be LFMM_STENCIL_5 or LFMM_STENCIL_9");
     return LFMM_OK;
 }
 
 OperatorParams operator_params(const lfmm_options& o) {
     OperatorParams p;
+    p.stencil = o.stencil;
     p.eps = o.eps;
     p.proxy_per_edge = o.proxy_per_edge;
     p.max_rank = o.max_rank;
@@ -58,6 +61,7 @@ lfmm_status lfmm_options_init(lfmm_options* opt) {
     opt->proxy_per_edge = 64;
     opt->max_rank = 48;
     opt->flags = 0;
+    opt->stencil = LFMM_STENCIL_5;
     return LFMM_OK;
 }
 
@@ -78,10 +82,11 @@ const char* lfmm_status_string(lfmm_status s) {
 
 const char* lfmm_last_error(void) { return g_last_error.c_str(); }
 
-lfmm_status lfmm_host_phi(int64_t n, const int32_t* mxy, double* out) {
+lfmm_status lfmm_host_phi(int32_t stencil, int64_t n, const int32_t* mxy, double* out) {
     if (n < 0 || (n > 0 && (!mxy || !out))) return fail(LFMM_E_INVAL, "lfmm_host_phi: bad arguments");
+    if (stencil != LFMM_STENCIL_5 && stencil != LFMM_STENCIL_9) return fail(LFMM_E_INVAL, "unknown stencil");
     try {
-        for (int64_t i = 0; i < n; ++i) out[i] = phi(mxy[2 * i], mxy[2 * i + 1]);
+        for (int64_t i = 0; i < n; ++i) out[i] = phi(stencil, mxy[2 * i], mxy[2 * i + 1]);
     } catch (const std::exception& e) {
         return fail(LFMM_E_NOMEM, e.what());
     }

@@ -50,30 +50,31 @@ __device__ inline uint32_t compact_bits(uint64_t x) {
     return uint32_t(x);
 }
 
-// eq. (3.1), truncated after the |m|^-8 term, true Euler constant; (a, b) != 0
-__device__ inline double phi_expansion_dev(double a, double b) {
+// Far-field expansion of phi (eq. (3.1) for the 5-point operator, true Euler constant;
+// coefficients of the context's operator in *e); (a, b) != 0
+__device__ inline double phi_expansion_dev(double a, double b, const PhiFar* e) {
     const double r2 = a * a + b * b;
     const double ir2 = 1.0 / r2;
-    const double c = a * a * ir2, s = b * b * ir2;
-    const double lead = -(0.5 * log(r2) + (kEulerGamma + 0.5 * 2.0794415416798357)) * (1.0 / (2.0 * kPi));
-    const double t4 = (c * c - 6.0 * c * s + s * s) * ir2 * (1.0 / (24.0 * kPi));
-    const double c2 = c * c, s2 = s * s;
-    const double t8 = (43.0 * c2 * c2 - 772.0 * c2 * c * s + 1570.0 * c2 * s2 - 772.0 * c * s2 * s + 43.0 * s2 * s2)
-                      * ir2 * ir2 * (1.0 / (480.0 * kPi));
-    return lead + t4 + t8;
+    const double c2 = (a * a - b * b) * ir2;   // cos 2 theta
+    const double c4 = 2.0 * c2 * c2 - 1.0, c8 = 2.0 * c4 * c4 - 1.0, c12 = 2.0 * c4 * c8 - c4;
+    const double lead = -(0.5 * log(r2) + e->C) * (1.0 / (2.0 * kPi));
+    const double t1 = e->c[0][0] + e->c[0][1] * c4;
+    const double t2 = e->c[1][0] + e->c[1][1] * c4 + e->c[1][2] * c8;
+    const double t3 = e->c[2][0] + e->c[2][1] * c4 + e->c[2][2] * c8 + e->c[2][3] * c12;
+    return lead + ir2 * (t1 + ir2 * (t2 + ir2 * t3));
 }
 
 // phi at offset (a, b), a, b >= 0: the device octant table (quadrature values inside radius
-// 128, eq. 3.1 evaluated once between 128 and kPhiDeviceRadius), eq. 3.1 outside
-__device__ inline double phi_oct(int a, int b, const double* oct) {
+// 128, the expansion evaluated once between 128 and kPhiDeviceRadius), the expansion outside
+__device__ inline double phi_oct(int a, int b, const double* oct, const PhiFar* far) {
     const int hi = max(a, b), lo = min(a, b);
     if (hi <= kPhiDeviceRadius) return oct[hi * (hi + 1) / 2 + lo];
-    return phi_expansion_dev(double(hi), double(lo));
+    return phi_expansion_dev(double(hi), double(lo), far);
 }
 
-// Octant entries with r0 < hi <= r1 (index hi (hi + 1) / 2 + lo) set to eq. 3.1, so that
-// lookups replace the logarithm and division of the expansion for offsets up to r1.
-__global__ void k_phi_extend(double* oct, int r0, int r1) {
+// Octant entries with r0 < hi <= r1 (index hi (hi + 1) / 2 + lo) set to the expansion, so
+// that lookups replace the logarithm and division of the expansion for offsets up to r1.
+__global__ void k_phi_extend(double* oct, int r0, int r1, const PhiFar* far) {
     const int64_t i0 = int64_t(r0 + 1) * (r0 + 2) / 2, i1 = int64_t(r1 + 1) * (r1 + 2) / 2;
     const int64_t i = i0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= i1) return;
@@ -81,7 +82,7 @@ __global__ void k_phi_extend(double* oct, int r0, int r1) {
     while (hi * (hi + 1) / 2 > i) --hi;
     while ((hi + 1) * (hi + 2) / 2 <= i) ++hi;
     const int64_t lo = i - hi * (hi + 1) / 2;
-    oct[i] = phi_expansion_dev(double(hi), double(lo));
+    oct[i] = phi_expansion_dev(double(hi), double(lo), far);
 }
 
 inline unsigned grid_for(int64_t n, int per_block = kBlock) {
@@ -719,7 +720,8 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
                                   const int2* pts,
                                   const uint32_t* pkey, const double* fs, const int32_t* perm_local,
                                   const ExecPtrs* tab_ptrs, double* u_single, int32_t tgt0_single, const double* U,
-                                  const double* leafT, const uint8_t* far_inst, const double* phi_oct_tab) {
+                                  const double* leafT, const uint8_t* far_inst, const double* phi_oct_tab,
+                                  const PhiFar* phi_far) {
     const int lane = threadIdx.x & 63;
     const cptr<int4_t> E = as_const(reinterpret_cast<const int4_t*>(ents));
     const cptr<uint32_t> SK = as_const(pkey);
@@ -768,7 +770,7 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
                 if (MODE == kWindow) return *reinterpret_cast<const double*>(tb + int32_t(ki - kj));
                 const int dx = abs(pi.x - pj.x), dy = abs(pi.y - pj.y);
                 if (MODE == kQuad) return tab[dy * W + dx];
-                return phi_oct(dx, dy, phi_oct_tab);
+                return phi_oct(dx, dy, phi_oct_tab, phi_far);
             };
             auto src_key = [&](int32_t j) -> uint32_t {
                 if (MODE != kWindow) return 0u;
@@ -870,7 +872,7 @@ __global__ __launch_bounds__(near_threads(MODE)) void k_near(int32_t q0, int32_t
                                                       const int32_t* perm_local, const ExecPtrs* tab_ptrs,
                                                       double* u_single, int32_t tgt0_single, const double* U,
                                                       const double* leafT, const uint8_t* far_inst,
-                                                      const double* phi_oct_tab) {
+                                                      const double* phi_oct_tab, const PhiFar* phi_far) {
     constexpr int kNearBlock = near_threads(MODE), kNearWaves = kNearBlock / 64;
     // fixed-size table (largest window: side 32), so that its base is a compile-time constant
     // and folds into the address of every read
@@ -911,11 +913,11 @@ __global__ __launch_bounds__(near_threads(MODE)) void k_near(int32_t q0, int32_t
         if (MODE != kGlobal && nt > 32)
             near_group<P, MODE, false>(qq, groups, ents, box_pt0, box_pt1, box_key, box_inst, side, W, tab, tb, kofs, pts,
                                        pkey, fs, perm_local, tab_ptrs, u_single, tgt0_single, U, leafT, far_inst,
-                                       phi_oct_tab);
+                                       phi_oct_tab, phi_far);
         else
             near_group<P, MODE, true>(qq, groups, ents, box_pt0, box_pt1, box_key, box_inst, side, W, tab, tb, kofs, pts,
                                       pkey, fs, perm_local, tab_ptrs, u_single, tgt0_single, U, leafT, far_inst,
-                                      phi_oct_tab);
+                                      phi_oct_tab, phi_far);
     }
 }
 
@@ -971,7 +973,8 @@ __global__ void k_load_stats_final(const double* part, double* out) {
 
 // Brute-force sum over all sources for blocks of 256 targets; sources staged through LDS.
 __global__ __launch_bounds__(kBlock) void k_direct(int64_t nt, const int2* txy, int64_t ns, const int2* sxy,
-                                                    const double* f, const double* phi_oct, double* u) {
+                                                    const double* f, const double* phi_oct, const PhiFar* far,
+                                                    double* u) {
     __shared__ int2 sp[kBlock];
     __shared__ double sf[kBlock];
     const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
@@ -993,7 +996,7 @@ __global__ __launch_bounds__(kBlock) void k_direct(int64_t nt, const int2* txy, 
             const int64_t hi = dx > dy ? dx : dy, lo = dx > dy ? dy : dx;
             double ph;
             if (hi <= kPhiDeviceRadius) ph = phi_oct[hi * (hi + 1) / 2 + lo];
-            else ph = phi_expansion_dev(double(hi), double(lo));
+            else ph = phi_expansion_dev(double(hi), double(lo), far);
             acc += ph * sf[k];
         }
         __syncthreads();
@@ -1128,7 +1131,7 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
                  const int32_t* box_pt1, const uint64_t* box_key, const int32_t* box_inst, int64_t side,
                  const int32_t* pts, const uint32_t* pkey, const double* fs, const int32_t* perm_local,
                  const ExecPtrs* tab, double* u_single, int32_t tgt0_single, const double* U, const double* leafT,
-                 const uint8_t* far_inst, const double* phi_oct, hipStream_t st) {
+                 const uint8_t* far_inst, const double* phi_oct, const PhiFar* phi_far, hipStream_t st) {
     if (q1 <= q0) return;
     // with an LDS table: persistent blocks, as many as fit on the device at once, so that
     // each builds its table once and then walks many groups; else one group per wave
@@ -1152,7 +1155,7 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
         const unsigned g = grid(reinterpret_cast<const void*>(&k_near<kRankPad, kWindow>), nt, lds, true);
         hipLaunchKernelGGL((k_near<kRankPad, kWindow>), dim3(g), dim3(nt), lds, st, q0, q1, groups, ents,
                            box_pt0, box_pt1, box_key, box_inst, side, W, p2, pkey, fs, perm_local, tab, u_single, tgt0_single, U,
-                           leafT, far_inst, phi_oct);
+                           leafT, far_inst, phi_oct, phi_far);
     } else if (side <= 32) {
         const int W = int(2 * side);
         const size_t lds = 0;
@@ -1161,13 +1164,13 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
         const unsigned g = grid(reinterpret_cast<const void*>(&k_near<kRankPad, kQuad>), nt, lds, true);
         hipLaunchKernelGGL((k_near<kRankPad, kQuad>), dim3(g), dim3(nt), lds, st, q0, q1, groups, ents,
                            box_pt0, box_pt1, box_key, box_inst, side, W, p2, pkey, fs, perm_local, tab, u_single, tgt0_single, U,
-                           leafT, far_inst, phi_oct);
+                           leafT, far_inst, phi_oct, phi_far);
     } else {
         constexpr int nt = near_threads(kGlobal);
         const unsigned g = grid(reinterpret_cast<const void*>(&k_near<kRankPad, kGlobal>), nt, 0, false);
         hipLaunchKernelGGL((k_near<kRankPad, kGlobal>), dim3(g), dim3(nt), 0, st, q0, q1, groups, ents,
                            box_pt0, box_pt1, box_key, box_inst, side, 0, p2, pkey, fs, perm_local, tab, u_single, tgt0_single, U,
-                           leafT, far_inst, phi_oct);
+                           leafT, far_inst, phi_oct, phi_far);
     }
 }
 
@@ -1178,17 +1181,17 @@ void launch_load_stats(const double* f, int64_t n, double* scratch, double* out3
     hipLaunchKernelGGL(k_load_stats_final, dim3(1), dim3(64), 0, st, scratch, out3);
 }
 
-void launch_phi_extend(double* oct, int r0, int r1, hipStream_t st) {
+void launch_phi_extend(double* oct, int r0, int r1, const PhiFar* far, hipStream_t st) {
     if (r1 <= r0) return;
     const int64_t n = int64_t(r1 + 1) * (r1 + 2) / 2 - int64_t(r0 + 1) * (r0 + 2) / 2;
-    hipLaunchKernelGGL(k_phi_extend, dim3(grid_for(n)), dim3(kBlock), 0, st, oct, r0, r1);
+    hipLaunchKernelGGL(k_phi_extend, dim3(grid_for(n)), dim3(kBlock), 0, st, oct, r0, r1, far);
 }
 
 void launch_direct(int64_t nt, const int32_t* txy, int64_t ns, const int32_t* sxy, const double* f,
-                   const double* phi_oct, double* u, hipStream_t st) {
+                   const double* phi_oct, const PhiFar* far, double* u, hipStream_t st) {
     if (nt <= 0) return;
     hipLaunchKernelGGL(k_direct, dim3(grid_for(nt)), dim3(kBlock), 0, st, nt, reinterpret_cast<const int2*>(txy), ns,
-                       reinterpret_cast<const int2*>(sxy), f, phi_oct, u);
+                       reinterpret_cast<const int2*>(sxy), f, phi_oct, far, u);
 }
 
 }  // namespace lfmm

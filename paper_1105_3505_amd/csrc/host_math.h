@@ -11,31 +11,49 @@
 namespace lfmm {
 
 // ---------------------------------------------------------------------------------------
-// phi: fundamental solution of the 5-point operator (eq. 1.2), A phi = delta.
+// phi: fundamental solution of a lattice operator, A phi = delta: the 5-point operator of
+// eq. (1.2), or the isotropic 9-point operator (the method carries over to other
+// constant-coefficient difference operators, Sections 1 and 3.1).
 // ---------------------------------------------------------------------------------------
 
-// Radius (infinity norm) of the tabulated octant; beyond it the expansion eq. (3.1) holds
+// Radius (infinity norm) of the tabulated octant; beyond it the far-field expansion holds
 // to better than 4e-14.
 constexpr int kPhiTableRadius = 128;
+
+enum { kStencil5 = 0, kStencil9 = 1, kNumStencils = 2 };
+
+// A D4-symmetric operator with zero row sum whose symbol is affine in cos t1:
+// sigma(t) = (alpha(t2) - beta(t2) cos t1) / w, alpha = a0 + a1 cos t2, beta = b0 + b1 cos t2;
+// and its far-field expansion phi ~ -(1/2pi)(log|m| + C) + sum_k |m|^-2k sum_j c[k-1][j] cos(4 j theta).
+struct Stencil {
+    int id = 0;
+    double a0 = 0, a1 = 0, b0 = 0, b1 = 0, w = 1;
+    double C = 0;
+    double c[3][4] = {};
+};
+
+// The operator's data, its table built (and, for operators other than the 5-point one, its
+// far-field coefficients fitted) on first use.
+const Stencil& stencil(int id);
 
 inline int64_t octant_index(int64_t a, int64_t b) { return a * (a + 1) / 2 + b; }
 inline int64_t octant_size(int64_t r) { return (r + 1) * (r + 2) / 2; }
 
 // phi(m) by the one-dimensional integral obtained by integrating eq. (1.8) over t1
 // analytically (remark closing Section 3), with 20-point Gauss-Legendre panels.
-double phi_reduced_integral(int64_t m1, int64_t m2);
+double phi_reduced_integral(const Stencil& st, int64_t m1, int64_t m2);
 
-// The truncated expansion eq. (3.1) with the true Euler constant; (a, b) != 0.
-double phi_expansion(double a, double b);
+// The far-field expansion ((3.1) for the 5-point operator, true Euler constant); (a, b) != 0.
+double phi_expansion(const Stencil& st, double a, double b);
 
 // Octant table phi(a, b), 0 <= b <= a <= radius, in octant_index order (multithreaded).
-std::vector<double> build_phi_table(int radius);
+std::vector<double> build_phi_table(const Stencil& st, int radius);
 
-// Process-wide table of radius kPhiTableRadius, built on first use.
-const std::vector<double>& phi_table();
+// Process-wide table of radius kPhiTableRadius of operator id, built on first use.
+const std::vector<double>& phi_table(int id);
 
-// phi at an integer offset: table inside the radius, expansion outside.
-double phi(int64_t m1, int64_t m2);
+// phi of operator id at an integer offset: table inside the radius, expansion outside.
+double phi(int id, int64_t m1, int64_t m2);
 
 // ---------------------------------------------------------------------------------------
 // Dense column-major matrices and the factorizations the precompute needs.
@@ -92,6 +110,7 @@ struct OperatorSet {
 };
 
 struct OperatorParams {
+    int stencil = 0;             // lattice operator whose phi the operators sample
     double eps = 1e-12;          // ID tolerance, relative to the first pivot
     int proxy_per_edge = 64;     // proxy points per ring edge once the full ring is larger
     int max_rank = 64;           // skeleton cap (kernels store P_pad = 64 coefficients)

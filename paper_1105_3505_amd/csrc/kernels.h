@@ -88,6 +88,13 @@ struct OpsPtrs {
     int32_t nlev, pad;
 };
 
+// Far-field expansion of phi in the form of eq. (3.1) (device copy, per context):
+// phi ~ -(1/2pi)(log|m| + C) + sum_k |m|^-2k sum_j c[k-1][j] cos(4 j theta)
+struct PhiFar {
+    double C;
+    double c[3][4];
+};
+
 // Near-field group: the leaves leaf0 .. leaf0 + nleaf - 1 (the children of one parent box,
 // or a root that is a leaf), whose sources are the ne point ranges listed for the group.
 struct NearGroup {
@@ -227,18 +234,18 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
                  const int32_t* box_pt1, const uint64_t* box_key, const int32_t* box_inst, int64_t side,
                  const int32_t* pts, const uint32_t* pkey, const double* fs, const int32_t* perm_local,
                  const ExecPtrs* tab, double* u_single, int32_t tgt0_single, const double* U, const double* leafT,
-                 const uint8_t* far_inst, const double* phi_oct, hipStream_t st);
+                 const uint8_t* far_inst, const double* phi_oct, const PhiFar* phi_far, hipStream_t st);
 // Radius of the device phi table: the host's quadrature table (radius 128) followed by eq. 3.1
 // for the octant entries up to this radius, filled by launch_phi_extend(oct, 128, radius).
 constexpr int kPhiDeviceRadius = 256;
 constexpr size_t kPhiDeviceEntries = size_t(kPhiDeviceRadius + 1) * (kPhiDeviceRadius + 2) / 2;
-void launch_phi_extend(double* oct, int r0, int r1, hipStream_t st);
+void launch_phi_extend(double* oct, int r0, int r1, const PhiFar* far, hipStream_t st);
 // Sum, sum of magnitudes and count of non-finite entries of f[0, n) into out3 (device);
 // scratch holds load_stats_scratch_bytes().
 size_t load_stats_scratch_bytes();
 void launch_load_stats(const double* f, int64_t n, double* scratch, double* out3, hipStream_t st);
 void launch_direct(int64_t nt, const int32_t* txy, int64_t ns, const int32_t* sxy,
-                   const double* f, const double* phi_oct, double* u, hipStream_t st);
+                   const double* f, const double* phi_oct, const PhiFar* far, double* u, hipStream_t st);
 hipError_t upload_dslots();
 
 }  // namespace lfmm

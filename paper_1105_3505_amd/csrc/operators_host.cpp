@@ -63,11 +63,11 @@ std::vector<int64_t> proxy_ring(int64_t s, int per_edge) {
 namespace {
 
 // [phi(F_i - Y_j)] with a trailing row of ones (the charge sum)
-Mat kernel_matrix_with_charge(const std::vector<int64_t>& F, const std::vector<int64_t>& Y) {
+Mat kernel_matrix_with_charge(int stencil_id, const std::vector<int64_t>& F, const std::vector<int64_t>& Y) {
     const int nf = int(F.size() / 2), ny = int(Y.size() / 2);
     Mat A(nf + 1, ny);
     for (int j = 0; j < ny; ++j) {
-        for (int i = 0; i < nf; ++i) A(i, j) = phi(F[2 * i] - Y[2 * j], F[2 * i + 1] - Y[2 * j + 1]);
+        for (int i = 0; i < nf; ++i) A(i, j) = phi(stencil_id, F[2 * i] - Y[2 * j], F[2 * i + 1] - Y[2 * j + 1]);
         A(nf, j) = 1.0;
     }
     return A;
@@ -96,7 +96,7 @@ OperatorSet build_operators(int64_t leaf_side, int nlevels, const OperatorParams
         const int64_t s = leaf_side;
         std::vector<int64_t> Y = box_boundary(s);
         std::vector<int64_t> F = proxy_ring(s, p.proxy_per_edge);
-        Mat A = kernel_matrix_with_charge(F, Y);
+        Mat A = kernel_matrix_with_charge(p.stencil, F, Y);
         IDResult id = interpolative_decomposition(A, p.eps, p.max_rank);
         LevelOps& L0 = ops.level[0];
         L0.side = s;
@@ -117,7 +117,7 @@ OperatorSet build_operators(int64_t leaf_side, int nlevels, const OperatorParams
                     cells.push_back(x);
                     cells.push_back(y);
                 }
-            Mat B = kernel_matrix_with_charge(F, cells);
+            Mat B = kernel_matrix_with_charge(p.stencil, F, cells);
             lf.T = least_squares(Ask, B);
         } else {
             lf.dense = false;
@@ -142,7 +142,7 @@ OperatorSet build_operators(int64_t leaf_side, int nlevels, const OperatorParams
             }
         }
         std::vector<int64_t> F = proxy_ring(L.side, p.proxy_per_edge);
-        Mat A = kernel_matrix_with_charge(F, Y);
+        Mat A = kernel_matrix_with_charge(p.stencil, F, Y);
         IDResult id = interpolative_decomposition(A, p.eps, p.max_rank);
         L.rank = int(id.skel.size());
         for (int j : id.skel) {

@@ -1,21 +1,35 @@
-// phi, the lattice fundamental solution, on the host.
+// phi, the lattice fundamental solution, on the host, for the 5-point operator of eq. (1.2)
+// and for other constant-coefficient operators of the same family (Sections 1 and 3.1: the
+// method needs only phi, so it carries over to other difference operators).
 //
-// Route: integrating eq. (1.8) over t1 in closed form (remark closing Section 3) leaves
-//   phi(m) = (1/pi) int_0^pi (cos(m2 t) lambda(t)^|m1| - 1) / sqrt(c^2 - 4) dt,
-//   c = 4 - 2 cos t,  lambda = (c - sqrt(c^2 - 4)) / 2,  |m1| >= |m2|
-// (the t1 integral is the classical int cos(k x)/(c - 2 cos x) dx = 2 pi lambda^k / sqrt(c^2-4)).
-// With s = sin(t/2) the pieces have cancellation-free forms:
-//   sqrt(c^2 - 4) = 4 s sqrt(1 + s^2),  lambda = exp(-2 asinh s),
-//   cos(m2 t) lambda^k - 1 = expm1(-2 k asinh s) - 2 sin^2(m2 t / 2) exp(-2 k asinh s).
-// The integrand is analytic on [0, pi] (its limit at 0 is -k/2); it varies on the scale 1/k
-// near 0 and oscillates m2/2 times, so panels are geometric near 0 and half a period wide
-// after, each with 20-point Gauss-Legendre.  Beyond |m|_inf = 128 the expansion eq. (3.1)
-// (true Euler constant) is used; its error there is below 4e-14.
+// Route: an operator whose symbol is affine in cos t1,
+//   sigma(t) = (alpha(t2) - beta(t2) cos t1) / w,  alpha = a0 + a1 cos t2,  beta = b0 + b1 cos t2,
+// lets eq. (1.8) be integrated over t1 in closed form (the remark closing Section 3 does this
+// for the 5-point operator; the t1 integral is int cos(k x) / (alpha - beta cos x) dx =
+// 2 pi lambda^k / sqrt(alpha^2 - beta^2), lambda = exp(-acosh(alpha / beta))), leaving
+//   phi(m) = (w / pi) int_0^pi (cos(m2 t) lambda(t)^|m1| - 1) / sqrt(alpha^2 - beta^2) dt,
+// with |m1| >= |m2| (D4 symmetry).  A zero row sum (sigma(0) = 0) gives alpha - beta =
+// D1 s^2 with s = sin(t/2), D1 = 2 (b1 - a1), so the pieces have cancellation-free forms:
+//   sqrt(alpha^2 - beta^2) = s sqrt(D1 (alpha + beta)),  acosh(alpha / beta) = 2 asinh(s sqrt(D1 / (2 beta))),
+//   cos(m2 t) lambda^k - 1 = expm1(-k psi) - 2 sin^2(m2 t / 2) exp(-k psi),  psi = acosh(alpha / beta).
+// The integrand is analytic on [0, pi] (its limit at 0 is -k / beta(0)); it varies on the
+// scale 1/k near 0 and oscillates m2/2 times, so panels are geometric near 0 and half a
+// period wide after, each with 20-point Gauss-Legendre.
+//
+// Beyond |m|_inf = 128 an expansion in the form of eq. (3.1) is used,
+//   phi(m) ~ -(1/2pi) (log |m| + C) + sum_{k=1..3} |m|^-2k sum_{j=0..k} c_kj cos(4 j theta),
+// (D4 symmetry leaves only the harmonics cos(4 j theta)).  For the 5-point operator it is eq.
+// (3.1) itself, true Euler constant: C = gamma + log(8)/2, and the two printed correction
+// terms are cos(4 theta) / (24 pi |m|^2) and (18 cos(4 theta) + 25 cos(8 theta)) / (480 pi |m|^4).
+// Its error there is below 4e-14.  For other operators the paper leaves the expansion to
+// computer algebra that it does not give; here C and c_kj are fitted by least squares to the
+// tabulated values with |m| >= 40, where the next term is below 1e-15.
 #include "host_math.h"
 
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <stdexcept>
 #include <thread>
 
 namespace lfmm {
@@ -55,19 +69,22 @@ const GaussRule& gauss() {
 }
 
 // integrand of the reduced integral, k = |m1| >= j = |m2|
-inline double reduced_integrand(double t, double k, double j) {
-    double s = std::sin(0.5 * t);
-    if (s == 0.0) return -0.5 * k;
-    double q = std::sqrt(1.0 + s * s);
-    double e = -2.0 * k * std::asinh(s);
-    double sj = std::sin(0.5 * j * t);
-    double num = std::expm1(e) - 2.0 * sj * sj * std::exp(e);
-    return num / (4.0 * s * q);
+inline double reduced_integrand(const Stencil& st, double t, double k, double j) {
+    const double s = std::sin(0.5 * t);
+    const double beta = st.b0 + st.b1 * (1.0 - 2.0 * s * s);
+    if (s == 0.0) return -k / beta;
+    const double d1 = 2.0 * (st.b1 - st.a1);
+    const double sum = (st.a0 + st.b0 + st.a1 + st.b1) - 2.0 * (st.a1 + st.b1) * s * s;   // alpha + beta
+    const double psi = 2.0 * std::asinh(s * std::sqrt(d1 / (2.0 * beta)));
+    const double e = -k * psi;
+    const double sj = std::sin(0.5 * j * t);
+    const double num = std::expm1(e) - 2.0 * sj * sj * std::exp(e);
+    return num / (s * std::sqrt(d1 * sum));
 }
 
 }  // namespace
 
-double phi_reduced_integral(int64_t m1, int64_t m2) {
+double phi_reduced_integral(const Stencil& st, int64_t m1, int64_t m2) {
     int64_t k = std::llabs(m1), j = std::llabs(m2);
     if (j > k) std::swap(j, k);
     if (k == 0) return 0.0;
@@ -87,27 +104,27 @@ double phi_reduced_integral(int64_t m1, int64_t m2) {
     for (size_t p = 0; p + 1 < bp.size(); ++p) {
         double a = bp[p], b = bp[p + 1], c = 0.5 * (a + b), r = 0.5 * (b - a);
         double part = 0.0;
-        for (int i = 0; i < 20; ++i) part += g.w[i] * reduced_integrand(c + r * g.x[i], double(k), double(j));
+        for (int i = 0; i < 20; ++i) part += g.w[i] * reduced_integrand(st, c + r * g.x[i], double(k), double(j));
         part *= r;
         double t = sum + part;  // Neumaier
         comp += (std::fabs(sum) >= std::fabs(part)) ? (sum - t) + part : (part - t) + sum;
         sum = t;
     }
-    return (sum + comp) / kPi;
+    return st.w * (sum + comp) / kPi;
 }
 
-double phi_expansion(double a, double b) {
-    double r2 = a * a + b * b;
-    double c = a * a / r2, s = b * b / r2;
-    double lead = -(0.5 * std::log(r2) + kEulerGamma + 0.5 * std::log(8.0)) / (2.0 * kPi);
-    double t4 = (c * c - 6.0 * c * s + s * s) / (24.0 * kPi * r2);
-    double c2 = c * c, s2 = s * s;
-    double t8 = (43.0 * c2 * c2 - 772.0 * c2 * c * s + 1570.0 * c2 * s2 - 772.0 * c * s2 * s + 43.0 * s2 * s2)
-                / (480.0 * kPi * r2 * r2);
-    return lead + t4 + t8;
+double phi_expansion(const Stencil& st, double a, double b) {
+    const double r2 = a * a + b * b, ir2 = 1.0 / r2;
+    const double c2 = (a * a - b * b) * ir2;   // cos 2 theta
+    const double c4 = 2.0 * c2 * c2 - 1.0, c8 = 2.0 * c4 * c4 - 1.0, c12 = 2.0 * c4 * c8 - c4;
+    const double lead = -(0.5 * std::log(r2) + st.C) / (2.0 * kPi);
+    const double t1 = st.c[0][0] + st.c[0][1] * c4;
+    const double t2 = st.c[1][0] + st.c[1][1] * c4 + st.c[1][2] * c8;
+    const double t3 = st.c[2][0] + st.c[2][1] * c4 + st.c[2][2] * c8 + st.c[2][3] * c12;
+    return lead + ir2 * (t1 + ir2 * (t2 + ir2 * t3));
 }
 
-std::vector<double> build_phi_table(int radius) {
+std::vector<double> build_phi_table(const Stencil& st, int radius) {
     std::vector<double> tab(size_t(octant_size(radius)), 0.0);
     unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     std::vector<std::thread> pool;
@@ -115,25 +132,92 @@ std::vector<double> build_phi_table(int radius) {
         pool.emplace_back([&, t]() {
             // rows a interleaved over threads (cost grows with a)
             for (int a = int(t); a <= radius; a += int(nthreads))
-                for (int b = 0; b <= a; ++b) tab[size_t(octant_index(a, b))] = phi_reduced_integral(a, b);
+                for (int b = 0; b <= a; ++b) tab[size_t(octant_index(a, b))] = phi_reduced_integral(st, a, b);
         });
     }
     for (auto& th : pool) th.join();
     return tab;
 }
 
-const std::vector<double>& phi_table() {
-    static std::once_flag once;
-    static std::vector<double> tab;
-    std::call_once(once, [] { tab = build_phi_table(kPhiTableRadius); });
-    return tab;
+namespace {
+
+struct StencilData {
+    Stencil st;
+    std::vector<double> table;
+};
+
+// Far-field coefficients fitted to the table: least squares over the entries with |m| >= 40
+// of phi + log|m| / (2 pi) = -C / (2 pi) + sum_k |m|^-2k sum_j c_kj cos(4 j theta), each basis
+// column scaled to unit size at |m| = 40.
+void fit_far_field(StencilData& d) {
+    std::vector<std::pair<int, int>> pts;
+    for (int a = 0; a <= kPhiTableRadius; ++a)
+        for (int b = 0; b <= a; ++b)
+            if (double(a) * a + double(b) * b >= 40.0 * 40.0) pts.emplace_back(a, b);
+    const int ncol = 10;
+    Mat A(int(pts.size()), ncol), B(int(pts.size()), 1);
+    for (size_t i = 0; i < pts.size(); ++i) {
+        const double a = pts[i].first, b = pts[i].second, r2 = a * a + b * b;
+        const double c2 = (a * a - b * b) / r2, c4 = 2 * c2 * c2 - 1, c8 = 2 * c4 * c4 - 1, c12 = 2 * c4 * c8 - c4;
+        const double u = 1600.0 / r2;   // (40 / |m|)^2
+        const double row[ncol] = {1.0, u, u * c4, u * u, u * u * c4, u * u * c8, u * u * u, u * u * u * c4,
+                                  u * u * u * c8, u * u * u * c12};
+        for (int j = 0; j < ncol; ++j) A(int(i), j) = row[j];
+        B(int(i), 0) = d.table[size_t(octant_index(pts[i].first, pts[i].second))] + 0.5 * std::log(r2) / (2.0 * kPi);
+    }
+    const Mat X = least_squares(A, B);
+    d.st.C = -2.0 * kPi * X(0, 0);
+    const double s1 = 1600.0, s2 = s1 * s1, s3 = s2 * s1;
+    d.st.c[0][0] = X(1, 0) * s1;
+    d.st.c[0][1] = X(2, 0) * s1;
+    d.st.c[1][0] = X(3, 0) * s2;
+    d.st.c[1][1] = X(4, 0) * s2;
+    d.st.c[1][2] = X(5, 0) * s2;
+    d.st.c[2][0] = X(6, 0) * s3;
+    d.st.c[2][1] = X(7, 0) * s3;
+    d.st.c[2][2] = X(8, 0) * s3;
+    d.st.c[2][3] = X(9, 0) * s3;
 }
 
-double phi(int64_t m1, int64_t m2) {
+const StencilData& stencil_data(int id) {
+    static std::once_flag once[kNumStencils];
+    static StencilData data[kNumStencils];
+    if (id < 0 || id >= kNumStencils) throw std::invalid_argument("unknown lattice operator");
+    std::call_once(once[id], [id] {
+        StencilData& d = data[id];
+        Stencil& st = d.st;
+        st = Stencil{};
+        st.id = id;
+        if (id == kStencil5) {
+            // 4 u(m) - (sum of the four neighbours), eq. (1.2)
+            st.a0 = 4; st.a1 = -2; st.b0 = 2; st.b1 = 0; st.w = 1;
+            st.C = kEulerGamma + 0.5 * std::log(8.0);
+            st.c[0][1] = 1.0 / (24.0 * kPi);
+            st.c[1][1] = 18.0 / (480.0 * kPi);
+            st.c[1][2] = 25.0 / (480.0 * kPi);
+            d.table = build_phi_table(st, kPhiTableRadius);
+        } else {
+            // isotropic 9-point: (20 u(m) - 4 (four neighbours) - (four diagonal neighbours)) / 6
+            st.a0 = 20; st.a1 = -8; st.b0 = 8; st.b1 = 4; st.w = 6;
+            d.table = build_phi_table(st, kPhiTableRadius);
+            fit_far_field(d);
+        }
+    });
+    return data[id];
+}
+
+}  // namespace
+
+const Stencil& stencil(int id) { return stencil_data(id).st; }
+
+const std::vector<double>& phi_table(int id) { return stencil_data(id).table; }
+
+double phi(int id, int64_t m1, int64_t m2) {
     int64_t a = std::llabs(m1), b = std::llabs(m2);
     if (b > a) std::swap(a, b);
-    if (a <= kPhiTableRadius) return phi_table()[size_t(octant_index(a, b))];
-    return phi_expansion(double(a), double(b));
+    const StencilData& d = stencil_data(id);
+    if (a <= kPhiTableRadius) return d.table[size_t(octant_index(a, b))];
+    return phi_expansion(d.st, double(a), double(b));
 }
 
 }  // namespace lfmm

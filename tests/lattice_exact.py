@@ -99,3 +99,42 @@ def phi_reduced_integral(m1: int, m2: int, digits: int = 30) -> float:
             pts.append(p)
         val = mpmath.quad(g, pts) / mpmath.pi
         return float(val)
+
+
+def phi9_reduced_integral(m1: int, m2: int, digits: int = 30) -> float:
+    """phi of the isotropic 9-point operator (20 u - 4 (4 neighbours) - (4 diagonals)) / 6 from
+    the one-dimensional integral left after integrating eq. (1.8) in t1: its symbol is
+    (alpha - beta cos t1) / 6 with alpha = 20 - 8 cos t2, beta = 8 + 4 cos t2, and the t1
+    integral of cos(k t1) / (alpha - beta cos t1) is 2 pi lambda^k / sqrt(alpha^2 - beta^2),
+    lambda = (alpha - sqrt(alpha^2 - beta^2)) / beta, so that
+    phi(m) = (6/pi) int_0^pi (cos(m2 t) lambda^|m1| - 1) / sqrt(alpha^2 - beta^2) dt, |m1| >= |m2|.
+    Evaluated with mpmath at ``digits`` digits (extra working digits absorb the cancellation
+    near t = 0)."""
+    a, b = abs(m1), abs(m2)
+    if b > a:
+        a, b = b, a
+    if a == 0:
+        return 0.0
+    with mpmath.workdps(2 * digits + 20):
+        def g(t):
+            if t == 0:
+                return mpmath.mpf(-a) / 12     # the integrand's limit at t = 0 (beta(0) = 12)
+            # with s = sin(t/2): alpha = 12 + 16 s^2, beta = 12 - 8 s^2, alpha - beta = 24 s^2 and
+            # alpha + beta = 24 + 8 s^2, so sqrt(alpha^2 - beta^2) = s sqrt(24 (24 + 8 s^2))
+            s = mpmath.sin(t / 2)
+            al = 12 + 16 * s * s
+            be = 12 - 8 * s * s
+            rt = s * mpmath.sqrt(24 * (24 + 8 * s * s))
+            lam = (al - rt) / be
+            return (mpmath.cos(b * t) * lam ** a - 1) / rt
+        pts = [mpmath.mpf(0)]
+        h = mpmath.mpf(1) / (4 * a)
+        while h < mpmath.pi / max(8, 2 * b):
+            pts.append(h)
+            h *= 2
+        nun = max(8, 2 * b)
+        start = pts[-1]
+        for k in range(1, nun + 1):
+            pts.append(start + (mpmath.pi - start) * k / nun)
+        val = 6 * mpmath.quad(g, pts) / mpmath.pi
+        return float(val)

@@ -136,3 +136,51 @@ def test_bad_arguments_return_status():
         lf.HostOperators(16, 0)
     with pytest.raises(lf.LfmmError):
         lf.HostOperators(16, 2, eps=-1.0)
+
+
+def test_host_phi9_matches_oracle_table():
+    # the library's 9-point phi (one-dimensional reduced integral) against the oracle's (two-step
+    # quadrature of Section 3.2 with the 9-point symbol): independent routes
+    a, b = np.meshgrid(np.arange(129), np.arange(129), indexing="ij")
+    keep = b <= a
+    m = np.stack([a[keep], b[keep]], axis=1)
+    lib = lf.host_phi(m, stencil=9)
+    ref = od.phi(m, stencil=9)
+    assert np.max(np.abs(lib - ref)) <= 5e-15
+
+
+@pytest.mark.parametrize("m", [(129, 0), (140, 139), (181, 60), (256, 1), (400, 399), (1000, 10)])
+def test_host_phi9_far_field_against_reduced_integral(m):
+    # beyond the table the library uses its fitted expansion; the reference is the reduced
+    # integral at 30 digits (tests/lattice_exact.py)
+    import lattice_exact as le
+    assert abs(lf.host_phi([m], stencil=9)[0] - le.phi9_reduced_integral(*m, digits=30)) <= 2e-15
+
+
+def test_host_phi9_operator_equation_across_the_switch():
+    def A9(x, y):
+        pts = [[x, y], [x + 1, y], [x - 1, y], [x, y + 1], [x, y - 1],
+               [x + 1, y + 1], [x - 1, y + 1], [x + 1, y - 1], [x - 1, y - 1]]
+        v = lf.host_phi(pts, stencil=9)
+        return (20 * v[0] - 4 * v[1:5].sum() - v[5:].sum()) / 6
+    assert abs(A9(0, 0) - 1.0) <= 1e-14
+    for p in [(128, 0), (128, 77), (129, 129), (150, 2), (700, 300)]:
+        assert abs(A9(*p)) <= 1e-14, p
+
+
+def test_leaf_outgoing_expansion_9_point():
+    # eq. (5.1) for the 9-point operator: the skeleton charges reproduce the leaf's far field
+    s = 8
+    ops = lf.HostOperators(s, 1, stencil=9)
+    rng = np.random.default_rng(4)
+    cells = rng.choice(s * s, size=30, replace=False)
+    src = np.stack([cells % s, cells // s], axis=1)
+    q = rng.standard_normal(30)
+    qhat = ops.leaf()[:, cells] @ q
+    # well-separated targets inside the oracle's 9-point table radius
+    tgt = rng.integers(-56, 72, size=(2000, 2))
+    far = np.max(np.abs(tgt - s // 2), axis=1) >= 2 * s
+    tgt = tgt[far][:300]
+    ref = od.direct_sum(tgt, src, q, stencil=9)
+    app = od.direct_sum(tgt, ops.skeleton(0), qhat, stencil=9)
+    assert np.max(np.abs(app - ref)) <= 1e-11 * np.max(np.abs(ref))

@@ -212,7 +212,7 @@ def run_single(args, torch, lf):
     dev = torch.device("cuda:0")
     xy_d = torch.from_numpy(xy).to(dev)
     f_d = torch.from_numpy(f).to(dev)
-    ctx = lf.Context(0, precision=args.precision, max_leaf=args.max_leaf)
+    ctx = lf.Context(0, precision=args.precision, max_leaf=args.max_leaf, stencil=args.stencil)
     streams = streams_for(args.inflight, torch)
     outs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in streams]
 
@@ -249,24 +249,67 @@ def run_single(args, torch, lf):
     exec_ms = (time.perf_counter() - t0) * 1e3 / reps
     u = u_d.cpu().numpy()
     plan.close()
+    equation = None
+    if args.stencil == 9:
+        equation = nine_point_equation_residual(ctx, xy, f, torch)
     ctx.close()
 
     config = {"workload": WORKLOADS[args.workload], "n_sources": n, "precision": args.precision,
               "leaf_level": info["leaf_level"], "leaf_side": info["leaf_side"], "max_leaf": args.max_leaf,
-              "rank": RANK, "eps": 1e-12}
+              "rank": RANK, "eps": 1e-12,
+              "operator": "9-point isotropic" if args.stencil == 9 else "5-point"}
     result = base_result(args, value, ms_per_step, config)
     result.update(timing_fields(m, n, args.inflight))
     result.update({"inflight_outputs_equal": same,
                    "execute_only_ms": exec_ms, "execute_only_msources_per_s": n / (exec_ms * 1e-3) / 1e6,
                    "plan": info,
                    "roofline": roofline(m["dom"], m["dom_ms"], info, n, args.precision, args.workload)})
-    if not args.no_cpu_baseline:
+    if equation is not None:
+        result["equation_residual"] = equation
+        result["equation_residual_definition"] = ("max |A9 u - f| / max |u| over the 9-point stencils of 2,000 "
+                                                  "sampled cells (u there from a plan with those targets)")
+    if not args.no_cpu_baseline and args.stencil == 5:
         err, k, base = cpu_baseline(xy, f, u, args.cpu_targets)
         result["rel_err_vs_oracle"] = err
         result["rel_err_sample"] = k
         result["tolerance"] = TOLERANCE[args.precision]
         result["cpu_baseline"] = base
+    elif not args.no_cpu_baseline:
+        # the oracle's 9-point phi spans |m|_inf <= 128: its direct sum over the points of a
+        # 128 x 128 corner of the input, timed, and compared with a plan of those points
+        from oracle import direct as od
+        sub = np.all(xy < 128, axis=1)
+        xs, fs = xy[sub], f[sub]
+        c2 = lf.Context(0, precision=args.precision, max_leaf=args.max_leaf, stencil=9)
+        us = c2.plan(torch.from_numpy(xs).cuda()).execute(torch.from_numpy(fs).cuda()).cpu().numpy()
+        c2.close()
+        t0 = time.perf_counter()
+        ref = od.direct_sum(xs, xs, fs, stencil=9)
+        cpu_s = time.perf_counter() - t0
+        result["rel_err_vs_oracle"] = float(np.linalg.norm(us - ref) / np.linalg.norm(ref))
+        result["rel_err_sample"] = int(len(xs))
+        result["tolerance"] = TOLERANCE[args.precision]
+        result["cpu_baseline"] = {"value": len(xs) / cpu_s / 1e6, "unit": "Msources/s", "cores": od.threads(),
+                                  "kind": "oracle",
+                                  "sample": "9-point direct sum over the %d points of the 128x128 corner of the "
+                                            "input (all targets), %.3f s" % (len(xs), cpu_s)}
     return result
+
+
+def nine_point_equation_residual(ctx, xy, f, torch):
+    """A9 u = f (the 9-point operator's equation) at the stencils of 2,000 sampled cells."""
+    rng = np.random.default_rng(91)
+    centres = xy[rng.choice(len(xy), size=2000, replace=False)].astype(np.int64)
+    off = np.array([[0, 0], [1, 0], [-1, 0], [0, 1], [0, -1], [1, 1], [-1, 1], [1, -1], [-1, -1]])
+    pts = (centres[None, :, :] + off[:, None, :]).reshape(-1, 2).astype(np.int32)
+    plan = ctx.plan(torch.from_numpy(xy).cuda(), targets=torch.from_numpy(pts).cuda())
+    u = plan.execute(torch.from_numpy(f).cuda()).cpu().numpy().reshape(9, -1)
+    plan.close()
+    a9u = (20 * u[0] - 4 * u[1:5].sum(axis=0) - u[5:].sum(axis=0)) / 6
+    # loads at the centres (distinct cells: each centre is one source)
+    idx = {tuple(p): i for i, p in enumerate(xy.tolist())}
+    fc = np.array([f[idx[tuple(c)]] for c in centres.tolist()])
+    return float(np.max(np.abs(a9u - fc)) / np.max(np.abs(u)))
 
 
 def run_batched(args, torch, lf):
@@ -567,6 +610,8 @@ def main() -> None:
     ap.add_argument("--workload", default="large_uniform", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=sorted(TOLERANCE))
     ap.add_argument("--max-leaf", type=int, default=64)
+    ap.add_argument("--stencil", type=int, default=5, choices=(5, 9),
+                    help="lattice operator: the 5-point Laplacian of the paper or the isotropic 9-point one")
     ap.add_argument("--inflight", type=int, default=3,
                     help="independent solves in flight in the timed region, one stream each")
     ap.add_argument("--cpu-targets", type=int, default=20000)

@@ -1,0 +1,90 @@
+"""GPU parity of the lattice FMM for the isotropic 9-point operator against the oracle's direct
+sum with its 9-point phi (two-step quadrature, eq. 1.8 with the 9-point symbol).  The oracle
+holds that phi inside |m|_inf <= 128, so the point sets span at most 128 cells; small leaves
+(N_leaf 8 .. 64) still give trees of 4-5 levels, so every pass runs.
+
+Bar: relative l2 and max-norm errors <= 1e-10 (FP64), <= 1e-7 (mixed).
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import direct as od
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    return torch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _errs(u, ref):
+    return (float(np.linalg.norm(u - ref) / np.linalg.norm(ref)),
+            float(np.max(np.abs(u - ref)) / np.max(np.abs(ref))))
+
+
+@pytest.mark.parametrize("max_leaf,n,precision", [(8, 3000, "fp64"), (16, 9000, "fp64"), (64, 12000, "fp64"),
+                                                   (8, 6000, "mixed")])
+def test_fmm_9_point(torch_mod, max_leaf, n, precision):
+    import paper_1105_3505_amd as lf
+    torch = torch_mod
+    rng = np.random.default_rng(900 + max_leaf + n)
+    xy = wl.uniform_box(rng, n, 128, origin=(-31, 4000))
+    f = wl.zero_sum_loads(rng.standard_normal(n))
+    ctx = lf.Context(0, stencil=9, max_leaf=max_leaf, precision=precision)
+    plan = ctx.plan(_dev(torch, xy))
+    u = plan.execute(_dev(torch, f)).cpu().numpy()
+    info = plan.info()
+    assert info["leaf_level"] >= 3
+    l2, mx = _errs(u, od.direct_sum(xy, xy, f, stencil=9))
+    tol = 1e-10 if precision == "fp64" else 1e-7
+    print("9-point n=%d leaf side %d %s: rel l2 %.2e max %.2e" % (n, info["leaf_side"], precision, l2, mx))
+    assert l2 <= tol and mx <= tol
+    # the 5-point operator gives a different field on the same input
+    u5 = lf.Context(0, max_leaf=max_leaf).solve(_dev(torch, xy), _dev(torch, f)).cpu().numpy()
+    assert np.linalg.norm(u5 - u) > 1e-3 * np.linalg.norm(u)
+    plan.close()
+    ctx.close()
+
+
+def test_direct_kernel_and_targets_9_point(torch_mod):
+    import paper_1105_3505_amd as lf
+    torch = torch_mod
+    rng = np.random.default_rng(950)
+    src = wl.uniform_box(rng, 4000, 120)
+    f = wl.zero_sum_loads(rng.standard_normal(len(src)))
+    tgt = rng.integers(-4, 124, size=(2500, 2)).astype(np.int32)
+    ctx = lf.Context(0, stencil=9, max_leaf=16)
+    ref = od.direct_sum(tgt, src, f, stencil=9)
+    ud = ctx.direct(_dev(torch, tgt), _dev(torch, src), _dev(torch, f)).cpu().numpy()
+    assert _errs(ud, ref)[0] <= 1e-13
+    ut = ctx.plan(_dev(torch, src), targets=_dev(torch, tgt)).execute(_dev(torch, f)).cpu().numpy()
+    l2, mx = _errs(ut, ref)
+    assert l2 <= 1e-10 and mx <= 1e-10
+    ctx.close()
+
+
+def test_9_point_equation_on_a_window(torch_mod):
+    # A9 u = f at every cell of a window around the sources (targets = the window's cells)
+    import paper_1105_3505_amd as lf
+    torch = torch_mod
+    rng = np.random.default_rng(960)
+    src = wl.uniform_box(rng, 300, 60, origin=(1000, 1000))
+    f = rng.standard_normal(len(src))
+    g = np.arange(990, 1072)
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    tgt = np.stack([X.ravel(), Y.ravel()], axis=1).astype(np.int32)
+    ctx = lf.Context(0, stencil=9, max_leaf=16)
+    u = ctx.plan(_dev(torch, src), targets=_dev(torch, tgt)).execute(_dev(torch, f)).cpu().numpy().reshape(X.shape)
+    A9u = (20 * u[1:-1, 1:-1] - 4 * (u[2:, 1:-1] + u[:-2, 1:-1] + u[1:-1, 2:] + u[1:-1, :-2])
+           - (u[2:, 2:] + u[:-2, 2:] + u[2:, :-2] + u[:-2, :-2])) / 6
+    F = np.zeros_like(u)
+    F[src[:, 0] - 990, src[:, 1] - 990] = f
+    assert np.max(np.abs(A9u - F[1:-1, 1:-1])) <= 1e-9 * np.max(np.abs(u))
+    ctx.close()

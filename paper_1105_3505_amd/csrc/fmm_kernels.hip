@@ -250,8 +250,6 @@ __device__ inline int32_t xcd_tile(int32_t b, int32_t G, int32_t step, int32_t n
 
 // Box-matrix passes on the FP64 matrix cores: for a tile of up to 64 target boxes that share
 // their operators, out[box] (+)= sum over slots k of A_k in[src_k(box)] with 48 x 48 A_k:
-//   M2L (Section 8.2 step 3): 27 interaction slots, A_k = T_ifo^d(k) at the tile's height
-//        and child position, in = Q, out = U;
 //   M2M (step 2): 4 children, A_k = T_ofo^(k) at the tile's height, in = out = Q;
 //   L2L (step 4): the parent, A = T_ofo^(c)T at the parent's height, in = out = U, added.
 // Wave w of the block owns boxes 16 w .. 16 w + 15 (the 16 columns of its products) and runs
@@ -282,13 +280,14 @@ __device__ inline void boxmat_tiles(const BoxTile* tiles, int32_t ntiles, const 
                                     const int32_t* src_tab, const OpsPtrs* ops, const double* in, int32_t zrow,
                                     double* out) {
     constexpr int P = kRankPad, MT = P / 16, KQ = P / 4, NJ = KQ / 2;
-    constexpr int NS = (MODE == kModeM2L) ? kNumInteractions : (MODE == kModeM2M ? 4 : 1);
-    constexpr int SW = (MODE == kModeM2L) ? kNumInteractions : (MODE == kModeM2M ? 4 : 1);   // source table width
+    static_assert(MODE == kModeM2M || MODE == kModeL2L, "M2L has a kernel of its own");
+    constexpr int NS = (MODE == kModeM2M) ? 4 : 1;
+    constexpr int SW = NS;   // source table width
     constexpr int A2 = P * P / 2;                      // double2_t per operator: 4.5 per thread
     static_assert(A2 == 4 * kBlock + kBlock / 2, "staging below assumes P = 48");
     static_assert(MT == 3, "three row blocks");
     __shared__ double2_t sA[2][A2];
-    __shared__ int s_dsl[kNumInteractions];   // operator of each slot of the tile
+    __shared__ int s_dsl[4];   // operator of each slot of the tile
     const int tid = int(threadIdx.x), wave = tid >> 6, lane = tid & 63;
     const int n = lane & 15, g = lane >> 4;
     const int32_t G = int32_t(gridDim.x);
@@ -303,14 +302,10 @@ __device__ inline void boxmat_tiles(const BoxTile* tiles, int32_t ntiles, const 
         const int col = 16 * wave + n;
         const int32_t box = (col < count) ? (box_list ? box_list[start + col] : start + col) : -1;
         const gptr<int32_t> srcs = global(src_tab + size_t(box >= 0 ? box : 0) * SW);
-        const double* base = (MODE == kModeM2L) ? ops[opi].ifo : (MODE == kModeM2M ? ops[opi].ofo_rm : ops[opi].ofo_cm);
+        const double* base = (MODE == kModeM2M) ? ops[opi].ofo_rm : ops[opi].ofo_cm;
         const gptr<double2_t> Ah = global(reinterpret_cast<const double2_t*>(base));
         const gptr<double> Xg = global(in) + g * KQ;
-        if (tid < NS) {
-            if (MODE == kModeM2L) s_dsl[tid] = height * kNumIfoSlots + c_dslot.s[cls][tid];
-            else if (MODE == kModeM2M) s_dsl[tid] = height * 4 + tid;
-            else s_dsl[tid] = (height + 1) * 4 + cls;
-        }
+        if (tid < NS) s_dsl[tid] = (MODE == kModeM2M) ? height * 4 + tid : (height + 1) * 4 + cls;
         __syncthreads();
         const int* dsl = s_dsl;
         // slot 0 operands
@@ -393,11 +388,9 @@ __device__ inline void boxmat_tiles(const BoxTile* tiles, int32_t ntiles, const 
             if (MODE == kModeM2M) fold(k == 0);   // one partial sum per child slot
         }
         if (MODE == kModeL2L) fold(false);
-        if (MODE != kModeM2L) {
-            acc0 = run0;
-            acc1 = run1;
-            acc2 = run2;
-        }
+        acc0 = run0;
+        acc1 = run1;
+        acc2 = run2;
         if (box >= 0) {
             double* ob = out + size_t(box) * P;
             #pragma unroll
@@ -417,10 +410,133 @@ __device__ inline void boxmat_tiles(const BoxTile* tiles, int32_t ntiles, const 
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list,
-                                                 const int32_t* il27, const OpsPtrs* ops, const double* Q,
-                                                 int32_t zrow, double* U) {
-    boxmat_tiles<kModeM2L>(tiles, ntiles, box_list, il27, ops, Q, zrow, U);
+// M2L (Section 8.2 step 3) on the FP64 matrix cores for tiles of up to 128 target boxes that
+// share their 27 operators (same operator set, height and child position).  Wave w owns the two
+// 16-box column blocks of boxes 32 w .. 32 w + 31, so each operator staged in LDS (once per slot
+// and block, double-buffered, one barrier per slot) feeds 72 matrix instructions per wave: the
+// staging and the barrier cost half as much per product as with one column block, and a launch
+// of the 1e6-point plan fits the device in one round of blocks.  The tile's interaction lists
+// are copied into LDS when the tile starts, so the slot loop issues no dependent global loads:
+// within a slot the wave runs its two column blocks one after the other, and the source
+// expansion of the next (slot, column block) pair is loaded from global memory while the
+// current pair's products run (its list entry read from LDS one pair earlier).  Absent sources
+// (empty list slots, boxes past the tile) read the zero row.
+// 16x16x4 FP64 instruction: step kk of row block m takes column g * 12 + kk in lane group
+// g = lane / 16; element i of lane (g, n) is row 16 m + g + 4 i, column n.
+__global__ __launch_bounds__(kBlock, 3) void k_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list,
+                                                    const int32_t* il27, const OpsPtrs* ops, const double* Q,
+                                                    int32_t zrow, double* U) {
+    constexpr int P = kRankPad, KQ = P / 4, NJ = KQ / 2, NS = kNumInteractions;
+    constexpr int A2 = P * P / 2;                      // double2_t per operator: 4.5 per thread
+    static_assert(A2 == 4 * kBlock + kBlock / 2, "staging below assumes P = 48");
+    static_assert(kM2LTile == 128, "two column blocks per wave");
+    __shared__ double2_t sA[2][A2];
+    __shared__ int32_t s_src[kM2LTile * NS];     // source box of (tile column, slot), zrow if none
+    __shared__ int32_t s_box[kM2LTile];
+    __shared__ int s_dsl[NS];
+    const int tid = int(threadIdx.x), wave = tid >> 6, lane = tid & 63;
+    const int n = lane & 15, g = lane >> 4;
+    const int32_t G = int32_t(gridDim.x);
+    const double2_t z2 = {0.0, 0.0};
+    for (int32_t step = 0;; ++step) {
+        const int32_t t = uniform(xcd_tile(int32_t(blockIdx.x), G, step, ntiles));
+        if (t < 0) break;                                  // uniform over the block
+        const int32_t count = uniform(tiles[t].count);
+        if (count == 0) continue;
+        const int32_t start = uniform(tiles[t].start), height = uniform(tiles[t].height);
+        const int32_t cls = uniform(tiles[t].cls), opi = uniform(tiles[t].ops);
+        if (tid < NS) s_dsl[tid] = height * kNumIfoSlots + c_dslot.s[cls][tid];
+        if (tid < kM2LTile) s_box[tid] = (tid < count) ? box_list[start + tid] : -1;
+        __syncthreads();
+        for (int i = tid; i < kM2LTile * NS; i += kBlock) {
+            const int b = i / NS;
+            const int32_t box = s_box[b];
+            const int32_t src = box >= 0 ? il27[size_t(box) * NS + (i - b * NS)] : -1;
+            s_src[i] = src < 0 ? zrow : src;
+        }
+        const gptr<double2_t> Ah = global(reinterpret_cast<const double2_t*>(ops[opi].ifo));
+        const gptr<double> Xg = global(Q) + g * KQ;
+        const int col0 = 32 * wave + n;
+        const int32_t box0 = s_box[col0], box1 = s_box[col0 + 16];
+        __syncthreads();
+        const int* dsl = s_dsl;
+        const int32_t* src0 = s_src + col0 * NS;          // this lane's two columns' lists
+        const int32_t* src1 = src0 + 16 * NS;
+        auto load_q = [&](int32_t src, double2_t (&r)[NJ]) {
+            const gptr<double2_t> q = reinterpret_cast<gptr<double2_t>>(Xg + size_t(src) * P);
+            #pragma unroll
+            for (int j = 0; j < NJ; ++j) r[j] = q[j];
+        };
+        double2_t bq[NJ], nq[NJ];
+        load_q(src0[0], nq);                               // pair (slot 0, block 0)
+        int32_t idx_next = src1[0];                        // pair (slot 0, block 1)
+        const gptr<double2_t> A0 = Ah + size_t(dsl[0]) * A2;
+        int32_t dsl_next = dsl[1];
+        double2_t ra0 = A0[tid], ra1 = A0[tid + kBlock], ra2 = A0[tid + 2 * kBlock], ra3 = A0[tid + 3 * kBlock];
+        double2_t ra4 = (tid < kBlock / 2) ? A0[tid + 4 * kBlock] : z2;
+        double4_t acc[2][3];
+        #pragma unroll
+        for (int c = 0; c < 2; ++c)
+            #pragma unroll
+            for (int m = 0; m < 3; ++m) acc[c][m] = double4_t{0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < NS; ++k) {
+            double2_t* buf = sA[k & 1];
+            buf[tid] = ra0;
+            buf[tid + kBlock] = ra1;
+            buf[tid + 2 * kBlock] = ra2;
+            buf[tid + 3 * kBlock] = ra3;
+            if (tid < kBlock / 2) buf[tid + 4 * kBlock] = ra4;
+            __syncthreads();
+            if (k + 1 < NS) {   // the next slot's operator, into registers
+                const gptr<double2_t> An = Ah + size_t(uniform(dsl_next)) * A2;
+                ra0 = An[tid];
+                ra1 = An[tid + kBlock];
+                ra2 = An[tid + 2 * kBlock];
+                ra3 = An[tid + 3 * kBlock];
+                if (tid < kBlock / 2) ra4 = An[tid + 4 * kBlock];
+                dsl_next = (k + 2 < NS) ? dsl[k + 2] : 0;
+            }
+            #pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                // each pass reads its operator fragments from LDS anew: holding the first pass's
+                // fragments in registers for the second would cost 72 VGPRs (a third of them)
+                asm volatile("" ::: "memory");
+                #pragma unroll
+                for (int j = 0; j < NJ; ++j) bq[j] = nq[j];
+                // the next pair: (k, block 1) after block 0, (k + 1, block 0) after block 1
+                if (c == 0 || k + 1 < NS) {
+                    load_q(idx_next, nq);
+                    idx_next = (c == 0) ? (k + 1 < NS ? src0[k + 1] : zrow) : src1[k + 1];
+                }
+                #pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    const double2_t a0 = buf[(0 * NJ + j) * 64 + lane];
+                    const double2_t a1 = buf[(1 * NJ + j) * 64 + lane];
+                    const double2_t a2 = buf[(2 * NJ + j) * 64 + lane];
+                    acc[c][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, bq[j].x, acc[c][0], 0, 0, 0);
+                    acc[c][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, bq[j].x, acc[c][1], 0, 0, 0);
+                    acc[c][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2.x, bq[j].x, acc[c][2], 0, 0, 0);
+                    acc[c][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, bq[j].y, acc[c][0], 0, 0, 0);
+                    acc[c][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, bq[j].y, acc[c][1], 0, 0, 0);
+                    acc[c][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2.y, bq[j].y, acc[c][2], 0, 0, 0);
+                }
+            }
+        }
+        #pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int32_t box = c ? box1 : box0;
+            if (box >= 0) {
+                double* ob = U + size_t(box) * P;
+                #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    ob[g + 4 * i] = acc[c][0][i];
+                    ob[16 + g + 4 * i] = acc[c][1][i];
+                    ob[32 + g + 4 * i] = acc[c][2][i];
+                }
+            }
+        }
+        __syncthreads();   // the next tile rewrites the staging buffers and lists read above
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_m2m(const BoxTile* tiles, int32_t ntiles, const int32_t* box_child,
@@ -536,7 +652,8 @@ __global__ void k_split_q(const double* Q, int32_t nrows, float* Qh, float* Ql, 
     if (lane == 0) qs[box] = s;
 }
 
-// Mixed-precision M2L on the FP32 matrix cores, same tiling and staging as k_m2l.  Each
+// Mixed-precision M2L on the FP32 matrix cores, on the same 128-box tiles as k_m2l (each wave's
+// two column blocks in two passes over the 27 slots) with the same staging.  Each
 // operator is written T^d = c_d 1 1^T + R^d with c_d its mean entry: the constant part,
 // which carries the large log|d| level of the kernel, is applied in FP64 as c_d times the
 // source's charge sum; only the remainder R^d, several times smaller, goes through FP32.
@@ -568,15 +685,11 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, cons
         if (count == 0) continue;
         const int32_t start = uniform(tiles[t].start), height = uniform(tiles[t].height);
         const int32_t cls = uniform(tiles[t].cls), opi = uniform(tiles[t].ops);
-        const bool wave_on = 16 * wave < count;
-        const int col = 16 * wave + n;
-        const int32_t box = (col < count) ? box_list[start + col] : -1;
         const int rk = ops[opi].rank[height];
         const size_t hbase = size_t(height) * kNumIfoSlots * A4;
         const gptr<float4_t> Hh = global(reinterpret_cast<const float4_t*>(ops[opi].ifo_hi)) + hbase;
         const gptr<float4_t> Lh = global(reinterpret_cast<const float4_t*>(ops[opi].ifo_lo)) + hbase;
         const gptr<double> mono = global(ops[opi].mono) + size_t(height) * kNumIfoSlots;
-        const gptr<int32_t> il = global(il27 + size_t(box >= 0 ? box : 0) * kNumInteractions);
         // lane group g supplies rows 12 g .. 12 g + 11 of its column's q-hat
         const gptr<float4_t> QH = global(reinterpret_cast<const float4_t*>(Qh)) + 3 * g;
         const gptr<float4_t> QL = global(reinterpret_cast<const float4_t*>(Ql)) + 3 * g;
@@ -584,6 +697,12 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, cons
         if (tid < kNumInteractions) s_dsl[tid] = c_dslot.s[cls][tid];
         __syncthreads();
         const int* dsl = s_dsl;
+        // the wave's two 16-box column blocks (boxes 32 w .. 32 w + 31 of the tile), one pass each
+        for (int cb = 0; cb < 2; ++cb) {
+        const bool wave_on = 32 * wave + 16 * cb < count;
+        const int col = 32 * wave + 16 * cb + n;
+        const int32_t box = (col < count) ? box_list[start + col] : -1;
+        const gptr<int32_t> il = global(il27 + size_t(box >= 0 ? box : 0) * kNumInteractions);
         int32_t src = (box >= 0) ? il[0] : -1;
         src = src < 0 ? zrow : src;
         float4_t h0 = QH[size_t(src) * 12], h1 = QH[size_t(src) * 12 + 1], h2 = QH[size_t(src) * 12 + 2];
@@ -669,7 +788,8 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, cons
                 for (int i = 0; i < 4; ++i) ub[16 * m + 4 * g + i] = acc[m][i];   // FP32 output layout
             }
         }
-        __syncthreads();
+        __syncthreads();   // the next pass (or tile) rewrites the staging buffers
+        }
     }
 }
 

@@ -50,8 +50,9 @@ struct BoxGroup {
     int32_t ops, height, g0, g1, cls_base, tile_base, tile_cap, tile_boxes;
 };
 
-// Boxes per tile: the box-matrix kernels give 16 boxes to each of their 4 waves.
-constexpr int kM2LTile = 64;
+// Boxes per tile: the M2L kernels give 32 boxes (two 16-column blocks) to each of their 4
+// waves, the M2M / L2L box-matrix kernels 16.
+constexpr int kM2LTile = 128;
 constexpr int kBoxMatTile = 64;
 
 // Per leaf side: operators in device memory (uploaded once, shared by every plan).
@@ -117,7 +118,7 @@ struct ExecPtrs {
     int32_t nsrc, tgt0;
 };
 
-enum BoxMatMode { kModeM2L = 0, kModeM2M = 1, kModeL2L = 2 };
+enum BoxMatMode { kModeM2M = 1, kModeL2L = 2 };
 
 // ---- construction (forest_kernels.hip) ---------------------------------------------------
 size_t radix_scratch_bytes(int64_t n);

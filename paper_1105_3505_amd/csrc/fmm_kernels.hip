@@ -1091,6 +1091,146 @@ __global__ void k_load_stats_final(const double* part, double* out) {
     out[2] = bad;
 }
 
+// Leaf pass for leaf sides >= 64 (phi from the device octant table, radius 256: every offset
+// of a near pair, at most 2 side - 1 = 255, is a table entry).  Such leaves are the sparse
+// ones of widely spread or clustered inputs: a group (the up to four leaves of one parent) holds
+// a few dozen targets and its 4 x 4 block of source leaves a few hundred sources.  A wave takes
+// one group.  It first copies the sources of all the group's ranges into LDS (coordinates and
+// loads; the ranges' loads are independent, so their latencies overlap), then sums from LDS:
+// the group's targets take T lanes each (T the power of two at or above their count, at most
+// 64) of S = 64 / T slices, slice s taking every S-th staged source; a pair counts when the
+// source's leaf neighbours the target's (leaf coordinates from the point coordinates), and its
+// phi is a gather from the table.  The slices' sums meet by xor shuffles.  Groups with more
+// than kStageCap sources are summed in chunks of that many.  L2P (T_tfi = T_ofs^T) and the
+// caller-order write are as in k_near.
+constexpr int kStageCap = 512;
+constexpr int kStagedWaves = 4;
+constexpr int kStageRound = 8;   // staged elements per lane with their loads in flight together
+
+template <int P>
+__global__ __launch_bounds__(64 * kStagedWaves) void k_near_staged(
+    int32_t q0, int32_t q1, const NearGroup* groups, const int4* ents, const int32_t* box_pt0, const int32_t* box_pt1,
+    const uint64_t* box_key, const int32_t* box_inst, int64_t side, const int2* pts, const double* fs,
+    const int32_t* perm_local, const ExecPtrs* tab_ptrs, double* u_single, int32_t tgt0_single, const double* U,
+    const double* leafT, const uint8_t* far_inst, const double* phi_oct_tab) {
+    __shared__ int2 s_xy[kStagedWaves][kStageCap];
+    __shared__ double s_f[kStagedWaves][kStageCap];
+    const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
+    const int32_t q = q0 + int32_t(blockIdx.x) * kStagedWaves + wave;
+    if (q >= q1) return;   // uniform over the wave; no block-wide barrier below
+    const int32_t qq = uniform(q);
+    int2* sxy = s_xy[wave];
+    double* sf = s_f[wave];
+    const cptr<int4_t> E = as_const(reinterpret_cast<const int4_t*>(ents)) + size_t(qq) * kNearEntries;
+    const int32_t leaf0 = uniform(groups[qq].leaf0), nleaf = uniform(groups[qq].nleaf);
+    const int32_t ne = uniform(groups[qq].ne);
+    int ls = 0;
+    while ((int64_t(1) << ls) < side) ++ls;
+    const int32_t t0 = uniform(box_pt0[leaf0]), t_end = uniform(box_pt1[leaf0 + nleaf - 1]);
+    const int32_t k_inst = uniform(box_inst[leaf0]);
+    const bool far = far_inst[k_inst] != 0;
+    double* u = tab_ptrs ? tab_ptrs[k_inst].u : u_single;
+    const int32_t tgt0 = tab_ptrs ? tab_ptrs[k_inst].tgt0 : tgt0_single;
+    // first points of the group's leaves, to find each target's leaf
+    int32_t bnd1 = t_end, bnd2 = t_end, bnd3 = t_end;
+    if (nleaf > 1) bnd1 = uniform(box_pt0[leaf0 + 1]);
+    if (nleaf > 2) bnd2 = uniform(box_pt0[leaf0 + 2]);
+    if (nleaf > 3) bnd3 = uniform(box_pt0[leaf0 + 3]);
+    // entries: start offset of each range in the concatenated source list
+    int32_t e_p0[kNearEntries], e_off[kNearEntries + 1];
+    e_off[0] = 0;
+    #pragma unroll
+    for (int e = 0; e < kNearEntries; ++e) {
+        int32_t a = 0, b = 0;
+        if (e < ne) {
+            const int4_t en = E[e];
+            a = en.x;
+            b = en.y;
+        }
+        e_p0[e] = a;
+        e_off[e + 1] = e_off[e] + (b - a);
+    }
+    const int32_t ns = e_off[kNearEntries];
+    const int32_t nt = t_end - t0;
+    int T = 1;
+    while (T < nt && T < 64) T <<= 1;
+    const int S = 64 / T, tl = lane & (T - 1), sl = lane / T;
+    for (int32_t i0 = t0; i0 < t_end; i0 += T) {
+        const int32_t i = i0 + tl;
+        const bool valid = i < t_end;
+        const int32_t ii = valid ? i : t0;
+        const int2 pi = pts[ii];
+        const int tlx = pi.x >> ls, tly = pi.y >> ls;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (int32_t c0 = 0; c0 < ns; c0 += kStageCap) {
+            const int32_t c1 = min(ns, c0 + kStageCap);
+            // stage sources [c0, c1) of the concatenated list (after the wave's reads of the
+            // previous chunk: other lanes' reads, so a fence and not only program order)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // eight elements per lane and round, every load issued before the stores: element t of
+            // the concatenated list is point t + (e_p0[e] - e_off[e]) of the range e holding it
+            for (int32_t base = c0; base < c1; base += 64 * kStageRound) {
+                int2 v[kStageRound];
+                double w[kStageRound];
+                #pragma unroll
+                for (int r = 0; r < kStageRound; ++r) {
+                    const int32_t t = base + r * 64 + lane;
+                    int32_t shift = e_p0[0] - e_off[0];
+                    #pragma unroll
+                    for (int e = 1; e < kNearEntries; ++e)
+                        if (t >= e_off[e]) shift = e_p0[e] - e_off[e];
+                    const int32_t j = t < c1 ? t + shift : t0;
+                    v[r] = pts[j];
+                    w[r] = fs[j];
+                }
+                #pragma unroll
+                for (int r = 0; r < kStageRound; ++r) {
+                    const int32_t t = base + r * 64 + lane;
+                    if (t < c1) {
+                        sxy[t - c0] = v[r];
+                        sf[t - c0] = w[r];
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int32_t m = c1 - c0;
+            auto pair = [&](int32_t j) -> double {
+                const int2 pj = sxy[j];
+                const int dlx = (pj.x >> ls) - tlx, dly = (pj.y >> ls) - tly;
+                const bool nb = dlx >= -1 && dlx <= 1 && dly >= -1 && dly <= 1;
+                const int dx = abs(pi.x - pj.x), dy = abs(pi.y - pj.y);
+                const int hi = max(dx, dy), lo = min(dx, dy);
+                const double ph = nb ? phi_oct_tab[hi * (hi + 1) / 2 + lo] : 0.0;
+                return ph * sf[j];
+            };
+            int32_t j = sl;
+            for (; j + 3 * S < m; j += 4 * S) {
+                a0 += pair(j);
+                a1 += pair(j + S);
+                a2 += pair(j + 2 * S);
+                a3 += pair(j + 3 * S);
+            }
+            for (; j < m; j += S) a0 += pair(j);
+        }
+        if (far) {
+            const int c = (ii >= bnd1) + (ii >= bnd2) + (ii >= bnd3);
+            const int32_t leaf = leaf0 + c;
+            const int64_t loc = int64_t(pi.x - tlx * side) + side * int64_t(pi.y - tly * side);
+            const double* tlp = leafT + loc * P;
+            const double* uh = U + size_t(leaf) * P;
+            for (int p = sl; p < P; p += S) a1 += tlp[p] * uh[p];
+        }
+        double acc = (a0 + a1) + (a2 + a3);
+        for (int o = T; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+        const int32_t pout = perm_local[ii];
+        if (valid && sl == 0 && pout >= tgt0) u[pout - tgt0] = acc;
+    }
+}
+
 // Brute-force sum over all sources for blocks of 256 targets; sources staged through LDS.
 __global__ __launch_bounds__(kBlock) void k_direct(int64_t nt, const int2* txy, int64_t ns, const int2* sxy,
                                                     const double* f, const double* phi_oct, const PhiFar* far,
@@ -1286,11 +1426,12 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
                            box_pt0, box_pt1, box_key, box_inst, side, W, p2, pkey, fs, perm_local, tab, u_single, tgt0_single, U,
                            leafT, far_inst, phi_oct, phi_far);
     } else {
-        constexpr int nt = near_threads(kGlobal);
-        const unsigned g = grid(reinterpret_cast<const void*>(&k_near<kRankPad, kGlobal>), nt, 0, false);
-        hipLaunchKernelGGL((k_near<kRankPad, kGlobal>), dim3(g), dim3(nt), 0, st, q0, q1, groups, ents,
-                           box_pt0, box_pt1, box_key, box_inst, side, 0, p2, pkey, fs, perm_local, tab, u_single, tgt0_single, U,
-                           leafT, far_inst, phi_oct, phi_far);
+        // every near offset (at most 2 side - 1 <= 255) lies inside the device octant table
+        if (2 * side - 1 > kPhiDeviceRadius) throw std::logic_error("leaf wider than the near-field table allows");
+        const unsigned g = unsigned((q1 - q0 + kStagedWaves - 1) / kStagedWaves);
+        hipLaunchKernelGGL(k_near_staged<kRankPad>, dim3(g), dim3(64 * kStagedWaves), 0, st, q0, q1, groups, ents,
+                           box_pt0, box_pt1, box_key, box_inst, side, p2, fs, perm_local, tab, u_single, tgt0_single,
+                           U, leafT, far_inst, phi_oct);
     }
 }
 

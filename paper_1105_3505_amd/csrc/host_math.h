@@ -17,7 +17,7 @@ namespace lfmm {
 // ---------------------------------------------------------------------------------------
 
 // Radius (infinity norm) of the tabulated octant; beyond it the far-field expansion holds
-// to better than 4e-14.
+// to about 4e-15 (the terms of eq. (3.1) and fitted |m|^-6 terms).
 constexpr int kPhiTableRadius = 128;
 
 enum { kStencil5 = 0, kStencil9 = 1, kNumStencils = 2 };
@@ -43,7 +43,8 @@ inline int64_t octant_size(int64_t r) { return (r + 1) * (r + 2) / 2; }
 // analytically (remark closing Section 3), with 20-point Gauss-Legendre panels.
 double phi_reduced_integral(const Stencil& st, int64_t m1, int64_t m2);
 
-// The far-field expansion ((3.1) for the 5-point operator, true Euler constant); (a, b) != 0.
+// The far-field expansion (for the 5-point operator eq. (3.1) with the true Euler constant and
+// fitted |m|^-6 terms); (a, b) != 0.
 double phi_expansion(const Stencil& st, double a, double b);
 
 // Octant table phi(a, b), 0 <= b <= a <= radius, in octant_index order (multithreaded).

@@ -146,6 +146,30 @@ struct StencilData {
     std::vector<double> table;
 };
 
+// The |m|^-6 terms of the 5-point expansion, which eq. (3.1) stops short of: least squares over
+// the table entries with |m| >= 40 of phi minus the eq. (3.1) value, columns |m|^-6 cos(4 j theta)
+// scaled to unit size at |m| = 40.  With them the expansion agrees with the quadrature table to
+// about 4e-15 for |m| >= 64 (2e-12 without), so kernels may use it from there on.
+void fit_far_field_k3(StencilData& d) {
+    std::vector<std::pair<int, int>> pts;
+    for (int a = 0; a <= kPhiTableRadius; ++a)
+        for (int b = 0; b <= a; ++b)
+            if (double(a) * a + double(b) * b >= 40.0 * 40.0) pts.emplace_back(a, b);
+    const int ncol = 4;
+    Mat A(int(pts.size()), ncol), B(int(pts.size()), 1);
+    for (size_t i = 0; i < pts.size(); ++i) {
+        const double a = pts[i].first, b = pts[i].second, r2 = a * a + b * b;
+        const double c2 = (a * a - b * b) / r2, c4 = 2 * c2 * c2 - 1, c8 = 2 * c4 * c4 - 1, c12 = 2 * c4 * c8 - c4;
+        const double u3 = std::pow(1600.0 / r2, 3);
+        const double row[ncol] = {u3, u3 * c4, u3 * c8, u3 * c12};
+        for (int j = 0; j < ncol; ++j) A(int(i), j) = row[j];
+        B(int(i), 0) = d.table[size_t(octant_index(pts[i].first, pts[i].second))] - phi_expansion(d.st, a, b);
+    }
+    const Mat X = least_squares(A, B);
+    const double s3 = 1600.0 * 1600.0 * 1600.0;
+    for (int j = 0; j < ncol; ++j) d.st.c[2][j] = X(j, 0) * s3;
+}
+
 // Far-field coefficients fitted to the table: least squares over the entries with |m| >= 40
 // of phi + log|m| / (2 pi) = -C / (2 pi) + sum_k |m|^-2k sum_j c_kj cos(4 j theta), each basis
 // column scaled to unit size at |m| = 40.
@@ -196,6 +220,7 @@ const StencilData& stencil_data(int id) {
             st.c[1][1] = 18.0 / (480.0 * kPi);
             st.c[1][2] = 25.0 / (480.0 * kPi);
             d.table = build_phi_table(st, kPhiTableRadius);
+            fit_far_field_k3(d);
         } else {
             // isotropic 9-point: (20 u(m) - 4 (four neighbours) - (four diagonal neighbours)) / 6
             st.a0 = 20; st.a1 = -8; st.b0 = 8; st.b1 = 4; st.w = 6;

@@ -48,7 +48,11 @@ def test_host_phi_symmetry_and_far_field():
     assert np.array_equal(v, lf.host_phi(-m))
     assert np.array_equal(v, lf.host_phi(m[:, ::-1]))
     ref = od.phi(m)
-    assert np.max(np.abs(v - ref)) <= 5e-15
+    # the oracle stops eq. (3.1) after the |m|^-4 terms, whose remainder against the Section 3.2
+    # quadrature is below 3.5e-14 (128 / |m|)^6; the library adds fitted |m|^-6 terms
+    r = np.hypot(m[:, 0], m[:, 1]).astype(np.float64)
+    bound = 5e-15 + 3.5e-14 * np.minimum(1.0, 128.0 / r) ** 6
+    assert np.all(np.abs(v - ref) <= bound)
 
 
 def test_host_phi_closed_forms():

@@ -101,6 +101,16 @@ typedef enum lfmm_stencil {
  * the device and a read-back, so the call synchronises the stream): NaN or infinite loads
  * give LFMM_E_INVAL with nothing launched, a non-zero total load LFMM_W_NONZERO_SUM. */
 #define LFMM_FLAG_CHECK_LOADS 2
+/* options.flags: plans use the adaptive tree of Section 6 (closing paragraph): a box is
+ * refined while it holds more than max_leaf points, so leaves sit at different levels and
+ * the far field goes through the lists of Carrier, Greengard and Rokhlin: V (interaction
+ * lists, M2L), W (multipole expansions of small boxes evaluated at a leaf's points), X (a
+ * large leaf's sources evaluated into a small box's incoming expansion) and U (adjacent
+ * leaves, summed directly).  Outgoing and incoming expansions of a leaf above the finest
+ * level are those of its descendants moved up by T_ofo and down by T_ofo^T, which composes
+ * the leaf's own T_ofs and T_tfi.  Suited to strongly non-uniform point sets.  Not with
+ * lfmm_solve_static or a server (LFMM_E_UNSUPPORTED). */
+#define LFMM_FLAG_ADAPTIVE 4
 
 typedef struct lfmm_ctx lfmm_ctx;     /* device, phi table, per-leaf-side operator cache  */
 typedef struct lfmm_plan lfmm_plan;   /* one or more point sets (instances): sorted points,
@@ -122,6 +132,13 @@ typedef struct lfmm_plan_info {
     int64_t m2l_pairs;        /* (box, interaction-list box) pairs (Section 8.2, step 3)   */
     int64_t device_bytes;     /* device memory the plan holds between executes             */
     int64_t n_targets;        /* potentials one execute writes, over all instances         */
+    int32_t adaptive;         /* 1: adaptive tree (LFMM_FLAG_ADAPTIVE); n_leaves, near_pairs
+                                 and m2l_pairs then count its leaves, U and V lists        */
+    int32_t pad0;
+    int64_t m2p_terms;        /* adaptive: sum over leaves of targets x W-list skeleton
+                                 points (multipole evaluations at targets)                 */
+    int64_t p2l_terms;        /* adaptive: sum over boxes of skeleton points x X-list
+                                 sources (sources evaluated into incoming expansions)      */
 } lfmm_plan_info;
 
 /* Fills *opt with the defaults listed above. */
@@ -249,7 +266,14 @@ typedef enum lfmm_export_item {
     LFMM_EXPORT_LOADS = 12,     /* float64 [n]: loads of the last execute in Morton order   */
     LFMM_EXPORT_LEVEL_COUNT = 13, /* int32 [L+1], instance 0: boxes of level l              */
     LFMM_EXPORT_BOX_LEVEL = 14, /* int8 [n_boxes]: level of the box in its instance's tree   */
-    LFMM_EXPORT_BOX_INSTANCE = 15 /* int32 [n_boxes]: instance of the box                    */
+    LFMM_EXPORT_BOX_INSTANCE = 15, /* int32 [n_boxes]: instance of the box                   */
+    LFMM_EXPORT_BOX_ROLE = 16,  /* int8 [n_boxes], adaptive plans: 0 below an adaptive leaf,
+                                   1 refined box of the adaptive tree, 2 its leaf           */
+    LFMM_EXPORT_LIST_U = 17,    /* int32, adaptive plans: [n_boxes + 1] row starts, then the
+                                   entries (box indices); row of a leaf: its U list          */
+    LFMM_EXPORT_LIST_W = 18,    /* int32, adaptive plans: the same for the W lists           */
+    LFMM_EXPORT_LIST_X = 19     /* int32, adaptive plans: the same for the X lists (rows of
+                                   every box of the adaptive tree)                          */
 } lfmm_export_item;
 
 /* Copies plan item `item` into host_out.  With host_out NULL, stores the byte size in *bytes;
@@ -262,7 +286,9 @@ lfmm_status lfmm_plan_export(lfmm_plan* plan, int32_t item, void* host_out, size
  * box, root_bits = ceil(log2(coordinate extent)) in [0, 31], or -1 if unknown (the bound for
  * any extent below 2^31).  Level l of a tree holds at most min(4^l, n) boxes, so the bound
  * grows with root_bits for sparse point sets.  Used for admission by memory footprint; the
- * bytes a built plan holds are lfmm_plan_info.device_bytes. */
+ * bytes a built plan holds are lfmm_plan_info.device_bytes.  Uniform trees only:
+ * LFMM_E_UNSUPPORTED for a context with LFMM_FLAG_ADAPTIVE (its list lengths depend on how
+ * the points cluster). */
 lfmm_status lfmm_plan_footprint_bytes(const lfmm_ctx* ctx, int64_t n_src, int64_t n_tgt, int32_t root_bits,
                                       size_t* out);
 

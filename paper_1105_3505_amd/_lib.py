@@ -42,7 +42,8 @@ class _PlanInfo(ctypes.Structure):
     _fields_ = [("n_points", _i64), ("n_instances", _i32), ("root_bits", _i32), ("leaf_level", _i32),
                 ("leaf_side", _i64),
                 ("rank", _i32), ("leaf_kind", _i32), ("n_boxes", _i64), ("n_leaves", _i64),
-                ("near_pairs", _i64), ("m2l_pairs", _i64), ("device_bytes", _i64), ("n_targets", _i64)]
+                ("near_pairs", _i64), ("m2l_pairs", _i64), ("device_bytes", _i64), ("n_targets", _i64),
+                ("adaptive", _i32), ("pad0", _i32), ("m2p_terms", _i64), ("p2l_terms", _i64)]
 
 
 class _ServerOptions(ctypes.Structure):
@@ -67,6 +68,7 @@ STATUS_BUSY = -7
 STATUS_NONZERO_SUM = 1
 FLAG_GRAPH = 1
 FLAG_CHECK_LOADS = 2
+FLAG_ADAPTIVE = 4
 
 
 def library_path() -> str:
@@ -158,7 +160,7 @@ def exported_symbols() -> list[str]:
 
 
 def _options(eps=None, max_leaf=None, precision=None, proxy_per_edge=None, max_rank=None,
-             flags=None, graph=None, check_loads=None, stencil=None) -> _Options:
+             flags=None, graph=None, check_loads=None, stencil=None, adaptive=None) -> _Options:
     o = _Options()
     _check(_lib.lfmm_options_init(ctypes.byref(o)))
     if eps is not None:
@@ -177,6 +179,8 @@ def _options(eps=None, max_leaf=None, precision=None, proxy_per_edge=None, max_r
         o.flags |= FLAG_GRAPH
     if check_loads:
         o.flags |= FLAG_CHECK_LOADS
+    if adaptive:
+        o.flags |= FLAG_ADAPTIVE
     if stencil is not None:
         o.stencil = STENCILS[stencil]
     return o
@@ -410,7 +414,8 @@ class Plan:
                "box_parent": (6, np.int32, 0), "box_child": (7, np.int32, 4), "interaction": (8, np.int32, 27),
                "neighbor": (9, np.int32, 9), "qhat": (10, np.float64, 48), "uhat": (11, np.float64, 48),
                "loads": (12, np.float64, 0), "level_count": (13, np.int32, 0), "box_level": (14, np.int8, 0),
-               "box_instance": (15, np.int32, 0)}
+               "box_instance": (15, np.int32, 0), "box_role": (16, np.int8, 0)}
+    LISTS = {"U": 17, "W": 18, "X": 19}
 
     def export(self, name: str) -> np.ndarray:
         """Copy of a plan internal (lfmm_plan_export) as a numpy array."""
@@ -421,6 +426,16 @@ class Plan:
         if size.value:
             _check(_lib.lfmm_plan_export(self._h, item, out.ctypes.data_as(_vp), ctypes.byref(size)))
         return out.reshape(-1, width) if width else out
+
+    def export_list(self, name: str):
+        """Adaptive plans: list `name` ("U", "W" or "X") as (row starts [n_boxes + 1], entries)."""
+        item = self.LISTS[name]
+        size = ctypes.c_size_t()
+        _check(_lib.lfmm_plan_export(self._h, item, None, ctypes.byref(size)))
+        out = np.empty(size.value // 4, dtype=np.int32)
+        _check(_lib.lfmm_plan_export(self._h, item, out.ctypes.data_as(_vp), ctypes.byref(size)))
+        nb = int(self.info()["n_boxes"])
+        return out[:nb + 1], out[nb + 1:]
 
     def set_timing(self, enable: bool = True) -> None:
         _check(_lib.lfmm_plan_set_timing(self._h, 1 if enable else 0))

@@ -31,6 +31,8 @@ lfmm_status root_bits_of(lfmm_ctx* ctx, int32_t K, const int64_t* n, const int32
                          int32_t* bits);
 // Device of a context.
 int ctx_device(const lfmm_ctx* ctx);
+// Option flags of a context (LFMM_FLAG_*).
+int32_t ctx_flags(const lfmm_ctx* ctx);
 // Servers of a context, destroyed with it if still alive.
 void ctx_add_server(lfmm_ctx* ctx, lfmm_server* srv);
 void ctx_remove_server(lfmm_ctx* ctx, lfmm_server* srv);

@@ -351,7 +351,7 @@ struct lfmm_plan {
     TileRange m2l;                          // M2L tiles (class-sorted, some empty)
     std::vector<TileRange> m2m, l2l;        // tiles per height
     int64_t m2l_pairs = 0;
-    Arena mem_small, mem_pts, mem_box;
+    Arena mem_small, mem_pts, mem_box, mem_ad;
     InstInfo* d_inst = nullptr;
     OpsPtrs* d_ops = nullptr;
     uint8_t* d_far = nullptr;
@@ -371,6 +371,16 @@ struct lfmm_plan {
     double *Q = nullptr, *U = nullptr;
     float *Qh = nullptr, *Ql = nullptr;     // mixed precision: FP32 parts of Q (with its zero row)
     double* qsum = nullptr;                 // and the charge sum of each row
+    // adaptive tree (LFMM_FLAG_ADAPTIVE)
+    bool adaptive = false;
+    int8_t* role = nullptr;                 // BoxRole of every box
+    int32_t* list_off = nullptr;            // [3][nbox + 1] row starts of the U, W, X lists
+    int32_t* list_ent[3] = {};              // their entries
+    int64_t list_len[3] = {};
+    int32_t* ad_leaves = nullptr;           // adaptive leaves (near-field items)
+    int32_t* ad_xboxes = nullptr;           // boxes with a non-empty X list (P2L items)
+    int32_t n_ad_leaves = 0, n_ad_xboxes = 0;
+    int32_t* pt_box = nullptr;              // finest box of every point
     ExecPtrs* h_exec = nullptr;             // pinned staging of the per-execute pointers
     size_t h_exec_cls = 0;
     hipEvent_t exec_copied = nullptr;       // the last staging copy has been read
@@ -465,6 +475,14 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st, bool l
     std::vector<float> ifo_hi(ifo.size(), 0.f), ifo_lo(ifo.size(), 0.f);
     std::vector<double> mono(size_t(nlev) * kNumIfoSlots, 0.0);
     std::vector<int32_t> ranks(static_cast<size_t>(nlev), 0);
+    std::vector<int32_t> skel(size_t(nlev) * P * 2, 0);   // skeleton points of each height
+    for (int h = 0; h < nlev; ++h) {
+        const LevelOps& lv = H.level[size_t(h)];
+        for (int p = 0; p < lv.rank; ++p) {
+            skel[(size_t(h) * P + p) * 2] = int32_t(lv.skel[2 * p]);
+            skel[(size_t(h) * P + p) * 2 + 1] = int32_t(lv.skel[2 * p + 1]);
+        }
+    }
     for (int h = 0; h < nlev; ++h) {
         const int r = H.level[size_t(h)].rank;
         ranks[size_t(h)] = r;
@@ -524,6 +542,7 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st, bool l
     co->mem.reserve(ifo.size() * sizeof(float));
     co->mem.reserve(mono.size() * sizeof(double));
     co->mem.reserve(ranks.size() * sizeof(int32_t));
+    co->mem.reserve(skel.size() * sizeof(int32_t));
     co->mem.allocate();
     co->dev.leaf_side = side;
     co->dev.nlev = nlev;
@@ -535,6 +554,7 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st, bool l
     co->dev.ifo_lo = co->mem.take<float>(ifo.size());
     co->dev.mono = co->mem.take<double>(mono.size());
     co->dev.rank = co->mem.take<int32_t>(ranks.size());
+    co->dev.skel = co->mem.take<int32_t>(skel.size());
     LFMM_HIP(hipMemcpyAsync(co->dev.leafT, leafT.data(), leafT.size() * 8, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipMemcpyAsync(co->dev.ofo_cm, ofo_cm.data(), ofo_cm.size() * 8, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipMemcpyAsync(co->dev.ofo_rm, ofo_rm.data(), ofo_rm.size() * 8, hipMemcpyHostToDevice, st));
@@ -543,6 +563,7 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st, bool l
     LFMM_HIP(hipMemcpyAsync(co->dev.ifo_lo, ifo_lo.data(), ifo.size() * 4, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipMemcpyAsync(co->dev.mono, mono.data(), mono.size() * 8, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipMemcpyAsync(co->dev.rank, ranks.data(), ranks.size() * 4, hipMemcpyHostToDevice, st));
+    LFMM_HIP(hipMemcpyAsync(co->dev.skel, skel.data(), skel.size() * 4, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipStreamSynchronize(st));
     CachedOps* raw = co.get();
     ctx->ops[side] = raw;             // a shallower set stays alive for the plans using it
@@ -560,6 +581,7 @@ OpsPtrs ops_ptrs(const CachedOps* co) {
     p.ifo_lo = co->dev.ifo_lo;
     p.mono = co->dev.mono;
     p.rank = co->dev.rank;
+    p.skel = co->dev.skel;
     p.side = co->dev.leaf_side;
     p.nlev = co->dev.nlev;
     return p;
@@ -1068,6 +1090,13 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
         mb.reserve(size_t(nb + 1) * P * 4);              // Q lo
         mb.reserve(size_t(nb + 1) * 8);                  // charge sums
     }
+    const bool adaptive = (ctx->opt.flags & LFMM_FLAG_ADAPTIVE) != 0;
+    pl->adaptive = adaptive;
+    if (adaptive) {
+        mb.reserve(size_t(nb));                          // roles
+        mb.reserve(size_t(3) * size_t(nb + 1) * 4);      // list row starts
+        mb.reserve(size_t(n) * 4);                       // finest box of each point
+    }
     mb.allocate();
     pl->box_key = mb.take<uint64_t>(nb);
     pl->box_pt0 = mb.take<int32_t>(nb);
@@ -1089,6 +1118,11 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
         pl->Qh = mb.take<float>(size_t(nb + 1) * P);
         pl->Ql = mb.take<float>(size_t(nb + 1) * P);
         pl->qsum = mb.take<double>(size_t(nb + 1));
+    }
+    if (adaptive) {
+        pl->role = mb.take<int8_t>(nb);
+        pl->list_off = mb.take<int32_t>(size_t(3) * size_t(nb + 1));
+        pl->pt_box = mb.take<int32_t>(n);
     }
 
     // ---- tables ---------------------------------------------------------------------------------
@@ -1119,6 +1153,14 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     tmp2.reserve(size_t(nb) * 4 * 4);                    // class scans
     tmp2.reserve(64);                                    // class totals
     tmp2.reserve(scan_scratch_bytes(nb, 4));
+    if (adaptive) {
+        tmp2.reserve(size_t(nb) * 4 * 4);                // class scans over the M2L boxes
+        tmp2.reserve(64);                                // their totals
+        tmp2.reserve(size_t(3) * size_t(nb + 1) * 4);    // list lengths
+        tmp2.reserve(size_t(3) * size_t(nb + 1) * 4);    // item positions
+        tmp2.reserve(64);                                // totals of both
+        tmp2.reserve(scan_scratch_bytes(nb + 1, 3));
+    }
     tmp2.allocate();
     SyncOnUnwind unwind_tmp2;
     int32_t* leaf_pt0 = tmp2.take<int32_t>(nl);
@@ -1130,6 +1172,16 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     int32_t* cscan = tmp2.take<int32_t>(size_t(nb) * 4);
     int32_t* ctotal = tmp2.take<int32_t>(16);
     void* cscr = tmp2.take<char>(scan_scratch_bytes(nb, 4));
+    int32_t *cscan_v = nullptr, *ctotal_v = nullptr, *lcnt = nullptr, *lpos = nullptr, *ltot = nullptr;
+    void* lscr2 = nullptr;
+    if (adaptive) {
+        cscan_v = tmp2.take<int32_t>(size_t(nb) * 4);
+        ctotal_v = tmp2.take<int32_t>(16);
+        lcnt = tmp2.take<int32_t>(size_t(3) * size_t(nb + 1));
+        lpos = tmp2.take<int32_t>(size_t(3) * size_t(nb + 1));
+        ltot = tmp2.take<int32_t>(16);
+        lscr2 = tmp2.take<char>(scan_scratch_bytes(nb + 1, 3));
+    }
 
     // leaves (and the window keys of the points) straight from the scan of the leaf starts
     scan_leaf_starts(cl, pl->pinst, pl->d_inst, n, skeys, Dmax, pl->pts, pl->pkey, leaf_pt0, leaf_key, leaf_cl,
@@ -1142,13 +1194,58 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
                       pl->box_child, pl->box_pt1, pl->Q + size_t(nb) * P, pl->U + size_t(nb) * P, st);
     launch_lists(pl->box_key, pl->box_parent, pl->box_child, pl->box_inst, pl->box_lev, pl->d_inst, nb, pl->nb9,
                  pl->il27, st);
-    for (size_t o = 0; o < side_of.size(); ++o)   // groups need the leaves' neighbour lists
-        launch_near_groups(pl->near_of_ops[o].t0, h1_start[o], h1_count[o], d_roots + root_off[o],
-                           int32_t(roots[o].size()), pl->box_child, pl->nb9, pl->box_pt0, pl->box_pt1, pl->box_key,
-                           pl->groups, pl->ents, st);
-    scan_child_classes(pl->box_key, nb, cscan, ctotal, cscr, st);
-    launch_class_lists(d_groups, int32_t(groups.size()), tile_slots, cscan, ctotal, pl->box_key, nb, pl->cls_box,
-                       pl->tiles, st);
+    const int32_t m2l_slots = pl->m2l.n;
+    const int32_t n_m2l_groups = int32_t(m2l_groups.size());
+    if (!adaptive) {
+        for (size_t o = 0; o < side_of.size(); ++o)   // groups need the leaves' neighbour lists
+            launch_near_groups(pl->near_of_ops[o].t0, h1_start[o], h1_count[o], d_roots + root_off[o],
+                               int32_t(roots[o].size()), pl->box_child, pl->nb9, pl->box_pt0, pl->box_pt1,
+                               pl->box_key, pl->groups, pl->ents, st);
+        scan_child_classes(pl->box_key, nb, cscan, ctotal, cscr, st);
+        launch_class_lists(d_groups, int32_t(groups.size()), 0, tile_slots, cscan, ctotal, pl->box_key, pl->box_lev,
+                           nullptr, nb, pl->cls_box, pl->tiles, st);
+    } else {
+        // roles, V lists (interaction lists without pruned boxes) and the M2L tiles over the
+        // boxes that take part; L2L keeps every box (pruned ones relay expansions)
+        launch_roles(pl->box_pt0, pl->box_pt1, pl->box_parent, pl->box_lev, pl->box_inst, pl->d_inst, nb, pl->role,
+                     st);
+        launch_filter_interactions(pl->role, nb, pl->il27, st);
+        scan_child_classes_active(pl->box_key, pl->box_lev, pl->role, nb, cscan_v, ctotal_v, cscr, st);
+        launch_class_lists(d_groups, n_m2l_groups, 0, m2l_slots, cscan_v, ctotal_v, pl->box_key, pl->box_lev,
+                           pl->role, nb, pl->cls_box, pl->tiles, st);
+        scan_child_classes(pl->box_key, nb, cscan, ctotal, cscr, st);
+        launch_class_lists(d_groups + n_m2l_groups, int32_t(groups.size()) - n_m2l_groups, m2l_slots,
+                           tile_slots - m2l_slots, cscan, ctotal, pl->box_key, pl->box_lev, nullptr, nb,
+                           pl->cls_box, pl->tiles, st);
+        // U, W, X lists: lengths, row starts, item positions, one read-back of the totals
+        const int64_t nb1 = nb + 1;
+        launch_adaptive_lists(false, pl->box_key, pl->box_parent, pl->box_child, pl->box_lev, pl->role, pl->nb9, nb,
+                              lcnt, nullptr, nullptr, st);
+        scan_rows(lcnt, pl->list_off, nb1, 3, ltot, lscr2, st);
+        scan_positive(lcnt, nb1, 3, lpos, ltot + 4, lscr2, st);
+        launch_point_boxes(pl->box_pt0, pl->box_pt1, pl->nleaf, pl->pt_box, st);
+        int32_t tot[8] = {};
+        LFMM_HIP(hipMemcpyAsync(tot, ltot, sizeof(tot), hipMemcpyDeviceToHost, st));
+        LFMM_HIP(hipStreamSynchronize(st));
+        Arena& ma = pl->mem_ad;
+        ma.set_pool(&ctx->pool, sreg);
+        for (int r = 0; r < 3; ++r) {
+            pl->list_len[r] = tot[r];
+            ma.reserve(size_t(std::max(tot[r], 1)) * 4);
+        }
+        pl->n_ad_leaves = tot[4];
+        pl->n_ad_xboxes = tot[6];
+        ma.reserve(size_t(std::max(tot[4], 1)) * 4);
+        ma.reserve(size_t(std::max(tot[6], 1)) * 4);
+        ma.allocate();
+        for (int r = 0; r < 3; ++r) pl->list_ent[r] = ma.take<int32_t>(size_t(std::max(tot[r], 1)));
+        pl->ad_leaves = ma.take<int32_t>(size_t(std::max(tot[4], 1)));
+        pl->ad_xboxes = ma.take<int32_t>(size_t(std::max(tot[6], 1)));
+        launch_adaptive_lists(true, pl->box_key, pl->box_parent, pl->box_child, pl->box_lev, pl->role, pl->nb9, nb,
+                              nullptr, pl->list_off, pl->list_ent, st);
+        launch_compact_positive(lcnt, lpos, nb, pl->ad_leaves, st);
+        launch_compact_positive(lcnt + 2 * nb1, lpos + 2 * nb1, nb, pl->ad_xboxes, st);
+    }
     LFMM_HIP(hipGetLastError());
     // staging for the per-execute pointer table of batched plans (and of graph replays,
     // whose kernels always read the table)
@@ -1201,12 +1298,32 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
         else
             launch_m2l(pl->tiles + pl->m2l.t0, pl->m2l.n, pl->cls_box, pl->il27, pl->d_ops, pl->Q, pl->nbox, pl->U, st);
     }
+    AdaptiveLists lists{};
+    if (pl->adaptive) {
+        for (int r = 0; r < 3; ++r) {
+            lists.off[r] = pl->list_off + size_t(r) * size_t(pl->nbox + 1);
+            lists.ent[r] = pl->list_ent[r];
+        }
+        // P2L of the X lists, counted with the interaction phase
+        launch_p2l(pl->n_ad_xboxes, pl->ad_xboxes, lists, pl->box_pt0, pl->box_pt1, pl->box_key, pl->box_lev,
+                   pl->box_inst, pl->d_inst, pl->d_ops, pl->pts, pl->fs, pl->U, pl->ctx->phi_oct, pl->ctx->phi_far,
+                   st);
+    }
     mark(4);
     for (int h = pl->Hmax; h >= 0; --h) {
         const TileRange& r = pl->l2l[size_t(h)];
-        if (r.n > 0) launch_l2l(pl->tiles + r.t0, r.n, pl->cls_box, pl->box_parent, pl->d_ops, pl->U, pl->nbox, st);
+        if (r.n > 0)
+            launch_l2l(pl->tiles + r.t0, r.n, pl->cls_box, pl->box_parent, pl->d_ops, pl->U, pl->nbox, pl->role, st);
     }
     mark(5);
+    if (pl->adaptive) {
+        launch_near_adaptive(pl->n_ad_leaves, pl->ad_leaves, lists, pl->box_pt0, pl->box_pt1, pl->box_key,
+                             pl->box_lev, pl->box_inst, pl->d_inst, pl->d_ops, pl->pts, pl->fs, pl->Q, pl->pt_box,
+                             pl->U, pl->perm, tab, u1, pl->tgt0[0], pl->d_far, pl->ctx->phi_oct, pl->ctx->phi_far,
+                             st);
+        mark(6);
+        return;
+    }
     for (size_t o = 0; o < pl->ops.size(); ++o) {
         const TileRange& r = pl->near_of_ops[o];
         launch_near(r.t0, r.t0 + r.n, pl->groups, pl->ents, pl->box_pt0, pl->box_pt1, pl->box_key, pl->box_inst,
@@ -1262,6 +1379,8 @@ void lfmm::plan_destroy_completed(lfmm_plan* pl) { delete pl; }
 
 
 int lfmm::ctx_device(const lfmm_ctx* ctx) { return ctx->device; }
+
+int32_t lfmm::ctx_flags(const lfmm_ctx* ctx) { return ctx->opt.flags; }
 
 void lfmm::ctx_add_server(lfmm_ctx* ctx, lfmm_server* srv) {
     std::lock_guard<std::mutex> lock(ctx->reg_mu);
@@ -1624,7 +1743,7 @@ lfmm_status lfmm_plan_get_info(lfmm_plan* pl, lfmm_plan_info* out) {
         LFMM_HIP(hipMemcpy(il.data(), pl->il27, nb * 4 * kNumInteractions, hipMemcpyDeviceToHost));
         LFMM_HIP(hipMemcpy(lev.data(), pl->box_lev, nb, hipMemcpyDeviceToHost));
         int64_t near = 0, m2l = 0;
-        for (int32_t g = 0; g < pl->nleaf; ++g) {
+        for (int32_t g = 0; g < pl->nleaf && !pl->adaptive; ++g) {
             int64_t ns = 0;
             for (int q = 0; q < 9; ++q) {
                 const int32_t s = nb9[size_t(g) * 9 + q];
@@ -1635,9 +1754,40 @@ lfmm_status lfmm_plan_get_info(lfmm_plan* pl, lfmm_plan_info* out) {
         for (size_t g = 0; g < nb; ++g)
             if (lev[g] >= 2)
                 for (int k = 0; k < kNumInteractions; ++k) m2l += (il[g * kNumInteractions + k] >= 0);
+        if (pl->adaptive) {
+            // U, W, X lists: near pairs, multipole evaluations and P2L terms
+            const size_t nb1 = nb + 1;
+            std::vector<int32_t> off(3 * nb1), rank;
+            std::vector<int32_t> ent[3];
+            LFMM_HIP(hipMemcpy(off.data(), pl->list_off, off.size() * 4, hipMemcpyDeviceToHost));
+            for (int r = 0; r < 3; ++r) {
+                ent[r].resize(size_t(pl->list_len[r]));
+                if (!ent[r].empty())
+                    LFMM_HIP(hipMemcpy(ent[r].data(), pl->list_ent[r], ent[r].size() * 4, hipMemcpyDeviceToHost));
+            }
+            std::vector<int32_t> binst(nb);
+            LFMM_HIP(hipMemcpy(binst.data(), pl->box_inst, nb * 4, hipMemcpyDeviceToHost));
+            auto rank_of = [&](size_t g) {
+                const InstInfo& I = pl->inst[size_t(binst[g])];
+                return pl->ops[size_t(I.ops)]->host.level[size_t(I.L - lev[g])].rank;
+            };
+            int64_t m2p = 0, p2l = 0;
+            for (size_t g = 0; g < nb; ++g) {
+                const int64_t ng = pt1[g] - pt0[g];
+                for (int32_t e = off[g]; e < off[g + 1]; ++e) near += ng * (pt1[size_t(ent[0][size_t(e)])] - pt0[size_t(ent[0][size_t(e)])]);
+                for (int32_t e = off[nb1 + g]; e < off[nb1 + g + 1]; ++e) m2p += ng * rank_of(size_t(ent[1][size_t(e)]));
+                for (int32_t e = off[2 * nb1 + g]; e < off[2 * nb1 + g + 1]; ++e)
+                    p2l += int64_t(rank_of(g)) * (pt1[size_t(ent[2][size_t(e)])] - pt0[size_t(ent[2][size_t(e)])]);
+            }
+            out->adaptive = 1;
+            out->n_leaves = pl->n_ad_leaves;
+            out->m2p_terms = m2p;
+            out->p2l_terms = p2l;
+        }
         out->near_pairs = near;
         out->m2l_pairs = m2l;
-        out->device_bytes = int64_t(pl->mem_small.bytes() + pl->mem_pts.bytes() + pl->mem_box.bytes());
+        out->device_bytes =
+            int64_t(pl->mem_small.bytes() + pl->mem_pts.bytes() + pl->mem_box.bytes() + pl->mem_ad.bytes());
         int64_t nt = 0;
         for (int32_t k = 0; k < pl->K; ++k) nt += pl->nout[size_t(k)];
         out->n_targets = nt;
@@ -1677,6 +1827,32 @@ lfmm_status lfmm_plan_export(lfmm_plan* pl, int32_t item, void* out, size_t* byt
         case LFMM_EXPORT_LOADS: src = pl->fs; size = n * 8; break;
         case LFMM_EXPORT_BOX_LEVEL: src = pl->box_lev; size = nb; break;
         case LFMM_EXPORT_BOX_INSTANCE: src = pl->box_inst; size = nb * 4; break;
+        case LFMM_EXPORT_BOX_ROLE:
+        case LFMM_EXPORT_LIST_U:
+        case LFMM_EXPORT_LIST_W:
+        case LFMM_EXPORT_LIST_X: {
+            if (!pl->adaptive) return fail(LFMM_E_INVAL, "adaptive-tree items of a plan without LFMM_FLAG_ADAPTIVE");
+            if (item == LFMM_EXPORT_BOX_ROLE) {
+                src = pl->role;
+                size = nb;
+                break;
+            }
+            const int r = item - LFMM_EXPORT_LIST_U;
+            size = (nb + 1 + size_t(pl->list_len[r])) * 4;
+            if (!out) break;
+            if (*bytes < size) return fail(LFMM_E_INVAL, "output buffer too small");
+            return guarded([&]() -> lfmm_status {
+                LFMM_HIP(hipSetDevice(pl->ctx->device));
+                LFMM_HIP(hipDeviceSynchronize());
+                int32_t* o32 = static_cast<int32_t*>(out);
+                LFMM_HIP(hipMemcpy(o32, pl->list_off + size_t(r) * (nb + 1), (nb + 1) * 4, hipMemcpyDeviceToHost));
+                if (pl->list_len[r] > 0)
+                    LFMM_HIP(hipMemcpy(o32 + nb + 1, pl->list_ent[r], size_t(pl->list_len[r]) * 4,
+                                       hipMemcpyDeviceToHost));
+                *bytes = size;
+                return LFMM_OK;
+            });
+        }
         default: return fail(LFMM_E_INVAL, "unknown export item");
     }
     if (!out) {
@@ -1735,6 +1911,8 @@ lfmm_status lfmm_plan_footprint_bytes(const lfmm_ctx* ctx, int64_t n_src, int64_
                                       size_t* out) {
     if (!ctx || !out || n_src < 0 || n_tgt < 0 || root_bits < -1 || root_bits > 31)
         return fail(LFMM_E_INVAL, "bad argument");
+    if (ctx->opt.flags & LFMM_FLAG_ADAPTIVE)
+        return fail(LFMM_E_UNSUPPORTED, "footprint bound of uniform trees only (context has LFMM_FLAG_ADAPTIVE)");
     // Bound on the device memory one single-instance plan holds, construction temporaries
     // included, each arena counted at the pool block that serves it (a power of two of at
     // least 64 KiB, so at most twice its size plus 64 KiB).  Level l of the tree holds at most
@@ -1822,6 +2000,8 @@ lfmm_status lfmm_solve_static(lfmm_ctx* ctx, int64_t n, const int32_t* xy, const
     if (n > kStaticMaxPoints)
         return fail(LFMM_E_RANGE, "lfmm_solve_static takes at most " + std::to_string(kStaticMaxPoints) + " points");
     if (!ctx->static_scratch) return fail(LFMM_E_HIP, "no static workspace on this device");
+    if (ctx->opt.flags & LFMM_FLAG_ADAPTIVE)
+        return fail(LFMM_E_UNSUPPORTED, "lfmm_solve_static builds uniform trees only (context has LFMM_FLAG_ADAPTIVE)");
     std::lock_guard<std::mutex> lock(g_static_mu[ctx->device & 63]);
     return guarded([&]() -> lfmm_status {
         LFMM_HIP(hipSetDevice(ctx->device));

@@ -27,7 +27,7 @@ lfmm_status validate_options(const lfmm_options* o) {
         return fail(LFMM_E_INVAL, "proxy_per_edge must lie in [8, 4096]");
     if (o->max_rank < 16 || o->max_rank > kMaxRank || o->max_rank % 16 != 0)
         return fail(LFMM_E_INVAL, "max_rank must be 16, 32, 48 or 64");
-    if (o->flags & ~(LFMM_FLAG_GRAPH | LFMM_FLAG_CHECK_LOADS)) return fail(LFMM_E_INVAL, "unknown bits in options.flags");
+    if (o->flags & ~(LFMM_FLAG_GRAPH | LFMM_FLAG_CHECK_LOADS | LFMM_FLAG_ADAPTIVE)) return fail(LFMM_E_INVAL, "unknown bits in options.flags");
     if (o->stencil != LFMM_STENCIL_5 && o->stencil != LFMM_STENCIL_9)
         return fail(LFMM_E_INVAL, "stencil must be LFMM_STENCIL_5 or LFMM_STENCIL_9");
     return LFMM_OK;

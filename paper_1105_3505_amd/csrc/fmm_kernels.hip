@@ -278,7 +278,7 @@ __device__ inline gptr<T> global(const T* p) {
 template <int MODE>
 __device__ inline void boxmat_tiles(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list,
                                     const int32_t* src_tab, const OpsPtrs* ops, const double* in, int32_t zrow,
-                                    double* out) {
+                                    double* out, const int8_t* role = nullptr) {
     constexpr int P = kRankPad, MT = P / 16, KQ = P / 4, NJ = KQ / 2;
     static_assert(MODE == kModeM2M || MODE == kModeL2L, "M2L has a kernel of its own");
     constexpr int NS = (MODE == kModeM2M) ? 4 : 1;
@@ -393,9 +393,11 @@ __device__ inline void boxmat_tiles(const BoxTile* tiles, int32_t ntiles, const 
         acc2 = run2;
         if (box >= 0) {
             double* ob = out + size_t(box) * P;
+            // a pruned box of the adaptive tree has no M2L result: it takes its parent's alone
+            const bool add = MODE == kModeL2L && !(role != nullptr && role[box] == kRolePruned);
             #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                if (MODE == kModeL2L) {
+                if (add) {
                     ob[g + 4 * i] += acc0[i];
                     ob[16 + g + 4 * i] += acc1[i];
                     ob[32 + g + 4 * i] += acc2[i];
@@ -546,8 +548,8 @@ __global__ __launch_bounds__(kBlock) void k_m2m(const BoxTile* tiles, int32_t nt
 
 __global__ __launch_bounds__(kBlock) void k_l2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list,
                                                  const int32_t* box_parent, const OpsPtrs* ops, double* U,
-                                                 int32_t zrow) {
-    boxmat_tiles<kModeL2L>(tiles, ntiles, box_list, box_parent, ops, U, zrow, U);
+                                                 int32_t zrow, const int8_t* role) {
+    boxmat_tiles<kModeL2L>(tiles, ntiles, box_list, box_parent, ops, U, zrow, U, role);
 }
 
 // Box-matrix passes for levels with few boxes (M2M and L2L).  The kernels above run a 64-box
@@ -561,7 +563,8 @@ __global__ __launch_bounds__(kBlock) void k_l2l(const BoxTile* tiles, int32_t nt
 // block are contiguous there), without LDS staging.
 template <int MODE>
 __device__ inline void boxmat_fine(const BoxTile* tiles, const int32_t* box_list, const int32_t* src_tab,
-                                   const OpsPtrs* ops, const double* in, int32_t zrow, double* out) {
+                                   const OpsPtrs* ops, const double* in, int32_t zrow, double* out,
+                                   const int8_t* role = nullptr) {
     constexpr int P = kRankPad, KQ = P / 4, NJ = KQ / 2, A2 = P * P / 2;
     static_assert(MODE == kModeM2M || MODE == kModeL2L, "fine mode serves M2M and L2L");
     __shared__ double red[4][4][64];
@@ -580,7 +583,8 @@ __device__ inline void boxmat_fine(const BoxTile* tiles, const int32_t* box_list
     if (box >= 0) src = (MODE == kModeM2M) ? src_tab[size_t(box) * 4 + wave] : src_tab[box];
     src = src < 0 ? zrow : src;
     const gptr<double> xs = global(in) + size_t(src) * P + g * KQ;
-    const double old = (MODE == kModeL2L && box >= 0) ? out[size_t(box) * P + 16 * m + g + 4 * wave] : 0.0;
+    const bool add = MODE == kModeL2L && box >= 0 && !(role != nullptr && role[box] == kRolePruned);
+    const double old = add ? out[size_t(box) * P + 16 * m + g + 4 * wave] : 0.0;
     const double4_t zero4 = {0.0, 0.0, 0.0, 0.0};
     double4_t acc = zero4;
     if (MODE == kModeM2M) {
@@ -627,8 +631,8 @@ __global__ __launch_bounds__(kBlock) void k_m2m_fine(const BoxTile* tiles, const
 
 __global__ __launch_bounds__(kBlock) void k_l2l_fine(const BoxTile* tiles, const int32_t* box_list,
                                                       const int32_t* box_parent, const OpsPtrs* ops, double* U,
-                                                      int32_t zrow) {
-    boxmat_fine<kModeL2L>(tiles, box_list, box_parent, ops, U, zrow, U);
+                                                      int32_t zrow, const int8_t* role) {
+    boxmat_fine<kModeL2L>(tiles, box_list, box_parent, ops, U, zrow, U, role);
 }
 
 // Mixed-precision operands of the outgoing expansions, once per box: q-hat split into FP32
@@ -1231,6 +1235,228 @@ __global__ __launch_bounds__(64 * kStagedWaves) void k_near_staged(
     }
 }
 
+// ---- adaptive tree passes ----------------------------------------------------------------
+
+__device__ inline double readlane_d(double v, int k) {
+    const int2_t w = __builtin_bit_cast(int2_t, v);
+    return __builtin_bit_cast(double, int2_t{__builtin_amdgcn_readlane(w.x, k), __builtin_amdgcn_readlane(w.y, k)});
+}
+
+// Lower-left corner of box g in its instance's root coordinates (root side 2^D).
+__device__ inline int2 box_corner(const uint64_t* box_key, const int8_t* box_lev, int32_t g, int D) {
+    const uint64_t k = box_key[g];
+    const int sh = D - int(box_lev[g]);
+    return make_int2(int32_t(compact_bits(k)) << sh, int32_t(compact_bits(k >> 1)) << sh);
+}
+
+// P2L (X lists): one wave per box tau, lane p for skeleton point p of tau; the points of each
+// leaf of X(tau) are read 64 at a time (one coalesced load per lane) and broadcast lane by
+// lane, every skeleton lane adding phi(y_p - x_j) f_j.  The sum joins tau's incoming
+// expansion, which M2L wrote before and L2L reads after (the incoming skeleton is the
+// outgoing one, T_ifi = T_ofo^T).
+__global__ __launch_bounds__(kBlock) void k_p2l(int32_t nx, const int32_t* xitems, AdaptiveLists L,
+                                                const int32_t* box_pt0, const int32_t* box_pt1,
+                                                const uint64_t* box_key, const int8_t* box_lev,
+                                                const int32_t* box_inst, const InstInfo* inst, const OpsPtrs* ops,
+                                                const int2* pts, const double* fs, double* U,
+                                                const double* phi_oct_tab, const PhiFar* phi_far) {
+    constexpr int P = kRankPad;
+    const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
+    const int32_t q = int32_t(blockIdx.x) * kWaves + wave;
+    if (q >= nx) return;
+    const int32_t tau = uniform(xitems[q]);
+    const int32_t k_inst = uniform(box_inst[tau]);
+    const int D = uniform(inst[k_inst].D), Lf = uniform(inst[k_inst].L), opi = uniform(inst[k_inst].ops);
+    const int h = Lf - int(box_lev[tau]);
+    const int rank = uniform(ops[opi].rank[h]);
+    const int2 c = box_corner(box_key, box_lev, tau, D);
+    const bool on = lane < rank;
+    int2 y = c;
+    if (on) {
+        const int32_t* sk = ops[opi].skel + (size_t(h) * P + lane) * 2;
+        y = make_int2(c.x + sk[0], c.y + sk[1]);
+    }
+    double acc = 0.0;
+    const int32_t e0 = uniform(L.off[2][tau]), e1 = uniform(L.off[2][tau + 1]);
+    for (int32_t e = e0; e < e1; ++e) {
+        const int32_t sg = uniform(L.ent[2][e]);
+        const int32_t j0 = uniform(box_pt0[sg]), j1 = uniform(box_pt1[sg]);
+        for (int32_t base = j0; base < j1; base += 64) {
+            const int32_t j = base + lane;
+            const bool ok = j < j1;
+            const int2 pj = ok ? pts[j] : make_int2(0, 0);
+            const double fj = ok ? fs[j] : 0.0;
+            const int m = min(64, j1 - base);
+            for (int k = 0; k < m; ++k) {
+                const int32_t xk = __builtin_amdgcn_readlane(pj.x, k), yk = __builtin_amdgcn_readlane(pj.y, k);
+                const double fk = readlane_d(fj, k);
+                acc += phi_oct(abs(y.x - xk), abs(y.y - yk), phi_oct_tab, phi_far) * fk;
+            }
+        }
+    }
+    if (on && e1 > e0) U[size_t(tau) * P + lane] += acc;
+}
+
+// Near field of the adaptive leaves (Section 8.2 step 5 on the adaptive tree), one wave per
+// leaf tau: the sources are the points of the U-list leaves and, for the W-list boxes, their
+// skeleton points carrying their outgoing expansions (M2P: phi(x_i - y_p) q_p).  The wave
+// first writes a descriptor of each list entry into LDS (up to 64 at a time: kind, start,
+// corner, and the prefix sum of the entry lengths), then copies the sources into LDS in
+// chunks of kStageCap, each lane finding an element's entry by bisection over the prefix sums
+// and keeping kStageRound loads in flight, and sums from LDS as k_near_staged does (T lanes per
+// target, S slices).  L2P runs at each point's finest box (its incoming expansion holds those
+// of the adaptive leaf relayed by L2L), then the caller-order write.
+constexpr int kAdWaves = 4;
+
+struct AdWaveLds {
+    int2 xy[kStageCap];
+    double f[kStageCap];
+    int32_t off[65];   // prefix sums of the entry lengths of the batch
+    int32_t a[64];     // U entry: first point; W entry: box
+    int32_t h[64];     // W entry: height of the box (its skeleton); U entry: -1
+    int2 c[64];        // W entry: corner of the box
+};
+
+template <int P>
+__global__ __launch_bounds__(64 * kAdWaves) void k_near_adaptive(
+    int32_t nitems, const int32_t* items, AdaptiveLists L, const int32_t* box_pt0, const int32_t* box_pt1,
+    const uint64_t* box_key, const int8_t* box_lev, const int32_t* box_inst, const InstInfo* inst,
+    const OpsPtrs* ops, const int2* pts, const double* fs, const double* Q, const int32_t* pt_box, const double* U,
+    const int32_t* perm_local, const ExecPtrs* tab_ptrs, double* u_single, int32_t tgt0_single,
+    const uint8_t* far_inst, const double* phi_oct_tab, const PhiFar* phi_far) {
+    __shared__ AdWaveLds s_w[kAdWaves];
+    const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
+    const int32_t q = int32_t(blockIdx.x) * kAdWaves + wave;
+    if (q >= nitems) return;   // uniform over the wave; no block-wide barrier below
+    AdWaveLds& S = s_w[wave];
+    const int32_t tau = uniform(items[q]);
+    const int32_t k_inst = uniform(box_inst[tau]);
+    const int D = uniform(inst[k_inst].D), Lf = uniform(inst[k_inst].L), opi = uniform(inst[k_inst].ops);
+    const OpsPtrs& O = ops[opi];
+    const int32_t side0 = int32_t(O.side);
+    const double* leafT = O.leafT;
+    const int32_t* skel = O.skel;
+    const bool far = far_inst[k_inst] != 0;
+    double* u = tab_ptrs ? tab_ptrs[k_inst].u : u_single;
+    const int32_t tgt0 = tab_ptrs ? tab_ptrs[k_inst].tgt0 : tgt0_single;
+    const int32_t t0 = uniform(box_pt0[tau]), t_end = uniform(box_pt1[tau]);
+    const int32_t u0 = uniform(L.off[0][tau]), nu = uniform(L.off[0][tau + 1]) - u0;
+    const int32_t w0 = uniform(L.off[1][tau]), nw = uniform(L.off[1][tau + 1]) - w0;
+    const int32_t ne = nu + nw;
+    const int32_t nt = t_end - t0;
+    int T = 1;
+    while (T < nt && T < 64) T <<= 1;
+    const int Sl = 64 / T, tl = lane & (T - 1), sl = lane / T;
+    auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    for (int32_t i0 = t0; i0 < t_end; i0 += T) {
+        const int32_t i = i0 + tl;
+        const bool valid = i < t_end;
+        const int32_t ii = valid ? i : t0;
+        const int2 pi = pts[ii];
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (int32_t eb = 0; eb < ne; eb += 64) {
+            // descriptors of entries eb .. eb + 63
+            const int32_t e = eb + lane;
+            int32_t len = 0, a = 0, hh = -1;
+            int2 cc = make_int2(0, 0);
+            if (e < nu) {
+                const int32_t sg = L.ent[0][u0 + e];
+                a = box_pt0[sg];
+                len = box_pt1[sg] - a;
+            } else if (e < ne) {
+                const int32_t d = L.ent[1][w0 + e - nu];
+                hh = Lf - int(box_lev[d]);
+                len = O.rank[hh];
+                a = d;
+                cc = box_corner(box_key, box_lev, d, D);
+            }
+            int32_t incl = len;
+            #pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t v = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += v;
+            }
+            const int32_t total = __builtin_amdgcn_readlane(incl, 63);
+            wave_sync();   // the previous batch's reads of the descriptors are done
+            S.off[lane] = incl - len;
+            if (lane == 63) S.off[64] = total;
+            S.a[lane] = a;
+            S.h[lane] = hh;
+            S.c[lane] = cc;
+            for (int32_t c0 = 0; c0 < total; c0 += kStageCap) {
+                const int32_t c1 = min(total, c0 + kStageCap);
+                wave_sync();   // descriptors written; the previous chunk's sums are done
+                for (int32_t base = c0; base < c1; base += 64 * kStageRound) {
+                    int2 v[kStageRound];
+                    double w[kStageRound];
+                    #pragma unroll
+                    for (int r = 0; r < kStageRound; ++r) {
+                        const int32_t t = base + r * 64 + lane;
+                        v[r] = make_int2(0, 0);
+                        w[r] = 0.0;
+                        if (t < c1) {
+                            int lo = 0, hi = 63;   // last entry starting at or before t
+                            while (lo < hi) {
+                                const int mid = (lo + hi + 1) >> 1;
+                                if (S.off[mid] <= t) lo = mid;
+                                else hi = mid - 1;
+                            }
+                            const int32_t k = t - S.off[lo];
+                            const int32_t hk = S.h[lo];
+                            if (hk < 0) {
+                                v[r] = pts[S.a[lo] + k];
+                                w[r] = fs[S.a[lo] + k];
+                            } else {
+                                const int32_t* sk = skel + (size_t(hk) * P + k) * 2;
+                                const int2 c = S.c[lo];
+                                v[r] = make_int2(c.x + sk[0], c.y + sk[1]);
+                                w[r] = Q[size_t(S.a[lo]) * P + k];
+                            }
+                        }
+                    }
+                    #pragma unroll
+                    for (int r = 0; r < kStageRound; ++r) {
+                        const int32_t t = base + r * 64 + lane;
+                        if (t < c1) {
+                            S.xy[t - c0] = v[r];
+                            S.f[t - c0] = w[r];
+                        }
+                    }
+                }
+                wave_sync();
+                const int32_t m = c1 - c0;
+                auto pair = [&](int32_t j) -> double {
+                    const int2 pj = S.xy[j];
+                    return phi_oct(abs(pi.x - pj.x), abs(pi.y - pj.y), phi_oct_tab, phi_far) * S.f[j];
+                };
+                int32_t j = sl;
+                for (; j + 3 * Sl < m; j += 4 * Sl) {
+                    a0 += pair(j);
+                    a1 += pair(j + Sl);
+                    a2 += pair(j + 2 * Sl);
+                    a3 += pair(j + 3 * Sl);
+                }
+                for (; j < m; j += Sl) a0 += pair(j);
+            }
+        }
+        if (far) {
+            const int32_t b = pt_box[ii];
+            const int64_t loc = int64_t(pi.x & (side0 - 1)) + int64_t(side0) * int64_t(pi.y & (side0 - 1));
+            const double* tlp = leafT + loc * P;
+            const double* uh = U + size_t(b) * P;
+            for (int p = sl; p < P; p += Sl) a1 += tlp[p] * uh[p];
+        }
+        double acc = (a0 + a1) + (a2 + a3);
+        for (int o = T; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+        const int32_t pout = perm_local[ii];
+        if (valid && sl == 0 && pout >= tgt0) u[pout - tgt0] = acc;
+    }
+}
+
 // Brute-force sum over all sources for blocks of 256 targets; sources staged through LDS.
 __global__ __launch_bounds__(kBlock) void k_direct(int64_t nt, const int2* txy, int64_t ns, const int2* sxy,
                                                     const double* f, const double* phi_oct, const PhiFar* far,
@@ -1350,17 +1576,17 @@ void launch_m2m(const BoxTile* tiles, int32_t ntiles, const int32_t* box_child, 
 }
 
 void launch_l2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, const int32_t* box_parent,
-                const OpsPtrs* ops, double* U, int32_t zrow, hipStream_t st) {
+                const OpsPtrs* ops, double* U, int32_t zrow, const int8_t* role, hipStream_t st) {
     if (ntiles <= 0) return;
     if (ntiles <= kFineL2lTiles) {
         hipLaunchKernelGGL(k_l2l_fine, dim3(unsigned(ntiles) * 12u), dim3(kBlock), 0, st, tiles, box_list, box_parent,
-                           ops, U, zrow);
+                           ops, U, zrow, role);
         return;
     }
     int64_t g = std::min<int64_t>(ntiles, 8192);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
     hipLaunchKernelGGL(k_l2l, dim3(static_cast<unsigned>(g)), dim3(kBlock), 0, st, tiles, ntiles, box_list,
-                       box_parent, ops, U, zrow);
+                       box_parent, ops, U, zrow, role);
 }
 
 void launch_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, const int32_t* il27,
@@ -1446,6 +1672,29 @@ void launch_phi_extend(double* oct, int r0, int r1, const PhiFar* far, hipStream
     if (r1 <= r0) return;
     const int64_t n = int64_t(r1 + 1) * (r1 + 2) / 2 - int64_t(r0 + 1) * (r0 + 2) / 2;
     hipLaunchKernelGGL(k_phi_extend, dim3(grid_for(n)), dim3(kBlock), 0, st, oct, r0, r1, far);
+}
+
+void launch_p2l(int32_t nx, const int32_t* xitems, const AdaptiveLists& lists, const int32_t* box_pt0,
+                const int32_t* box_pt1, const uint64_t* box_key, const int8_t* box_lev, const int32_t* box_inst,
+                const InstInfo* inst, const OpsPtrs* ops, const int32_t* pts, const double* fs, double* U,
+                const double* phi_oct, const PhiFar* phi_far, hipStream_t st) {
+    if (nx <= 0) return;
+    const unsigned g = unsigned((nx + kWaves - 1) / kWaves);
+    hipLaunchKernelGGL(k_p2l, dim3(g), dim3(kBlock), 0, st, nx, xitems, lists, box_pt0, box_pt1, box_key, box_lev,
+                       box_inst, inst, ops, reinterpret_cast<const int2*>(pts), fs, U, phi_oct, phi_far);
+}
+
+void launch_near_adaptive(int32_t nitems, const int32_t* items, const AdaptiveLists& lists, const int32_t* box_pt0,
+                          const int32_t* box_pt1, const uint64_t* box_key, const int8_t* box_lev,
+                          const int32_t* box_inst, const InstInfo* inst, const OpsPtrs* ops, const int32_t* pts,
+                          const double* fs, const double* Q, const int32_t* pt_box, const double* U,
+                          const int32_t* perm_local, const ExecPtrs* tab, double* u_single, int32_t tgt0_single,
+                          const uint8_t* far_inst, const double* phi_oct, const PhiFar* phi_far, hipStream_t st) {
+    if (nitems <= 0) return;
+    const unsigned g = unsigned((nitems + kAdWaves - 1) / kAdWaves);
+    hipLaunchKernelGGL(k_near_adaptive<kRankPad>, dim3(g), dim3(64 * kAdWaves), 0, st, nitems, items, lists, box_pt0,
+                       box_pt1, box_key, box_lev, box_inst, inst, ops, reinterpret_cast<const int2*>(pts), fs, Q,
+                       pt_box, U, perm_local, tab, u_single, tgt0_single, far_inst, phi_oct, phi_far);
 }
 
 void launch_direct(int64_t nt, const int32_t* txy, int64_t ns, const int32_t* sxy, const double* f,

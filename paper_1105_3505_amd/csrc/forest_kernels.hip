@@ -450,11 +450,18 @@ __device__ inline int32_t scan_at(const int32_t* cscan, const int32_t* ctotal, i
     return (g < nbox) ? cscan[size_t(c) * nbox + g] : ctotal[c];
 }
 
+// with role: whether box g takes part in M2L (pruned boxes of level >= 3 do not; those of
+// level 2 keep their tile so that M2L writes their zero expansion)
+__device__ inline bool m2l_box(const int8_t* box_lev, const int8_t* role, int64_t g) {
+    return role == nullptr || role[g] != kRolePruned || box_lev[g] < 3;
+}
+
 // box -> position in the class list of every group containing it
 __global__ void k_class_boxes(const BoxGroup* groups, int32_t ngroups, const int32_t* cscan, const int32_t* ctotal,
-                              const uint64_t* box_key, int64_t nbox, int32_t* cls_box) {
+                              const uint64_t* box_key, const int8_t* box_lev, const int8_t* role, int64_t nbox,
+                              int32_t* cls_box) {
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= nbox) return;
+    if (g >= nbox || !m2l_box(box_lev, role, g)) return;
     const int c = int(box_key[g] & 3ull);
     for (int32_t q = 0; q < ngroups; ++q) {   // groups are few (heights x leaf sides x 2)
         const BoxGroup G = groups[q];
@@ -474,10 +481,10 @@ __device__ inline int32_t rounds_before(const int32_t* nt, int32_t i) {
 // tile of class 0, 1, 2, 3 in turn, classes with fewer tiles dropping out), so that tiles
 // next to each other in the list cover the same region of the level and share their
 // source expansions in cache; empty tiles fill the rest of the group.
-__global__ void k_class_tiles(const BoxGroup* groups, int32_t ngroups, int32_t nslots, const int32_t* cscan,
-                              const int32_t* ctotal, int64_t nbox, BoxTile* tiles) {
-    const int32_t t = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= nslots) return;
+__global__ void k_class_tiles(const BoxGroup* groups, int32_t ngroups, int32_t slot0, int32_t nslots,
+                              const int32_t* cscan, const int32_t* ctotal, int64_t nbox, BoxTile* tiles) {
+    const int32_t t = slot0 + int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= slot0 + nslots) return;
     int32_t lo = 0, hi = ngroups - 1;
     while (lo < hi) {
         const int32_t mid = (lo + hi + 1) >> 1;
@@ -521,6 +528,158 @@ __global__ void k_class_tiles(const BoxGroup* groups, int32_t ngroups, int32_t n
         }
     }
     tiles[t] = tl;
+}
+
+// ---- adaptive tree ------------------------------------------------------------------------
+// Role of every box: a box belongs to the adaptive tree when its parent holds more than N_leaf
+// points (the root always); it is a leaf of it when it holds at most N_leaf points or lies on
+// the finest level.  Counts are monotone along parent links, so no pass over ancestors.
+__global__ void k_roles(const int32_t* box_pt0, const int32_t* box_pt1, const int32_t* box_parent,
+                        const int8_t* box_lev, const int32_t* box_inst, const InstInfo* inst, int64_t nbox,
+                        int8_t* role) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= nbox) return;
+    const InstInfo& I = inst[box_inst[g]];
+    const int lev = box_lev[g];
+    const int32_t p = box_parent[g];
+    const bool member = lev == 0 || p < 0 || box_pt1[p] - box_pt0[p] > I.max_leaf;
+    const bool leaf = box_pt1[g] - box_pt0[g] <= I.max_leaf || lev >= I.L;
+    role[g] = member ? (leaf ? kRoleLeaf : kRoleInner) : kRolePruned;
+}
+
+__global__ void k_filter_interactions(const int8_t* role, int64_t nbox, int32_t* il27) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nbox * kNumInteractions) return;
+    const int64_t g = t / kNumInteractions;
+    const int32_t r = il27[t];
+    if (r >= 0 && (role[g] == kRolePruned || role[r] == kRolePruned)) il27[t] = -1;
+}
+
+// Box (level, x, y), x and y in units of its level.
+struct BoxAt {
+    int lev;
+    int32_t x, y;
+};
+
+__device__ inline BoxAt box_at(const uint64_t* box_key, const int8_t* box_lev, int32_t g) {
+    const uint64_t k = box_key[g];
+    return BoxAt{int(box_lev[g]), int32_t(compact_bits(k)), int32_t(compact_bits(k >> 1))};
+}
+
+// whether the closed squares of two disjoint boxes of one instance meet (share an edge or a
+// corner)
+__device__ inline bool touches(BoxAt a, BoxAt b) {
+    if (a.lev < b.lev) {
+        const BoxAt t = a;
+        a = b;
+        b = t;
+    }
+    const int d = a.lev - b.lev;   // b covers [x << d, (x + 1) << d) in units of a's level
+    const int64_t x0 = int64_t(b.x) << d, x1 = (int64_t(b.x) + 1) << d;
+    const int64_t y0 = int64_t(b.y) << d, y1 = (int64_t(b.y) + 1) << d;
+    return int64_t(a.x) + 1 >= x0 && int64_t(a.x) <= x1 && int64_t(a.y) + 1 >= y0 && int64_t(a.y) <= y1;
+}
+
+struct ListOut {
+    bool fill;
+    int32_t* cnt;            // [3][nbox + 1] counts (count pass; the last of each row zero)
+    const int32_t* off[3];   // row starts (fill pass)
+    int32_t* ent[3];
+    int64_t nbox;
+    __device__ void put(int r, int32_t g, int32_t& n, int32_t v) const {
+        if (fill) ent[r][off[r][g] + n] = v;
+        ++n;
+    }
+};
+
+// Depth of the stack of the W/U descent below a colleague: each level leaves at most three
+// siblings waiting, over at most kMaxLevels levels.
+constexpr int kListStack = 3 * kMaxLevels + 4;
+
+// U and W of every adaptive leaf and X of every box of the adaptive tree, one thread per box.
+//   U(tau): tau; the colleagues that are leaves; below the other colleagues (inner boxes), the
+//     descendants that touch tau and are leaves (a descent through those that touch tau);
+//     and the coarser leaves that touch tau, found among the neighbours of its ancestors
+//     (a leaf touching tau touches the ancestor of tau on its own level).
+//   W(tau): in that descent, the children that do not touch tau.
+//   X(tau): the leaves coarser than tau that touch its parent but not tau, among the
+//     neighbours of its ancestors.
+__global__ void k_adaptive_lists(const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_child,
+                                 const int8_t* box_lev, const int8_t* role, const int32_t* nb9, int64_t nbox,
+                                 ListOut o) {
+    const int64_t gg = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gg > nbox) return;
+    const int32_t g = int32_t(gg);
+    const size_t stride = size_t(nbox) + 1;
+    if (gg == nbox || role[g] == kRolePruned) {
+        if (!o.fill)
+            for (int r = 0; r < 3; ++r) o.cnt[size_t(r) * stride + g] = 0;
+        return;
+    }
+    const int8_t rg = role[g];
+    const BoxAt tau = box_at(box_key, box_lev, g);
+    int32_t nu = 0, nw = 0, nx = 0;
+    if (rg == kRoleLeaf) {
+        o.put(0, g, nu, g);
+        int32_t stack[kListStack];
+        int sp = 0;
+        for (int q = 0; q < 9; ++q) {
+            if (q == 4) continue;
+            const int32_t c = nb9[size_t(g) * 9 + q];
+            if (c < 0 || role[c] == kRolePruned) continue;
+            if (role[c] == kRoleLeaf) {
+                o.put(0, g, nu, c);
+                continue;
+            }
+            stack[sp++] = c;
+            while (sp > 0) {
+                const int32_t b = stack[--sp];
+                for (int k = 3; k >= 0; --k) {   // pushed in reverse: children visited in order
+                    const int32_t d = box_child[size_t(b) * 4 + k];
+                    if (d < 0) continue;
+                    if (!touches(tau, box_at(box_key, box_lev, d))) o.put(1, g, nw, d);
+                    else if (role[d] == kRoleLeaf) o.put(0, g, nu, d);
+                    else if (sp < kListStack) stack[sp++] = d;
+                }
+            }
+        }
+        for (int32_t a = box_parent[g]; a >= 0 && box_lev[a] >= 1; a = box_parent[a])
+            for (int q = 0; q < 9; ++q) {
+                if (q == 4) continue;
+                const int32_t c = nb9[size_t(a) * 9 + q];
+                if (c >= 0 && role[c] == kRoleLeaf && touches(tau, box_at(box_key, box_lev, c))) o.put(0, g, nu, c);
+            }
+    }
+    if (tau.lev >= 2) {
+        const int32_t p = box_parent[g];
+        const BoxAt par = box_at(box_key, box_lev, p);
+        for (int32_t a = p; a >= 0 && box_lev[a] >= 1; a = box_parent[a])
+            for (int q = 0; q < 9; ++q) {
+                if (q == 4) continue;
+                const int32_t c = nb9[size_t(a) * 9 + q];
+                if (c < 0 || role[c] != kRoleLeaf) continue;
+                const BoxAt cb = box_at(box_key, box_lev, c);
+                if (touches(par, cb) && !touches(tau, cb)) o.put(2, g, nx, c);
+            }
+    }
+    if (!o.fill) {
+        o.cnt[g] = nu;
+        o.cnt[stride + g] = nw;
+        o.cnt[2 * stride + g] = nx;
+    }
+}
+
+__global__ void k_compact_positive(const int32_t* cnt, const int32_t* pos, int64_t nbox, int32_t* items) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g < nbox && cnt[g] > 0) items[pos[g]] = int32_t(g);
+}
+
+// finest box of every point: a thread per finest box (their blocks follow the instance order
+// of the height blocks, not the point order) writes its index over its points
+__global__ void k_point_boxes(const int32_t* box_pt0, const int32_t* box_pt1, int32_t nleaf, int32_t* pt_box) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= nleaf) return;
+    for (int32_t i = box_pt0[g]; i < box_pt1[g]; ++i) pt_box[i] = int32_t(g);
 }
 
 // Near-field groups, 16 lanes per group: the group's leaves (the children of a height-1 box,
@@ -795,6 +954,19 @@ struct ChildClass {   // row c: 1 where box g sits in child position c of its pa
     const uint64_t* box_key;
     __device__ int32_t operator()(int c, int64_t g) const { return int(box_key[g] & 3ull) == c ? 1 : 0; }
 };
+struct ChildClassM2L {   // the same over the boxes that take part in M2L
+    const uint64_t* box_key;
+    const int8_t* box_lev;
+    const int8_t* role;
+    __device__ int32_t operator()(int c, int64_t g) const {
+        return (int(box_key[g] & 3ull) == c && m2l_box(box_lev, role, g)) ? 1 : 0;
+    }
+};
+struct RowsPositive {   // 1 where the value is positive, row stride n
+    const int32_t* in;
+    int64_t n;
+    __device__ int32_t operator()(int r, int64_t i) const { return in[size_t(r) * n + i] > 0 ? 1 : 0; }
+};
 
 __device__ inline int32_t block_sum(int32_t v) {
     __shared__ int32_t ws[kBlock / 64];
@@ -928,6 +1100,16 @@ void scan_level_starts(const int8_t* leaf_cl, const int32_t* leaf_inst, const In
 void scan_child_classes(const uint64_t* box_key, int64_t nbox, int32_t* out, int32_t* totals, void* scratch,
                         hipStream_t st) {
     scan_source(ChildClass{box_key}, out, nbox, 4, totals, scratch, st);
+}
+
+void scan_child_classes_active(const uint64_t* box_key, const int8_t* box_lev, const int8_t* role, int64_t nbox,
+                               int32_t* out, int32_t* totals, void* scratch, hipStream_t st) {
+    scan_source(ChildClassM2L{box_key, box_lev, role}, out, nbox, 4, totals, scratch, st);
+}
+
+void scan_positive(const int32_t* cnt, int64_t n, int rows, int32_t* out, int32_t* totals, void* scratch,
+                   hipStream_t st) {
+    scan_source(RowsPositive{cnt, n}, out, n, rows, totals, scratch, st);
 }
 
 // Tiles whose counts a scatter block sums itself (tile-major counts, no scan launches); above
@@ -1069,14 +1251,56 @@ void launch_lists(const uint64_t* box_key, const int32_t* box_parent, const int3
                        box_parent, box_child, box_lev, nbox, nb9, il27);
 }
 
-void launch_class_lists(const BoxGroup* groups, int32_t ngroups, int32_t nslots, const int32_t* cscan,
-                        const int32_t* ctotal, const uint64_t* box_key, int64_t nbox, int32_t* cls_box,
+void launch_class_lists(const BoxGroup* groups, int32_t ngroups, int32_t slot0, int32_t nslots,
+                        const int32_t* cscan, const int32_t* ctotal, const uint64_t* box_key,
+                        const int8_t* box_lev, const int8_t* role, int64_t nbox, int32_t* cls_box,
                         BoxTile* tiles, hipStream_t st) {
     if (ngroups <= 0) return;
     hipLaunchKernelGGL(k_class_boxes, dim3(grid_for(nbox)), dim3(kBlock), 0, st, groups, ngroups, cscan, ctotal,
-                       box_key, nbox, cls_box);
-    hipLaunchKernelGGL(k_class_tiles, dim3(grid_for(nslots)), dim3(kBlock), 0, st, groups, ngroups, nslots, cscan,
-                       ctotal, nbox, tiles);
+                       box_key, box_lev, role, nbox, cls_box);
+    if (nslots > 0)
+        hipLaunchKernelGGL(k_class_tiles, dim3(grid_for(nslots)), dim3(kBlock), 0, st, groups, ngroups, slot0, nslots,
+                           cscan, ctotal, nbox, tiles);
+}
+
+void launch_roles(const int32_t* box_pt0, const int32_t* box_pt1, const int32_t* box_parent, const int8_t* box_lev,
+                  const int32_t* box_inst, const InstInfo* inst, int64_t nbox, int8_t* role, hipStream_t st) {
+    if (nbox <= 0) return;
+    hipLaunchKernelGGL(k_roles, dim3(grid_for(nbox)), dim3(kBlock), 0, st, box_pt0, box_pt1, box_parent, box_lev,
+                       box_inst, inst, nbox, role);
+}
+
+void launch_filter_interactions(const int8_t* role, int64_t nbox, int32_t* il27, hipStream_t st) {
+    if (nbox <= 0) return;
+    hipLaunchKernelGGL(k_filter_interactions, dim3(grid_for(nbox * kNumInteractions)), dim3(kBlock), 0, st, role,
+                       nbox, il27);
+}
+
+void launch_adaptive_lists(bool fill, const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_child,
+                           const int8_t* box_lev, const int8_t* role, const int32_t* nb9, int64_t nbox,
+                           int32_t* cnt, const int32_t* off, int32_t* const* ent, hipStream_t st) {
+    if (nbox <= 0) return;
+    ListOut o{};
+    o.fill = fill;
+    o.cnt = cnt;
+    o.nbox = nbox;
+    for (int r = 0; r < 3; ++r) {
+        o.off[r] = off ? off + size_t(r) * size_t(nbox + 1) : nullptr;
+        o.ent[r] = ent ? ent[r] : nullptr;
+    }
+    hipLaunchKernelGGL(k_adaptive_lists, dim3(grid_for(nbox + 1)), dim3(kBlock), 0, st, box_key, box_parent,
+                       box_child, box_lev, role, nb9, nbox, o);
+}
+
+void launch_compact_positive(const int32_t* cnt, const int32_t* pos, int64_t nbox, int32_t* items, hipStream_t st) {
+    if (nbox <= 0) return;
+    hipLaunchKernelGGL(k_compact_positive, dim3(grid_for(nbox)), dim3(kBlock), 0, st, cnt, pos, nbox, items);
+}
+
+void launch_point_boxes(const int32_t* box_pt0, const int32_t* box_pt1, int32_t nleaf, int32_t* pt_box,
+                        hipStream_t st) {
+    if (nleaf <= 0) return;
+    hipLaunchKernelGGL(k_point_boxes, dim3(grid_for(nleaf)), dim3(kBlock), 0, st, box_pt0, box_pt1, nleaf, pt_box);
 }
 
 void launch_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, const int32_t* roots, int32_t nroots,

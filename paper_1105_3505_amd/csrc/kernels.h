@@ -73,6 +73,7 @@ struct DevOps {
     float* ifo_lo = nullptr;
     double* mono = nullptr;        // [nlev][49] c_d
     int32_t* rank = nullptr;       // [nlev] skeleton size of each height
+    int32_t* skel = nullptr;       // [nlev][kRankPad][2] skeleton points, offsets from the box corner
 };
 
 // Device copy of the operator pointers of every operator set a plan uses.
@@ -85,6 +86,7 @@ struct OpsPtrs {
     const float* ifo_lo;
     const double* mono;
     const int32_t* rank;
+    const int32_t* skel;
     int64_t side;
     int32_t nlev, pad;
 };
@@ -119,6 +121,22 @@ struct ExecPtrs {
 };
 
 enum BoxMatMode { kModeM2M = 1, kModeL2L = 2 };
+
+// Adaptive tree (Section 6: a box is refined while it holds more than N_leaf points), kept on
+// top of the uniform-depth tree: every box of the uniform tree takes a role.  Boxes below an
+// adaptive leaf only relay expansions (their outgoing ones up to the leaf, its incoming one
+// down to the finest level, where P2M and L2P run): composing T_ofo with T_ofs, and T_ofs^T
+// with T_ofo^T, is the leaf's own operator at its height.
+enum BoxRole : int8_t { kRolePruned = 0, kRoleInner = 1, kRoleLeaf = 2 };
+// Lists of the adaptive tree (Carrier, Greengard and Rokhlin): for a leaf tau, U = the leaves
+// touching it (tau included), W = the boxes whose parents touch tau but which do not touch it,
+// inside the colleagues of tau; for any box, X = the leaves coarser than it that touch its
+// parent but not it (the dual of W).  V is the interaction list of Definition 6.1 with pruned
+// boxes taken out.  CSR rows of the three lists, indexed by box.
+struct AdaptiveLists {
+    const int32_t* off[3];     // [nbox + 1] each: U, W, X
+    const int32_t* ent[3];
+};
 
 // ---- construction (forest_kernels.hip) ---------------------------------------------------
 size_t radix_scratch_bytes(int64_t n);
@@ -196,10 +214,32 @@ void launch_lists(const uint64_t* box_key, const int32_t* box_parent, const int3
                   const int32_t* box_inst, const int8_t* box_lev, const InstInfo* inst, int64_t nbox, int32_t* nb9,
                   int32_t* il27, hipStream_t st);
 // class lists (boxes of each group sorted by child position) and the tiles over them;
-// nslots = tile slots of all groups
-void launch_class_lists(const BoxGroup* groups, int32_t ngroups, int32_t nslots, const int32_t* cscan,
-                        const int32_t* ctotal, const uint64_t* box_key, int64_t nbox,
-                        int32_t* cls_box, BoxTile* tiles, hipStream_t st);
+// the groups own tile slots [slot0, slot0 + nslots); with role non-null, boxes of role
+// kRolePruned below level 3 are left out (cscan / ctotal must count the same boxes)
+void launch_class_lists(const BoxGroup* groups, int32_t ngroups, int32_t slot0, int32_t nslots,
+                        const int32_t* cscan, const int32_t* ctotal, const uint64_t* box_key,
+                        const int8_t* box_lev, const int8_t* role, int64_t nbox, int32_t* cls_box,
+                        BoxTile* tiles, hipStream_t st);
+// scan_child_classes restricted to the boxes that launch_class_lists keeps for role
+void scan_child_classes_active(const uint64_t* box_key, const int8_t* box_lev, const int8_t* role, int64_t nbox,
+                               int32_t* out, int32_t* totals, void* scratch, hipStream_t st);
+// roles of the boxes of the adaptive tree (N_leaf and leaf level from each box's instance)
+void launch_roles(const int32_t* box_pt0, const int32_t* box_pt1, const int32_t* box_parent, const int8_t* box_lev,
+                  const int32_t* box_inst, const InstInfo* inst, int64_t nbox, int8_t* role, hipStream_t st);
+// interaction-list slots naming a pruned box, or of a pruned box, set to -1 (V lists)
+void launch_filter_interactions(const int8_t* role, int64_t nbox, int32_t* il27, hipStream_t st);
+// U, W and X lists: fill = false counts them into cnt[3][nbox + 1] (the last of each row
+// zero); fill = true writes entries at the row starts off[3][nbox + 1] into ent[3]
+void launch_adaptive_lists(bool fill, const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_child,
+                           const int8_t* box_lev, const int8_t* role, const int32_t* nb9, int64_t nbox,
+                           int32_t* cnt, const int32_t* off, int32_t* const* ent, hipStream_t st);
+// items[pos[g]] = g for the boxes with cnt[g] > 0 (pos = exclusive scan of those flags)
+void launch_compact_positive(const int32_t* cnt, const int32_t* pos, int64_t nbox, int32_t* items, hipStream_t st);
+void scan_positive(const int32_t* cnt, int64_t n, int rows, int32_t* out, int32_t* totals, void* scratch,
+                   hipStream_t st);
+// finest (height-0) box of every point: the box g of [0, nleaf) with box_pt0[g] <= i < box_pt1[g]
+void launch_point_boxes(const int32_t* box_pt0, const int32_t* box_pt1, int32_t nleaf, int32_t* pt_box,
+                        hipStream_t st);
 // near-field groups [q0, q0 + h1_count + nroots): the children of the height-1 boxes
 // h1_start .. h1_start + h1_count - 1, then the root leaves roots[0 .. nroots)
 void launch_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, const int32_t* roots, int32_t nroots,
@@ -218,9 +258,10 @@ void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int3
 // M2M over the consecutive-box tiles of one height (Q row zrow is all zeros)
 void launch_m2m(const BoxTile* tiles, int32_t ntiles, const int32_t* box_child, const OpsPtrs* ops, double* Q,
                 int32_t zrow, hipStream_t st);
-// L2L over the class-sorted tiles of one height (U row zrow is all zeros)
+// L2L over the class-sorted tiles of one height (U row zrow is all zeros); boxes of role
+// kRolePruned (role non-null) take the parent's expansion alone (no M2L wrote theirs)
 void launch_l2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, const int32_t* box_parent,
-                const OpsPtrs* ops, double* U, int32_t zrow, hipStream_t st);
+                const OpsPtrs* ops, double* U, int32_t zrow, const int8_t* role, hipStream_t st);
 // M2L over the class-sorted tiles; Q row zrow is all zeros (read for absent sources)
 void launch_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, const int32_t* il27,
                 const OpsPtrs* ops, const double* Q, int32_t zrow, double* U, hipStream_t st);
@@ -236,6 +277,20 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
                  const int32_t* pts, const uint32_t* pkey, const double* fs, const int32_t* perm_local,
                  const ExecPtrs* tab, double* u_single, int32_t tgt0_single, const double* U, const double* leafT,
                  const uint8_t* far_inst, const double* phi_oct, const PhiFar* phi_far, hipStream_t st);
+// Adaptive tree passes.  P2L (X lists): u-hat of box tau += phi(skeleton of tau - x_j) f_j over
+// the points of its X leaves, for the nx boxes xitems.  Near field of the adaptive leaves
+// (items): U-list sources, W-list skeletons with their q-hat (M2P), L2P at each point's finest
+// box, un-permutation.
+void launch_p2l(int32_t nx, const int32_t* xitems, const AdaptiveLists& lists, const int32_t* box_pt0,
+                const int32_t* box_pt1, const uint64_t* box_key, const int8_t* box_lev, const int32_t* box_inst,
+                const InstInfo* inst, const OpsPtrs* ops, const int32_t* pts, const double* fs, double* U,
+                const double* phi_oct, const PhiFar* phi_far, hipStream_t st);
+void launch_near_adaptive(int32_t nitems, const int32_t* items, const AdaptiveLists& lists, const int32_t* box_pt0,
+                          const int32_t* box_pt1, const uint64_t* box_key, const int8_t* box_lev,
+                          const int32_t* box_inst, const InstInfo* inst, const OpsPtrs* ops, const int32_t* pts,
+                          const double* fs, const double* Q, const int32_t* pt_box, const double* U,
+                          const int32_t* perm_local, const ExecPtrs* tab, double* u_single, int32_t tgt0_single,
+                          const uint8_t* far_inst, const double* phi_oct, const PhiFar* phi_far, hipStream_t st);
 // Radius of the device phi table: the host's quadrature table (radius 128) followed by eq. 3.1
 // for the octant entries up to this radius, filled by launch_phi_extend(oct, 128, radius).
 constexpr int kPhiDeviceRadius = 256;

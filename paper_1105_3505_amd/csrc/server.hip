@@ -266,6 +266,9 @@ extern "C" {
 lfmm_status lfmm_server_create(lfmm_ctx* ctx, const lfmm_server_options* opt, lfmm_server** out) {
     if (!ctx || !out) return fail(LFMM_E_INVAL, "null argument");
     *out = nullptr;
+    // admission reserves a plan's footprint bound, which holds for uniform trees only
+    if (ctx_flags(ctx) & LFMM_FLAG_ADAPTIVE)
+        return fail(LFMM_E_UNSUPPORTED, "servers build uniform trees (context has LFMM_FLAG_ADAPTIVE)");
     lfmm_server_options o{};
     if (opt) o = *opt;
     if (o.max_batch < 0 || o.max_inflight < 0 || o.max_batch_points < 0)

@@ -8,6 +8,7 @@ from .generators import (  # noqa: F401
     zero_sum_loads,
     uniform_box,
     gaussian_clusters,
+    clusters_on_background,
     config_small_uniform,
     config_large_uniform,
     config_clusters,

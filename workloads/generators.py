@@ -102,6 +102,32 @@ def gaussian_clusters(rng: np.random.Generator, n: int, centres: np.ndarray, sig
 # a 2^20 region, a batch of 512 uneven instances and a stream of serving requests.
 # ----------------------------------------------------------------------------------------
 
+def clusters_on_background(rng: np.random.Generator, n: int, extent: int, n_clusters: int = 3,
+                           sigma: float = 0.0, background: float = 0.3) -> np.ndarray:
+    """``n`` distinct lattice points in [0, extent)^2: a fraction ``background`` uniform over the
+    whole square, the rest in Gaussian clusters (sigma default extent / 400) centred in its
+    middle 60 %.  Densities differ by orders of magnitude, so an adaptive tree puts its leaves
+    on many levels."""
+    extent = int(extent)
+    sigma = float(sigma) if sigma > 0 else extent / 400.0
+    nb = int(round(background * n))
+    centres = rng.uniform(0.2 * extent, 0.8 * extent, size=(n_clusters, 2))
+    core = gaussian_clusters(rng, n - nb, centres, sigma, extent)
+    taken = set((core[:, 0].astype(np.int64) * extent + core[:, 1]).tolist())
+    bg = []
+    while len(bg) < nb:
+        c = rng.integers(0, extent, size=(2 * (nb - len(bg)) + 8, 2))
+        for x, y in c.tolist():
+            k = x * extent + y
+            if k not in taken:
+                taken.add(k)
+                bg.append((x, y))
+                if len(bg) == nb:
+                    break
+    xy = np.concatenate([core, np.array(bg, dtype=np.int32).reshape(-1, 2)]).astype(np.int32)
+    return xy[rng.permutation(len(xy))]
+
+
 def config_small_uniform(seed: int = 1, n: int = 1000, side: int = 256):
     """1,000 distinct sources uniform in a 256 x 256 box, N(0,1) loads, zero sum."""
     rng = np.random.default_rng(seed)

@@ -17,6 +17,7 @@ Workloads (all seeded, synthetic):
   large_uniform (default)  1,000,000 distinct sources uniform in a 4096 x 4096 box, FP64
   small_uniform            1,000 sources uniform in a 256 x 256 box
   clusters                 2,000,000 sources in 64 Gaussian clusters in a 2^20 x 2^20 region
+                           (adaptive tree by default, --tree uniform for the uniform-depth one)
   batched                  512 independent instances (log-uniform sizes 1e3..1e5) per step
   serving                  Poisson stream of requests (sizes log-uniform 1e2..1e6) through
                            the continuous-batching server; reports p50/p99 latency
@@ -93,11 +94,24 @@ def roofline(dom: str, dom_ms: float, info: dict, n: int, precision: str, worklo
         return {"kernel": kernel, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": measured_traffic(workload, kernel), "work_per_launch": flops,
                 "work_definition": "2 P^2 flops per interaction-list pair, P = 48"}
+    if dom == "leaf" and info.get("adaptive"):
+        pairs = info["near_pairs"] + info["m2p_terms"]
+        flops = 2.0 * pairs + 2.0 * RANK * n
+        achieved = flops / sec / 1e12
+        kernel = "k_near_adaptive<48>"
+        return {"kernel": kernel, "bound": "alu", "achieved": achieved,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": measured_traffic(workload, kernel), "work_per_launch": flops,
+                "work_definition": "one FP64 FMA per U-list pair and per W-list skeleton term, plus 2P "
+                                   "flops of L2P per target",
+                "pairs_per_s": pairs / sec}
     if dom == "leaf":
         flops = 2.0 * info["near_pairs"] + 2.0 * RANK * n
         achieved = flops / sec / 1e12
         side = info["leaf_side"]
         kernel = "k_near<48, %d>" % (0 if side <= 16 else (1 if side <= 32 else 2))
+        if side >= 64:
+            kernel = "k_near_staged<48>"
         return {"kernel": kernel, "bound": "alu", "achieved": achieved,
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                 "traffic": measured_traffic(workload, kernel), "work_per_launch": flops,
@@ -212,7 +226,8 @@ def run_single(args, torch, lf):
     dev = torch.device("cuda:0")
     xy_d = torch.from_numpy(xy).to(dev)
     f_d = torch.from_numpy(f).to(dev)
-    ctx = lf.Context(0, precision=args.precision, max_leaf=args.max_leaf, stencil=args.stencil)
+    ctx = lf.Context(0, precision=args.precision, max_leaf=args.max_leaf, stencil=args.stencil,
+                     adaptive=args.tree == "adaptive")
     streams = streams_for(args.inflight, torch)
     outs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in streams]
 
@@ -255,8 +270,8 @@ def run_single(args, torch, lf):
     ctx.close()
 
     config = {"workload": WORKLOADS[args.workload], "n_sources": n, "precision": args.precision,
-              "leaf_level": info["leaf_level"], "leaf_side": info["leaf_side"], "max_leaf": args.max_leaf,
-              "rank": RANK, "eps": 1e-12,
+              "tree": args.tree, "leaf_level": info["leaf_level"], "leaf_side": info["leaf_side"],
+              "max_leaf": args.max_leaf, "rank": RANK, "eps": 1e-12,
               "operator": "9-point isotropic" if args.stencil == 9 else "5-point"}
     result = base_result(args, value, ms_per_step, config)
     result.update(timing_fields(m, n, args.inflight))
@@ -609,7 +624,11 @@ def main() -> None:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large_uniform", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=sorted(TOLERANCE))
-    ap.add_argument("--max-leaf", type=int, default=64)
+    ap.add_argument("--max-leaf", type=int, default=None,
+                    help="N_leaf (default 64; 32 on the adaptive tree)")
+    ap.add_argument("--tree", choices=("uniform", "adaptive"), default=None,
+                    help="tree of Section 6: uniform depth, or adaptive (refined while a box holds more than "
+                         "N_leaf points); default adaptive for clusters, uniform otherwise")
     ap.add_argument("--stencil", type=int, default=5, choices=(5, 9),
                     help="lattice operator: the 5-point Laplacian of the paper or the isotropic 9-point one")
     ap.add_argument("--inflight", type=int, default=3,
@@ -623,6 +642,10 @@ def main() -> None:
                     help="first fill and copy a buffer of this many MiB (a known-traffic reference for "
                          "hardware byte counters)")
     args = ap.parse_args()
+    if args.tree is None:
+        args.tree = "adaptive" if args.workload == "clusters" else "uniform"
+    if args.max_leaf is None:
+        args.max_leaf = 32 if args.tree == "adaptive" else 64
     if args.inflight < 1:
         ap.error("--inflight must be at least 1")
     if args.gpus != 1:

@@ -381,6 +381,7 @@ struct lfmm_plan {
     int32_t* ad_xboxes = nullptr;           // boxes with a non-empty X list (P2L items)
     int32_t n_ad_leaves = 0, n_ad_xboxes = 0;
     int32_t* pt_box = nullptr;              // finest box of every point
+    BoxTile* m2l_tiles = nullptr;           // the non-empty M2L tiles, compacted
     ExecPtrs* h_exec = nullptr;             // pinned staging of the per-execute pointers
     size_t h_exec_cls = 0;
     hipEvent_t exec_copied = nullptr;       // the last staging copy has been read
@@ -1096,6 +1097,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
         mb.reserve(size_t(nb));                          // roles
         mb.reserve(size_t(3) * size_t(nb + 1) * 4);      // list row starts
         mb.reserve(size_t(n) * 4);                       // finest box of each point
+        mb.reserve(size_t(std::max(pl->m2l.n, 1)) * sizeof(BoxTile));   // compacted M2L tiles
     }
     mb.allocate();
     pl->box_key = mb.take<uint64_t>(nb);
@@ -1123,6 +1125,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
         pl->role = mb.take<int8_t>(nb);
         pl->list_off = mb.take<int32_t>(size_t(3) * size_t(nb + 1));
         pl->pt_box = mb.take<int32_t>(n);
+        pl->m2l_tiles = mb.take<BoxTile>(size_t(std::max(pl->m2l.n, 1)));
     }
 
     // ---- tables ---------------------------------------------------------------------------------
@@ -1213,14 +1216,17 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
         scan_child_classes_active(pl->box_key, pl->box_lev, pl->role, nb, cscan_v, ctotal_v, cscr, st);
         launch_class_lists(d_groups, n_m2l_groups, 0, m2l_slots, cscan_v, ctotal_v, pl->box_key, pl->box_lev,
                            pl->role, nb, pl->cls_box, pl->tiles, st);
+        // most slots stay empty (pruned boxes): M2L walks the non-empty tiles only, so that its
+        // XCD-contiguous split of the tile list stays balanced
+        compact_tiles(pl->tiles, m2l_slots, pl->m2l_tiles, pl->d_m2l_ntiles, cscr, st);
         scan_child_classes(pl->box_key, nb, cscan, ctotal, cscr, st);
         launch_class_lists(d_groups + n_m2l_groups, int32_t(groups.size()) - n_m2l_groups, m2l_slots,
                            tile_slots - m2l_slots, cscan, ctotal, pl->box_key, pl->box_lev, nullptr, nb,
                            pl->cls_box, pl->tiles, st);
         // U, W, X lists: lengths, row starts, item positions, one read-back of the totals
         const int64_t nb1 = nb + 1;
-        launch_adaptive_lists(false, pl->box_key, pl->box_parent, pl->box_child, pl->box_lev, pl->role, pl->nb9, nb,
-                              lcnt, nullptr, nullptr, st);
+        launch_adaptive_lists(false, pl->box_key, pl->box_parent, pl->box_child, pl->box_lev, pl->role, pl->nb9,
+                              pl->box_pt0, pl->box_pt1, nb, lcnt, nullptr, nullptr, st);
         scan_rows(lcnt, pl->list_off, nb1, 3, ltot, lscr2, st);
         scan_positive(lcnt, nb1, 3, lpos, ltot + 4, lscr2, st);
         launch_point_boxes(pl->box_pt0, pl->box_pt1, pl->nleaf, pl->pt_box, st);
@@ -1241,8 +1247,8 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
         for (int r = 0; r < 3; ++r) pl->list_ent[r] = ma.take<int32_t>(size_t(std::max(tot[r], 1)));
         pl->ad_leaves = ma.take<int32_t>(size_t(std::max(tot[4], 1)));
         pl->ad_xboxes = ma.take<int32_t>(size_t(std::max(tot[6], 1)));
-        launch_adaptive_lists(true, pl->box_key, pl->box_parent, pl->box_child, pl->box_lev, pl->role, pl->nb9, nb,
-                              nullptr, pl->list_off, pl->list_ent, st);
+        launch_adaptive_lists(true, pl->box_key, pl->box_parent, pl->box_child, pl->box_lev, pl->role, pl->nb9,
+                              pl->box_pt0, pl->box_pt1, nb, nullptr, pl->list_off, pl->list_ent, st);
         launch_compact_positive(lcnt, lpos, nb, pl->ad_leaves, st);
         launch_compact_positive(lcnt + 2 * nb1, lpos + 2 * nb1, nb, pl->ad_xboxes, st);
     }
@@ -1290,26 +1296,28 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
     }
     mark(3);
     if (pl->m2l.n > 0) {
+        const BoxTile* mt = pl->m2l_tiles ? pl->m2l_tiles : pl->tiles + pl->m2l.t0;
         if (mixed) {
             launch_split_q(pl->Q, pl->nbox + 1, pl->Qh, pl->Ql, pl->qsum, st);
-            launch_m2l_mixed(pl->tiles + pl->m2l.t0, pl->d_m2l_ntiles, pl->m2l.n, pl->cls_box, pl->il27, pl->d_ops,
-                             pl->Qh, pl->Ql, pl->qsum, pl->nbox, pl->U, st);
+            launch_m2l_mixed(mt, pl->d_m2l_ntiles, pl->m2l.n, pl->cls_box, pl->il27, pl->d_ops, pl->Qh, pl->Ql,
+                             pl->qsum, pl->nbox, pl->U, st);
         }
         else
-            launch_m2l(pl->tiles + pl->m2l.t0, pl->m2l.n, pl->cls_box, pl->il27, pl->d_ops, pl->Q, pl->nbox, pl->U, st);
+            launch_m2l(mt, pl->d_m2l_ntiles, pl->m2l.n, pl->cls_box, pl->il27, pl->d_ops, pl->Q, pl->nbox, pl->U, st);
     }
+    mark(4);
     AdaptiveLists lists{};
     if (pl->adaptive) {
         for (int r = 0; r < 3; ++r) {
             lists.off[r] = pl->list_off + size_t(r) * size_t(pl->nbox + 1);
             lists.ent[r] = pl->list_ent[r];
         }
-        // P2L of the X lists, counted with the interaction phase
+        // P2L of the X lists (after M2L wrote the incoming expansions, before L2L reads
+        // them), timed with the downward pass
         launch_p2l(pl->n_ad_xboxes, pl->ad_xboxes, lists, pl->box_pt0, pl->box_pt1, pl->box_key, pl->box_lev,
                    pl->box_inst, pl->d_inst, pl->d_ops, pl->pts, pl->fs, pl->U, pl->ctx->phi_oct, pl->ctx->phi_far,
                    st);
     }
-    mark(4);
     for (int h = pl->Hmax; h >= 0; --h) {
         const TileRange& r = pl->l2l[size_t(h)];
         if (r.n > 0)

@@ -425,9 +425,10 @@ __device__ inline void boxmat_tiles(const BoxTile* tiles, int32_t ntiles, const 
 // (empty list slots, boxes past the tile) read the zero row.
 // 16x16x4 FP64 instruction: step kk of row block m takes column g * 12 + kk in lane group
 // g = lane / 16; element i of lane (g, n) is row 16 m + g + 4 i, column n.
-__global__ __launch_bounds__(kBlock, 3) void k_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list,
-                                                    const int32_t* il27, const OpsPtrs* ops, const double* Q,
-                                                    int32_t zrow, double* U) {
+__global__ __launch_bounds__(kBlock, 3) void k_m2l(const BoxTile* tiles, const int32_t* ntiles_dev,
+                                                    const int32_t* box_list, const int32_t* il27, const OpsPtrs* ops,
+                                                    const double* Q, int32_t zrow, double* U) {
+    const int32_t ntiles = uniform(*ntiles_dev);
     constexpr int P = kRankPad, KQ = P / 4, NJ = KQ / 2, NS = kNumInteractions;
     constexpr int A2 = P * P / 2;                      // double2_t per operator: 4.5 per thread
     static_assert(A2 == 4 * kBlock + kBlock / 2, "staging below assumes P = 48");
@@ -1095,7 +1096,7 @@ __global__ void k_load_stats_final(const double* part, double* out) {
     out[2] = bad;
 }
 
-// Leaf pass for leaf sides >= 64 (phi from the device octant table, radius 256: every offset
+// Leaf pass for leaf sides >= 64 (phi from the device octant table: every offset
 // of a near pair, at most 2 side - 1 = 255, is a table entry).  Such leaves are the sparse
 // ones of widely spread or clustered inputs: a group (the up to four leaves of one parent) holds
 // a few dozen targets and its 4 x 4 block of source leaves a few hundred sources.  A wave takes
@@ -1589,12 +1590,12 @@ void launch_l2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, c
                        box_parent, ops, U, zrow, role);
 }
 
-void launch_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, const int32_t* il27,
-                const OpsPtrs* ops, const double* Q, int32_t zrow, double* U, hipStream_t st) {
-    if (ntiles <= 0) return;
-    int64_t g = std::min<int64_t>(ntiles, 8192);
+void launch_m2l(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t max_tiles, const int32_t* box_list,
+                const int32_t* il27, const OpsPtrs* ops, const double* Q, int32_t zrow, double* U, hipStream_t st) {
+    if (max_tiles <= 0) return;
+    int64_t g = std::min<int64_t>(max_tiles, 8192);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
-    hipLaunchKernelGGL(k_m2l, dim3(static_cast<unsigned>(g)), dim3(kBlock), 0, st, tiles, ntiles, box_list, il27,
+    hipLaunchKernelGGL(k_m2l, dim3(static_cast<unsigned>(g)), dim3(kBlock), 0, st, tiles, ntiles_dev, box_list, il27,
                        ops, Q, zrow, U);
 }
 

@@ -596,6 +596,24 @@ struct ListOut {
 // siblings waiting, over at most kMaxLevels levels.
 constexpr int kListStack = 3 * kMaxLevels + 4;
 
+// X entries of box a (level >= 2): the leaves coarser than a that touch a's parent but not a,
+// among the neighbours of a's ancestors; out(list, entry) takes each.
+template <class Out>
+__device__ inline void x_entries(int32_t a, const uint64_t* box_key, const int32_t* box_parent, const int8_t* box_lev,
+                                 const int8_t* role, const int32_t* nb9, Out out) {
+    const BoxAt ab = box_at(box_key, box_lev, a);
+    const int32_t p = box_parent[a];
+    const BoxAt par = box_at(box_key, box_lev, p);
+    for (int32_t b = p; b >= 0 && box_lev[b] >= 1; b = box_parent[b])
+        for (int q = 0; q < 9; ++q) {
+            if (q == 4) continue;
+            const int32_t c = nb9[size_t(b) * 9 + q];
+            if (c < 0 || role[c] != kRoleLeaf) continue;
+            const BoxAt cb = box_at(box_key, box_lev, c);
+            if (touches(par, cb) && !touches(ab, cb)) out(c);
+        }
+}
+
 // U and W of every adaptive leaf and X of every box of the adaptive tree, one thread per box.
 //   U(tau): tau; the colleagues that are leaves; below the other colleagues (inner boxes), the
 //     descendants that touch tau and are leaves (a descent through those that touch tau);
@@ -604,9 +622,13 @@ constexpr int kListStack = 3 * kMaxLevels + 4;
 //   W(tau): in that descent, the children that do not touch tau.
 //   X(tau): the leaves coarser than tau that touch its parent but not tau, among the
 //     neighbours of its ancestors.
+// Expansions pay only for boxes with more points than skeleton points: a W box holding at most
+// kDirectMax points joins U instead (its points summed directly: fewer terms than its
+// skeleton), and a box holding at most kDirectMax points keeps no X list: the leaves below it
+// take its X entries into their U lists.  Every (target, source) pair stays counted once.
 __global__ void k_adaptive_lists(const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_child,
-                                 const int8_t* box_lev, const int8_t* role, const int32_t* nb9, int64_t nbox,
-                                 ListOut o) {
+                                 const int8_t* box_lev, const int8_t* role, const int32_t* nb9,
+                                 const int32_t* box_pt0, const int32_t* box_pt1, int64_t nbox, ListOut o) {
     const int64_t gg = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gg > nbox) return;
     const int32_t g = int32_t(gg);
@@ -637,8 +659,10 @@ __global__ void k_adaptive_lists(const uint64_t* box_key, const int32_t* box_par
                 for (int k = 3; k >= 0; --k) {   // pushed in reverse: children visited in order
                     const int32_t d = box_child[size_t(b) * 4 + k];
                     if (d < 0) continue;
-                    if (!touches(tau, box_at(box_key, box_lev, d))) o.put(1, g, nw, d);
-                    else if (role[d] == kRoleLeaf) o.put(0, g, nu, d);
+                    if (!touches(tau, box_at(box_key, box_lev, d))) {
+                        if (box_pt1[d] - box_pt0[d] <= kDirectMax) o.put(0, g, nu, d);
+                        else o.put(1, g, nw, d);
+                    } else if (role[d] == kRoleLeaf) o.put(0, g, nu, d);
                     else if (sp < kListStack) stack[sp++] = d;
                 }
             }
@@ -649,19 +673,12 @@ __global__ void k_adaptive_lists(const uint64_t* box_key, const int32_t* box_par
                 const int32_t c = nb9[size_t(a) * 9 + q];
                 if (c >= 0 && role[c] == kRoleLeaf && touches(tau, box_at(box_key, box_lev, c))) o.put(0, g, nu, c);
             }
+        // X entries of tau and of its ancestors small enough to keep none (counts grow upwards)
+        for (int32_t a = g; a >= 0 && box_lev[a] >= 2 && box_pt1[a] - box_pt0[a] <= kDirectMax; a = box_parent[a])
+            x_entries(a, box_key, box_parent, box_lev, role, nb9, [&](int32_t c) { o.put(0, g, nu, c); });
     }
-    if (tau.lev >= 2) {
-        const int32_t p = box_parent[g];
-        const BoxAt par = box_at(box_key, box_lev, p);
-        for (int32_t a = p; a >= 0 && box_lev[a] >= 1; a = box_parent[a])
-            for (int q = 0; q < 9; ++q) {
-                if (q == 4) continue;
-                const int32_t c = nb9[size_t(a) * 9 + q];
-                if (c < 0 || role[c] != kRoleLeaf) continue;
-                const BoxAt cb = box_at(box_key, box_lev, c);
-                if (touches(par, cb) && !touches(tau, cb)) o.put(2, g, nx, c);
-            }
-    }
+    if (tau.lev >= 2 && box_pt1[g] - box_pt0[g] > kDirectMax)
+        x_entries(g, box_key, box_parent, box_lev, role, nb9, [&](int32_t c) { o.put(2, g, nx, c); });
     if (!o.fill) {
         o.cnt[g] = nu;
         o.cnt[stride + g] = nw;
@@ -962,6 +979,17 @@ struct ChildClassM2L {   // the same over the boxes that take part in M2L
         return (int(box_key[g] & 3ull) == c && m2l_box(box_lev, role, g)) ? 1 : 0;
     }
 };
+struct TileNonEmpty {   // 1 where tile i holds boxes
+    const BoxTile* tiles;
+    __device__ int32_t operator()(int, int64_t i) const { return tiles[i].count > 0 ? 1 : 0; }
+};
+struct TileScatter {    // non-empty tile i to its rank among them
+    const BoxTile* in;
+    BoxTile* out;
+    __device__ void operator()(int, int64_t i, int32_t x, int32_t v) const {
+        if (v) out[x] = in[i];
+    }
+};
 struct RowsPositive {   // 1 where the value is positive, row stride n
     const int32_t* in;
     int64_t n;
@@ -1110,6 +1138,11 @@ void scan_child_classes_active(const uint64_t* box_key, const int8_t* box_lev, c
 void scan_positive(const int32_t* cnt, int64_t n, int rows, int32_t* out, int32_t* totals, void* scratch,
                    hipStream_t st) {
     scan_source(RowsPositive{cnt, n}, out, n, rows, totals, scratch, st);
+}
+
+void compact_tiles(const BoxTile* in, int32_t n, BoxTile* out, int32_t* count, void* scratch, hipStream_t st) {
+    if (n <= 0) return;
+    scan_sink(TileNonEmpty{in}, TileScatter{in, out}, n, 1, count, scratch, st);
 }
 
 // Tiles whose counts a scatter block sums itself (tile-major counts, no scan launches); above
@@ -1277,8 +1310,9 @@ void launch_filter_interactions(const int8_t* role, int64_t nbox, int32_t* il27,
 }
 
 void launch_adaptive_lists(bool fill, const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_child,
-                           const int8_t* box_lev, const int8_t* role, const int32_t* nb9, int64_t nbox,
-                           int32_t* cnt, const int32_t* off, int32_t* const* ent, hipStream_t st) {
+                           const int8_t* box_lev, const int8_t* role, const int32_t* nb9, const int32_t* box_pt0,
+                           const int32_t* box_pt1, int64_t nbox, int32_t* cnt, const int32_t* off,
+                           int32_t* const* ent, hipStream_t st) {
     if (nbox <= 0) return;
     ListOut o{};
     o.fill = fill;
@@ -1289,7 +1323,7 @@ void launch_adaptive_lists(bool fill, const uint64_t* box_key, const int32_t* bo
         o.ent[r] = ent ? ent[r] : nullptr;
     }
     hipLaunchKernelGGL(k_adaptive_lists, dim3(grid_for(nbox + 1)), dim3(kBlock), 0, st, box_key, box_parent,
-                       box_child, box_lev, role, nb9, nbox, o);
+                       box_child, box_lev, role, nb9, box_pt0, box_pt1, nbox, o);
 }
 
 void launch_compact_positive(const int32_t* cnt, const int32_t* pos, int64_t nbox, int32_t* items, hipStream_t st) {

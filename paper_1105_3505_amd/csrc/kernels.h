@@ -133,6 +133,10 @@ enum BoxRole : int8_t { kRolePruned = 0, kRoleInner = 1, kRoleLeaf = 2 };
 // inside the colleagues of tau; for any box, X = the leaves coarser than it that touch its
 // parent but not it (the dual of W).  V is the interaction list of Definition 6.1 with pruned
 // boxes taken out.  CSR rows of the three lists, indexed by box.
+// Boxes with at most this many points take no expansion route in the adaptive lists (their
+// points are fewer than the skeleton points an expansion would cost): W entries and X lists
+// of such boxes turn into direct (U) entries.
+constexpr int32_t kDirectMax = kRankPad;
 struct AdaptiveLists {
     const int32_t* off[3];     // [nbox + 1] each: U, W, X
     const int32_t* ent[3];
@@ -231,8 +235,11 @@ void launch_filter_interactions(const int8_t* role, int64_t nbox, int32_t* il27,
 // U, W and X lists: fill = false counts them into cnt[3][nbox + 1] (the last of each row
 // zero); fill = true writes entries at the row starts off[3][nbox + 1] into ent[3]
 void launch_adaptive_lists(bool fill, const uint64_t* box_key, const int32_t* box_parent, const int32_t* box_child,
-                           const int8_t* box_lev, const int8_t* role, const int32_t* nb9, int64_t nbox,
-                           int32_t* cnt, const int32_t* off, int32_t* const* ent, hipStream_t st);
+                           const int8_t* box_lev, const int8_t* role, const int32_t* nb9, const int32_t* box_pt0,
+                           const int32_t* box_pt1, int64_t nbox, int32_t* cnt, const int32_t* off,
+                           int32_t* const* ent, hipStream_t st);
+// the non-empty tiles of in[0, n) to the front of out, in order; their number to *count (device)
+void compact_tiles(const BoxTile* in, int32_t n, BoxTile* out, int32_t* count, void* scratch, hipStream_t st);
 // items[pos[g]] = g for the boxes with cnt[g] > 0 (pos = exclusive scan of those flags)
 void launch_compact_positive(const int32_t* cnt, const int32_t* pos, int64_t nbox, int32_t* items, hipStream_t st);
 void scan_positive(const int32_t* cnt, int64_t n, int rows, int32_t* out, int32_t* totals, void* scratch,
@@ -262,9 +269,10 @@ void launch_m2m(const BoxTile* tiles, int32_t ntiles, const int32_t* box_child, 
 // kRolePruned (role non-null) take the parent's expansion alone (no M2L wrote theirs)
 void launch_l2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, const int32_t* box_parent,
                 const OpsPtrs* ops, double* U, int32_t zrow, const int8_t* role, hipStream_t st);
-// M2L over the class-sorted tiles; Q row zrow is all zeros (read for absent sources)
-void launch_m2l(const BoxTile* tiles, int32_t ntiles, const int32_t* box_list, const int32_t* il27,
-                const OpsPtrs* ops, const double* Q, int32_t zrow, double* U, hipStream_t st);
+// M2L over the class-sorted tiles, *ntiles_dev of them (max_tiles at most); Q row zrow is all
+// zeros (read for absent sources)
+void launch_m2l(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t max_tiles, const int32_t* box_list,
+                const int32_t* il27, const OpsPtrs* ops, const double* Q, int32_t zrow, double* U, hipStream_t st);
 // mixed-precision operands of Q rows [0, nrows): FP32 hi and lo parts and FP64 charge sums
 void launch_split_q(const double* Q, int32_t nrows, float* Qh, float* Ql, double* qs, hipStream_t st);
 void launch_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t max_tiles,
@@ -291,9 +299,11 @@ void launch_near_adaptive(int32_t nitems, const int32_t* items, const AdaptiveLi
                           const double* fs, const double* Q, const int32_t* pt_box, const double* U,
                           const int32_t* perm_local, const ExecPtrs* tab, double* u_single, int32_t tgt0_single,
                           const uint8_t* far_inst, const double* phi_oct, const PhiFar* phi_far, hipStream_t st);
-// Radius of the device phi table: the host's quadrature table (radius 128) followed by eq. 3.1
-// for the octant entries up to this radius, filled by launch_phi_extend(oct, 128, radius).
-constexpr int kPhiDeviceRadius = 256;
+// Radius of the device phi table: the host's quadrature table (radius 128) followed by the
+// far-field expansion for the octant entries up to this radius, filled by
+// launch_phi_extend(oct, 128, radius).  4.2 MB: near-field offsets between the wide leaves of
+// adaptive trees stay table lookups (a gather) instead of logarithms.
+constexpr int kPhiDeviceRadius = 1024;
 constexpr size_t kPhiDeviceEntries = size_t(kPhiDeviceRadius + 1) * (kPhiDeviceRadius + 2) / 2;
 void launch_phi_extend(double* oct, int r0, int r1, const PhiFar* far, hipStream_t st);
 // Sum, sum of magnitudes and count of non-finite entries of f[0, n) into out3 (device);

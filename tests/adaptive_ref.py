@@ -9,6 +9,11 @@ through the lists of Carrier, Greengard and Rokhlin (1988):
 * W(tau), tau a leaf: boxes finer than tau that do not touch it but whose parents do;
 * X(tau): leaves coarser than tau that touch tau's parent but not tau.
 
+With ``direct_max`` (the library uses its skeleton size, 48), a box holding at most that many
+points takes no expansion route: a W box that small joins U (its points summed directly,
+fewer terms than its skeleton), and a box that small keeps no X list, the leaves below it
+taking its X entries into their U lists.
+
 Boxes are given as arrays over the non-empty boxes of a uniform-depth quadtree (level,
 integer coordinates at that level, parent index, point count), the layout the library
 exports.  ``coverage`` checks the property the lists exist for: every (target leaf, source
@@ -63,8 +68,9 @@ def _overlap(la, xa, ya, lb, xb, yb):
             (ya * sa < (yb + 1) * sb) & (yb * sb < (ya + 1) * sa))
 
 
-def lists(level, x, y, parent, inst, role):
-    """U, V, W, X of every box as sorted lists of box indices (empty where undefined)."""
+def lists(level, x, y, parent, inst, role, count=None, direct_max=None):
+    """U, V, W, X of every box as sorted lists of box indices (empty where undefined); with
+    direct_max, small W boxes and the X lists of small boxes move to U (see above)."""
     level = np.asarray(level, dtype=np.int64)
     x = np.asarray(x, dtype=np.int64)
     y = np.asarray(y, dtype=np.int64)
@@ -95,7 +101,25 @@ def lists(level, x, y, parent, inst, role):
             V[t] = sorted(np.nonzero(same & (level == lt) & ~touch_t & (np.arange(nb) != t) & pp_touch)[0].tolist())
             touch_p = _touch(lp, xp, yp, level, x, y) & ~_overlap(lp, xp, yp, level, x, y)
             X[t] = sorted(np.nonzero(same & (role == LEAF) & (level < lt) & touch_p & ~touch_t)[0].tolist())
-    return U, V, W, X
+    if direct_max is None:
+        return U, V, W, X
+    count = np.asarray(count)
+    small = count <= direct_max
+    X2 = [x if not small[t] else [] for t, x in enumerate(X)]
+    U2, W2 = [], []
+    for t in range(nb):
+        if role[t] != LEAF:
+            U2.append([])
+            W2.append([])
+            continue
+        extra = [d for d in W[t] if small[d]]
+        a = t
+        while a >= 0 and level[a] >= 2 and small[a]:
+            extra += X[a]
+            a = parent[a]
+        U2.append(sorted(U[t] + extra))
+        W2.append([d for d in W[t] if not small[d]])
+    return U2, V, W2, X2
 
 
 def coverage(parent, role, U, V, W, X, inst):

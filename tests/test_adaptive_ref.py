@@ -27,7 +27,7 @@ def _clustered(seed, n, D, ncl=4, sigma=6.0):
     return np.array(sorted(pts), dtype=np.int64)
 
 
-def _tree(xy, D, max_leaf):
+def _tree(xy, D, max_leaf, direct_max=None):
     L = 0
     while True:   # leaf level: the smallest at which no box holds more than max_leaf points
         _, c = np.unique(xy >> (D - L), axis=0, return_counts=True)
@@ -37,7 +37,7 @@ def _tree(xy, D, max_leaf):
     level, x, y, parent, count = ar.uniform_tree(xy, D, L)
     role = ar.roles(level, parent, count, max_leaf, L)
     inst = np.zeros(len(level), dtype=np.int64)
-    U, V, W, X = ar.lists(level, x, y, parent, inst, role)
+    U, V, W, X = ar.lists(level, x, y, parent, inst, role, count, direct_max)
     return dict(level=level, x=x, y=y, parent=parent, count=count, role=role, inst=inst, U=U, V=V, W=W, X=X, L=L)
 
 
@@ -51,6 +51,22 @@ def test_every_pair_counted_once(seed, n, D, max_leaf):
     assert cov and set(cov.values()) == {1}
     # the leaves partition the points
     assert t["count"][t["role"] == ar.LEAF].sum() == n
+
+
+@pytest.mark.parametrize("seed,n,D,max_leaf,direct_max", [(1, 400, 9, 4, 6), (2, 700, 10, 8, 12),
+                                                          (4, 900, 11, 4, 48)])
+def test_direct_rule_keeps_every_pair_counted_once(seed, n, D, max_leaf, direct_max):
+    t = _tree(_clustered(seed, n, D), D, max_leaf, direct_max)
+    base = _tree(_clustered(seed, n, D), D, max_leaf)
+    # the rule only moves work: fewer W and X entries, more U entries
+    assert sum(map(len, t["W"])) < sum(map(len, base["W"]))
+    assert sum(map(len, t["X"])) < sum(map(len, base["X"]))
+    assert sum(map(len, t["U"])) > sum(map(len, base["U"]))
+    small = t["count"] <= direct_max
+    assert all(not small[d] for w in t["W"] for d in w)
+    assert all(len(t["X"][b]) == 0 for b in np.nonzero(small)[0])
+    cov = ar.coverage(t["parent"], t["role"], t["U"], t["V"], t["W"], t["X"], t["inst"])
+    assert set(cov.values()) == {1}
 
 
 @pytest.mark.parametrize("drop", ["U", "V", "W", "X"])

@@ -550,49 +550,84 @@ def run_dirichlet(args, torch, lf):
 
 
 def run_serving(args, torch, lf):
+    """Serving protocol: a stream of args.requests requests (the first args.warm_requests of each
+    run are warm-up and left out of the latency statistics).  First a closed-loop run (every
+    request submitted at once) measures the sustainable rate mu (requests per second); then
+    Poisson arrivals at lambda = rho mu for each rho of --loads (value: the rho = 0.8 run), or at
+    the fixed --rate."""
     import workloads as wl
     m = args.requests
-    reqs = [wl.config_serving_request(5, i) for i in range(m)]
+    w = min(args.warm_requests, m - 1)
+    reqs = []
+    for i in range(m):
+        reqs.append(wl.config_serving_request(5, i))
+        if (i + 1) % 200 == 0:
+            print("serving: %d of %d requests generated" % (i + 1, m), file=sys.stderr, flush=True)
     n_total = sum(len(r[0]) for r in reqs)
+    n_counted = sum(len(r[0]) for r in reqs[w:])
     dev = [(torch.from_numpy(xy).cuda(), torch.from_numpy(f).cuda()) for xy, f, _ in reqs]
     us = [torch.empty_like(f) for _, f in dev]
-    rng = np.random.default_rng(6)
-    gaps = rng.exponential(1.0 / args.rate, size=m)
     ctx = lf.Context(0, precision=args.precision, max_leaf=args.max_leaf)
     srv = lf.Server(ctx, max_batch=args.max_batch, max_inflight=3)
 
-    def run_stream(timed):
+    def run_stream(gaps):
+        """Submits request i at time sum(gaps[:i + 1]) (all at once when gaps is None)."""
         tickets = [None] * m
         t_start = time.perf_counter()
 
         def client():
             t = t_start
             for i in range(m):
-                t += gaps[i]
-                d = t - time.perf_counter()
-                if d > 0 and timed:
-                    time.sleep(d)
+                if gaps is not None:
+                    t += gaps[i]
+                    d = t - time.perf_counter()
+                    if d > 0:
+                        time.sleep(d)
                 tickets[i] = srv.submit(dev[i][0], dev[i][1], us[i])
 
         th = threading.Thread(target=client)
         th.start()
         th.join()
         stats = [srv.wait(t)[1] for t in tickets]
-        return stats, time.perf_counter() - t_start
+        makespan = time.perf_counter() - t_start
+        lat = np.array([(s["t_done"] - s["t_submit"]) * 1e3 for s in stats[w:]])
+        t_first = min(s["t_submit"] for s in stats[w:])
+        t_last = max(s["t_done"] for s in stats[w:])
+        return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "msources_per_s": n_counted / (t_last - t_first) / 1e6,
+                "iterations": len({s["batch_id"] for s in stats}), "makespan_s": makespan}
 
-    run_stream(False)            # warm-up: operators of every leaf side, memory pool
-    stats, makespan = run_stream(True)
+    run_stream(None)                     # warm-up: operators of every leaf side, memory pool
+    closed = run_stream(None)
+    mu = m / closed["makespan_s"]
+    print("serving: closed loop %.1f requests/s" % mu, file=sys.stderr, flush=True)
+    runs = {}
+    rng = np.random.default_rng(6)
+    if args.rate > 0:
+        plan_rates = {"fixed": args.rate}
+    else:
+        plan_rates = {"%.2f" % float(r): float(r) * mu for r in args.loads.split(",")}
+    for key, lam in plan_rates.items():
+        gaps = rng.exponential(1.0 / lam, size=m)
+        r = run_stream(gaps)
+        print("serving: load %s done (p99 %.2f ms)" % (key, r["p99_ms"]), file=sys.stderr, flush=True)
+        r["rate_per_s"] = lam
+        r["offered_msources_per_s"] = n_total / float(np.sum(gaps)) / 1e6
+        runs[key] = r
     srv.close()
     ctx.close()
-    lat = np.array([(s["t_done"] - s["t_submit"]) * 1e3 for s in stats])
-    batches = len({s["batch_id"] for s in stats})
-    config = {"workload": WORKLOADS["serving"], "requests": m, "rate_per_s": args.rate,
+    main_key = "fixed" if args.rate > 0 else ("0.80" if "0.80" in runs else next(iter(runs)))
+    main = runs[main_key]
+    config = {"workload": WORKLOADS["serving"], "requests": m, "warm_requests": w,
               "n_sources_total": n_total, "precision": args.precision, "max_batch": args.max_batch,
-              "max_inflight": 3}
-    result = base_result(args, n_total / makespan / 1e6, makespan * 1e3 / m, config)
-    result.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                   "mean_batch": m / batches, "iterations": batches, "makespan_s": makespan,
-                   "offered_msources_per_s": n_total / float(np.sum(gaps)) / 1e6})
+              "max_inflight": 3, "protocol": ("Poisson arrivals at %s" % ("a fixed rate" if args.rate > 0 else
+                                                                         "lambda = rho mu, mu closed-loop")),
+              "rho": None if args.rate > 0 else float(main_key)}
+    result = base_result(args, main["msources_per_s"], main["makespan_s"] * 1e3 / m, config)
+    result.update({"p50_ms": main["p50_ms"], "p99_ms": main["p99_ms"],
+                   "closed_loop": {"requests_per_s": mu, "msources_per_s": closed["msources_per_s"],
+                                   "p50_ms": closed["p50_ms"], "p99_ms": closed["p99_ms"]},
+                   "loads": runs})
     if not args.no_cpu_baseline:
         from oracle import direct as od
         num = den = 0.0
@@ -635,8 +670,12 @@ def main() -> None:
                     help="independent solves in flight in the timed region, one stream each")
     ap.add_argument("--cpu-targets", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--requests", type=int, default=200, help="serving: requests in the stream")
-    ap.add_argument("--rate", type=float, default=1000.0, help="serving: arrivals per second")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: requests in the stream")
+    ap.add_argument("--warm-requests", type=int, default=200,
+                    help="serving: first requests of each run left out of the latency statistics")
+    ap.add_argument("--loads", default="0.5,0.8,0.95",
+                    help="serving: arrival rates as fractions of the closed-loop rate (0.8 gives value)")
+    ap.add_argument("--rate", type=float, default=0.0, help="serving: fixed arrivals per second instead")
     ap.add_argument("--max-batch", type=int, default=64, help="serving: requests per iteration")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first fill and copy a buffer of this many MiB (a known-traffic reference for "

@@ -188,3 +188,19 @@ def test_leaf_outgoing_expansion_9_point():
     ref = od.direct_sum(tgt, src, q, stencil=9)
     app = od.direct_sum(tgt, ops.skeleton(0), qhat, stencil=9)
     assert np.max(np.abs(app - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_skeleton_ranks_follow_table1():
+    """Table 1 (tests/golden/table1_ranks.txt): skeleton sizes for eps = 1e-6 .. 1e-13 of the
+    continuum kernel are 19-21, 27-29, 36-37, 49-51 whatever the box size.  The lattice
+    operators of boxes of side 32 to 256 need the same numbers within a few points (their ID
+    also keeps the total charge, one more column, and its tolerance is relative to the first
+    pivot), and the rank does not grow with the box."""
+    import golden_fixtures as gf
+    table = gf.table1_ranks()
+    for eps, ref in table.items():
+        ops = lf.HostOperators(32, 4, eps=eps, max_rank=64)
+        ranks = [ops.level(h)[1] for h in range(4)]
+        ops.close()
+        assert min(ref) - 2 <= min(ranks) and max(ranks) <= max(ref) + 4, (eps, ranks, ref)
+        assert max(ranks) - min(ranks) <= 3

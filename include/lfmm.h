@@ -53,7 +53,9 @@ typedef enum lfmm_status {
                                  the potentials are computed all the same                 */
     LFMM_E_INVAL = -1,        /* null pointer, bad size, bad option value, NaN/Inf load  */
     LFMM_E_RANGE = -2,        /* coordinate extent >= 2^31, or a size the plan cannot hold */
-    LFMM_E_NOMEM = -3,        /* device or host allocation failed                        */
+    LFMM_E_NOMEM = -3,        /* device or host allocation failed (tests can force one:
+                                 LFMM_TEST_FAIL_ALLOC=k in the environment fails the k-th
+                                 device block requested after it is set)                   */
     LFMM_E_HIP = -4,          /* a HIP runtime call failed; the plan is unusable          */
     LFMM_E_UNSUPPORTED = -5,  /* valid request this build does not implement              */
     LFMM_E_NODEVICE = -6,     /* no GPU visible, or the device id does not exist          */

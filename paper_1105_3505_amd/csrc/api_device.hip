@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <limits>
@@ -101,6 +102,25 @@ struct Deferred {
 // does not call hipMalloc/hipFree (each costs far more than a small solve).  A block is
 // returned only after the work that used it is ordered before any later user: a release
 // follows a synchronisation, or names the fence after which the block is free.
+// Failure injection for tests of the out-of-memory paths: while LFMM_TEST_FAIL_ALLOC=k is set in
+// the environment, the k-th device block requested after it was set (or changed) fails as if
+// hipMalloc had, and the requests after it proceed.  Unset, one environment read per request.
+bool injected_alloc_failure() {
+    static std::mutex mu;
+    static std::string last;
+    static long count = 0;
+    const char* e = std::getenv("LFMM_TEST_FAIL_ALLOC");
+    const std::string v = e ? e : "";
+    std::lock_guard<std::mutex> lock(mu);
+    if (v != last) {
+        last = v;
+        count = 0;
+    }
+    if (v.empty()) return false;
+    const long k = std::atol(v.c_str());
+    return k > 0 && ++count == k;
+}
+
 class DevicePool {
   public:
     static size_t size_class(size_t bytes) {
@@ -110,6 +130,7 @@ class DevicePool {
     }
     void* acquire(size_t bytes, size_t* got) {
         size_t cls = size_class(bytes);
+        if (injected_alloc_failure()) throw NoMemory{"injected device allocation failure (LFMM_TEST_FAIL_ALLOC)"};
         {
             std::lock_guard<std::mutex> lock(mu_);
             if (!pending_.items.empty()) pending_.reap([&](size_t c, void* q) { give_back(c, q); }, false);

@@ -118,8 +118,10 @@ struct OperatorParams {
     int64_t dense_leaf_max = 32; // largest leaf side with a dense-model operator
 };
 
-// Builds leaf and level operators for leaves of side leaf_side and nlevels heights.
+// Builds leaf and level operators for leaves of side leaf_side and nlevels heights; with
+// LFMM_CACHE_DIR set in the environment, through the on-disk cache of opcache_host.cpp.
 OperatorSet build_operators(int64_t leaf_side, int nlevels, const OperatorParams& p);
+OperatorSet build_operators_uncached(int64_t leaf_side, int nlevels, const OperatorParams& p);
 
 // Proxy ring of a box of side s with lower-left corner at the origin: the lattice points
 // on the boundary of the concentric box of side 3s, all of them when there are at most

@@ -82,7 +82,7 @@ Mat columns(const Mat& A, const std::vector<int>& idx) {
 
 }  // namespace
 
-OperatorSet build_operators(int64_t leaf_side, int nlevels, const OperatorParams& p) {
+OperatorSet build_operators_uncached(int64_t leaf_side, int nlevels, const OperatorParams& p) {
     auto t0 = std::chrono::steady_clock::now();
     if (leaf_side < 1 || nlevels < 1) throw std::runtime_error("build_operators: bad sizes");
     OperatorSet ops;

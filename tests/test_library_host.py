@@ -204,3 +204,41 @@ def test_skeleton_ranks_follow_table1():
         ops.close()
         assert min(ref) - 2 <= min(ranks) and max(ranks) <= max(ref) + 4, (eps, ranks, ref)
         assert max(ranks) - min(ranks) <= 3
+
+
+def _opset_arrays(ops, n_levels):
+    out = [np.array([ops.level(h) for h in range(n_levels)])]
+    out += [ops.skeleton(h) for h in range(n_levels)]
+    out += [ops.ofo(h, c) for h in range(1, n_levels) for c in range(4)]
+    out.append(ops.leaf())
+    return out
+
+
+def test_operator_cache_round_trip(tmp_path, monkeypatch):
+    """LFMM_CACHE_DIR: the first build writes the operator set, later builds read it back bit for
+    bit; a damaged file is rebuilt (and rewritten), never trusted."""
+    monkeypatch.delenv("LFMM_CACHE_DIR", raising=False)
+    ref = lf.HostOperators(32, 3)
+    want = _opset_arrays(ref, 3)
+    ref.close()
+    monkeypatch.setenv("LFMM_CACHE_DIR", str(tmp_path))
+    stamps = []
+    for _ in range(2):   # build and store, then load (the file is not rewritten)
+        ops = lf.HostOperators(32, 3)
+        got = _opset_arrays(ops, 3)
+        ops.close()
+        assert all(np.array_equal(a, b) for a, b in zip(want, got))
+        files = sorted(tmp_path.glob("opset_*.bin"))
+        assert len(files) == 1
+        stamps.append(files[0].stat().st_mtime_ns)
+    assert stamps[0] == stamps[1]
+    size = files[0].stat().st_size
+    files[0].write_bytes(files[0].read_bytes()[:-100])
+    ops = lf.HostOperators(32, 3)
+    got = _opset_arrays(ops, 3)
+    ops.close()
+    assert all(np.array_equal(a, b) for a, b in zip(want, got))
+    assert files[0].stat().st_size == size
+    other = lf.HostOperators(32, 3, eps=1e-10)   # another key: another file
+    other.close()
+    assert len(list(tmp_path.glob("opset_*.bin"))) == 2

@@ -269,8 +269,8 @@ typedef enum lfmm_export_item {
     LFMM_EXPORT_LEVEL_COUNT = 13, /* int32 [L+1], instance 0: boxes of level l              */
     LFMM_EXPORT_BOX_LEVEL = 14, /* int8 [n_boxes]: level of the box in its instance's tree   */
     LFMM_EXPORT_BOX_INSTANCE = 15, /* int32 [n_boxes]: instance of the box                   */
-    LFMM_EXPORT_BOX_ROLE = 16,  /* int8 [n_boxes], adaptive plans: 0 below an adaptive leaf,
-                                   1 refined box of the adaptive tree, 2 its leaf           */
+    LFMM_EXPORT_BOX_ROLE = 16,  /* int8 [n_boxes]: 0 below an adaptive leaf, 1 refined box,
+                                   2 leaf (uniform plans: the level-L boxes are the leaves)  */
     LFMM_EXPORT_LIST_U = 17,    /* int32, adaptive plans: [n_boxes + 1] row starts, then the
                                    entries (box indices); row of a leaf: its U list          */
     LFMM_EXPORT_LIST_W = 18,    /* int32, adaptive plans: the same for the W lists           */

@@ -1830,6 +1830,7 @@ lfmm_status lfmm_plan_export(lfmm_plan* pl, int32_t item, void* out, size_t* byt
     size_t size = 0;
     const size_t nb = size_t(pl->nbox), n = size_t(pl->n), P = kRankPad;
     std::vector<int32_t> levels;
+    std::vector<int8_t> roles;
     bool host = false;
     switch (item) {
         case LFMM_EXPORT_POINTS: src = pl->pts; size = n * 8; break;
@@ -1860,12 +1861,20 @@ lfmm_status lfmm_plan_export(lfmm_plan* pl, int32_t item, void* out, size_t* byt
         case LFMM_EXPORT_LIST_U:
         case LFMM_EXPORT_LIST_W:
         case LFMM_EXPORT_LIST_X: {
-            if (!pl->adaptive) return fail(LFMM_E_INVAL, "adaptive-tree items of a plan without LFMM_FLAG_ADAPTIVE");
             if (item == LFMM_EXPORT_BOX_ROLE) {
-                src = pl->role;
                 size = nb;
+                if (pl->adaptive) {
+                    src = pl->role;
+                    break;
+                }
+                // uniform tree: the leaves (the height-0 block) and inner boxes
+                roles.assign(nb, int8_t(kRoleInner));
+                std::fill(roles.begin(), roles.begin() + pl->nleaf, int8_t(kRoleLeaf));
+                src = roles.data();
+                host = true;
                 break;
             }
+            if (!pl->adaptive) return fail(LFMM_E_INVAL, "list items of a plan without LFMM_FLAG_ADAPTIVE");
             const int r = item - LFMM_EXPORT_LIST_U;
             size = (nb + 1 + size_t(pl->list_len[r])) * 4;
             if (!out) break;

@@ -2,7 +2,7 @@
 
 python bench.py [--gpus 1] [--steps K] [--warmup W]
                 [--workload large_uniform|small_uniform|clusters|batched|serving]
-                [--precision fp64|mixed]
+                [--precision fp64|mixed|mixed-bf16]
 
 A step is one whole solve of the hot path on one batch of synthetic input already resident
 in HBM: tree construction (Morton keys, radix sort, levels, lists) plus the evaluation
@@ -43,6 +43,7 @@ METRIC = "Msources/s at rel.err ≤1e-10 (FP64) vs ≤1e-7 (mixed); p50/p99 solv
 # MI355X published peaks
 PEAK_FP64_TFLOPS = 78.6       # FP64 vector and FP64 matrix (MFMA) alike
 PEAK_FP32_TFLOPS = 157.3      # FP32 matrix (MFMA)
+PEAK_BF16_TFLOPS = 2500.0     # bf16 matrix (MFMA), dense
 PEAK_HBM_GBS = 8000.0
 RANK = 48                     # skeleton size the kernels are compiled for
 
@@ -63,7 +64,10 @@ WORKLOADS = {
     "dirichlet": ("Dirichlet problem on the 16384x16384 box: 65,532 boundary nodes, the dipole operator D "
                   "applied by the FMM, GMRES on D q = g"),
 }
-TOLERANCE = {"fp64": 1e-10, "mixed": 1e-7}
+TOLERANCE = {"fp64": 1e-10, "mixed": 1e-7, "mixed-bf16": 1e-7}
+# M2L kernel, its matrix-core peak, and the matrix-core flops it executes per algorithmic flop
+M2L_KERNEL = {"fp64": ("k_m2l", PEAK_FP64_TFLOPS, 1.0), "mixed": ("k_m2l_mixed", PEAK_FP32_TFLOPS, 3.0),
+              "mixed-bf16": ("k_m2l_bf16", PEAK_BF16_TFLOPS, 6.0)}
 
 
 def measured_traffic(workload: str, kernel: str):
@@ -89,11 +93,15 @@ def roofline(dom: str, dom_ms: float, info: dict, n: int, precision: str, worklo
     if dom == "m2l":
         flops = 2.0 * RANK * RANK * info["m2l_pairs"]
         achieved = flops / sec / 1e12
-        peak = PEAK_FP64_TFLOPS if precision == "fp64" else PEAK_FP32_TFLOPS
-        kernel = "k_m2l" if precision == "fp64" else "k_m2l_mixed"
-        return {"kernel": kernel, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": measured_traffic(workload, kernel), "work_per_launch": flops,
-                "work_definition": "2 P^2 flops per interaction-list pair, P = 48"}
+        kernel, peak, executed = M2L_KERNEL[precision]
+        out = {"kernel": kernel, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+               "frac": achieved / peak, "traffic": measured_traffic(workload, kernel), "work_per_launch": flops,
+               "work_definition": "2 P^2 flops per interaction-list pair, P = 48"}
+        if executed != 1.0:
+            # split products: the matrix cores execute `executed` flops per algorithmic flop
+            out["executed_frac"] = executed * achieved / peak
+            out["fp64_equivalent_frac"] = achieved / PEAK_FP64_TFLOPS
+        return out
     if dom == "leaf" and info.get("adaptive"):
         pairs = info["near_pairs"] + info["m2p_terms"]
         flops = 2.0 * pairs + 2.0 * RANK * n
@@ -121,7 +129,13 @@ def roofline(dom: str, dom_ms: float, info: dict, n: int, precision: str, worklo
             "frac": None, "traffic": None}
 
 
-def base_result(args, value, ms_per_step, config, dtype="f64"):
+# arithmetic of each path: FP64 throughout, or FP64 with the M2L products on split operands
+DTYPE = {"fp64": "f64", "mixed": "f64 (M2L: f32 hi/lo products)", "mixed-bf16": "f64 (M2L: 3-part bf16 products)"}
+
+
+def base_result(args, value, ms_per_step, config, dtype=None):
+    if dtype is None:
+        dtype = DTYPE.get(getattr(args, "precision", "fp64"), "f64")
     return {
         "metric": METRIC, "value": value, "unit": "Msources/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",

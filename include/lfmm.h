@@ -64,8 +64,14 @@ typedef enum lfmm_status {
 
 typedef enum lfmm_precision {
     LFMM_FP64 = 0,            /* every step in FP64                                        */
-    LFMM_MIXED = 1            /* M2L as FP32 matrix-core products with hi/lo splitting,
+    LFMM_MIXED = 1,           /* M2L as FP32 matrix-core products with hi/lo splitting,
                                  accumulated in FP64; everything else FP64                 */
+    LFMM_MIXED_BF16 = 2       /* M2L as bf16 matrix-core products: the operator (less its
+                                 constant part, applied in FP64) and q-hat each split into
+                                 three bf16 parts, the six products of parts whose orders
+                                 sum to at most 2, FP32 sums added to FP64 accumulators
+                                 once per interaction; everything else FP64.  Same error
+                                 target as LFMM_MIXED (relative 1e-7)                       */
 } lfmm_precision;
 
 typedef struct lfmm_options {

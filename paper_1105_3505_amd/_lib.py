@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liblfmm.so")
 _HEADER = os.path.join(os.path.dirname(_HERE), "include", "lfmm.h")
 
-PRECISIONS = {"fp64": 0, "mixed": 1}
+PRECISIONS = {"fp64": 0, "mixed": 1, "mixed-bf16": 2}
 STENCILS = {5: 0, 9: 1, "5": 0, "9": 1, "5-point": 0, "9-point": 1}
 
 _i32, _i64, _dbl, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p

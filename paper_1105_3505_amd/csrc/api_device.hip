@@ -392,6 +392,7 @@ struct lfmm_plan {
     double *Q = nullptr, *U = nullptr;
     float *Qh = nullptr, *Ql = nullptr;     // mixed precision: FP32 parts of Q (with its zero row)
     double* qsum = nullptr;                 // and the charge sum of each row
+    uint16_t* Qb = nullptr;                 // bf16 mixed precision: the three bf16 parts of Q
     // adaptive tree (LFMM_FLAG_ADAPTIVE)
     bool adaptive = false;
     int8_t* role = nullptr;                 // BoxRole of every box
@@ -524,6 +525,28 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st, bool l
                 }
         }
     }
+    // bf16 mixed precision: R^d = T^d - c_d 1 1^T (the FP64 remainder, not the FP32 parts)
+    // split into three bf16 parts R_p, each the round-to-nearest of what the earlier parts
+    // leave, laid out in the kernel's fragment order (group of 8 bf16 per lane and part)
+    std::vector<uint16_t> ifo_b(size_t(nlev) * kNumIfoSlots * kBf16OpVecs * 8, 0);
+    for (int h = 0; h < nlev; ++h) {
+        const int r = H.level[size_t(h)].rank;
+        for (int slot = 0; slot < kNumIfoSlots; ++slot) {
+            const size_t base = (size_t(h) * kNumIfoSlots + slot) * P * P;
+            const double mean = mono[size_t(h) * kNumIfoSlots + slot];
+            uint16_t* ob = ifo_b.data() + (size_t(h) * kNumIfoSlots + slot) * kBf16OpVecs * 8;
+            for (int row = 0; row < r; ++row)
+                for (int col = 0; col < r; ++col) {
+                    double rem = ifo[base + size_t(row) * P + col] - mean;
+                    const int m = row / 16, n = row % 16, sg = col / 8, e = col % 8;
+                    for (int part = 0; part < 3; ++part) {
+                        const uint16_t b = bf16_rne(rem);
+                        ob[(size_t((part * 3 + m) * 6 + sg) * 16 + n) * 8 + e] = b;
+                        rem -= bf16_value(b);   // exact: b is within 2^-8 of rem
+                    }
+                }
+        }
+    }
     // fragment order for the M2L kernels: lane l's operands of one matrix instruction sit
     // next to lane l+1's, so a wave reads 1 KB contiguous per load (P = 48: 3 row blocks,
     // lane group g = l / 16 covers columns 12 g .. 12 g + 11)
@@ -562,6 +585,7 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st, bool l
     }
     co->mem.reserve(ifo.size() * sizeof(float));
     co->mem.reserve(ifo.size() * sizeof(float));
+    co->mem.reserve(ifo_b.size() * sizeof(uint16_t));
     co->mem.reserve(mono.size() * sizeof(double));
     co->mem.reserve(ranks.size() * sizeof(int32_t));
     co->mem.reserve(skel.size() * sizeof(int32_t));
@@ -574,6 +598,7 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st, bool l
     co->dev.ifo = co->mem.take<double>(ifo.size());
     co->dev.ifo_hi = co->mem.take<float>(ifo.size());
     co->dev.ifo_lo = co->mem.take<float>(ifo.size());
+    co->dev.ifo_b = co->mem.take<uint16_t>(ifo_b.size());
     co->dev.mono = co->mem.take<double>(mono.size());
     co->dev.rank = co->mem.take<int32_t>(ranks.size());
     co->dev.skel = co->mem.take<int32_t>(skel.size());
@@ -583,6 +608,7 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st, bool l
     LFMM_HIP(hipMemcpyAsync(co->dev.ifo, ifo.data(), ifo.size() * 8, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipMemcpyAsync(co->dev.ifo_hi, ifo_hi.data(), ifo.size() * 4, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipMemcpyAsync(co->dev.ifo_lo, ifo_lo.data(), ifo.size() * 4, hipMemcpyHostToDevice, st));
+    LFMM_HIP(hipMemcpyAsync(co->dev.ifo_b, ifo_b.data(), ifo_b.size() * 2, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipMemcpyAsync(co->dev.mono, mono.data(), mono.size() * 8, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipMemcpyAsync(co->dev.rank, ranks.data(), ranks.size() * 4, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipMemcpyAsync(co->dev.skel, skel.data(), skel.size() * 4, hipMemcpyHostToDevice, st));
@@ -601,6 +627,7 @@ OpsPtrs ops_ptrs(const CachedOps* co) {
     p.ifo = co->dev.ifo;
     p.ifo_hi = co->dev.ifo_hi;
     p.ifo_lo = co->dev.ifo_lo;
+    p.ifo_b = co->dev.ifo_b;
     p.mono = co->dev.mono;
     p.rank = co->dev.rank;
     p.skel = co->dev.skel;
@@ -1107,9 +1134,18 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     mb.reserve(size_t(std::max(pl->nq, 1)) * kNearEntries * sizeof(int4));
     mb.reserve(size_t(nb + 1) * P * 8);                  // U and its zero row
     const bool mixed = ctx->opt.precision == LFMM_MIXED;
+    const bool mixed_bf16 = ctx->opt.precision == LFMM_MIXED_BF16;
     if (mixed) {
         mb.reserve(size_t(nb + 1) * P * 4);              // Q hi
         mb.reserve(size_t(nb + 1) * P * 4);              // Q lo
+        mb.reserve(size_t(nb + 1) * 8);                  // charge sums
+    }
+    if (mixed_bf16) {
+        // the bf16 M2L kernel addresses Q's parts by 32-bit byte offsets
+        if ((uint64_t(nb) + 1) * uint64_t(kBf16QVecs) * 16u > uint64_t(UINT32_MAX))
+            throw std::out_of_range("LFMM_MIXED_BF16 plans hold at most " +
+                                    std::to_string(uint64_t(UINT32_MAX) / (kBf16QVecs * 16u) - 1) + " boxes");
+        mb.reserve(size_t(nb + 1) * P * 6);              // Q in three bf16 parts
         mb.reserve(size_t(nb + 1) * 8);                  // charge sums
     }
     const bool adaptive = (ctx->opt.flags & LFMM_FLAG_ADAPTIVE) != 0;
@@ -1140,6 +1176,10 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     if (mixed) {
         pl->Qh = mb.take<float>(size_t(nb + 1) * P);
         pl->Ql = mb.take<float>(size_t(nb + 1) * P);
+        pl->qsum = mb.take<double>(size_t(nb + 1));
+    }
+    if (mixed_bf16) {
+        pl->Qb = mb.take<uint16_t>(size_t(nb + 1) * P * 3);
         pl->qsum = mb.take<double>(size_t(nb + 1));
     }
     if (adaptive) {
@@ -1299,6 +1339,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
 // pointers on the device, or null with f1/u1 those of the single instance.
 void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double* u1, uint32_t marks, hipStream_t st) {
     const bool mixed = pl->ctx->opt.precision == LFMM_MIXED;
+    const bool mixed_bf16 = pl->ctx->opt.precision == LFMM_MIXED_BF16;
     auto mark = [&](int k) {
         // event k opens phase k and closes phase k - 1
         if ((marks >> k & 1u) || (k > 0 && (marks >> (k - 1) & 1u))) LFMM_HIP(hipEventRecord(pl->ev[k], st));
@@ -1318,7 +1359,11 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
     mark(3);
     if (pl->m2l.n > 0) {
         const BoxTile* mt = pl->m2l_tiles ? pl->m2l_tiles : pl->tiles + pl->m2l.t0;
-        if (mixed) {
+        if (mixed_bf16) {
+            launch_split_q_bf16(pl->Q, pl->nbox + 1, pl->Qb, pl->qsum, st);
+            launch_m2l_bf16(mt, pl->d_m2l_ntiles, pl->m2l.n, pl->cls_box, pl->il27, pl->d_ops, pl->Qb, pl->qsum,
+                            pl->nbox, pl->U, st);
+        } else if (mixed) {
             launch_split_q(pl->Q, pl->nbox + 1, pl->Qh, pl->Ql, pl->qsum, st);
             launch_m2l_mixed(mt, pl->d_m2l_ntiles, pl->m2l.n, pl->cls_box, pl->il27, pl->d_ops, pl->Qh, pl->Ql,
                              pl->qsum, pl->nbox, pl->U, st);
@@ -1968,7 +2013,9 @@ lfmm_status lfmm_plan_footprint_bytes(const lfmm_ctx* ctx, int64_t n_src, int64_
     // class lists (M2L and L2L groups, four slots per box each), tiles, Q and U with their zero
     // rows, near-field groups and their 16 entries
     const size_t tiles = nb / 32 + 8 * size_t(D + 2);
-    const size_t mixed = ctx->opt.precision == LFMM_MIXED ? (nb + 1) * (P * 8 + 8) + 3 * al : 0;
+    const size_t mixed = ctx->opt.precision == LFMM_MIXED        ? (nb + 1) * (P * 8 + 8) + 3 * al
+                         : ctx->opt.precision == LFMM_MIXED_BF16 ? (nb + 1) * (P * 6 + 8) + 2 * al
+                                                                 : 0;
     const size_t box = nb * (8 + 20 + 1 + 16 + 36 + 4 * kNumInteractions + 32) + tiles * sizeof(BoxTile) +
                        2 * (nb + 1) * P * 8 + nl * (sizeof(NearGroup) + kNearEntries * 16) + 14 * al + mixed;
     const size_t small = sizeof(InstInfo) + 64 * sizeof(OpsPtrs) + 16 + 4 * size_t(D + 2) * sizeof(BoxGroup) +

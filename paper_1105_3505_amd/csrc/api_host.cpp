@@ -21,8 +21,8 @@ lfmm_status fail(lfmm_status s, const std::string& msg) {
 lfmm_status validate_options(const lfmm_options* o) {
     if (!(o->eps > 0.0 && o->eps < 1e-2)) return fail(LFMM_E_INVAL, "eps must lie in (0, 1e-2)");
     if (o->max_leaf < 0 || o->max_leaf > 4096) return fail(LFMM_E_INVAL, "max_leaf must lie in [0, 4096]");
-    if (o->precision != LFMM_FP64 && o->precision != LFMM_MIXED)
-        return fail(LFMM_E_INVAL, "precision must be LFMM_FP64 or LFMM_MIXED");
+    if (o->precision != LFMM_FP64 && o->precision != LFMM_MIXED && o->precision != LFMM_MIXED_BF16)
+        return fail(LFMM_E_INVAL, "precision must be LFMM_FP64, LFMM_MIXED or LFMM_MIXED_BF16");
     if (o->proxy_per_edge < 8 || o->proxy_per_edge > 4096)
         return fail(LFMM_E_INVAL, "proxy_per_edge must lie in [8, 4096]");
     if (o->max_rank < 16 || o->max_rank > kMaxRank || o->max_rank % 16 != 0)

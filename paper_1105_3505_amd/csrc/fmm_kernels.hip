@@ -21,6 +21,7 @@ namespace lfmm {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kBf16Block = 512;   // bf16 M2L: eight waves per 128-box tile
 constexpr int kWaves = kBlock / 64;
 // Levels of at most this many 64-box tiles run M2M and L2L on the fine-grained kernels, which
 // spread one tile over twelve blocks (measured: M2M gains up to 64 tiles, L2L up to 256).
@@ -795,6 +796,220 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mixed(const BoxTile* tiles, cons
         }
         __syncthreads();   // the next pass (or tile) rewrites the staging buffers
         }
+    }
+}
+
+// bf16 mixed precision.  On gfx950 the bf16 matrix instructions run 32 times faster than the
+// FP64 ones (16x16x32 in 16 cycles against 16x16x4 in 64), while FP32 runs only twice as fast,
+// so that a split FP32 product (three instructions) cannot beat FP64.  Here q-hat and R^d
+// (T^d less its constant part, applied in FP64 as for the FP32 form) are each split into three
+// bf16 parts, x = x0 + x1 + x2 with x_k the rounded remainder of the parts before (about 24
+// significant bits in all), and R q is formed from the six products R_a q_b with a + b <= 2:
+// the dropped ones are below 2^-24 of the leading product.  bf16 x bf16 products are exact in
+// FP32.  The six 48-term products are 36 (product, group of 8 columns) pieces, laid along the
+// contraction of nine K = 32 instructions that sum into one FP32 accumulator, which is added
+// to the FP64 accumulator once per interaction.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+// bits of the bf16 nearest to x (through FP32, as the operators' host split) and their value
+__device__ inline uint32_t bf16_bits(double x) {
+    uint32_t u = __float_as_uint(float(x));
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ inline double bf16_val(uint32_t b) { return double(__uint_as_float(b << 16)); }
+
+// q-hat in three bf16 parts (row of a box: part p holds entries p * 48 .. p * 48 + 47) and its
+// FP64 charge sum, for boxes [0, nrows) (the all-zero row included); each remainder is exact.
+__global__ void k_split_q_bf16(const double* Q, int32_t nrows, uint16_t* Qb, double* qs) {
+    constexpr int P = kRankPad;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t box = t / 64;
+    const int lane = int(t & 63);
+    if (box >= nrows) return;   // uniform over the wave: a wave is one box
+    const double q = lane < P ? Q[box * P + lane] : 0.0;
+    if (lane < P) {
+        uint16_t* row = Qb + box * (3 * P);
+        double r = q;
+        #pragma unroll
+        for (int part = 0; part < 3; ++part) {
+            const uint32_t b = bf16_bits(r);
+            row[part * P + lane] = uint16_t(b);
+            r -= bf16_val(b);
+        }
+    }
+    double s = q;
+    #pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) qs[box] = s;
+}
+
+// M2L on the bf16 matrix cores, on the same 128-box tiles as k_m2l: eight waves per tile, wave w
+// owning the 16-box column block w, four waves per SIMD.  (Two column blocks per wave would
+// read each operator fragment from LDS once for two products, but its registers allow only
+// two waves per SIMD, too few to hide the latencies of a slot that lasts a quarter of an FP64
+// one; measured slower.)  The operator's three parts (13.5 KB) are staged in LDS once per slot
+// and block.
+//
+// Contraction layout.  16x16x32 bf16 instruction: lane (g, n) supplies row n of the operator
+// and column n of q-hat at contraction indices 8 g .. 8 g + 7 (one group of 8 columns of one
+// part each); element i of its result is row 4 g + i, column n.  Lane group g owns column
+// groups c = 3 (g & 1) + t, t = 0, 1, 2; in instruction j = 3 t + r it takes column group
+// 3 (g & 1) + t of the product
+//   g = 0, 1:  r = 0: R0 q0,  r = 1: R1 q0,  r = 2: R2 q0
+//   g = 2, 3:  r = 0: R0 q1,  r = 1: R1 q1,  r = 2: R0 q2
+// so every (product, column group) piece appears once, and a lane reads three groups of q-hat
+// (g = 0, 1: q0) or six (g = 2, 3: q1 and q2) per source.
+//
+// Rounding.  The leading product R0 q0 sits in the instructions r = 0 (a third of it in each);
+// each of them starts from zero and is added to the FP64 accumulator at once, so FP32 rounds
+// partial sums of a third of the leading product only.  The r = 1, 2 instructions (at most
+// 2^-8 of it) share one FP32 sum per interaction.  The constant part c_d times the source's
+// charge sum is summed per column in FP64 and added once at the end.
+//
+// The next slot's q-hat groups are loaded into the registers of group t as soon as the
+// current slot's instructions 3 t .. 3 t + 2 have read them.
+__global__ __launch_bounds__(kBf16Block, 4) void k_m2l_bf16(const BoxTile* tiles, const int32_t* ntiles_dev,
+                                                              const int32_t* box_list, const int32_t* il27,
+                                                              const OpsPtrs* ops, const uint16_t* Qb,
+                                                              const double* qs, int32_t zrow, double* U) {
+    const int32_t ntiles = uniform(*ntiles_dev);
+    constexpr int P = kRankPad, NS = kNumInteractions, NF = kBf16OpVecs, NT = kBf16Block;
+    static_assert(kM2LTile == 16 * (kBf16Block / 64), "one column block per wave");
+    constexpr int NST = (NF + NT - 1) / NT;     // staged groups per thread
+    constexpr uint32_t QB = kBf16QVecs * 16;    // bytes of q-hat parts per box
+    __shared__ u32x4_t sA[2][NF];
+    __shared__ int32_t s_src[kM2LTile * NS];     // source box of (tile column, slot), zrow if none
+    __shared__ int32_t s_box[kM2LTile];
+    __shared__ int s_dsl[NS];
+    __shared__ double s_mono[NS];
+    const int tid = int(threadIdx.x), wave = tid >> 6, lane = tid & 63;
+    const int n = lane & 15, g = lane >> 4;
+    const bool q0_lanes = g < 2;                 // lane groups 0, 1: the three products with q0
+    const int c0 = 3 * (g & 1);                  // first column group of the lane group
+    const int32_t G = int32_t(gridDim.x);
+    const u32x4_t z4 = {0u, 0u, 0u, 0u};
+    const float4_t zero = {0.f, 0.f, 0.f, 0.f};
+    // operator fragment of instruction j = 3 t + r, row block m: group
+    // pa * 288 + 96 m + 16 (c0 + t) + n with pa = r, except pa = 0 for r = 2 on lanes 2, 3
+    const int abase = c0 * 16 + n;
+    const int abase2 = abase + (q0_lanes ? 2 * 288 : 0);
+    // q-hat groups of a source, byte offsets: lanes 0, 1 part 0, groups c0 .. c0 + 2 (twice, so
+    // that instruction r = 2 reads the second copy on every lane); lanes 2, 3 part 1, then part 2
+    const uint32_t qoff1 = uint32_t((q0_lanes ? 0 : 6) + c0) * 16u;
+    const uint32_t qoff2 = uint32_t((q0_lanes ? 0 : 12) + c0) * 16u;
+    const int col = 16 * wave + n;               // this lane's column of the tile
+    for (int32_t step = 0;; ++step) {
+        const int32_t t = uniform(xcd_tile(int32_t(blockIdx.x), G, step, ntiles));
+        if (t < 0) break;                                  // uniform over the block
+        const int32_t count = uniform(tiles[t].count);
+        if (count == 0) continue;
+        const int32_t start = uniform(tiles[t].start), height = uniform(tiles[t].height);
+        const int32_t cls = uniform(tiles[t].cls), opi = uniform(tiles[t].ops);
+        if (tid < NS) {
+            const int d = height * kNumIfoSlots + c_dslot.s[cls][tid];
+            s_dsl[tid] = d;
+            s_mono[tid] = ops[opi].mono[d];
+        }
+        if (tid < kM2LTile) s_box[tid] = (tid < count) ? box_list[start + tid] : -1;
+        __syncthreads();
+        for (int i = tid; i < kM2LTile * NS; i += NT) {
+            const int b = i / NS;
+            const int32_t box = s_box[b];
+            const int32_t src = box >= 0 ? il27[size_t(box) * NS + (i - b * NS)] : -1;
+            s_src[i] = src < 0 ? zrow : src;
+        }
+        const int rk = uniform(ops[opi].rank[height]);
+        const gptr<u32x4_t> Ah = global(reinterpret_cast<const u32x4_t*>(ops[opi].ifo_b));
+        const gptr<double> QS = global(qs);
+        const gptr<uint8_t> Xb = global(reinterpret_cast<const uint8_t*>(Qb));
+        const int32_t box = s_box[col];
+        __syncthreads();
+        const int32_t* srcs = s_src + col * NS;
+        // q-hat groups of the slot's source: [t] first part, [3 + t] the part that instruction
+        // 3 t + 2 reads; sources addressed by 32-bit byte offsets from Qb
+        u32x4_t bq[6];
+        uint32_t qn = uint32_t(srcs[0]) * QB;
+        double nsum = QS[srcs[0]];
+        auto load_group = [&](int tt) {
+            bq[tt] = *reinterpret_cast<gptr<u32x4_t>>(Xb + (qn + qoff1 + 16u * tt));
+            bq[3 + tt] = *reinterpret_cast<gptr<u32x4_t>>(Xb + (qn + qoff2 + 16u * tt));
+        };
+        #pragma unroll
+        for (int tt = 0; tt < 3; ++tt) load_group(tt);
+        int32_t dsl_next = s_dsl[1];
+        u32x4_t ra[NST];
+        {
+            const gptr<u32x4_t> A0 = Ah + size_t(s_dsl[0]) * NF;
+            #pragma unroll
+            for (int e = 0; e < NST; ++e) ra[e] = (e * NT + tid < NF) ? A0[e * NT + tid] : z4;
+        }
+        double4_t acc[3];
+        #pragma unroll
+        for (int m = 0; m < 3; ++m) acc[m] = double4_t{0.0, 0.0, 0.0, 0.0};
+        double mono_acc = 0.0;
+        for (int k = 0; k < NS; ++k) {
+            u32x4_t* buf = sA[k & 1];
+            #pragma unroll
+            for (int e = 0; e < NST; ++e)
+                if (e * NT + tid < NF) buf[e * NT + tid] = ra[e];
+            mono_acc += s_mono[k] * nsum;   // constant part of T^d times the charge sum
+            __syncthreads();
+            if (k + 1 < NS) {   // the next slot's operator, into registers; its source
+                const gptr<u32x4_t> An = Ah + size_t(uniform(dsl_next)) * NF;
+                #pragma unroll
+                for (int e = 0; e < NST; ++e)
+                    if (e * NT + tid < NF) ra[e] = An[e * NT + tid];
+                dsl_next = (k + 2 < NS) ? s_dsl[k + 2] : 0;
+                const int32_t sn = srcs[k + 1];
+                qn = uint32_t(sn) * QB;
+                nsum = QS[sn];
+            }
+            asm volatile("" ::: "memory");
+            float4_t small[3];
+            #pragma unroll
+            for (int tt = 0; tt < 3; ++tt) {
+                #pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const int j = 3 * tt + r;
+                    // three operator fragments in flight: more would cost the fourth wave per SIMD
+                    asm volatile("" ::: "memory");
+                    #pragma unroll
+                    for (int m = 0; m < 3; ++m) {
+                        const u32x4_t a =
+                            (r == 2) ? buf[abase2 + 96 * m + 16 * tt] : buf[abase + r * 288 + 96 * m + 16 * tt];
+                        // r = 2: q0 (lanes 0, 1) or q2 (lanes 2, 3); else the lane group's first part
+                        const u32x4_t b = (r == 2) ? bq[3 + tt] : bq[tt];
+                        const bf16x8_t av = __builtin_bit_cast(bf16x8_t, a), bv = __builtin_bit_cast(bf16x8_t, b);
+                        if (r == 0) {
+                            const float4_t p = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, zero, 0, 0, 0);
+                            #pragma unroll
+                            for (int i = 0; i < 4; ++i) acc[m][i] += double(p[i]);
+                        } else {
+                            small[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, j == 1 ? zero : small[m], 0,
+                                                                               0, 0);
+                        }
+                    }
+                }
+                if (k + 1 < NS) load_group(tt);   // group tt of the next slot's source
+            }
+            #pragma unroll
+            for (int m = 0; m < 3; ++m)
+                #pragma unroll
+                for (int i = 0; i < 4; ++i) acc[m][i] += double(small[m][i]);
+        }
+        if (box >= 0) {
+            double* ob = U + size_t(box) * P;
+            #pragma unroll
+            for (int m = 0; m < 3; ++m)
+                #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = 16 * m + 4 * g + i;
+                    ob[row] = acc[m][i] + (row < rk ? mono_acc : 0.0);   // padded rows stay zero
+                }
+        }
+        __syncthreads();   // the next tile rewrites the staging buffers and lists read above
     }
 }
 
@@ -1612,6 +1827,21 @@ void launch_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t m
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
     hipLaunchKernelGGL(k_m2l_mixed, dim3(static_cast<unsigned>(g)), dim3(kBlock), 0, st, tiles, ntiles_dev, box_list,
                        il27, ops, Qh, Ql, qs, zrow, U);
+}
+
+void launch_split_q_bf16(const double* Q, int32_t nrows, uint16_t* Qb, double* qs, hipStream_t st) {
+    if (nrows <= 0) return;
+    hipLaunchKernelGGL(k_split_q_bf16, dim3(grid_for(int64_t(nrows) * 64)), dim3(kBlock), 0, st, Q, nrows, Qb, qs);
+}
+
+void launch_m2l_bf16(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t max_tiles, const int32_t* box_list,
+                     const int32_t* il27, const OpsPtrs* ops, const uint16_t* Qb, const double* qs, int32_t zrow,
+                     double* U, hipStream_t st) {
+    if (max_tiles <= 0) return;
+    int64_t g = std::min<int64_t>(max_tiles, 8192);
+    g = std::max<int64_t>(8, (g + 7) / 8 * 8);
+    hipLaunchKernelGGL(k_m2l_bf16, dim3(static_cast<unsigned>(g)), dim3(kBf16Block), 0, st, tiles, ntiles_dev,
+                       box_list, il27, ops, Qb, qs, zrow, U);
 }
 
 void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* ents, const int32_t* box_pt0,

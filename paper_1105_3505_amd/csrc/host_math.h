@@ -5,6 +5,7 @@
 #pragma once
 
 #include <cstdint>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -35,6 +36,25 @@ struct Stencil {
 // The operator's data, its table built (and, for operators other than the 5-point one, its
 // far-field coefficients fitted) on first use.
 const Stencil& stencil(int id);
+
+// bfloat16 (8 significant bits, FP32's exponent range): the bits of the value nearest to x,
+// rounded to FP32 first and then to nearest-even (the two roundings can differ from one
+// direct rounding by one unit in the last bit; the splits that use it take the remainder
+// exactly, so that only changes how the value is shared between the parts), and the
+// value of such bits.
+inline uint16_t bf16_rne(double x) {
+    const float f = float(x);
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+inline double bf16_value(uint16_t b) {
+    const uint32_t u = uint32_t(b) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return double(f);
+}
 
 inline int64_t octant_index(int64_t a, int64_t b) { return a * (a + 1) / 2 + b; }
 inline int64_t octant_size(int64_t r) { return (r + 1) * (r + 2) / 2; }

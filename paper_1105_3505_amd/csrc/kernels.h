@@ -53,6 +53,10 @@ struct BoxGroup {
 // Boxes per tile: the M2L kernels give 32 boxes (two 16-column blocks) to each of their 4
 // waves, the M2M / L2L box-matrix kernels 16.
 constexpr int kM2LTile = 128;
+// bf16 mixed precision: 16-byte groups of 8 bf16 per operator (3 parts x 3 row blocks x 6
+// column groups x 16 rows) and per outgoing expansion (3 parts x 6 groups)
+constexpr int kBf16OpVecs = 3 * 3 * 6 * 16;
+constexpr int kBf16QVecs = 3 * 6;
 constexpr int kBoxMatTile = 64;
 
 // Per leaf side: operators in device memory (uploaded once, shared by every plan).
@@ -71,6 +75,10 @@ struct DevOps {
     // element ((m * 3 + j) * 64 + l) * 4 + e is row 16 m + (l % 16), column (l / 16) * 12 + 4 j + e
     float* ifo_hi = nullptr;
     float* ifo_lo = nullptr;
+    // bf16 mixed precision: R^d = R0 + R1 + R2 (three bf16 parts, each the rounded remainder
+    // of the ones before), [nlev][49][kBf16OpVecs] groups of 8 bf16 in fragment order: group
+    // ((p * 3 + m) * 6 + s) * 16 + n holds R_p[16 m + n][8 s .. 8 s + 7]
+    uint16_t* ifo_b = nullptr;
     double* mono = nullptr;        // [nlev][49] c_d
     int32_t* rank = nullptr;       // [nlev] skeleton size of each height
     int32_t* skel = nullptr;       // [nlev][kRankPad][2] skeleton points, offsets from the box corner
@@ -84,6 +92,7 @@ struct OpsPtrs {
     const double* ifo;
     const float* ifo_hi;
     const float* ifo_lo;
+    const uint16_t* ifo_b;
     const double* mono;
     const int32_t* rank;
     const int32_t* skel;
@@ -275,6 +284,10 @@ void launch_m2l(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t max_til
                 const int32_t* il27, const OpsPtrs* ops, const double* Q, int32_t zrow, double* U, hipStream_t st);
 // mixed-precision operands of Q rows [0, nrows): FP32 hi and lo parts and FP64 charge sums
 void launch_split_q(const double* Q, int32_t nrows, float* Qh, float* Ql, double* qs, hipStream_t st);
+void launch_split_q_bf16(const double* Q, int32_t nrows, uint16_t* Qb, double* qs, hipStream_t st);
+void launch_m2l_bf16(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t max_tiles, const int32_t* box_list,
+                     const int32_t* il27, const OpsPtrs* ops, const uint16_t* Qb, const double* qs, int32_t zrow,
+                     double* U, hipStream_t st);
 void launch_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t max_tiles,
                       const int32_t* box_list, const int32_t* il27, const OpsPtrs* ops,
                       const float* Qh, const float* Ql, const double* qs, int32_t zrow, double* U,

@@ -157,13 +157,14 @@ def test_parity_fp64(torch_mod, lf, case):
     plan.close()
 
 
+@pytest.mark.parametrize("precision", ["mixed", "mixed-bf16"])
 @pytest.mark.parametrize("case", ["background_20k", "clusters_30k"])
-def test_parity_mixed(torch_mod, lf, case):
+def test_parity_mixed(torch_mod, lf, case, precision):
     make, max_leaf = PARITY_CASES[case]
     xy = make()
     f = _loads(8, len(xy))
-    u, plan = _solve(torch_mod, _ctx(lf, max_leaf=max_leaf, precision="mixed"), xy, f)
-    _check(u, od.direct_sum(xy, xy, f), MIXED_TOL, case + " mixed")
+    u, plan = _solve(torch_mod, _ctx(lf, max_leaf=max_leaf, precision=precision), xy, f)
+    _check(u, od.direct_sum(xy, xy, f), MIXED_TOL, case + " " + precision)
     plan.close()
 
 
@@ -249,12 +250,12 @@ def test_unsupported_entry_points(torch_mod, lf):
 
 def test_clusters_full_size_sampled(torch_mod, lf):
     """2,000,000 clustered sources (64 Gaussian clusters, sigma 2,000, in 2^20 x 2^20) on the
-    adaptive tree, FP64 and mixed, compared on 2,000 sampled targets."""
+    adaptive tree, FP64 and both mixed forms, compared on 2,000 sampled targets."""
     torch = torch_mod
     xy, f = wl.config_clusters()
     k = wl.sample_targets(3, len(xy), 2000)
     ref = od.direct_sum(xy[k], xy, f)
-    for prec, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
+    for prec, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL), ("mixed-bf16", MIXED_TOL)):
         u, plan = _solve(torch, _ctx(lf, max_leaf=32, precision=prec), xy, f)
         info = plan.info()
         print(prec, {key: info[key] for key in ("n_boxes", "n_leaves", "near_pairs", "m2l_pairs", "m2p_terms",

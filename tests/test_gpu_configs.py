@@ -2,9 +2,9 @@
 (direct sum of eq. 1.7) on sampled targets:
 
 * 2,000,000 sources in 64 Gaussian clusters over a 2^20 x 2^20 region, mixed precision
-  (FP32 hi/lo matrix-core M2L), tolerance 1e-7;
+  (FP32 hi/lo or three-part bf16 matrix-core M2L), tolerance 1e-7;
 * the 512-instance batch (sizes log-uniform in [1e3, 1e5]) as one forest plan, FP64
-  (tolerance 1e-10) and mixed (1e-7);
+  (tolerance 1e-10) and both mixed forms (1e-7);
 * serving requests up to ~8.7e5 points through the continuous-batching server.
 
 Each check asserts the relative l2 error and the max-norm error max |u - u_ref| / max |u_ref|.
@@ -17,7 +17,7 @@ from oracle import direct as od
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
-TOL = {"fp64": 1e-10, "mixed": 1e-7}
+TOL = {"fp64": 1e-10, "mixed": 1e-7, "mixed-bf16": 1e-7}
 
 
 @pytest.fixture(scope="module")
@@ -35,11 +35,12 @@ def _errs(u, ref):
             float(np.max(np.abs(u - ref)) / np.max(np.abs(ref))))
 
 
-def test_clusters_mixed_full_size(torch_mod):
+@pytest.mark.parametrize("precision", ["mixed", "mixed-bf16"])
+def test_clusters_mixed_full_size(torch_mod, precision):
     import paper_1105_3505_amd as lf
     torch = torch_mod
     xy, f = wl.config_clusters()
-    ctx = lf.Context(0, precision="mixed")
+    ctx = lf.Context(0, precision=precision)
     plan = ctx.plan(_dev(torch, xy))
     u = plan.execute(_dev(torch, f))
     torch.cuda.synchronize()
@@ -47,14 +48,14 @@ def test_clusters_mixed_full_size(torch_mod):
     ref = od.direct_sum(xy[idx], xy, f)
     l2, mx = _errs(u.cpu().numpy()[idx], ref)
     info = plan.info()
-    print("2e6 clusters mixed: leaf side %d, %d boxes, rel l2 %.3e, max %.3e"
-          % (info["leaf_side"], info["n_boxes"], l2, mx))
-    assert l2 <= TOL["mixed"] and mx <= TOL["mixed"]
+    print("2e6 clusters %s: leaf side %d, %d boxes, rel l2 %.3e, max %.3e"
+          % (precision, info["leaf_side"], info["n_boxes"], l2, mx))
+    assert l2 <= TOL[precision] and mx <= TOL[precision]
     plan.close()
     ctx.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed-bf16"])
 def test_batched_512_full_forest(torch_mod, precision):
     import paper_1105_3505_amd as lf
     torch = torch_mod

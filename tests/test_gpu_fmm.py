@@ -219,10 +219,11 @@ def test_leaf_sizes(torch_mod, max_leaf):
     ctx.close()
 
 
-def test_mixed_precision_m2l(torch_mod):
-    # FP32 hi/lo matrix-core M2L; everything else FP64; target 1e-7
+@pytest.mark.parametrize("precision", ["mixed", "mixed-bf16"])
+def test_mixed_precision_m2l(torch_mod, precision):
+    # FP32 hi/lo (or three-part bf16) matrix-core M2L; everything else FP64; target 1e-7
     import paper_1105_3505_amd as lf
-    ctx = lf.Context(0, precision="mixed")
+    ctx = lf.Context(0, precision=precision)
     for seed, n, side in [(61, 1000, 256), (62, 30000, 700)]:
         rng = np.random.default_rng(seed)
         xy = wl.uniform_box(rng, n, side)
@@ -230,6 +231,6 @@ def test_mixed_precision_m2l(torch_mod):
         u, _ = _fmm(torch_mod, ctx, xy, f)
         ref = od.direct_sum(xy, xy, f)
         err, mx = _rel(u, ref), _maxrel(u, ref)
-        print("mixed n=%d rel err %.3e max %.3e" % (n, err, mx))
+        print("%s n=%d rel err %.3e max %.3e" % (precision, n, err, mx))
         assert err <= 1e-7 and mx <= 1e-7
     ctx.close()

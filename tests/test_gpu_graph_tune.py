@@ -24,7 +24,7 @@ def _dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed-bf16"])
 def test_graph_replay_equals_eager(torch_mod, precision):
     import paper_1105_3505_amd as lf
     torch = torch_mod

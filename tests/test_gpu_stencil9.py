@@ -30,7 +30,7 @@ def _errs(u, ref):
 
 
 @pytest.mark.parametrize("max_leaf,n,precision", [(8, 3000, "fp64"), (16, 9000, "fp64"), (64, 12000, "fp64"),
-                                                   (8, 6000, "mixed")])
+                                                   (8, 6000, "mixed"), (8, 6000, "mixed-bf16")])
 def test_fmm_9_point(torch_mod, max_leaf, n, precision):
     import paper_1105_3505_amd as lf
     torch = torch_mod

@@ -531,11 +531,13 @@ __global__ __launch_bounds__(kBlock, 3) void k_m2l(const BoxTile* tiles, const i
             const int32_t box = c ? box1 : box0;
             if (box >= 0) {
                 double* ob = U + size_t(box) * P;
+                // streaming stores: the incoming expansions are read by later passes only, and
+                // in L2 they would evict source expansions that other tiles still gather
                 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    ob[g + 4 * i] = acc[c][0][i];
-                    ob[16 + g + 4 * i] = acc[c][1][i];
-                    ob[32 + g + 4 * i] = acc[c][2][i];
+                    __builtin_nontemporal_store(acc[c][0][i], ob + g + 4 * i);
+                    __builtin_nontemporal_store(acc[c][1][i], ob + 16 + g + 4 * i);
+                    __builtin_nontemporal_store(acc[c][2][i], ob + 32 + g + 4 * i);
                 }
             }
         }

@@ -244,13 +244,26 @@ def run_single(args, torch, lf):
                      adaptive=args.tree == "adaptive")
     streams = streams_for(args.inflight, torch)
     outs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in streams]
+    sorted_io = args.io == "sorted"
+    if sorted_io:
+        # loads already in the plan's Morton order (the sort of these points is the same for
+        # every plan of them): potentials come back in that order too
+        p0 = ctx.plan(xy_d)
+        perm_d = torch.from_numpy(p0.export("perm").astype(np.int64)).to(dev)
+        p0.close()
+        f_in = f_d[perm_d].contiguous()
+    else:
+        f_in = f_d
 
     def step(timing, slot):
         st = streams[slot]
         plan = ctx.plan(xy_d, stream=st)
         if timing:
             plan.set_timing_phases(timing)
-        plan.execute(f_d, outs[slot], stream=st)
+        if sorted_io:
+            plan.execute_sorted(f_in, outs[slot], stream=st)
+        else:
+            plan.execute(f_in, outs[slot], stream=st)
         return plan
 
     for _ in range(max(args.warmup, 1)):
@@ -267,15 +280,22 @@ def run_single(args, torch, lf):
     u_d = outs[0]
     plan = ctx.plan(xy_d, stream=stream)
     info = plan.info()
+    run = (lambda: plan.execute_sorted(f_in, u_d, stream=stream)) if sorted_io else \
+        (lambda: plan.execute(f_in, u_d, stream=stream))
     for _ in range(3):
-        plan.execute(f_d, u_d, stream=stream)
+        run()
     torch.cuda.synchronize()
     reps = max(args.steps, 10)
     t0 = time.perf_counter()
     for _ in range(reps):
-        plan.execute(f_d, u_d, stream=stream)
+        run()
     torch.cuda.synchronize()
     exec_ms = (time.perf_counter() - t0) * 1e3 / reps
+    if sorted_io:   # back to the caller's order for the checks below
+        u_caller = torch.empty_like(u_d)
+        u_caller[perm_d] = u_d
+        for o in outs:
+            o.copy_(u_caller)
     u = u_d.cpu().numpy()
     plan.close()
     equation = None
@@ -286,7 +306,8 @@ def run_single(args, torch, lf):
     config = {"workload": WORKLOADS[args.workload], "n_sources": n, "precision": args.precision,
               "tree": args.tree, "leaf_level": info["leaf_level"], "leaf_side": info["leaf_side"],
               "max_leaf": args.max_leaf, "rank": RANK, "eps": 1e-12,
-              "operator": "9-point isotropic" if args.stencil == 9 else "5-point"}
+              "operator": "9-point isotropic" if args.stencil == 9 else "5-point",
+              "io": "plan (Morton) order" if sorted_io else "caller order"}
     result = base_result(args, value, ms_per_step, config)
     result.update(timing_fields(m, n, args.inflight))
     result.update({"inflight_outputs_equal": same,
@@ -680,6 +701,9 @@ def main() -> None:
                          "N_leaf points); default adaptive for clusters, uniform otherwise")
     ap.add_argument("--stencil", type=int, default=5, choices=(5, 9),
                     help="lattice operator: the 5-point Laplacian of the paper or the isotropic 9-point one")
+    ap.add_argument("--io", choices=("caller", "sorted"), default="caller",
+                    help="single-plan workloads: loads and potentials in the caller's order (lfmm_execute) or "
+                         "in the plan's Morton order (lfmm_execute_sorted)")
     ap.add_argument("--inflight", type=int, default=3,
                     help="independent solves in flight in the timed region, one stream each")
     ap.add_argument("--cpu-targets", type=int, default=20000)

@@ -197,6 +197,22 @@ lfmm_status lfmm_plan_create_batch(lfmm_ctx* ctx, int32_t n_inst, const int64_t*
  * an execute on another stream than the plan was built on waits for the build. */
 lfmm_status lfmm_execute(lfmm_plan* plan, const double* f_dev, double* u_dev, void* stream);
 
+/* lfmm_execute with loads and potentials in the plan's own point order, for callers that keep
+ * their vectors in that order across many executes of one plan (iterative solvers, repeated
+ * right-hand sides): P2M then reads the loads, and the near field writes the potentials, as
+ * contiguous runs instead of one scattered word per point.  Index s runs over every point of
+ * the plan (n_points of lfmm_plan_get_info: sources and separate targets of all instances,
+ * concatenated in instance order, Morton-ordered inside each; LFMM_EXPORT_PERM gives the
+ * caller index perm[s] of each).  f_sorted_dev[s] is the load of point s where perm[s] is a
+ * source index (perm[s] < n_src of its instance); other entries are not read.  u_sorted_dev[s]
+ * receives the potential of point s where it is a target (with separate targets, perm[s] >=
+ * n_src: target perm[s] - n_src); other entries are not written.  Same arithmetic as
+ * lfmm_execute, so u_sorted_dev[s] equals u_dev[perm[s]] of the same loads bit for bit.
+ * Device float64 arrays of n_points entries; enqueued on `stream`, no sync (with
+ * LFMM_FLAG_CHECK_LOADS all n_points loads are checked).  Works for every plan, including
+ * several instances, adaptive trees and graph replays. */
+lfmm_status lfmm_execute_sorted(lfmm_plan* plan, const double* f_sorted_dev, double* u_sorted_dev, void* stream);
+
 /* lfmm_execute for a plan of several instances: f_dev[k] and u_dev[k] (device arrays of
  * n_host[k] float64, in instance k's caller order) belong to instance k; the pointer arrays
  * are host memory read during the call.  One launch per pass covers every instance. */

@@ -91,6 +91,7 @@ def _load():
         "lfmm_plan_create_batch": [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
         "lfmm_execute": [_vp, _vp, _vp, _vp],
         "lfmm_execute_instances": [_vp, _vp, _vp, _vp],
+        "lfmm_execute_sorted": [_vp, _vp, _vp, _vp],
         "lfmm_execute_batch": [_vp, _i32, _vp, _vp, _vp, _vp],
         "lfmm_plan_get_info": [_vp, _vp],
         "lfmm_autotune": [_vp, _i64, _vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp],
@@ -270,7 +271,8 @@ class Context:
         h = ctypes.c_void_p()
         _check(_lib.lfmm_plan_create(self._h, int(xy.shape[0]), ptr, nt, tp, _stream_handle(stream),
                                      ctypes.byref(h)))
-        plan = Plan(self, h, [int(xy.shape[0])], [nt if targets is not None else int(xy.shape[0])])
+        plan = Plan(self, h, [int(xy.shape[0])], [nt if targets is not None else int(xy.shape[0])],
+                    n_points=int(xy.shape[0]) + nt)
         self._plans.add(plan)
         return plan
 
@@ -295,7 +297,8 @@ class Context:
         _check(_lib.lfmm_plan_create_batch(self._h, k, sizes.ctypes.data_as(_vp), ptrs,
                                            None if tsz is None else tsz.ctypes.data_as(_vp), tptrs,
                                            _stream_handle(stream), ctypes.byref(h)))
-        plan = Plan(self, h, [int(v) for v in sizes], outs)
+        plan = Plan(self, h, [int(v) for v in sizes], outs,
+                    n_points=int(sizes.sum()) + (0 if tsz is None else int(tsz.sum())))
         self._plans.add(plan)
         return plan
 
@@ -366,13 +369,14 @@ class Context:
 class Plan:
     """lfmm_plan: the trees of one or more point sets (instances), resident on the device."""
 
-    def __init__(self, ctx: Context, handle, sizes, out_sizes=None):
+    def __init__(self, ctx: Context, handle, sizes, out_sizes=None, n_points=None):
         self.ctx = ctx
         self._h = handle
         self.sizes = list(sizes)                    # sources per instance
         self.out_sizes = list(out_sizes if out_sizes is not None else sizes)   # targets per instance
         self.n = sum(self.sizes)
         self.n_out = sum(self.out_sizes)
+        self._n_points = n_points                   # points of the plan: sources and separate targets
 
     def execute(self, f, u=None, stream=None):
         """lfmm_execute: f has one load per source, u one potential per target."""
@@ -385,6 +389,24 @@ class Plan:
             raise ValueError("u must have one entry per target")
         _check(_lib.lfmm_execute(self._h, _dev_tensor(f, torch.float64, (), "f"),
                                  _dev_tensor(u, torch.float64, (), "u"), _stream_handle(stream)))
+        _keep_for(stream, f, u)
+        return u
+
+    def execute_sorted(self, f, u=None, stream=None):
+        """lfmm_execute_sorted: f and u span every point of the plan in its Morton order
+        (export("perm") gives each point's caller index)."""
+        import torch
+        if self._n_points is None:   # get_info reads back plan statistics: once
+            self._n_points = int(self.info()["n_points"])
+        n_all = self._n_points
+        if int(f.shape[0]) != n_all:
+            raise ValueError("f must have one entry per point of the plan (%d)" % n_all)
+        if u is None:
+            u = _empty_on(stream, n_all, f.device)
+        elif int(u.shape[0]) != n_all:
+            raise ValueError("u must have one entry per point of the plan (%d)" % n_all)
+        _check(_lib.lfmm_execute_sorted(self._h, _dev_tensor(f, torch.float64, (), "f"),
+                                        _dev_tensor(u, torch.float64, (), "u"), _stream_handle(stream)))
         _keep_for(stream, f, u)
         return u
 

@@ -404,9 +404,15 @@ struct lfmm_plan {
     int32_t n_ad_leaves = 0, n_ad_xboxes = 0;
     int32_t* pt_box = nullptr;              // finest box of every point
     BoxTile* m2l_tiles = nullptr;           // the non-empty M2L tiles, compacted
-    ExecPtrs* h_exec = nullptr;             // pinned staging of the per-execute pointers
+    // pinned staging of the per-execute pointer table: kExecRing slots of K entries, each
+    // rewritten only after the upload that read it (its event); the host copy of the table
+    // last uploaded to d_exec lets an execute with the same pointers skip the upload
+    static constexpr int kExecRing = 4;
+    ExecPtrs* h_exec = nullptr;
     size_t h_exec_cls = 0;
-    hipEvent_t exec_copied = nullptr;       // the last staging copy has been read
+    hipEvent_t exec_copied[kExecRing] = {};
+    int exec_slot = 0;
+    std::vector<ExecPtrs> exec_last;
     bool failed = false;
     uint32_t timing_mask = 0;   // phases whose bounding events later executes record
     uint32_t timed_mask = 0;    // phases timed by the most recent timed execute
@@ -427,7 +433,8 @@ struct lfmm_plan {
         if (graph) (void)hipGraphDestroy(graph);
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
-        if (exec_copied) (void)hipEventDestroy(exec_copied);
+        for (hipEvent_t e : exec_copied)
+            if (e) (void)hipEventDestroy(e);
         if (h_exec) ctx->pinned.release(h_exec, h_exec_cls);
     }
 };
@@ -734,6 +741,12 @@ namespace {
 // near fields of the union are those of the sources, and the incoming expansion of any box
 // holding targets is evaluated at them by T_tfi = T_ofs^T of the dense model box, which
 // covers every cell of the box (Section 4.3, incoming skeleton; Remark 8.2).
+void acquire_exec_staging(lfmm_plan* pl) {
+    pl->h_exec = static_cast<ExecPtrs*>(pl->ctx->pinned.acquire(
+        size_t(lfmm_plan::kExecRing) * size_t(pl->K) * sizeof(ExecPtrs), &pl->h_exec_cls));
+    for (hipEvent_t& e : pl->exec_copied) LFMM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+}
+
 void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max_leaf, hipStream_t st) {
     lfmm_ctx* ctx = pl->ctx;
     pl->K = K;
@@ -1318,8 +1331,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     // whose kernels always read the table)
     pl->use_graph = (ctx->opt.flags & LFMM_FLAG_GRAPH) != 0 && !sreg;
     if (K > 1 || pl->use_graph) {
-        pl->h_exec = static_cast<ExecPtrs*>(ctx->pinned.acquire(size_t(K) * sizeof(ExecPtrs), &pl->h_exec_cls));
-        LFMM_HIP(hipEventCreateWithFlags(&pl->exec_copied, hipEventDisableTiming));
+        acquire_exec_staging(pl);
     }
     pl->build_stream = st;
     if (sreg) {   // the staged host copies must have been read before they go
@@ -1407,21 +1419,37 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
     mark(6);
 }
 
-void run_forest(lfmm_plan* pl, const double* const* f, double* const* u, hipStream_t st) {
+
+// sorted: f[0] and u[0] span every point of the plan in its Morton order (lfmm_execute_sorted)
+void run_forest(lfmm_plan* pl, const double* const* f, double* const* u, hipStream_t st, bool sorted = false) {
     if (st != pl->build_stream) {
         pl->one_stream = false;
         if (pl->built) LFMM_HIP(hipStreamWaitEvent(st, pl->built->ev, 0));
     }
-    if (pl->K == 1 && !pl->use_graph) {
+    if (pl->K == 1 && !pl->use_graph && !sorted) {
         enqueue_passes(pl, nullptr, f[0], u[0], pl->timing_mask, st);
         if (pl->timing_mask) pl->timed_mask = pl->timing_mask;
         return;
     }
-    // the previous execute's copy must have read the staging buffer before it is rewritten
-    LFMM_HIP(hipEventSynchronize(pl->exec_copied));
-    for (int32_t k = 0; k < pl->K; ++k) pl->h_exec[k] = ExecPtrs{f[k], u[k], pl->nsrc[size_t(k)], pl->tgt0[size_t(k)]};
-    launch_upload(pl->d_exec, pl->h_exec, size_t(pl->K) * sizeof(ExecPtrs), st);
-    LFMM_HIP(hipEventRecord(pl->exec_copied, st));
+    if (!pl->h_exec) acquire_exec_staging(pl);   // a single-instance plan's first sorted execute
+    std::vector<ExecPtrs> table(static_cast<size_t>(pl->K));
+    for (int32_t k = 0; k < pl->K; ++k)
+        table[size_t(k)] = ExecPtrs{sorted ? f[0] : f[k], sorted ? u[0] : u[k], pl->nsrc[size_t(k)],
+                                    pl->tgt0[size_t(k)], sorted ? 1 : 0, 0};
+    const bool same = pl->exec_last.size() == table.size() &&
+                      std::memcmp(pl->exec_last.data(), table.data(), table.size() * sizeof(ExecPtrs)) == 0;
+    if (!same) {
+        // the upload is stream-ordered after every earlier execute on st (which read d_exec);
+        // the staging slot is rewritten only after the upload that last read it
+        const int slot = pl->exec_slot;
+        pl->exec_slot = (slot + 1) % lfmm_plan::kExecRing;
+        ExecPtrs* h = pl->h_exec + size_t(slot) * size_t(pl->K);
+        LFMM_HIP(hipEventSynchronize(pl->exec_copied[slot]));
+        std::memcpy(h, table.data(), table.size() * sizeof(ExecPtrs));
+        launch_upload(pl->d_exec, h, size_t(pl->K) * sizeof(ExecPtrs), st);
+        LFMM_HIP(hipEventRecord(pl->exec_copied[slot], st));
+        pl->exec_last.swap(table);
+    }
     if (!pl->use_graph) {
         enqueue_passes(pl, pl->d_exec, nullptr, nullptr, pl->timing_mask, st);
         if (pl->timing_mask) pl->timed_mask = pl->timing_mask;
@@ -1551,16 +1579,20 @@ lfmm_status check_loads(lfmm_ctx* ctx, int32_t K, const double* const* f, const 
     return res;
 }
 
-lfmm_status execute_forest(lfmm_plan* pl, const double* const* f, double* const* u, void* stream, bool check) {
+lfmm_status execute_forest(lfmm_plan* pl, const double* const* f, double* const* u, void* stream, bool check,
+                           bool sorted = false) {
     if (pl->failed) return fail(LFMM_E_HIP, "plan is in a failed state");
     return guarded([&]() -> lfmm_status {
         LFMM_HIP(hipSetDevice(pl->ctx->device));
         lfmm_status res = LFMM_OK;
         if (check || (pl->ctx->opt.flags & LFMM_FLAG_CHECK_LOADS)) {
-            res = check_loads(pl->ctx, pl->K, f, pl->nsrc.data(), as_stream(stream), pl->sreg);
+            // sorted loads: one vector over every point of the plan
+            const int32_t n_all = int32_t(pl->n);
+            res = sorted ? check_loads(pl->ctx, 1, f, &n_all, as_stream(stream), pl->sreg)
+                         : check_loads(pl->ctx, pl->K, f, pl->nsrc.data(), as_stream(stream), pl->sreg);
             if (res < 0) return res;
         }
-        run_forest(pl, f, u, as_stream(stream));
+        run_forest(pl, f, u, as_stream(stream), sorted);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
             pl->failed = true;
@@ -1770,6 +1802,13 @@ lfmm_status lfmm_execute(lfmm_plan* pl, const double* f, double* u, void* stream
     const double* fa[1] = {f};
     double* ua[1] = {u};
     return execute_forest(pl, fa, ua, stream, false);
+}
+
+lfmm_status lfmm_execute_sorted(lfmm_plan* pl, const double* f_sorted, double* u_sorted, void* stream) {
+    if (!pl || !f_sorted || !u_sorted) return fail(LFMM_E_INVAL, "null argument");
+    const double* fa[1] = {f_sorted};
+    double* ua[1] = {u_sorted};
+    return execute_forest(pl, fa, ua, stream, false, true);
 }
 
 lfmm_status lfmm_execute_instances(lfmm_plan* pl, const double* const* f, double* const* u, void* stream) {

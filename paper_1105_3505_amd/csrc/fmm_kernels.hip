@@ -91,20 +91,22 @@ inline unsigned grid_for(int64_t n, int per_block = kBlock) {
     return unsigned(g < 1 ? 1 : g);
 }
 
-// Load of sorted point s in the caller's order (instance-local index perm_local[s] of
-// instance pinst[s]; zero for a point that is a target only), also stored at fs[s] for the
-// near field: P2M visits every point once.
+// Load of sorted point s: in the caller's order, the instance-local index perm_local[s] of
+// instance pinst[s]; with sorted loads, index s itself (coalesced); zero for a point that is a
+// target only.  Also stored at fs[s] for the near field: P2M visits every point once.
 __device__ inline double gather_f(const ExecPtrs* tab, const double* f_single, int32_t nsrc_single,
                                   const int32_t* perm_local, const int32_t* pinst, int64_t s, double* fs) {
     const double* f = f_single;
     int32_t nsrc = nsrc_single;
+    bool sorted = false;
     if (tab) {
         const ExecPtrs& e = tab[pinst[s]];
         f = e.f;
         nsrc = e.nsrc;
+        sorted = e.sorted != 0;
     }
     const int32_t j = perm_local[s];
-    const double v = j < nsrc ? f[j] : 0.0;
+    const double v = j < nsrc ? f[sorted ? s : int64_t(j)] : 0.0;
     fs[s] = v;
     return v;
 }
@@ -1082,6 +1084,7 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
     const int32_t k_inst = uniform(box_inst[leaf0]);
     const bool far = far_inst[k_inst] != 0;
     double* u = tab_ptrs ? tab_ptrs[k_inst].u : u_single;
+    const bool sorted_out = tab_ptrs && tab_ptrs[k_inst].sorted;   // u indexed by sorted point
     const int32_t tgt0 = tab_ptrs ? tab_ptrs[k_inst].tgt0 : tgt0_single;   // first target index
     // passes: the whole group once (group mode) or each leaf in turn (sliced mode)
     for (int c0 = 0; c0 < (SLICED ? nleaf : 1); ++c0) {
@@ -1200,7 +1203,7 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
             double acc = (a0 + a1) + (a2 + a3);
             if (SLICED)
                 for (int o = T; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
-            if (valid && sl == 0 && pout >= tgt0) u[pout - tgt0] = acc;
+            if (valid && sl == 0 && pout >= tgt0) u[sorted_out ? int64_t(ii) : int64_t(pout - tgt0)] = acc;
         }
     }
 }
@@ -1352,6 +1355,7 @@ __global__ __launch_bounds__(64 * kStagedWaves) void k_near_staged(
     const int32_t k_inst = uniform(box_inst[leaf0]);
     const bool far = far_inst[k_inst] != 0;
     double* u = tab_ptrs ? tab_ptrs[k_inst].u : u_single;
+    const bool sorted_out = tab_ptrs && tab_ptrs[k_inst].sorted;   // u indexed by sorted point
     const int32_t tgt0 = tab_ptrs ? tab_ptrs[k_inst].tgt0 : tgt0_single;
     // first points of the group's leaves, to find each target's leaf
     int32_t bnd1 = t_end, bnd2 = t_end, bnd3 = t_end;
@@ -1449,7 +1453,7 @@ __global__ __launch_bounds__(64 * kStagedWaves) void k_near_staged(
         double acc = (a0 + a1) + (a2 + a3);
         for (int o = T; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
         const int32_t pout = perm_local[ii];
-        if (valid && sl == 0 && pout >= tgt0) u[pout - tgt0] = acc;
+        if (valid && sl == 0 && pout >= tgt0) u[sorted_out ? int64_t(ii) : int64_t(pout - tgt0)] = acc;
     }
 }
 
@@ -1556,6 +1560,7 @@ __global__ __launch_bounds__(64 * kAdWaves) void k_near_adaptive(
     const int32_t* skel = O.skel;
     const bool far = far_inst[k_inst] != 0;
     double* u = tab_ptrs ? tab_ptrs[k_inst].u : u_single;
+    const bool sorted_out = tab_ptrs && tab_ptrs[k_inst].sorted;   // u indexed by sorted point
     const int32_t tgt0 = tab_ptrs ? tab_ptrs[k_inst].tgt0 : tgt0_single;
     const int32_t t0 = uniform(box_pt0[tau]), t_end = uniform(box_pt1[tau]);
     const int32_t u0 = uniform(L.off[0][tau]), nu = uniform(L.off[0][tau + 1]) - u0;
@@ -1671,7 +1676,7 @@ __global__ __launch_bounds__(64 * kAdWaves) void k_near_adaptive(
         double acc = (a0 + a1) + (a2 + a3);
         for (int o = T; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
         const int32_t pout = perm_local[ii];
-        if (valid && sl == 0 && pout >= tgt0) u[pout - tgt0] = acc;
+        if (valid && sl == 0 && pout >= tgt0) u[sorted_out ? int64_t(ii) : int64_t(pout - tgt0)] = acc;
     }
 }
 

@@ -123,10 +123,14 @@ constexpr int32_t kNearAll = -(1 << 30);
 // instance's points are its sources followed by its targets (the same points when targets =
 // sources).  Point of local index j carries the load f[j] if j < nsrc (else zero), and its
 // potential goes to u[j - tgt0] if j >= tgt0 (else nowhere).
+// Loads and potentials of one instance for an execute: in the caller's order (f[j] for the
+// instance's source j, u[j - tgt0] for its target j), or, with sorted set, indexed by the
+// plan's global Morton-ordered point index (f, u then span every point of the plan).
 struct ExecPtrs {
     const double* f;
     double* u;
     int32_t nsrc, tgt0;
+    int32_t sorted, pad;
 };
 
 enum BoxMatMode { kModeM2M = 1, kModeL2L = 2 };

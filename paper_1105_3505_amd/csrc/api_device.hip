@@ -1348,8 +1348,11 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
 }
 
 // Enqueues the evaluation passes (Section 8.2) on st.  tab = per-instance load/potential
-// pointers on the device, or null with f1/u1 those of the single instance.
-void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double* u1, uint32_t marks, hipStream_t st) {
+// pointers on the device, or null with f1/u1 those of the single instance (in the plan's
+// Morton order when sorted).
+void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double* u1, uint32_t marks, hipStream_t st,
+                    bool sorted = false) {
+    const ExecPtrs single{f1, u1, pl->nsrc[0], pl->tgt0[0], sorted ? 1 : 0, 0};
     const bool mixed = pl->ctx->opt.precision == LFMM_MIXED;
     const bool mixed_bf16 = pl->ctx->opt.precision == LFMM_MIXED_BF16;
     auto mark = [&](int k) {
@@ -1361,7 +1364,7 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
     for (size_t o = 0; o < pl->ops.size(); ++o) {
         const TileRange& r = pl->leaf_of_ops[o];
         launch_p2m(r.t0, r.t0 + r.n, pl->box_pt0, pl->box_pt1, pl->box_key, pl->ops[o]->dev.leaf_side, pl->pts, tab,
-                   f1, pl->nsrc[0], pl->perm, pl->pinst, pl->fs, pl->ops[o]->dev.leafT, pl->Q, st);
+                   single, pl->perm, pl->pinst, pl->fs, pl->ops[o]->dev.leafT, pl->Q, st);
     }
     mark(2);
     for (int h = 1; h <= pl->Hmax; ++h) {
@@ -1405,7 +1408,7 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
     if (pl->adaptive) {
         launch_near_adaptive(pl->n_ad_leaves, pl->ad_leaves, lists, pl->box_pt0, pl->box_pt1, pl->box_key,
                              pl->box_lev, pl->box_inst, pl->d_inst, pl->d_ops, pl->pts, pl->fs, pl->Q, pl->pt_box,
-                             pl->U, pl->perm, tab, u1, pl->tgt0[0], pl->d_far, pl->ctx->phi_oct, pl->ctx->phi_far,
+                             pl->U, pl->perm, tab, single, pl->d_far, pl->ctx->phi_oct, pl->ctx->phi_far,
                              st);
         mark(6);
         return;
@@ -1413,7 +1416,7 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
     for (size_t o = 0; o < pl->ops.size(); ++o) {
         const TileRange& r = pl->near_of_ops[o];
         launch_near(r.t0, r.t0 + r.n, pl->groups, pl->ents, pl->box_pt0, pl->box_pt1, pl->box_key, pl->box_inst,
-                    pl->ops[o]->dev.leaf_side, pl->pts, pl->pkey, pl->fs, pl->perm, tab, u1, pl->tgt0[0], pl->U,
+                    pl->ops[o]->dev.leaf_side, pl->pts, pl->pkey, pl->fs, pl->perm, tab, single, pl->U,
                     pl->ops[o]->dev.leafT, pl->d_far, pl->ctx->phi_oct, pl->ctx->phi_far, st);
     }
     mark(6);
@@ -1426,12 +1429,11 @@ void run_forest(lfmm_plan* pl, const double* const* f, double* const* u, hipStre
         pl->one_stream = false;
         if (pl->built) LFMM_HIP(hipStreamWaitEvent(st, pl->built->ev, 0));
     }
-    if (pl->K == 1 && !pl->use_graph && !sorted) {
-        enqueue_passes(pl, nullptr, f[0], u[0], pl->timing_mask, st);
+    if (pl->K == 1 && !pl->use_graph) {
+        enqueue_passes(pl, nullptr, f[0], u[0], pl->timing_mask, st, sorted);
         if (pl->timing_mask) pl->timed_mask = pl->timing_mask;
         return;
     }
-    if (!pl->h_exec) acquire_exec_staging(pl);   // a single-instance plan's first sorted execute
     std::vector<ExecPtrs> table(static_cast<size_t>(pl->K));
     for (int32_t k = 0; k < pl->K; ++k)
         table[size_t(k)] = ExecPtrs{sorted ? f[0] : f[k], sorted ? u[0] : u[k], pl->nsrc[size_t(k)],

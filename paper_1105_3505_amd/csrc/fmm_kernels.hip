@@ -94,17 +94,12 @@ inline unsigned grid_for(int64_t n, int per_block = kBlock) {
 // Load of sorted point s: in the caller's order, the instance-local index perm_local[s] of
 // instance pinst[s]; with sorted loads, index s itself (coalesced); zero for a point that is a
 // target only.  Also stored at fs[s] for the near field: P2M visits every point once.
-__device__ inline double gather_f(const ExecPtrs* tab, const double* f_single, int32_t nsrc_single,
-                                  const int32_t* perm_local, const int32_t* pinst, int64_t s, double* fs) {
-    const double* f = f_single;
-    int32_t nsrc = nsrc_single;
-    bool sorted = false;
-    if (tab) {
-        const ExecPtrs& e = tab[pinst[s]];
-        f = e.f;
-        nsrc = e.nsrc;
-        sorted = e.sorted != 0;
-    }
+__device__ inline double gather_f(const ExecPtrs* tab, const ExecPtrs& single, const int32_t* perm_local,
+                                  const int32_t* pinst, int64_t s, double* fs) {
+    const ExecPtrs e = tab ? tab[pinst[s]] : single;
+    const double* f = e.f;
+    const int32_t nsrc = e.nsrc;
+    const bool sorted = e.sorted != 0;
     const int32_t j = perm_local[s];
     const double v = j < nsrc ? f[sorted ? s : int64_t(j)] : 0.0;
     fs[s] = v;
@@ -119,8 +114,8 @@ __device__ inline double gather_f(const ExecPtrs* tab, const double* f_single, i
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0,
                                                  const int32_t* box_pt1, const uint64_t* box_key, int64_t side,
-                                                 const int2* pts, const ExecPtrs* tab, const double* f_single,
-                                                 int32_t nsrc_single, const int32_t* perm_local, const int32_t* pinst,
+                                                 const int2* pts, const ExecPtrs* tab, ExecPtrs single,
+                                                 const int32_t* perm_local, const int32_t* pinst,
                                                  double* fs, const double* leafT, double* Q) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int32_t g = leaf0 + int32_t(blockIdx.x) * kWaves + wave;
@@ -137,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_p2m(int32_t leaf0, int32_t leaf1, co
         if (j < p1) {
             const int2 q = pts[j];
             loc = int32_t(int64_t(q.x - cx) + side * int64_t(q.y - cy));
-            f = gather_f(tab, f_single, nsrc_single, perm_local, pinst, j, fs);
+            f = gather_f(tab, single, perm_local, pinst, j, fs);
         }
         const int cnt = min(64, p1 - c0);
         for (int k = 0; k < cnt; k += 4) {   // k + 3 < 64: the tail reads the zero-load lanes
@@ -167,8 +162,8 @@ constexpr int kP2mLeaves = 64 / kP2mGroup;     // leaves per wave and step
 template <int P>
 __global__ __launch_bounds__(kP2mThreads) void k_p2m_lds(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0,
                                                         const int32_t* box_pt1, const uint64_t* box_key, int64_t side,
-                                                        const int2* pts, const ExecPtrs* tab, const double* f_single,
-                                                        int32_t nsrc_single, const int32_t* perm_local,
+                                                        const int2* pts, const ExecPtrs* tab, ExecPtrs single,
+                                                        const int32_t* perm_local,
                                                         const int32_t* pinst, double* fs, const double* leafT,
                                                         double* Q) {
     constexpr int R = P / kP2mGroup;   // rows per lane
@@ -217,7 +212,7 @@ __global__ __launch_bounds__(kP2mThreads) void k_p2m_lds(int32_t leaf0, int32_t 
             if (c0 + l < npt) {
                 const int2 pt = pts[p0 + c0 + l];
                 loc = int32_t(int64_t(pt.x - cx) + side * int64_t(pt.y - cy));
-                f = gather_f(tab, f_single, nsrc_single, perm_local, pinst, p0 + c0 + l, fs);
+                f = gather_f(tab, single, perm_local, pinst, p0 + c0 + l, fs);
             }
             #pragma unroll
             for (int k = 0; k < kP2mGroup; ++k) {
@@ -1063,7 +1058,7 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
                                   int64_t side, int W, const double* tab, const char* tb, uint32_t kofs,
                                   const int2* pts,
                                   const uint32_t* pkey, const double* fs, const int32_t* perm_local,
-                                  const ExecPtrs* tab_ptrs, double* u_single, int32_t tgt0_single, const double* U,
+                                  const ExecPtrs* tab_ptrs, ExecPtrs single, const double* U,
                                   const double* leafT, const uint8_t* far_inst, const double* phi_oct_tab,
                                   const PhiFar* phi_far) {
     const int lane = threadIdx.x & 63;
@@ -1083,9 +1078,10 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
     bnd[nleaf] = t_end;
     const int32_t k_inst = uniform(box_inst[leaf0]);
     const bool far = far_inst[k_inst] != 0;
-    double* u = tab_ptrs ? tab_ptrs[k_inst].u : u_single;
-    const bool sorted_out = tab_ptrs && tab_ptrs[k_inst].sorted;   // u indexed by sorted point
-    const int32_t tgt0 = tab_ptrs ? tab_ptrs[k_inst].tgt0 : tgt0_single;   // first target index
+    const ExecPtrs eio = tab_ptrs ? tab_ptrs[k_inst] : single;
+    double* u = eio.u;
+    const bool sorted_out = eio.sorted != 0;   // u indexed by sorted point
+    const int32_t tgt0 = eio.tgt0;   // first target index
     // passes: the whole group once (group mode) or each leaf in turn (sliced mode)
     for (int c0 = 0; c0 < (SLICED ? nleaf : 1); ++c0) {
         const int32_t p0 = SLICED ? bnd[c0] : bnd[0];
@@ -1215,7 +1211,7 @@ __global__ __launch_bounds__(near_threads(MODE)) void k_near(int32_t q0, int32_t
                                                       const int32_t* box_inst, int64_t side, int W, const int2* pts,
                                                       const uint32_t* pkey, const double* fs,
                                                       const int32_t* perm_local, const ExecPtrs* tab_ptrs,
-                                                      double* u_single, int32_t tgt0_single, const double* U,
+                                                      ExecPtrs single, const double* U,
                                                       const double* leafT, const uint8_t* far_inst,
                                                       const double* phi_oct_tab, const PhiFar* phi_far) {
     constexpr int kNearBlock = near_threads(MODE), kNearWaves = kNearBlock / 64;
@@ -1257,11 +1253,11 @@ __global__ __launch_bounds__(near_threads(MODE)) void k_near(int32_t q0, int32_t
         // leaf otherwise (the octant table in global memory is read faster a leaf at a time)
         if (MODE != kGlobal && nt > 32)
             near_group<P, MODE, false>(qq, groups, ents, box_pt0, box_pt1, box_key, box_inst, side, W, tab, tb, kofs, pts,
-                                       pkey, fs, perm_local, tab_ptrs, u_single, tgt0_single, U, leafT, far_inst,
+                                       pkey, fs, perm_local, tab_ptrs, single, U, leafT, far_inst,
                                        phi_oct_tab, phi_far);
         else
             near_group<P, MODE, true>(qq, groups, ents, box_pt0, box_pt1, box_key, box_inst, side, W, tab, tb, kofs, pts,
-                                      pkey, fs, perm_local, tab_ptrs, u_single, tgt0_single, U, leafT, far_inst,
+                                      pkey, fs, perm_local, tab_ptrs, single, U, leafT, far_inst,
                                       phi_oct_tab, phi_far);
     }
 }
@@ -1336,7 +1332,7 @@ template <int P>
 __global__ __launch_bounds__(64 * kStagedWaves) void k_near_staged(
     int32_t q0, int32_t q1, const NearGroup* groups, const int4* ents, const int32_t* box_pt0, const int32_t* box_pt1,
     const uint64_t* box_key, const int32_t* box_inst, int64_t side, const int2* pts, const double* fs,
-    const int32_t* perm_local, const ExecPtrs* tab_ptrs, double* u_single, int32_t tgt0_single, const double* U,
+    const int32_t* perm_local, const ExecPtrs* tab_ptrs, ExecPtrs single, const double* U,
     const double* leafT, const uint8_t* far_inst, const double* phi_oct_tab) {
     __shared__ int2 s_xy[kStagedWaves][kStageCap];
     __shared__ double s_f[kStagedWaves][kStageCap];
@@ -1354,9 +1350,10 @@ __global__ __launch_bounds__(64 * kStagedWaves) void k_near_staged(
     const int32_t t0 = uniform(box_pt0[leaf0]), t_end = uniform(box_pt1[leaf0 + nleaf - 1]);
     const int32_t k_inst = uniform(box_inst[leaf0]);
     const bool far = far_inst[k_inst] != 0;
-    double* u = tab_ptrs ? tab_ptrs[k_inst].u : u_single;
-    const bool sorted_out = tab_ptrs && tab_ptrs[k_inst].sorted;   // u indexed by sorted point
-    const int32_t tgt0 = tab_ptrs ? tab_ptrs[k_inst].tgt0 : tgt0_single;
+    const ExecPtrs eio = tab_ptrs ? tab_ptrs[k_inst] : single;
+    double* u = eio.u;
+    const bool sorted_out = eio.sorted != 0;   // u indexed by sorted point
+    const int32_t tgt0 = eio.tgt0;
     // first points of the group's leaves, to find each target's leaf
     int32_t bnd1 = t_end, bnd2 = t_end, bnd3 = t_end;
     if (nleaf > 1) bnd1 = uniform(box_pt0[leaf0 + 1]);
@@ -1544,7 +1541,7 @@ __global__ __launch_bounds__(64 * kAdWaves) void k_near_adaptive(
     int32_t nitems, const int32_t* items, AdaptiveLists L, const int32_t* box_pt0, const int32_t* box_pt1,
     const uint64_t* box_key, const int8_t* box_lev, const int32_t* box_inst, const InstInfo* inst,
     const OpsPtrs* ops, const int2* pts, const double* fs, const double* Q, const int32_t* pt_box, const double* U,
-    const int32_t* perm_local, const ExecPtrs* tab_ptrs, double* u_single, int32_t tgt0_single,
+    const int32_t* perm_local, const ExecPtrs* tab_ptrs, ExecPtrs single,
     const uint8_t* far_inst, const double* phi_oct_tab, const PhiFar* phi_far) {
     __shared__ AdWaveLds s_w[kAdWaves];
     const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
@@ -1559,9 +1556,10 @@ __global__ __launch_bounds__(64 * kAdWaves) void k_near_adaptive(
     const double* leafT = O.leafT;
     const int32_t* skel = O.skel;
     const bool far = far_inst[k_inst] != 0;
-    double* u = tab_ptrs ? tab_ptrs[k_inst].u : u_single;
-    const bool sorted_out = tab_ptrs && tab_ptrs[k_inst].sorted;   // u indexed by sorted point
-    const int32_t tgt0 = tab_ptrs ? tab_ptrs[k_inst].tgt0 : tgt0_single;
+    const ExecPtrs eio = tab_ptrs ? tab_ptrs[k_inst] : single;
+    double* u = eio.u;
+    const bool sorted_out = eio.sorted != 0;   // u indexed by sorted point
+    const int32_t tgt0 = eio.tgt0;
     const int32_t t0 = uniform(box_pt0[tau]), t_end = uniform(box_pt1[tau]);
     const int32_t u0 = uniform(L.off[0][tau]), nu = uniform(L.off[0][tau + 1]) - u0;
     const int32_t w0 = uniform(L.off[1][tau]), nw = uniform(L.off[1][tau + 1]) - w0;
@@ -1763,7 +1761,7 @@ P2mDevice p2m_device() {
 }
 
 void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1, const uint64_t* box_key,
-                int64_t side, const int32_t* pts, const ExecPtrs* tab, const double* f_single, int32_t nsrc_single,
+                int64_t side, const int32_t* pts, const ExecPtrs* tab, const ExecPtrs& single,
                 const int32_t* perm_local, const int32_t* pinst, double* fs, const double* leafT, double* Q,
                 hipStream_t st) {
     if (leaf1 <= leaf0) return;
@@ -1775,12 +1773,12 @@ void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int3
         const int64_t want = (int64_t(leaf1 - leaf0) + per_block - 1) / per_block;
         const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(want, int64_t(dv.cus) * per_cu));
         hipLaunchKernelGGL(k_p2m_lds<kRankPad>, dim3(unsigned(grid)), dim3(kP2mThreads), lds, st, leaf0, leaf1,
-                           box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), tab, f_single,
-                           nsrc_single, perm_local, pinst, fs, leafT, Q);
+                           box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), tab, single,
+                           perm_local, pinst, fs, leafT, Q);
         return;
     }
     hipLaunchKernelGGL(k_p2m<kRankPad>, dim3(grid_for(leaf1 - leaf0, kWaves)), dim3(kBlock), 0, st, leaf0, leaf1,
-                       box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), tab, f_single, nsrc_single,
+                       box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), tab, single,
                        perm_local, pinst, fs, leafT, Q);
 }
 
@@ -1854,7 +1852,7 @@ void launch_m2l_bf16(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t ma
 void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* ents, const int32_t* box_pt0,
                  const int32_t* box_pt1, const uint64_t* box_key, const int32_t* box_inst, int64_t side,
                  const int32_t* pts, const uint32_t* pkey, const double* fs, const int32_t* perm_local,
-                 const ExecPtrs* tab, double* u_single, int32_t tgt0_single, const double* U, const double* leafT,
+                 const ExecPtrs* tab, const ExecPtrs& single, const double* U, const double* leafT,
                  const uint8_t* far_inst, const double* phi_oct, const PhiFar* phi_far, hipStream_t st) {
     if (q1 <= q0) return;
     // with an LDS table: persistent blocks, as many as fit on the device at once, so that
@@ -1878,7 +1876,7 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
         constexpr int nt = near_threads(kWindow);
         const unsigned g = grid(reinterpret_cast<const void*>(&k_near<kRankPad, kWindow>), nt, lds, true);
         hipLaunchKernelGGL((k_near<kRankPad, kWindow>), dim3(g), dim3(nt), lds, st, q0, q1, groups, ents,
-                           box_pt0, box_pt1, box_key, box_inst, side, W, p2, pkey, fs, perm_local, tab, u_single, tgt0_single, U,
+                           box_pt0, box_pt1, box_key, box_inst, side, W, p2, pkey, fs, perm_local, tab, single, U,
                            leafT, far_inst, phi_oct, phi_far);
     } else if (side <= 32) {
         const int W = int(2 * side);
@@ -1887,14 +1885,14 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
         constexpr int nt = near_threads(kQuad);
         const unsigned g = grid(reinterpret_cast<const void*>(&k_near<kRankPad, kQuad>), nt, lds, true);
         hipLaunchKernelGGL((k_near<kRankPad, kQuad>), dim3(g), dim3(nt), lds, st, q0, q1, groups, ents,
-                           box_pt0, box_pt1, box_key, box_inst, side, W, p2, pkey, fs, perm_local, tab, u_single, tgt0_single, U,
+                           box_pt0, box_pt1, box_key, box_inst, side, W, p2, pkey, fs, perm_local, tab, single, U,
                            leafT, far_inst, phi_oct, phi_far);
     } else {
         // every near offset (at most 2 side - 1 <= 255) lies inside the device octant table
         if (2 * side - 1 > kPhiDeviceRadius) throw std::logic_error("leaf wider than the near-field table allows");
         const unsigned g = unsigned((q1 - q0 + kStagedWaves - 1) / kStagedWaves);
         hipLaunchKernelGGL(k_near_staged<kRankPad>, dim3(g), dim3(64 * kStagedWaves), 0, st, q0, q1, groups, ents,
-                           box_pt0, box_pt1, box_key, box_inst, side, p2, fs, perm_local, tab, u_single, tgt0_single,
+                           box_pt0, box_pt1, box_key, box_inst, side, p2, fs, perm_local, tab, single,
                            U, leafT, far_inst, phi_oct);
     }
 }
@@ -1926,13 +1924,13 @@ void launch_near_adaptive(int32_t nitems, const int32_t* items, const AdaptiveLi
                           const int32_t* box_pt1, const uint64_t* box_key, const int8_t* box_lev,
                           const int32_t* box_inst, const InstInfo* inst, const OpsPtrs* ops, const int32_t* pts,
                           const double* fs, const double* Q, const int32_t* pt_box, const double* U,
-                          const int32_t* perm_local, const ExecPtrs* tab, double* u_single, int32_t tgt0_single,
+                          const int32_t* perm_local, const ExecPtrs* tab, const ExecPtrs& single,
                           const uint8_t* far_inst, const double* phi_oct, const PhiFar* phi_far, hipStream_t st) {
     if (nitems <= 0) return;
     const unsigned g = unsigned((nitems + kAdWaves - 1) / kAdWaves);
     hipLaunchKernelGGL(k_near_adaptive<kRankPad>, dim3(g), dim3(64 * kAdWaves), 0, st, nitems, items, lists, box_pt0,
                        box_pt1, box_key, box_lev, box_inst, inst, ops, reinterpret_cast<const int2*>(pts), fs, Q,
-                       pt_box, U, perm_local, tab, u_single, tgt0_single, far_inst, phi_oct, phi_far);
+                       pt_box, U, perm_local, tab, single, far_inst, phi_oct, phi_far);
 }
 
 void launch_direct(int64_t nt, const int32_t* txy, int64_t ns, const int32_t* sxy, const double* f,

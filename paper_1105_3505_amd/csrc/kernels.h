@@ -268,12 +268,12 @@ void launch_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, const in
                         hipStream_t st);
 
 // ---- evaluation passes (fmm_kernels.hip) ---------------------------------------------------
-// P2M of the leaves [leaf0, leaf1); reads the caller-order loads (tab per instance, or
-// f_single) through perm_local / pinst and also stores them in Morton order at fs
-// (tab null: the single instance's loads f_single, of which the first nsrc_single are real)
+// P2M of the leaves [leaf0, leaf1); reads the loads (tab per instance, or single for a
+// single-instance plan when tab is null) in the caller's order through perm_local / pinst, or
+// in Morton order when the entry is sorted, and stores them in Morton order at fs
 void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1,
                 const uint64_t* box_key, int64_t side, const int32_t* pts, const ExecPtrs* tab,
-                const double* f_single, int32_t nsrc_single, const int32_t* perm_local, const int32_t* pinst,
+                const ExecPtrs& single, const int32_t* perm_local, const int32_t* pinst,
                 double* fs, const double* leafT, double* Q, hipStream_t st);
 // M2M over the consecutive-box tiles of one height (Q row zrow is all zeros)
 void launch_m2m(const BoxTile* tiles, int32_t ntiles, const int32_t* box_child, const OpsPtrs* ops, double* Q,
@@ -300,7 +300,7 @@ void launch_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t m
 void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* ents, const int32_t* box_pt0,
                  const int32_t* box_pt1, const uint64_t* box_key, const int32_t* box_inst, int64_t side,
                  const int32_t* pts, const uint32_t* pkey, const double* fs, const int32_t* perm_local,
-                 const ExecPtrs* tab, double* u_single, int32_t tgt0_single, const double* U, const double* leafT,
+                 const ExecPtrs* tab, const ExecPtrs& single, const double* U, const double* leafT,
                  const uint8_t* far_inst, const double* phi_oct, const PhiFar* phi_far, hipStream_t st);
 // Adaptive tree passes.  P2L (X lists): u-hat of box tau += phi(skeleton of tau - x_j) f_j over
 // the points of its X leaves, for the nx boxes xitems.  Near field of the adaptive leaves
@@ -314,7 +314,7 @@ void launch_near_adaptive(int32_t nitems, const int32_t* items, const AdaptiveLi
                           const int32_t* box_pt1, const uint64_t* box_key, const int8_t* box_lev,
                           const int32_t* box_inst, const InstInfo* inst, const OpsPtrs* ops, const int32_t* pts,
                           const double* fs, const double* Q, const int32_t* pt_box, const double* U,
-                          const int32_t* perm_local, const ExecPtrs* tab, double* u_single, int32_t tgt0_single,
+                          const int32_t* perm_local, const ExecPtrs* tab, const ExecPtrs& single,
                           const uint8_t* far_inst, const double* phi_oct, const PhiFar* phi_far, hipStream_t st);
 // Radius of the device phi table: the host's quadrature table (radius 128) followed by the
 // far-field expansion for the octant entries up to this radius, filled by

@@ -528,13 +528,14 @@ __global__ __launch_bounds__(kBlock, 3) void k_m2l(const BoxTile* tiles, const i
             const int32_t box = c ? box1 : box0;
             if (box >= 0) {
                 double* ob = U + size_t(box) * P;
-                // streaming stores: the incoming expansions are read by later passes only, and
-                // in L2 they would evict source expansions that other tiles still gather
+                // plain stores: streaming (non-temporal) ones were measured to leave the time
+                // unchanged and to send these 8-byte pieces to memory uncombined (2.4x the
+                // written bytes)
                 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    __builtin_nontemporal_store(acc[c][0][i], ob + g + 4 * i);
-                    __builtin_nontemporal_store(acc[c][1][i], ob + 16 + g + 4 * i);
-                    __builtin_nontemporal_store(acc[c][2][i], ob + 32 + g + 4 * i);
+                    ob[g + 4 * i] = acc[c][0][i];
+                    ob[16 + g + 4 * i] = acc[c][1][i];
+                    ob[32 + g + 4 * i] = acc[c][2][i];
                 }
             }
         }
@@ -821,27 +822,46 @@ __device__ inline double bf16_val(uint32_t b) { return double(__uint_as_float(b 
 
 // q-hat in three bf16 parts (row of a box: part p holds entries p * 48 .. p * 48 + 47) and its
 // FP64 charge sum, for boxes [0, nrows) (the all-zero row included); each remainder is exact.
+// Eight lanes per box, lane g < 6 taking entries 8 g .. 8 g + 7 (one 64-byte read, one 16-byte
+// write per part); the charge sum adds the six lanes' partial sums in a fixed order.
 __global__ void k_split_q_bf16(const double* Q, int32_t nrows, uint16_t* Qb, double* qs) {
     constexpr int P = kRankPad;
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t box = t / 64;
-    const int lane = int(t & 63);
-    if (box >= nrows) return;   // uniform over the wave: a wave is one box
-    const double q = lane < P ? Q[box * P + lane] : 0.0;
-    if (lane < P) {
-        uint16_t* row = Qb + box * (3 * P);
-        double r = q;
+    const int64_t box = t >> 3;
+    const int g = int(t & 7);
+    if (box >= nrows) return;   // uniform over each 8-lane group
+    double part_sum = 0.0;
+    if (g < P / 8) {
+        const double2* src = reinterpret_cast<const double2*>(Q + box * P + 8 * g);
+        double q[8];
         #pragma unroll
-        for (int part = 0; part < 3; ++part) {
-            const uint32_t b = bf16_bits(r);
-            row[part * P + lane] = uint16_t(b);
-            r -= bf16_val(b);
+        for (int e = 0; e < 4; ++e) {
+            const double2 v = src[e];
+            q[2 * e] = v.x;
+            q[2 * e + 1] = v.y;
         }
+        uint32_t bits[3][4];
+        #pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            part_sum += q[e];
+            double r = q[e];
+            #pragma unroll
+            for (int part = 0; part < 3; ++part) {
+                const uint32_t b = bf16_bits(r);
+                r -= bf16_val(b);
+                if (e & 1) bits[part][e >> 1] |= b << 16;
+                else bits[part][e >> 1] = b;
+            }
+        }
+        uint4* row = reinterpret_cast<uint4*>(Qb + box * (3 * P));
+        #pragma unroll
+        for (int part = 0; part < 3; ++part)
+            row[part * (P / 8) + g] = make_uint4(bits[part][0], bits[part][1], bits[part][2], bits[part][3]);
     }
-    double s = q;
-    #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) qs[box] = s;
+    part_sum += __shfl_xor(part_sum, 1, 64);
+    part_sum += __shfl_xor(part_sum, 2, 64);
+    part_sum += __shfl_xor(part_sum, 4, 64);
+    if (g == 0) qs[box] = part_sum;
 }
 
 // M2L on the bf16 matrix cores, on the same 128-box tiles as k_m2l: eight waves per tile, wave w
@@ -1836,7 +1856,7 @@ void launch_m2l_mixed(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t m
 
 void launch_split_q_bf16(const double* Q, int32_t nrows, uint16_t* Qb, double* qs, hipStream_t st) {
     if (nrows <= 0) return;
-    hipLaunchKernelGGL(k_split_q_bf16, dim3(grid_for(int64_t(nrows) * 64)), dim3(kBlock), 0, st, Q, nrows, Qb, qs);
+    hipLaunchKernelGGL(k_split_q_bf16, dim3(grid_for(int64_t(nrows) * 8)), dim3(kBlock), 0, st, Q, nrows, Qb, qs);
 }
 
 void launch_m2l_bf16(const BoxTile* tiles, const int32_t* ntiles_dev, int32_t max_tiles, const int32_t* box_list,

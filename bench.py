@@ -368,7 +368,13 @@ def run_batched(args, torch, lf):
     n = sum(len(a) for a, _ in inst)
     xs = [torch.from_numpy(a).cuda() for a, _ in inst]
     fs = [torch.from_numpy(b).cuda() for _, b in inst]
-    ctx = lf.Context(0, precision=args.precision, max_leaf=args.max_leaf)
+    ctx = lf.Context(0, precision=args.precision, max_leaf=0 if args.autotune else args.max_leaf)
+    tuned = None
+    if args.autotune:
+        # one N_leaf for the whole forest, timed on the forest (lfmm_autotune_batch), recorded
+        # for every instance's size class; the timed plans then take it in automatic mode
+        best, times = ctx.autotune_batch(xs, candidates=(16, 32, 64, 128), objective="execute", reps=2)
+        tuned = {"max_leaf": best, "execute_ms": {str(c): round(t, 4) for c, t in times.items()}}
     streams = streams_for(args.inflight, torch)
     outs = [[torch.empty_like(b) for b in fs] for _ in streams]
 
@@ -402,9 +408,12 @@ def run_batched(args, torch, lf):
     plan.close()
     ctx.close()
     config = {"workload": WORKLOADS["batched"], "n_instances": len(inst), "n_sources": n,
-              "precision": args.precision, "max_leaf": args.max_leaf, "rank": RANK, "eps": 1e-12}
+              "precision": args.precision, "max_leaf": "autotuned (%d)" % tuned["max_leaf"] if tuned else args.max_leaf,
+              "rank": RANK, "eps": 1e-12}
     result = base_result(args, n / (ms_per_step * 1e-3) / 1e6, ms_per_step, config)
     result.update(timing_fields(m, n, args.inflight))
+    if tuned:
+        result["autotuned_max_leaf"] = tuned
     result.update({"inflight_outputs_equal": same,
                    "execute_only_ms": exec_ms, "execute_only_msources_per_s": n / (exec_ms * 1e-3) / 1e6,
                    "plan": info,
@@ -701,6 +710,8 @@ def main() -> None:
                          "N_leaf points); default adaptive for clusters, uniform otherwise")
     ap.add_argument("--stencil", type=int, default=5, choices=(5, 9),
                     help="lattice operator: the 5-point Laplacian of the paper or the isotropic 9-point one")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batched: N_leaf chosen by lfmm_autotune_batch on the whole forest before the timed steps")
     ap.add_argument("--io", choices=("caller", "sorted"), default="caller",
                     help="single-plan workloads: loads and potentials in the caller's order (lfmm_execute) or "
                          "in the plan's Morton order (lfmm_execute_sorted)")

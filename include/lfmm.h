@@ -239,6 +239,17 @@ lfmm_status lfmm_autotune(lfmm_ctx* ctx, int64_t n, const int32_t* xy_dev, int32
                           const int32_t* cand_host, int32_t objective, int32_t reps, void* stream,
                           int32_t* best_host, double* ms_host);
 
+/* lfmm_autotune for a plan of several instances (lfmm_plan_create_batch): every candidate is
+ * applied to all n_inst instances at once (n_host[k] points at xy_dev[k], host arrays of
+ * device pointers) and the whole plan is timed, so the choice accounts for the launches the
+ * instances share (instances of mixed N_leaf split them into more, smaller groups).  The
+ * fastest candidate is recorded for the size and density class of every instance, where a
+ * context in automatic mode (max_leaf 0) finds it when it builds such instances again. */
+lfmm_status lfmm_autotune_batch(lfmm_ctx* ctx, int32_t n_inst, const int64_t* n_host,
+                                const int32_t* const* xy_dev, int32_t n_cand, const int32_t* cand_host,
+                                int32_t objective, int32_t reps, void* stream, int32_t* best_host,
+                                double* ms_host);
+
 /* Phases of lfmm_execute, in launch order, for lfmm_plan_phase_times. */
 typedef enum lfmm_phase {
     LFMM_PHASE_GATHER = 0,    /* loads into Morton order (empty: P2M gathers them)         */

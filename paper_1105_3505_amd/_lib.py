@@ -95,6 +95,7 @@ def _load():
         "lfmm_execute_batch": [_vp, _i32, _vp, _vp, _vp, _vp],
         "lfmm_plan_get_info": [_vp, _vp],
         "lfmm_autotune": [_vp, _i64, _vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp],
+        "lfmm_autotune_batch": [_vp, _i32, _vp, _vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp],
         "lfmm_plan_set_timing": [_vp, _i32],
         "lfmm_plan_set_timing_phases": [_vp, ctypes.c_uint32],
         "lfmm_plan_export": [_vp, _i32, _vp, _vp],
@@ -356,6 +357,23 @@ class Context:
         _check(_lib.lfmm_autotune(self._h, int(xy.shape[0]), _dev_tensor(xy, torch.int32, (2,), "xy"), len(cand),
                                   cand.ctypes.data_as(_vp), obj, int(reps), _stream_handle(stream),
                                   ctypes.byref(best), ms.ctypes.data_as(_vp)))
+        return int(best.value), dict(zip([int(c) for c in cand], [float(v) for v in ms]))
+
+    def autotune_batch(self, xys, candidates=(16, 32, 64, 128), objective="execute", reps=3, stream=None):
+        """lfmm_autotune_batch: the fastest N_leaf among `candidates` for a plan of all the point
+        sets `xys` (each candidate applied to every instance); recorded for the size and density
+        class of each instance.  Returns (best, {candidate: ms})."""
+        import torch
+        k = len(xys)
+        ptrs = (ctypes.c_void_p * k)(*[_dev_tensor(xy, torch.int32, (2,), "xy").value for xy in xys])
+        sizes = np.ascontiguousarray([int(xy.shape[0]) for xy in xys], dtype=np.int64)
+        cand = np.ascontiguousarray(candidates, dtype=np.int32)
+        ms = np.zeros(len(cand), dtype=np.float64)
+        best = ctypes.c_int32()
+        obj = {"solve": 0, "execute": 1}[objective]
+        _check(_lib.lfmm_autotune_batch(self._h, k, sizes.ctypes.data_as(_vp), ptrs, len(cand),
+                                        cand.ctypes.data_as(_vp), obj, int(reps), _stream_handle(stream),
+                                        ctypes.byref(best), ms.ctypes.data_as(_vp)))
         return int(best.value), dict(zip([int(c) for c in cand], [float(v) for v in ms]))
 
     def footprint_bytes(self, n_src: int, n_tgt: int = 0, root_bits: int = -1) -> int:

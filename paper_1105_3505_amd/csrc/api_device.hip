@@ -1729,16 +1729,15 @@ lfmm_status lfmm_plan_create_batch(lfmm_ctx* ctx, int32_t n_inst, const int64_t*
     return create_forest(ctx, n_inst, in.data(), 0, stream, out);
 }
 
-lfmm_status lfmm_autotune(lfmm_ctx* ctx, int64_t n, const int32_t* xy, int32_t n_cand, const int32_t* cand,
-                          int32_t objective, int32_t reps, void* stream, int32_t* best, double* ms) {
-    if (!ctx || !xy || !cand || !best || n_cand < 1 || reps < 1 || (objective != 0 && objective != 1))
-        return fail(LFMM_E_INVAL, "bad argument");
-    if (n < 1 || n > (int64_t(1) << 30)) return fail(LFMM_E_INVAL, "n must lie in [1, 2^30]");
-    for (int32_t c = 0; c < n_cand; ++c)
-        if (cand[c] < 1 || cand[c] > 4096) return fail(LFMM_E_INVAL, "candidates must lie in [1, 4096]");
+// Times every candidate N_leaf on the K point sets in[] (one plan holding all of them, every
+// instance with that N_leaf) and records the fastest for the size and density class of each.
+static lfmm_status autotune_forest(lfmm_ctx* ctx, int32_t K, const InstanceInput* in, int32_t n_cand, const int32_t* cand,
+                                   int32_t objective, int32_t reps, void* stream, int32_t* best, double* ms) {
     return guarded([&]() -> lfmm_status {
         LFMM_HIP(hipSetDevice(ctx->device));
         hipStream_t st = as_stream(stream);
+        int64_t n = 0;
+        for (int32_t k = 0; k < K; ++k) n += in[k].n_src;
         Arena io(&ctx->pool);
         io.reserve(size_t(n) * sizeof(double));
         io.reserve(size_t(n) * sizeof(double));
@@ -1746,6 +1745,12 @@ lfmm_status lfmm_autotune(lfmm_ctx* ctx, int64_t n, const int32_t* xy, int32_t n
         double* f = io.take<double>(size_t(n));
         double* u = io.take<double>(size_t(n));
         LFMM_HIP(hipMemsetAsync(f, 0, size_t(n) * sizeof(double), st));
+        std::vector<const double*> fa(static_cast<size_t>(K));
+        std::vector<double*> ua(static_cast<size_t>(K));
+        for (int32_t k = 0, off = 0; k < K; off += int32_t(in[k].n_src), ++k) {
+            fa[size_t(k)] = f + off;
+            ua[size_t(k)] = u + off;
+        }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         LFMM_HIP(hipEventCreate(&e0));
         LFMM_HIP(hipEventCreate(&e1));
@@ -1756,11 +1761,8 @@ lfmm_status lfmm_autotune(lfmm_ctx* ctx, int64_t n, const int32_t* xy, int32_t n
                 (void)hipEventDestroy(b);
             }
         } guard{e0, e1};
-        InstanceInput one;
-        one.n_src = n;
-        one.src = xy;
         double best_ms = 0.0;
-        int D = 0;
+        std::vector<std::pair<int, int>> keys;
         for (int32_t c = 0; c < n_cand; ++c) {
             double total = 0.0;
             for (int r = 0; r < reps + 1; ++r) {   // the first round warms the operator cache
@@ -1768,14 +1770,15 @@ lfmm_status lfmm_autotune(lfmm_ctx* ctx, int64_t n, const int32_t* xy, int32_t n
                 const auto t0 = std::chrono::steady_clock::now();
                 auto pl = std::make_unique<lfmm_plan>();
                 pl->ctx = ctx;
-                build_forest(pl.get(), 1, &one, cand[c], st);
+                build_forest(pl.get(), K, in, cand[c], st);
                 const double build_ms =
                     std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-                D = pl->inst[0].D;
-                const double* fa[1] = {f};
-                double* ua[1] = {u};
+                if (keys.empty())
+                    for (int32_t k = 0; k < K; ++k)
+                        keys.push_back(tune_key(pl->inst[size_t(k)].pt1 - pl->inst[size_t(k)].pt0,
+                                                pl->inst[size_t(k)].D));
                 LFMM_HIP(hipEventRecord(e0, st));
-                run_forest(pl.get(), fa, ua, st);
+                run_forest(pl.get(), fa.data(), ua.data(), st);
                 LFMM_HIP(hipEventRecord(e1, st));
                 LFMM_HIP(hipEventSynchronize(e1));
                 float exec_ms = 0.f;
@@ -1791,11 +1794,48 @@ lfmm_status lfmm_autotune(lfmm_ctx* ctx, int64_t n, const int32_t* xy, int32_t n
         }
         {
             std::lock_guard<std::mutex> lock(ctx->mu);
-            ctx->tuned[tune_key(n, D)] = *best;
+            for (const auto& key : keys) ctx->tuned[key] = *best;
         }
         LFMM_HIP(hipStreamSynchronize(st));
         return LFMM_OK;
     });
+}
+
+static lfmm_status check_tune_args(int32_t n_cand, const int32_t* cand, int32_t objective, int32_t reps) {
+    if (!cand || n_cand < 1 || reps < 1 || (objective != 0 && objective != 1)) return fail(LFMM_E_INVAL, "bad argument");
+    for (int32_t c = 0; c < n_cand; ++c)
+        if (cand[c] < 1 || cand[c] > 4096) return fail(LFMM_E_INVAL, "candidates must lie in [1, 4096]");
+    return LFMM_OK;
+}
+
+lfmm_status lfmm_autotune(lfmm_ctx* ctx, int64_t n, const int32_t* xy, int32_t n_cand, const int32_t* cand,
+                          int32_t objective, int32_t reps, void* stream, int32_t* best, double* ms) {
+    if (!ctx || !xy || !best) return fail(LFMM_E_INVAL, "bad argument");
+    const lfmm_status s = check_tune_args(n_cand, cand, objective, reps);
+    if (s != LFMM_OK) return s;
+    if (n < 1 || n > (int64_t(1) << 30)) return fail(LFMM_E_INVAL, "n must lie in [1, 2^30]");
+    InstanceInput one;
+    one.n_src = n;
+    one.src = xy;
+    return autotune_forest(ctx, 1, &one, n_cand, cand, objective, reps, stream, best, ms);
+}
+
+lfmm_status lfmm_autotune_batch(lfmm_ctx* ctx, int32_t n_inst, const int64_t* n_host, const int32_t* const* xy_dev,
+                                int32_t n_cand, const int32_t* cand, int32_t objective, int32_t reps, void* stream,
+                                int32_t* best, double* ms) {
+    if (!ctx || !n_host || !xy_dev || !best || n_inst < 1) return fail(LFMM_E_INVAL, "bad argument");
+    const lfmm_status s = check_tune_args(n_cand, cand, objective, reps);
+    if (s != LFMM_OK) return s;
+    std::vector<InstanceInput> in(static_cast<size_t>(n_inst));
+    int64_t total = 0;
+    for (int32_t k = 0; k < n_inst; ++k) {
+        if (!xy_dev[k] || n_host[k] < 1) return fail(LFMM_E_INVAL, "every instance needs points");
+        in[size_t(k)].n_src = n_host[k];
+        in[size_t(k)].src = xy_dev[k];
+        total += n_host[k];
+    }
+    if (total > (int64_t(1) << 30)) return fail(LFMM_E_INVAL, "at most 2^30 points in all");
+    return autotune_forest(ctx, n_inst, in.data(), n_cand, cand, objective, reps, stream, best, ms);
 }
 
 lfmm_status lfmm_execute(lfmm_plan* pl, const double* f, double* u, void* stream) {

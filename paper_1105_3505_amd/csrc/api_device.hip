@@ -1364,7 +1364,8 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
     for (size_t o = 0; o < pl->ops.size(); ++o) {
         const TileRange& r = pl->leaf_of_ops[o];
         launch_p2m(r.t0, r.t0 + r.n, pl->box_pt0, pl->box_pt1, pl->box_key, pl->ops[o]->dev.leaf_side, pl->pts, tab,
-                   single, pl->perm, pl->pinst, pl->fs, pl->ops[o]->dev.leafT, pl->Q, st);
+                   single, pl->perm, pl->pinst, pl->fs, pl->ops[o]->dev.leafT, pl->Q,
+                   double(pl->n) / double(std::max<int32_t>(pl->nleaf, 1)), st);
     }
     mark(2);
     for (int h = 1; h <= pl->Hmax; ++h) {

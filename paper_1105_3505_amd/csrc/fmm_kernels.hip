@@ -158,8 +158,14 @@ __global__ __launch_bounds__(kBlock) void k_p2m(int32_t leaf0, int32_t leaf1, co
 constexpr int kP2mThreads = 1024;
 constexpr int kP2mGroup = 8;                   // lanes per leaf
 constexpr int kP2mLeaves = 64 / kP2mGroup;     // leaves per wave and step
+// leaves with T_ofs too large for LDS take the grouped kernel (global T_ofs) when they hold
+// at most this many points on average, else one wave each
+constexpr int kP2mSparsePoints = 16;
 
-template <int P>
+// STAGED false: the same grouping for leaves whose T_ofs is too large for LDS but that hold few
+// points each (the sparse leaves of clustered inputs): the operator rows come from global memory
+// (L2-resident), eight lanes reading one 384-byte row together.
+template <int P, bool STAGED = true>
 __global__ __launch_bounds__(kP2mThreads) void k_p2m_lds(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0,
                                                         const int32_t* box_pt1, const uint64_t* box_key, int64_t side,
                                                         const int2* pts, const ExecPtrs* tab, ExecPtrs single,
@@ -168,13 +174,14 @@ __global__ __launch_bounds__(kP2mThreads) void k_p2m_lds(int32_t leaf0, int32_t 
                                                         double* Q) {
     constexpr int R = P / kP2mGroup;   // rows per lane
     static_assert(P % kP2mGroup == 0, "rows split evenly over a group");
-    extern __shared__ double sT[];
+    extern __shared__ double sT_lds[];
     const int ncell = int(side * side);
-    {
+    if (STAGED) {
         const double2* src = reinterpret_cast<const double2*>(leafT);
-        double2* dst = reinterpret_cast<double2*>(sT);
+        double2* dst = reinterpret_cast<double2*>(sT_lds);
         for (int i = int(threadIdx.x); i < ncell * P / 2; i += kP2mThreads) dst[i] = src[i];
     }
+    const double* sT = STAGED ? sT_lds : leafT;
     const int wave = int(threadIdx.x) >> 6, lane = int(threadIdx.x) & 63, l = lane % kP2mGroup;
     const int grp = lane / kP2mGroup;
     const int32_t nleaf = leaf1 - leaf0;
@@ -1783,7 +1790,7 @@ P2mDevice p2m_device() {
 void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1, const uint64_t* box_key,
                 int64_t side, const int32_t* pts, const ExecPtrs* tab, const ExecPtrs& single,
                 const int32_t* perm_local, const int32_t* pinst, double* fs, const double* leafT, double* Q,
-                hipStream_t st) {
+                double avg_pts, hipStream_t st) {
     if (leaf1 <= leaf0) return;
     const size_t lds = size_t(side * side) * kRankPad * sizeof(double);
     const P2mDevice dv = p2m_device();
@@ -1793,6 +1800,15 @@ void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int3
         const int64_t want = (int64_t(leaf1 - leaf0) + per_block - 1) / per_block;
         const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(want, int64_t(dv.cus) * per_cu));
         hipLaunchKernelGGL(k_p2m_lds<kRankPad>, dim3(unsigned(grid)), dim3(kP2mThreads), lds, st, leaf0, leaf1,
+                           box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), tab, single,
+                           perm_local, pinst, fs, leafT, Q);
+        return;
+    }
+    if (avg_pts <= double(kP2mSparsePoints)) {
+        // few points per leaf: eight leaves per wave, T_ofs rows from global memory
+        const int64_t per_block = (kP2mThreads / 64) * kP2mLeaves;
+        const int64_t grid = std::max<int64_t>(1, (int64_t(leaf1 - leaf0) + per_block - 1) / per_block);
+        hipLaunchKernelGGL((k_p2m_lds<kRankPad, false>), dim3(unsigned(grid)), dim3(kP2mThreads), 0, st, leaf0, leaf1,
                            box_pt0, box_pt1, box_key, side, reinterpret_cast<const int2*>(pts), tab, single,
                            perm_local, pinst, fs, leafT, Q);
         return;

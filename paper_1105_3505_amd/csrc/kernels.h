@@ -270,11 +270,12 @@ void launch_near_groups(int32_t q0, int32_t h1_start, int32_t h1_count, const in
 // ---- evaluation passes (fmm_kernels.hip) ---------------------------------------------------
 // P2M of the leaves [leaf0, leaf1); reads the loads (tab per instance, or single for a
 // single-instance plan when tab is null) in the caller's order through perm_local / pinst, or
-// in Morton order when the entry is sorted, and stores them in Morton order at fs
+// in Morton order when the entry is sorted, and stores them in Morton order at fs; avg_pts,
+// the average number of points per leaf, picks the kernel for leaves too wide for LDS
 void launch_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0, const int32_t* box_pt1,
                 const uint64_t* box_key, int64_t side, const int32_t* pts, const ExecPtrs* tab,
                 const ExecPtrs& single, const int32_t* perm_local, const int32_t* pinst,
-                double* fs, const double* leafT, double* Q, hipStream_t st);
+                double* fs, const double* leafT, double* Q, double avg_pts, hipStream_t st);
 // M2M over the consecutive-box tiles of one height (Q row zrow is all zeros)
 void launch_m2m(const BoxTile* tiles, int32_t ntiles, const int32_t* box_child, const OpsPtrs* ops, double* Q,
                 int32_t zrow, hipStream_t st);

@@ -110,7 +110,9 @@ __device__ inline double gather_f(const ExecPtrs* tab, const ExecPtrs& single, c
 // wave per leaf, lane p < P accumulating entry p.  The leaf's points are loaded once, one
 // per lane (coalesced), and handed to all lanes by shuffles, so the only memory reads in the
 // loop are the operator rows, whose addresses are known in advance and can be in flight
-// together.
+// together.  Each entry is one sum over the leaf's points in order, as in k_p2m_lds: which of
+// the two kernels a launch takes depends on the plan (the mean points per leaf), so a leaf must
+// get the same bits from both for an instance alone and in a forest to agree.
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_p2m(int32_t leaf0, int32_t leaf1, const int32_t* box_pt0,
                                                  const int32_t* box_pt1, const uint64_t* box_key, int64_t side,
@@ -124,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_p2m(int32_t leaf0, int32_t leaf1, co
     const uint64_t key = box_key[g];
     const int32_t cx = int32_t(compact_bits(key) * side), cy = int32_t(compact_bits(key >> 1) * side);
     const int l = lane < P ? lane : 0;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double a = 0.0;
     for (int32_t c0 = p0; c0 < p1; c0 += 64) {
         const int32_t j = c0 + lane;
         int32_t loc = 0;   // lanes past the leaf's points carry a zero load at cell 0
@@ -140,13 +142,16 @@ __global__ __launch_bounds__(kBlock) void k_p2m(int32_t leaf0, int32_t leaf1, co
             const int32_t l2 = __shfl(loc, k + 2, 64), l3 = __shfl(loc, k + 3, 64);
             const double f0 = __shfl(f, k, 64), f1 = __shfl(f, k + 1, 64);
             const double f2 = __shfl(f, k + 2, 64), f3 = __shfl(f, k + 3, 64);
-            a0 += leafT[int64_t(l0) * P + l] * f0;
-            a1 += leafT[int64_t(l1) * P + l] * f1;
-            a2 += leafT[int64_t(l2) * P + l] * f2;
-            a3 += leafT[int64_t(l3) * P + l] * f3;
+            // the four rows are loaded together; the sum takes them in point order
+            const double t0 = leafT[int64_t(l0) * P + l], t1 = leafT[int64_t(l1) * P + l];
+            const double t2 = leafT[int64_t(l2) * P + l], t3 = leafT[int64_t(l3) * P + l];
+            a += t0 * f0;
+            a += t1 * f1;
+            a += t2 * f2;
+            a += t3 * f3;
         }
     }
-    if (lane < P) Q[size_t(g) * P + lane] = (a0 + a1) + (a2 + a3);
+    if (lane < P) Q[size_t(g) * P + lane] = a;
 }
 
 // P2M with the leaf operator staged in LDS (leaf sides whose T_ofs fits: side^2 P doubles):

@@ -470,6 +470,9 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st, bool l
     std::vector<double> leafT(size_t(s2) * P, 0.0);
     for (int64_t c = 0; c < s2; ++c)
         for (int p = 0; p < H.level[0].rank; ++p) leafT[size_t(c) * P + p] = H.leaf.T(p, int(c));
+    std::vector<double> leafTt(side <= 32 ? leafT.size() : 0);
+    for (int64_t c = 0; c < s2 && !leafTt.empty(); ++c)
+        for (int p = 0; p < P; ++p) leafTt[(size_t(p / 2) * size_t(s2) + size_t(c)) * 2 + (p & 1)] = leafT[size_t(c) * P + p];
     std::vector<double> ofo_cm(size_t(nlev) * 4 * P * P, 0.0), ofo_rm(size_t(nlev) * 4 * P * P, 0.0);
     for (int h = 1; h < nlev; ++h)
         for (int c = 0; c < 4; ++c) {
@@ -497,6 +500,7 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st, bool l
             }
     }
     co->mem.reserve(leafT.size() * sizeof(double));
+    if (!leafTt.empty()) co->mem.reserve(leafTt.size() * sizeof(double));
     co->mem.reserve(ofo_cm.size() * sizeof(double));
     co->mem.reserve(ofo_rm.size() * sizeof(double));
     co->mem.reserve(ifo.size() * sizeof(double));
@@ -600,6 +604,7 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st, bool l
     co->dev.leaf_side = side;
     co->dev.nlev = nlev;
     co->dev.leafT = co->mem.take<double>(leafT.size());
+    co->dev.leafTt = leafTt.empty() ? nullptr : co->mem.take<double>(leafTt.size());
     co->dev.ofo_cm = co->mem.take<double>(ofo_cm.size());
     co->dev.ofo_rm = co->mem.take<double>(ofo_rm.size());
     co->dev.ifo = co->mem.take<double>(ifo.size());
@@ -610,6 +615,8 @@ CachedOps* get_ops(lfmm_ctx* ctx, int64_t side, int nlev, hipStream_t st, bool l
     co->dev.rank = co->mem.take<int32_t>(ranks.size());
     co->dev.skel = co->mem.take<int32_t>(skel.size());
     LFMM_HIP(hipMemcpyAsync(co->dev.leafT, leafT.data(), leafT.size() * 8, hipMemcpyHostToDevice, st));
+    if (co->dev.leafTt)
+        LFMM_HIP(hipMemcpyAsync(co->dev.leafTt, leafTt.data(), leafTt.size() * 8, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipMemcpyAsync(co->dev.ofo_cm, ofo_cm.data(), ofo_cm.size() * 8, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipMemcpyAsync(co->dev.ofo_rm, ofo_rm.data(), ofo_rm.size() * 8, hipMemcpyHostToDevice, st));
     LFMM_HIP(hipMemcpyAsync(co->dev.ifo, ifo.data(), ifo.size() * 8, hipMemcpyHostToDevice, st));
@@ -1418,7 +1425,8 @@ void enqueue_passes(lfmm_plan* pl, const ExecPtrs* tab, const double* f1, double
         const TileRange& r = pl->near_of_ops[o];
         launch_near(r.t0, r.t0 + r.n, pl->groups, pl->ents, pl->box_pt0, pl->box_pt1, pl->box_key, pl->box_inst,
                     pl->ops[o]->dev.leaf_side, pl->pts, pl->pkey, pl->fs, pl->perm, tab, single, pl->U,
-                    pl->ops[o]->dev.leafT, pl->d_far, pl->ctx->phi_oct, pl->ctx->phi_far, st);
+                    pl->ops[o]->dev.leafT, pl->ops[o]->dev.leafTt, pl->d_far, pl->ctx->phi_oct, pl->ctx->phi_far,
+                    st);
     }
     mark(6);
 }

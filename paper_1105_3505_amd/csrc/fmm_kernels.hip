@@ -1091,8 +1091,8 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
                                   const int2* pts,
                                   const uint32_t* pkey, const double* fs, const int32_t* perm_local,
                                   const ExecPtrs* tab_ptrs, ExecPtrs single, const double* U,
-                                  const double* leafT, const uint8_t* far_inst, const double* phi_oct_tab,
-                                  const PhiFar* phi_far) {
+                                  const double* leafT, const double* leafTt, const uint8_t* far_inst,
+                                  const double* phi_oct_tab, const PhiFar* phi_far) {
     const int lane = threadIdx.x & 63;
     const cptr<int4_t> E = as_const(reinterpret_cast<const int4_t*>(ents));
     const cptr<uint32_t> SK = as_const(pkey);
@@ -1216,11 +1216,15 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
                 if (SLICED) {
                     for (int p = sl; p < P; p += S) a1 += tlp[p] * uh[p];
                 } else {
-                    const double2_t* tl2 = reinterpret_cast<const double2_t*>(tlp);
+                    // coefficient pairs from the coefficient-major table: the wave's lanes read
+                    // pair p of their cells from one span of 16 side^2 bytes (about half as many
+                    // cache lines per load as whole rows of the cell-major table)
+                    const int64_t nc = side * side;
+                    const double2_t* tl2 = reinterpret_cast<const double2_t*>(leafTt) + loc;
                     const double2_t* uh2 = reinterpret_cast<const double2_t*>(uh);
                     #pragma unroll
                     for (int p = 0; p < P / 2; p += 2) {
-                        const double2_t x0 = tl2[p], y0 = uh2[p], x1 = tl2[p + 1], y1 = uh2[p + 1];
+                        const double2_t x0 = tl2[p * nc], y0 = uh2[p], x1 = tl2[(p + 1) * nc], y1 = uh2[p + 1];
                         a0 += x0.x * y0.x;
                         a1 += x0.y * y0.y;
                         a2 += x1.x * y1.x;
@@ -1236,16 +1240,20 @@ __device__ inline void near_group(int32_t qq, const NearGroup* groups, const int
     }
 }
 
+// Window mode is held to six waves per SIMD (80 VGPRs): left free, the compiler keeps all 24
+// coefficient-pair loads of the far field in flight (103 VGPRs, four waves per SIMD), which
+// measured slower.
 template <int P, int MODE>
-__global__ __launch_bounds__(near_threads(MODE)) void k_near(int32_t q0, int32_t q1, const NearGroup* groups,
+__global__ __launch_bounds__(near_threads(MODE), MODE == kWindow ? 6 : 1) void k_near(int32_t q0, int32_t q1, const NearGroup* groups,
                                                       const int4* ents, const int32_t* box_pt0,
                                                       const int32_t* box_pt1, const uint64_t* box_key,
                                                       const int32_t* box_inst, int64_t side, int W, const int2* pts,
                                                       const uint32_t* pkey, const double* fs,
                                                       const int32_t* perm_local, const ExecPtrs* tab_ptrs,
                                                       ExecPtrs single, const double* U,
-                                                      const double* leafT, const uint8_t* far_inst,
-                                                      const double* phi_oct_tab, const PhiFar* phi_far) {
+                                                      const double* leafT, const double* leafTt,
+                                                      const uint8_t* far_inst, const double* phi_oct_tab,
+                                                      const PhiFar* phi_far) {
     constexpr int kNearBlock = near_threads(MODE), kNearWaves = kNearBlock / 64;
     // fixed-size table (largest window: side 32), so that its base is a compile-time constant
     // and folds into the address of every read
@@ -1285,11 +1293,11 @@ __global__ __launch_bounds__(near_threads(MODE)) void k_near(int32_t q0, int32_t
         // leaf otherwise (the octant table in global memory is read faster a leaf at a time)
         if (MODE != kGlobal && nt > 32)
             near_group<P, MODE, false>(qq, groups, ents, box_pt0, box_pt1, box_key, box_inst, side, W, tab, tb, kofs, pts,
-                                       pkey, fs, perm_local, tab_ptrs, single, U, leafT, far_inst,
+                                       pkey, fs, perm_local, tab_ptrs, single, U, leafT, leafTt, far_inst,
                                        phi_oct_tab, phi_far);
         else
             near_group<P, MODE, true>(qq, groups, ents, box_pt0, box_pt1, box_key, box_inst, side, W, tab, tb, kofs, pts,
-                                      pkey, fs, perm_local, tab_ptrs, single, U, leafT, far_inst,
+                                      pkey, fs, perm_local, tab_ptrs, single, U, leafT, leafTt, far_inst,
                                       phi_oct_tab, phi_far);
     }
 }
@@ -1894,8 +1902,10 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
                  const int32_t* box_pt1, const uint64_t* box_key, const int32_t* box_inst, int64_t side,
                  const int32_t* pts, const uint32_t* pkey, const double* fs, const int32_t* perm_local,
                  const ExecPtrs* tab, const ExecPtrs& single, const double* U, const double* leafT,
-                 const uint8_t* far_inst, const double* phi_oct, const PhiFar* phi_far, hipStream_t st) {
+                 const double* leafTt, const uint8_t* far_inst, const double* phi_oct, const PhiFar* phi_far,
+                 hipStream_t st) {
     if (q1 <= q0) return;
+    if (side <= 32 && leafTt == nullptr) throw std::logic_error("near field without its coefficient-major T_ofs");
     // with an LDS table: persistent blocks, as many as fit on the device at once, so that
     // each builds its table once and then walks many groups; else one group per wave
     auto grid = [&](const void* fn, int threads, size_t lds, bool persistent) {
@@ -1918,7 +1928,7 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
         const unsigned g = grid(reinterpret_cast<const void*>(&k_near<kRankPad, kWindow>), nt, lds, true);
         hipLaunchKernelGGL((k_near<kRankPad, kWindow>), dim3(g), dim3(nt), lds, st, q0, q1, groups, ents,
                            box_pt0, box_pt1, box_key, box_inst, side, W, p2, pkey, fs, perm_local, tab, single, U,
-                           leafT, far_inst, phi_oct, phi_far);
+                           leafT, leafTt, far_inst, phi_oct, phi_far);
     } else if (side <= 32) {
         const int W = int(2 * side);
         const size_t lds = 0;
@@ -1927,7 +1937,7 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
         const unsigned g = grid(reinterpret_cast<const void*>(&k_near<kRankPad, kQuad>), nt, lds, true);
         hipLaunchKernelGGL((k_near<kRankPad, kQuad>), dim3(g), dim3(nt), lds, st, q0, q1, groups, ents,
                            box_pt0, box_pt1, box_key, box_inst, side, W, p2, pkey, fs, perm_local, tab, single, U,
-                           leafT, far_inst, phi_oct, phi_far);
+                           leafT, leafTt, far_inst, phi_oct, phi_far);
     } else {
         // every near offset (at most 2 side - 1 <= 255) lies inside the device octant table
         if (2 * side - 1 > kPhiDeviceRadius) throw std::logic_error("leaf wider than the near-field table allows");

@@ -64,6 +64,10 @@ struct DevOps {
     int64_t leaf_side = 0;
     int nlev = 0;                  // heights 0 .. nlev-1
     double* leafT = nullptr;       // [side^2][kRankPad]: T_ofs column of each cell, cell-major
+    // sides up to 32 (the near-field kernel with an LDS phi table): the same entries
+    // coefficient-major in pairs, [kRankPad / 2][side^2][2], so that lanes evaluating the far
+    // field at different cells read one pair each from a span of 16 side^2 bytes
+    double* leafTt = nullptr;
     // [nlev][4] operators in the fragment order of ifo below: T_ofo (M2M, rows = parent
     // skeleton) and T_ofo^T (L2L, rows = child skeleton)
     double* ofo_rm = nullptr;
@@ -302,7 +306,8 @@ void launch_near(int32_t q0, int32_t q1, const NearGroup* groups, const int4* en
                  const int32_t* box_pt1, const uint64_t* box_key, const int32_t* box_inst, int64_t side,
                  const int32_t* pts, const uint32_t* pkey, const double* fs, const int32_t* perm_local,
                  const ExecPtrs* tab, const ExecPtrs& single, const double* U, const double* leafT,
-                 const uint8_t* far_inst, const double* phi_oct, const PhiFar* phi_far, hipStream_t st);
+                 const double* leafTt, const uint8_t* far_inst, const double* phi_oct, const PhiFar* phi_far,
+                 hipStream_t st);
 // Adaptive tree passes.  P2L (X lists): u-hat of box tau += phi(skeleton of tau - x_j) f_j over
 // the points of its X leaves, for the nx boxes xitems.  Near field of the adaptive leaves
 // (items): U-list sources, W-list skeletons with their q-hat (M2P), L2P at each point's finest

@@ -805,7 +805,13 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     tmp.reserve(size_t(K + 1) * 4);             // chunk_first
     tmp.reserve(size_t(nch) * 16);              // bbox partials
     tmp.reserve(size_t(K) * sizeof(InstInfo));  // instances up to the level statistics
-    tmp.reserve(size_t(K) * (kMaxLevels + 3) * 4 + 4);   // level histograms, look-ahead maxima, counter
+    // copies of the level statistics: enough that no copy takes the atomics of more than about
+    // 32 chunks of one instance
+    int32_t max_chunks = 0;
+    for (int32_t k = 0; k < K; ++k)
+        max_chunks = std::max(max_chunks, chunk_first[size_t(k) + 1] - chunk_first[size_t(k)]);
+    const int32_t stat_copies = std::min(kLevelStatsCopies, std::max(1, max_chunks / 32));
+    tmp.reserve(size_t(stat_copies) * K * (kMaxLevels + 3) * 4 + 4);   // level histograms, look-ahead maxima, counter
     tmp.reserve(4);                             // deepest root box
     tmp.reserve(nseg > 1 ? size_t(n) * 8 : 0);  // concatenated points
     tmp.reserve(size_t(n) * 8);                 // keys
@@ -824,7 +830,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
     int32_t* d_chfirst = tmp.take<int32_t>(K + 1);
     int32_t* d_part = tmp.take<int32_t>(size_t(nch) * 4);
     InstInfo* d_inst0 = tmp.take<InstInfo>(K);
-    const int32_t nstats = K * (kMaxLevels + 3);
+    const int32_t nstats = stat_copies * K * (kMaxLevels + 3);
     int32_t* d_stats = tmp.take<int32_t>(size_t(nstats) + 1);   // zeroed by the key kernel
     int32_t* d_dmax = tmp.take<int32_t>(1);
     // results of the two read-backs: pinned host memory that the kernels write (the root boxes
@@ -951,7 +957,7 @@ void build_forest(lfmm_plan* pl, int32_t K, const InstanceInput* in, int32_t max
 
     // ---- leaf levels and box counts ---------------------------------------------------------
     launch_level_stats(skeys, svals, d_chunks, nch, d_inst0, Dmax, K, pl->pts, pl->perm, pl->pinst, cl, d_stats,
-                       d_stats + nstats, stats, st);
+                       stat_copies, d_stats + nstats, stats, st);
     if (sreg) {
         LFMM_HIP(hipMemcpyAsync(rb_host.data() + size_t(K) * 4, stats, (rb_words - size_t(K) * 4) * 4,
                                 hipMemcpyDeviceToHost, st));
@@ -2113,8 +2119,9 @@ lfmm_status lfmm_plan_footprint_bytes(const lfmm_ctx* ctx, int64_t n_src, int64_
     // construction temporaries: concatenated points, keys and indices (two copies), common
     // levels, sort and scan scratch; then per leaf: first point, key, level, instance and one
     // scan row per level; per box: class scans
+    const size_t chunks = size_t(n) / kChunk + 1;   // each: its range and box partials
     const size_t tmp = size_t(n) * (8 + 16 + 8 + 1) + radix_scratch_bytes(n) + scan_scratch_bytes(n, 1) +
-                       (kMaxLevels + 10) * 4 * 4 + 24 * al;
+                       chunks * 2 * 16 + (kMaxLevels + 10) * 4 * 4 * kLevelStatsCopies + 24 * al;
     const size_t rows = size_t(std::max(D, 1));
     const size_t tmp2 = nl * (4 + 8 + 1 + 4 + 4 * rows) + scan_scratch_bytes(int64_t(nl), int(rows)) + nb * 16 + 64 +
                         scan_scratch_bytes(int64_t(nb), 4) + 10 * al;

@@ -138,10 +138,18 @@ __global__ void k_bbox_chunks(const int2* xy, const Chunk* chunks, int32_t* part
     if (blockIdx.x == 0 && threadIdx.x == 0) *dmax = 0;   // the deepest root box, raised by k_bbox_final
     const Chunk c = chunks[blockIdx.x];
     int v[4] = {INT_MAX, INT_MAX, INT_MIN, INT_MIN};
-    for (int32_t i = c.begin + int32_t(threadIdx.x); i < c.end; i += kBlock) {
-        const int2 p = xy[i];
-        v[0] = min(v[0], p.x); v[1] = min(v[1], p.y);
-        v[2] = max(v[2], p.x); v[3] = max(v[3], p.y);
+    // all of the thread's points loaded before any is used (one wait, not one per point)
+    constexpr int kIt = kChunk / kBlock;
+    int2 q[kIt];
+    #pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int32_t i = c.begin + it * kBlock + int32_t(threadIdx.x);
+        q[it] = i < c.end ? xy[i] : xy[c.begin];   // a chunk's first point stands in past its end
+    }
+    #pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        v[0] = min(v[0], q[it].x); v[1] = min(v[1], q[it].y);
+        v[2] = max(v[2], q[it].x); v[3] = max(v[3], q[it].y);
     }
     if (block_minmax4(v))
         for (int q = 0; q < 4; ++q) part[size_t(blockIdx.x) * 4 + q] = v[q];
@@ -245,7 +253,8 @@ __global__ void k_keys(const int2* xy, const int32_t* pt_off, int32_t K, const I
 // is needed.
 __global__ void k_level_stats(const uint64_t* keys, const uint32_t* vals, const Chunk* chunks,
                               const InstInfo* inst, int Dmax, int32_t K, int2* pts, int32_t* perm_local,
-                              int32_t* pinst, int8_t* cl, int32_t* hist, int32_t* done, int32_t* host_out) {
+                              int32_t* pinst, int8_t* cl, int32_t* hist, int32_t R, int32_t* done,
+                              int32_t* host_out) {
     constexpr int NH = kMaxLevels + 2;
     __shared__ int32_t h[NH];
     __shared__ int32_t wmax[kBlock / 64];
@@ -285,32 +294,43 @@ __global__ void k_level_stats(const uint64_t* keys, const uint32_t* vals, const 
             cl[s] = int8_t(v);
             if (s + nleaf < I.pt1) mc = max(mc, common_levels(kk[it], ka[it], Dmax) - shift);
         }
-        uint64_t active = __ballot(valid);
-        while (active) {
-            const int leader = __ffsll((unsigned long long)active) - 1;
-            const int vv = __shfl(v, leader, 64);
-            const uint64_t m = __ballot(valid && v == vv);
-            if (lane == leader) atomicAdd(&h[vv + 1], int32_t(__popcll(m)));
-            active &= ~m;
-        }
+        // LDS atomics straight from every lane: the few distinct levels of a wave's neighbouring
+        // keys make short queues, cheaper than a chain of leader elections
+        if (valid) atomicAdd(&h[v + 1], 1);
     }
     #pragma unroll
     for (int o = 32; o > 0; o >>= 1) mc = max(mc, __shfl_xor(mc, o, 64));
     if (lane == 0) wmax[wave] = mc;
     __syncthreads();
-    int32_t* maxc = hist + size_t(K) * NH;
+    // the block's counts go to copy blockIdx % R of the counters: with one instance split over
+    // hundreds of chunks, the blocks' atomics then queue on R lines instead of one
+    const size_t per = size_t(K) * (NH + 1);
+    int32_t* hc = hist + size_t(blockIdx.x % unsigned(R)) * per;
+    int32_t* maxc = hc + size_t(K) * NH;
     if (threadIdx.x == 0) {
         int bm = wmax[0];
         for (int w = 1; w < kBlock / 64; ++w) bm = max(bm, wmax[w]);
         if (bm >= 0) atomicMax(&maxc[c.inst], bm);
     }
-    if (threadIdx.x < NH && h[threadIdx.x] != 0) atomicAdd(&hist[size_t(c.inst) * NH + threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x < NH && h[threadIdx.x] != 0) atomicAdd(&hc[size_t(c.inst) * NH + threadIdx.x], h[threadIdx.x]);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) is_last = atomicAdd(done, 1) == int(gridDim.x) - 1;
     __syncthreads();
     if (is_last)
-        for (int i = threadIdx.x; i < K * (NH + 1); i += blockDim.x) host_out[i] = atomicAdd(&hist[i], 0);
+        for (size_t i = threadIdx.x; i < per; i += blockDim.x) {
+            const bool is_max = i >= size_t(K) * NH;
+            int32_t v = 0;
+            // device-scope loads (past this compute unit's caches), all in flight together
+            #pragma unroll
+            for (int32_t r = 0; r < kLevelStatsCopies; ++r) {
+                if (r >= R) break;
+                const int32_t x = __hip_atomic_load(&hist[size_t(r) * per + i], __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+                v = is_max ? max(v, x) : v + x;
+            }
+            host_out[i] = v;
+        }
 }
 
 // One thread per (leaf, level): the leaf that starts a box of that level writes the box and
@@ -1253,9 +1273,11 @@ void launch_keys(const int32_t* xy, const int32_t* pt_off, int32_t K, const Inst
 
 void launch_level_stats(const uint64_t* keys, const uint32_t* vals, const Chunk* chunks, int32_t nchunks,
                         const InstInfo* inst, int Dmax, int32_t K, int32_t* pts, int32_t* perm_local, int32_t* pinst,
-                        int8_t* cl, int32_t* hist, int32_t* done, int32_t* host_out, hipStream_t st) {
+                        int8_t* cl, int32_t* hist, int32_t copies, int32_t* done, int32_t* host_out,
+                        hipStream_t st) {
     hipLaunchKernelGGL(k_level_stats, dim3(unsigned(nchunks)), dim3(kBlock), 0, st, keys, vals, chunks, inst, Dmax, K,
-                       reinterpret_cast<int2*>(pts), perm_local, pinst, cl, hist, done, host_out);
+                       reinterpret_cast<int2*>(pts), perm_local, pinst, cl, hist, std::max(copies, 1), done,
+                       host_out);
 }
 
 void launch_build_boxes(const int32_t* lscan, const int8_t* leaf_cl, const int32_t* leaf_pt0, const uint64_t* leaf_key,

@@ -207,9 +207,13 @@ void launch_keys(const int32_t* xy, const int32_t* pt_off, int32_t K, const Inst
 // and instances; per-level box counts and look-ahead maxima of every instance into hist
 // ([K][kMaxLevels + 2] counts, then [K] maxima; zero before the launch), copied to host_out
 // (host memory) by the last block; *done counts finished blocks (zero before the launch)
+// hist: `copies` zeroed copies of [K][kMaxLevels + 2] histograms and K maxima, added up into
+// host_out by the last block
+constexpr int kLevelStatsCopies = 16;
 void launch_level_stats(const uint64_t* keys, const uint32_t* vals, const Chunk* chunks, int32_t nchunks,
                         const InstInfo* inst, int Dmax, int32_t K, int32_t* pts, int32_t* perm_local, int32_t* pinst,
-                        int8_t* cl, int32_t* hist, int32_t* done, int32_t* host_out, hipStream_t st);
+                        int8_t* cl, int32_t* hist, int32_t copies, int32_t* done, int32_t* host_out,
+                        hipStream_t st);
 // exclusive scans of the flags "a leaf starts here" (per point), "leaf b starts a box of
 // level lev" (row lev, per leaf) and "box g is child c of its parent" (row c, per box)
 void scan_leaf_starts(const int8_t* cl, const int32_t* pinst, const InstInfo* inst, int64_t n,

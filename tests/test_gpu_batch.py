@@ -137,3 +137,34 @@ def test_batch_rejects_bad_input(torch_mod):
         ctx.plan_batch([good, far])
     assert e.value.status == -2
     ctx.close()
+
+
+def test_large_instances_in_one_forest(torch_mod):
+    """Instances of a few hundred thousand points each: the plan build counts each instance's
+    level statistics over many chunks (into several copies of the counters), for every
+    instance of the forest at once; each instance must still get the tree, and the bits, of
+    its own plan, and meet the FP64 target on sampled targets."""
+    import paper_1105_3505_amd as lf
+    torch = torch_mod
+    rng = np.random.default_rng(1301)
+    inst = []
+    for n, side, origin in [(300000, 2500, (0, 0)), (280000, 600, (10 ** 6, -(10 ** 6))),
+                            (3000, 100, (-5000, 70))]:
+        xy = wl.uniform_box(rng, n, side, origin=origin)
+        inst.append((xy, wl.zero_sum_loads(rng.standard_normal(n))))
+    ctx = lf.Context(0)
+    plan = ctx.plan_batch([_dev(torch, xy) for xy, _ in inst])
+    us = plan.execute_instances([_dev(torch, f) for _, f in inst])
+    torch.cuda.synchronize()
+    for k, (xy, f) in enumerate(inst):
+        alone = ctx.plan(_dev(torch, xy))
+        ua = alone.execute(_dev(torch, f)).cpu().numpy()
+        ub = us[k].cpu().numpy()
+        assert np.array_equal(ua, ub), "instance %d differs from its own plan" % k
+        idx = wl.sample_targets(11 + k, len(xy), 300)
+        ref = od.direct_sum(xy[idx], xy, f)
+        assert _rel(ub[idx], ref) <= FMM_TOL, k
+        assert np.max(np.abs(ub[idx] - ref)) <= FMM_TOL * np.max(np.abs(ref)), k
+        alone.close()
+    plan.close()
+    ctx.close()

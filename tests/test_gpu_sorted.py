@@ -49,7 +49,8 @@ def _run_sorted(torch, plan, fs):
 
 
 @pytest.mark.parametrize("precision,adaptive,graph", [("fp64", False, False), ("mixed-bf16", False, False),
-                                                      ("fp64", True, False), ("fp64", False, True)])
+                                                      ("mixed", False, False), ("fp64", True, False),
+                                                      ("fp64", False, True)])
 def test_sorted_equals_caller_order(torch_mod, precision, adaptive, graph):
     import paper_1105_3505_amd as lf
     torch = torch_mod

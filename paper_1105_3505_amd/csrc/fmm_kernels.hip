@@ -1290,7 +1290,19 @@ __global__ __launch_bounds__(near_threads(MODE), MODE == kWindow ? 6 : 1) void k
     const int cw = (MODE == kWindow) ? int(2 * side - 1) : 0;
     const char* tb = reinterpret_cast<const char*>(tab);
     const uint32_t kofs = 8u * uint32_t(cw * W + cw);
-    for (int32_t q = q0 + int32_t(blockIdx.x) * kNearWaves + wave; q < q1; q += int32_t(gridDim.x) * kNearWaves) {
+    // XCD-contiguous split of the group list: block b runs on XCD b % 8, so the blocks of one XCD
+    // walk one contiguous eighth of the (Morton-ordered) groups, and the sources that neighbouring
+    // groups share are read through the same L2 (with fewer than 8 blocks, one range for all)
+    const int32_t G = int32_t(gridDim.x);
+    int32_t lo = q0, hi = q1, first = int32_t(blockIdx.x), nb = G;
+    if (G >= 8) {
+        const int32_t x = first & 7, chunk = (q1 - q0 + 7) >> 3;
+        lo = min(q1, q0 + x * chunk);
+        hi = min(q1, lo + chunk);
+        first >>= 3;
+        nb = (G + 7 - x) >> 3;   // blocks on XCD x
+    }
+    for (int32_t q = lo + first * kNearWaves + wave; q < hi; q += nb * kNearWaves) {
         const int32_t qq = uniform(q);
         const int32_t leaf0 = uniform(groups[qq].leaf0), nleaf = uniform(groups[qq].nleaf);
         const int32_t nt = uniform(box_pt1[leaf0 + nleaf - 1]) - uniform(box_pt0[leaf0]);
